@@ -1,0 +1,638 @@
+/*
+ * FP64 CPU oracle for one semi-implicit BDF step of the VMS-LES Navier-Stokes
+ * system on tetrahedra (Africa et al., "lifex-cfd", arXiv 2304.12032).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the device library links, includes or
+ * calls this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline use it.  It is written to be checked against the paper by eye:
+ * one loop over elements, one loop over quadrature points, and every matrix
+ * entry written out from the weak form, with no factoring or fusion.
+ *
+ * Paper passages followed (section / equation names of the paper):
+ *   - fully discrete weak form: Sec. 2.3, eq. (fullydiscrete_ns_ale_riis...)
+ *   - diffusion forms: Sec. 2.3, eq. (diffusion-term)
+ *   - SUPG-PSPG and VMS terms: Sec. 2.3, eqs. (stabilization_form_SUPG/VMS)
+ *   - semi-implicit LES term: Sec. 2.3, eq. (stabilization_form_LES), 2nd case
+ *   - strong residuals r_M, r_C and tau_M, tau_C, G, g: Sec. 2.3
+ *   - RIIS term and smoothed delta: Sec. 2.1.2, eq. (riis)
+ *   - Neumann data: Sec. 2.2.3, eq. (bcs-neumann)
+ *   - GMRES with the SIMPLE preconditioner: Sec. 2.4
+ *
+ * Readings where the paper is silent (kept identical on the device side and
+ * listed in the design notes): local velocity index 3a+c, pressure 12+a;
+ * vector-valued test functions phi_a e_c; the VMS term's component j is
+ * sum_i u*_i d_j v_i; the LES term is -rho sum_ij atil_i b_j d_j v_i with atil
+ * from (u_EXT, p_EXT); tau_M's first term uses the BDF order sigma; G and g
+ * are built from the element map of the unit simplex with the element's
+ * vertex order as given; the P1 quadrature is the symmetric 4-point degree-2
+ * rule; the valve distance is measured at the quadrature point's reference
+ * position; u_Sigma = 0.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_STAB_NONE 0
+#define ORC_STAB_SUPG_PSPG 1
+#define ORC_STAB_VMS_LES 2
+
+typedef struct {
+    double alpha;     /* BDF coefficient of u^{n+1} at this step                 */
+    double sigma;     /* BDF order used at this step (first term of tau_M)       */
+    double dt, rho, mu, C_r;
+    int32_t stab;     /* ORC_STAB_*                                              */
+    int32_t symgrad;  /* 0: gradient-gradient, 1: symmetric-gradient forms      */
+    int32_t n_riis;
+    int32_t pad;
+    const double *riis; /* per valve 10 doubles: center[3], unit normal[3],
+                           inner (orifice) radius, outer radius, R, eps         */
+} orc_params;
+
+/* ---------------------------------------------------------------- geometry */
+
+/* Symmetric 4-point rule on the tetrahedron, degree 2: barycentric (a,b,b,b)
+ * and permutations, a = (5+3 sqrt5)/20, b = (5-sqrt5)/20, each weight 1/4 of
+ * the volume. */
+void orc_quad_p1(double lam[4][4], double w[4])
+{
+    const double a = (5.0 + 3.0 * sqrt(5.0)) / 20.0;
+    const double b = (5.0 - sqrt(5.0)) / 20.0;
+    for (int q = 0; q < 4; ++q) {
+        for (int k = 0; k < 4; ++k) lam[q][k] = (k == q) ? a : b;
+        w[q] = 0.25;
+    }
+}
+
+/* J = [x1-x0, x2-x0, x3-x0] (columns) maps the unit simplex onto the element.
+ * Returns det J, fills Jinv. */
+static double jacobian(const double X[4][3], double Jinv[3][3])
+{
+    double J[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) J[i][k] = X[k + 1][i] - X[0][i];
+    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+               - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+               + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    Jinv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+    Jinv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    Jinv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    Jinv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+    Jinv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    Jinv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    Jinv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+    Jinv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    Jinv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    return det;
+}
+
+/* Smoothed Dirac delta of half-width eps (Sec. 2.1.2). */
+double orc_delta(double phi, double eps)
+{
+    if (fabs(phi) > eps) return 0.0;
+    return (1.0 + cos(M_PI * phi / eps)) / (2.0 * eps);
+}
+
+/* Unsigned distance from point y to an annular disc (center c, unit normal n,
+ * inner radius r0, outer radius r1).  A full disc has r0 = 0. */
+double orc_valve_distance(const double *y, const double *v)
+{
+    double rel[3] = {y[0] - v[0], y[1] - v[1], y[2] - v[2]};
+    double z = rel[0] * v[3] + rel[1] * v[4] + rel[2] * v[5];
+    double p[3] = {rel[0] - z * v[3], rel[1] - z * v[4], rel[2] - z * v[5]};
+    double rp = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    double dr = 0.0;
+    if (rp < v[6]) dr = v[6] - rp;
+    if (rp > v[7]) dr = rp - v[7];
+    return sqrt(z * z + dr * dr);
+}
+
+/* tau_M and tau_C of Sec. 2.3 from the metric tensor G, metric vector g and
+ * advection velocity u*, with the RIIS sum supplied as riis2 = sum R^2/eps^2 delta^2. */
+void orc_tau(const orc_params *P, const double G[3][3], const double g[3], const double us[3],
+             double riis2, double *tauM, double *tauC)
+{
+    double uGu = 0.0, GG = 0.0, gg = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        gg += g[i] * g[i];
+        for (int j = 0; j < 3; ++j) {
+            uGu += us[i] * G[i][j] * us[j];
+            GG += G[i][j] * G[i][j];
+        }
+    }
+    double rho = P->rho, mu = P->mu;
+    double s = P->sigma * P->sigma * rho * rho / (P->dt * P->dt) + rho * rho * uGu
+             + P->C_r * mu * mu * GG + riis2;
+    *tauM = 1.0 / sqrt(s);
+    *tauC = 1.0 / ((*tauM) * gg);
+}
+
+/*
+ * Element matrix Ke (16x16) and right-hand side Fe (16) of the P1-P1 element.
+ * Inputs per local vertex a: current coordinates X, reference coordinates Xh,
+ * extrapolated velocity uE and pressure pE, BDF velocity combination uB, ALE
+ * velocity uA and forcing f (all P1 nodal values).  Returns det J.
+ */
+double orc_element_p1(const double X[4][3], const double Xh[4][3], const double uE[4][3],
+                      const double uB[4][3], const double uA[4][3], const double pE[4],
+                      const double f[4][3], const orc_params *P, double Ke[16][16], double Fe[16])
+{
+    double Jinv[3][3];
+    double det = jacobian(X, Jinv);
+    double vol = fabs(det) / 6.0;
+
+    /* gradients of the barycentric basis: grad lambda_k = row k-1 of J^{-1} */
+    double dphi[4][3];
+    for (int j = 0; j < 3; ++j) {
+        dphi[1][j] = Jinv[0][j];
+        dphi[2][j] = Jinv[1][j];
+        dphi[3][j] = Jinv[2][j];
+        dphi[0][j] = -(Jinv[0][j] + Jinv[1][j] + Jinv[2][j]);
+    }
+    /* metric tensor G = J^{-T} J^{-1}, metric vector g = J^{-T} (1,1,1) */
+    double G[3][3], g[3];
+    for (int i = 0; i < 3; ++i) {
+        g[i] = Jinv[0][i] + Jinv[1][i] + Jinv[2][i];
+        for (int j = 0; j < 3; ++j)
+            G[i][j] = Jinv[0][i] * Jinv[0][j] + Jinv[1][i] * Jinv[1][j] + Jinv[2][i] * Jinv[2][j];
+    }
+
+    memset(Ke, 0, sizeof(double) * 256);
+    memset(Fe, 0, sizeof(double) * 16);
+
+    double lam[4][4], wq[4];
+    orc_quad_p1(lam, wq);
+    const double rho = P->rho, mu = P->mu, dt = P->dt, alpha = P->alpha;
+
+    for (int q = 0; q < 4; ++q) {
+        const double *phi = lam[q];
+        double w = wq[q] * vol;
+
+        /* fields at the quadrature point */
+        double uEq[3] = {0}, uBq[3] = {0}, uAq[3] = {0}, fq[3] = {0}, xh[3] = {0};
+        double gradUE[3][3] = {{0}}, gradPE[3] = {0};
+        for (int a = 0; a < 4; ++a)
+            for (int c = 0; c < 3; ++c) {
+                uEq[c] += phi[a] * uE[a][c];
+                uBq[c] += phi[a] * uB[a][c];
+                uAq[c] += phi[a] * uA[a][c];
+                fq[c] += phi[a] * f[a][c];
+                xh[c] += phi[a] * Xh[a][c];
+                gradPE[c] += pE[a] * dphi[a][c];
+                for (int j = 0; j < 3; ++j) gradUE[c][j] += uE[a][c] * dphi[a][j];
+            }
+
+        /* RIIS: sigma_R = sum_k R_k/eps_k delta_k, riis2 = sum_k R_k^2/eps_k^2 delta_k^2 */
+        double sigR = 0.0, riis2 = 0.0;
+        for (int k = 0; k < P->n_riis; ++k) {
+            const double *v = P->riis + 10 * k;
+            double R = v[8], eps = v[9];
+            double dl = orc_delta(orc_valve_distance(xh, v), eps);
+            sigR += R / eps * dl;
+            riis2 += (R * R) / (eps * eps) * dl * dl;
+        }
+
+        double us[3];
+        for (int c = 0; c < 3; ++c) us[c] = uEq[c] - uAq[c];
+
+        double tauM = 0.0, tauC = 0.0;
+        if (P->stab != ORC_STAB_NONE) orc_tau(P, G, g, us, riis2, &tauM, &tauC);
+
+        /* data collected on the right-hand side: K = f + rho u_BDF/dt + sigma_R u_ALE */
+        double Kv[3];
+        for (int c = 0; c < 3; ++c) Kv[c] = fq[c] + rho * uBq[c] / dt + sigR * uAq[c];
+
+        /* strong momentum residual of the extrapolated state (mu Lap u = 0 for P1) */
+        double at[3];
+        for (int c = 0; c < 3; ++c) {
+            double adv = 0.0;
+            for (int j = 0; j < 3; ++j) adv += us[j] * gradUE[c][j];
+            double rt = rho * (alpha * uEq[c] / dt + adv) + gradPE[c] + sigR * uEq[c] - Kv[c];
+            at[c] = tauM * rt;
+        }
+
+        /* T[a][c][j]: the stabilisation test direction of test function phi_a e_c */
+        double adv_phi[4], T[4][3][3], s[4];
+        for (int a = 0; a < 4; ++a) {
+            adv_phi[a] = us[0] * dphi[a][0] + us[1] * dphi[a][1] + us[2] * dphi[a][2];
+        }
+        for (int a = 0; a < 4; ++a)
+            for (int c = 0; c < 3; ++c)
+                for (int j = 0; j < 3; ++j) {
+                    double t = (c == j) ? adv_phi[a] : 0.0;                       /* SUPG */
+                    if (P->stab == ORC_STAB_VMS_LES) t += us[c] * dphi[a][j];     /* VMS  */
+                    if (P->stab == ORC_STAB_VMS_LES) t -= at[c] * dphi[a][j];     /* LES  */
+                    T[a][c][j] = rho * t;
+                }
+        /* s_b: momentum strong residual of the trial function phi_b e_d, per component */
+        for (int b = 0; b < 4; ++b)
+            s[b] = rho * (alpha / dt * phi[b] + adv_phi[b]) + sigR * phi[b];
+
+        for (int a = 0; a < 4; ++a) {
+            for (int c = 0; c < 3; ++c) {
+                int ia = 3 * a + c;
+                for (int b = 0; b < 4; ++b) {
+                    double gg_ab = dphi[a][0] * dphi[b][0] + dphi[a][1] * dphi[b][1] + dphi[a][2] * dphi[b][2];
+                    for (int d = 0; d < 3; ++d) {
+                        int jb = 3 * b + d;
+                        double v = 0.0;
+                        if (c == d) {
+                            v += (rho * alpha / dt + sigR) * phi[a] * phi[b];   /* time + RIIS */
+                            v += rho * phi[a] * adv_phi[b];                     /* advection   */
+                            v += mu * gg_ab;                                    /* diffusion   */
+                        }
+                        if (P->symgrad) v += mu * dphi[b][c] * dphi[a][d];
+                        v += tauM * s[b] * T[a][c][d];                          /* SUPG/VMS/LES */
+                        v += tauC * dphi[a][c] * dphi[b][d];                    /* grad-div    */
+                        Ke[ia][jb] += w * v;
+                    }
+                    /* pressure trial psi_b = phi_b */
+                    double v = -phi[b] * dphi[a][c];
+                    v += tauM * (dphi[b][0] * T[a][c][0] + dphi[b][1] * T[a][c][1] + dphi[b][2] * T[a][c][2]);
+                    Ke[ia][12 + b] += w * v;
+                }
+                double r = Kv[c] * phi[a];
+                r += tauM * (Kv[0] * T[a][c][0] + Kv[1] * T[a][c][1] + Kv[2] * T[a][c][2]);
+                Fe[ia] += w * r;
+            }
+            /* pressure test function q = psi_a */
+            for (int b = 0; b < 4; ++b) {
+                for (int d = 0; d < 3; ++d)
+                    Ke[12 + a][3 * b + d] += w * (phi[a] * dphi[b][d] + tauM * s[b] * dphi[a][d]);
+                double gg_ab = dphi[a][0] * dphi[b][0] + dphi[a][1] * dphi[b][1] + dphi[a][2] * dphi[b][2];
+                Ke[12 + a][12 + b] += w * tauM * gg_ab;
+            }
+            Fe[12 + a] += w * tauM * (Kv[0] * dphi[a][0] + Kv[1] * dphi[a][1] + Kv[2] * dphi[a][2]);
+        }
+    }
+    return det;
+}
+
+/* ------------------------------------------------------- global assembly */
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * Vertex adjacency (each vertex with itself and every vertex sharing a tet),
+ * as CSR: vptr[nv+1], vadj[vptr[nv]] sorted.  Two passes: count, then fill.
+ * Returns the adjacency size, or -1 on allocation failure; the caller passes
+ * vadj = NULL first to get the size.
+ */
+int64_t orc_vertex_graph(int64_t nv, int64_t nt, int64_t nvpe, const int32_t *tets, int64_t *vptr,
+                         int32_t *vadj)
+{
+    /* candidate lists with duplicates: each vertex gets nvpe entries per incident tet */
+    int64_t *cnt = calloc((size_t)nv + 1, sizeof(int64_t));
+    if (!cnt) return -1;
+    for (int64_t e = 0; e < nt; ++e)
+        for (int a = 0; a < nvpe; ++a) cnt[tets[e * nvpe + a] + 1] += nvpe;
+    for (int64_t v = 0; v < nv; ++v) cnt[v + 1] += cnt[v];
+    int32_t *cand = malloc(sizeof(int32_t) * (size_t)cnt[nv]);
+    int64_t *fill = malloc(sizeof(int64_t) * (size_t)nv);
+    if (!cand || !fill) { free(cnt); free(cand); free(fill); return -1; }
+    for (int64_t v = 0; v < nv; ++v) fill[v] = cnt[v];
+    for (int64_t e = 0; e < nt; ++e)
+        for (int a = 0; a < nvpe; ++a) {
+            int32_t va = tets[e * nvpe + a];
+            for (int b = 0; b < nvpe; ++b) cand[fill[va]++] = tets[e * nvpe + b];
+        }
+    int64_t total = 0;
+    if (vptr) vptr[0] = 0;
+    for (int64_t v = 0; v < nv; ++v) {
+        int32_t *lst = cand + cnt[v];
+        int64_t n = cnt[v + 1] - cnt[v];
+        qsort(lst, (size_t)n, sizeof(int32_t), cmp_i32);
+        int64_t u = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (i == 0 || lst[i] != lst[i - 1]) {
+                if (vadj) vadj[total + u] = lst[i];
+                ++u;
+            }
+        total += u;
+        if (vptr) vptr[v + 1] = total;
+    }
+    free(cnt); free(cand); free(fill);
+    return total;
+}
+
+/*
+ * Scalar CSR pattern of the P1-P1 system, global numbering: velocity dof
+ * (v, c) -> 3v + c, pressure dof v -> 3 nv + v.  Row r of vertex v holds the
+ * columns {3w + d} for w in adj(v), d = 0..2, then {3 nv + w}.
+ */
+void orc_pattern_p1(int64_t nv, const int64_t *vptr, const int32_t *vadj, int64_t *rowptr,
+                    int32_t *col)
+{
+    int64_t N = 4 * nv, pos = 0;
+    rowptr[0] = 0;
+    for (int64_t r = 0; r < N; ++r) {
+        int64_t v = (r < 3 * nv) ? r / 3 : r - 3 * nv;
+        for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k)
+            for (int d = 0; d < 3; ++d) col[pos++] = (int32_t)(3 * vadj[k] + d);
+        for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k) col[pos++] = (int32_t)(3 * nv + vadj[k]);
+        rowptr[r + 1] = pos;
+    }
+}
+
+static int64_t find_col(const int64_t *rowptr, const int32_t *col, int64_t r, int32_t c)
+{
+    int64_t lo = rowptr[r], hi = rowptr[r + 1] - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (col[mid] == c) return mid;
+        if (col[mid] < c) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+/*
+ * Assemble the P1-P1 system: for every element gather its nodal data, form
+ * Ke, Fe with orc_element_p1 and add them into (val, rhs).  val and rhs must
+ * be zeroed by the caller.  Field arrays are [nv][3] (velocity-like) or [nv].
+ * Returns 0, or -(e+1) for the first element with |det J| <= 0.
+ */
+int64_t orc_assemble_p1(int64_t nv, int64_t nt, const double *x, const double *xh,
+                        const int32_t *tets, const double *uE, const double *uB, const double *uA,
+                        const double *pE, const double *f, const orc_params *P,
+                        const int64_t *rowptr, const int32_t *col, double *val, double *rhs)
+{
+    for (int64_t e = 0; e < nt; ++e) {
+        double X[4][3], Xh[4][3], ue[4][3], ub[4][3], ua[4][3], pe[4], fe[4][3];
+        int32_t v[4];
+        for (int a = 0; a < 4; ++a) {
+            v[a] = tets[4 * e + a];
+            for (int c = 0; c < 3; ++c) {
+                X[a][c] = x[3 * v[a] + c];
+                Xh[a][c] = xh[3 * v[a] + c];
+                ue[a][c] = uE[3 * v[a] + c];
+                ub[a][c] = uB[3 * v[a] + c];
+                ua[a][c] = uA ? uA[3 * v[a] + c] : 0.0;
+                fe[a][c] = f ? f[3 * v[a] + c] : 0.0;
+            }
+            pe[a] = pE[v[a]];
+        }
+        double Ke[16][16], Fe[16];
+        double det = orc_element_p1(X, Xh, ue, ub, ua, pe, fe, P, Ke, Fe);
+        if (!(fabs(det) > 0.0)) return -(e + 1);
+        int64_t gdof[16];
+        for (int a = 0; a < 4; ++a) {
+            for (int c = 0; c < 3; ++c) gdof[3 * a + c] = 3 * (int64_t)v[a] + c;
+            gdof[12 + a] = 3 * nv + v[a];
+        }
+        for (int i = 0; i < 16; ++i) {
+            rhs[gdof[i]] += Fe[i];
+            for (int j = 0; j < 16; ++j) {
+                int64_t k = find_col(rowptr, col, gdof[i], (int32_t)gdof[j]);
+                if (k < 0) return -(e + 1);
+                val[k] += Ke[i][j];
+            }
+        }
+    }
+    return 0;
+}
+
+/*
+ * Neumann term (h, v) on boundary triangles (Sec. 2.2.3): h is a nodal vector
+ * traction [nv][3], interpolated linearly on each face and integrated with the
+ * edge-midpoint rule (exact for the quadratic integrand).
+ */
+void orc_neumann_p1(int64_t nv, int64_t nf, const double *x, const int32_t *faces, const double *h,
+                    double *rhs)
+{
+    (void)nv;
+    for (int64_t e = 0; e < nf; ++e) {
+        const int32_t *v = faces + 3 * e;
+        double a[3], b[3];
+        for (int c = 0; c < 3; ++c) {
+            a[c] = x[3 * v[1] + c] - x[3 * v[0] + c];
+            b[c] = x[3 * v[2] + c] - x[3 * v[0] + c];
+        }
+        double n[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+        double area = 0.5 * sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        /* midpoint of edge (i,j): phi_i = phi_j = 1/2, weight area/3 */
+        for (int m = 0; m < 3; ++m) {
+            int i = m, j = (m + 1) % 3;
+            for (int c = 0; c < 3; ++c) {
+                double hq = 0.5 * (h[3 * v[i] + c] + h[3 * v[j] + c]);
+                rhs[3 * (int64_t)v[i] + c] += area / 3.0 * hq * 0.5;
+                rhs[3 * (int64_t)v[j] + c] += area / 3.0 * hq * 0.5;
+            }
+        }
+    }
+}
+
+/* Dirichlet rows: keep a_ii, zero the rest of the row, b_i = a_ii g_i. */
+void orc_dirichlet_rows(int64_t nrows, const int64_t *rows, const double *g, const int64_t *rowptr,
+                        const int32_t *col, double *val, double *rhs)
+{
+    for (int64_t k = 0; k < nrows; ++k) {
+        int64_t r = rows[k];
+        double aii = 0.0;
+        for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+            if (col[p] == r) aii = val[p];
+            else val[p] = 0.0;
+        }
+        rhs[r] = aii * g[k];
+    }
+}
+
+/* ------------------------------------------------------------- linear solve */
+
+static void csr_mv(int64_t N, const int64_t *rowptr, const int32_t *col, const double *val,
+                   const double *x, double *y)
+{
+    for (int64_t r = 0; r < N; ++r) {
+        double s = 0.0;
+        for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) s += val[p] * x[col[p]];
+        y[r] = s;
+    }
+}
+
+static double dot(int64_t N, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < N; ++i) s += a[i] * b[i];
+    return s;
+}
+
+typedef struct {
+    int64_t nv;
+    const int64_t *rowptr;
+    const int32_t *col;
+    const double *val;
+    double *Dinv;    /* [3nv] 1/F_ii                        */
+    double *Finv;    /* [nv][9] inverse nodal 3x3 blocks    */
+    double *Sinv;    /* [nv]  1/diag(C - B D^-1 G)          */
+    double *tmp;     /* [4nv] work                          */
+} simple_t;
+
+static void inv3(const double A[9], double B[9])
+{
+    double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6])
+               + A[2] * (A[3] * A[7] - A[4] * A[6]);
+    B[0] = (A[4] * A[8] - A[5] * A[7]) / det;
+    B[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+    B[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+    B[3] = (A[5] * A[6] - A[3] * A[8]) / det;
+    B[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+    B[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+    B[6] = (A[3] * A[7] - A[4] * A[6]) / det;
+    B[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+    B[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+}
+
+/* SIMPLE setup (Sec. 2.4, aSIMPLE with block-Jacobi blocks): D = diag(F),
+ * F~ = nodal 3x3 diagonal blocks of F, S~ = diag(C - B D^-1 G). */
+static int simple_setup(simple_t *S)
+{
+    int64_t nv = S->nv;
+    const int64_t *rp = S->rowptr;
+    const int32_t *col = S->col;
+    const double *val = S->val;
+    for (int64_t v = 0; v < nv; ++v) {
+        double blk[9];
+        for (int c = 0; c < 3; ++c)
+            for (int d = 0; d < 3; ++d) {
+                int64_t k = find_col(rp, col, 3 * v + c, (int32_t)(3 * v + d));
+                blk[3 * c + d] = (k >= 0) ? val[k] : 0.0;
+            }
+        for (int c = 0; c < 3; ++c) S->Dinv[3 * v + c] = 1.0 / blk[4 * c];
+        inv3(blk, S->Finv + 9 * v);
+    }
+    for (int64_t v = 0; v < nv; ++v) {
+        int64_t r = 3 * nv + v;
+        double s = 0.0, cvv = 0.0;
+        for (int64_t p = rp[r]; p < rp[r + 1]; ++p) {
+            int32_t j = col[p];
+            if (j == r) cvv = val[p];
+            if (j < 3 * nv) {
+                int64_t k = find_col(rp, col, j, (int32_t)r);
+                double gji = (k >= 0) ? val[k] : 0.0;
+                s += val[p] * S->Dinv[j] * gji;
+            }
+        }
+        S->Sinv[v] = 1.0 / (cvv - s);
+    }
+    return 0;
+}
+
+/* z = P^-1 r: z_u = F~^-1 r_u; z_p = S~^-1 (r_p - B z_u); x_u = z_u - D^-1 G z_p. */
+static void simple_apply(const simple_t *S, const double *r, double *x)
+{
+    int64_t nv = S->nv;
+    const int64_t *rp = S->rowptr;
+    const int32_t *col = S->col;
+    const double *val = S->val;
+    double *zu = S->tmp;
+    for (int64_t v = 0; v < nv; ++v)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int d = 0; d < 3; ++d) s += S->Finv[9 * v + 3 * c + d] * r[3 * v + d];
+            zu[3 * v + c] = s;
+        }
+    for (int64_t v = 0; v < nv; ++v) {
+        int64_t row = 3 * nv + v;
+        double s = r[row];
+        for (int64_t p = rp[row]; p < rp[row + 1]; ++p)
+            if (col[p] < 3 * nv) s -= val[p] * zu[col[p]];
+        x[row] = S->Sinv[v] * s;
+    }
+    for (int64_t i = 0; i < 3 * nv; ++i) {
+        double s = 0.0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+            if (col[p] >= 3 * nv) s += val[p] * x[col[p]];
+        x[i] = zu[i] - S->Dinv[i] * s;
+    }
+}
+
+/*
+ * Right-preconditioned restarted GMRES(m) with classical Gram-Schmidt applied
+ * twice, Givens rotations on the Hessenberg matrix, and the SIMPLE
+ * preconditioner.  Stops when ||b - A x|| <= rtol ||b||, checked with the true
+ * residual at every restart.  x holds the initial guess on entry.  Returns the
+ * number of iterations, or -1 if max_iters is reached first.  res_out gets
+ * the final true relative residual.
+ */
+int64_t orc_gmres_simple(int64_t nv, const int64_t *rowptr, const int32_t *col, const double *val,
+                         const double *b, double *x, int32_t m, double rtol, int64_t max_iters,
+                         double *res_out)
+{
+    int64_t N = 4 * nv;
+    simple_t S = {nv, rowptr, col, val, malloc(sizeof(double) * 3 * nv),
+                  malloc(sizeof(double) * 9 * nv), malloc(sizeof(double) * nv),
+                  malloc(sizeof(double) * N)};
+    double *V = malloc(sizeof(double) * (size_t)N * (m + 1));
+    double *w = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N);
+    double *H = calloc((size_t)(m + 1) * m, sizeof(double));
+    double *cs = malloc(sizeof(double) * m), *sn = malloc(sizeof(double) * m);
+    double *gv = malloc(sizeof(double) * (m + 1)), *y = malloc(sizeof(double) * m);
+    double *h1 = malloc(sizeof(double) * (m + 1));
+    simple_setup(&S);
+
+    double bnorm = sqrt(dot(N, b, b));
+    if (bnorm == 0.0) bnorm = 1.0;
+    int64_t it = 0;
+    double rel = 0.0;
+    for (;;) {
+        csr_mv(N, rowptr, col, val, x, w);
+        for (int64_t i = 0; i < N; ++i) w[i] = b[i] - w[i];
+        double beta = sqrt(dot(N, w, w));
+        rel = beta / bnorm;
+        if (rel <= rtol || it >= max_iters) break;
+        for (int64_t i = 0; i < N; ++i) V[i] = w[i] / beta;
+        memset(gv, 0, sizeof(double) * (m + 1));
+        gv[0] = beta;
+        int k = 0;
+        for (; k < m && it < max_iters; ++k, ++it) {
+            double *vk = V + (size_t)k * N, *vn = V + (size_t)(k + 1) * N;
+            simple_apply(&S, vk, z);
+            csr_mv(N, rowptr, col, val, z, w);
+            for (int j = 0; j <= k; ++j) H[j * m + k] = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int j = 0; j <= k; ++j) h1[j] = dot(N, V + (size_t)j * N, w);
+                for (int j = 0; j <= k; ++j) {
+                    const double *vj = V + (size_t)j * N;
+                    for (int64_t i = 0; i < N; ++i) w[i] -= h1[j] * vj[i];
+                    H[j * m + k] += h1[j];
+                }
+            }
+            double hn = sqrt(dot(N, w, w));
+            H[(k + 1) * m + k] = hn;
+            for (int64_t i = 0; i < N; ++i) vn[i] = (hn > 0.0) ? w[i] / hn : 0.0;
+            for (int j = 0; j < k; ++j) {
+                double t = cs[j] * H[j * m + k] + sn[j] * H[(j + 1) * m + k];
+                H[(j + 1) * m + k] = -sn[j] * H[j * m + k] + cs[j] * H[(j + 1) * m + k];
+                H[j * m + k] = t;
+            }
+            double a = H[k * m + k], bb = H[(k + 1) * m + k];
+            double r = hypot(a, bb);
+            cs[k] = a / r;
+            sn[k] = bb / r;
+            H[k * m + k] = r;
+            H[(k + 1) * m + k] = 0.0;
+            gv[k + 1] = -sn[k] * gv[k];
+            gv[k] = cs[k] * gv[k];
+            if (fabs(gv[k + 1]) / bnorm <= rtol || hn == 0.0) { ++k; ++it; break; }
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double s = gv[i];
+            for (int j = i + 1; j < k; ++j) s -= H[i * m + j] * y[j];
+            y[i] = s / H[i * m + i];
+        }
+        memset(w, 0, sizeof(double) * N);
+        for (int j = 0; j < k; ++j) {
+            const double *vj = V + (size_t)j * N;
+            for (int64_t i = 0; i < N; ++i) w[i] += y[j] * vj[i];
+        }
+        simple_apply(&S, w, z);
+        for (int64_t i = 0; i < N; ++i) x[i] += z[i];
+    }
+    if (res_out) *res_out = rel;
+    free(S.Dinv); free(S.Finv); free(S.Sinv); free(S.tmp);
+    free(V); free(w); free(z); free(H); free(cs); free(sn); free(gv); free(y); free(h1);
+    return (rel <= rtol) ? it : -1;
+}

@@ -1,0 +1,415 @@
+"""FP64 CPU oracle: time loop, boundary data and linear solve around the C element
+routines in lxo.c.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU baseline, never by the device library or its binding.
+
+What it computes per step (paper Sec. 2.3 and 2.4; readings listed in lxo.c):
+  1. t^{n+1} = t^n + dt; BDF order min(sigma, number of stored levels); alpha,
+     u_BDF = sum beta_i u^{n-i}, u_EXT = sum gamma_i u^{n-i}, p_EXT likewise.
+  2. ALE (if on): boundary displacement at t^{n+1}, harmonic extension on the
+     reference mesh, x^{n+1} = x^ + d^{n+1}, u_ALE = (alpha d^{n+1} - d_BDF)/dt.
+  3. Element assembly on x^{n+1} (lxo.c), Neumann face terms, Dirichlet rows.
+  4. Solve A x = b exactly (dense LU, or sparse LU), or by the oracle's own
+     GMRES + SIMPLE for large systems; rotate the history.
+"""
+import ctypes
+import os
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+# BDF tables (constant step): alpha, beta (u_BDF weights), gamma (u_EXT weights)
+BDF = {
+    1: (1.0, [1.0], [1.0]),
+    2: (1.5, [2.0, -0.5], [2.0, -1.0]),
+    3: (11.0 / 6.0, [3.0, -1.5, 1.0 / 3.0], [3.0, -3.0, 1.0]),
+}
+
+STAB = {"none": 0, "supg_pspg": 1, "vms_les": 2}
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("sigma", ctypes.c_double), ("dt", ctypes.c_double),
+                ("rho", ctypes.c_double), ("mu", ctypes.c_double), ("C_r", ctypes.c_double),
+                ("stab", ctypes.c_int32), ("symgrad", ctypes.c_int32), ("n_riis", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("riis", ctypes.POINTER(ctypes.c_double))]
+
+
+def lib_path():
+    return os.path.join(_HERE, "liblxo.so")
+
+
+def build(quiet=True):
+    """Compile lxo.c into liblxo.so with gcc (plain C, -O2)."""
+    import subprocess
+    src = os.path.join(_HERE, "lxo.c")
+    cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-o", lib_path(), src, "-lm"]
+    subprocess.check_call(cmd)
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(lib_path()):
+            build()
+        L = ctypes.CDLL(lib_path())
+        P, D, I64, I32 = ctypes.POINTER, ctypes.c_double, ctypes.c_int64, ctypes.c_int32
+        vp = ctypes.c_void_p
+        L.orc_element_p1.restype = D
+        L.orc_element_p1.argtypes = [vp] * 7 + [P(OrcParams), vp, vp]
+        L.orc_vertex_graph.restype = I64
+        L.orc_vertex_graph.argtypes = [I64, I64, I64, vp, vp, vp]
+        L.orc_pattern_p1.restype = None
+        L.orc_pattern_p1.argtypes = [I64, vp, vp, vp, vp]
+        L.orc_assemble_p1.restype = I64
+        L.orc_assemble_p1.argtypes = [I64, I64] + [vp] * 8 + [P(OrcParams)] + [vp] * 4
+        L.orc_neumann_p1.restype = None
+        L.orc_neumann_p1.argtypes = [I64, I64, vp, vp, vp, vp]
+        L.orc_dirichlet_rows.restype = None
+        L.orc_dirichlet_rows.argtypes = [I64, vp, vp, vp, vp, vp, vp]
+        L.orc_gmres_simple.restype = I64
+        L.orc_gmres_simple.argtypes = [I64, vp, vp, vp, vp, vp, I32, D, I64, P(D)]
+        L.orc_tau.restype = None
+        L.orc_tau.argtypes = [P(OrcParams), vp, vp, vp, D, P(D), P(D)]
+        L.orc_delta.restype = D
+        L.orc_delta.argtypes = [D, D]
+        L.orc_valve_distance.restype = D
+        L.orc_valve_distance.argtypes = [vp, vp]
+        L.orc_quad_p1.restype = None
+        L.orc_quad_p1.argtypes = [vp, vp]
+        _LIB = L
+    return _LIB
+
+
+def _p(a):
+    return a.ctypes.data if a is not None else None
+
+
+# ---------------------------------------------------------------- boundary data
+
+def time_law(law, t):
+    """g(t) of Sec. 2.2.1: constant, pulsatile, sinusoidal ramp, and an open-then-close
+    pair of ramps (optionally periodic) for valve schedules."""
+    k, p = law.kind, law.p
+    if k == "constant":
+        return p[0]
+    if k == "pulsatile":
+        gmin, gmax, T = p[:3]
+        return gmin + (gmax - gmin) * 0.5 * (1.0 - np.cos(2.0 * np.pi * t / T))
+    if k == "ramp":
+        g0, g1, t0, tL = p[:4]
+        if t < t0:
+            return g0
+        if t < t0 + tL:
+            return g0 + 0.5 * (g1 - g0) * (1.0 - np.cos(np.pi * (t - t0) / tL))
+        return g1
+    if k == "ramp2":
+        g0, g1, to, do, tc, dc, per = p[:7]
+        tau = np.fmod(t, per) if per > 0 else t
+        if tau < to:
+            return g0
+        if tau < to + do:
+            return g0 + 0.5 * (g1 - g0) * (1.0 - np.cos(np.pi * (tau - to) / do))
+        if tau < tc:
+            return g1
+        if tau < tc + dc:
+            return g1 + 0.5 * (g0 - g1) * (1.0 - np.cos(np.pi * (tau - tc) / dc))
+        return g0
+    raise ValueError(k)
+
+
+def profile_values(prof, X):
+    """s(x) at points X (Sec. 2.2.1): parabolic -2 (R^2 - r^2)/(pi R^4) n with r the
+    distance to the profile centre, or uniform -n."""
+    n = np.asarray(prof.normal, float)
+    if prof.kind == "uniform":
+        return np.broadcast_to(-n, X.shape).copy()
+    if prof.kind == "parabolic":
+        R = prof.radius
+        r2 = np.sum((X - np.asarray(prof.center, float)) ** 2, axis=1)
+        return (-2.0 * (R * R - r2) / (np.pi * R ** 4))[:, None] * n[None, :]
+    raise ValueError(prof.kind)
+
+
+def dirichlet_sets(mesh, prob):
+    """Vertex -> boundary-condition index for Dirichlet-type conditions.  No-slip wins
+    over other Dirichlet data on shared vertices; otherwise the first listed wins."""
+    owner = np.full(mesh.nv, -1, dtype=np.int64)
+    order = [i for i, b in enumerate(prob.bcs) if b.type == "noslip"] + \
+            [i for i, b in enumerate(prob.bcs) if b.type == "dirichlet"]
+    for i in order:
+        b = prob.bcs[i]
+        faces = mesh.bfaces[np.isin(mesh.btags, b.tags)]
+        vs = np.unique(faces.reshape(-1))
+        vs = vs[owner[vs] < 0]
+        owner[vs] = i
+    return owner
+
+
+# ---------------------------------------------------------------- the oracle
+
+class OracleSim:
+    """The oracle's time stepper for the P1-P1 system."""
+
+    def __init__(self, mesh, prob, solve="auto", gmres_rtol=1e-13, restart=30, max_iters=100000):
+        assert prob.fe == "p1p1", "P2-P1 oracle lives in OracleSimP2"
+        self.mesh, self.prob = mesh, prob
+        self.nv = mesh.nv
+        self.xhat = np.ascontiguousarray(mesh.coords, dtype=np.float64)
+        self.x = self.xhat.copy()
+        self.tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
+        self.solve_mode = solve
+        self.gmres_rtol, self.restart, self.max_iters = gmres_rtol, restart, max_iters
+        self.t = prob.t0
+        self.step_index = 0
+        nv = self.nv
+        self.u_hist = [np.zeros((nv, 3))]
+        self.p_hist = [np.zeros(nv)]
+        self.d_hist = [np.zeros((nv, 3))]
+        self.n_levels = 0            # valid history levels (0: start from rest, counts as 1)
+        self.owner = dirichlet_sets(mesh, prob)
+        self.dir_nodal = {}          # bc index -> [nv][3] values at t^{n+1}
+        self.neu_nodal = {}          # bc index -> [nv][3] traction at t^{n+1}
+        self.forcing = None
+        self.ale_shape = np.zeros((nv, 3))
+        L = lib()
+        self.vptr = np.zeros(nv + 1, dtype=np.int64)
+        nadj = L.orc_vertex_graph(nv, mesh.nt, 4, _p(self.tets), None, None)
+        self.vadj = np.zeros(nadj, dtype=np.int32)
+        L.orc_vertex_graph(nv, mesh.nt, 4, _p(self.tets), _p(self.vptr), _p(self.vadj))
+        nnz = 16 * nadj
+        self.rowptr = np.zeros(4 * nv + 1, dtype=np.int64)
+        self.col = np.zeros(nnz, dtype=np.int32)
+        L.orc_pattern_p1(nv, _p(self.vptr), _p(self.vadj), _p(self.rowptr), _p(self.col))
+        self.val = np.zeros(nnz)
+        self.rhs = np.zeros(4 * nv)
+        self.last_iters = 0
+        self.last_res = 0.0
+
+    # ---- state
+    def set_state(self, level, u, p, d=None):
+        while len(self.u_hist) <= level:
+            self.u_hist.append(np.zeros((self.nv, 3)))
+            self.p_hist.append(np.zeros(self.nv))
+            self.d_hist.append(np.zeros((self.nv, 3)))
+        self.u_hist[level] = np.array(u, dtype=np.float64).reshape(self.nv, 3)
+        self.p_hist[level] = np.array(p, dtype=np.float64).reshape(self.nv)
+        if d is not None:
+            self.d_hist[level] = np.array(d, dtype=np.float64).reshape(self.nv, 3)
+        self.n_levels = max(self.n_levels, level + 1)
+        if level == 0 and self.prob.ale:
+            self.x = self.xhat + self.d_hist[0]
+
+    def set_dirichlet_values(self, bc_index, g):
+        self.dir_nodal[bc_index] = np.array(g, dtype=np.float64).reshape(self.nv, 3)
+
+    def set_neumann_traction(self, bc_index, h):
+        self.neu_nodal[bc_index] = np.array(h, dtype=np.float64).reshape(self.nv, 3)
+
+    def set_forcing(self, f):
+        self.forcing = np.array(f, dtype=np.float64).reshape(self.nv, 3)
+
+    def set_ale_displacement(self, d):
+        self.ale_shape = np.array(d, dtype=np.float64).reshape(self.nv, 3)
+
+    # ---- one step
+    def _coeffs(self):
+        order = min(self.prob.bdf_order, max(self.n_levels, 1))
+        alpha, beta, gamma = BDF[order]
+        return order, alpha, beta, gamma
+
+    def _combo(self, hist, w):
+        out = np.zeros_like(hist[0])
+        for i, wi in enumerate(w):
+            out += wi * hist[i]
+        return out
+
+    def _ale_update(self, t1, alpha, beta):
+        """Harmonic extension (alpha = 1 stiffening) of the boundary displacement on the
+        reference mesh; returns d^{n+1} and u_ALE."""
+        from scipy.sparse import coo_matrix
+        from scipy.sparse.linalg import spsolve
+        prob, m = self.prob, self.mesh
+        dB = time_law(prob.ale_law, t1) * self.ale_shape
+        faces = m.bfaces[np.isin(m.btags, prob.ale_tags)]
+        bnodes = np.unique(faces.reshape(-1))
+        K = self.laplacian()
+        K = K.tolil()
+        rhs = np.zeros((self.nv, 3))
+        diag = K.diagonal()
+        for v in bnodes:
+            K.rows[v] = [v]
+            K.data[v] = [diag[v]]
+            rhs[v] = diag[v] * dB[v]
+        K = K.tocsc()
+        d = np.zeros((self.nv, 3))
+        for c in range(3):
+            d[:, c] = spsolve(K, rhs[:, c])
+        dbdf = self._combo(self.d_hist, beta)
+        uale = (alpha * d - dbdf) / prob.dt
+        return d, uale
+
+    def laplacian(self):
+        """P1 stiffness matrix on the reference mesh: int grad phi_a . grad phi_b."""
+        from scipy.sparse import coo_matrix
+        X = self.xhat[self.tets]                                  # [nt][4][3]
+        J = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=2)
+        Jinv = np.linalg.inv(J)
+        vol = np.abs(np.linalg.det(J)) / 6.0
+        grads = np.concatenate([-Jinv.sum(axis=1, keepdims=True), Jinv], axis=1)  # [nt][4][3]
+        Ke = vol[:, None, None] * np.einsum("eaj,ebj->eab", grads, grads)
+        rows = np.repeat(self.tets, 4, axis=1).reshape(-1)
+        cols = np.tile(self.tets, (1, 4)).reshape(-1)
+        return coo_matrix((Ke.reshape(-1), (rows, cols)), shape=(self.nv, self.nv)).tocsr()
+
+    def params(self, order, alpha, t1):
+        prob = self.prob
+        riis = []
+        for v in prob.valves:
+            nrm = np.asarray(v.normal, float)
+            nrm = nrm / np.linalg.norm(nrm)
+            riis += list(v.center) + list(nrm) + [time_law(v.orifice, t1), v.outer_radius, v.R, v.eps]
+        self._riis = np.array(riis if riis else [0.0], dtype=np.float64)
+        P = OrcParams(alpha=alpha, sigma=float(order), dt=prob.dt, rho=prob.rho, mu=prob.mu,
+                      C_r=prob.c_r(), stab=STAB[prob.stab], symgrad=int(prob.diffusion == "symgrad"),
+                      n_riis=len(prob.valves), pad=0,
+                      riis=self._riis.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return P
+
+    def assemble(self):
+        """Build (A, b) of the coming step without solving.  Returns t^{n+1}."""
+        L = lib()
+        prob = self.prob
+        t1 = self.t + prob.dt
+        order, alpha, beta, gamma = self._coeffs()
+        uE = self._combo(self.u_hist, gamma)
+        pE = self._combo(self.p_hist, gamma)
+        uB = self._combo(self.u_hist, beta)
+        if prob.ale:
+            d1, uA = self._ale_update(t1, alpha, beta)
+            x = self.xhat + d1
+        else:
+            d1, uA = None, np.zeros((self.nv, 3))
+            x = self.xhat
+        self._pending_d = d1
+        self.x_next = x
+        self.uA = uA
+        P = self.params(order, alpha, t1)
+        self.val[:] = 0.0
+        self.rhs[:] = 0.0
+        f = self.forcing if prob.forcing else None
+        rc = L.orc_assemble_p1(self.nv, self.mesh.nt, _p(np.ascontiguousarray(x)), _p(self.xhat),
+                               _p(self.tets), _p(np.ascontiguousarray(uE)), _p(np.ascontiguousarray(uB)),
+                               _p(np.ascontiguousarray(uA)), _p(np.ascontiguousarray(pE)),
+                               _p(None if f is None else np.ascontiguousarray(f)), ctypes.byref(P),
+                               _p(self.rowptr), _p(self.col), _p(self.val), _p(self.rhs))
+        if rc != 0:
+            raise RuntimeError("oracle assembly failed at element %d" % (-rc - 1))
+        # Neumann terms
+        for i, b in enumerate(prob.bcs):
+            if b.type != "neumann":
+                continue
+            faces = np.ascontiguousarray(self.mesh.bfaces[np.isin(self.mesh.btags, b.tags)], dtype=np.int32)
+            if b.profile.kind == "nodal":
+                h = self.neu_nodal.get(i)
+                if h is None:
+                    continue
+            else:
+                hv = b.theta * time_law(b.law, t1)
+                if hv == 0.0:
+                    continue
+                h = np.broadcast_to(-hv * np.asarray(b.profile.normal, float), (self.nv, 3))
+            h = np.ascontiguousarray(h, dtype=np.float64)
+            L.orc_neumann_p1(self.nv, len(faces), _p(np.ascontiguousarray(x)), _p(faces), _p(h), _p(self.rhs))
+        # Dirichlet rows
+        rows, gvals = self.dirichlet_rows(t1, x, uA)
+        L.orc_dirichlet_rows(len(rows), _p(rows), _p(gvals), _p(self.rowptr), _p(self.col),
+                             _p(self.val), _p(self.rhs))
+        self.dir_rows, self.dir_vals = rows, gvals
+        return t1
+
+    def dirichlet_values(self, t1, x, uA):
+        """[nv][3] Dirichlet data at t^{n+1} (rows of non-Dirichlet vertices are 0)."""
+        g = np.zeros((self.nv, 3))
+        for i, b in enumerate(self.prob.bcs):
+            vs = np.nonzero(self.owner == i)[0]
+            if len(vs) == 0:
+                continue
+            if b.type == "noslip":
+                g[vs] = uA[vs]
+            elif b.profile.kind == "nodal":
+                g[vs] = self.dir_nodal[i][vs]
+            else:
+                g[vs] = b.theta * time_law(b.law, t1) * profile_values(b.profile, x[vs])
+        return g
+
+    def dirichlet_rows(self, t1, x, uA):
+        g = self.dirichlet_values(t1, x, uA)
+        vs = np.nonzero(self.owner >= 0)[0]
+        rows = (3 * vs[:, None] + np.arange(3)[None, :]).reshape(-1).astype(np.int64)
+        return np.ascontiguousarray(rows), np.ascontiguousarray(g[vs].reshape(-1))
+
+    def matrix(self):
+        from scipy.sparse import csr_matrix
+        N = 4 * self.nv
+        return csr_matrix((self.val.copy(), self.col.copy(), self.rowptr.copy()), shape=(N, N))
+
+    def solve(self, x0=None):
+        N = 4 * self.nv
+        mode = self.solve_mode
+        if mode == "auto":
+            mode = "dense" if N <= 6000 else ("direct" if N <= 150000 else "gmres")
+        if mode == "dense":
+            A = self.matrix().toarray()
+            sol = np.linalg.solve(A, self.rhs)
+            self.last_iters, self.last_res = 0, 0.0
+        elif mode == "direct":
+            from scipy.sparse.linalg import spsolve
+            sol = spsolve(self.matrix().tocsc(), self.rhs)
+            self.last_iters, self.last_res = 0, 0.0
+        else:
+            sol = np.ascontiguousarray(x0.copy() if x0 is not None else np.zeros(N))
+            res = ctypes.c_double(0.0)
+            it = lib().orc_gmres_simple(self.nv, _p(self.rowptr), _p(self.col), _p(self.val),
+                                        _p(self.rhs), _p(sol), self.restart, self.gmres_rtol,
+                                        self.max_iters, ctypes.byref(res))
+            if it < 0:
+                raise RuntimeError("oracle GMRES did not converge (res %.3e)" % res.value)
+            self.last_iters, self.last_res = int(it), res.value
+        return sol
+
+    def step(self):
+        t1 = self.assemble()
+        x0 = np.concatenate([self.u_hist[0].reshape(-1), self.p_hist[0]])
+        sol = self.solve(x0)
+        u = sol[:3 * self.nv].reshape(self.nv, 3).copy()
+        p = sol[3 * self.nv:].copy()
+        self.u_hist = [u] + self.u_hist[: self.prob.bdf_order - 1]
+        self.p_hist = [p] + self.p_hist[: self.prob.bdf_order - 1]
+        if self.prob.ale:
+            self.d_hist = [self._pending_d] + self.d_hist[: self.prob.bdf_order - 1]
+            self.x = self.x_next
+        self.n_levels = min(max(self.n_levels, 1) + 1, self.prob.bdf_order)
+        self.t = t1
+        self.step_index += 1
+        return u, p
+
+    def solution(self):
+        return self.u_hist[0].copy(), self.p_hist[0].copy(), self.t
+
+
+def element_p1(X, Xh, uE, uB, uA, pE, f, alpha=1.0, sigma=1.0, dt=0.01, rho=1.0, mu=0.01, C_r=30.0,
+               stab="vms_les", symgrad=False, valves=()):
+    """Element matrix (16x16) and vector (16) of one P1 element, for unit tests.
+    valves: sequence of 10-tuples (center3, normal3, r_in, r_out, R, eps)."""
+    riis = np.array([x for v in valves for x in v] or [0.0], dtype=np.float64)
+    P = OrcParams(alpha=alpha, sigma=sigma, dt=dt, rho=rho, mu=mu, C_r=C_r, stab=STAB[stab],
+                  symgrad=int(symgrad), n_riis=len(valves), pad=0,
+                  riis=riis.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in (X, Xh, uE, uB, uA, pE, f)]
+    Ke = np.zeros((16, 16))
+    Fe = np.zeros(16)
+    det = lib().orc_element_p1(*[_p(a) for a in arrs], ctypes.byref(P), _p(Ke), _p(Fe))
+    return Ke, Fe, det

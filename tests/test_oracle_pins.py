@@ -1,0 +1,499 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms,
+invariants, exactness properties, brute force on tiny inputs and convergence
+orders printed in the paper.  None of them touches the device library.
+"""
+import ctypes
+import json
+import os
+
+import numpy as np
+import pytest
+
+from inputs import cube_kuhn, tube, exact
+from inputs.problem import Boundary, Profile, Problem, TimeLaw, beltrami_cube_problem
+from inputs.meshes import TUBE_TAGS
+from oracle import OracleSim, element_p1, time_law, profile_values, BDF, lib
+from oracle.oracle import OrcParams
+from oracle.errors import p1_errors, tet_rule
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+rng = np.random.default_rng(12345)
+
+
+def rand_tet(scale=1.0):
+    while True:
+        X = rng.normal(size=(4, 3)) * scale
+        J = np.stack([X[1] - X[0], X[2] - X[0], X[3] - X[0]], axis=1)
+        if abs(np.linalg.det(J)) > 0.05 * scale ** 3:
+            return X
+
+
+def bary_grads(X):
+    """Gradients of the barycentric functions from the 4x4 system [1 x y z] (an
+    independent route to the basis gradients)."""
+    M = np.hstack([np.ones((4, 1)), X])
+    Minv = np.linalg.inv(M)
+    return Minv[1:, :].T, abs(np.linalg.det(M)) / 6.0
+
+
+# ------------------------------------------------------------- quadrature
+
+def test_p1_rule_moments():
+    """The 4-point rule integrates every monomial of degree <= 2 in the barycentric
+    coordinates exactly: int lam^k = k1!k2!k3!k4! 3! / (|k|+3)! |K|."""
+    from math import factorial
+    lam = np.zeros((4, 4))
+    w = np.zeros(4)
+    lib().orc_quad_p1(lam.ctypes.data, w.ctypes.data)
+    assert abs(w.sum() - 1.0) < 1e-15
+    for k in np.ndindex(3, 3, 3, 3):
+        if sum(k) > 2:
+            continue
+        exact_m = np.prod([factorial(x) for x in k]) * 6.0 / factorial(sum(k) + 3) / 6.0
+        quad = np.sum(w * np.prod(lam ** np.array(k)[None, :], axis=1)) / 6.0
+        assert abs(quad - exact_m) < 1e-15, k
+    # and it is NOT exact at degree 3 (confirms the degree claim is tight)
+    assert abs(np.sum(w * lam[:, 0] ** 3) / 6.0 - 6.0 * 6.0 / factorial(6) / 6.0) > 1e-6
+
+
+def test_conical_rule_moments():
+    from math import factorial
+    lam, w = tet_rule(4)       # exact to degree 7
+    for k in np.ndindex(8, 8, 8, 8):
+        if sum(k) > 7:
+            continue
+        exact_m = np.prod([factorial(x) for x in k]) * 6.0 / factorial(sum(k) + 3) / 6.0
+        quad = np.sum(w * np.prod(lam ** np.array(k)[None, :], axis=1))
+        assert abs(quad - exact_m) < 1e-14, k
+
+
+# ------------------------------------------------------------- delta, valves, tau
+
+def test_delta_integral_and_support():
+    L = lib()
+    for eps in (0.05, 0.1, 0.7):
+        xs, ws = np.polynomial.legendre.leggauss(40)
+        phi = eps * xs
+        integral = eps * sum(wi * L.orc_delta(p, eps) for p, wi in zip(phi, ws))
+        assert abs(integral - 1.0) < 1e-12
+        assert L.orc_delta(1.0001 * eps, eps) == 0.0
+        assert L.orc_delta(-1.0001 * eps, eps) == 0.0
+        assert abs(L.orc_delta(0.0, eps) - 1.0 / eps) < 1e-12
+        assert L.orc_delta(0.3 * eps, eps) == L.orc_delta(-0.3 * eps, eps)
+
+
+def test_valve_distance_geometry():
+    L = lib()
+    v = np.array([0, 0, 5, 0, 0, 1, 0.0, 100.0, 1e4, 0.05])       # full disc z = 5
+    for y in ([0.3, -0.2, 5.04], [0.9, 0.1, 4.0], [0, 0, 5]):
+        y = np.array(y, float)
+        assert abs(L.orc_valve_distance(y.ctypes.data, v.ctypes.data) - abs(y[2] - 5)) < 1e-15
+    ann = np.array([1, 2, 3, 1, 0, 0, 0.5, 2.0, 1.0, 0.1])        # annulus normal x, r in [0.5, 2]
+    y = np.array([1.2, 2.0, 3.0])                                 # on axis, 0.2 off plane
+    assert abs(L.orc_valve_distance(y.ctypes.data, ann.ctypes.data) - np.hypot(0.2, 0.5)) < 1e-14
+    y = np.array([0.9, 2.0, 4.0])                                  # r = 1, 0.1 off plane
+    assert abs(L.orc_valve_distance(y.ctypes.data, ann.ctypes.data) - 0.1) < 1e-14
+
+
+def test_tau_reference_element():
+    """J = I: G = I, G:G = 3, g.g = 3.  With u* = 0 and no valve
+    tau_M = (sigma^2 rho^2/dt^2 + 3 C_r mu^2)^(-1/2), tau_C = 1/(3 tau_M)."""
+    for sigma, rho, mu, dt, C_r in ((1, 1.0, 0.01, 0.01, 30.0), (2, 1.06, 0.035, 1e-3, 60.0)):
+        P = OrcParams(alpha=1.0, sigma=sigma, dt=dt, rho=rho, mu=mu, C_r=C_r, stab=2)
+        G = np.eye(3)
+        g = np.ones(3)
+        us = np.zeros(3)
+        tm, tc = ctypes.c_double(), ctypes.c_double()
+        lib().orc_tau(ctypes.byref(P), G.ctypes.data, g.ctypes.data, us.ctypes.data, 0.0,
+                      ctypes.byref(tm), ctypes.byref(tc))
+        ref = (sigma ** 2 * rho ** 2 / dt ** 2 + 3 * C_r * mu ** 2) ** -0.5
+        assert abs(tm.value - ref) / ref < 1e-15
+        assert abs(tc.value - 1.0 / (3 * ref)) * ref * 3 < 1e-14
+        # an advection velocity enters through rho^2 u.G u
+        us = np.array([0.3, -0.4, 1.2])
+        lib().orc_tau(ctypes.byref(P), G.ctypes.data, g.ctypes.data, us.ctypes.data, 2.5,
+                      ctypes.byref(tm), ctypes.byref(tc))
+        ref = (sigma ** 2 * rho ** 2 / dt ** 2 + rho ** 2 * us @ us + 3 * C_r * mu ** 2 + 2.5) ** -0.5
+        assert abs(tm.value - ref) / ref < 1e-15
+
+
+# ------------------------------------------------------------- element matrices
+
+def _fields(n=4):
+    return (rng.normal(size=(n, 3)), rng.normal(size=(n, 3)), rng.normal(size=(n, 3)),
+            rng.normal(size=n), rng.normal(size=(n, 3)))
+
+
+def test_p1_element_closed_form_galerkin():
+    """No stabilisation, u* = 0, no valve: velocity block = (rho alpha/dt) M + mu K per
+    component, with M = |K|(1+delta_ab)/20 and K_ab = |K| grad l_a . grad l_b; G =
+    -|K|/4 d_c l_a; B = |K|/4 d_d l_b; C = 0; rhs = M (f + rho u_BDF/dt)."""
+    X = rand_tet()
+    dl, vol = bary_grads(X)
+    uB, _, _, pE, f = _fields()
+    rho, mu, dt, alpha = 1.3, 0.07, 0.02, 1.5
+    Ke, Fe, det = element_p1(X, X, np.zeros((4, 3)), uB, np.zeros((4, 3)), pE, f, alpha=alpha,
+                             sigma=2, dt=dt, rho=rho, mu=mu, stab="none")
+    assert abs(abs(det) / 6 - vol) < 1e-14 * vol
+    M = vol * (np.ones((4, 4)) + np.eye(4)) / 20.0
+    K = vol * dl @ dl.T
+    ref = np.zeros((16, 16))
+    for a in range(4):
+        for b in range(4):
+            for c in range(3):
+                ref[3 * a + c, 3 * b + c] = rho * alpha / dt * M[a, b] + mu * K[a, b]
+            for c in range(3):
+                ref[3 * a + c, 12 + b] = -vol / 4 * dl[a, c]
+                ref[12 + a, 3 * b + c] = vol / 4 * dl[b, c]
+    scale = np.abs(ref).max()
+    assert np.abs(Ke - ref).max() < 1e-13 * scale
+    rhs = np.zeros(16)
+    for a in range(4):
+        for c in range(3):
+            rhs[3 * a + c] = sum(M[a, b] * (f[b, c] + rho * uB[b, c] / dt) for b in range(4))
+    assert np.abs(Fe - rhs).max() < 1e-13 * np.abs(rhs).max()
+
+
+def test_p1_element_invariants():
+    X = rand_tet()
+    uE, uB, uA, pE, f = _fields()
+    # diffusion annihilates constants, symmetric; advection annihilates constants
+    Kd, _, _ = element_p1(X, X, np.zeros((4, 3)), uB, np.zeros((4, 3)), pE, f, dt=1e300, mu=0.3,
+                          stab="none")
+    Fv = Kd[:12, :12]
+    assert np.abs(Fv - Fv.T).max() < 1e-15 * np.abs(Fv).max()
+    assert np.abs(Fv @ np.tile([1.0, 0, 0], 4)).max() < 1e-13 * np.abs(Fv).max()
+    Ka, _, _ = element_p1(X, X, uE, uB, uA, pE, f, dt=1e300, mu=0.0, stab="none")
+    for c in range(3):
+        ones = np.zeros(12)
+        ones[c::3] = 1.0
+        assert np.abs(Ka[:12, :12] @ ones).max() < 1e-13 * np.abs(Ka).max()
+    # symmetric-gradient diffusion: rigid rotation field is in its kernel only with
+    # the symmetric form; check the extra term is mu d_c phi_b d_d phi_a
+    Ks, _, _ = element_p1(X, X, np.zeros((4, 3)), uB, np.zeros((4, 3)), pE, f, dt=1e300, mu=0.3,
+                          stab="none", symgrad=True)
+    dl, vol = bary_grads(X)
+    extra = np.zeros((12, 12))
+    for a in range(4):
+        for b in range(4):
+            for c in range(3):
+                for d in range(3):
+                    extra[3 * a + c, 3 * b + d] = 0.3 * vol * dl[b, c] * dl[a, d]
+    assert np.abs(Ks[:12, :12] - Kd[:12, :12] - extra).max() < 1e-13 * np.abs(extra).max()
+    # pressure-pressure block (PSPG): symmetric, PSD, annihilates constants
+    Kf, _, _ = element_p1(X, X, uE, uB, uA, pE, f, stab="vms_les")
+    C = Kf[12:, 12:]
+    assert np.abs(C - C.T).max() < 1e-14 * np.abs(C).max()
+    assert np.linalg.eigvalsh(0.5 * (C + C.T)).min() > -1e-13 * np.abs(C).max()
+    assert np.abs(C @ np.ones(4)).max() < 1e-13 * np.abs(C).max()
+    # the stabilised pressure-gradient columns sum to the Galerkin ones (grad of constants)
+    K0, _, _ = element_p1(X, X, uE, uB, uA, pE, f, stab="none")
+    assert np.abs(Kf[:12, 12:].sum(axis=1) - K0[:12, 12:].sum(axis=1)).max() < 1e-12 * np.abs(Kf).max()
+
+
+def test_p1_element_rigid_motion():
+    """Rotating and translating the element together with all vector data (and the
+    valve) rotates the element matrix: Ke' = P Ke P^T with P = diag(Q,Q,Q,Q,I4)."""
+    X = rand_tet()
+    uE, uB, uA, pE, f = _fields()
+    A = rng.normal(size=(3, 3))
+    Q, _ = np.linalg.qr(A)
+    t0 = rng.normal(size=3)
+    valve = np.array([0.1, 0.2, 0.0, 0, 0, 1, 0.0, 50.0, 30.0, 0.8])
+    Kr, Fr, _ = element_p1(X, X, uE, uB, uA, pE, f, valves=[valve], dt=0.05)
+    Xq = X @ Q.T + t0
+    vq = valve.copy()
+    vq[:3] = Q @ valve[:3] + t0
+    vq[3:6] = Q @ valve[3:6]
+    Kq, Fq, _ = element_p1(Xq, Xq, uE @ Q.T, uB @ Q.T, uA @ Q.T, pE, f @ Q.T, valves=[vq], dt=0.05)
+    P = np.zeros((16, 16))
+    for a in range(4):
+        P[3 * a:3 * a + 3, 3 * a:3 * a + 3] = Q
+    P[12:, 12:] = np.eye(4)
+    assert np.abs(Kq - P @ Kr @ P.T).max() < 1e-11 * np.abs(Kr).max()
+    assert np.abs(Fq - P @ Fr).max() < 1e-11 * np.abs(Fr).max()
+
+
+def test_p1_stabilisation_consistency():
+    """For an exact affine steady solution (div-free u, affine p, matching forcing, exact
+    history) the strong residual vanishes at every quadrature point, so the SUPG/PSPG/
+    VMS/LES and grad-div contributions to the element residual Ke x - Fe must cancel:
+    the stabilised and unstabilised residuals coincide."""
+    X = rand_tet()
+    ex = exact.Affine([[0.3, 0.5, -0.2], [0.1, -0.7, 0.4], [0.6, 0.2, 0.4]], u0=(0.2, -0.1, 0.3),
+                      q=(0.3, -0.2, 0.5), p0=1.0, rho=1.2, mu=0.04)
+    u = ex.velocity(X)
+    p = ex.pressure(X)
+    f = ex.forcing(X)
+    xe = np.concatenate([u.reshape(-1), p])
+    for stab in ("supg_pspg", "vms_les"):
+        Ks, Fs, _ = element_p1(X, X, u, u, np.zeros((4, 3)), p, f, rho=1.2, mu=0.04, stab=stab)
+        K0, F0, _ = element_p1(X, X, u, u, np.zeros((4, 3)), p, f, rho=1.2, mu=0.04, stab="none")
+        r_s = Ks @ xe - Fs
+        r_0 = K0 @ xe - F0
+        assert np.abs(r_s - r_0).max() < 1e-10 * np.abs(Fs).max(), stab
+        # and the stabilisation does change the matrix (the check is not vacuous)
+        assert np.abs(Ks - K0).max() > 1e-3 * np.abs(K0).max()
+
+
+def test_riis_zero_resistance_bitwise():
+    X = rand_tet()
+    uE, uB, uA, pE, f = _fields()
+    Kn, Fn, _ = element_p1(X, X, uE, uB, uA, pE, f)
+    valve = np.array([0, 0, 0, 0, 0, 1, 0.0, 100.0, 0.0, 5.0])   # R = 0, eps covers the tet
+    Kv, Fv, _ = element_p1(X, X, uE, uB, uA, pE, f, valves=[valve])
+    assert np.array_equal(Kn, Kv) and np.array_equal(Fn, Fv)
+    valve[8] = 100.0
+    Kv, Fv, _ = element_p1(X, X, uE, uB, uA, pE, f, valves=[valve])
+    assert not np.array_equal(Kn, Kv)
+
+
+# ------------------------------------------------------------- BDF
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_bdf_exactness(order):
+    """BDF_s differentiates polynomials of degree <= s exactly; the extrapolation of the
+    same order reproduces polynomials of degree <= s-1."""
+    alpha, beta, gamma = BDF[order]
+    dt, tn1 = 0.1, 1.7
+    ts = [tn1 - dt * (i + 1) for i in range(order)]
+    for k in range(order + 1):
+        d = (alpha * tn1 ** k - sum(b * t ** k for b, t in zip(beta, ts))) / dt
+        assert abs(d - k * tn1 ** max(k - 1, 0) * (k > 0)) < 1e-11
+        if k <= order - 1:
+            e = sum(g * t ** k for g, t in zip(gamma, ts))
+            assert abs(e - tn1 ** k) < 1e-12
+    assert abs(alpha - sum(beta)) < 1e-15 and abs(sum(gamma) - 1.0) < 1e-15
+
+
+def test_time_laws():
+    assert time_law(TimeLaw("constant", (2.5,)), 3.0) == 2.5
+    pl = TimeLaw("pulsatile", (1.0, 5.0, 0.8))
+    assert abs(time_law(pl, 0.0) - 1.0) < 1e-15 and abs(time_law(pl, 0.4) - 5.0) < 1e-14
+    rp = TimeLaw("ramp", (1.0, 3.0, 0.2, 0.1))
+    assert time_law(rp, 0.1) == 1.0 and abs(time_law(rp, 0.25) - 2.0) < 1e-14 and time_law(rp, 0.4) == 3.0
+    r2 = TimeLaw("ramp2", (0.0, 2.0, 0.1, 0.1, 0.5, 0.2, 1.0))
+    assert time_law(r2, 0.05) == 0.0 and abs(time_law(r2, 0.15) - 1.0) < 1e-14
+    assert time_law(r2, 0.3) == 2.0 and abs(time_law(r2, 0.6) - 1.0) < 1e-14
+    assert time_law(r2, 0.9) == 0.0 and abs(time_law(r2, 1.15) - 1.0) < 1e-14
+
+
+def test_parabolic_profile_unit_flow_rate():
+    """Parabolic profile has unit flow rate through a disc of radius R (Sec. 2.2.1 remark)."""
+    R = 1.3
+    prof = Profile("parabolic", center=(0, 0, 0), normal=(0, 0, -1), radius=R)
+    r, w = np.polynomial.legendre.leggauss(20)
+    r = 0.5 * R * (r + 1)
+    w = 0.5 * R * w
+    X = np.stack([r, np.zeros_like(r), np.zeros_like(r)], axis=1)
+    s = profile_values(prof, X)
+    q = np.sum(w * 2 * np.pi * r * s[:, 2])
+    assert abs(q - 1.0) < 1e-13
+    assert np.allclose(profile_values(Profile("uniform", normal=(1, 0, 0)), X), [-1, 0, 0])
+
+
+# ------------------------------------------------------------- global assembly
+
+def test_global_assembly_equals_dense_sum():
+    """The CSR assembly equals a brute-force dense sum of element matrices (1 Kuhn cube
+    with a jittered interior-free mesh and random fields, full VMS-LES with a valve)."""
+    mesh = tube(nxy=2, nz=2, radius=1.0, length=1.0, seed=3)
+    nv = mesh.nv
+    prob = Problem(stab="vms_les", dt=0.03, mu=0.02)
+    sim = OracleSim(mesh, prob)
+    u0 = rng.normal(size=(nv, 3))
+    p0 = rng.normal(size=nv)
+    sim.set_state(0, u0, p0)
+    from inputs.problem import Valve
+    prob.valves = [Valve(center=(0, 0, 0.5), normal=(0, 0, 1), outer_radius=5, orifice=TimeLaw(),
+                         R=50.0, eps=0.4)]
+    sim.assemble()
+    A = sim.matrix().toarray()
+    dense = np.zeros((4 * nv, 4 * nv))
+    rhs = np.zeros(4 * nv)
+    valve = np.array([0, 0, 0.5, 0, 0, 1, 0.0, 5.0, 50.0, 0.4])
+    for e in range(mesh.nt):
+        v = mesh.tets[e]
+        X = mesh.coords[v]
+        Ke, Fe, _ = element_p1(X, X, u0[v], u0[v], np.zeros((4, 3)), p0[v], np.zeros((4, 3)),
+                               alpha=1.0, sigma=1, dt=0.03, mu=0.02, valves=[valve])
+        g = np.concatenate([(3 * v[:, None] + np.arange(3)).reshape(-1), 3 * nv + v])
+        dense[np.ix_(g, g)] += Ke
+        rhs[g] += Fe
+    # Dirichlet-free problem (no BCs given): compare directly
+    assert np.abs(A - dense).max() < 1e-12 * np.abs(dense).max()
+    assert np.abs(sim.rhs - rhs).max() < 1e-12 * np.abs(rhs).max()
+
+
+def test_discrete_gradient_of_constants():
+    """Sum over pressure columns of interior velocity rows vanishes (the Galerkin part
+    integrates d_c phi_a over the support of phi_a; the stabilised part has
+    sum_b grad psi_b = 0)."""
+    mesh = tube(nxy=4, nz=6, radius=1.0, length=3.0, seed=5)
+    nv = mesh.nv
+    sim = OracleSim(mesh, Problem(stab="vms_les", dt=0.01, mu=0.03))
+    sim.set_state(0, rng.normal(size=(nv, 3)), rng.normal(size=nv))
+    sim.assemble()
+    A = sim.matrix().tocsr()
+    bnd = np.zeros(nv, bool)
+    bnd[np.unique(mesh.bfaces)] = True
+    inner = np.nonzero(~bnd)[0]
+    rows = (3 * inner[:, None] + np.arange(3)).reshape(-1)
+    Gsum = np.asarray(A[rows][:, 3 * nv:].sum(axis=1)).ravel()
+    assert np.abs(Gsum).max() < 1e-12 * np.abs(A[:, 3 * nv:]).max()
+    assert len(inner) > 10
+
+
+# ------------------------------------------------------------- full steps
+
+def _patch_run(field, bdf_order=1, steps=2, solve="dense", history=None):
+    """Run a jittered, shuffled tube with Dirichlet data from `field` on inlet and wall and
+    its exact traction on the outlet.  Returns max nodal errors (u, p)."""
+    mesh = tube(nxy=3, nz=4, radius=1.0, length=2.0, seed=11)
+    X = mesh.coords
+    bcs = [Boundary("dirichlet", (TUBE_TAGS["inlet"], TUBE_TAGS["wall"]), profile=Profile("nodal")),
+           Boundary("neumann", (TUBE_TAGS["outlet"],), profile=Profile("nodal", normal=(0, 0, 1)))]
+    prob = Problem(bdf_order=bdf_order, dt=0.05, rho=field.rho, mu=field.mu, stab="vms_les",
+                   forcing=True, bcs=bcs)
+    sim = OracleSim(mesh, prob, solve=solve)
+    for lev in range(bdf_order):
+        tl = -lev * prob.dt
+        sim.set_state(lev, field.velocity(X, tl), field.pressure(X, tl))
+    for _ in range(steps):
+        t1 = sim.t + prob.dt
+        sim.set_dirichlet_values(0, field.velocity(X, t1))
+        sim.set_neumann_traction(1, field.traction(X, t1, (0, 0, 1)))
+        sim.set_forcing(field.forcing(X, t1))
+        u, p = sim.step()
+    return (np.abs(u - field.velocity(X, sim.t)).max() / np.abs(field.velocity(X, sim.t)).max(),
+            np.abs(p - field.pressure(X, sim.t)).max() / max(np.abs(field.pressure(X, sim.t)).max(), 1e-300))
+
+
+@pytest.mark.parametrize("name", ["constant", "couette", "stagnation", "general"])
+def test_patch_affine_exact(name):
+    f = {"constant": exact.constant_flow(), "couette": exact.couette(), "stagnation": exact.stagnation(),
+         "general": exact.Affine([[0.3, 0.5, -0.2], [0.1, -0.7, 0.4], [0.6, 0.2, 0.4]],
+                                 u0=(0.2, -0.1, 0.3), q=(0.3, -0.2, 0.5), p0=1.0, mu=0.04)}[name]
+    eu, ep = _patch_run(f)
+    assert eu < 1e-10
+    if name == "general":
+        assert ep < 1e-9
+
+
+class _TimePoly:
+    """u = (a + b t + c t^2, 0, 0) uniform in space, p = 0, f = rho (b + 2 c t) e_x."""
+
+    def __init__(self, a, b, c, rho=1.0, mu=0.02):
+        self.a, self.b, self.c, self.rho, self.mu = a, b, c, rho, mu
+
+    def velocity(self, X, t):
+        u = np.zeros_like(X)
+        u[:, 0] = self.a + self.b * t + self.c * t * t
+        return u
+
+    def pressure(self, X, t):
+        return np.zeros(X.shape[0])
+
+    def forcing(self, X, t):
+        f = np.zeros_like(X)
+        f[:, 0] = self.rho * (self.b + 2 * self.c * t)
+        return f
+
+    def traction(self, X, t, n):
+        return np.zeros_like(X)
+
+
+@pytest.mark.parametrize("order,c", [(1, 0.0), (2, 0.0), (2, 0.7), (3, 0.7)])
+def test_bdf_full_step_exact_in_time(order, c):
+    """With exact history the step reproduces a spatially uniform flow polynomial in
+    time up to the BDF order (quadratic needs order >= 2)."""
+    eu, _ = _patch_run(_TimePoly(0.4, 1.3, c), bdf_order=order, steps=3)
+    assert eu < 1e-10
+
+
+def test_oracle_gmres_matches_dense():
+    mesh, prob = beltrami_cube_problem(3)
+    ex = exact.Beltrami(mu=prob.mu)
+    X = mesh.coords
+    sols = []
+    for mode in ("dense", "gmres"):
+        sim = OracleSim(mesh, prob, solve=mode, gmres_rtol=1e-14)
+        sim.set_state(0, ex.velocity(X, 0.0), ex.pressure(X, 0.0))
+        sim.set_dirichlet_values(0, ex.velocity(X, prob.dt))
+        sim.set_neumann_traction(1, ex.traction(X, prob.dt, (-1, 0, 0)))
+        u, p = sim.step()
+        sols.append(np.concatenate([u.ravel(), p]))
+    assert np.linalg.norm(sols[0] - sols[1]) / np.linalg.norm(sols[0]) < 1e-10
+
+
+def test_beltrami_is_navier_stokes():
+    """The retyped Beltrami fields satisfy div u = 0 and the momentum equation with zero
+    forcing, checked by 4th-order finite differences (independent of the analytic grad)."""
+    ex = exact.Beltrami(mu=0.01)
+    P = rng.uniform(0, 1, size=(20, 3))
+    t, h = 0.3, 1e-3
+
+    def d(fn, k):
+        e = np.zeros(3)
+        e[k] = h
+        return (-fn(P + 2 * e) + 8 * fn(P + e) - 8 * fn(P - e) + fn(P - 2 * e)) / (12 * h)
+
+    U = lambda Y: ex.velocity(Y, t)
+    div = sum(d(U, k)[:, k] for k in range(3))
+    assert np.abs(div).max() < 1e-9
+    G = np.stack([d(U, k) for k in range(3)], axis=2)          # G[:, i, k] = d u_i / d x_k
+    assert np.abs(G - ex.grad(P, t)).max() < 1e-9
+    ut = (-ex.velocity(P, t + 2 * h) + 8 * ex.velocity(P, t + h) - 8 * ex.velocity(P, t - h)
+          + ex.velocity(P, t - 2 * h)) / (12 * h)
+    gp = np.stack([d(lambda Y: ex.pressure(Y, t), k) for k in range(3)], axis=1)
+    lap = np.zeros_like(ut)
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        lap += (-U(P + 2 * e) + 16 * U(P + e) - 30 * U(P) + 16 * U(P - e) - U(P - 2 * e)) / (12 * h * h)
+    u = U(P)
+    res = ut + np.einsum("nik,nk->ni", G, u) + gp / ex.rho - ex.nu * lap
+    assert np.abs(res).max() < 1e-6
+
+
+def _beltrami_errors(n, dt=1e-2, steps=10):
+    mesh, prob = beltrami_cube_problem(n, dt=dt)
+    ex = exact.Beltrami(mu=prob.mu)
+    X = mesh.coords
+    sim = OracleSim(mesh, prob, solve="gmres" if n > 8 else "dense")
+    sim.set_state(0, ex.velocity(X, 0.0), ex.pressure(X, 0.0))
+    for _ in range(steps):
+        t1 = sim.t + prob.dt
+        sim.set_dirichlet_values(0, ex.velocity(X, t1))
+        sim.set_neumann_traction(1, ex.traction(X, t1, (-1, 0, 0)))
+        u, p = sim.step()
+    return np.array(p1_errors(X, mesh.tets, u, p, ex, sim.t))
+
+
+def test_beltrami_space_rates_p1():
+    """Errors against the exact solution decrease at the paper's expected orders
+    (golden/convergence_orders.json) between h = 1/4 and h = 1/8."""
+    orders = json.load(open(os.path.join(GOLDEN, "convergence_orders.json")))["p1p1"]
+    e4 = _beltrami_errors(4)
+    e8 = _beltrami_errors(8)
+    rates = np.log2(e4 / e8)
+    assert rates[0] > orders["u_L2"] - 0.15
+    assert rates[1] > orders["u_H1"] - 0.1
+    assert rates[2] > orders["p_L2"] - 0.2
+    assert e8[0] < 0.01
+
+
+def test_harmonic_extension_linear_exact():
+    """The lifting reproduces a linear boundary displacement exactly in the bulk."""
+    mesh = tube(nxy=4, nz=4, radius=1.0, length=2.0, seed=9)
+    prob = Problem(ale=True, ale_tags=(1, 2, 3), ale_law=TimeLaw("constant", (1.0,)))
+    sim = OracleSim(mesh, prob)
+    Lm = np.array([[0.01, 0.02, -0.01], [0.0, -0.03, 0.02], [0.01, 0.0, 0.02]])
+    sim.set_ale_displacement(mesh.coords @ Lm.T + np.array([0.1, -0.2, 0.05]))
+    order, alpha, beta, _ = sim._coeffs()
+    d, uale = sim._ale_update(0.01, alpha, beta)
+    ref = mesh.coords @ Lm.T + np.array([0.1, -0.2, 0.05])
+    assert np.abs(d - ref).max() < 1e-12
+    assert np.abs(uale - ref / 0.01).max() < 1e-9
