@@ -1,0 +1,306 @@
+/*
+ * lxns.h -- C ABI of the MI355X (gfx950) library for one semi-implicit BDF time
+ * step of the VMS-LES-stabilised incompressible Navier-Stokes equations on
+ * tetrahedral meshes, with RIIS resistive immersed valves and ALE mesh motion
+ * (Africa et al., "lifex-cfd", arXiv 2304.12032).
+ *
+ * Every call returns an lx_status; nothing throws or aborts across the ABI.
+ * On a negative status, lx_last_error() returns a thread-local message that is
+ * valid until the next call on the same thread.
+ *
+ * Conventions for all calls:
+ *   - All array arguments are HOST pointers to caller-owned memory.  Inputs are
+ *     copied before the call returns; the caller may free them afterwards.
+ *     Outputs are written into caller buffers whose sizes follow lx_sim_query.
+ *   - Layouts: coordinates and vector fields are node-major [n][3] doubles;
+ *     pressure is [n_vertices] doubles; connectivity is [n_tets][4] int32,
+ *     0-based.  Vertex ids are the caller's; the library renumbers internally
+ *     and maps back on output.
+ *   - The library owns all device memory it allocates (hipMalloc on the
+ *     device named in lx_device) and frees it in the matching destroy call.
+ *   - Work is queued on the stream given in lx_device (NULL: the library
+ *     creates its own); calls that return host data synchronise that stream.
+ *   - Units are the caller's, used consistently (the synthetic vascular cases
+ *     are in CGS).
+ */
+#ifndef LXNS_H
+#define LXNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LX_OK = 0,
+    LX_EINVAL = -1,    /* bad argument or unsupported option                         */
+    LX_ENOMEM = -2,    /* host or device allocation failed                           */
+    LX_EDEVICE = -3,   /* HIP runtime error                                          */
+    LX_ENOCONV = -4,   /* GMRES / refinement missed its tolerance; state NOT advanced */
+    LX_EMESH = -5,     /* degenerate tetrahedron (|det J| <= 1e-14 h^3) or bad ids    */
+    LX_EBUSY = -6,     /* request exceeds the server's device-memory budget           */
+    LX_ESTATE = -7     /* call not valid in the object's current state               */
+} lx_status;
+
+const char *lx_last_error(void);
+
+/* ------------------------------------------------------------------ inputs */
+
+typedef struct {
+    int32_t device;      /* HIP device ordinal                                       */
+    void *hip_stream;    /* hipStream_t to queue work on, or NULL                    */
+} lx_device;
+
+/* Mesh (the paper's mesh input, Sec. 3.1): reference configuration x^ and a
+ * labelled boundary. */
+typedef struct {
+    int64_t n_vertices, n_tets, n_bfaces;
+    const double *coords;     /* [n_vertices][3] reference coordinates x^       */
+    const int32_t *tets;      /* [n_tets][4]; the local vertex order is kept and
+                                 defines the element map of the unit simplex     */
+    const int32_t *bfaces;    /* [n_bfaces][3] vertex ids of boundary triangles  */
+    const int32_t *bface_tag; /* [n_bfaces] boundary tags                       */
+} lx_mesh;
+
+/* Time laws g(t) of Sec. 2.2.1. */
+enum {
+    LX_LAW_CONSTANT = 0,  /* p = {g}                                                  */
+    LX_LAW_PULSATILE = 1, /* p = {gmin, gmax, period}: gmin + (gmax-gmin)(1-cos 2pi t/T)/2 */
+    LX_LAW_RAMP = 2,      /* p = {g0, g1, t0, tL}: sinusoidal ramp from g0 to g1         */
+    LX_LAW_RAMP2 = 3      /* p = {g0, g1, t_open, dur_open, t_close, dur_close, period}:
+                             ramp up then back down, repeated every period if > 0      */
+};
+typedef struct {
+    int32_t kind;
+    int32_t pad;
+    double p[8];
+} lx_time_law;
+
+/* Space profiles s(x) of Sec. 2.2.1. */
+enum {
+    LX_PROFILE_UNIFORM = 0,   /* s = -n                                               */
+    LX_PROFILE_PARABOLIC = 1, /* s = -2 (R^2 - r^2)/(pi R^4) n, unit flow rate        */
+    LX_PROFILE_NODAL = 2      /* values supplied per step (lx_sim_set_dirichlet_values /
+                                 lx_sim_set_neumann_traction)                          */
+};
+typedef struct {
+    int32_t kind;
+    int32_t pad;
+    double center[3];         /* r = |x - center|                                     */
+    double normal[3];         /* outward unit normal n of the boundary portion        */
+    double radius;            /* R of the parabolic profile                           */
+} lx_profile;
+
+/* Boundary conditions, Sec. 2.2: no-slip u = u_ALE (or 0), Dirichlet
+ * u = theta g(t) s(x), Neumann sigma(u,p) n = -theta h(t) n (uniform profile)
+ * or a nodal traction vector (nodal profile).  Where conditions share a
+ * vertex, no-slip wins, then the first Dirichlet condition in the list. */
+enum { LX_BC_NOSLIP = 0, LX_BC_DIRICHLET = 1, LX_BC_NEUMANN = 2 };
+typedef struct {
+    int32_t type;
+    int32_t n_tags;
+    const int32_t *tags;
+    double theta;
+    lx_time_law law;
+    lx_profile profile;
+} lx_boundary;
+
+/* RIIS immersed surface (Sec. 2.1.2, eq. (riis)): an annular disc (center, unit
+ * normal, outer radius, central orifice radius following a time law) with
+ * resistance R and half-thickness eps.  The distance is measured at the
+ * reference position of each quadrature point, so the surface moves with the
+ * mesh; the surface velocity u_Sigma is zero. */
+typedef struct {
+    double center[3];
+    double normal[3];
+    double outer_radius;
+    lx_time_law orifice_radius;
+    double R, eps;
+} lx_riis;
+
+enum { LX_P1P1 = 1, LX_P2P1 = 2 };
+enum { LX_DIFF_GRADGRAD = 0, LX_DIFF_SYMGRAD = 1 };              /* eq. (diffusion-term) */
+enum { LX_STAB_NONE = 0, LX_STAB_SUPG_PSPG = 1, LX_STAB_VMS_LES = 2 };
+
+/* The problem of Sec. 2.1-2.3: FE pair, BDF order (1..3) and time step (eq. (bdf)),
+ * density and viscosity, diffusion form, stabilisation with constant C_r of
+ * tau_M, semi-implicit advection (the only mode), ALE on/off with the boundary
+ * displacement d^ = ale_law(t) * D^(x^) on the vertices of faces tagged ale_tags
+ * (D^ set by lx_sim_set_ale_displacement), nodal forcing on/off. */
+typedef struct {
+    int32_t fe, bdf_order;
+    double dt, t0, rho, mu;
+    int32_t diffusion, stab;
+    double C_r;
+    int32_t semi_implicit;   /* must be 1                                            */
+    int32_t ale;             /* 0 | 1                                                */
+    int32_t forcing;         /* 0: f = 0; 1: nodal f from lx_sim_set_forcing        */
+    int32_t n_bc;
+    const lx_boundary *bc;
+    int32_t n_riis;
+    int32_t n_ale_tags;
+    const lx_riis *riis;
+    const int32_t *ale_tags;
+    lx_time_law ale_law;
+} lx_problem;
+
+enum { LX_FP64 = 0, LX_FP32_IR = 1 };
+/* Linear solver (Sec. 2.4): right-preconditioned restarted GMRES(restart) with
+ * the SIMPLE block preconditioner (D = diag(F), F~ = nodal 3x3 diagonal blocks
+ * of F, S~ = C - B D^{-1} G); stop when ||b - A x|| <= rtol ||b||.  The Schur
+ * block S~^{-1} is applied as diag(S~)^{-1} (schur_degree = 0) or as a
+ * Chebyshev iteration of degree schur_degree on S~ z = t with diagonal
+ * scaling over [lam / schur_ratio, lam], lam the Gershgorin bound of
+ * diag(S~)^{-1} S~.  LX_FP32_IR: FP32 matrix and FP32 inner GMRES inside an
+ * FP64 iterative refinement loop that stops when the FP64 residual satisfies
+ * ir_rtol; inner solves aim at one more refinement step but never tighter
+ * than inner_rtol. */
+typedef struct {
+    int32_t precision, restart, max_iters, max_ir;
+    double rtol, ir_rtol, inner_rtol;
+    int32_t deterministic;   /* reserved; the scatter uses device atomics          */
+    int32_t collect_timing;  /* 1: record per-kernel HIP events (SpMV, assembly)   */
+    int32_t schur_degree;    /* 0..32                                               */
+    int32_t asm_fp64;        /* LX_FP32_IR only: 1 = build the FP32 matrix by FP64
+                                element arithmetic and scatter, rounded to FP32;
+                                0 = FP32 element arithmetic and FP32 scatter       */
+    double schur_ratio;      /* > 1                                                  */
+} lx_solver;
+
+/* ---------------------------------------------------------------- outputs */
+
+typedef struct {
+    int64_t n_vertices, n_tets, n_u_nodes, n_dofs, n_blocks;
+    int64_t device_bytes;    /* device memory held by the simulation              */
+} lx_sizes;
+
+typedef struct {
+    int32_t gmres_iters;      /* total (inner) GMRES iterations of the step           */
+    int32_t ir_iters;         /* refinement iterations (0 for FP64)                   */
+    int32_t restarts;
+    int32_t converged;
+    double rel_residual;      /* final true FP64 ||b - A x|| / ||b||                  */
+    double t_step_ms;         /* wall time of the step on the stream (HIP events)     */
+    double t_assembly_ms;     /* assembly + scatter + Dirichlet + SIMPLE setup        */
+    double t_solve_ms;
+    double spmv_ms;           /* summed SpMV kernel time (collect_timing = 1)         */
+    int64_t spmv_calls;
+    double asm_ms;            /* assembly-kernel time (collect_timing = 1)            */
+    int64_t asm_calls;
+    double resid_ms;          /* FP64 matrix-free residual kernel time                */
+    int64_t resid_calls;
+} lx_step_stats;
+
+typedef struct lx_sim lx_sim;
+
+/* Create a simulation: validates the mesh (LX_EMESH on a degenerate tet or an
+ * id out of range), renumbers vertices (reverse Cuthill-McKee) and elements,
+ * builds the shared block-CSR pattern, element->slot maps and boundary lists,
+ * and uploads everything to the device.  History starts at rest (u = p = 0)
+ * at time problem->t0. */
+lx_status lx_sim_create(const lx_device *dev, const lx_mesh *mesh, const lx_problem *problem,
+                        const lx_solver *solver, lx_sim **out);
+
+lx_status lx_sim_query(const lx_sim *sim, lx_sizes *out);
+
+/* Set history level `level` (0 = u^n, 1 = u^{n-1}, ...): u [n_vertices][3],
+ * p [n_vertices], optional ALE displacement d [n_vertices][3] (NULL: 0).
+ * The BDF order used at a step is min(bdf_order, levels set or computed). */
+lx_status lx_sim_set_state(lx_sim *sim, int32_t level, const double *u, const double *p,
+                           const double *d);
+lx_status lx_sim_set_time(lx_sim *sim, double t);
+
+/* Nodal data for a boundary condition with a nodal profile, at t^{n+1} of the
+ * next step: Dirichlet values or Neumann traction vectors, [n_vertices][3]
+ * (only the rows of that condition's vertices are read). */
+lx_status lx_sim_set_dirichlet_values(lx_sim *sim, int32_t bc_index, const double *g);
+lx_status lx_sim_set_neumann_traction(lx_sim *sim, int32_t bc_index, const double *h);
+/* Forcing f at t^{n+1}, [n_vertices][3] (problem.forcing = 1). */
+lx_status lx_sim_set_forcing(lx_sim *sim, const double *f);
+/* ALE boundary-displacement shape D^ [n_vertices][3] (rows of ALE boundary
+ * vertices are read); the displacement at t is ale_law(t) * D^ (Sec. 2.1.1). */
+lx_status lx_sim_set_ale_displacement(lx_sim *sim, const double *d);
+
+/* Advance one time step (paper's fully discrete problem, Sec. 2.3): boundary
+ * data at t^{n+1}, ALE lifting and mesh velocity, element assembly and
+ * scatter, Dirichlet rows, SIMPLE setup, GMRES (or FP32 GMRES inside FP64
+ * refinement), history rotation.  Transactional: on LX_ENOCONV the state and
+ * time are left unchanged.  stats may be NULL. */
+lx_status lx_sim_step(lx_sim *sim, lx_step_stats *stats);
+
+/* Copy the current solution to caller buffers: u [n_vertices][3], p
+ * [n_vertices], t (any may be NULL).  Synchronises the stream. */
+lx_status lx_sim_get_solution(const lx_sim *sim, double *u, double *p, double *t);
+
+/* Parity export (tests only): assemble the system of the coming step without
+ * solving and copy it out in the caller's numbering as block COO with 4x4
+ * blocks (row-major within the block: rows u_x,u_y,u_z,p; cols likewise):
+ * brow/bcol [n_blocks], vals [n_blocks][16], rhs [n_vertices][4].  Values are
+ * FP64 (FP32 matrices are widened).  rhs is zero for FP32 precision. */
+lx_status lx_sim_debug_export(lx_sim *sim, int32_t *brow, int32_t *bcol, double *vals, double *rhs);
+
+/* FP64 matrix-free residual b - A x of the coming step at the caller's state
+ * x = (u [n][3], p [n]), written to r [n_vertices][4] (tests only). */
+lx_status lx_sim_debug_residual(lx_sim *sim, const double *u, const double *p, double *r);
+
+void lx_sim_destroy(lx_sim *sim);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A continuous-batching server: requests (mesh + problem + solver + step
+ * count) are admitted while the device-memory budget and the active-slot limit
+ * allow, stepped together on the device with their work interleaved on a pool
+ * of streams, and retired when done; new requests are admitted as memory and
+ * slots free up. */
+typedef struct {
+    lx_device device;
+    int64_t hbm_budget_bytes;   /* admission limit on summed simulation footprints */
+    int32_t max_active;         /* slot limit                                        */
+    int32_t n_streams;          /* streams the active simulations are spread over    */
+} lx_server_cfg;
+
+typedef struct {
+    lx_mesh mesh;
+    lx_problem problem;
+    lx_solver solver;
+    int32_t n_steps;
+    int32_t pad;
+} lx_request;
+
+enum { LX_REQ_QUEUED = 0, LX_REQ_RUNNING = 1, LX_REQ_DONE = 2, LX_REQ_FAILED = 3 };
+typedef struct {
+    int32_t state;
+    int32_t steps_done;
+    int64_t footprint_bytes;
+} lx_request_status;
+
+typedef struct {
+    double admit_wait_ms;       /* submission to admission                          */
+    double total_ms;            /* submission to completion                         */
+    double step_p50_ms, step_p99_ms;  /* per step: eligible -> completed            */
+    int32_t n_steps;
+    int32_t gmres_iters;
+} lx_latency_stats;
+
+typedef struct lx_server lx_server;
+
+lx_status lx_server_create(const lx_server_cfg *cfg, lx_server **out);
+/* Copies the request's arrays; returns a ticket.  LX_EBUSY if the request alone
+ * exceeds the budget. */
+lx_status lx_server_submit(lx_server *srv, const lx_request *req, int64_t *ticket);
+/* Run one scheduling tick: admit what fits, advance every active simulation by
+ * one step, retire finished ones.  *n_active gets the active count afterwards. */
+lx_status lx_server_tick(lx_server *srv, int32_t *n_active);
+lx_status lx_server_poll(lx_server *srv, int64_t ticket, lx_request_status *st);
+/* Copy a finished request's solution (u [n][3], p [n], caller numbering) and
+ * latency statistics, then release it.  LX_ESTATE if not done. */
+lx_status lx_server_result(lx_server *srv, int64_t ticket, double *u, double *p,
+                           lx_latency_stats *lat);
+void lx_server_destroy(lx_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LXNS_H */

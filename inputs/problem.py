@@ -86,6 +86,10 @@ class SolverCfg:
     ir_rtol: float = 1e-8
     inner_rtol: float = 1e-4
     deterministic: bool = True
+    collect_timing: bool = False
+    schur_degree: int = 8
+    schur_ratio: float = 100.0
+    asm_fp64: bool = False
 
 
 # ----------------------------------------------------------------- configs

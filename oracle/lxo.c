@@ -468,6 +468,10 @@ typedef struct {
     double *Finv;    /* [nv][9] inverse nodal 3x3 blocks    */
     double *Sinv;    /* [nv]  1/diag(C - B D^-1 G)          */
     double *tmp;     /* [4nv] work                          */
+    int32_t degree;  /* Chebyshev degree for S~^{-1}; 0: diagonal only */
+    double ratio;    /* lambda_max / lambda_min of the Chebyshev interval */
+    double lam_max;  /* Gershgorin bound of diag(S~)^{-1} S~ */
+    double *cw;      /* [6nv] Chebyshev work: r, d, y(3), t */
 } simple_t;
 
 static void inv3(const double A[9], double B[9])
@@ -517,7 +521,76 @@ static int simple_setup(simple_t *S)
         }
         S->Sinv[v] = 1.0 / (cvv - s);
     }
+    /* Gershgorin bound of diag(S~)^{-1} S~ with S~ = C - B D^{-1} G (not formed):
+       row v: (sum |C_vw| + sum_(w,d) |B_v,(w,d)| sum_u |G_(w,d),u| / |D_(w,d)|) / |S~_vv| */
+    S->lam_max = 0.0;
+    if (S->degree > 0) {
+        double *ag = S->cw;   /* [3nv] */
+        for (int64_t r = 0; r < 3 * nv; ++r) {
+            double a = 0.0;
+            for (int64_t p = rp[r]; p < rp[r + 1]; ++p)
+                if (col[p] >= 3 * nv) a += fabs(val[p]);
+            ag[r] = a * fabs(S->Dinv[r]);
+        }
+        for (int64_t v = 0; v < nv; ++v) {
+            int64_t r = 3 * nv + v;
+            double a = 0.0;
+            for (int64_t p = rp[r]; p < rp[r + 1]; ++p)
+                a += (col[p] >= 3 * nv) ? fabs(val[p]) : fabs(val[p]) * ag[col[p]];
+            a *= fabs(S->Sinv[v]);
+            if (a > S->lam_max) S->lam_max = a;
+        }
+    }
     return 0;
+}
+
+/* y = S~ d = C d - B D^{-1} G d for a pressure vector d (matrix-free). */
+static void schur_mv(const simple_t *S, const double *d, double *gu, double *y)
+{
+    int64_t nv = S->nv;
+    const int64_t *rp = S->rowptr;
+    const int32_t *col = S->col;
+    const double *val = S->val;
+    for (int64_t r = 0; r < 3 * nv; ++r) {
+        double a = 0.0;
+        for (int64_t p = rp[r]; p < rp[r + 1]; ++p)
+            if (col[p] >= 3 * nv) a += val[p] * d[col[p] - 3 * nv];
+        gu[r] = S->Dinv[r] * a;
+    }
+    for (int64_t v = 0; v < nv; ++v) {
+        int64_t r = 3 * nv + v;
+        double a = 0.0;
+        for (int64_t p = rp[r]; p < rp[r + 1]; ++p)
+            a += (col[p] >= 3 * nv) ? val[p] * d[col[p] - 3 * nv] : -val[p] * gu[col[p]];
+        y[v] = a;
+    }
+}
+
+/* z ~= S~^{-1} t: Chebyshev iteration of the given degree on S~ z = t with
+   diagonal scaling, started from z = 0, for eigenvalues of diag(S~)^{-1} S~ in
+   [lam_max / ratio, lam_max] (Saad, Iterative Methods, Alg. 12.1). */
+static void schur_cheb(const simple_t *S, const double *t, double *z)
+{
+    int64_t nv = S->nv;
+    double *r = S->cw, *d = S->cw + nv, *gu = S->cw + 2 * nv, *q = S->cw + 5 * nv;
+    double lmax = S->lam_max, lmin = lmax / S->ratio;
+    double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+    double sigma = theta / delta, rho = 1.0 / sigma;
+    for (int64_t v = 0; v < nv; ++v) {
+        r[v] = t[v];
+        d[v] = S->Sinv[v] * r[v] / theta;
+        z[v] = d[v];
+    }
+    for (int i = 1; i < S->degree; ++i) {
+        schur_mv(S, d, gu, q);
+        double rho_new = 1.0 / (2.0 * sigma - rho);
+        for (int64_t v = 0; v < nv; ++v) {
+            r[v] -= q[v];
+            d[v] = rho_new * rho * d[v] + 2.0 * rho_new / delta * S->Sinv[v] * r[v];
+            z[v] += d[v];
+        }
+        rho = rho_new;
+    }
 }
 
 /* z = P^-1 r: z_u = F~^-1 r_u; z_p = S~^-1 (r_p - B z_u); x_u = z_u - D^-1 G z_p. */
@@ -539,7 +612,14 @@ static void simple_apply(const simple_t *S, const double *r, double *x)
         double s = r[row];
         for (int64_t p = rp[row]; p < rp[row + 1]; ++p)
             if (col[p] < 3 * nv) s -= val[p] * zu[col[p]];
-        x[row] = S->Sinv[v] * s;
+        x[row] = s;
+    }
+    if (S->degree > 0) {
+        double *t = S->cw + 6 * nv;
+        memcpy(t, x + 3 * nv, sizeof(double) * nv);
+        schur_cheb(S, t, x + 3 * nv);
+    } else {
+        for (int64_t v = 0; v < nv; ++v) x[3 * nv + v] *= S->Sinv[v];
     }
     for (int64_t i = 0; i < 3 * nv; ++i) {
         double s = 0.0;
@@ -552,19 +632,22 @@ static void simple_apply(const simple_t *S, const double *r, double *x)
 /*
  * Right-preconditioned restarted GMRES(m) with classical Gram-Schmidt applied
  * twice, Givens rotations on the Hessenberg matrix, and the SIMPLE
- * preconditioner.  Stops when ||b - A x|| <= rtol ||b||, checked with the true
+ * preconditioner (Sec. 2.4) whose Schur block S~ = C - B D^{-1} G is inverted
+ * either by its diagonal (cheb_degree = 0) or by a Chebyshev polynomial of
+ * the given degree in diag(S~)^{-1} S~.  Stops when ||b - A x|| <= rtol ||b||, checked with the true
  * residual at every restart.  x holds the initial guess on entry.  Returns the
  * number of iterations, or -1 if max_iters is reached first.  res_out gets
  * the final true relative residual.
  */
 int64_t orc_gmres_simple(int64_t nv, const int64_t *rowptr, const int32_t *col, const double *val,
                          const double *b, double *x, int32_t m, double rtol, int64_t max_iters,
-                         double *res_out)
+                         int32_t cheb_degree, double cheb_ratio, double *res_out)
 {
     int64_t N = 4 * nv;
     simple_t S = {nv, rowptr, col, val, malloc(sizeof(double) * 3 * nv),
                   malloc(sizeof(double) * 9 * nv), malloc(sizeof(double) * nv),
-                  malloc(sizeof(double) * N)};
+                  malloc(sizeof(double) * N), cheb_degree, cheb_ratio, 0.0,
+                  malloc(sizeof(double) * 7 * nv)};
     double *V = malloc(sizeof(double) * (size_t)N * (m + 1));
     double *w = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N);
     double *H = calloc((size_t)(m + 1) * m, sizeof(double));
@@ -632,7 +715,7 @@ int64_t orc_gmres_simple(int64_t nv, const int64_t *rowptr, const int32_t *col, 
         for (int64_t i = 0; i < N; ++i) x[i] += z[i];
     }
     if (res_out) *res_out = rel;
-    free(S.Dinv); free(S.Finv); free(S.Sinv); free(S.tmp);
+    free(S.Dinv); free(S.Finv); free(S.Sinv); free(S.tmp); free(S.cw);
     free(V); free(w); free(z); free(H); free(cs); free(sn); free(gv); free(y); free(h1);
     return (rel <= rtol) ? it : -1;
 }

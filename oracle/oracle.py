@@ -70,7 +70,7 @@ def lib():
         L.orc_dirichlet_rows.restype = None
         L.orc_dirichlet_rows.argtypes = [I64, vp, vp, vp, vp, vp, vp]
         L.orc_gmres_simple.restype = I64
-        L.orc_gmres_simple.argtypes = [I64, vp, vp, vp, vp, vp, I32, D, I64, P(D)]
+        L.orc_gmres_simple.argtypes = [I64, vp, vp, vp, vp, vp, I32, D, I64, I32, D, P(D)]
         L.orc_tau.restype = None
         L.orc_tau.argtypes = [P(OrcParams), vp, vp, vp, D, P(D), P(D)]
         L.orc_delta.restype = D
@@ -153,7 +153,8 @@ def dirichlet_sets(mesh, prob):
 class OracleSim:
     """The oracle's time stepper for the P1-P1 system."""
 
-    def __init__(self, mesh, prob, solve="auto", gmres_rtol=1e-13, restart=30, max_iters=100000):
+    def __init__(self, mesh, prob, solve="auto", gmres_rtol=1e-13, restart=30, max_iters=100000,
+                 schur_degree=8, schur_ratio=100.0):
         assert prob.fe == "p1p1", "P2-P1 oracle lives in OracleSimP2"
         self.mesh, self.prob = mesh, prob
         self.nv = mesh.nv
@@ -162,6 +163,7 @@ class OracleSim:
         self.tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
         self.solve_mode = solve
         self.gmres_rtol, self.restart, self.max_iters = gmres_rtol, restart, max_iters
+        self.schur_degree, self.schur_ratio = schur_degree, schur_ratio
         self.t = prob.t0
         self.step_index = 0
         nv = self.nv
@@ -374,7 +376,8 @@ class OracleSim:
             res = ctypes.c_double(0.0)
             it = lib().orc_gmres_simple(self.nv, _p(self.rowptr), _p(self.col), _p(self.val),
                                         _p(self.rhs), _p(sol), self.restart, self.gmres_rtol,
-                                        self.max_iters, ctypes.byref(res))
+                                        self.max_iters, self.schur_degree, self.schur_ratio,
+                                        ctypes.byref(res))
             if it < 0:
                 raise RuntimeError("oracle GMRES did not converge (res %.3e)" % res.value)
             self.last_iters, self.last_res = int(it), res.value

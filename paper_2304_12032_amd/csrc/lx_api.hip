@@ -1,0 +1,251 @@
+// C ABI entry points for lx_sim (see include/lxns.h).
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lx_sim.h"
+
+using lx::fail;
+
+#define LX_GUARD(sim)                                                   \
+    do {                                                                \
+        if (!(sim)) return fail(LX_EINVAL, "simulation handle is NULL"); \
+    } while (0)
+
+extern "C" lx_status lx_sim_create(const lx_device *dev, const lx_mesh *mesh, const lx_problem *problem,
+                                   const lx_solver *solver, lx_sim **out)
+{
+    if (!out) return fail(LX_EINVAL, "out is NULL");
+    *out = nullptr;
+    lx_sim *s = new (std::nothrow) lx_sim();
+    if (!s) return fail(LX_ENOMEM, "host allocation failed");
+    lx_status st;
+    try {
+        st = s->create(dev, mesh, problem, solver);
+    } catch (const std::bad_alloc &) {
+        st = fail(LX_ENOMEM, "host allocation failed during setup");
+    }
+    if (st != LX_OK) {
+        delete s;
+        return st;
+    }
+    *out = s;
+    return LX_OK;
+}
+
+extern "C" lx_status lx_sim_query(const lx_sim *s, lx_sizes *out)
+{
+    LX_GUARD(s);
+    if (!out) return fail(LX_EINVAL, "out is NULL");
+    out->n_vertices = s->nv;
+    out->n_tets = s->nt;
+    out->n_u_nodes = s->nv;
+    out->n_dofs = s->N;
+    out->n_blocks = s->nblk;
+    out->device_bytes = s->device_bytes;
+    return LX_OK;
+}
+
+// caller [n][3] + [n] -> internal [nv][4]
+static void to_internal(const lx_sim *s, const double *u, const double *p, std::vector<double> &x)
+{
+    x.assign(4 * s->nv, 0.0);
+    for (int64_t i = 0; i < s->nv; ++i) {
+        const int64_t o = s->hs.perm_v[i];
+        for (int c = 0; c < 3; ++c) x[4 * i + c] = u ? u[3 * o + c] : 0.0;
+        x[4 * i + 3] = p ? p[o] : 0.0;
+    }
+}
+
+extern "C" lx_status lx_sim_set_state(lx_sim *s, int32_t level, const double *u, const double *p, const double *d)
+{
+    LX_GUARD(s);
+    if (level < 0 || level >= s->prob.bdf_order) return fail(LX_EINVAL, "level must be in [0, bdf_order)");
+    (void)hipSetDevice(s->device);
+    std::vector<double> x;
+    to_internal(s, u, p, x);
+    LX_HIP(hipMemcpyAsync(s->d_hist[level], x.data(), sizeof(double) * x.size(), hipMemcpyHostToDevice, s->stream));
+    if (d && s->prob.ale) {
+        std::vector<double> dd(3 * s->nv);
+        for (int64_t i = 0; i < s->nv; ++i)
+            for (int c = 0; c < 3; ++c) dd[3 * i + c] = d[3 * (int64_t)s->hs.perm_v[i] + c];
+        LX_HIP(hipMemcpyAsync(s->d_dhist[level], dd.data(), sizeof(double) * dd.size(), hipMemcpyHostToDevice,
+                              s->stream));
+        LX_HIP(hipStreamSynchronize(s->stream));
+    }
+    LX_HIP(hipStreamSynchronize(s->stream));
+    s->nlev = std::max(s->nlev, level + 1);
+    return LX_OK;
+}
+
+extern "C" lx_status lx_sim_set_time(lx_sim *s, double t)
+{
+    LX_GUARD(s);
+    s->t = t;
+    return LX_OK;
+}
+
+extern "C" lx_status lx_sim_set_dirichlet_values(lx_sim *s, int32_t bc, const double *g)
+{
+    LX_GUARD(s);
+    if (bc < 0 || bc >= (int32_t)s->bcs.size() || !g) return fail(LX_EINVAL, "bad bc index or NULL values");
+    const lx_boundary &b = s->bcs[bc].spec;
+    if (b.type != LX_BC_DIRICHLET || b.profile.kind != LX_PROFILE_NODAL)
+        return fail(LX_EINVAL, "bc %d is not a Dirichlet condition with a nodal profile", bc);
+    for (int64_t k = 0; k < s->n_dir; ++k) {
+        if (s->h_dir_bc[k] != bc) continue;
+        const int64_t o = s->hs.perm_v[s->h_dir_node[k]];
+        for (int c = 0; c < 3; ++c) s->h_gnodal[3 * k + c] = g[3 * o + c];
+    }
+    s->dirty_gnodal = true;
+    return LX_OK;
+}
+
+static lx_status upload_nodal3(lx_sim *s, const double *src, double *dst)
+{
+    std::vector<double> h(3 * s->nv);
+    for (int64_t i = 0; i < s->nv; ++i)
+        for (int c = 0; c < 3; ++c) h[3 * i + c] = src[3 * (int64_t)s->hs.perm_v[i] + c];
+    LX_HIP(hipMemcpyAsync(dst, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s->stream));
+    LX_HIP(hipStreamSynchronize(s->stream));
+    return LX_OK;
+}
+
+extern "C" lx_status lx_sim_set_neumann_traction(lx_sim *s, int32_t bc, const double *h)
+{
+    LX_GUARD(s);
+    if (bc < 0 || bc >= (int32_t)s->bcs.size() || !h) return fail(LX_EINVAL, "bad bc index or NULL values");
+    auto &b = s->bcs[bc];
+    if (b.spec.type != LX_BC_NEUMANN || b.spec.profile.kind != LX_PROFILE_NODAL)
+        return fail(LX_EINVAL, "bc %d is not a Neumann condition with a nodal profile", bc);
+    if (!b.d_hnodal) return LX_OK;   // no faces carry this tag
+    (void)hipSetDevice(s->device);
+    lx_status st = upload_nodal3(s, h, b.d_hnodal);
+    if (st == LX_OK) b.nodal_set = true;
+    return st;
+}
+
+extern "C" lx_status lx_sim_set_forcing(lx_sim *s, const double *f)
+{
+    LX_GUARD(s);
+    if (!s->prob.forcing || !s->d_f) return fail(LX_ESTATE, "problem was created without nodal forcing");
+    if (!f) return fail(LX_EINVAL, "f is NULL");
+    (void)hipSetDevice(s->device);
+    return upload_nodal3(s, f, s->d_f);
+}
+
+extern "C" lx_status lx_sim_set_ale_displacement(lx_sim *s, const double *d)
+{
+    LX_GUARD(s);
+    if (!s->prob.ale) return fail(LX_ESTATE, "problem was created without ALE");
+    if (!d) return fail(LX_EINVAL, "d is NULL");
+    (void)hipSetDevice(s->device);
+    lx_status st = upload_nodal3(s, d, s->d_ale_shape);
+    if (st == LX_OK) s->ale_ext_valid = false;
+    return st;
+}
+
+extern "C" lx_status lx_sim_step(lx_sim *s, lx_step_stats *stats)
+{
+    LX_GUARD(s);
+    try {
+        return s->step(stats);
+    } catch (const std::bad_alloc &) {
+        return fail(LX_ENOMEM, "host allocation failed");
+    }
+}
+
+extern "C" lx_status lx_sim_get_solution(const lx_sim *s, double *u, double *p, double *t)
+{
+    LX_GUARD(s);
+    (void)hipSetDevice(s->device);
+    std::vector<double> x(4 * s->nv);
+    LX_HIP(hipMemcpyAsync(x.data(), s->d_hist[0], sizeof(double) * x.size(), hipMemcpyDeviceToHost, s->stream));
+    LX_HIP(hipStreamSynchronize(s->stream));
+    for (int64_t i = 0; i < s->nv; ++i) {
+        const int64_t o = s->hs.perm_v[i];
+        if (u)
+            for (int c = 0; c < 3; ++c) u[3 * o + c] = x[4 * i + c];
+        if (p) p[o] = x[4 * i + 3];
+    }
+    if (t) *t = s->t;
+    return LX_OK;
+}
+
+// 4x4 block entry (r, c) -> plane
+static inline int plane_of(int r, int c)
+{
+    if (r < 3 && c < 3) return 3 * r + c;
+    if (r < 3) return 9 + r;
+    if (c < 3) return 12 + c;
+    return 15;
+}
+
+extern "C" lx_status lx_sim_debug_export(lx_sim *s, int32_t *brow, int32_t *bcol, double *vals, double *rhs)
+{
+    LX_GUARD(s);
+    (void)hipSetDevice(s->device);
+    lx::StepCoef C;
+    lx_step_stats S;
+    memset(&S, 0, sizeof(S));
+    lx_status st = s->build_system(s->t + s->prob.dt, C, S);
+    if (st != LX_OK) return st;
+    const int64_t nb = s->nblk;
+    std::vector<double> planes(16 * nb);
+    if (s->solver.precision == LX_FP64) {
+        LX_HIP(hipMemcpyAsync(planes.data(), s->d_val64, sizeof(double) * 16 * nb, hipMemcpyDeviceToHost, s->stream));
+    } else {
+        std::vector<float> p32(16 * nb);
+        LX_HIP(hipMemcpyAsync(p32.data(), s->d_val32, sizeof(float) * 16 * nb, hipMemcpyDeviceToHost, s->stream));
+        LX_HIP(hipStreamSynchronize(s->stream));
+        for (int64_t i = 0; i < 16 * nb; ++i) planes[i] = p32[i];
+    }
+    std::vector<double> r(4 * s->nv, 0.0);
+    if (s->solver.precision == LX_FP64)
+        LX_HIP(hipMemcpyAsync(r.data(), s->d_rhs64, sizeof(double) * r.size(), hipMemcpyDeviceToHost, s->stream));
+    LX_HIP(hipStreamSynchronize(s->stream));
+    for (int64_t i = 0; i < s->nv; ++i) {
+        const int32_t oi = s->hs.perm_v[i];
+        for (int32_t k = s->hs.rowptr[i]; k < s->hs.rowptr[i + 1]; ++k) {
+            if (brow) brow[k] = oi;
+            if (bcol) bcol[k] = s->hs.perm_v[s->hs.col[k]];
+            if (vals)
+                for (int a = 0; a < 4; ++a)
+                    for (int b = 0; b < 4; ++b) vals[16 * (int64_t)k + 4 * a + b] = planes[plane_of(a, b) * nb + k];
+        }
+        if (rhs)
+            for (int c = 0; c < 4; ++c) rhs[4 * (int64_t)oi + c] = r[4 * i + c];
+    }
+    return LX_OK;
+}
+
+extern "C" lx_status lx_sim_debug_residual(lx_sim *s, const double *u, const double *p, double *r)
+{
+    LX_GUARD(s);
+    if (!r) return fail(LX_EINVAL, "r is NULL");
+    (void)hipSetDevice(s->device);
+    if (!s->d_r64) {
+        lx_status a = s->dalloc((void **)&s->d_r64, sizeof(double) * s->N);
+        if (a != LX_OK) return a;
+        a = s->dalloc((void **)&s->d_b64, sizeof(double) * s->N);
+        if (a != LX_OK) return a;
+    }
+    lx::StepCoef C;
+    lx_status st = s->prepare(s->t + s->prob.dt, C);
+    if (st != LX_OK) return st;
+    std::vector<double> x;
+    to_internal(s, u, p, x);
+    LX_HIP(hipMemcpyAsync(s->d_xs, x.data(), sizeof(double) * x.size(), hipMemcpyHostToDevice, s->stream));
+    st = s->residual64(C, s->d_xs, true, s->t + s->prob.dt);
+    if (st != LX_OK) return st;
+    std::vector<double> h(4 * s->nv);
+    LX_HIP(hipMemcpyAsync(h.data(), s->d_r64, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s->stream));
+    LX_HIP(hipStreamSynchronize(s->stream));
+    for (int64_t i = 0; i < s->nv; ++i) {
+        const int64_t o = s->hs.perm_v[i];
+        for (int c = 0; c < 4; ++c) r[4 * o + c] = h[4 * i + c];
+    }
+    return LX_OK;
+}
+
+extern "C" void lx_sim_destroy(lx_sim *s) { delete s; }

@@ -1,0 +1,84 @@
+// Device-side helpers shared by the kernel translation units.
+#pragma once
+
+#include "lx_common.h"
+
+namespace lx {
+
+struct __align__(32) v4d { double v[4]; };
+struct __align__(16) v4f { float v[4]; };
+template <typename T> struct V4;
+template <> struct V4<double> { using type = v4d; };
+template <> struct V4<float> { using type = v4f; };
+
+__device__ inline double lx_cos(double x) { return cos(x); }
+__device__ inline float lx_cos(float x) { return cosf(x); }
+__device__ inline double lx_sqrt(double x) { return sqrt(x); }
+__device__ inline float lx_sqrt(float x) { return sqrtf(x); }
+
+__device__ inline void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ inline void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+
+template <typename T, int LPR>
+__device__ inline T group_sum(T v)
+{
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, LPR);
+    return v;
+}
+
+constexpr int kRedThreads = 256;
+
+// Sums K per-thread values over the block; the result is valid in thread 0.
+template <int K>
+__device__ inline void block_sum(double (&acc)[K], double *lds)
+{
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < K; ++j) lds[j * 4 + wid] = acc[j];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[j] = (lds[j * 4] + lds[j * 4 + 1]) + (lds[j * 4 + 2] + lds[j * 4 + 3]);
+}
+
+// Arrival protocol: every block publishes its partial sums, then the last block
+// to arrive reduces all partials in a fixed order (deterministic) and resets
+// the counter.
+__device__ inline bool arrive_last(uint32_t *counter)
+{
+    __shared__ int is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t prev = atomicAdd(counter, 1u);
+        is_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (is_last) __threadfence();
+    return is_last != 0;
+}
+
+// Final reduction of partial[nb][K] (stride K) in the last block.
+template <int K>
+__device__ inline void reduce_partials(const double *partial, int nb, int count, double (&out)[K], double *lds)
+{
+#pragma unroll
+    for (int j = 0; j < K; ++j) out[j] = 0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < count) out[j] += partial[(int64_t)b * K + j];
+    block_sum<K>(out, lds);
+}
+
+template <typename T>
+__device__ inline double to_d(T v) { return (double)v; }
+
+}  // namespace lx

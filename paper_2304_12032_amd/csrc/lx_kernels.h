@@ -1,0 +1,121 @@
+// Device kernels of the step and their host launchers.
+#pragma once
+
+#include "lx_common.h"
+
+namespace lx {
+
+// Block values are stored as 16 planes of length nblk ("SoA" block-CSR):
+// plane 3c+d holds F[c][d] (velocity-velocity), 9+c holds G[c] (velocity row,
+// pressure column), 12+d holds B[d] (pressure row, velocity column), 15 holds
+// C.  Vectors are [nv][4] = (u_x, u_y, u_z, p) per vertex.
+constexpr int kPlanes = 16;
+
+template <typename T>
+struct AsmArgs {
+    int64_t nt, nblk;
+    const int32_t *tet;    // [4][nt]
+    const int32_t *eslot;  // [16][nt]
+    const double *x;       // [nv][3] current coordinates
+    const double *xh;      // [nv][3] reference coordinates
+    const double *h0, *h1, *h2;  // history levels [nv][4]
+    const double *uA;      // [nv][3] ALE velocity or null
+    const double *f;       // [nv][3] forcing or null
+    T *val;                // planes
+    T *rhs;                // [nv][4] or null
+};
+
+struct ResArgs {
+    int64_t nt;
+    const int32_t *tet;
+    const double *x, *xh, *h0, *h1, *h2, *uA, *f;
+    const double *xs;        // iterate [nv][4]
+    const int32_t *dir_index;  // [nv] Dirichlet index or -1
+    double *r;               // [nv][4] accumulates b - A xs (non-Dirichlet rows)
+    double *b;               // [nv][4] accumulates b, or null
+    double *dg;              // [n_dir][3] accumulates FP64 diagonal of Dirichlet rows, or null
+};
+
+struct RowPattern {
+    int64_t nv, nblk;
+    const int32_t *rowptr, *col, *diag, *tslot;
+};
+
+template <typename T>
+void launch_assemble_p1(const AsmArgs<T> &a, const StepCoef &c, hipStream_t s);
+void launch_residual_p1(const ResArgs &a, const StepCoef &c, hipStream_t s);
+
+void launch_dirichlet_values(int64_t n_dir, const int32_t *dir_node, const int32_t *dir_bc,
+                             const BCSet &bcs, const double *x, const double *uA,
+                             const double *gnodal, double *g, hipStream_t s);
+template <typename T>
+void launch_dirichlet_rows(int64_t n_dir, const int32_t *dir_node, const double *g,
+                           const RowPattern &P, T *val, T *rhs, hipStream_t s);
+void launch_dirichlet_residual(int64_t n_dir, const int32_t *dir_node, const double *g,
+                               const double *dg, const double *xs, double *r, double *b,
+                               hipStream_t s);
+void launch_neumann(int64_t nf, const int32_t *faces, const double *x, const double *hnodal,
+                    const double hconst[3], double *out0, double *out1, float *out32,
+                    hipStream_t s);
+
+template <typename T>
+void launch_simple_setup(const RowPattern &P, const T *val, T *Finv, T *Dinv, T *Sinv, hipStream_t s);
+// st->lam_max = Gershgorin bound of diag(S~)^{-1} S~, S~ = C - B D^{-1} G (not formed);
+// work: 4 nv entries of T.
+template <typename T>
+void launch_schur_bound(const RowPattern &P, const T *val, const T *Dinv, const T *Sinv, T *work,
+                        GmState *st, double *partial, int nb, hipStream_t s);
+
+// The SIMPLE preconditioner's operands.  degree = 0: S~^{-1} ~ diag(S~)^{-1};
+// degree k > 0: k-step Chebyshev iteration on S~ z = t with diagonal scaling on
+// [lam_max / ratio, lam_max] (work: 6 nv entries of T).
+template <typename T>
+struct Simple {
+    const T *val, *Finv, *Dinv, *Sinv;
+    int degree;
+    double ratio;
+    T *work;
+    const GmState *st;
+};
+// z <- SIMPLE^{-1} (scale * r), scale = *scale_ptr (or 1 if null)
+template <typename T>
+void launch_simple_apply(const RowPattern &P, const Simple<T> &S, const T *r, const double *scale_ptr, T *z,
+                         const int32_t *done, hipStream_t s);
+template <typename T>
+void launch_spmv(const RowPattern &P, const T *val, const T *x, T *y, const int32_t *done,
+                 hipStream_t s);
+
+// GMRES building blocks (vectors of length n = 4 nv, basis stride ldv).
+template <typename T>
+void launch_gm_start(int64_t n, const T *b, const T *Ax, T *V0, GmState *st, double *partial,
+                     int nb, hipStream_t s);
+template <typename T>
+void launch_gm_dot1(int64_t n, int k, const T *V, int64_t ldv, const T *w, GmState *st,
+                    double *partial, int nb, hipStream_t s);
+template <typename T>
+void launch_gm_axpy_dot2(int64_t n, int k, const T *V, int64_t ldv, T *w, GmState *st,
+                         double *partial, int nb, hipStream_t s);
+template <typename T>
+void launch_gm_axpy_norm(int64_t n, int k, T *V, int64_t ldv, const T *w, GmState *st,
+                         double *partial, int nb, hipStream_t s);
+void launch_gm_solve_y(GmState *st, hipStream_t s);
+// x += sum_j y_j Z_j (flexible GMRES solution update)
+template <typename T>
+void launch_gm_update(int64_t n, const T *Z, int64_t ldz, const GmState *st, T *x, hipStream_t s);
+// st->norms[slot] = ||x||; if rtol > 0, st->tol_abs = rtol * ||x||
+template <typename T>
+void launch_norm(int64_t n, const T *x, GmState *st, double rtol, double *partial, int nb, int slot,
+                 hipStream_t s);
+
+// vector utilities
+template <typename T>
+void launch_fill(int64_t n, T *x, T v, hipStream_t s);
+template <typename TD, typename TS>
+void launch_axpy(int64_t n, TD *y, const TS *x, const double *scale_ptr, double scale, hipStream_t s);
+// dst = (TD)(src * factor)
+template <typename TD, typename TS>
+void launch_scale_copy(int64_t n, TD *dst, const TS *src, double factor, hipStream_t s);
+void launch_set_dirichlet_x(int64_t n_dir, const int32_t *dir_node, const double *g, double *xs,
+                            hipStream_t s);
+
+}  // namespace lx

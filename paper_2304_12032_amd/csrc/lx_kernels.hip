@@ -1,0 +1,1305 @@
+// HIP kernels for gfx950: P1-P1 VMS-LES element assembly and matrix-free FP64
+// residual, boundary rows, SIMPLE block preconditioner, block-CSR SpMV and the
+// GMRES orthogonalisation / Hessenberg kernels.
+//
+// The element integrals follow the fully discrete weak form of the paper
+// (Sec. 2.3): BDF time term, semi-implicit advection with u* = u_EXT - u_ALE,
+// gradient-gradient (optionally symmetric-gradient) diffusion, the RIIS
+// resistive term with its smoothed delta (Sec. 2.1.2), SUPG-PSPG + grad-div,
+// the VMS cross term and the semi-implicit LES term, with tau_M, tau_C built
+// from the metric tensor G = J^{-T} J^{-1} and vector g = J^{-T} 1.
+//
+// Unlike a per-entry evaluation, the P1 assembly accumulates a handful of
+// per-element moments over the quadrature points (X_ab, Y_bc, Z_a, W_c, S_b,
+// sum tau_M, sum tau_C and three right-hand-side moments) and expands the 16
+// blocks of the element matrix from them: for P1 every basis gradient is
+// constant on the element, so each stabilised entry factors into a gradient
+// product times a quadrature sum.  That keeps the element in registers with
+// one thread per element; the 16 blocks are added into the block-CSR planes
+// with hardware floating-point atomics.
+#include "lx_device.h"
+#include "lx_kernels.h"
+
+namespace lx {
+
+// symmetric 4-point degree-2 rule: barycentric (qa, qb, qb, qb) and permutations
+#define LX_QA 0.58541019662496845446
+#define LX_QB 0.13819660112501051518
+
+// ------------------------------------------------------------------ element data
+
+template <typename T>
+struct Elem {
+    int32_t v[4];
+    T dphi[4][3];
+    T G[3][3], g[3], GG, gg;
+    T vol;
+    T uE[4][3];   // u_EXT at the vertices
+    T K0[4][3];   // f + rho u_BDF / dt at the vertices
+    T uA[4][3];   // u_ALE at the vertices
+    T gU[3][3];   // grad u_EXT (constant), gU[c][j] = d_j u_c
+    T gP[3];      // grad p_EXT (constant)
+    T xh[4][3];   // reference coordinates (valve distance)
+};
+
+template <typename T>
+__device__ inline bool load_elem(Elem<T> &E, int64_t e, int64_t nt, const int32_t *tet, const double *x,
+                                 const double *xh, const double *h0, const double *h1, const double *h2,
+                                 const double *uA, const double *f, const StepCoef &C)
+{
+#pragma unroll
+    for (int a = 0; a < 4; ++a) E.v[a] = tet[a * nt + e];
+    // edge vectors and J^{-1} in FP64 (an FP32 inverse of a flat element loses
+    // digits in every gradient), then rounded to T
+    double X0[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) X0[i] = x[3 * (int64_t)E.v[0] + i];
+    double J[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) J[i][k] = x[3 * (int64_t)E.v[k + 1] + i] - X0[i];
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const double id = 1.0 / det;
+    double Ji[3][3];
+    Ji[0][0] = c00 * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][0] = c01 * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][0] = c02 * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    E.vol = (T)(fabs(det) / 6.0);
+    // J^{-1} rounded to T; the gradients, G and g are formed from it in T so that
+    // sum_a grad phi_a = 0 holds in T arithmetic as well
+    T Jt[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Jt[i][j] = (T)Ji[i][j];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        E.dphi[1][j] = Jt[0][j];
+        E.dphi[2][j] = Jt[1][j];
+        E.dphi[3][j] = Jt[2][j];
+        E.dphi[0][j] = -(Jt[0][j] + Jt[1][j] + Jt[2][j]);
+    }
+    E.GG = 0;
+    E.gg = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        E.g[i] = Jt[0][i] + Jt[1][i] + Jt[2][i];
+        E.gg += E.g[i] * E.g[i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            E.G[i][j] = Jt[0][i] * Jt[0][j] + Jt[1][i] * Jt[1][j] + Jt[2][i] * Jt[2][j];
+            E.GG += E.G[i][j] * E.G[i][j];
+        }
+    }
+    const double *H[3] = {h0, h1, h2};
+    const double rdt = C.rho / C.dt;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) E.gP[j] = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        int64_t v = E.v[a];
+        double ue[3] = {0, 0, 0}, ub[3] = {0, 0, 0}, pe = 0;
+        for (int l = 0; l < C.nlev; ++l) {
+            const double *h = H[l] + 4 * v;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                ue[c] += C.gamma[l] * h[c];
+                ub[c] += C.beta[l] * h[c];
+            }
+            pe += C.gamma[l] * h[3];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            E.uE[a][c] = (T)ue[c];
+            E.K0[a][c] = (T)((f ? f[3 * v + c] : 0.0) + rdt * ub[c]);
+            E.uA[a][c] = uA ? (T)uA[3 * v + c] : T(0);
+            E.xh[a][c] = (T)xh[3 * v + c];
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) E.gP[j] += (T)pe * E.dphi[a][j];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            E.gU[c][j] = E.uE[0][c] * E.dphi[0][j] + E.uE[1][c] * E.dphi[1][j] + E.uE[2][c] * E.dphi[2][j] +
+                         E.uE[3][c] * E.dphi[3][j];
+    return det != 0.0;
+}
+
+// Quadrature-point quantities shared by assembly and residual.
+template <typename T>
+struct QP {
+    T lam[4];
+    T uEq[3], uAq[3], Kv[3], us[3], dv[3];
+    T Aq, sigR, tauM, tauC;
+    T adv[4];
+    T s[4];
+};
+
+template <typename T>
+__device__ inline void eval_qp(const Elem<T> &E, int q, const StepCoef &C, QP<T> &Q)
+{
+    const T qa = (T)LX_QA, qb = (T)LX_QB, dq = qa - qb;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) Q.lam[a] = (a == q) ? qa : qb;
+    T xq[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Q.uEq[c] = qb * (E.uE[0][c] + E.uE[1][c] + E.uE[2][c] + E.uE[3][c]) + dq * E.uE[q][c];
+        Q.uAq[c] = qb * (E.uA[0][c] + E.uA[1][c] + E.uA[2][c] + E.uA[3][c]) + dq * E.uA[q][c];
+        T k0 = qb * (E.K0[0][c] + E.K0[1][c] + E.K0[2][c] + E.K0[3][c]) + dq * E.K0[q][c];
+        Q.Kv[c] = k0;
+        xq[c] = qb * (E.xh[0][c] + E.xh[1][c] + E.xh[2][c] + E.xh[3][c]) + dq * E.xh[q][c];
+    }
+    // RIIS: sigma_R = sum R/eps delta(phi), riis2 = sum R^2/eps^2 delta^2
+    T sigR = 0, riis2 = 0;
+    for (int k = 0; k < C.n_valves; ++k) {
+        const double *vp = C.valve[k];
+        T rel[3] = {xq[0] - (T)vp[0], xq[1] - (T)vp[1], xq[2] - (T)vp[2]};
+        T z = rel[0] * (T)vp[3] + rel[1] * (T)vp[4] + rel[2] * (T)vp[5];
+        T p0 = rel[0] - z * (T)vp[3], p1 = rel[1] - z * (T)vp[4], p2 = rel[2] - z * (T)vp[5];
+        T rp = lx_sqrt(p0 * p0 + p1 * p1 + p2 * p2);
+        T dr = 0;
+        if (rp < (T)vp[6]) dr = (T)vp[6] - rp;
+        if (rp > (T)vp[7]) dr = rp - (T)vp[7];
+        T phi = lx_sqrt(z * z + dr * dr);
+        T eps = (T)vp[9];
+        if (phi <= eps) {
+            T dl = (T(1) + lx_cos((T)M_PI * phi / eps)) / (T(2) * eps);
+            T ratio = (T)vp[8] / eps;
+            sigR += ratio * dl;
+            riis2 += ratio * ratio * dl * dl;
+        }
+    }
+    Q.sigR = sigR;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Q.us[c] = Q.uEq[c] - Q.uAq[c];
+        Q.Kv[c] += sigR * Q.uAq[c];
+    }
+    const T rho = (T)C.rho, adt = (T)(C.alpha / C.dt);
+    Q.Aq = rho * adt + sigR;
+    Q.tauM = 0;
+    Q.tauC = 0;
+    if (C.stab != LX_STAB_NONE) {
+        T uGu = 0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) uGu += Q.us[i] * E.G[i][j] * Q.us[j];
+        T tsum = (T)(C.sigma * C.sigma * C.rho * C.rho / (C.dt * C.dt)) + rho * rho * uGu +
+                 (T)(C.C_r * C.mu * C.mu) * E.GG + riis2;
+        Q.tauM = T(1) / lx_sqrt(tsum);
+        Q.tauC = T(1) / (Q.tauM * E.gg);
+    }
+    // dv = rho (u* - tau_M r_M(u_EXT, p_EXT)) used by the VMS and LES parts
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T adv = Q.us[0] * E.gU[c][0] + Q.us[1] * E.gU[c][1] + Q.us[2] * E.gU[c][2];
+        T rt = rho * (adt * Q.uEq[c] + adv) + E.gP[c] + sigR * Q.uEq[c] - Q.Kv[c];
+        Q.dv[c] = (C.stab == LX_STAB_VMS_LES) ? rho * (Q.us[c] - Q.tauM * rt) : T(0);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        Q.adv[a] = Q.us[0] * E.dphi[a][0] + Q.us[1] * E.dphi[a][1] + Q.us[2] * E.dphi[a][2];
+        Q.s[a] = Q.Aq * Q.lam[a] + rho * Q.adv[a];
+    }
+}
+
+// ------------------------------------------------------------------ assembly
+
+template <typename T, bool RHS>
+__global__ __launch_bounds__(256) void k_assemble_p1(AsmArgs<T> A, StepCoef C)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= A.nt) return;
+    Elem<T> E;
+    load_elem<T>(E, e, A.nt, A.tet, A.x, A.xh, A.h0, A.h1, A.h2, A.uA, A.f, C);
+    const T rho = (T)C.rho;
+    const T w = E.vol * T(0.25);
+    T X[4][4], Y[4][3], Z[4], W[3], S[4], TC = 0, TM = 0;
+    T KP[4][3], KW[3][3], KT[3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        Z[a] = 0;
+        S[a] = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) X[a][b] = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Y[a][c] = 0;
+            KP[a][c] = 0;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        W[c] = 0;
+        KT[c] = 0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) KW[c][j] = 0;
+    }
+
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        QP<T> Q;
+        eval_qp<T>(E, q, C, Q);
+        const T wt = w * Q.tauM;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                X[a][b] += w * (Q.Aq * Q.lam[a] * Q.lam[b] + rho * Q.lam[a] * Q.adv[b]) +
+                           wt * rho * Q.s[b] * Q.adv[a];
+            Z[a] += wt * rho * Q.adv[a];
+            S[a] += wt * Q.s[a];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Y[a][c] += wt * Q.s[a] * Q.dv[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) W[c] += wt * Q.dv[c];
+        TC += w * Q.tauC;
+        TM += wt;
+        if (RHS) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) KP[a][c] += w * Q.Kv[c] * (Q.lam[a] + Q.tauM * rho * Q.adv[a]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                KT[c] += wt * Q.Kv[c];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) KW[c][j] += wt * Q.dv[c] * Q.Kv[j];
+            }
+        }
+    }
+    const T mv = (T)C.mu * E.vol;
+    const T w1 = E.vol * T(0.25);   // integral of one basis function
+    T *val = A.val;
+    const int64_t nb = A.nblk;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t slot = A.eslot[(int64_t)(4 * a + b) * A.nt + e];
+            const T gab = E.dphi[a][0] * E.dphi[b][0] + E.dphi[a][1] * E.dphi[b][1] + E.dphi[a][2] * E.dphi[b][2];
+            const T xab = X[a][b] + mv * gab;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    T F = E.dphi[a][d] * Y[b][c] + TC * E.dphi[a][c] * E.dphi[b][d];
+                    if (c == d) F += xab;
+                    if (C.symgrad) F += mv * E.dphi[b][c] * E.dphi[a][d];
+                    atomic_add(&val[(3 * c + d) * nb + slot], F);
+                }
+                T G = -w1 * E.dphi[a][c] + E.dphi[b][c] * Z[a] + gab * W[c];
+                atomic_add(&val[(9 + c) * nb + slot], G);
+                T B = w1 * E.dphi[b][c] + E.dphi[a][c] * S[b];
+                atomic_add(&val[(12 + c) * nb + slot], B);
+            }
+            atomic_add(&val[15 * nb + slot], TM * gab);
+        }
+        if (RHS) {
+            T *r = A.rhs + 4 * (int64_t)E.v[a];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                atomic_add(&r[c], KP[a][c] + KW[c][0] * E.dphi[a][0] + KW[c][1] * E.dphi[a][1] +
+                                      KW[c][2] * E.dphi[a][2]);
+            atomic_add(&r[3], KT[0] * E.dphi[a][0] + KT[1] * E.dphi[a][1] + KT[2] * E.dphi[a][2]);
+        }
+    }
+}
+
+template <typename T>
+void launch_assemble_p1(const AsmArgs<T> &a, const StepCoef &c, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.nt + 255) / 256));
+    if (a.rhs)
+        hipLaunchKernelGGL((k_assemble_p1<T, true>), grid, dim3(256), 0, s, a, c);
+    else
+        hipLaunchKernelGGL((k_assemble_p1<T, false>), grid, dim3(256), 0, s, a, c);
+}
+template void launch_assemble_p1<double>(const AsmArgs<double> &, const StepCoef &, hipStream_t);
+template void launch_assemble_p1<float>(const AsmArgs<float> &, const StepCoef &, hipStream_t);
+
+// ------------------------------------------------------------------ FP64 residual
+
+// r = b - A xs on every row except Dirichlet velocity rows, evaluated element
+// by element at the quadrature points from the strong residual of the iterate
+// (no matrix is formed).  Optionally accumulates b and the FP64 diagonal of
+// the Dirichlet velocity rows.
+__global__ __launch_bounds__(256) void k_residual_p1(ResArgs A, StepCoef C)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= A.nt) return;
+    Elem<double> E;
+    load_elem<double>(E, e, A.nt, A.tet, A.x, A.xh, A.h0, A.h1, A.h2, A.uA, A.f, C);
+    const double rho = C.rho, mu = C.mu;
+    const double w = E.vol * 0.25;
+    double xu[4][3], xp[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const double *p = A.xs + 4 * (int64_t)E.v[a];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xu[a][c] = p[c];
+        xp[a] = p[3];
+    }
+    double gX[3][3], gXP[3] = {0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            gX[c][j] = xu[0][c] * E.dphi[0][j] + xu[1][c] * E.dphi[1][j] + xu[2][c] * E.dphi[2][j] +
+                       xu[3][c] * E.dphi[3][j];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gXP[j] += xp[a] * E.dphi[a][j];
+    const double divX = gX[0][0] + gX[1][1] + gX[2][2];
+    int32_t dir[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) dir[a] = A.dir_index[E.v[a]];
+
+    double ru[4][3], rp[4], bu[4][3], bp[4], dg[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        rp[a] = bp[a] = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ru[a][c] = bu[a][c] = dg[a][c] = 0;
+    }
+    const double qa = LX_QA, qb = LX_QB, dq = qa - qb;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        QP<double> Q;
+        eval_qp<double>(E, q, C, Q);
+        double xuq[3], xpq;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xuq[c] = qb * (xu[0][c] + xu[1][c] + xu[2][c] + xu[3][c]) + dq * xu[q][c];
+        xpq = qb * (xp[0] + xp[1] + xp[2] + xp[3]) + dq * xp[q];
+        double rM[3], advX[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            advX[c] = Q.us[0] * gX[c][0] + Q.us[1] * gX[c][1] + Q.us[2] * gX[c][2];
+            rM[c] = Q.Aq * xuq[c] + rho * advX[c] + gXP[c] - Q.Kv[c];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const double la = Q.lam[a], ad = Q.adv[a];
+            const double rMd = rM[0] * E.dphi[a][0] + rM[1] * E.dphi[a][1] + rM[2] * E.dphi[a][2];
+            const double Kd = Q.Kv[0] * E.dphi[a][0] + Q.Kv[1] * E.dphi[a][1] + Q.Kv[2] * E.dphi[a][2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double gal = Q.Kv[c] * la - Q.Aq * xuq[c] * la - rho * advX[c] * la -
+                             mu * (gX[c][0] * E.dphi[a][0] + gX[c][1] * E.dphi[a][1] + gX[c][2] * E.dphi[a][2]) +
+                             xpq * E.dphi[a][c];
+                if (C.symgrad)
+                    gal -= mu * (gX[0][c] * E.dphi[a][0] + gX[1][c] * E.dphi[a][1] + gX[2][c] * E.dphi[a][2]);
+                double st = -Q.tauM * (rho * ad * rM[c] + Q.dv[c] * rMd) - Q.tauC * divX * E.dphi[a][c];
+                ru[a][c] += w * (gal + st);
+                if (A.b) bu[a][c] += w * (Q.Kv[c] * la + Q.tauM * (rho * ad * Q.Kv[c] + Q.dv[c] * Kd));
+                if (A.dg && dir[a] >= 0) {
+                    const double dca = E.dphi[a][c];
+                    dg[a][c] += w * (Q.Aq * la * la + rho * la * ad +
+                                     Q.tauM * Q.s[a] * (rho * ad + Q.dv[c] * dca) + Q.tauC * dca * dca);
+                }
+            }
+            rp[a] += w * (-la * divX - Q.tauM * rMd);
+            if (A.b) bp[a] += w * Q.tauM * Kd;
+        }
+    }
+    const double mv = mu * E.vol;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int64_t v = E.v[a];
+        if (dir[a] < 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) atomic_add(&A.r[4 * v + c], ru[a][c]);
+            if (A.b)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) atomic_add(&A.b[4 * v + c], bu[a][c]);
+        } else if (A.dg) {
+            const double gaa = E.dphi[a][0] * E.dphi[a][0] + E.dphi[a][1] * E.dphi[a][1] + E.dphi[a][2] * E.dphi[a][2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double d = dg[a][c] + mv * gaa;
+                if (C.symgrad) d += mv * E.dphi[a][c] * E.dphi[a][c];
+                atomic_add(&A.dg[3 * (int64_t)dir[a] + c], d);
+            }
+        }
+        atomic_add(&A.r[4 * v + 3], rp[a]);
+        if (A.b) atomic_add(&A.b[4 * v + 3], bp[a]);
+    }
+}
+
+void launch_residual_p1(const ResArgs &a, const StepCoef &c, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.nt + 255) / 256));
+    hipLaunchKernelGGL(k_residual_p1, grid, dim3(256), 0, s, a, c);
+}
+
+// ------------------------------------------------------------------ boundary data
+
+__global__ void k_dirichlet_values(int64_t n_dir, const int32_t *dir_node, const int32_t *dir_bc, BCSet S,
+                                   const double *x, const double *uA, const double *gnodal, double *g)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_dir) return;
+    const int64_t v = dir_node[k];
+    const BCVal &B = S.bc[dir_bc[k]];
+    double out[3] = {0, 0, 0};
+    if (B.type == LX_BC_NOSLIP) {
+        if (uA)
+            for (int c = 0; c < 3; ++c) out[c] = uA[3 * v + c];
+    } else if (B.profile == LX_PROFILE_NODAL) {
+        for (int c = 0; c < 3; ++c) out[c] = gnodal[3 * k + c];
+    } else if (B.profile == LX_PROFILE_PARABOLIC) {
+        double r2 = 0;
+        for (int c = 0; c < 3; ++c) {
+            double d = x[3 * v + c] - B.center[c];
+            r2 += d * d;
+        }
+        const double R = B.radius;
+        const double s = -2.0 * (R * R - r2) / (M_PI * R * R * R * R);
+        for (int c = 0; c < 3; ++c) out[c] = B.scale * s * B.normal[c];
+    } else {  // uniform
+        for (int c = 0; c < 3; ++c) out[c] = -B.scale * B.normal[c];
+    }
+    for (int c = 0; c < 3; ++c) g[3 * k + c] = out[c];
+}
+
+void launch_dirichlet_values(int64_t n_dir, const int32_t *dir_node, const int32_t *dir_bc, const BCSet &bcs,
+                             const double *x, const double *uA, const double *gnodal, double *g,
+                             hipStream_t s)
+{
+    if (n_dir == 0) return;
+    hipLaunchKernelGGL(k_dirichlet_values, dim3((unsigned)((n_dir + 255) / 256)), dim3(256), 0, s, n_dir,
+                       dir_node, dir_bc, bcs, x, uA, gnodal, g);
+}
+
+// Dirichlet velocity rows: keep the diagonal entry a_ii of each component,
+// zero the rest of the row (F and G parts), b_i = a_ii g_i.
+template <typename T>
+__global__ void k_dirichlet_rows(int64_t n_dir, const int32_t *dir_node, const double *g, RowPattern P, T *val,
+                                 T *rhs)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_dir) return;
+    const int64_t i = dir_node[k];
+    const int64_t dk = P.diag[i];
+    const int64_t nb = P.nblk;
+    for (int64_t s = P.rowptr[i]; s < P.rowptr[i + 1]; ++s) {
+        for (int c = 0; c < 3; ++c) {
+            for (int d = 0; d < 3; ++d)
+                if (s != dk || c != d) val[(3 * c + d) * nb + s] = T(0);
+            val[(9 + c) * nb + s] = T(0);
+        }
+    }
+    if (rhs)
+        for (int c = 0; c < 3; ++c) rhs[4 * i + c] = (T)((double)val[(4 * c) * nb + dk] * g[3 * k + c]);
+}
+
+template <typename T>
+void launch_dirichlet_rows(int64_t n_dir, const int32_t *dir_node, const double *g, const RowPattern &P, T *val,
+                           T *rhs, hipStream_t s)
+{
+    if (n_dir == 0) return;
+    hipLaunchKernelGGL((k_dirichlet_rows<T>), dim3((unsigned)((n_dir + 127) / 128)), dim3(128), 0, s, n_dir,
+                       dir_node, g, P, val, rhs);
+}
+template void launch_dirichlet_rows<double>(int64_t, const int32_t *, const double *, const RowPattern &,
+                                            double *, double *, hipStream_t);
+template void launch_dirichlet_rows<float>(int64_t, const int32_t *, const double *, const RowPattern &,
+                                           float *, float *, hipStream_t);
+
+__global__ void k_dirichlet_residual(int64_t n_dir, const int32_t *dir_node, const double *g, const double *dg,
+                                     const double *xs, double *r, double *b)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_dir) return;
+    const int64_t i = dir_node[k];
+    for (int c = 0; c < 3; ++c) {
+        r[4 * i + c] = dg[3 * k + c] * (g[3 * k + c] - xs[4 * i + c]);
+        if (b) b[4 * i + c] = dg[3 * k + c] * g[3 * k + c];
+    }
+}
+
+void launch_dirichlet_residual(int64_t n_dir, const int32_t *dir_node, const double *g, const double *dg,
+                               const double *xs, double *r, double *b, hipStream_t s)
+{
+    if (n_dir == 0) return;
+    hipLaunchKernelGGL(k_dirichlet_residual, dim3((unsigned)((n_dir + 255) / 256)), dim3(256), 0, s, n_dir,
+                       dir_node, g, dg, xs, r, b);
+}
+
+// Neumann term (h, v) on boundary triangles with a nodal (or constant) traction
+// vector, linear on each face, integrated by the edge-midpoint rule.
+__global__ void k_neumann(int64_t nf, const int32_t *faces, const double *x, const double *hn, double h0,
+                          double h1, double h2, double *o0, double *o1, float *o32)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nf) return;
+    int64_t v[3] = {faces[3 * e], faces[3 * e + 1], faces[3 * e + 2]};
+    double a[3], b[3];
+    for (int c = 0; c < 3; ++c) {
+        a[c] = x[3 * v[1] + c] - x[3 * v[0] + c];
+        b[c] = x[3 * v[2] + c] - x[3 * v[0] + c];
+    }
+    double n0 = a[1] * b[2] - a[2] * b[1], n1 = a[2] * b[0] - a[0] * b[2], n2 = a[0] * b[1] - a[1] * b[0];
+    double area = 0.5 * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    double h[3][3];
+    for (int i = 0; i < 3; ++i) {
+        h[i][0] = hn ? hn[3 * v[i]] : h0;
+        h[i][1] = hn ? hn[3 * v[i] + 1] : h1;
+        h[i][2] = hn ? hn[3 * v[i] + 2] : h2;
+    }
+    // int h_c phi_i = area/12 (2 h_i + h_j + h_k)
+    for (int i = 0; i < 3; ++i)
+        for (int c = 0; c < 3; ++c) {
+            double val = area / 12.0 * (2.0 * h[i][c] + h[(i + 1) % 3][c] + h[(i + 2) % 3][c]);
+            if (o0) atomic_add(&o0[4 * v[i] + c], val);
+            if (o1) atomic_add(&o1[4 * v[i] + c], val);
+            if (o32) atomic_add(&o32[4 * v[i] + c], (float)val);
+        }
+}
+
+void launch_neumann(int64_t nf, const int32_t *faces, const double *x, const double *hnodal, const double hc[3],
+                    double *out0, double *out1, float *out32, hipStream_t s)
+{
+    if (nf == 0) return;
+    hipLaunchKernelGGL(k_neumann, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s, nf, faces, x, hnodal,
+                       hc[0], hc[1], hc[2], out0, out1, out32);
+}
+
+// ------------------------------------------------------------------ SIMPLE
+
+// D = diag(F); F~^{-1}: inverse of the nodal 3x3 diagonal block of F;
+// S~ = diag(C - B D^{-1} G), reading G_ji through the transposed slot.
+template <typename T>
+__global__ void k_simple_setup(RowPattern P, const T *val, T *Finv, T *Dinv, T *Sinv)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.nv) return;
+    const int64_t nb = P.nblk, nv = P.nv, dk = P.diag[i];
+    double A[9];
+    for (int p = 0; p < 9; ++p) A[p] = (double)val[p * nb + dk];
+    double c0 = A[4] * A[8] - A[5] * A[7], c1 = A[5] * A[6] - A[3] * A[8], c2 = A[3] * A[7] - A[4] * A[6];
+    double id = 1.0 / (A[0] * c0 + A[1] * c1 + A[2] * c2);
+    double B[9] = {c0 * id, (A[2] * A[7] - A[1] * A[8]) * id, (A[1] * A[5] - A[2] * A[4]) * id,
+                   c1 * id, (A[0] * A[8] - A[2] * A[6]) * id, (A[2] * A[3] - A[0] * A[5]) * id,
+                   c2 * id, (A[1] * A[6] - A[0] * A[7]) * id, (A[0] * A[4] - A[1] * A[3]) * id};
+    for (int p = 0; p < 9; ++p) Finv[p * nv + i] = (T)B[p];
+    for (int c = 0; c < 3; ++c) Dinv[c * nv + i] = (T)(1.0 / A[4 * c]);
+    double s = (double)val[15 * nb + dk];
+    for (int64_t k = P.rowptr[i]; k < P.rowptr[i + 1]; ++k) {
+        const int64_t j = P.col[k], ts = P.tslot[k], dj = P.diag[j];
+        for (int d = 0; d < 3; ++d)
+            s -= (double)val[(12 + d) * nb + k] * (double)val[(9 + d) * nb + ts] / (double)val[(4 * d) * nb + dj];
+    }
+    Sinv[i] = (T)(1.0 / s);
+}
+
+template <typename T>
+void launch_simple_setup(const RowPattern &P, const T *val, T *Finv, T *Dinv, T *Sinv, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_simple_setup<T>), dim3((unsigned)((P.nv + 127) / 128)), dim3(128), 0, s, P, val, Finv,
+                       Dinv, Sinv);
+}
+template void launch_simple_setup<double>(const RowPattern &, const double *, double *, double *, double *,
+                                          hipStream_t);
+template void launch_simple_setup<float>(const RowPattern &, const float *, float *, float *, float *,
+                                         hipStream_t);
+
+constexpr int kLPR = 16;
+
+// ---- Gershgorin bound of diag(S~)^{-1} S~
+
+// ag[c][i] = |1/D_(i,c)| sum_j |G_ij[c]|
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_schur_ag(RowPattern P, const T *val, const T *Dinv, T *ag)
+{
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= P.nv) return;
+    const int64_t nb = P.nblk, nv = P.nv;
+    T a0 = 0, a1 = 0, a2 = 0;
+    for (int32_t k = P.rowptr[row] + lane; k < P.rowptr[row + 1]; k += LPR) {
+        a0 += fabs(val[9 * nb + k]);
+        a1 += fabs(val[10 * nb + k]);
+        a2 += fabs(val[11 * nb + k]);
+    }
+    a0 = group_sum<T, LPR>(a0);
+    a1 = group_sum<T, LPR>(a1);
+    a2 = group_sum<T, LPR>(a2);
+    if (lane == 0) {
+        ag[row] = a0 * fabs(Dinv[row]);
+        ag[nv + row] = a1 * fabs(Dinv[nv + row]);
+        ag[2 * nv + row] = a2 * fabs(Dinv[2 * nv + row]);
+    }
+}
+
+// gers[i] = |1/S~_ii| (sum_j |C_ij| + sum_j sum_d |B_ij[d]| ag[d][j])
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_schur_gers(RowPattern P, const T *val, const T *Sinv, const T *ag, T *gers)
+{
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= P.nv) return;
+    const int64_t nb = P.nblk, nv = P.nv;
+    T a = 0;
+    for (int32_t k = P.rowptr[row] + lane; k < P.rowptr[row + 1]; k += LPR) {
+        const int64_t j = P.col[k];
+        a += fabs(val[15 * nb + k]) + fabs(val[12 * nb + k]) * ag[j] + fabs(val[13 * nb + k]) * ag[nv + j] +
+             fabs(val[14 * nb + k]) * ag[2 * nv + j];
+    }
+    a = group_sum<T, LPR>(a);
+    if (lane == 0) gers[row] = a * fabs(Sinv[row]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_max(int64_t n, const T *x, GmState *st, double *partial)
+{
+    __shared__ double lds[4];
+    double m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = fmax(m, (double)x[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) lds[wid] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
+    if (!arrive_last(&st->counter)) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double mm = 0;
+        for (unsigned b = 0; b < gridDim.x; ++b) mm = fmax(mm, partial[b]);
+        st->lam_max = mm;
+        st->counter = 0;
+    }
+}
+
+template <typename T>
+void launch_schur_bound(const RowPattern &P, const T *val, const T *Dinv, const T *Sinv, T *work, GmState *st,
+                        double *partial, int nb, hipStream_t s)
+{
+    const unsigned g = (unsigned)((P.nv * kLPR + 255) / 256);
+    hipLaunchKernelGGL((k_schur_ag<T, kLPR>), dim3(g), dim3(256), 0, s, P, val, Dinv, work);
+    hipLaunchKernelGGL((k_schur_gers<T, kLPR>), dim3(g), dim3(256), 0, s, P, val, Sinv, work, work + 3 * P.nv);
+    hipLaunchKernelGGL((k_max<T>), dim3(nb), dim3(kRedThreads), 0, s, P.nv, work + 3 * P.nv, st, partial);
+}
+template void launch_schur_bound<double>(const RowPattern &, const double *, const double *, const double *,
+                                         double *, GmState *, double *, int, hipStream_t);
+template void launch_schur_bound<float>(const RowPattern &, const float *, const float *, const float *, float *,
+                                        GmState *, double *, int, hipStream_t);
+
+// ---- SIMPLE apply
+
+// z.u = F~^{-1} (scale r.u)   (node-local); z.p = scale r.p for the next pass
+template <typename T>
+__global__ void k_simple_zu(int64_t nv, const T *Finv, const T *r, const double *scale_ptr, T *z,
+                            const int32_t *done)
+{
+    if (done && *done) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    const T sc = scale_ptr ? (T)(*scale_ptr) : T(1);
+    using V = typename V4<T>::type;
+    V rv = reinterpret_cast<const V *>(r)[i];
+    T r0 = rv.v[0] * sc, r1 = rv.v[1] * sc, r2 = rv.v[2] * sc;
+    V zv;
+    zv.v[0] = Finv[0 * nv + i] * r0 + Finv[1 * nv + i] * r1 + Finv[2 * nv + i] * r2;
+    zv.v[1] = Finv[3 * nv + i] * r0 + Finv[4 * nv + i] * r1 + Finv[5 * nv + i] * r2;
+    zv.v[2] = Finv[6 * nv + i] * r0 + Finv[7 * nv + i] * r1 + Finv[8 * nv + i] * r2;
+    zv.v[3] = rv.v[3] * sc;
+    reinterpret_cast<V *>(z)[i] = zv;
+}
+
+// Chebyshev scalars of step i >= 1 for the interval [lmax/ratio, lmax]:
+// d_i = a d_{i-1} + b diag(S~)^{-1} r_i; step 0 is d_0 = diag(S~)^{-1} r_0 / theta.
+__device__ inline void cheb_coef(double lmax, double ratio, int i, double &theta, double &a, double &b)
+{
+    const double lmin = lmax / ratio;
+    theta = 0.5 * (lmax + lmin);
+    const double delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+    double rho = 1.0 / sigma, rho_prev = rho;
+    for (int j = 1; j <= i; ++j) {
+        rho_prev = rho;
+        rho = 1.0 / (2.0 * sigma - rho);
+    }
+    a = rho * rho_prev;
+    b = 2.0 * rho / delta;
+}
+
+// t = z.p - sum_j B_ij z.u_j (z.p holds scale*r.p on entry); degree 0: z.p = S~^{-1}_diag t;
+// degree > 0: Chebyshev step 0 (rc = t, d0 = Sinv t / theta, z.p = d0).
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_simple_zp(RowPattern P, const T *val, const T *Sinv, T *z, int degree,
+                                                   double ratio, T *rc, T *d0, const GmState *st,
+                                                   const int32_t *done)
+{
+    if (done && *done) return;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= P.nv) return;
+    const int64_t nb = P.nblk;
+    const int32_t beg = P.rowptr[row], end = P.rowptr[row + 1];
+    double acc = 0;
+    for (int32_t k = beg + lane; k < end; k += LPR) {
+        const int64_t j = P.col[k];
+        const T *zj = z + 4 * j;
+        acc += (double)val[12 * nb + k] * zj[0] + (double)val[13 * nb + k] * zj[1] + (double)val[14 * nb + k] * zj[2];
+    }
+    acc = group_sum<double, LPR>(acc);
+    if (lane == 0) {
+        const T t = (T)((double)z[4 * row + 3] - acc);
+        if (degree == 0) {
+            z[4 * row + 3] = Sinv[row] * t;
+        } else {
+            double theta, a, b;
+            cheb_coef(st->lam_max, ratio, 0, theta, a, b);
+            const T d = (T)((double)(Sinv[row] * t) / theta);
+            rc[row] = t;
+            d0[row] = d;
+            z[4 * row + 3] = d;
+        }
+    }
+}
+
+// Chebyshev pass A: y = D^{-1} (G d)   (velocity side of S~ d)
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_cheb_gd(RowPattern P, const T *val, const T *Dinv, const T *d, T *y,
+                                                 const int32_t *done)
+{
+    if (done && *done) return;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= P.nv) return;
+    const int64_t nb = P.nblk, nv = P.nv;
+    double a0 = 0, a1 = 0, a2 = 0;
+    for (int32_t k = P.rowptr[row] + lane; k < P.rowptr[row + 1]; k += LPR) {
+        const double dj = d[P.col[k]];
+        a0 += (double)val[9 * nb + k] * dj;
+        a1 += (double)val[10 * nb + k] * dj;
+        a2 += (double)val[11 * nb + k] * dj;
+    }
+    a0 = group_sum<double, LPR>(a0);
+    a1 = group_sum<double, LPR>(a1);
+    a2 = group_sum<double, LPR>(a2);
+    if (lane == 0) {
+        y[row] = (T)((double)Dinv[row] * a0);
+        y[nv + row] = (T)((double)Dinv[nv + row] * a1);
+        y[2 * nv + row] = (T)((double)Dinv[2 * nv + row] * a2);
+    }
+}
+
+// Chebyshev pass B (step i >= 1): q = C d - B y = S~ d; rc -= q;
+// dn = a d + b Sinv rc; z.p += dn
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_cheb_step(RowPattern P, const T *val, const T *Sinv, const T *d,
+                                                   const T *y, T *rc, T *dn, T *z, int i, double ratio,
+                                                   const GmState *st, const int32_t *done)
+{
+    if (done && *done) return;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= P.nv) return;
+    const int64_t nb = P.nblk, nv = P.nv;
+    double q = 0;
+    for (int32_t k = P.rowptr[row] + lane; k < P.rowptr[row + 1]; k += LPR) {
+        const int64_t j = P.col[k];
+        q += (double)val[15 * nb + k] * d[j] - ((double)val[12 * nb + k] * y[j] + (double)val[13 * nb + k] * y[nv + j] +
+                                                (double)val[14 * nb + k] * y[2 * nv + j]);
+    }
+    q = group_sum<double, LPR>(q);
+    if (lane == 0) {
+        double theta, a, b;
+        cheb_coef(st->lam_max, ratio, i, theta, a, b);
+        const double r = (double)rc[row] - q;
+        rc[row] = (T)r;
+        const double dnew = a * (double)d[row] + b * (double)Sinv[row] * r;
+        dn[row] = (T)dnew;
+        z[4 * row + 3] = (T)((double)z[4 * row + 3] + dnew);
+    }
+}
+
+// z.u -= D^{-1} sum_j G_ij z.p_j
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_simple_xu(RowPattern P, const T *val, const T *Dinv, T *z,
+                                                   const int32_t *done)
+{
+    if (done && *done) return;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= P.nv) return;
+    const int64_t nb = P.nblk, nv = P.nv;
+    const int32_t beg = P.rowptr[row], end = P.rowptr[row + 1];
+    double a0 = 0, a1 = 0, a2 = 0;
+    for (int32_t k = beg + lane; k < end; k += LPR) {
+        const double zp = z[4 * (int64_t)P.col[k] + 3];
+        a0 += (double)val[9 * nb + k] * zp;
+        a1 += (double)val[10 * nb + k] * zp;
+        a2 += (double)val[11 * nb + k] * zp;
+    }
+    a0 = group_sum<double, LPR>(a0);
+    a1 = group_sum<double, LPR>(a1);
+    a2 = group_sum<double, LPR>(a2);
+    if (lane == 0) {
+        z[4 * row + 0] = (T)((double)z[4 * row + 0] - (double)Dinv[row] * a0);
+        z[4 * row + 1] = (T)((double)z[4 * row + 1] - (double)Dinv[nv + row] * a1);
+        z[4 * row + 2] = (T)((double)z[4 * row + 2] - (double)Dinv[2 * nv + row] * a2);
+    }
+}
+
+template <typename T>
+void launch_simple_apply(const RowPattern &P, const Simple<T> &S, const T *r, const double *scale_ptr, T *z,
+                         const int32_t *done, hipStream_t s)
+{
+    const int64_t nv = P.nv;
+    hipLaunchKernelGGL((k_simple_zu<T>), dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, nv, S.Finv, r,
+                       scale_ptr, z, done);
+    const unsigned g = (unsigned)((nv * kLPR + 255) / 256);
+    T *rc = S.work, *da = S.work + nv, *db = S.work + 2 * nv, *y = S.work + 3 * nv;
+    hipLaunchKernelGGL((k_simple_zp<T, kLPR>), dim3(g), dim3(256), 0, s, P, S.val, S.Sinv, z, S.degree, S.ratio, rc,
+                       da, S.st, done);
+    for (int i = 1; i < S.degree; ++i) {
+        hipLaunchKernelGGL((k_cheb_gd<T, kLPR>), dim3(g), dim3(256), 0, s, P, S.val, S.Dinv, da, y, done);
+        hipLaunchKernelGGL((k_cheb_step<T, kLPR>), dim3(g), dim3(256), 0, s, P, S.val, S.Sinv, da, y, rc, db, z, i,
+                           S.ratio, S.st, done);
+        std::swap(da, db);
+    }
+    hipLaunchKernelGGL((k_simple_xu<T, kLPR>), dim3(g), dim3(256), 0, s, P, S.val, S.Dinv, z, done);
+}
+template void launch_simple_apply<double>(const RowPattern &, const Simple<double> &, const double *,
+                                          const double *, double *, const int32_t *, hipStream_t);
+template void launch_simple_apply<float>(const RowPattern &, const Simple<float> &, const float *, const double *,
+                                         float *, const int32_t *, hipStream_t);
+
+// ------------------------------------------------------------------ SpMV
+
+// y = A x over the block-CSR planes: LPR lanes per block row, each lane one
+// 4x4 block per iteration (16 unit-stride plane loads + one gathered 4-vector),
+// then a cross-lane reduction of the 4 row sums.
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_spmv(RowPattern P, const T *__restrict__ val, const T *__restrict__ x,
+                                              T *__restrict__ y, const int32_t *done)
+{
+    if (done && *done) return;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= P.nv) return;
+    const int64_t nb = P.nblk;
+    const int32_t beg = P.rowptr[row], end = P.rowptr[row + 1];
+    using V = typename V4<T>::type;
+    // products of two T values are exact in FP64; sums are accumulated in FP64
+    double y0 = 0, y1 = 0, y2 = 0, y3 = 0;
+    for (int32_t k = beg + lane; k < end; k += LPR) {
+        const V xv = reinterpret_cast<const V *>(x)[P.col[k]];
+        const double x0 = xv.v[0], x1 = xv.v[1], x2 = xv.v[2], x3 = xv.v[3];
+        double a[16];
+#pragma unroll
+        for (int p = 0; p < 16; ++p) a[p] = (double)val[p * nb + k];
+        y0 += a[0] * x0 + a[1] * x1 + a[2] * x2 + a[9] * x3;
+        y1 += a[3] * x0 + a[4] * x1 + a[5] * x2 + a[10] * x3;
+        y2 += a[6] * x0 + a[7] * x1 + a[8] * x2 + a[11] * x3;
+        y3 += a[12] * x0 + a[13] * x1 + a[14] * x2 + a[15] * x3;
+    }
+    y0 = group_sum<double, LPR>(y0);
+    y1 = group_sum<double, LPR>(y1);
+    y2 = group_sum<double, LPR>(y2);
+    y3 = group_sum<double, LPR>(y3);
+    if (lane == 0) {
+        V out;
+        out.v[0] = (T)y0;
+        out.v[1] = (T)y1;
+        out.v[2] = (T)y2;
+        out.v[3] = (T)y3;
+        reinterpret_cast<V *>(y)[row] = out;
+    }
+}
+
+template <typename T>
+void launch_spmv(const RowPattern &P, const T *val, const T *x, T *y, const int32_t *done, hipStream_t s)
+{
+    const unsigned g = (unsigned)((P.nv * kLPR + 255) / 256);
+    hipLaunchKernelGGL((k_spmv<T, kLPR>), dim3(g), dim3(256), 0, s, P, val, x, y, done);
+}
+template void launch_spmv<double>(const RowPattern &, const double *, const double *, double *, const int32_t *,
+                                  hipStream_t);
+template void launch_spmv<float>(const RowPattern &, const float *, const float *, float *, const int32_t *,
+                                 hipStream_t);
+
+// ------------------------------------------------------------------ reductions
+
+
+// r = b - Ax (or b), V0 = r, beta = ||r||; initialises the cycle.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_gm_start(int64_t n, const T *b, const T *Ax, T *V0, GmState *st,
+                                                          double *partial)
+{
+    __shared__ double lds[4 * 4];
+    double acc[1] = {0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        T r = Ax ? (T)(b[i] - Ax[i]) : b[i];
+        V0[i] = r;
+        acc[0] += to_d(r) * to_d(r);
+    }
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc[0];
+    if (!arrive_last(&st->counter)) return;
+    double tot[1];
+    reduce_partials<1>(partial, gridDim.x, 1, tot, lds);
+    if (threadIdx.x == 0) {
+        double beta = sqrt(tot[0]);
+        st->resid = beta;
+        st->g[0] = beta;
+        for (int j = 1; j <= kMaxRestart; ++j) st->g[j] = 0;
+        st->s[0] = beta > 0 ? 1.0 / beta : 0.0;
+        st->kused = 0;
+        st->converged = (beta <= st->tol_abs) ? 1 : 0;
+        st->breakdown = (beta != beta) ? 1 : 0;
+        st->done = (st->converged || st->breakdown) ? 1 : 0;
+        st->counter = 0;
+    }
+}
+
+template <typename T>
+void launch_gm_start(int64_t n, const T *b, const T *Ax, T *V0, GmState *st, double *partial, int nb,
+                     hipStream_t s)
+{
+    hipLaunchKernelGGL((k_gm_start<T>), dim3(nb), dim3(kRedThreads), 0, s, n, b, Ax, V0, st, partial);
+}
+template void launch_gm_start<double>(int64_t, const double *, const double *, double *, GmState *, double *, int,
+                                      hipStream_t);
+template void launch_gm_start<float>(int64_t, const float *, const float *, float *, GmState *, double *, int,
+                                     hipStream_t);
+
+// h1_j = <V_j, w>, j = 0..k  (V_j = s_j Vhat_j)
+template <typename T, int K>
+__global__ __launch_bounds__(kRedThreads) void k_gm_dot1(int64_t n, int k, const T *V, int64_t ldv, const T *w,
+                                                         GmState *st, double *partial)
+{
+    if (st->done) return;
+    __shared__ double lds[4 * K];
+    double acc[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc[j] = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double wi = to_d(w[i]);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j <= k) acc[j] += to_d(V[j * ldv + i]) * wi;
+    }
+    block_sum<K>(acc, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < K; ++j) partial[(int64_t)blockIdx.x * K + j] = acc[j];
+    if (!arrive_last(&st->counter)) return;
+    double tot[K];
+    reduce_partials<K>(partial, gridDim.x, k + 1, tot, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j <= k) st->h1[j] = tot[j] * st->s[j];
+        st->counter = 0;
+    }
+}
+
+// w -= sum_j h1_j V_j ; h2_j = <V_j, w>; H[j][k] = h1_j + h2_j
+template <typename T, int K>
+__global__ __launch_bounds__(kRedThreads) void k_gm_axpy_dot2(int64_t n, int k, const T *V, int64_t ldv, T *w,
+                                                              GmState *st, double *partial)
+{
+    if (st->done) return;
+    __shared__ double lds[4 * K];
+    __shared__ double coef[K];
+    if (threadIdx.x < K) coef[threadIdx.x] = (threadIdx.x <= (unsigned)k) ? st->h1[threadIdx.x] * st->s[threadIdx.x] : 0.0;
+    __syncthreads();
+    double acc[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc[j] = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        T vj[K];
+        double wi = to_d(w[i]);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j <= k) {
+                vj[j] = V[j * ldv + i];
+                wi -= coef[j] * to_d(vj[j]);
+            }
+        const T wt = (T)wi;
+        w[i] = wt;
+        const double wd = to_d(wt);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j <= k) acc[j] += to_d(vj[j]) * wd;
+    }
+    block_sum<K>(acc, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < K; ++j) partial[(int64_t)blockIdx.x * K + j] = acc[j];
+    if (!arrive_last(&st->counter)) return;
+    double tot[K];
+    reduce_partials<K>(partial, gridDim.x, k + 1, tot, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j <= k) {
+                double h2 = tot[j] * st->s[j];
+                st->H[j * kMaxRestart + k] = st->h1[j] + h2;
+                st->h1[j] = h2;   // h2 kept for the second update
+            }
+        st->counter = 0;
+    }
+}
+
+// Vhat_{k+1} = w - sum_j h2_j V_j ; then Givens update of column k.
+template <typename T, int K>
+__global__ __launch_bounds__(kRedThreads) void k_gm_axpy_norm(int64_t n, int k, T *V, int64_t ldv, const T *w,
+                                                              GmState *st, double *partial)
+{
+    if (st->done) return;
+    __shared__ double lds[4 * 4];
+    __shared__ double coef[K];
+    if (threadIdx.x < K) coef[threadIdx.x] = (threadIdx.x <= (unsigned)k) ? st->h1[threadIdx.x] * st->s[threadIdx.x] : 0.0;
+    __syncthreads();
+    double acc[1] = {0};
+    T *Vn = V + (int64_t)(k + 1) * ldv;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double wi = to_d(w[i]);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j <= k) wi -= coef[j] * to_d(V[j * ldv + i]);
+        const T wt = (T)wi;
+        Vn[i] = wt;
+        acc[0] += to_d(wt) * to_d(wt);
+    }
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc[0];
+    if (!arrive_last(&st->counter)) return;
+    double tot[1];
+    reduce_partials<1>(partial, gridDim.x, 1, tot, lds);
+    if (threadIdx.x == 0) {
+        const int M = kMaxRestart;
+        double *H = st->H;
+        const double hn = sqrt(tot[0]);
+        H[(k + 1) * M + k] = hn;
+        for (int j = 0; j < k; ++j) {
+            double t = st->cs[j] * H[j * M + k] + st->sn[j] * H[(j + 1) * M + k];
+            H[(j + 1) * M + k] = -st->sn[j] * H[j * M + k] + st->cs[j] * H[(j + 1) * M + k];
+            H[j * M + k] = t;
+        }
+        const double a = H[k * M + k];
+        const double r = hypot(a, hn);
+        const double c = (r > 0) ? a / r : 1.0, sn = (r > 0) ? hn / r : 0.0;
+        st->cs[k] = c;
+        st->sn[k] = sn;
+        H[k * M + k] = r;
+        H[(k + 1) * M + k] = 0.0;
+        st->g[k + 1] = -sn * st->g[k];
+        st->g[k] = c * st->g[k];
+        st->s[k + 1] = hn > 0 ? 1.0 / hn : 0.0;
+        const double res = fabs(st->g[k + 1]);
+        st->resid = res;
+        st->kused = k + 1;
+        const bool bad = !(res == res) || !(r > 0);
+        st->breakdown = bad ? 1 : 0;
+        st->converged = (!bad && res <= st->tol_abs) ? 1 : 0;
+        // a zero new direction means the Krylov space is invariant: the solution is exact
+        if (!bad && hn == 0.0) st->converged = 1;
+        st->done = (st->converged || bad) ? 1 : 0;
+        st->counter = 0;
+    }
+}
+
+#define LX_GM_DISPATCH(KERNEL, T, ...)                                                                         \
+    do {                                                                                                       \
+        if (k + 1 <= 8)                                                                                        \
+            hipLaunchKernelGGL((KERNEL<T, 8>), dim3(nb), dim3(kRedThreads), 0, s, __VA_ARGS__);               \
+        else if (k + 1 <= 16)                                                                                  \
+            hipLaunchKernelGGL((KERNEL<T, 16>), dim3(nb), dim3(kRedThreads), 0, s, __VA_ARGS__);              \
+        else if (k + 1 <= 32)                                                                                  \
+            hipLaunchKernelGGL((KERNEL<T, 32>), dim3(nb), dim3(kRedThreads), 0, s, __VA_ARGS__);              \
+        else                                                                                                   \
+            hipLaunchKernelGGL((KERNEL<T, 64>), dim3(nb), dim3(kRedThreads), 0, s, __VA_ARGS__);              \
+    } while (0)
+
+template <typename T>
+void launch_gm_dot1(int64_t n, int k, const T *V, int64_t ldv, const T *w, GmState *st, double *partial, int nb,
+                    hipStream_t s)
+{
+    LX_GM_DISPATCH(k_gm_dot1, T, n, k, V, ldv, w, st, partial);
+}
+template <typename T>
+void launch_gm_axpy_dot2(int64_t n, int k, const T *V, int64_t ldv, T *w, GmState *st, double *partial, int nb,
+                         hipStream_t s)
+{
+    LX_GM_DISPATCH(k_gm_axpy_dot2, T, n, k, V, ldv, w, st, partial);
+}
+template <typename T>
+void launch_gm_axpy_norm(int64_t n, int k, T *V, int64_t ldv, const T *w, GmState *st, double *partial, int nb,
+                         hipStream_t s)
+{
+    LX_GM_DISPATCH(k_gm_axpy_norm, T, n, k, V, ldv, w, st, partial);
+}
+template void launch_gm_dot1<double>(int64_t, int, const double *, int64_t, const double *, GmState *, double *,
+                                     int, hipStream_t);
+template void launch_gm_dot1<float>(int64_t, int, const float *, int64_t, const float *, GmState *, double *, int,
+                                    hipStream_t);
+template void launch_gm_axpy_dot2<double>(int64_t, int, const double *, int64_t, double *, GmState *, double *,
+                                          int, hipStream_t);
+template void launch_gm_axpy_dot2<float>(int64_t, int, const float *, int64_t, float *, GmState *, double *, int,
+                                         hipStream_t);
+template void launch_gm_axpy_norm<double>(int64_t, int, double *, int64_t, const double *, GmState *, double *,
+                                          int, hipStream_t);
+template void launch_gm_axpy_norm<float>(int64_t, int, float *, int64_t, const float *, GmState *, double *, int,
+                                         hipStream_t);
+
+// y = H^{-1} g over the kused columns (back substitution).
+__global__ void k_gm_solve_y(GmState *st)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int M = kMaxRestart, k = st->kused;
+    double y[kMaxRestart];
+    for (int i = k - 1; i >= 0; --i) {
+        double s = st->g[i];
+        for (int j = i + 1; j < k; ++j) s -= st->H[i * M + j] * y[j];
+        y[i] = s / st->H[i * M + i];
+    }
+    for (int j = 0; j < k; ++j) st->y[j] = y[j];
+}
+
+void launch_gm_solve_y(GmState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gm_solve_y, dim3(1), dim3(64), 0, s, st);
+}
+
+// x += sum_j y_j Z_j over the kused preconditioned directions (flexible GMRES update)
+template <typename T>
+__global__ void k_gm_update(int64_t n, const T *Z, int64_t ldz, const GmState *st, T *x)
+{
+    const int k = st->kused;
+    __shared__ double y[kMaxRestart];
+    if (threadIdx.x < kMaxRestart) y[threadIdx.x] = (threadIdx.x < (unsigned)k) ? st->y[threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = to_d(x[i]);
+        for (int j = 0; j < k; ++j) s += y[j] * to_d(Z[j * ldz + i]);
+        x[i] = (T)s;
+    }
+}
+
+template <typename T>
+void launch_gm_update(int64_t n, const T *Z, int64_t ldz, const GmState *st, T *x, hipStream_t s)
+{
+    unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL((k_gm_update<T>), dim3(g), dim3(256), 0, s, n, Z, ldz, st, x);
+}
+template void launch_gm_update<double>(int64_t, const double *, int64_t, const GmState *, double *, hipStream_t);
+template void launch_gm_update<float>(int64_t, const float *, int64_t, const GmState *, float *, hipStream_t);
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_norm(int64_t n, const T *x, GmState *st, double rtol,
+                                                      double *partial, int slot)
+{
+    __shared__ double lds[4 * 4];
+    double acc[1] = {0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc[0] += to_d(x[i]) * to_d(x[i]);
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc[0];
+    if (!arrive_last(&st->counter)) return;
+    double tot[1];
+    reduce_partials<1>(partial, gridDim.x, 1, tot, lds);
+    if (threadIdx.x == 0) {
+        st->norms[slot] = sqrt(tot[0]);
+        if (rtol > 0) st->tol_abs = rtol * st->norms[slot];
+        st->counter = 0;
+    }
+}
+
+template <typename T>
+void launch_norm(int64_t n, const T *x, GmState *st, double rtol, double *partial, int nb, int slot, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_norm<T>), dim3(nb), dim3(kRedThreads), 0, s, n, x, st, rtol, partial, slot);
+}
+template void launch_norm<double>(int64_t, const double *, GmState *, double, double *, int, int, hipStream_t);
+template void launch_norm<float>(int64_t, const float *, GmState *, double, double *, int, int, hipStream_t);
+
+// ------------------------------------------------------------------ vector utilities
+
+template <typename T>
+__global__ void k_fill(int64_t n, T *x, T v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+template <typename T>
+void launch_fill(int64_t n, T *x, T v, hipStream_t s)
+{
+    if (n <= 0) return;
+    unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL((k_fill<T>), dim3(g), dim3(256), 0, s, n, x, v);
+}
+template void launch_fill<double>(int64_t, double *, double, hipStream_t);
+template void launch_fill<float>(int64_t, float *, float, hipStream_t);
+template void launch_fill<int32_t>(int64_t, int32_t *, int32_t, hipStream_t);
+
+template <typename TD, typename TS>
+__global__ void k_axpy(int64_t n, TD *y, const TS *x, const double *scale_ptr, double scale)
+{
+    const double a = scale_ptr ? scale * (*scale_ptr) : scale;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (TD)((double)y[i] + a * (double)x[i]);
+}
+template <typename TD, typename TS>
+void launch_axpy(int64_t n, TD *y, const TS *x, const double *scale_ptr, double scale, hipStream_t s)
+{
+    unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL((k_axpy<TD, TS>), dim3(g), dim3(256), 0, s, n, y, x, scale_ptr, scale);
+}
+template void launch_axpy<double, double>(int64_t, double *, const double *, const double *, double, hipStream_t);
+template void launch_axpy<float, float>(int64_t, float *, const float *, const double *, double, hipStream_t);
+template void launch_axpy<double, float>(int64_t, double *, const float *, const double *, double, hipStream_t);
+
+template <typename TD, typename TS>
+__global__ void k_scale_copy(int64_t n, TD *dst, const TS *src, double a)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (TD)((double)src[i] * a);
+}
+template <typename TD, typename TS>
+void launch_scale_copy(int64_t n, TD *dst, const TS *src, double factor, hipStream_t s)
+{
+    unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL((k_scale_copy<TD, TS>), dim3(g), dim3(256), 0, s, n, dst, src, factor);
+}
+template void launch_scale_copy<float, double>(int64_t, float *, const double *, double, hipStream_t);
+template void launch_scale_copy<double, double>(int64_t, double *, const double *, double, hipStream_t);
+template void launch_scale_copy<double, float>(int64_t, double *, const float *, double, hipStream_t);
+
+__global__ void k_set_dirichlet_x(int64_t n_dir, const int32_t *dir_node, const double *g, double *xs)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_dir) return;
+    const int64_t i = dir_node[k];
+    for (int c = 0; c < 3; ++c) xs[4 * i + c] = g[3 * k + c];
+}
+void launch_set_dirichlet_x(int64_t n_dir, const int32_t *dir_node, const double *g, double *xs, hipStream_t s)
+{
+    if (n_dir == 0) return;
+    hipLaunchKernelGGL(k_set_dirichlet_x, dim3((unsigned)((n_dir + 255) / 256)), dim3(256), 0, s, n_dir, dir_node,
+                       g, xs);
+}
+
+}  // namespace lx

@@ -1,0 +1,126 @@
+// The simulation object behind lx_sim*.
+#pragma once
+
+#include <utility>
+#include <vector>
+
+#include "lx_common.h"
+#include "lx_kernels.h"
+
+namespace lx {
+
+double law_value(const lx_time_law &L, double t);
+
+struct BCDesc {
+    lx_boundary spec{};
+    std::vector<int32_t> tags;
+    int64_t nf = 0;                 // Neumann faces
+    std::vector<int32_t> h_faces;   // [nf][3] new numbering
+    int32_t *d_faces = nullptr;
+    double *d_hnodal = nullptr;     // [nv][3] nodal traction (nodal profile)
+    bool nodal_set = false;
+};
+
+struct GmResult {
+    int iters = 0;
+    int restarts = 0;
+    bool converged = false;
+    double resid = 0;
+    double bnorm = 0;
+};
+
+struct Sim {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    HostSetup hs;
+    lx_problem prob{};
+    lx_solver solver{};
+    std::vector<BCDesc> bcs;
+    std::vector<lx_riis> valves;
+    std::vector<int32_t> ale_tags;
+    std::vector<int32_t> h_ale_nodes;
+    int64_t nv = 0, nt = 0, nblk = 0, N = 0, n_dir = 0;
+    std::vector<int32_t> h_dir_index, h_dir_node, h_dir_bc;
+    std::vector<double> h_gnodal;
+    bool dirty_gnodal = false;
+
+    // device arrays (new numbering)
+    double *d_xh = nullptr, *d_x = nullptr;
+    int32_t *d_tet = nullptr, *d_eslot = nullptr, *d_rowptr = nullptr, *d_col = nullptr, *d_diag = nullptr,
+            *d_tslot = nullptr;
+    int32_t *d_dir_index = nullptr, *d_dir_node = nullptr, *d_dir_bc = nullptr;
+    double *d_g = nullptr, *d_gnodal = nullptr, *d_dg = nullptr;
+    double *d_hist[4] = {nullptr, nullptr, nullptr, nullptr};   // [nv][4] u^n, u^{n-1}, ...
+    double *d_xs = nullptr;                                      // solution of the step in progress
+    double *d_f = nullptr, *d_uA = nullptr;
+    // ALE
+    double *d_dhist[4] = {nullptr, nullptr, nullptr, nullptr};  // [nv][3] displacement history
+    double *d_dnew = nullptr;                                    // displacement at t^{n+1}
+    double *d_ale_shape = nullptr;                               // [nv][3] D^
+    double *d_lap = nullptr;                                     // [nblk] P1 Laplacian on x^ (eliminated)
+    double *d_lapfull = nullptr;                                 // [nblk] P1 Laplacian on x^
+    double *d_lapdinv = nullptr;                                 // [nv]
+    int32_t *d_ale_nodes = nullptr;
+    int32_t *d_ale_mark = nullptr;                               // [nv] 1 on ALE boundary
+    double *d_cg = nullptr;                                      // CG work: 6 vectors [nv][3] + state
+    double *d_cg_partial = nullptr;
+    bool ale_ext_valid = false;
+    int ale_iters = 0;
+    // FP64 system
+    double *d_val64 = nullptr, *d_rhs64 = nullptr, *d_Finv64 = nullptr, *d_Dinv64 = nullptr, *d_Sinv64 = nullptr;
+    double *d_V64 = nullptr, *d_w64 = nullptr, *d_sw64 = nullptr, *d_Z64 = nullptr;
+    // FP32 system + refinement
+    float *d_val32 = nullptr, *d_Finv32 = nullptr, *d_Dinv32 = nullptr, *d_Sinv32 = nullptr;
+    float *d_V32 = nullptr, *d_w32 = nullptr, *d_x32 = nullptr, *d_r32 = nullptr, *d_sw32 = nullptr,
+          *d_Z32 = nullptr;
+    double *d_r64 = nullptr, *d_b64 = nullptr;
+    // reductions
+    GmState *d_st = nullptr;
+    GmState *h_st = nullptr;
+    double *d_partial = nullptr;
+    int nb_red = 1;
+
+    std::vector<void *> allocs;
+    int64_t device_bytes = 0;
+
+    // timing
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+    std::vector<std::pair<int, int>> ev_tag;
+    size_t ev_used = 0;
+    hipEvent_t ev_step0 = nullptr, ev_step1 = nullptr, ev_asm1 = nullptr;
+
+    double t = 0;
+    int nlev = 0;
+    int64_t step_index = 0;
+
+    ~Sim();
+    lx_status dalloc(void **p, size_t bytes);
+    lx_status create(const lx_device *dev, const lx_mesh *mesh, const lx_problem *pr, const lx_solver *sv);
+    RowPattern pattern() const;
+    const double *hist(int l) const { return (l < prob.bdf_order && d_hist[l]) ? d_hist[l] : d_hist[0]; }
+
+    std::pair<hipEvent_t, hipEvent_t> *timer_begin(int kind, int iter);
+    void timer_end(std::pair<hipEvent_t, hipEvent_t> *p);
+    void timer_flush(int kused, lx_step_stats &acc);
+    lx_status read_state();
+
+    template <typename T>
+    lx_status gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, GmResult &res,
+                    lx_step_stats &tstats, bool inner = false);
+    void coefficients(double t1, StepCoef &C, BCSet &B) const;
+    lx_status prepare(double t1, StepCoef &C);
+    lx_status build_system(double t1, StepCoef &C, lx_step_stats &tstats);
+    void add_neumann(double t1, double *out0, double *out1);
+    lx_status residual64(const StepCoef &C, const double *xs, bool first, double t1);
+    lx_status step(lx_step_stats *out);
+
+    lx_status ale_setup();
+    lx_status ale_extend();
+    lx_status ale_update(double t1, const StepCoef &C);
+    void ale_commit();
+};
+
+}  // namespace lx
+
+struct lx_sim : public lx::Sim {};

@@ -1,0 +1,727 @@
+// The simulation object behind the C ABI: device state, one time step (FP64,
+// or FP32 with FP64 iterative refinement) and the GMRES driver.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <cstdio>
+#include <cstdlib>
+#include <memory>
+
+#include "lx_kernels.h"
+#include "lx_sim.h"
+
+namespace lx {
+
+// ------------------------------------------------------------------ helpers
+
+double law_value(const lx_time_law &L, double t)
+{
+    const double *p = L.p;
+    switch (L.kind) {
+    case LX_LAW_CONSTANT:
+        return p[0];
+    case LX_LAW_PULSATILE:
+        return p[0] + (p[1] - p[0]) * 0.5 * (1.0 - std::cos(2.0 * M_PI * t / p[2]));
+    case LX_LAW_RAMP:
+        if (t < p[2]) return p[0];
+        if (t < p[2] + p[3]) return p[0] + 0.5 * (p[1] - p[0]) * (1.0 - std::cos(M_PI * (t - p[2]) / p[3]));
+        return p[1];
+    case LX_LAW_RAMP2: {
+        double tau = p[6] > 0 ? std::fmod(t, p[6]) : t;
+        if (tau < p[2]) return p[0];
+        if (tau < p[2] + p[3]) return p[0] + 0.5 * (p[1] - p[0]) * (1.0 - std::cos(M_PI * (tau - p[2]) / p[3]));
+        if (tau < p[4]) return p[1];
+        if (tau < p[4] + p[5]) return p[1] + 0.5 * (p[0] - p[1]) * (1.0 - std::cos(M_PI * (tau - p[4]) / p[5]));
+        return p[0];
+    }
+    }
+    return 0.0;
+}
+
+static const double kAlpha[4] = {0, 1.0, 1.5, 11.0 / 6.0};
+static const double kBeta[4][3] = {{0, 0, 0}, {1.0, 0, 0}, {2.0, -0.5, 0}, {3.0, -1.5, 1.0 / 3.0}};
+static const double kGamma[4][3] = {{0, 0, 0}, {1.0, 0, 0}, {2.0, -1.0, 0}, {3.0, -3.0, 1.0}};
+
+lx_status Sim::dalloc(void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) return LX_OK;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail(LX_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    allocs.push_back(*p);
+    device_bytes += (int64_t)bytes;
+    return LX_OK;
+}
+
+Sim::~Sim()
+{
+    if (device >= 0) (void)hipSetDevice(device);
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void *p : allocs) (void)hipFree(p);
+    if (h_st) (void)hipHostFree(h_st);
+    for (auto &ev : ev_pool) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    if (ev_step0) (void)hipEventDestroy(ev_step0);
+    if (ev_step1) (void)hipEventDestroy(ev_step1);
+    if (ev_asm1) (void)hipEventDestroy(ev_asm1);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+// ------------------------------------------------------------------ creation
+
+lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_problem *pr, const lx_solver *sv)
+{
+    if (!pr || !sv) return fail(LX_EINVAL, "problem/solver NULL");
+    if (pr->fe != LX_P1P1) return fail(LX_EINVAL, "only the P1-P1 pair is built in this library");
+    if (pr->bdf_order < 1 || pr->bdf_order > 3) return fail(LX_EINVAL, "bdf_order must be 1..3");
+    if (!(pr->dt > 0) || !(pr->rho > 0) || !(pr->mu >= 0)) return fail(LX_EINVAL, "dt, rho must be > 0, mu >= 0");
+    if (pr->semi_implicit != 1) return fail(LX_EINVAL, "only the semi-implicit formulation is supported");
+    if (pr->n_riis < 0 || pr->n_riis > kMaxValves) return fail(LX_EINVAL, "at most %d RIIS surfaces", kMaxValves);
+    if (pr->n_bc < 0 || pr->n_bc > kMaxBC) return fail(LX_EINVAL, "at most %d boundary conditions", kMaxBC);
+    if (sv->restart < 1 || sv->restart > kMaxRestart) return fail(LX_EINVAL, "restart must be 1..%d", kMaxRestart);
+    if (sv->precision != LX_FP64 && sv->precision != LX_FP32_IR) return fail(LX_EINVAL, "bad precision");
+    if (pr->stab < 0 || pr->stab > 2) return fail(LX_EINVAL, "bad stabilisation");
+    if (sv->schur_degree < 0 || sv->schur_degree > 32) return fail(LX_EINVAL, "schur_degree must be 0..32");
+    if (sv->schur_degree > 0 && !(sv->schur_ratio > 1.0)) return fail(LX_EINVAL, "schur_ratio must be > 1");
+
+    prob = *pr;
+    solver = *sv;
+    for (int i = 0; i < pr->n_bc; ++i) {
+        BCDesc b;
+        b.spec = pr->bc[i];
+        if (b.spec.n_tags > 0 && !b.spec.tags) return fail(LX_EINVAL, "bc %d: tags NULL", i);
+        b.tags.assign(b.spec.tags, b.spec.tags + b.spec.n_tags);
+        b.spec.tags = nullptr;
+        if (b.spec.type < 0 || b.spec.type > 2) return fail(LX_EINVAL, "bc %d: bad type", i);
+        bcs.push_back(b);
+    }
+    prob.bc = nullptr;
+    valves.assign(pr->riis, pr->riis + pr->n_riis);
+    prob.riis = nullptr;
+    if (pr->ale) {
+        ale_tags.assign(pr->ale_tags, pr->ale_tags + pr->n_ale_tags);
+    }
+    prob.ale_tags = nullptr;
+    if (prob.C_r <= 0) prob.C_r = 30.0;
+
+    lx_status st = build_setup(mesh, hs);
+    if (st != LX_OK) return st;
+    nv = hs.nv;
+    nt = hs.nt;
+    nblk = (int64_t)hs.col.size();
+    N = 4 * nv;
+
+    // boundary sets in the new numbering
+    std::vector<int32_t> owner(nv, -1);
+    auto face_vertices = [&](const std::vector<int32_t> &tags, std::vector<int32_t> &out_faces) {
+        out_faces.clear();
+        for (int64_t f = 0; f < mesh->n_bfaces; ++f) {
+            int32_t tg = mesh->bface_tag[f];
+            if (std::find(tags.begin(), tags.end(), tg) == tags.end()) continue;
+            for (int k = 0; k < 3; ++k) {
+                int32_t v = mesh->bfaces[3 * f + k];
+                if (v < 0 || v >= nv) return false;
+                out_faces.push_back(hs.iperm_v[v]);
+            }
+        }
+        return true;
+    };
+    std::vector<int32_t> fv;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int i = 0; i < (int)bcs.size(); ++i) {
+            int ty = bcs[i].spec.type;
+            if ((pass == 0 && ty != LX_BC_NOSLIP) || (pass == 1 && ty != LX_BC_DIRICHLET)) continue;
+            if (!face_vertices(bcs[i].tags, fv)) return fail(LX_EMESH, "boundary face vertex out of range");
+            for (int32_t v : fv)
+                if (owner[v] < 0) owner[v] = i;
+        }
+    h_dir_index.assign(nv, -1);
+    for (int64_t v = 0; v < nv; ++v)
+        if (owner[v] >= 0) {
+            h_dir_index[v] = (int32_t)h_dir_node.size();
+            h_dir_node.push_back((int32_t)v);
+            h_dir_bc.push_back(owner[v]);
+        }
+    n_dir = (int64_t)h_dir_node.size();
+    h_gnodal.assign(3 * std::max<int64_t>(n_dir, 1), 0.0);
+    for (int i = 0; i < (int)bcs.size(); ++i) {
+        if (bcs[i].spec.type != LX_BC_NEUMANN) continue;
+        if (!face_vertices(bcs[i].tags, fv)) return fail(LX_EMESH, "boundary face vertex out of range");
+        bcs[i].nf = (int64_t)fv.size() / 3;
+        bcs[i].h_faces = fv;
+    }
+    if (prob.ale) {
+        if (!face_vertices(ale_tags, fv)) return fail(LX_EMESH, "boundary face vertex out of range");
+        std::vector<char> mark(nv, 0);
+        for (int32_t v : fv) mark[v] = 1;
+        for (int64_t v = 0; v < nv; ++v)
+            if (mark[v]) h_ale_nodes.push_back((int32_t)v);
+    }
+
+    // ---- device side: everything above is host-only validation and setup
+    device = dev ? dev->device : 0;
+    LX_HIP(hipSetDevice(device));
+    if (dev && dev->hip_stream) {
+        stream = (hipStream_t)dev->hip_stream;
+        own_stream = false;
+    } else {
+        LX_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        own_stream = true;
+    }
+
+#define ALLOC(ptr, bytes)                                      \
+    do {                                                       \
+        lx_status _s = dalloc((void **)&(ptr), (bytes));       \
+        if (_s != LX_OK) return _s;                            \
+    } while (0)
+    ALLOC(d_xh, sizeof(double) * 3 * nv);
+    ALLOC(d_x, sizeof(double) * 3 * nv);
+    ALLOC(d_tet, sizeof(int32_t) * 4 * nt);
+    ALLOC(d_eslot, sizeof(int32_t) * 16 * nt);
+    ALLOC(d_rowptr, sizeof(int32_t) * (nv + 1));
+    ALLOC(d_col, sizeof(int32_t) * nblk);
+    ALLOC(d_diag, sizeof(int32_t) * nv);
+    ALLOC(d_tslot, sizeof(int32_t) * nblk);
+    ALLOC(d_dir_index, sizeof(int32_t) * nv);
+    if (n_dir > 0) {
+        ALLOC(d_dir_node, sizeof(int32_t) * n_dir);
+        ALLOC(d_dir_bc, sizeof(int32_t) * n_dir);
+        ALLOC(d_g, sizeof(double) * 3 * n_dir);
+        ALLOC(d_gnodal, sizeof(double) * 3 * n_dir);
+        ALLOC(d_dg, sizeof(double) * 3 * n_dir);
+    }
+    const int L = prob.bdf_order;
+    for (int l = 0; l < L; ++l) ALLOC(d_hist[l], sizeof(double) * N);
+    ALLOC(d_xs, sizeof(double) * N);
+    if (prob.forcing) ALLOC(d_f, sizeof(double) * 3 * nv);
+    if (prob.ale) {
+        ALLOC(d_uA, sizeof(double) * 3 * nv);
+        for (int l = 0; l < L; ++l) ALLOC(d_dhist[l], sizeof(double) * 3 * nv);
+        ALLOC(d_ale_shape, sizeof(double) * 3 * nv);
+        lx_status s2 = ale_setup();
+        if (s2 != LX_OK) return s2;
+    }
+    for (auto &b : bcs)
+        if (b.spec.type == LX_BC_NEUMANN && b.nf > 0) {
+            ALLOC(b.d_faces, sizeof(int32_t) * 3 * b.nf);
+            if (b.spec.profile.kind == LX_PROFILE_NODAL) ALLOC(b.d_hnodal, sizeof(double) * 3 * nv);
+        }
+    const int m = solver.restart;
+    nb_red = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (N + 2047) / 2048));
+    ALLOC(d_st, sizeof(GmState));
+    ALLOC(d_partial, sizeof(double) * nb_red * 64);
+    LX_HIP(hipHostMalloc((void **)&h_st, sizeof(GmState), hipHostMallocDefault));
+    if (solver.precision == LX_FP64) {
+        ALLOC(d_val64, sizeof(double) * kPlanes * nblk);
+        ALLOC(d_rhs64, sizeof(double) * N);
+        ALLOC(d_Finv64, sizeof(double) * 9 * nv);
+        ALLOC(d_Dinv64, sizeof(double) * 3 * nv);
+        ALLOC(d_Sinv64, sizeof(double) * nv);
+        ALLOC(d_V64, sizeof(double) * N * (m + 1));
+        ALLOC(d_Z64, sizeof(double) * N * m);
+        ALLOC(d_sw64, sizeof(double) * 6 * nv);
+        ALLOC(d_w64, sizeof(double) * N);
+    } else {
+        ALLOC(d_val32, sizeof(float) * kPlanes * nblk);
+        ALLOC(d_Finv32, sizeof(float) * 9 * nv);
+        ALLOC(d_Dinv32, sizeof(float) * 3 * nv);
+        ALLOC(d_Sinv32, sizeof(float) * nv);
+        ALLOC(d_V32, sizeof(float) * N * (m + 1));
+        if (solver.asm_fp64) ALLOC(d_val64, sizeof(double) * kPlanes * nblk);
+        ALLOC(d_Z32, sizeof(float) * N * m);
+        ALLOC(d_sw32, sizeof(float) * 6 * nv);
+        ALLOC(d_w32, sizeof(float) * N);
+        ALLOC(d_x32, sizeof(float) * N);
+        ALLOC(d_r32, sizeof(float) * N);
+        ALLOC(d_r64, sizeof(double) * N);
+        ALLOC(d_b64, sizeof(double) * N);
+    }
+#undef ALLOC
+    // ---- uploads
+    LX_HIP(hipMemcpyAsync(d_xh, hs.xh.data(), sizeof(double) * 3 * nv, hipMemcpyHostToDevice, stream));
+    LX_HIP(hipMemcpyAsync(d_x, hs.xh.data(), sizeof(double) * 3 * nv, hipMemcpyHostToDevice, stream));
+    LX_HIP(hipMemcpyAsync(d_tet, hs.tet_soa.data(), sizeof(int32_t) * 4 * nt, hipMemcpyHostToDevice, stream));
+    LX_HIP(hipMemcpyAsync(d_eslot, hs.eslot.data(), sizeof(int32_t) * 16 * nt, hipMemcpyHostToDevice, stream));
+    LX_HIP(hipMemcpyAsync(d_rowptr, hs.rowptr.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice, stream));
+    LX_HIP(hipMemcpyAsync(d_col, hs.col.data(), sizeof(int32_t) * nblk, hipMemcpyHostToDevice, stream));
+    LX_HIP(hipMemcpyAsync(d_diag, hs.diag.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, stream));
+    LX_HIP(hipMemcpyAsync(d_tslot, hs.tslot.data(), sizeof(int32_t) * nblk, hipMemcpyHostToDevice, stream));
+    LX_HIP(hipMemcpyAsync(d_dir_index, h_dir_index.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, stream));
+    if (n_dir > 0) {
+        LX_HIP(hipMemcpyAsync(d_dir_node, h_dir_node.data(), sizeof(int32_t) * n_dir, hipMemcpyHostToDevice, stream));
+        LX_HIP(hipMemcpyAsync(d_dir_bc, h_dir_bc.data(), sizeof(int32_t) * n_dir, hipMemcpyHostToDevice, stream));
+        launch_fill<double>(3 * n_dir, d_gnodal, 0.0, stream);
+    }
+    for (auto &b : bcs)
+        if (b.d_faces)
+            LX_HIP(hipMemcpyAsync(b.d_faces, b.h_faces.data(), sizeof(int32_t) * 3 * b.nf, hipMemcpyHostToDevice,
+                                  stream));
+    for (int l = 0; l < L; ++l) launch_fill<double>(N, d_hist[l], 0.0, stream);
+    launch_fill<double>(N, d_xs, 0.0, stream);
+    if (d_f) launch_fill<double>(3 * nv, d_f, 0.0, stream);
+    if (prob.ale) {
+        launch_fill<double>(3 * nv, d_uA, 0.0, stream);
+        for (int l = 0; l < L; ++l) launch_fill<double>(3 * nv, d_dhist[l], 0.0, stream);
+        launch_fill<double>(3 * nv, d_dnew, 0.0, stream);
+        launch_fill<double>(3 * nv, d_ale_shape, 0.0, stream);
+    }
+    for (auto &b : bcs)
+        if (b.d_hnodal) launch_fill<double>(3 * nv, b.d_hnodal, 0.0, stream);
+    LX_HIP(hipMemsetAsync(d_st, 0, sizeof(GmState), stream));
+    LX_HIP(hipEventCreate(&ev_step0));
+    LX_HIP(hipEventCreate(&ev_step1));
+    LX_HIP(hipEventCreate(&ev_asm1));
+    LX_HIP(hipStreamSynchronize(stream));
+    LX_HIP(hipGetLastError());
+    t = prob.t0;
+    nlev = 0;
+    return LX_OK;
+}
+
+RowPattern Sim::pattern() const
+{
+    RowPattern P;
+    P.nv = nv;
+    P.nblk = nblk;
+    P.rowptr = d_rowptr;
+    P.col = d_col;
+    P.diag = d_diag;
+    P.tslot = d_tslot;
+    return P;
+}
+
+// ------------------------------------------------------------------ timing
+
+std::pair<hipEvent_t, hipEvent_t> *Sim::timer_begin(int kind, int iter)
+{
+    if (!solver.collect_timing) return nullptr;
+    if (ev_used >= ev_pool.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return nullptr;
+        if (hipEventCreate(&b) != hipSuccess) return nullptr;
+        ev_pool.push_back({a, b});
+        ev_tag.push_back({0, 0});
+    }
+    auto *p = &ev_pool[ev_used];
+    ev_tag[ev_used] = {kind, iter};
+    ++ev_used;
+    (void)hipEventRecord(p->first, stream);
+    return p;
+}
+
+void Sim::timer_end(std::pair<hipEvent_t, hipEvent_t> *p)
+{
+    if (p) (void)hipEventRecord(p->second, stream);
+}
+
+// Accumulate recorded kernel times; in-cycle SpMVs with iteration index >= kused
+// were skipped by the device-side exit and are not counted.
+void Sim::timer_flush(int kused, lx_step_stats &acc)
+{
+    for (size_t i = 0; i < ev_used; ++i) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, ev_pool[i].first, ev_pool[i].second) != hipSuccess) continue;
+        int kind = ev_tag[i].first, it = ev_tag[i].second;
+        if (kind == 0) {
+            if (it >= 0 && it >= kused) continue;
+            acc.spmv_ms += ms;
+            acc.spmv_calls += 1;
+        } else if (kind == 1) {
+            acc.asm_ms += ms;
+            acc.asm_calls += 1;
+        } else if (kind == 2) {
+            acc.resid_ms += ms;
+            acc.resid_calls += 1;
+        }
+    }
+    ev_used = 0;
+}
+
+// ------------------------------------------------------------------ GMRES
+
+template <typename T>
+struct Ops;
+template <>
+struct Ops<double> {
+    static double *val(Sim *s) { return s->d_val64; }
+    static double *Finv(Sim *s) { return s->d_Finv64; }
+    static double *Dinv(Sim *s) { return s->d_Dinv64; }
+    static double *Sinv(Sim *s) { return s->d_Sinv64; }
+    static double *V(Sim *s) { return s->d_V64; }
+    static double *w(Sim *s) { return s->d_w64; }
+    static double *sw(Sim *s) { return s->d_sw64; }
+    static double *Z(Sim *s) { return s->d_Z64; }
+};
+template <>
+struct Ops<float> {
+    static float *val(Sim *s) { return s->d_val32; }
+    static float *Finv(Sim *s) { return s->d_Finv32; }
+    static float *Dinv(Sim *s) { return s->d_Dinv32; }
+    static float *Sinv(Sim *s) { return s->d_Sinv32; }
+    static float *V(Sim *s) { return s->d_V32; }
+    static float *w(Sim *s) { return s->d_w32; }
+    static float *sw(Sim *s) { return s->d_sw32; }
+    static float *Z(Sim *s) { return s->d_Z32; }
+};
+
+lx_status Sim::read_state()
+{
+    const size_t off = offsetof(GmState, tol_abs);
+    LX_HIP(hipMemcpyAsync((char *)h_st + off, (char *)d_st + off, sizeof(GmState) - off, hipMemcpyDeviceToHost,
+                          stream));
+    LX_HIP(hipStreamSynchronize(stream));
+    return LX_OK;
+}
+
+static bool verbose()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("LXNS_VERBOSE");
+        v = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return v == 1;
+}
+
+// Flexible (right-preconditioned) restarted GMRES(m) with CGS2 orthogonalisation:
+// the preconditioned directions Z_j = M^{-1} v_j are kept and x += Z y at the end
+// of a cycle, so the update uses exactly the vectors of the Arnoldi process.
+// b and x
+// are device vectors of length N; x holds the initial guess (x_zero: it is 0).
+// An inner solve (of iterative refinement) stops as soon as the Givens
+// residual estimate meets rtol inside a cycle; the outer FP64 residual judges
+// the correction, so the true residual is not re-verified in low precision.
+template <typename T>
+lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, GmResult &res,
+                     lx_step_stats &tstats, bool inner)
+{
+    const RowPattern P = pattern();
+    const T *val = Ops<T>::val(this);
+    T *V = Ops<T>::V(this), *w = Ops<T>::w(this), *Z = Ops<T>::Z(this);
+    const Simple<T> SP{val, Ops<T>::Finv(this), Ops<T>::Dinv(this), Ops<T>::Sinv(this), solver.schur_degree,
+                       solver.schur_ratio, Ops<T>::sw(this), d_st};
+    const int m = solver.restart;
+    const int64_t ld = N;
+    launch_norm<T>(N, b, d_st, rtol, d_partial, nb_red, 0, stream);
+    if (x_zero) launch_fill<T>(N, x, T(0), stream);
+    int it = 0;
+    res = GmResult();
+    for (int cycle = 0;; ++cycle) {
+        if (x_zero && cycle == 0) {
+            launch_gm_start<T>(N, b, nullptr, V, d_st, d_partial, nb_red, stream);
+        } else {
+            auto *tm = timer_begin(0, -1);
+            launch_spmv<T>(P, val, x, w, nullptr, stream);
+            timer_end(tm);
+            launch_gm_start<T>(N, b, w, V, d_st, d_partial, nb_red, stream);
+        }
+        const int kmax = std::min(m, max_iters - it);
+        for (int k = 0; k < kmax; ++k) {
+            T *zk = Z + k * ld;
+            launch_simple_apply<T>(P, SP, V + k * ld, &d_st->s[k], zk, &d_st->done, stream);
+            auto *tm = timer_begin(0, k);
+            launch_spmv<T>(P, val, zk, w, &d_st->done, stream);
+            timer_end(tm);
+            launch_gm_dot1<T>(N, k, V, ld, w, d_st, d_partial, nb_red, stream);
+            launch_gm_axpy_dot2<T>(N, k, V, ld, w, d_st, d_partial, nb_red, stream);
+            launch_gm_axpy_norm<T>(N, k, V, ld, w, d_st, d_partial, nb_red, stream);
+        }
+        LX_HIP(hipGetLastError());
+        lx_status s = read_state();
+        if (s != LX_OK) return s;
+        timer_flush(h_st->kused, tstats);
+        res.bnorm = h_st->norms[0];
+        if (h_st->kused == 0) {
+            // the cycle start found the true residual below tolerance (or broke down)
+            res.resid = h_st->resid;
+            res.converged = h_st->converged != 0;
+            res.iters = it;
+            return LX_OK;
+        }
+        ++res.restarts;
+        it += h_st->kused;
+        if (verbose())
+            fprintf(stderr, "[lxns] gmres<%s> cycle %d: k=%d est=%.3e tol=%.3e bnorm=%.3e\n",
+                    sizeof(T) == 4 ? "f32" : "f64", cycle, h_st->kused, h_st->resid, h_st->tol_abs, h_st->norms[0]);
+        launch_gm_solve_y(d_st, stream);
+        launch_gm_update<T>(N, Z, ld, d_st, x, stream);
+        if (inner && h_st->converged) {
+            res.iters = it;
+            res.resid = h_st->resid;
+            res.converged = true;
+            return LX_OK;
+        }
+        if (inner && it >= max_iters) {
+            res.iters = it;
+            res.resid = h_st->resid;
+            res.converged = false;
+            return LX_OK;
+        }
+        if (h_st->breakdown) {
+            res.iters = it;
+            res.resid = h_st->resid;
+            return fail(LX_ENOCONV, "GMRES breakdown (non-finite value) after %d iterations", it);
+        }
+        if (it >= max_iters && !h_st->converged) {
+            // final true residual
+            launch_spmv<T>(P, val, x, w, nullptr, stream);
+            launch_gm_start<T>(N, b, w, V, d_st, d_partial, nb_red, stream);
+            s = read_state();
+            if (s != LX_OK) return s;
+            res.iters = it;
+            res.resid = h_st->resid;
+            res.converged = h_st->converged != 0;
+            return LX_OK;
+        }
+        x_zero = false;
+    }
+}
+template lx_status Sim::gmres<double>(const double *, double *, bool, double, int, GmResult &, lx_step_stats &,
+                                      bool);
+template lx_status Sim::gmres<float>(const float *, float *, bool, double, int, GmResult &, lx_step_stats &,
+                                     bool);
+
+// ------------------------------------------------------------------ step
+
+void Sim::coefficients(double t1, StepCoef &C, BCSet &B) const
+{
+    memset(&C, 0, sizeof(C));
+    const int order = std::max(1, std::min(prob.bdf_order, std::max(nlev, 1)));
+    C.alpha = kAlpha[order];
+    C.sigma = order;
+    C.dt = prob.dt;
+    C.rho = prob.rho;
+    C.mu = prob.mu;
+    C.C_r = prob.C_r;
+    for (int l = 0; l < 3; ++l) {
+        C.beta[l] = kBeta[order][l];
+        C.gamma[l] = kGamma[order][l];
+    }
+    C.nlev = order;
+    C.stab = prob.stab;
+    C.symgrad = prob.diffusion == LX_DIFF_SYMGRAD;
+    C.n_valves = (int)valves.size();
+    for (int k = 0; k < C.n_valves; ++k) {
+        const lx_riis &v = valves[k];
+        double nn = std::sqrt(v.normal[0] * v.normal[0] + v.normal[1] * v.normal[1] + v.normal[2] * v.normal[2]);
+        for (int c = 0; c < 3; ++c) {
+            C.valve[k][c] = v.center[c];
+            C.valve[k][3 + c] = v.normal[c] / nn;
+        }
+        C.valve[k][6] = law_value(v.orifice_radius, t1);
+        C.valve[k][7] = v.outer_radius;
+        C.valve[k][8] = v.R;
+        C.valve[k][9] = v.eps;
+    }
+    memset(&B, 0, sizeof(B));
+    B.n = (int)bcs.size();
+    B.ale = prob.ale;
+    for (int i = 0; i < B.n; ++i) {
+        const lx_boundary &s = bcs[i].spec;
+        B.bc[i].type = s.type;
+        B.bc[i].profile = s.profile.kind;
+        B.bc[i].scale = s.theta * law_value(s.law, t1);
+        for (int c = 0; c < 3; ++c) {
+            B.bc[i].center[c] = s.profile.center[c];
+            B.bc[i].normal[c] = s.profile.normal[c];
+        }
+        B.bc[i].radius = s.profile.radius;
+    }
+}
+
+// Coefficients, mesh motion and boundary values of the coming step.
+lx_status Sim::prepare(double t1, StepCoef &C)
+{
+    BCSet B;
+    coefficients(t1, C, B);
+    if (prob.ale) {
+        lx_status s = ale_update(t1, C);
+        if (s != LX_OK) return s;
+    }
+    if (n_dir > 0) {
+        if (dirty_gnodal) {
+            LX_HIP(hipMemcpyAsync(d_gnodal, h_gnodal.data(), sizeof(double) * 3 * n_dir, hipMemcpyHostToDevice,
+                                  stream));
+            dirty_gnodal = false;
+        }
+        launch_dirichlet_values(n_dir, d_dir_node, d_dir_bc, B, d_x, d_uA, d_gnodal, d_g, stream);
+    }
+    return LX_OK;
+}
+
+// Everything that builds the system of the coming step (no solve).
+lx_status Sim::build_system(double t1, StepCoef &C, lx_step_stats &tstats)
+{
+    (void)tstats;
+    lx_status ps = prepare(t1, C);
+    if (ps != LX_OK) return ps;
+    const RowPattern P = pattern();
+    if (solver.precision == LX_FP64) {
+        launch_fill<double>(kPlanes * nblk, d_val64, 0.0, stream);
+        launch_fill<double>(N, d_rhs64, 0.0, stream);
+        AsmArgs<double> A{nt, nblk, d_tet, d_eslot, d_x, d_xh, hist(0), hist(1), hist(2), d_uA, d_f, d_val64, d_rhs64};
+        auto *tm = timer_begin(1, 0);
+        launch_assemble_p1<double>(A, C, stream);
+        timer_end(tm);
+        add_neumann(t1, d_rhs64, nullptr);
+        launch_dirichlet_rows<double>(n_dir, d_dir_node, d_g, P, d_val64, d_rhs64, stream);
+        launch_simple_setup<double>(P, d_val64, d_Finv64, d_Dinv64, d_Sinv64, stream);
+        if (solver.schur_degree > 0)
+            launch_schur_bound<double>(P, d_val64, d_Dinv64, d_Sinv64, d_sw64, d_st, d_partial, nb_red, stream);
+    } else {
+        if (solver.asm_fp64) {
+            launch_fill<double>(kPlanes * nblk, d_val64, 0.0, stream);
+            AsmArgs<double> A{nt, nblk, d_tet, d_eslot, d_x, d_xh, hist(0), hist(1), hist(2), d_uA, d_f, d_val64,
+                              nullptr};
+            auto *tm = timer_begin(1, 0);
+            launch_assemble_p1<double>(A, C, stream);
+            timer_end(tm);
+            launch_scale_copy<float, double>(kPlanes * nblk, d_val32, d_val64, 1.0, stream);
+        } else {
+            launch_fill<float>(kPlanes * nblk, d_val32, 0.0f, stream);
+            AsmArgs<float> A{nt, nblk, d_tet, d_eslot, d_x, d_xh, hist(0), hist(1), hist(2), d_uA, d_f, d_val32,
+                             nullptr};
+            auto *tm = timer_begin(1, 0);
+            launch_assemble_p1<float>(A, C, stream);
+            timer_end(tm);
+        }
+        launch_dirichlet_rows<float>(n_dir, d_dir_node, d_g, P, d_val32, (float *)nullptr, stream);
+        launch_simple_setup<float>(P, d_val32, d_Finv32, d_Dinv32, d_Sinv32, stream);
+        if (solver.schur_degree > 0)
+            launch_schur_bound<float>(P, d_val32, d_Dinv32, d_Sinv32, d_sw32, d_st, d_partial, nb_red, stream);
+    }
+    LX_HIP(hipGetLastError());
+    return LX_OK;
+}
+
+void Sim::add_neumann(double t1, double *out0, double *out1)
+{
+    for (auto &b : bcs) {
+        if (b.spec.type != LX_BC_NEUMANN || b.nf == 0) continue;
+        double hc[3] = {0, 0, 0};
+        const double *hn = nullptr;
+        if (b.spec.profile.kind == LX_PROFILE_NODAL) {
+            if (!b.nodal_set) continue;
+            hn = b.d_hnodal;
+        } else {
+            // sigma n = -theta h(t) n
+            double h = b.spec.theta * law_value(b.spec.law, t1);
+            if (h == 0.0) continue;
+            for (int c = 0; c < 3; ++c) hc[c] = -h * b.spec.profile.normal[c];
+        }
+        launch_neumann(b.nf, b.d_faces, d_x, hn, hc, out0, out1, nullptr, stream);
+    }
+}
+
+// FP64 matrix-free residual r = b - A xs (first: also b and the Dirichlet diagonal).
+lx_status Sim::residual64(const StepCoef &C, const double *xs, bool first, double t1)
+{
+    launch_fill<double>(N, d_r64, 0.0, stream);
+    if (first) {
+        launch_fill<double>(N, d_b64, 0.0, stream);
+        if (n_dir > 0) launch_fill<double>(3 * n_dir, d_dg, 0.0, stream);
+    }
+    ResArgs R{nt, d_tet, d_x, d_xh, hist(0), hist(1), hist(2), d_uA, d_f, xs, d_dir_index, d_r64,
+              first ? d_b64 : nullptr, first ? d_dg : nullptr};
+    auto *tm = timer_begin(2, 0);
+    launch_residual_p1(R, C, stream);
+    timer_end(tm);
+    add_neumann(t1, d_r64, first ? d_b64 : nullptr);
+    launch_dirichlet_residual(n_dir, d_dir_node, d_g, d_dg, xs, d_r64, first ? d_b64 : nullptr, stream);
+    LX_HIP(hipGetLastError());
+    return LX_OK;
+}
+
+lx_status Sim::step(lx_step_stats *out)
+{
+    LX_HIP(hipSetDevice(device));
+    lx_step_stats S;
+    memset(&S, 0, sizeof(S));
+    const double t1 = t + prob.dt;
+    const int L = prob.bdf_order;
+    LX_HIP(hipEventRecord(ev_step0, stream));
+    StepCoef C;
+    lx_status st = build_system(t1, C, S);
+    if (st != LX_OK) return st;
+    LX_HIP(hipEventRecord(ev_asm1, stream));
+    // initial guess: previous solution with the new Dirichlet values
+    LX_HIP(hipMemcpyAsync(d_xs, d_hist[0], sizeof(double) * N, hipMemcpyDeviceToDevice, stream));
+    launch_set_dirichlet_x(n_dir, d_dir_node, d_g, d_xs, stream);
+    GmResult gr;
+    if (solver.precision == LX_FP64) {
+        st = gmres<double>(d_rhs64, d_xs, false, solver.rtol, solver.max_iters, gr, S);
+        if (st != LX_OK) return st;
+        S.gmres_iters = gr.iters;
+        S.restarts = gr.restarts;
+        S.rel_residual = gr.bnorm > 0 ? gr.resid / gr.bnorm : gr.resid;
+        S.converged = gr.converged;
+    } else {
+        // FP32 matrix and inner GMRES inside FP64 iterative refinement
+        st = residual64(C, d_xs, true, t1);
+        if (st != LX_OK) return st;
+        launch_norm<double>(N, d_b64, d_st, 0.0, d_partial, nb_red, 1, stream);
+        launch_norm<double>(N, d_r64, d_st, 0.0, d_partial, nb_red, 2, stream);
+        st = read_state();
+        if (st != LX_OK) return st;
+        const double bnorm = h_st->norms[1] > 0 ? h_st->norms[1] : 1.0;
+        double rnorm = h_st->norms[2];
+        int total = 0, ir = 0;
+        bool conv = rnorm <= solver.ir_rtol * bnorm;
+        while (!conv && ir < solver.max_ir && total < solver.max_iters) {
+            // aim the inner tolerance at finishing in one more refinement step, but not below inner_rtol
+            double want = 0.3 * solver.ir_rtol * bnorm / rnorm;
+            double rin = std::max(solver.inner_rtol, std::min(want, 0.5));
+            launch_scale_copy<float, double>(N, d_r32, d_r64, 1.0 / rnorm, stream);
+            GmResult g32;
+            st = gmres<float>(d_r32, d_x32, true, rin, solver.max_iters - total, g32, S, true);
+            if (st != LX_OK) return st;
+            total += g32.iters;
+            S.restarts += g32.restarts;
+            launch_axpy<double, float>(N, d_xs, d_x32, nullptr, rnorm, stream);
+            ++ir;
+            st = residual64(C, d_xs, false, t1);
+            if (st != LX_OK) return st;
+            launch_norm<double>(N, d_r64, d_st, 0.0, d_partial, nb_red, 2, stream);
+            st = read_state();
+            if (st != LX_OK) return st;
+            if (verbose())
+                fprintf(stderr, "[lxns] IR %d: inner rtol %.2e, %d iterations, FP64 rel. residual %.3e -> %.3e\n", ir,
+                        rin, g32.iters, rnorm / bnorm, h_st->norms[2] / bnorm);
+            rnorm = h_st->norms[2];
+            conv = rnorm <= solver.ir_rtol * bnorm;
+            if (!(rnorm == rnorm)) break;
+            if (g32.iters == 0 && !g32.converged) break;
+        }
+        S.gmres_iters = total;
+        S.ir_iters = ir;
+        S.rel_residual = rnorm / bnorm;
+        S.converged = conv;
+        timer_flush(0, S);
+    }
+    LX_HIP(hipEventRecord(ev_step1, stream));
+    LX_HIP(hipEventSynchronize(ev_step1));
+    float ms = 0, ma = 0;
+    (void)hipEventElapsedTime(&ms, ev_step0, ev_step1);
+    (void)hipEventElapsedTime(&ma, ev_step0, ev_asm1);
+    S.t_step_ms = ms;
+    S.t_assembly_ms = ma;
+    S.t_solve_ms = ms - ma;
+    if (out) *out = S;
+    if (!S.converged)
+        return fail(LX_ENOCONV, "step did not converge: rel. residual %.3e after %d iterations", S.rel_residual,
+                    S.gmres_iters);
+    // commit: rotate history (u^n -> u^{n-1}, ...) and advance time
+    double *oldest = d_hist[L - 1];
+    for (int l = L - 1; l > 0; --l) d_hist[l] = d_hist[l - 1];
+    d_hist[0] = d_xs;
+    d_xs = oldest;
+    if (prob.ale) ale_commit();
+    nlev = std::min(std::max(nlev, 1) + 1, L);
+    t = t1;
+    ++step_index;
+    return LX_OK;
+}
+
+}  // namespace lx

@@ -1,0 +1,97 @@
+"""Shared problem set-ups for the device-vs-oracle parity tests.
+
+Each case returns (mesh, problem, drive) where drive(sim, t1) pushes the nodal
+data of the step ending at t1 into any object with the simulation interface
+(the device binding or the oracle), and init(sim) sets the history.
+"""
+import numpy as np
+
+from inputs import tube, cube_kuhn, exact
+from inputs.meshes import TUBE_TAGS
+from inputs.problem import (Boundary, Profile, Problem, TimeLaw, Valve, beltrami_cube_problem,
+                            tube_problem)
+
+
+class Case:
+    def __init__(self, mesh, prob, init, drive, name):
+        self.mesh, self.prob, self.init, self.drive, self.name = mesh, prob, init, drive, name
+
+
+def beltrami(n=4, dt=0.01, bdf=1, stab="vms_les"):
+    mesh, prob = beltrami_cube_problem(n, dt=dt, bdf_order=bdf, stab=stab)
+    ex = exact.Beltrami(mu=prob.mu)
+    X = mesh.coords
+
+    def init(s):
+        for lev in range(bdf):
+            s.set_state(lev, ex.velocity(X, -lev * dt), ex.pressure(X, -lev * dt))
+
+    def drive(s, t1):
+        s.set_dirichlet_values(0, ex.velocity(X, t1))
+        s.set_neumann_traction(1, ex.traction(X, t1, (-1, 0, 0)))
+
+    return Case(mesh, prob, init, drive, "beltrami%d" % n)
+
+
+def tube_valve(nxy=4, nz=8, length=2.0, bdf=2, stab="vms_les", diffusion="gradgrad", seed=7, random_hist=True,
+               forcing=False, R=300.0, eps=0.3, peak=50.0):
+    """Jittered, shuffled tube with pulsatile parabolic inflow, no-slip wall, zero-traction
+    outlet and a mid-length RIIS disc; random (seeded) history so that every term is active."""
+    mesh = tube(nxy=nxy, nz=nz, radius=1.0, length=length, seed=seed)
+    prob = tube_problem(mesh, dt=2e-3, bdf_order=bdf, peak=peak, R=R, eps=eps, t0=0.1)
+    prob.stab = stab
+    prob.diffusion = diffusion
+    prob.forcing = forcing
+    rng = np.random.default_rng(seed)
+    hist = [(rng.normal(size=(mesh.nv, 3)) * 10.0, rng.normal(size=mesh.nv) * 100.0) for _ in range(bdf)]
+    f = rng.normal(size=(mesh.nv, 3)) * 5.0
+
+    def init(s):
+        if random_hist:
+            for lev in range(bdf):
+                s.set_state(lev, *hist[lev])
+
+    def drive(s, t1):
+        if forcing:
+            s.set_forcing(f)
+
+    return Case(mesh, prob, init, drive, "tube%dx%d_%s_bdf%d" % (nxy, nz, stab, bdf))
+
+
+def oracle_matrix_from_blocks(br, bc, vals, nv):
+    """Block COO (caller numbering) -> scipy CSR in the oracle's DOF numbering
+    (velocity 3v+c, pressure 3nv+v)."""
+    from scipy.sparse import coo_matrix
+    r = np.arange(4)
+    rowoff = np.where(r < 3, r, 0)
+    rows = np.where(r[None, :] < 3, 3 * br[:, None] + r[None, :], 3 * nv + br[:, None])      # [nb][4]
+    cols = np.where(r[None, :] < 3, 3 * bc[:, None] + r[None, :], 3 * nv + bc[:, None])
+    R = np.repeat(rows[:, :, None], 4, axis=2)
+    Cc = np.repeat(cols[:, None, :], 4, axis=1)
+    del rowoff
+    return coo_matrix((vals.reshape(-1), (R.reshape(-1), Cc.reshape(-1))), shape=(4 * nv, 4 * nv)).tocsr()
+
+
+def rowwise_rel_err(A, Bm):
+    """max over rows of max|A_r - B_r| / max|B_r|."""
+    D = (A - Bm).tocsr()
+    Bc = Bm.tocsr()
+    n = Bc.shape[0]
+    worst = 0.0
+    dmax = np.zeros(n)
+    bmax = np.zeros(n)
+    for M, out in ((D, dmax), (Bc, bmax)):
+        Mabs = abs(M).tocsr()
+        nz = np.diff(Mabs.indptr) > 0
+        out[nz] = np.maximum.reduceat(Mabs.data, Mabs.indptr[:-1][nz])
+    mask = bmax > 0
+    if mask.any():
+        worst = float((dmax[mask] / bmax[mask]).max())
+    if (~mask).any():
+        worst = max(worst, float(dmax[~mask].max()))
+    return worst
+
+
+def rel_l2(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)

@@ -1,0 +1,94 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point that include/lxns.h declares, and rejects bad input before
+touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from inputs import cube_kuhn, tube
+from inputs.problem import SolverCfg, beltrami_cube_problem, tube_problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "lxns.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:lx_status|void|const char \*)\s*\*?\s*(lx_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2304_12032_amd import lib
+    L = lib()
+    syms = declared_symbols()
+    assert len(syms) >= 18
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_binding_signatures_cover_header():
+    from paper_2304_12032_amd.lxns import SIGNATURES
+    assert set(declared_symbols()) == set(SIGNATURES)
+
+
+def _create(mesh, prob, solver):
+    from paper_2304_12032_amd import Sim
+    return Sim(mesh, prob, solver)
+
+
+def test_degenerate_tet_rejected():
+    from paper_2304_12032_amd import LxError
+    mesh, prob = beltrami_cube_problem(2)
+    mesh.coords = mesh.coords.copy()
+    t = mesh.tets[5]
+    # collapse one tet: move a vertex onto the plane of the other three
+    mesh.coords[t[3]] = mesh.coords[t[0]] + 0.3 * (mesh.coords[t[1]] - mesh.coords[t[0]]) \
+        + 0.3 * (mesh.coords[t[2]] - mesh.coords[t[0]])
+    with pytest.raises(LxError) as ei:
+        _create(mesh, prob, SolverCfg())
+    assert ei.value.status == -5
+
+
+def test_vertex_out_of_range_rejected():
+    from paper_2304_12032_amd import LxError
+    mesh, prob = beltrami_cube_problem(2)
+    mesh.tets = mesh.tets.copy()
+    mesh.tets[0, 0] = mesh.nv + 3
+    with pytest.raises(LxError) as ei:
+        _create(mesh, prob, SolverCfg())
+    assert ei.value.status == -5
+
+
+@pytest.mark.parametrize("field,value", [("bdf_order", 4), ("dt", 0.0), ("fe", "p2p1")])
+def test_bad_problem_rejected(field, value):
+    from paper_2304_12032_amd import LxError
+    mesh, prob = beltrami_cube_problem(2)
+    setattr(prob, field, value)
+    with pytest.raises(LxError) as ei:
+        _create(mesh, prob, SolverCfg())
+    assert ei.value.status == -1
+
+
+def test_bad_restart_rejected():
+    from paper_2304_12032_amd import LxError
+    mesh, prob = beltrami_cube_problem(2)
+    with pytest.raises(LxError) as ei:
+        _create(mesh, prob, SolverCfg(restart=65))
+    assert ei.value.status == -1
+
+
+def test_server_rejects_request_over_budget():
+    from paper_2304_12032_amd import Server, LxError
+    m = tube(nxy=4, nz=8, length=2.0)
+    srv = Server(hbm_budget_bytes=1 << 20, max_active=4)
+    with pytest.raises(LxError) as ei:
+        srv.submit(m, tube_problem(m), SolverCfg(precision="fp32_ir"), 5)
+    assert ei.value.status == -6
+    srv2 = Server(hbm_budget_bytes=1 << 34, max_active=4)
+    t = srv2.submit(m, tube_problem(m), SolverCfg(precision="fp32_ir"), 5)
+    assert srv2.poll(t)["state"] == "queued"
+    assert srv2.poll(t)["footprint_bytes"] > 0
+    srv.close()
+    srv2.close()

@@ -1,0 +1,114 @@
+"""Device (HIP, through the C ABI) versus oracle parity.
+
+Tolerances: FP64 matrices and residuals row-wise relative <= 1e-12; FP64 steps
+(device GMRES at rtol 1e-14, oracle dense LU) relative L2 <= 1e-10 for u and p
+separately (the pressure error is the solve tolerance times a conditioning
+factor of about 1e3, hence the tight solve); FP32 matrices <= 2e-5 row-wise;
+FP32 + FP64 refinement steps (refined to 1e-13) <= 1e-8.
+"""
+import numpy as np
+import pytest
+
+from inputs.problem import SolverCfg
+from oracle import OracleSim
+from tests._cases import beltrami, tube_valve, oracle_matrix_from_blocks, rowwise_rel_err, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def stream():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.init()
+    return torch.cuda.current_stream(0).cuda_stream
+
+
+def _gpu(case, stream, precision="fp64", rtol=1e-12, **kw):
+    from paper_2304_12032_amd import Sim
+    sv = SolverCfg(precision=precision, rtol=rtol, ir_rtol=rtol, max_iters=20000, **kw)
+    return Sim(case.mesh, case.prob, sv, device=0, stream=stream)
+
+
+CASES = [
+    lambda: beltrami(4),
+    lambda: tube_valve(4, 8),
+    lambda: tube_valve(8, 16, length=4.0, bdf=3, stab="supg_pspg", diffusion="symgrad", forcing=True),
+    lambda: tube_valve(6, 10, bdf=1, stab="none"),
+]
+IDS = ["beltrami4", "tube_vms_bdf2", "tube8x16_supg_symgrad_bdf3_forcing", "tube_galerkin_bdf1"]
+
+
+@pytest.mark.parametrize("mk", CASES, ids=IDS)
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_matrix_parity(mk, precision, stream):
+    case = mk()
+    print("case", case.name, precision, flush=True)
+    g = _gpu(case, stream, precision)
+    o = OracleSim(case.mesh, case.prob)
+    for s in (g, o):
+        case.init(s)
+        case.drive(s, case.prob.t0 + case.prob.dt)
+    br, bc, vals, rhs = g.export()
+    o.assemble()
+    Ag = oracle_matrix_from_blocks(br, bc, vals, case.mesh.nv)
+    Ao = o.matrix()
+    err = rowwise_rel_err(Ag, Ao)
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    assert err < tol, err
+    if precision == "fp64":
+        nv = case.mesh.nv
+        rg = np.concatenate([rhs[:, :3].reshape(-1), rhs[:, 3]])
+        assert rel_l2(rg, o.rhs) < 1e-12
+    g.close()
+
+
+@pytest.mark.parametrize("mk", CASES, ids=IDS)
+def test_matrix_free_residual(mk, stream):
+    """The FP64 element-wise residual equals b - A x of the oracle's assembled system."""
+    case = mk()
+    print("case", case.name, flush=True)
+    g = _gpu(case, stream, "fp32_ir")
+    o = OracleSim(case.mesh, case.prob)
+    for s in (g, o):
+        case.init(s)
+        case.drive(s, case.prob.t0 + case.prob.dt)
+    rng = np.random.default_rng(3)
+    nv = case.mesh.nv
+    u = rng.normal(size=(nv, 3))
+    p = rng.normal(size=nv) * 10
+    r = g.residual(u, p)
+    o.assemble()
+    x = np.concatenate([u.reshape(-1), p])
+    ro = o.rhs - o.matrix() @ x
+    rg = np.concatenate([r[:, :3].reshape(-1), r[:, 3]])
+    scale = np.abs(o.rhs).max() + np.abs(o.matrix()).max() * np.abs(x).max()
+    assert np.abs(rg - ro).max() < 1e-12 * scale
+    g.close()
+
+
+@pytest.mark.parametrize("mk,steps", [(CASES[0], 10), (CASES[1], 4), (CASES[2], 3)], ids=IDS[:3])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_steps_parity(mk, steps, precision, stream):
+    case = mk()
+    print("case", case.name, precision, flush=True)
+    g = _gpu(case, stream, precision, rtol=1e-14 if precision == "fp64" else 1e-13)
+    o = OracleSim(case.mesh, case.prob)
+    for s in (g, o):
+        case.init(s)
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    worst = (0.0, 0.0)
+    for k in range(steps):
+        t1 = o.t + case.prob.dt
+        for s in (g, o):
+            case.drive(s, t1)
+        st = g.step()
+        uo, po = o.step()
+        ug, pg, tg = g.solution()
+        assert abs(tg - o.t) < 1e-12
+        eu, ep = rel_l2(ug, uo), rel_l2(pg, po)
+        worst = (max(worst[0], eu), max(worst[1], ep))
+        print("step", k, "iters", st["gmres_iters"], "ir", st["ir_iters"], "res %.2e" % st["rel_residual"],
+              "err u %.2e p %.2e" % (eu, ep), flush=True)
+    assert worst[0] < tol and worst[1] < tol, worst
+    g.close()
