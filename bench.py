@@ -36,8 +36,8 @@ def parse():
     ap.add_argument("--nxy", type=int, default=32)
     ap.add_argument("--nz", type=int, default=160)
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32_ir"])
-    ap.add_argument("--schur-degree", type=int, default=8)
-    ap.add_argument("--schur-ratio", type=float, default=100.0)
+    ap.add_argument("--schur-degree", type=int, default=16)
+    ap.add_argument("--schur-ratio", type=float, default=300.0)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     ap.add_argument("--asm-fp64", type=int, default=0)

@@ -87,8 +87,8 @@ class SolverCfg:
     inner_rtol: float = 1e-4
     deterministic: bool = True
     collect_timing: bool = False
-    schur_degree: int = 8
-    schur_ratio: float = 100.0
+    schur_degree: int = 16
+    schur_ratio: float = 300.0
     asm_fp64: bool = False
 
 

@@ -154,7 +154,7 @@ class OracleSim:
     """The oracle's time stepper for the P1-P1 system."""
 
     def __init__(self, mesh, prob, solve="auto", gmres_rtol=1e-13, restart=30, max_iters=100000,
-                 schur_degree=8, schur_ratio=100.0):
+                 schur_degree=16, schur_ratio=300.0):
         assert prob.fe == "p1p1", "P2-P1 oracle lives in OracleSimP2"
         self.mesh, self.prob = mesh, prob
         self.nv = mesh.nv

@@ -68,7 +68,7 @@ void launch_schur_bound(const RowPattern &P, const T *val, const T *Dinv, const 
 
 // The SIMPLE preconditioner's operands.  degree = 0: S~^{-1} ~ diag(S~)^{-1};
 // degree k > 0: k-step Chebyshev iteration on S~ z = t with diagonal scaling on
-// [lam_max / ratio, lam_max] (work: 6 nv entries of T).
+// [lam_max / ratio, lam_max] (work: 9 nv entries of T).
 template <typename T>
 struct Simple {
     const T *val, *Finv, *Dinv, *Sinv;

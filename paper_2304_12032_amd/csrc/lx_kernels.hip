@@ -17,6 +17,8 @@
 // product times a quadrature sum.  That keeps the element in registers with
 // one thread per element; the 16 blocks are added into the block-CSR planes
 // with hardware floating-point atomics.
+#include <cstdlib>
+
 #include "lx_device.h"
 #include "lx_kernels.h"
 
@@ -742,10 +744,10 @@ __device__ inline void cheb_coef(double lmax, double ratio, int i, double &theta
 }
 
 // t = z.p - sum_j B_ij z.u_j (z.p holds scale*r.p on entry); degree 0: z.p = S~^{-1}_diag t;
-// degree > 0: Chebyshev step 0 (rc = t, d0 = Sinv t / theta, z.p = d0).
+// degree > 0: Chebyshev step 0 (rc = t, cur.w = d0 = Sinv t / theta, z.p = d0).
 template <typename T, int LPR>
 __global__ __launch_bounds__(256) void k_simple_zp(RowPattern P, const T *val, const T *Sinv, T *z, int degree,
-                                                   double ratio, T *rc, T *d0, const GmState *st,
+                                                   double ratio, T *rc, T *cur, const GmState *st,
                                                    const int32_t *done)
 {
     if (done && *done) return;
@@ -754,11 +756,12 @@ __global__ __launch_bounds__(256) void k_simple_zp(RowPattern P, const T *val, c
     if (row >= P.nv) return;
     const int64_t nb = P.nblk;
     const int32_t beg = P.rowptr[row], end = P.rowptr[row + 1];
+    using V = typename V4<T>::type;
     double acc = 0;
     for (int32_t k = beg + lane; k < end; k += LPR) {
-        const int64_t j = P.col[k];
-        const T *zj = z + 4 * j;
-        acc += (double)val[12 * nb + k] * zj[0] + (double)val[13 * nb + k] * zj[1] + (double)val[14 * nb + k] * zj[2];
+        const V zj = reinterpret_cast<const V *>(z)[P.col[k]];
+        acc += (double)val[12 * nb + k] * zj.v[0] + (double)val[13 * nb + k] * zj.v[1] +
+               (double)val[14 * nb + k] * zj.v[2];
     }
     acc = group_sum<double, LPR>(acc);
     if (lane == 0) {
@@ -770,15 +773,15 @@ __global__ __launch_bounds__(256) void k_simple_zp(RowPattern P, const T *val, c
             cheb_coef(st->lam_max, ratio, 0, theta, a, b);
             const T d = (T)((double)(Sinv[row] * t) / theta);
             rc[row] = t;
-            d0[row] = d;
+            cur[4 * row + 3] = d;
             z[4 * row + 3] = d;
         }
     }
 }
 
-// Chebyshev pass A: y = D^{-1} (G d)   (velocity side of S~ d)
+// Chebyshev pass A: cur.xyz = D^{-1} (G d), d = cur.w   (velocity side of S~ d)
 template <typename T, int LPR>
-__global__ __launch_bounds__(256) void k_cheb_gd(RowPattern P, const T *val, const T *Dinv, const T *d, T *y,
+__global__ __launch_bounds__(256) void k_cheb_gd(RowPattern P, const T *val, const T *Dinv, T *cur,
                                                  const int32_t *done)
 {
     if (done && *done) return;
@@ -788,7 +791,7 @@ __global__ __launch_bounds__(256) void k_cheb_gd(RowPattern P, const T *val, con
     const int64_t nb = P.nblk, nv = P.nv;
     double a0 = 0, a1 = 0, a2 = 0;
     for (int32_t k = P.rowptr[row] + lane; k < P.rowptr[row + 1]; k += LPR) {
-        const double dj = d[P.col[k]];
+        const double dj = cur[4 * (int64_t)P.col[k] + 3];
         a0 += (double)val[9 * nb + k] * dj;
         a1 += (double)val[10 * nb + k] * dj;
         a2 += (double)val[11 * nb + k] * dj;
@@ -797,29 +800,31 @@ __global__ __launch_bounds__(256) void k_cheb_gd(RowPattern P, const T *val, con
     a1 = group_sum<double, LPR>(a1);
     a2 = group_sum<double, LPR>(a2);
     if (lane == 0) {
-        y[row] = (T)((double)Dinv[row] * a0);
-        y[nv + row] = (T)((double)Dinv[nv + row] * a1);
-        y[2 * nv + row] = (T)((double)Dinv[2 * nv + row] * a2);
+        cur[4 * row + 0] = (T)((double)Dinv[row] * a0);
+        cur[4 * row + 1] = (T)((double)Dinv[nv + row] * a1);
+        cur[4 * row + 2] = (T)((double)Dinv[2 * nv + row] * a2);
     }
 }
 
-// Chebyshev pass B (step i >= 1): q = C d - B y = S~ d; rc -= q;
-// dn = a d + b Sinv rc; z.p += dn
+// Chebyshev pass B (step i >= 1): q = C d - B y = S~ d with (y, d) = cur (one
+// 4-vector gather per block); rc -= q; next.w = a d + b Sinv rc; z.p += next.w
 template <typename T, int LPR>
-__global__ __launch_bounds__(256) void k_cheb_step(RowPattern P, const T *val, const T *Sinv, const T *d,
-                                                   const T *y, T *rc, T *dn, T *z, int i, double ratio,
-                                                   const GmState *st, const int32_t *done)
+__global__ __launch_bounds__(256) void k_cheb_step(RowPattern P, const T *val, const T *Sinv, const T *cur,
+                                                   T *rc, T *next, T *z, int i, double ratio, const GmState *st,
+                                                   const int32_t *done)
 {
     if (done && *done) return;
     const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= P.nv) return;
-    const int64_t nb = P.nblk, nv = P.nv;
+    const int64_t nb = P.nblk;
+    using V = typename V4<T>::type;
     double q = 0;
     for (int32_t k = P.rowptr[row] + lane; k < P.rowptr[row + 1]; k += LPR) {
-        const int64_t j = P.col[k];
-        q += (double)val[15 * nb + k] * d[j] - ((double)val[12 * nb + k] * y[j] + (double)val[13 * nb + k] * y[nv + j] +
-                                                (double)val[14 * nb + k] * y[2 * nv + j]);
+        const V c = reinterpret_cast<const V *>(cur)[P.col[k]];
+        q += (double)val[15 * nb + k] * c.v[3] - ((double)val[12 * nb + k] * c.v[0] +
+                                                  (double)val[13 * nb + k] * c.v[1] +
+                                                  (double)val[14 * nb + k] * c.v[2]);
     }
     q = group_sum<double, LPR>(q);
     if (lane == 0) {
@@ -827,8 +832,8 @@ __global__ __launch_bounds__(256) void k_cheb_step(RowPattern P, const T *val, c
         cheb_coef(st->lam_max, ratio, i, theta, a, b);
         const double r = (double)rc[row] - q;
         rc[row] = (T)r;
-        const double dnew = a * (double)d[row] + b * (double)Sinv[row] * r;
-        dn[row] = (T)dnew;
+        const double dnew = a * (double)cur[4 * row + 3] + b * (double)Sinv[row] * r;
+        next[4 * row + 3] = (T)dnew;
         z[4 * row + 3] = (T)((double)z[4 * row + 3] + dnew);
     }
 }
@@ -861,24 +866,47 @@ __global__ __launch_bounds__(256) void k_simple_xu(RowPattern P, const T *val, c
     }
 }
 
-template <typename T>
-void launch_simple_apply(const RowPattern &P, const Simple<T> &S, const T *r, const double *scale_ptr, T *z,
-                         const int32_t *done, hipStream_t s)
+// Lanes per block row of the sparse row passes (4, 8 or 16; LXNS_LPR overrides).
+static int lanes_per_row()
+{
+    static int v = 0;
+    if (v == 0) {
+        const char *e = getenv("LXNS_LPR");
+        int x = e ? atoi(e) : 8;
+        v = (x == 4 || x == 8 || x == 16) ? x : 8;
+    }
+    return v;
+}
+
+template <typename T, int LPR>
+static void simple_apply_lpr(const RowPattern &P, const Simple<T> &S, const T *r, const double *scale_ptr, T *z,
+                             const int32_t *done, hipStream_t s)
 {
     const int64_t nv = P.nv;
     hipLaunchKernelGGL((k_simple_zu<T>), dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, nv, S.Finv, r,
                        scale_ptr, z, done);
-    const unsigned g = (unsigned)((nv * kLPR + 255) / 256);
-    T *rc = S.work, *da = S.work + nv, *db = S.work + 2 * nv, *y = S.work + 3 * nv;
-    hipLaunchKernelGGL((k_simple_zp<T, kLPR>), dim3(g), dim3(256), 0, s, P, S.val, S.Sinv, z, S.degree, S.ratio, rc,
-                       da, S.st, done);
+    const unsigned g = (unsigned)((nv * LPR + 255) / 256);
+    T *rc = S.work, *ca = S.work + nv, *cb = S.work + 5 * nv;   // rc [nv]; two [nv][4] (y, d) buffers
+    hipLaunchKernelGGL((k_simple_zp<T, LPR>), dim3(g), dim3(256), 0, s, P, S.val, S.Sinv, z, S.degree, S.ratio, rc,
+                       ca, S.st, done);
     for (int i = 1; i < S.degree; ++i) {
-        hipLaunchKernelGGL((k_cheb_gd<T, kLPR>), dim3(g), dim3(256), 0, s, P, S.val, S.Dinv, da, y, done);
-        hipLaunchKernelGGL((k_cheb_step<T, kLPR>), dim3(g), dim3(256), 0, s, P, S.val, S.Sinv, da, y, rc, db, z, i,
+        hipLaunchKernelGGL((k_cheb_gd<T, LPR>), dim3(g), dim3(256), 0, s, P, S.val, S.Dinv, ca, done);
+        hipLaunchKernelGGL((k_cheb_step<T, LPR>), dim3(g), dim3(256), 0, s, P, S.val, S.Sinv, ca, rc, cb, z, i,
                            S.ratio, S.st, done);
-        std::swap(da, db);
+        std::swap(ca, cb);
     }
-    hipLaunchKernelGGL((k_simple_xu<T, kLPR>), dim3(g), dim3(256), 0, s, P, S.val, S.Dinv, z, done);
+    hipLaunchKernelGGL((k_simple_xu<T, LPR>), dim3(g), dim3(256), 0, s, P, S.val, S.Dinv, z, done);
+}
+
+template <typename T>
+void launch_simple_apply(const RowPattern &P, const Simple<T> &S, const T *r, const double *scale_ptr, T *z,
+                         const int32_t *done, hipStream_t s)
+{
+    switch (lanes_per_row()) {
+    case 4: simple_apply_lpr<T, 4>(P, S, r, scale_ptr, z, done, s); break;
+    case 16: simple_apply_lpr<T, 16>(P, S, r, scale_ptr, z, done, s); break;
+    default: simple_apply_lpr<T, 8>(P, S, r, scale_ptr, z, done, s); break;
+    }
 }
 template void launch_simple_apply<double>(const RowPattern &, const Simple<double> &, const double *,
                                           const double *, double *, const int32_t *, hipStream_t);
@@ -928,11 +956,29 @@ __global__ __launch_bounds__(256) void k_spmv(RowPattern P, const T *__restrict_
     }
 }
 
+// Lanes per block row of the SpMV (4, 8 or 16; LXNS_LPR_SPMV overrides).
+static int lanes_per_row_spmv()
+{
+    static int v = 0;
+    if (v == 0) {
+        const char *e = getenv("LXNS_LPR_SPMV");
+        int x = e ? atoi(e) : 16;
+        v = (x == 4 || x == 8 || x == 16) ? x : 16;
+    }
+    return v;
+}
+
 template <typename T>
 void launch_spmv(const RowPattern &P, const T *val, const T *x, T *y, const int32_t *done, hipStream_t s)
 {
-    const unsigned g = (unsigned)((P.nv * kLPR + 255) / 256);
-    hipLaunchKernelGGL((k_spmv<T, kLPR>), dim3(g), dim3(256), 0, s, P, val, x, y, done);
+    const int lpr = lanes_per_row_spmv();
+    const unsigned g = (unsigned)((P.nv * lpr + 255) / 256);
+    if (lpr == 4)
+        hipLaunchKernelGGL((k_spmv<T, 4>), dim3(g), dim3(256), 0, s, P, val, x, y, done);
+    else if (lpr == 8)
+        hipLaunchKernelGGL((k_spmv<T, 8>), dim3(g), dim3(256), 0, s, P, val, x, y, done);
+    else
+        hipLaunchKernelGGL((k_spmv<T, 16>), dim3(g), dim3(256), 0, s, P, val, x, y, done);
 }
 template void launch_spmv<double>(const RowPattern &, const double *, const double *, double *, const int32_t *,
                                   hipStream_t);

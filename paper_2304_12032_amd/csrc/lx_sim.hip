@@ -221,7 +221,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         ALLOC(d_Sinv64, sizeof(double) * nv);
         ALLOC(d_V64, sizeof(double) * N * (m + 1));
         ALLOC(d_Z64, sizeof(double) * N * m);
-        ALLOC(d_sw64, sizeof(double) * 6 * nv);
+        ALLOC(d_sw64, sizeof(double) * 9 * nv);
         ALLOC(d_w64, sizeof(double) * N);
     } else {
         ALLOC(d_val32, sizeof(float) * kPlanes * nblk);
@@ -231,7 +231,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         ALLOC(d_V32, sizeof(float) * N * (m + 1));
         if (solver.asm_fp64) ALLOC(d_val64, sizeof(double) * kPlanes * nblk);
         ALLOC(d_Z32, sizeof(float) * N * m);
-        ALLOC(d_sw32, sizeof(float) * 6 * nv);
+        ALLOC(d_sw32, sizeof(float) * 9 * nv);
         ALLOC(d_w32, sizeof(float) * N);
         ALLOC(d_x32, sizeof(float) * N);
         ALLOC(d_r32, sizeof(float) * N);

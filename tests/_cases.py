@@ -95,3 +95,50 @@ def rowwise_rel_err(A, Bm):
 def rel_l2(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def tube_ale(nxy=4, nz=8, length=2.0, bdf=2, seed=5):
+    """Tube whose whole boundary contracts radially (d^ = law(t) * (-0.1 x^, -0.1 y^, 0),
+    pulsatile law), no-slip wall u = u_ALE, parabolic inflow, zero-traction outlet and an
+    annular RIIS valve whose orifice opens during the run."""
+    mesh = tube(nxy=nxy, nz=nz, radius=1.0, length=length, seed=seed)
+    prob = tube_problem(mesh, dt=2e-3, bdf_order=bdf, peak=30.0, R=200.0, eps=0.3, t0=0.0)
+    prob.valves = [Valve(center=(0.0, 0.0, length / 2), normal=(0.0, 0.0, 1.0), outer_radius=10.0,
+                         orifice=TimeLaw("ramp2", (0.0, 0.6, 0.0, 0.004, 1.0, 0.1, 0.0)), R=200.0, eps=0.3)]
+    prob.ale = True
+    prob.ale_tags = (TUBE_TAGS["wall"], TUBE_TAGS["inlet"], TUBE_TAGS["outlet"])
+    prob.ale_law = TimeLaw("pulsatile", (0.0, 1.0, 0.02))
+    shape = np.zeros_like(mesh.coords)
+    shape[:, 0] = -0.1 * mesh.coords[:, 0]
+    shape[:, 1] = -0.1 * mesh.coords[:, 1]
+
+    def init(s):
+        s.set_ale_displacement(shape)
+
+    def drive(s, t1):
+        pass
+
+    return Case(mesh, prob, init, drive, "tube_ale%dx%d" % (nxy, nz))
+
+
+def tube_ale_curved(nxy=4, nz=6, length=1.5, seed=2):
+    """ALE with a non-linear boundary displacement (sinusoidal bulge), so that the
+    harmonic extension is not trivially exact."""
+    mesh = tube(nxy=nxy, nz=nz, radius=1.0, length=length, seed=seed)
+    prob = tube_problem(mesh, dt=2e-3, bdf_order=2, peak=20.0, valve=False)
+    prob.ale = True
+    prob.ale_tags = (TUBE_TAGS["wall"],)
+    prob.ale_law = TimeLaw("ramp", (0.0, 1.0, 0.0, 0.01))
+    X = mesh.coords
+    shape = np.zeros_like(X)
+    bump = 0.05 * np.sin(np.pi * X[:, 2] / length)
+    shape[:, 0] = bump * X[:, 0]
+    shape[:, 1] = bump * X[:, 1]
+
+    def init(s):
+        s.set_ale_displacement(shape)
+
+    def drive(s, t1):
+        pass
+
+    return Case(mesh, prob, init, drive, "tube_ale_curved")
