@@ -83,7 +83,7 @@ void launch_simple_apply(const RowPattern &P, const Simple<T> &S, const T *r, co
                          const int32_t *done, hipStream_t s);
 template <typename T>
 void launch_spmv(const RowPattern &P, const T *val, const T *x, T *y, const int32_t *done,
-                 hipStream_t s);
+                 hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // GMRES building blocks (vectors of length n = 4 nv, basis stride ldv).
 template <typename T>

@@ -17,6 +17,8 @@
 // product times a quadrature sum.  That keeps the element in registers with
 // one thread per element; the 16 blocks are added into the block-CSR planes
 // with hardware floating-point atomics.
+#include <hip/hip_ext.h>
+
 #include <cstdlib>
 
 #include "lx_device.h"
@@ -968,22 +970,24 @@ static int lanes_per_row_spmv()
     return v;
 }
 
+// ev0/ev1 (optional): events stamped by the dispatch itself around the kernel
 template <typename T>
-void launch_spmv(const RowPattern &P, const T *val, const T *x, T *y, const int32_t *done, hipStream_t s)
+void launch_spmv(const RowPattern &P, const T *val, const T *x, T *y, const int32_t *done, hipStream_t s,
+                 hipEvent_t ev0, hipEvent_t ev1)
 {
     const int lpr = lanes_per_row_spmv();
     const unsigned g = (unsigned)((P.nv * lpr + 255) / 256);
     if (lpr == 4)
-        hipLaunchKernelGGL((k_spmv<T, 4>), dim3(g), dim3(256), 0, s, P, val, x, y, done);
+        hipExtLaunchKernelGGL((k_spmv<T, 4>), dim3(g), dim3(256), 0, s, ev0, ev1, 0, P, val, x, y, done);
     else if (lpr == 8)
-        hipLaunchKernelGGL((k_spmv<T, 8>), dim3(g), dim3(256), 0, s, P, val, x, y, done);
+        hipExtLaunchKernelGGL((k_spmv<T, 8>), dim3(g), dim3(256), 0, s, ev0, ev1, 0, P, val, x, y, done);
     else
-        hipLaunchKernelGGL((k_spmv<T, 16>), dim3(g), dim3(256), 0, s, P, val, x, y, done);
+        hipExtLaunchKernelGGL((k_spmv<T, 16>), dim3(g), dim3(256), 0, s, ev0, ev1, 0, P, val, x, y, done);
 }
 template void launch_spmv<double>(const RowPattern &, const double *, const double *, double *, const int32_t *,
-                                  hipStream_t);
+                                  hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_spmv<float>(const RowPattern &, const float *, const float *, float *, const int32_t *,
-                                 hipStream_t);
+                                 hipStream_t, hipEvent_t, hipEvent_t);
 
 // ------------------------------------------------------------------ reductions
 

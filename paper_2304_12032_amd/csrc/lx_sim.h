@@ -100,7 +100,7 @@ struct Sim {
     RowPattern pattern() const;
     const double *hist(int l) const { return (l < prob.bdf_order && d_hist[l]) ? d_hist[l] : d_hist[0]; }
 
-    std::pair<hipEvent_t, hipEvent_t> *timer_begin(int kind, int iter);
+    std::pair<hipEvent_t, hipEvent_t> *timer_begin(int kind, int iter, bool record = true);
     void timer_end(std::pair<hipEvent_t, hipEvent_t> *p);
     void timer_flush(int kused, lx_step_stats &acc);
     lx_status read_state();

@@ -294,7 +294,10 @@ RowPattern Sim::pattern() const
 
 // ------------------------------------------------------------------ timing
 
-std::pair<hipEvent_t, hipEvent_t> *Sim::timer_begin(int kind, int iter)
+// A pair of events for one timed launch.  record = true: bracket the launch with
+// hipEventRecord (timer_end closes it); record = false: the caller hands the pair
+// to hipExtLaunchKernelGGL, which stamps the kernel's own start and end.
+std::pair<hipEvent_t, hipEvent_t> *Sim::timer_begin(int kind, int iter, bool record)
 {
     if (!solver.collect_timing) return nullptr;
     if (ev_used >= ev_pool.size()) {
@@ -307,7 +310,7 @@ std::pair<hipEvent_t, hipEvent_t> *Sim::timer_begin(int kind, int iter)
     auto *p = &ev_pool[ev_used];
     ev_tag[ev_used] = {kind, iter};
     ++ev_used;
-    (void)hipEventRecord(p->first, stream);
+    if (record) (void)hipEventRecord(p->first, stream);
     return p;
 }
 
@@ -412,18 +415,16 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
         if (x_zero && cycle == 0) {
             launch_gm_start<T>(N, b, nullptr, V, d_st, d_partial, nb_red, stream);
         } else {
-            auto *tm = timer_begin(0, -1);
-            launch_spmv<T>(P, val, x, w, nullptr, stream);
-            timer_end(tm);
+            auto *tm = timer_begin(0, -1, false);
+            launch_spmv<T>(P, val, x, w, nullptr, stream, tm ? tm->first : nullptr, tm ? tm->second : nullptr);
             launch_gm_start<T>(N, b, w, V, d_st, d_partial, nb_red, stream);
         }
         const int kmax = std::min(m, max_iters - it);
         for (int k = 0; k < kmax; ++k) {
             T *zk = Z + k * ld;
             launch_simple_apply<T>(P, SP, V + k * ld, &d_st->s[k], zk, &d_st->done, stream);
-            auto *tm = timer_begin(0, k);
-            launch_spmv<T>(P, val, zk, w, &d_st->done, stream);
-            timer_end(tm);
+            auto *tm = timer_begin(0, k, false);
+            launch_spmv<T>(P, val, zk, w, &d_st->done, stream, tm ? tm->first : nullptr, tm ? tm->second : nullptr);
             launch_gm_dot1<T>(N, k, V, ld, w, d_st, d_partial, nb_red, stream);
             launch_gm_axpy_dot2<T>(N, k, V, ld, w, d_st, d_partial, nb_red, stream);
             launch_gm_axpy_norm<T>(N, k, V, ld, w, d_st, d_partial, nb_red, stream);
