@@ -62,3 +62,38 @@ def p1_errors(coords, tets, u_h, p_h, exact, t, nq=4):
         ep += np.sum(wq * (pq - pe) ** 2)
         npp += np.sum(wq * pe ** 2)
     return np.sqrt(eu / nu), np.sqrt(eg / ng), np.sqrt(ep / npp)
+
+
+def p2_errors(coords, tets, edge_of_tet, u_h, p_h, exact, t, nq=4):
+    """Relative errors (e_L2^u, e_H1^u, e_L2^p) of a P2 velocity (nodal values at the
+    vertices, then at the edges indexed by edge_of_tet [nt][6]) and a P1 pressure."""
+    lam, w = tet_rule(nq)
+    nv = coords.shape[0]
+    X = coords[tets]
+    J = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=2)
+    Jinv = np.linalg.inv(J)
+    det = np.abs(np.linalg.det(J))
+    dl = np.concatenate([-Jinv.sum(axis=1, keepdims=True), Jinv], axis=1)      # [nt][4][3]
+    nodes = np.concatenate([tets, nv + edge_of_tet], axis=1)
+    U = u_h[nodes]                                                             # [nt][10][3]
+    P = p_h[tets]
+    E = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+    eu = nu = eg = ng = ep = npp = 0.0
+    for q in range(len(w)):
+        L = lam[q]
+        phi = np.array([L[a] * (2 * L[a] - 1) for a in range(4)] + [4 * L[i] * L[j] for i, j in E])
+        dphi = np.concatenate([(4 * L[:4, None] - 1)[None, :, :] * dl,
+                               np.stack([4 * (L[i] * dl[:, j] + L[j] * dl[:, i]) for i, j in E], axis=1)], axis=1)
+        xq = np.einsum("a,eac->ec", L, X)
+        uq = np.einsum("a,eac->ec", phi, U)
+        gq = np.einsum("eac,eaj->ecj", U, dphi)
+        pq = P @ L
+        ue, ge, pe = exact.velocity(xq, t), exact.grad(xq, t), exact.pressure(xq, t)
+        wq = w[q] * det
+        eu += np.sum(wq * np.sum((uq - ue) ** 2, axis=1))
+        nu += np.sum(wq * np.sum(ue ** 2, axis=1))
+        eg += np.sum(wq * np.sum((gq - ge) ** 2, axis=(1, 2)))
+        ng += np.sum(wq * np.sum(ge ** 2, axis=(1, 2)))
+        ep += np.sum(wq * (pq - pe) ** 2)
+        npp += np.sum(wq * pe ** 2)
+    return np.sqrt(eu / nu), np.sqrt(eg / ng), np.sqrt(ep / npp)

@@ -719,3 +719,194 @@ int64_t orc_gmres_simple(int64_t nv, const int64_t *rowptr, const int32_t *col, 
     free(V); free(w); free(z); free(H); free(cs); free(sn); free(gv); free(y); free(h1);
     return (rel <= rtol) ? it : -1;
 }
+
+/* ------------------------------------------------------------ P2-P1 element */
+
+/* Local P2 nodes: vertices 0..3, then the midpoints of the edges
+ * (0,1), (0,2), (0,3), (1,2), (1,3), (2,3) as nodes 4..9. */
+static const int P2_EDGE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+
+/* P2 basis values, gradients and (constant) Laplacians from the barycentric
+ * coordinates lam and their gradients dl: phi_a = lam_a (2 lam_a - 1) at the
+ * vertices, phi_ij = 4 lam_i lam_j at the edge midpoints. */
+static void p2_basis(const double lam[4], const double dl[4][3], double phi[10], double dphi[10][3],
+                     double lap[10])
+{
+    for (int a = 0; a < 4; ++a) {
+        phi[a] = lam[a] * (2.0 * lam[a] - 1.0);
+        for (int j = 0; j < 3; ++j) dphi[a][j] = (4.0 * lam[a] - 1.0) * dl[a][j];
+        lap[a] = 4.0 * (dl[a][0] * dl[a][0] + dl[a][1] * dl[a][1] + dl[a][2] * dl[a][2]);
+    }
+    for (int e = 0; e < 6; ++e) {
+        int i = P2_EDGE[e][0], k = P2_EDGE[e][1];
+        phi[4 + e] = 4.0 * lam[i] * lam[k];
+        for (int j = 0; j < 3; ++j) dphi[4 + e][j] = 4.0 * (lam[i] * dl[k][j] + lam[k] * dl[i][j]);
+        lap[4 + e] = 8.0 * (dl[i][0] * dl[k][0] + dl[i][1] * dl[k][1] + dl[i][2] * dl[k][2]);
+    }
+}
+
+/*
+ * Element matrix Ke (34x34) and vector Fe (34) of the P2-P1 element.  Local
+ * velocity index 3a+c (a = 0..9 P2 nodes), pressure 30+a (a = 0..3 vertices).
+ * Nodal data: X, Xh (vertex coordinates, current and reference), uE, uB, uA, f
+ * at the 10 P2 nodes, pE at the 4 vertices.  Quadrature: nq points with
+ * barycentric coordinates qlam[nq][4] and weights qw summing to 1/6 (unit
+ * simplex).  The same weak form as orc_element_p1, with -mu Lap terms in the
+ * strong residuals (nonzero for P2).
+ */
+double orc_element_p2(const double X[4][3], const double Xh[4][3], const double uE[10][3],
+                      const double uB[10][3], const double uA[10][3], const double pE[4],
+                      const double f[10][3], const orc_params *P, int32_t nq, const double *qlam,
+                      const double *qw, double Ke[34][34], double Fe[34])
+{
+    double Jinv[3][3];
+    double det = jacobian(X, Jinv);
+    double dl[4][3];
+    for (int j = 0; j < 3; ++j) {
+        dl[1][j] = Jinv[0][j];
+        dl[2][j] = Jinv[1][j];
+        dl[3][j] = Jinv[2][j];
+        dl[0][j] = -(Jinv[0][j] + Jinv[1][j] + Jinv[2][j]);
+    }
+    double G[3][3], g[3];
+    for (int i = 0; i < 3; ++i) {
+        g[i] = Jinv[0][i] + Jinv[1][i] + Jinv[2][i];
+        for (int j = 0; j < 3; ++j)
+            G[i][j] = Jinv[0][i] * Jinv[0][j] + Jinv[1][i] * Jinv[1][j] + Jinv[2][i] * Jinv[2][j];
+    }
+    memset(Ke, 0, sizeof(double) * 34 * 34);
+    memset(Fe, 0, sizeof(double) * 34);
+    const double rho = P->rho, mu = P->mu, dt = P->dt, alpha = P->alpha;
+    for (int q = 0; q < nq; ++q) {
+        const double *lam = qlam + 4 * q;
+        double w = qw[q] * fabs(det);
+        double phi[10], dphi[10][3], lap[10];
+        p2_basis(lam, dl, phi, dphi, lap);
+
+        double uEq[3] = {0}, uBq[3] = {0}, uAq[3] = {0}, fq[3] = {0}, xh[3] = {0}, lapUE[3] = {0};
+        double gradUE[3][3] = {{0}}, gradPE[3] = {0};
+        for (int a = 0; a < 10; ++a)
+            for (int c = 0; c < 3; ++c) {
+                uEq[c] += phi[a] * uE[a][c];
+                uBq[c] += phi[a] * uB[a][c];
+                uAq[c] += phi[a] * uA[a][c];
+                fq[c] += phi[a] * f[a][c];
+                lapUE[c] += lap[a] * uE[a][c];
+                for (int j = 0; j < 3; ++j) gradUE[c][j] += uE[a][c] * dphi[a][j];
+            }
+        for (int a = 0; a < 4; ++a)
+            for (int c = 0; c < 3; ++c) {
+                xh[c] += lam[a] * Xh[a][c];
+                gradPE[c] += pE[a] * dl[a][c];
+            }
+        double sigR = 0.0, riis2 = 0.0;
+        for (int k = 0; k < P->n_riis; ++k) {
+            const double *v = P->riis + 10 * k;
+            double R = v[8], eps = v[9];
+            double dlt = orc_delta(orc_valve_distance(xh, v), eps);
+            sigR += R / eps * dlt;
+            riis2 += (R * R) / (eps * eps) * dlt * dlt;
+        }
+        double us[3];
+        for (int c = 0; c < 3; ++c) us[c] = uEq[c] - uAq[c];
+        double tauM = 0.0, tauC = 0.0;
+        if (P->stab != ORC_STAB_NONE) orc_tau(P, G, g, us, riis2, &tauM, &tauC);
+        double Kv[3];
+        for (int c = 0; c < 3; ++c) Kv[c] = fq[c] + rho * uBq[c] / dt + sigR * uAq[c];
+        double at[3];
+        for (int c = 0; c < 3; ++c) {
+            double adv = 0.0;
+            for (int j = 0; j < 3; ++j) adv += us[j] * gradUE[c][j];
+            double rt = rho * (alpha * uEq[c] / dt + adv) + gradPE[c] - mu * lapUE[c] + sigR * uEq[c] - Kv[c];
+            at[c] = tauM * rt;
+        }
+        double adv_phi[10], T[10][3][3], s[10];
+        for (int a = 0; a < 10; ++a)
+            adv_phi[a] = us[0] * dphi[a][0] + us[1] * dphi[a][1] + us[2] * dphi[a][2];
+        for (int a = 0; a < 10; ++a)
+            for (int c = 0; c < 3; ++c)
+                for (int j = 0; j < 3; ++j) {
+                    double t = (c == j) ? adv_phi[a] : 0.0;
+                    if (P->stab == ORC_STAB_VMS_LES) t += us[c] * dphi[a][j];
+                    if (P->stab == ORC_STAB_VMS_LES) t -= at[c] * dphi[a][j];
+                    T[a][c][j] = rho * t;
+                }
+        for (int b = 0; b < 10; ++b)
+            s[b] = rho * (alpha / dt * phi[b] + adv_phi[b]) - mu * lap[b] + sigR * phi[b];
+
+        for (int a = 0; a < 10; ++a) {
+            for (int c = 0; c < 3; ++c) {
+                int ia = 3 * a + c;
+                for (int b = 0; b < 10; ++b) {
+                    double gg_ab = dphi[a][0] * dphi[b][0] + dphi[a][1] * dphi[b][1] + dphi[a][2] * dphi[b][2];
+                    for (int d = 0; d < 3; ++d) {
+                        double v = 0.0;
+                        if (c == d) {
+                            v += (rho * alpha / dt + sigR) * phi[a] * phi[b];
+                            v += rho * phi[a] * adv_phi[b];
+                            v += mu * gg_ab;
+                        }
+                        if (P->symgrad) v += mu * dphi[b][c] * dphi[a][d];
+                        v += tauM * s[b] * T[a][c][d];
+                        v += tauC * dphi[a][c] * dphi[b][d];
+                        Ke[ia][3 * b + d] += w * v;
+                    }
+                }
+                for (int b = 0; b < 4; ++b) {
+                    double v = -lam[b] * dphi[a][c];
+                    v += tauM * (dl[b][0] * T[a][c][0] + dl[b][1] * T[a][c][1] + dl[b][2] * T[a][c][2]);
+                    Ke[ia][30 + b] += w * v;
+                }
+                double r = Kv[c] * phi[a];
+                r += tauM * (Kv[0] * T[a][c][0] + Kv[1] * T[a][c][1] + Kv[2] * T[a][c][2]);
+                Fe[ia] += w * r;
+            }
+        }
+        for (int a = 0; a < 4; ++a) {
+            for (int b = 0; b < 10; ++b)
+                for (int d = 0; d < 3; ++d)
+                    Ke[30 + a][3 * b + d] += w * (lam[a] * dphi[b][d] + tauM * s[b] * dl[a][d]);
+            for (int b = 0; b < 4; ++b) {
+                double gg_ab = dl[a][0] * dl[b][0] + dl[a][1] * dl[b][1] + dl[a][2] * dl[b][2];
+                Ke[30 + a][30 + b] += w * tauM * gg_ab;
+            }
+            Fe[30 + a] += w * tauM * (Kv[0] * dl[a][0] + Kv[1] * dl[a][1] + Kv[2] * dl[a][2]);
+        }
+    }
+    return det;
+}
+
+/* All P2-P1 element matrices of a mesh: nodes[e][10] are the global P2 node
+ * ids (vertices then edges) of element e; fields are nodal arrays over the
+ * P2 nodes (uE, uB, uA, f: [nu][3]) and the vertices (pE: [nv]); x and xh are
+ * vertex coordinates.  Writes Ke_all[nt][34][34] and Fe_all[nt][34]. */
+int64_t orc_elements_p2(int64_t nt, const double *x, const double *xh, const int32_t *tets,
+                        const int32_t *nodes, const double *uE, const double *uB, const double *uA,
+                        const double *pE, const double *f, const orc_params *P, int32_t nq,
+                        const double *qlam, const double *qw, double *Ke_all, double *Fe_all)
+{
+    for (int64_t e = 0; e < nt; ++e) {
+        double X[4][3], Xh[4][3], ue[10][3], ub[10][3], ua[10][3], pe[4], fe[10][3];
+        for (int a = 0; a < 4; ++a) {
+            int32_t v = tets[4 * e + a];
+            for (int c = 0; c < 3; ++c) {
+                X[a][c] = x[3 * (int64_t)v + c];
+                Xh[a][c] = xh[3 * (int64_t)v + c];
+            }
+            pe[a] = pE[v];
+        }
+        for (int a = 0; a < 10; ++a) {
+            int64_t n = nodes[10 * e + a];
+            for (int c = 0; c < 3; ++c) {
+                ue[a][c] = uE[3 * n + c];
+                ub[a][c] = uB[3 * n + c];
+                ua[a][c] = uA ? uA[3 * n + c] : 0.0;
+                fe[a][c] = f ? f[3 * n + c] : 0.0;
+            }
+        }
+        double det = orc_element_p2(X, Xh, ue, ub, ua, pe, fe, P, nq, qlam, qw,
+                                    (double(*)[34])(Ke_all + (size_t)e * 34 * 34), Fe_all + (size_t)e * 34);
+        if (!(fabs(det) > 0.0)) return -(e + 1);
+    }
+    return 0;
+}

@@ -497,3 +497,97 @@ def test_harmonic_extension_linear_exact():
     ref = mesh.coords @ Lm.T + np.array([0.1, -0.2, 0.05])
     assert np.abs(d - ref).max() < 1e-12
     assert np.abs(uale - ref / 0.01).max() < 1e-9
+
+
+# ------------------------------------------------------------- P2-P1 oracle
+
+class _PlanarPoiseuille:
+    """u = (y(1-y), 0, 0), p = p0 - 2 mu x: a steady Navier-Stokes solution that is
+    quadratic in space, hence exactly representable by P2-P1."""
+
+    def __init__(self, mu=0.05, p0=0.3):
+        self.mu, self.p0, self.rho = mu, p0, 1.0
+
+    def velocity(self, X, t=0.0):
+        u = np.zeros_like(X)
+        u[:, 0] = X[:, 1] * (1 - X[:, 1])
+        return u
+
+    def pressure(self, X, t=0.0):
+        return self.p0 - 2 * self.mu * X[:, 0]
+
+    def grad(self, X, t=0.0):
+        G = np.zeros((len(X), 3, 3))
+        G[:, 0, 1] = 1 - 2 * X[:, 1]
+        return G
+
+    def traction(self, X, t, n):
+        n = np.asarray(n, float)
+        return self.mu * np.einsum("kij,j->ki", self.grad(X), n) - self.pressure(X)[:, None] * n[None, :]
+
+
+@pytest.mark.parametrize("stab", ["none", "supg_pspg", "vms_les"])
+def test_p2_poiseuille_patch_exact(stab):
+    """P2-P1 reproduces a quadratic steady solution exactly for every stabilisation
+    (the strong residual, including -mu Lap u, vanishes at every quadrature point)."""
+    from inputs.meshes import CUBE_TAGS as T
+    from oracle.oracle_p2 import OracleSimP2
+    ex = _PlanarPoiseuille()
+    mesh = cube_kuhn(3)
+    bcs = [Boundary("dirichlet", (T["x0"], T["y0"], T["y1"], T["z0"], T["z1"]), profile=Profile("nodal")),
+           Boundary("neumann", (T["x1"],), profile=Profile("nodal", normal=(1, 0, 0)))]
+    prob = Problem(fe="p2p1", bdf_order=1, dt=0.05, mu=ex.mu, stab=stab, bcs=bcs)
+    sim = OracleSimP2(mesh, prob)
+    X = sim.xnode
+    sim.set_state(0, ex.velocity(X), ex.pressure(mesh.coords))
+    for _ in range(2):
+        sim.set_dirichlet_values(0, ex.velocity(X))
+        sim.set_neumann_traction(1, ex.traction(X, 0.0, (1, 0, 0)))
+        u, p = sim.step()
+    assert np.abs(u - ex.velocity(X)).max() < 1e-12
+    assert np.abs(p - ex.pressure(mesh.coords)).max() < 1e-12
+
+
+def test_p2_interpolation_rates():
+    """The P2 error norms of the nodal interpolant converge at orders 3 (L2) and 2 (H1):
+    pins the P2 basis and the norm integration."""
+    from oracle.oracle_p2 import OracleSimP2
+    from oracle.errors import p2_errors
+    errs = []
+    for n in (2, 4):
+        mesh, prob = beltrami_cube_problem(n)
+        prob.fe = "p2p1"
+        sim = OracleSimP2(mesh, prob)
+        ex = exact.Beltrami(mu=prob.mu)
+        errs.append(np.array(p2_errors(mesh.coords, mesh.tets, sim.tedge, ex.velocity(sim.xnode, 0.0),
+                                       ex.pressure(mesh.coords, 0.0), ex, 0.0)))
+    r = np.log2(errs[0] / errs[1])
+    assert r[0] > 2.9 and r[1] > 1.9 and r[2] > 1.8
+
+
+@pytest.mark.slow
+def test_beltrami_space_rates_p2():
+    """P2-P1 VMS-LES Beltrami errors decrease at the expected orders
+    (golden/convergence_orders.json) between h = 1/4 and h = 1/8 (dt = 1e-3, so the
+    time error stays below the space error)."""
+    from oracle.oracle_p2 import OracleSimP2
+    from oracle.errors import p2_errors
+    orders = json.load(open(os.path.join(GOLDEN, "convergence_orders.json")))["p2p1"]
+    errs = []
+    for n in (4, 8):
+        mesh, prob = beltrami_cube_problem(n, dt=1e-3)
+        prob.fe = "p2p1"
+        ex = exact.Beltrami(mu=prob.mu)
+        sim = OracleSimP2(mesh, prob)
+        X = sim.xnode
+        sim.set_state(0, ex.velocity(X, 0.0), ex.pressure(mesh.coords, 0.0))
+        for _ in range(2):
+            t1 = sim.t + prob.dt
+            sim.set_dirichlet_values(0, ex.velocity(X, t1))
+            sim.set_neumann_traction(1, ex.traction(X, t1, (-1, 0, 0)))
+            u, p = sim.step()
+        errs.append(np.array(p2_errors(mesh.coords, mesh.tets, sim.tedge, u, p, ex, sim.t)))
+    r = np.log2(errs[0] / errs[1])
+    assert r[0] > orders["u_L2"] - 0.3
+    assert r[1] > orders["u_H1"] - 0.35
+    assert r[2] > orders["p_L2"] - 0.2
