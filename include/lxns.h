@@ -147,13 +147,25 @@ typedef struct {
 } lx_problem;
 
 enum { LX_FP64 = 0, LX_FP32_IR = 1 };
-/* Linear solver (Sec. 2.4): right-preconditioned restarted GMRES(restart) with
- * the SIMPLE block preconditioner (D = diag(F), F~ = nodal 3x3 diagonal blocks
- * of F, S~ = C - B D^{-1} G); stop when ||b - A x|| <= rtol ||b||.  The Schur
- * block S~^{-1} is applied as diag(S~)^{-1} (schur_degree = 0) or as a
- * Chebyshev iteration of degree schur_degree on S~ z = t with diagonal
- * scaling over [lam / schur_ratio, lam], lam the Gershgorin bound of
- * diag(S~)^{-1} S~.  LX_FP32_IR: FP32 matrix and FP32 inner GMRES inside an
+enum { LX_PC_AMG = 0, LX_PC_CHEB_SCHUR = 1 };
+/* Linear solver (Sec. 2.4): right-preconditioned (flexible) restarted
+ * GMRES(restart) with the SIMPLE block preconditioner (D = diag(F), F~ = nodal
+ * 3x3 diagonal blocks of F, S~ = C - B D^{-1} G); stop when
+ * ||b - A x|| <= rtol ||b||.  The paper approximates the velocity and Schur
+ * blocks of SIMPLE by AMG, additive Schwarz or block Jacobi; the two choices
+ * here are
+ *   LX_PC_AMG (default): S~ is formed explicitly and approximated by one
+ *     V-cycle of aggregation AMG with Chebyshev smoothing of degree
+ *     amg_degree over [lam / amg_ratio, lam] on every level (lam the
+ *     Gershgorin bound of diag(A_l)^{-1} A_l) and a dense coarsest solve; F is
+ *     approximated by a Chebyshev iteration of degree f_degree on F~^{-1} F
+ *     over [lam_F / f_ratio, lam_F] (lam_F from power iterations; f_degree 1
+ *     is plain block Jacobi F~^{-1});
+ *   LX_PC_CHEB_SCHUR: F by F~^{-1}; S~ (not formed) by diag(S~)^{-1}
+ *     (schur_degree = 0) or a Chebyshev iteration of degree schur_degree with
+ *     diagonal scaling over [lam / schur_ratio, lam].
+ * A zero in f_degree, amg_degree, f_ratio or amg_ratio selects its default
+ * (3, 2, 10, 30).  LX_FP32_IR: FP32 matrix and FP32 inner GMRES inside an
  * FP64 iterative refinement loop that stops when the FP64 residual satisfies
  * ir_rtol; inner solves aim at one more refinement step but never tighter
  * than inner_rtol. */
@@ -167,6 +179,12 @@ typedef struct {
                                 element arithmetic and scatter, rounded to FP32;
                                 0 = FP32 element arithmetic and FP32 scatter       */
     double schur_ratio;      /* > 1                                                  */
+    int32_t precond;         /* LX_PC_AMG | LX_PC_CHEB_SCHUR                         */
+    int32_t f_degree;        /* LX_PC_AMG: 0..8 (0: default 3)                       */
+    int32_t amg_degree;      /* LX_PC_AMG: 0..8 (0: default 2)                       */
+    int32_t pad;
+    double f_ratio;          /* LX_PC_AMG: 0 (default 10) or > 1                     */
+    double amg_ratio;        /* LX_PC_AMG: 0 (default 30) or > 1                     */
 } lx_solver;
 
 /* ---------------------------------------------------------------- outputs */

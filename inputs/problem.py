@@ -87,9 +87,14 @@ class SolverCfg:
     inner_rtol: float = 1e-4
     deterministic: bool = True
     collect_timing: bool = False
-    schur_degree: int = 16
+    schur_degree: int = 16           # precond = "cheb_schur" only
     schur_ratio: float = 300.0
     asm_fp64: bool = False
+    precond: str = "amg"             # amg | cheb_schur
+    f_degree: int = 3                # amg: Chebyshev degree on the velocity block (1 = block Jacobi)
+    f_ratio: float = 10.0
+    amg_degree: int = 2              # amg: Chebyshev smoothing degree per level
+    amg_ratio: float = 30.0
 
 
 # ----------------------------------------------------------------- configs

@@ -78,6 +78,23 @@ __device__ inline void reduce_partials(const double *partial, int nb, int count,
     block_sum<K>(out, lds);
 }
 
+// Chebyshev scalars of step i >= 1 for the interval [lmax/ratio, lmax] of the
+// scaled operator M^{-1} A (M a diagonal or block-diagonal scaling):
+// d_i = a d_{i-1} + b M^{-1} r_i; step 0 is d_0 = M^{-1} r_0 / theta.
+__device__ inline void cheb_coef(double lmax, double ratio, int i, double &theta, double &a, double &b)
+{
+    const double lmin = lmax / ratio;
+    theta = 0.5 * (lmax + lmin);
+    const double delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+    double rho = 1.0 / sigma, rho_prev = rho;
+    for (int j = 1; j <= i; ++j) {
+        rho_prev = rho;
+        rho = 1.0 / (2.0 * sigma - rho);
+    }
+    a = rho * rho_prev;
+    b = 2.0 * rho / delta;
+}
+
 template <typename T>
 __device__ inline double to_d(T v) { return (double)v; }
 

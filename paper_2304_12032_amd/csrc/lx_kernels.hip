@@ -729,22 +729,6 @@ __global__ void k_simple_zu(int64_t nv, const T *Finv, const T *r, const double 
     reinterpret_cast<V *>(z)[i] = zv;
 }
 
-// Chebyshev scalars of step i >= 1 for the interval [lmax/ratio, lmax]:
-// d_i = a d_{i-1} + b diag(S~)^{-1} r_i; step 0 is d_0 = diag(S~)^{-1} r_0 / theta.
-__device__ inline void cheb_coef(double lmax, double ratio, int i, double &theta, double &a, double &b)
-{
-    const double lmin = lmax / ratio;
-    theta = 0.5 * (lmax + lmin);
-    const double delta = 0.5 * (lmax - lmin), sigma = theta / delta;
-    double rho = 1.0 / sigma, rho_prev = rho;
-    for (int j = 1; j <= i; ++j) {
-        rho_prev = rho;
-        rho = 1.0 / (2.0 * sigma - rho);
-    }
-    a = rho * rho_prev;
-    b = 2.0 * rho / delta;
-}
-
 // t = z.p - sum_j B_ij z.u_j (z.p holds scale*r.p on entry); degree 0: z.p = S~^{-1}_diag t;
 // degree > 0: Chebyshev step 0 (rc = t, cur.w = d0 = Sinv t / theta, z.p = d0).
 template <typename T, int LPR>

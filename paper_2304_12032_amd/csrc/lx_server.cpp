@@ -77,7 +77,12 @@ int64_t estimate_footprint(const Request &r)
     b += nv * (48 + 16 + 12 * s + 4);         // coords, rowptr/diag/dir index, SIMPLE blocks
     b += N * 8 * (r.problem.bdf_order + 2);   // history + solution (FP64)
     b += N * s * (2 * r.solver.restart + 3);  // basis, preconditioned directions, work
-    b += nv * s * 9;                          // Schur Chebyshev work
+    if (r.solver.precond == LX_PC_AMG)
+        // S~ on the vertex 2-ring (about 4x the block count) with its coarsening
+        // lists, level vectors, velocity-block Chebyshev work, coarse levels
+        b += 4 * nblk * (s + 8) + nv * (22 * s + 24) + (3 << 20);
+    else
+        b += nv * s * 9;                      // Schur Chebyshev work
     if (r.solver.precision != LX_FP64) b += N * (8 * 2 + 4 * 2);
     if (r.problem.ale) b += nv * 8 * 3 * 12 + nblk * 16;
     return b + (1 << 20);

@@ -4,6 +4,7 @@
 #include <utility>
 #include <vector>
 
+#include "lx_amg.h"
 #include "lx_common.h"
 #include "lx_kernels.h"
 
@@ -75,6 +76,10 @@ struct Sim {
     float *d_V32 = nullptr, *d_w32 = nullptr, *d_x32 = nullptr, *d_r32 = nullptr, *d_sw32 = nullptr,
           *d_Z32 = nullptr;
     double *d_r64 = nullptr, *d_b64 = nullptr;
+    // SIMPLE block approximations of LX_PC_AMG (one of the two, by precision)
+    AmgHost amgh;
+    Amg<double> amg64;
+    Amg<float> amg32;
     // reductions
     GmState *d_st = nullptr;
     GmState *h_st = nullptr;
@@ -105,6 +110,8 @@ struct Sim {
     void timer_flush(int kused, lx_step_stats &acc);
     lx_status read_state();
 
+    template <typename T>
+    lx_status setup_amg(Amg<T> &A);
     template <typename T>
     lx_status gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, GmResult &res,
                     lx_step_stats &tstats, bool inner = false);

@@ -83,11 +83,25 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     if (sv->restart < 1 || sv->restart > kMaxRestart) return fail(LX_EINVAL, "restart must be 1..%d", kMaxRestart);
     if (sv->precision != LX_FP64 && sv->precision != LX_FP32_IR) return fail(LX_EINVAL, "bad precision");
     if (pr->stab < 0 || pr->stab > 2) return fail(LX_EINVAL, "bad stabilisation");
-    if (sv->schur_degree < 0 || sv->schur_degree > 32) return fail(LX_EINVAL, "schur_degree must be 0..32");
-    if (sv->schur_degree > 0 && !(sv->schur_ratio > 1.0)) return fail(LX_EINVAL, "schur_ratio must be > 1");
+    if (sv->precond != LX_PC_AMG && sv->precond != LX_PC_CHEB_SCHUR) return fail(LX_EINVAL, "bad precond");
+    if (sv->precond == LX_PC_CHEB_SCHUR) {
+        if (sv->schur_degree < 0 || sv->schur_degree > 32) return fail(LX_EINVAL, "schur_degree must be 0..32");
+        if (sv->schur_degree > 0 && !(sv->schur_ratio > 1.0)) return fail(LX_EINVAL, "schur_ratio must be > 1");
+    } else {
+        if (sv->f_degree < 0 || sv->f_degree > 8) return fail(LX_EINVAL, "f_degree must be 0..8");
+        if (sv->amg_degree < 0 || sv->amg_degree > 8) return fail(LX_EINVAL, "amg_degree must be 0..8");
+        if (sv->f_ratio != 0.0 && !(sv->f_ratio > 1.0)) return fail(LX_EINVAL, "f_ratio must be 0 or > 1");
+        if (sv->amg_ratio != 0.0 && !(sv->amg_ratio > 1.0)) return fail(LX_EINVAL, "amg_ratio must be 0 or > 1");
+    }
 
     prob = *pr;
     solver = *sv;
+    if (solver.precond == LX_PC_AMG) {
+        if (solver.f_degree == 0) solver.f_degree = 3;
+        if (solver.amg_degree == 0) solver.amg_degree = 2;
+        if (solver.f_ratio == 0.0) solver.f_ratio = 10.0;
+        if (solver.amg_ratio == 0.0) solver.amg_ratio = 30.0;
+    }
     for (int i = 0; i < pr->n_bc; ++i) {
         BCDesc b;
         b.spec = pr->bc[i];
@@ -158,6 +172,11 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         for (int32_t v : fv) mark[v] = 1;
         for (int64_t v = 0; v < nv; ++v)
             if (mark[v]) h_ale_nodes.push_back((int32_t)v);
+    }
+
+    if (solver.precond == LX_PC_AMG) {
+        lx_status sa = amg_build_host(hs, amgh);
+        if (sa != LX_OK) return sa;
     }
 
     // ---- device side: everything above is host-only validation and setup
@@ -239,6 +258,11 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         ALLOC(d_b64, sizeof(double) * N);
     }
 #undef ALLOC
+    if (solver.precond == LX_PC_AMG) {
+        lx_status sa = solver.precision == LX_FP64 ? setup_amg<double>(amg64) : setup_amg<float>(amg32);
+        if (sa != LX_OK) return sa;
+        amgh = AmgHost();
+    }
     // ---- uploads
     LX_HIP(hipMemcpyAsync(d_xh, hs.xh.data(), sizeof(double) * 3 * nv, hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_x, hs.xh.data(), sizeof(double) * 3 * nv, hipMemcpyHostToDevice, stream));
@@ -290,6 +314,85 @@ RowPattern Sim::pattern() const
     P.diag = d_diag;
     P.tslot = d_tslot;
     return P;
+}
+
+// Device arrays of the Schur-block hierarchy (patterns uploaded once; values
+// are refreshed every step by launch_amg_setup).
+template <typename T>
+lx_status Sim::setup_amg(Amg<T> &A)
+{
+    const int nl = (int)amgh.lev.size();
+    A.nlev = nl - 1;
+    A.degree = solver.amg_degree;
+    A.ratio = solver.amg_ratio;
+    A.f_degree = solver.f_degree;
+    A.f_ratio = solver.f_ratio;
+    A.f_warm = false;
+    const char *env = getenv("LXNS_AMG_LPR");
+    const int lpr_env = env ? atoi(env) : 0;
+    int64_t maxgrid = (nv * 16 + 255) / 256;
+    auto up = [&](int32_t *&d, const std::vector<int32_t> &h) -> lx_status {
+        lx_status s = dalloc((void **)&d, sizeof(int32_t) * std::max<size_t>(h.size(), 1));
+        if (s != LX_OK) return s;
+        if (!h.empty()) LX_HIP(hipMemcpyAsync(d, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, stream));
+        return LX_OK;
+    };
+    auto vec = [&](T *&d, int64_t n) { return dalloc((void **)&d, sizeof(T) * std::max<int64_t>(n, 1)); };
+#define CK(x)                          \
+    do {                               \
+        lx_status _s = (x);            \
+        if (_s != LX_OK) return _s;    \
+    } while (0)
+    for (int l = 0; l < nl; ++l) {
+        const AmgLevelHost &H = amgh.lev[l];
+        AmgLevel<T> &L = A.L[l];
+        L.n = H.n;
+        L.nnz = (int64_t)H.col.size();
+        const double avg = (double)L.nnz / (double)std::max<int64_t>(L.n, 1);
+        L.lpr = avg >= 40 ? 32 : avg >= 12 ? 16 : avg >= 6 ? 8 : 4;
+        if (lpr_env == 4 || lpr_env == 8 || lpr_env == 16 || lpr_env == 32) L.lpr = lpr_env;
+        maxgrid = std::max<int64_t>(maxgrid, (L.n * L.lpr + 255) / 256);
+        CK(up(L.rowptr, H.rowptr));
+        CK(up(L.col, H.col));
+        CK(up(L.diag, H.diag));
+        CK(vec(L.val, L.nnz));
+        CK(vec(L.x1, L.n));
+        if (l < A.nlev) {
+            CK(up(L.agg, H.agg));
+            CK(up(L.mptr, H.mptr));
+            CK(up(L.mem, H.mem));
+            CK(up(L.cptr, H.cptr));
+            CK(up(L.cidx, H.cidx));
+            CK(vec(L.dinv, L.n));
+            CK(vec(L.x0, L.n));
+            CK(vec(L.res, L.n));
+            CK(vec(L.d0, L.n));
+            CK(vec(L.d1, L.n));
+        }
+        if (l < A.nlev || l == 0) CK(vec(L.r, L.n));
+    }
+    const AmgLevelHost &Hc = amgh.lev.back();
+    A.nc = Hc.n;
+    std::vector<int32_t> crow(Hc.col.size());
+    for (int64_t i = 0; i < Hc.n; ++i)
+        for (int32_t k = Hc.rowptr[i]; k < Hc.rowptr[i + 1]; ++k) crow[k] = (int32_t)i;
+    CK(up(A.crow, crow));
+    CK(dalloc((void **)&A.dense, sizeof(double) * 2 * A.nc * std::max<int64_t>(A.nc, 1)));
+    CK(dalloc((void **)&A.lam, sizeof(double) * kLamSlots));
+    CK(dalloc((void **)&A.partial, sizeof(double) * (maxgrid + 64)));
+    CK(dalloc((void **)&A.counter, sizeof(uint32_t) * 4));
+    CK(vec(A.fr, 4 * nv));
+    CK(vec(A.fd0, 4 * nv));
+    CK(vec(A.fd1, 4 * nv));
+    CK(vec(A.fv, 4 * nv));
+#undef CK
+    LX_HIP(hipMemsetAsync(A.lam, 0, sizeof(double) * kLamSlots, stream));
+    LX_HIP(hipMemsetAsync(A.counter, 0, sizeof(uint32_t) * 4, stream));
+    launch_fill<T>(4 * nv, A.fr, T(0), stream);
+    launch_fill<T>(4 * nv, A.fd0, T(0), stream);
+    launch_fill<T>(4 * nv, A.fd1, T(0), stream);
+    launch_fill<T>(4 * nv, A.fv, T(0), stream);
+    return LX_OK;
 }
 
 // ------------------------------------------------------------------ timing
@@ -356,6 +459,7 @@ struct Ops<double> {
     static double *w(Sim *s) { return s->d_w64; }
     static double *sw(Sim *s) { return s->d_sw64; }
     static double *Z(Sim *s) { return s->d_Z64; }
+    static Amg<double> &amg(Sim *s) { return s->amg64; }
 };
 template <>
 struct Ops<float> {
@@ -367,6 +471,7 @@ struct Ops<float> {
     static float *w(Sim *s) { return s->d_w32; }
     static float *sw(Sim *s) { return s->d_sw32; }
     static float *Z(Sim *s) { return s->d_Z32; }
+    static Amg<float> &amg(Sim *s) { return s->amg32; }
 };
 
 lx_status Sim::read_state()
@@ -422,7 +527,11 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
         const int kmax = std::min(m, max_iters - it);
         for (int k = 0; k < kmax; ++k) {
             T *zk = Z + k * ld;
-            launch_simple_apply<T>(P, SP, V + k * ld, &d_st->s[k], zk, &d_st->done, stream);
+            if (solver.precond == LX_PC_AMG)
+                launch_simple_amg_apply<T>(P, val, SP.Finv, SP.Dinv, Ops<T>::amg(this), V + k * ld, &d_st->s[k], zk,
+                                           &d_st->done, stream);
+            else
+                launch_simple_apply<T>(P, SP, V + k * ld, &d_st->s[k], zk, &d_st->done, stream);
             auto *tm = timer_begin(0, k, false);
             launch_spmv<T>(P, val, zk, w, &d_st->done, stream, tm ? tm->first : nullptr, tm ? tm->second : nullptr);
             launch_gm_dot1<T>(N, k, V, ld, w, d_st, d_partial, nb_red, stream);
@@ -569,7 +678,9 @@ lx_status Sim::build_system(double t1, StepCoef &C, lx_step_stats &tstats)
         add_neumann(t1, d_rhs64, nullptr);
         launch_dirichlet_rows<double>(n_dir, d_dir_node, d_g, P, d_val64, d_rhs64, stream);
         launch_simple_setup<double>(P, d_val64, d_Finv64, d_Dinv64, d_Sinv64, stream);
-        if (solver.schur_degree > 0)
+        if (solver.precond == LX_PC_AMG)
+            launch_amg_setup<double>(P, d_val64, d_Finv64, d_Dinv64, amg64, stream);
+        else if (solver.schur_degree > 0)
             launch_schur_bound<double>(P, d_val64, d_Dinv64, d_Sinv64, d_sw64, d_st, d_partial, nb_red, stream);
     } else {
         if (solver.asm_fp64) {
@@ -590,7 +701,9 @@ lx_status Sim::build_system(double t1, StepCoef &C, lx_step_stats &tstats)
         }
         launch_dirichlet_rows<float>(n_dir, d_dir_node, d_g, P, d_val32, (float *)nullptr, stream);
         launch_simple_setup<float>(P, d_val32, d_Finv32, d_Dinv32, d_Sinv32, stream);
-        if (solver.schur_degree > 0)
+        if (solver.precond == LX_PC_AMG)
+            launch_amg_setup<float>(P, d_val32, d_Finv32, d_Dinv32, amg32, stream);
+        else if (solver.schur_degree > 0)
             launch_schur_bound<float>(P, d_val32, d_Dinv32, d_Sinv32, d_sw32, d_st, d_partial, nb_red, stream);
     }
     LX_HIP(hipGetLastError());

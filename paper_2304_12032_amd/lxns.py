@@ -28,6 +28,7 @@ FE = {"p1p1": 1, "p2p1": 2}
 DIFF = {"gradgrad": 0, "symgrad": 1}
 STAB = {"none": 0, "supg_pspg": 1, "vms_les": 2}
 PREC = {"fp64": 0, "fp32_ir": 1}
+PRECOND = {"amg": 0, "cheb_schur": 1}
 REQ_STATE = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 
 
@@ -74,7 +75,9 @@ class lx_problem(ctypes.Structure):
 class lx_solver(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("restart", c_i32), ("max_iters", c_i32), ("max_ir", c_i32),
                 ("rtol", c_dbl), ("ir_rtol", c_dbl), ("inner_rtol", c_dbl), ("deterministic", c_i32),
-                ("collect_timing", c_i32), ("schur_degree", c_i32), ("asm_fp64", c_i32), ("schur_ratio", c_dbl)]
+                ("collect_timing", c_i32), ("schur_degree", c_i32), ("asm_fp64", c_i32), ("schur_ratio", c_dbl),
+                ("precond", c_i32), ("f_degree", c_i32), ("amg_degree", c_i32), ("pad", c_i32), ("f_ratio", c_dbl),
+                ("amg_ratio", c_dbl)]
 
 
 class lx_sizes(ctypes.Structure):
@@ -240,6 +243,11 @@ class _Marshal:
         s.schur_degree = int(getattr(solver, "schur_degree", 8))
         s.schur_ratio = float(getattr(solver, "schur_ratio", 100.0))
         s.asm_fp64 = int(bool(getattr(solver, "asm_fp64", False)))
+        s.precond = PRECOND[getattr(solver, "precond", "amg")]
+        s.f_degree = int(getattr(solver, "f_degree", 0))
+        s.amg_degree = int(getattr(solver, "amg_degree", 0))
+        s.f_ratio = float(getattr(solver, "f_ratio", 0.0))
+        s.amg_ratio = float(getattr(solver, "amg_ratio", 0.0))
         self.solver = s
 
 
