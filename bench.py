@@ -36,6 +36,12 @@ def parse():
     ap.add_argument("--nxy", type=int, default=32)
     ap.add_argument("--nz", type=int, default=160)
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32_ir"])
+    ap.add_argument("--precond", default="amg", choices=["amg", "cheb_schur"])
+    ap.add_argument("--f-degree", type=int, default=3)
+    ap.add_argument("--f-ratio", type=float, default=5.0)
+    ap.add_argument("--amg-degree", type=int, default=2)
+    ap.add_argument("--amg-cycle", type=int, default=2)
+    ap.add_argument("--amg-ratio", type=float, default=30.0)
     ap.add_argument("--schur-degree", type=int, default=16)
     ap.add_argument("--schur-ratio", type=float, default=300.0)
     ap.add_argument("--restart", type=int, default=30)
@@ -58,7 +64,9 @@ def run_precision(mesh, prob, precision, args, stream, torch):
     from inputs.problem import SolverCfg
     sv = SolverCfg(precision=precision, rtol=1e-8, ir_rtol=1e-8, inner_rtol=args.inner_rtol, max_iters=20000,
                    collect_timing=True, schur_degree=args.schur_degree, schur_ratio=args.schur_ratio,
-                   restart=args.restart, asm_fp64=bool(args.asm_fp64))
+                   restart=args.restart, asm_fp64=bool(args.asm_fp64), precond=args.precond,
+                   f_degree=args.f_degree, f_ratio=args.f_ratio, amg_degree=args.amg_degree,
+                   amg_cycle=args.amg_cycle, amg_ratio=args.amg_ratio)
     sim = Sim(mesh, prob, sv, device=0, stream=stream)
     q = sim.query()
     for _ in range(args.warmup):
@@ -152,8 +160,11 @@ def main():
         "config": {"workload": "tube R=1 L=10, %d tets, %d vertices, N=%d, P1-P1 VMS-LES BDF2 dt=1e-3 nu=0.035, "
                                "pulsatile 50 cm/s inflow, RIIS disc R=1e4 eps=0.05, from rest" %
                                (q["n_tets"], nv, q["n_dofs"]),
-                   "precision": headp, "rel_residual_target": 1e-8, "schur_degree": args.schur_degree,
-                   "schur_ratio": args.schur_ratio, "restart": args.restart,
+                   "precision": headp, "rel_residual_target": 1e-8, "restart": args.restart,
+                   "precond": (("amg: F chebyshev deg %d ratio %g, S~ aggregation AMG cycle %d smoothing deg %d "
+                                "ratio %g") % (args.f_degree, args.f_ratio, args.amg_cycle, args.amg_degree,
+                                               args.amg_ratio)) if args.precond == "amg" else
+                              ("cheb_schur deg %d ratio %g" % (args.schur_degree, args.schur_ratio)),
                    "asm_fp64": bool(args.asm_fp64), "inner_rtol": args.inner_rtol},
         "p50_ms": round(float(np.percentile(head["lat"], 50)), 3),
         "p99_ms": round(float(np.percentile(head["lat"], 99)), 3),

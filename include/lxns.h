@@ -155,7 +155,8 @@ enum { LX_PC_AMG = 0, LX_PC_CHEB_SCHUR = 1 };
  * blocks of SIMPLE by AMG, additive Schwarz or block Jacobi; the two choices
  * here are
  *   LX_PC_AMG (default): S~ is formed explicitly and approximated by one
- *     V-cycle of aggregation AMG with Chebyshev smoothing of degree
+ *     multigrid cycle of aggregation AMG (amg_cycle coarse corrections on
+ *     every level below the finest) with Chebyshev smoothing of degree
  *     amg_degree over [lam / amg_ratio, lam] on every level (lam the
  *     Gershgorin bound of diag(A_l)^{-1} A_l) and a dense coarsest solve; F is
  *     approximated by a Chebyshev iteration of degree f_degree on F~^{-1} F
@@ -164,8 +165,8 @@ enum { LX_PC_AMG = 0, LX_PC_CHEB_SCHUR = 1 };
  *   LX_PC_CHEB_SCHUR: F by F~^{-1}; S~ (not formed) by diag(S~)^{-1}
  *     (schur_degree = 0) or a Chebyshev iteration of degree schur_degree with
  *     diagonal scaling over [lam / schur_ratio, lam].
- * A zero in f_degree, amg_degree, f_ratio or amg_ratio selects its default
- * (3, 2, 10, 30).  LX_FP32_IR: FP32 matrix and FP32 inner GMRES inside an
+ * A zero in f_degree, amg_degree, amg_cycle, f_ratio or amg_ratio selects its
+ * default (3, 2, 2, 5, 30).  LX_FP32_IR: FP32 matrix and FP32 inner GMRES inside an
  * FP64 iterative refinement loop that stops when the FP64 residual satisfies
  * ir_rtol; inner solves aim at one more refinement step but never tighter
  * than inner_rtol. */
@@ -182,8 +183,9 @@ typedef struct {
     int32_t precond;         /* LX_PC_AMG | LX_PC_CHEB_SCHUR                         */
     int32_t f_degree;        /* LX_PC_AMG: 0..8 (0: default 3)                       */
     int32_t amg_degree;      /* LX_PC_AMG: 0..8 (0: default 2)                       */
-    int32_t pad;
-    double f_ratio;          /* LX_PC_AMG: 0 (default 10) or > 1                     */
+    int32_t amg_cycle;       /* LX_PC_AMG: coarse corrections per level below the
+                                finest, 0..3 (0: default 2, a W-cycle there)        */
+    double f_ratio;          /* LX_PC_AMG: 0 (default 5) or > 1                      */
     double amg_ratio;        /* LX_PC_AMG: 0 (default 30) or > 1                     */
 } lx_solver;
 

@@ -44,11 +44,15 @@ def _grid_ids(nx, ny, nz):
     return np.arange((nx + 1) * (ny + 1) * (nz + 1), dtype=np.int64).reshape(nz + 1, ny + 1, nx + 1)
 
 
-def _kuhn_tets(nx, ny, nz):
+def _kuhn_tets(nx, ny, nz, mirror_xy=False):
     """Kuhn split of an nx*ny*nz cell grid; vertex (i,j,k) has id i + (nx+1)(j + (ny+1)k).
 
     Cell corners c[dz][dy][dx]; for every permutation (p0,p1,p2) of the axes the
-    tetrahedron is c000 -> c000+e_p0 -> c000+e_p0+e_p1 -> c111.
+    tetrahedron is c000 -> c000+e_p0 -> c000+e_p0+e_p1 -> c111.  mirror_xy: cells
+    in the lower half of x (of y) use the split reflected in x (in y), so the main
+    diagonal of every cell points away from the grid centre; reflected splits
+    meet conformingly on the mirror planes.  On a square grid mapped to a disc
+    this splits each corner cell through its corner vertex instead of across it.
     """
     ids = _grid_ids(nx, ny, nz)
     c = {}
@@ -56,15 +60,27 @@ def _kuhn_tets(nx, ny, nz):
         for dy in (0, 1):
             for dx in (0, 1):
                 c[(dx, dy, dz)] = ids[dz:dz + nz, dy:dy + ny, dx:dx + nx].reshape(-1)
+    if mirror_xy:
+        ci = np.broadcast_to(np.arange(nx)[None, None, :], (nz, ny, nx)).reshape(-1)
+        cj = np.broadcast_to(np.arange(ny)[None, :, None], (nz, ny, nx)).reshape(-1)
+        fx, fy = ci < nx // 2, cj < ny // 2
+
+        def corner(dx, dy, dz):
+            a = np.where(fx, c[(1 - dx, dy, dz)], c[(dx, dy, dz)])
+            b = np.where(fx, c[(1 - dx, 1 - dy, dz)], c[(dx, 1 - dy, dz)])
+            return np.where(fy, b, a)
+    else:
+        def corner(dx, dy, dz):
+            return c[(dx, dy, dz)]
     perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
     out = []
     for p in perms:
         e = [0, 0, 0]
-        path = [c[(0, 0, 0)]]
+        path = [corner(0, 0, 0)]
         for ax in p[:2]:
             e[ax] = 1
-            path.append(c[tuple(e)])
-        path.append(c[(1, 1, 1)])
+            path.append(corner(*e))
+        path.append(corner(1, 1, 1))
         out.append(np.stack(path, axis=1))
     # interleave so that the 6 tets of one cell are consecutive
     tets = np.stack(out, axis=1).reshape(-1, 4)
@@ -96,18 +112,31 @@ def boundary_faces(tets, nv):
     return f[idx[cnt == 1]].astype(np.int32)
 
 
+def tet_quality(coords, tets, sign=None):
+    """Volume over cubed longest edge (0.118 for the regular tetrahedron); negative
+    for inverted elements when sign gives the reference orientation."""
+    vol = tet_signed_volumes(coords, tets)
+    if sign is not None:
+        vol = vol * sign
+    X = coords[tets]
+    lmax = np.zeros(len(tets))
+    for a, b in ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)):
+        lmax = np.maximum(lmax, np.linalg.norm(X[:, a] - X[:, b], axis=1))
+    return vol / lmax ** 3
+
+
 def _jitter_interior(coords, tets, interior, amp, seed):
-    """Uniform jitter in [-amp, amp]^3 on interior nodes; vertices of any tet whose
-    orientation flips (or whose volume drops below 1% of its unjittered value) get
-    their jitter halved, repeatedly, until no tet is inverted."""
+    """Uniform jitter in [-amp, amp]^3 on interior nodes; the vertices of any tet
+    whose quality (volume / longest edge^3) falls below half of its unjittered
+    value, inverted ones included, get their jitter halved, repeatedly."""
     nv = coords.shape[0]
     r = uniform01(seed, 3 * nv).reshape(nv, 3) * 2.0 - 1.0
     jit = r * amp
     jit[~interior] = 0.0
-    vol0 = tet_signed_volumes(coords, tets)
+    sign = np.sign(tet_signed_volumes(coords, tets))
+    q0 = tet_quality(coords, tets, sign)
     for _ in range(60):
-        vol = tet_signed_volumes(coords + jit, tets)
-        bad = (vol * np.sign(vol0)) < 0.01 * np.abs(vol0)
+        bad = tet_quality(coords + jit, tets, sign) < 0.5 * q0
         if not bad.any():
             break
         vb = np.unique(tets[bad].reshape(-1))
@@ -156,17 +185,19 @@ def _disc_map(sx, sy):
 
 
 def tube(nxy=32, nz=160, radius=1.0, length=10.0, jitter=0.1, seed=0, shuffle=True):
-    """Straight tube along z with nxy^2 x nz hexahedra split into 6 tets each.
+    """Straight tube along z with nxy^2 x nz hexahedra split into 6 tets each
+    (Kuhn split mirrored about the axis planes, see _kuhn_tets).
 
     Interior nodes are jittered uniformly by up to jitter*h per coordinate with
-    h = 2*radius/nxy.  Tags: inlet (z=0) 1, outlet (z=length) 2, wall 3.
+    h = 2*radius/nxy, limited where it would halve an element's quality.  Tags:
+    inlet (z=0) 1, outlet (z=length) 2, wall 3.
     """
     s = np.linspace(-1.0, 1.0, nxy + 1)
     zc = np.linspace(0.0, length, nz + 1)
     Z, SY, SX = np.meshgrid(zc, s, s, indexing="ij")
     X, Y = _disc_map(SX, SY)
     coords = np.stack([radius * X.ravel(), radius * Y.ravel(), Z.ravel()], axis=1)
-    tets = _orient_positive(coords, _kuhn_tets(nxy, nxy, nz)).astype(np.int32)
+    tets = _orient_positive(coords, _kuhn_tets(nxy, nxy, nz, mirror_xy=True)).astype(np.int32)
     h = 2.0 * radius / nxy
     on_wall = (np.abs(SX.ravel()) == 1.0) | (np.abs(SY.ravel()) == 1.0)
     on_cap = (Z.ravel() == 0.0) | (Z.ravel() == length)
@@ -206,7 +237,7 @@ def spheroid(nyz=105, nx=121, semi=(4.0, 3.0, 3.0), xcut=3.5, jitter=0.1, seed=0
     r = b * np.sqrt(1.0 - XX * XX / (a * a))
     coords = np.stack([XX.ravel(), (r * U).ravel(), (r * V).ravel()], axis=1)
     # index order (i fastest) is (sy, sz, x): build tets on that grid then they map through
-    tets = _orient_positive(coords, _kuhn_tets(nyz, nyz, nx)).astype(np.int32)
+    tets = _orient_positive(coords, _kuhn_tets(nyz, nyz, nx, mirror_xy=True)).astype(np.int32)
     h = 2.0 * b / nyz
     on_wall = (np.abs(SY.ravel()) == 1.0) | (np.abs(SZ.ravel()) == 1.0)
     on_cap = np.abs(np.abs(XX.ravel()) - xcut) < 1e-12

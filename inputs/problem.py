@@ -92,8 +92,9 @@ class SolverCfg:
     asm_fp64: bool = False
     precond: str = "amg"             # amg | cheb_schur
     f_degree: int = 3                # amg: Chebyshev degree on the velocity block (1 = block Jacobi)
-    f_ratio: float = 10.0
+    f_ratio: float = 5.0
     amg_degree: int = 2              # amg: Chebyshev smoothing degree per level
+    amg_cycle: int = 2               # amg: coarse corrections per level below the finest (2 = W)
     amg_ratio: float = 30.0
 
 

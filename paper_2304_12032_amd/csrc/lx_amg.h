@@ -5,8 +5,8 @@
 // The paper's solver applies SIMPLE with its velocity and Schur blocks
 // approximated by AMG, additive Schwarz or block Jacobi (Sec. 2.4).  Here the
 // Schur block is formed explicitly (its pattern is the vertex 2-ring) and
-// approximated by one V-cycle of unsmoothed-aggregation AMG with Chebyshev
-// smoothing; the aggregates depend on the mesh only, so the host builds the
+// approximated by one cycle of unsmoothed-aggregation AMG with Chebyshev
+// smoothing (a W-cycle below the finest level by default); the aggregates depend on the mesh only, so the host builds the
 // hierarchy's patterns once and the device refreshes every level's values at
 // each step (Galerkin products with piecewise-constant prolongation are plain
 // sums over fixed index lists).  The coarsest level is inverted densely.
@@ -66,6 +66,7 @@ struct Amg {
     uint32_t *counter = nullptr;
     int nb = 1;                         // reduction blocks
     int degree = 2;                     // Chebyshev smoothing degree (pre and post)
+    int cycle = 1;                      // coarse corrections per level below the finest (1 V, 2 W)
     double ratio = 30.0;                // smoothing interval [lam / ratio, lam]
     int f_degree = 3;                   // Chebyshev degree on F (1: plain block Jacobi)
     double f_ratio = 10.0;

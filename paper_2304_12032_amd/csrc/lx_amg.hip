@@ -1,7 +1,7 @@
 // Device side of the SIMPLE block approximations (Sec. 2.4 names AMG and block
 // Jacobi among the block approximations of its SIMPLE preconditioner):
 //  * the Schur block S~ = C - B D^{-1} G is formed explicitly each step, and
-//    approximated by one V-cycle of unsmoothed-aggregation multigrid with
+//    approximated by one cycle of unsmoothed-aggregation multigrid with
 //    Chebyshev smoothing on diag(A_l)^{-1} A_l and a dense inverse on the
 //    coarsest level;
 //  * the velocity block F is approximated by a Chebyshev iteration on
@@ -71,13 +71,13 @@ __device__ inline double block_max(double v, double *lds)
     return fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
 }
 
-// dinv_i = 1 / A_ii and *lam = max_i sum_k |A_ik| / |A_ii| (Gershgorin bound of
-// diag(A)^{-1} A); the last block to finish reduces the block maxima.
+// dinv_i = 1 / A_ii and partial[block] = max over the block's rows of
+// sum_k |A_ik| / |A_ii|; k_max_fin turns the block maxima into the Gershgorin
+// bound of diag(A)^{-1} A.
 template <typename T, int LPR>
 __global__ __launch_bounds__(256) void k_amg_rowinfo(int64_t n, const int32_t *__restrict__ rowptr,
                                                      const int32_t *__restrict__ diag, const T *__restrict__ val,
-                                                     T *__restrict__ dinv, double *lam, double *partial,
-                                                     uint32_t *counter)
+                                                     T *__restrict__ dinv, double *partial)
 {
     __shared__ double lds[4];
     const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
@@ -96,14 +96,16 @@ __global__ __launch_bounds__(256) void k_amg_rowinfo(int64_t n, const int32_t *_
     }
     const double m = block_max(g, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = m;
-    if (!arrive_last(counter)) return;
-    double mm = 0;
-    for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x) mm = fmax(mm, partial[b]);
-    mm = block_max(mm, lds);
-    if (threadIdx.x == 0) {
-        *lam = mm;
-        *counter = 0;
-    }
+}
+
+// *out = max of partial[0..nb) (one block of 256)
+__global__ __launch_bounds__(256) void k_max_fin(int nb, const double *partial, double *out)
+{
+    __shared__ double lds[4];
+    double m = 0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) m = fmax(m, partial[b]);
+    m = block_max(m, lds);
+    if (threadIdx.x == 0) *out = m;
 }
 
 // Galerkin sum with piecewise-constant prolongation: each coarse entry is the
@@ -207,9 +209,10 @@ __global__ __launch_bounds__(1024) void k_dense_gj(int nc, double *aug)
     }
 }
 
-// One power step w = F~^{-1} F v / ||v|| (velocity block, [nv][4] vectors);
-// ||w||^2 goes to lam[slot_out].  v = null: the start vector of +-1 entries from
-// a multiplicative hash of the index.  factor > 0: lam[kLamF] = factor ||w||.
+// One power step w = F~^{-1} F v / ||v|| (velocity block, [nv][4] vectors),
+// ||v||^2 read from lam[slot_in]; partial[block] = the block's part of ||w||^2.
+// v = null: the start vector of +-1 entries from a multiplicative hash of the
+// index.
 __device__ inline double pm_one(uint32_t q)
 {
     return ((q * 2654435761u) >> 13) & 1u ? 1.0 : -1.0;
@@ -217,8 +220,8 @@ __device__ inline double pm_one(uint32_t q)
 
 template <typename T, int LPR>
 __global__ __launch_bounds__(256) void k_fpow(RowPattern P, const T *__restrict__ val, const T *__restrict__ Finv,
-                                              const T *__restrict__ v, T *__restrict__ w, double *lam, int slot_in,
-                                              int slot_out, double factor, double *partial, uint32_t *counter)
+                                              const T *__restrict__ v, T *__restrict__ w, const double *lam,
+                                              int slot_in, double *partial)
 {
     __shared__ double lds[16];
     const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
@@ -266,13 +269,20 @@ __global__ __launch_bounds__(256) void k_fpow(RowPattern P, const T *__restrict_
     }
     block_sum<1>(acc, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc[0];
-    if (!arrive_last(counter)) return;
-    double tot[1];
-    reduce_partials<1>(partial, gridDim.x, 1, tot, lds);
+}
+
+// lam[slot_out] = sum of partial[0..nb) in a fixed order; factor > 0 also sets
+// lam[kLamF] = factor * sqrt(that sum).
+__global__ __launch_bounds__(256) void k_fpow_fin(int nb, const double *partial, double *lam, int slot_out,
+                                                  double factor)
+{
+    __shared__ double lds[16];
+    double a[1] = {0.0};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) a[0] += partial[b];
+    block_sum<1>(a, lds);
     if (threadIdx.x == 0) {
-        lam[slot_out] = tot[0];
-        if (factor > 0) lam[kLamF] = factor * sqrt(tot[0]);
-        *counter = 0;
+        lam[slot_out] = a[0];
+        if (factor > 0) lam[kLamF] = factor * sqrt(a[0]);
     }
 }
 
@@ -449,15 +459,19 @@ __global__ __launch_bounds__(256) void k_xu_amg(RowPattern P, const T *__restric
 
 // Level l > 0 start: r = restriction of the finer residual (sum over the
 // aggregate's members), x0 = d0 = dinv r / theta, res = r.
-template <typename T>
-__global__ void k_amg_pre(AmgLevel<T> L, const T *__restrict__ fres, const int32_t *__restrict__ mptr,
-                          const int32_t *__restrict__ mem, const double *lam, double ratio, const int32_t *done)
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_amg_pre(AmgLevel<T> L, const T *__restrict__ fres,
+                                                 const int32_t *__restrict__ mptr, const int32_t *__restrict__ mem,
+                                                 const double *lam, double ratio, const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
     if (i >= L.n) return;
     double s = 0;
-    for (int32_t q = mptr[i]; q < mptr[i + 1]; ++q) s += (double)fres[mem[q]];
+    for (int32_t q = mptr[i] + lane; q < mptr[i + 1]; q += LPR) s += (double)fres[mem[q]];
+    s = group_sum<double, LPR>(s);
+    if (lane != 0) return;
     double theta, a, b;
     cheb_coef(*lam, ratio, 0, theta, a, b);
     const T x = (T)((double)L.dinv[i] * s / theta);
@@ -604,9 +618,10 @@ void launch_amg_setup(const RowPattern &P, const T *val, const T *Finv, const T 
                        L0.col, L0.val);
     for (int l = 0; l < A.nlev; ++l) {
         AmgLevel<T> &L = A.L[l];
-        LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_rowinfo<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s,
-                                                L.n, L.rowptr, L.diag, L.val, L.dinv, &A.lam[l], A.partial,
-                                                A.counter));
+        const unsigned g = rows_grid(L.n, L.lpr);
+        LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_rowinfo<T, LP>), dim3(g), dim3(256), 0, s, L.n, L.rowptr,
+                                                L.diag, L.val, L.dinv, A.partial));
+        hipLaunchKernelGGL(k_max_fin, dim3(1), dim3(256), 0, s, (int)g, A.partial, &A.lam[l]);
         AmgLevel<T> &C = A.L[l + 1];
         hipLaunchKernelGGL((k_amg_coarsen<T>), dim3(flat_grid(C.nnz)), dim3(256), 0, s, C.nnz, L.cptr, L.cidx, L.val,
                            C.val);
@@ -626,9 +641,10 @@ void launch_amg_setup(const RowPattern &P, const T *val, const T *Finv, const T 
             T *vout = even ? A.fd1 : A.fv;
             const int sin = even ? kNormA : kNormB, sout = even ? kNormB : kNormA;
             const double fac = (it == iters - 1) ? A.f_safety : 0.0;
-            LX_LPR_SWITCH(lpr, hipLaunchKernelGGL((k_fpow<T, LP>), dim3(rows_grid(P.nv, LP)), dim3(256), 0, s, P,
-                                                  val, Finv, vin, vout, A.lam, sin, sout, fac, A.partial,
-                                                  A.counter));
+            const unsigned g = rows_grid(P.nv, lpr);
+            LX_LPR_SWITCH(lpr, hipLaunchKernelGGL((k_fpow<T, LP>), dim3(g), dim3(256), 0, s, P, val, Finv, vin, vout,
+                                                  A.lam, sin, A.partial));
+            hipLaunchKernelGGL(k_fpow_fin, dim3(1), dim3(256), 0, s, (int)g, A.partial, A.lam, sout, fac);
         }
         A.f_warm = true;
     }
@@ -649,12 +665,12 @@ static void vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s)
                            A.L[l].x1, done);
         return;
     }
-    AmgLevel<T> &L = A.L[l];
+    AmgLevel<T> L = A.L[l];
     const double *lam = &A.lam[l];
     if (l > 0) {
         const AmgLevel<T> &F = A.L[l - 1];
-        hipLaunchKernelGGL((k_amg_pre<T>), dim3(flat_grid(L.n)), dim3(256), 0, s, L, F.res, F.mptr, F.mem, lam,
-                           A.ratio, done);
+        hipLaunchKernelGGL((k_amg_pre<T, 16>), dim3(rows_grid(L.n, 16)), dim3(256), 0, s, L, F.res, F.mptr, F.mem,
+                           lam, A.ratio, done);
     }
     T *dc = L.d0, *dn = L.d1;
     for (int i = 1; i < A.degree; ++i) {
@@ -662,18 +678,27 @@ static void vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s)
                                                 L.x0, dc, dn, lam, A.ratio, i, done));
         std::swap(dc, dn);
     }
-    LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_resid<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s, L, L.x0,
-                                            done));
-    vcycle(A, l + 1, done, s);
-    LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_post0<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s, L,
-                                            A.L[l + 1].x1, lam, A.ratio, done));
-    dc = L.d0;
-    dn = L.d1;
-    for (int i = 1; i < A.degree; ++i) {
-        LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_cheb<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s, L,
-                                                L.x1, dc, dn, lam, A.ratio, i, done));
-        std::swap(dc, dn);
+    // gamma coarse corrections (1: V-cycle, 2: W-cycle below the finest level),
+    // each followed by post-smoothing; the iterate alternates between x0 and x1
+    const int gamma = l > 0 ? A.cycle : 1;
+    for (int c = 0; c < gamma; ++c) {
+        LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_resid<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s, L,
+                                                L.x0, done));
+        vcycle(A, l + 1, done, s);
+        LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_post0<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s, L,
+                                                A.L[l + 1].x1, lam, A.ratio, done));
+        dc = L.d0;
+        dn = L.d1;
+        for (int i = 1; i < A.degree; ++i) {
+            LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_cheb<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s,
+                                                    L, L.x1, dc, dn, lam, A.ratio, i, done));
+            std::swap(dc, dn);
+        }
+        if (c + 1 < gamma) std::swap(L.x0, L.x1);
     }
+    // the level's result is read from x1
+    A.L[l].x0 = L.x0;
+    A.L[l].x1 = L.x1;
 }
 
 template <typename T>

@@ -85,27 +85,24 @@ template <typename T>
 void launch_spmv(const RowPattern &P, const T *val, const T *x, T *y, const int32_t *done,
                  hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
-// GMRES building blocks (vectors of length n = 4 nv, basis stride ldv).
+// GMRES building blocks (vectors of length n = 4 nv, basis stride ldv).  Each
+// reduction writes per-block partial sums into partial (gm_partial_size(n)
+// doubles) and a one-block kernel finishes it.
+constexpr int kDotChunk = 4096;
+int64_t gm_partial_size(int64_t n);
+// r = b - Ax (Ax null: r = b), V0 = r, beta = ||r||; starts a cycle or marks it done
 template <typename T>
-void launch_gm_start(int64_t n, const T *b, const T *Ax, T *V0, GmState *st, double *partial,
-                     int nb, hipStream_t s);
+void launch_gm_start(int64_t n, const T *b, const T *Ax, T *V0, GmState *st, double *partial, hipStream_t s);
+// CGS2 of w against Vhat_0..Vhat_k, Vhat_{k+1}, Hessenberg column k and its Givens update
 template <typename T>
-void launch_gm_dot1(int64_t n, int k, const T *V, int64_t ldv, const T *w, GmState *st,
-                    double *partial, int nb, hipStream_t s);
-template <typename T>
-void launch_gm_axpy_dot2(int64_t n, int k, const T *V, int64_t ldv, T *w, GmState *st,
-                         double *partial, int nb, hipStream_t s);
-template <typename T>
-void launch_gm_axpy_norm(int64_t n, int k, T *V, int64_t ldv, const T *w, GmState *st,
-                         double *partial, int nb, hipStream_t s);
+void launch_gm_orth(int64_t n, int k, T *V, int64_t ldv, T *w, GmState *st, double *partial, hipStream_t s);
 void launch_gm_solve_y(GmState *st, hipStream_t s);
 // x += sum_j y_j Z_j (flexible GMRES solution update)
 template <typename T>
 void launch_gm_update(int64_t n, const T *Z, int64_t ldz, const GmState *st, T *x, hipStream_t s);
 // st->norms[slot] = ||x||; if rtol > 0, st->tol_abs = rtol * ||x||
 template <typename T>
-void launch_norm(int64_t n, const T *x, GmState *st, double rtol, double *partial, int nb, int slot,
-                 hipStream_t s);
+void launch_norm(int64_t n, const T *x, GmState *st, double rtol, double *partial, int slot, hipStream_t s);
 
 // vector utilities
 template <typename T>

@@ -976,25 +976,60 @@ template void launch_spmv<float>(const RowPattern &, const float *, const float 
 // ------------------------------------------------------------------ reductions
 
 
-// r = b - Ax (or b), V0 = r, beta = ||r||; initialises the cycle.
-template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_gm_start(int64_t n, const T *b, const T *Ax, T *V0, GmState *st,
-                                                          double *partial)
+// Reductions run in two kernels: the data-parallel pass writes one partial sum
+// per block (or per chunk and vector), and a one-block kernel adds them in a
+// fixed order.  Kernel boundaries order the two, so no block waits for or
+// fences against another (a device-scope fence per block is expensive on a
+// multi-die GPU), and every result is independent of scheduling.
+
+// Blocks of the elementwise passes: about four elements per thread.
+static unsigned vec_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 4096)); }
+
+int64_t gm_partial_size(int64_t n)
 {
-    __shared__ double lds[4 * 4];
-    double acc[1] = {0};
+    const int64_t nbx = (n + kDotChunk - 1) / kDotChunk;
+    return std::max<int64_t>((kMaxRestart + 1) * nbx, vec_blocks(n)) + 64;
+}
+
+// Sum of the block's per-thread values, valid in thread 0 (blockDim 256).
+__device__ inline double block_total(double v, double *lds)
+{
+    double a[1] = {v};
+    block_sum<1>(a, lds);
+    return a[0];
+}
+
+// r = b - Ax (or b), V0 = r; partial[block] = sum r^2.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gm_start(int64_t n, const T *b, const T *Ax, T *V0, double *partial)
+{
+    __shared__ double lds[4];
+    double acc = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        T r = Ax ? (T)(b[i] - Ax[i]) : b[i];
-        V0[i] = r;
-        acc[0] += to_d(r) * to_d(r);
+        const double r = Ax ? to_d(b[i]) - to_d(Ax[i]) : to_d(b[i]);
+        const T rt = (T)r;
+        V0[i] = rt;
+        acc += to_d(rt) * to_d(rt);
     }
-    block_sum<1>(acc, lds);
-    if (threadIdx.x == 0) partial[blockIdx.x] = acc[0];
-    if (!arrive_last(&st->counter)) return;
-    double tot[1];
-    reduce_partials<1>(partial, gridDim.x, 1, tot, lds);
+    const double t = block_total(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// Fixed-order sum of partial[0..nb) in one block of 256 threads (valid in thread 0).
+__device__ inline double sum_partials(const double *partial, int nb, double *lds)
+{
+    double s = 0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partial[b];
+    return block_total(s, lds);
+}
+
+// beta = ||r||: starts a cycle (g = beta e_1, V_0 scale 1/beta) or stops it.
+__global__ __launch_bounds__(256) void k_gm_start_fin(int nb, const double *partial, GmState *st)
+{
+    __shared__ double lds[4];
+    const double tot = sum_partials(partial, nb, lds);
     if (threadIdx.x == 0) {
-        double beta = sqrt(tot[0]);
+        const double beta = sqrt(tot);
         st->resid = beta;
         st->g[0] = beta;
         for (int j = 1; j <= kMaxRestart; ++j) st->g[j] = 0;
@@ -1003,112 +1038,90 @@ __global__ __launch_bounds__(kRedThreads) void k_gm_start(int64_t n, const T *b,
         st->converged = (beta <= st->tol_abs) ? 1 : 0;
         st->breakdown = (beta != beta) ? 1 : 0;
         st->done = (st->converged || st->breakdown) ? 1 : 0;
-        st->counter = 0;
     }
 }
 
 template <typename T>
-void launch_gm_start(int64_t n, const T *b, const T *Ax, T *V0, GmState *st, double *partial, int nb,
-                     hipStream_t s)
+void launch_gm_start(int64_t n, const T *b, const T *Ax, T *V0, GmState *st, double *partial, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_gm_start<T>), dim3(nb), dim3(kRedThreads), 0, s, n, b, Ax, V0, st, partial);
+    const unsigned nb = vec_blocks(n);
+    hipLaunchKernelGGL((k_gm_start<T>), dim3(nb), dim3(256), 0, s, n, b, Ax, V0, partial);
+    hipLaunchKernelGGL(k_gm_start_fin, dim3(1), dim3(256), 0, s, (int)nb, partial, st);
 }
-template void launch_gm_start<double>(int64_t, const double *, const double *, double *, GmState *, double *, int,
+template void launch_gm_start<double>(int64_t, const double *, const double *, double *, GmState *, double *,
                                       hipStream_t);
-template void launch_gm_start<float>(int64_t, const float *, const float *, float *, GmState *, double *, int,
+template void launch_gm_start<float>(int64_t, const float *, const float *, float *, GmState *, double *,
                                      hipStream_t);
 
-// h1_j = <V_j, w>, j = 0..k  (V_j = s_j Vhat_j)
-template <typename T, int K>
-__global__ __launch_bounds__(kRedThreads) void k_gm_dot1(int64_t n, int k, const T *V, int64_t ldv, const T *w,
-                                                         GmState *st, double *partial)
+// partial[j * gridDim.x + bx] = <Vhat_j, w> over chunk bx, j = blockIdx.y.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gm_dot(int64_t n, const T *V, int64_t ldv, const T *w, double *partial,
+                                                const GmState *st)
 {
     if (st->done) return;
-    __shared__ double lds[4 * K];
-    double acc[K];
+    __shared__ double lds[4];
+    const T *v = V + (int64_t)blockIdx.y * ldv;
+    const int64_t i0 = (int64_t)blockIdx.x * kDotChunk;
+    const int64_t i1 = i0 + kDotChunk < n ? i0 + kDotChunk : n;
+    double acc = 0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) acc += to_d(v[i]) * to_d(w[i]);
+    const double t = block_total(acc, lds);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+}
+
+// dot_j = sum_b partial[j][b] (fixed order, one wavefront per j); with V_j =
+// s_j Vhat_j: mode 0 h1_j = s_j dot_j; mode 1 h2_j = s_j dot_j, H[j][k] = h1_j + h2_j
+// and h1 <- h2 for the second update.
+__global__ __launch_bounds__(256) void k_gm_fin_dot(int k, int nbx, const double *partial, GmState *st, int mode)
+{
+    if (st->done) return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int j = wid; j <= k; j += 4) {
+        double s = 0;
+        for (int b = lane; b < nbx; b += 64) s += partial[(int64_t)j * nbx + b];
 #pragma unroll
-    for (int j = 0; j < K; ++j) acc[j] = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double wi = to_d(w[i]);
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (j <= k) acc[j] += to_d(V[j * ldv + i]) * wi;
-    }
-    block_sum<K>(acc, lds);
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int j = 0; j < K; ++j) partial[(int64_t)blockIdx.x * K + j] = acc[j];
-    if (!arrive_last(&st->counter)) return;
-    double tot[K];
-    reduce_partials<K>(partial, gridDim.x, k + 1, tot, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (j <= k) st->h1[j] = tot[j] * st->s[j];
-        st->counter = 0;
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) {
+            const double h = s * st->s[j];
+            if (mode == 0) {
+                st->h1[j] = h;
+            } else {
+                st->H[j * kMaxRestart + k] = st->h1[j] + h;
+                st->h1[j] = h;
+            }
+        }
     }
 }
 
-// w -= sum_j h1_j V_j ; h2_j = <V_j, w>; H[j][k] = h1_j + h2_j
+// w -= sum_j h1_j V_j  (= sum_j h1_j s_j Vhat_j)
 template <typename T, int K>
-__global__ __launch_bounds__(kRedThreads) void k_gm_axpy_dot2(int64_t n, int k, const T *V, int64_t ldv, T *w,
-                                                              GmState *st, double *partial)
+__global__ __launch_bounds__(256) void k_gm_axpy(int64_t n, int k, const T *V, int64_t ldv, T *w, const GmState *st)
 {
     if (st->done) return;
-    __shared__ double lds[4 * K];
     __shared__ double coef[K];
     if (threadIdx.x < K) coef[threadIdx.x] = (threadIdx.x <= (unsigned)k) ? st->h1[threadIdx.x] * st->s[threadIdx.x] : 0.0;
     __syncthreads();
-    double acc[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) acc[j] = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        T vj[K];
         double wi = to_d(w[i]);
 #pragma unroll
         for (int j = 0; j < K; ++j)
-            if (j <= k) {
-                vj[j] = V[j * ldv + i];
-                wi -= coef[j] * to_d(vj[j]);
-            }
-        const T wt = (T)wi;
-        w[i] = wt;
-        const double wd = to_d(wt);
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (j <= k) acc[j] += to_d(vj[j]) * wd;
-    }
-    block_sum<K>(acc, lds);
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int j = 0; j < K; ++j) partial[(int64_t)blockIdx.x * K + j] = acc[j];
-    if (!arrive_last(&st->counter)) return;
-    double tot[K];
-    reduce_partials<K>(partial, gridDim.x, k + 1, tot, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (j <= k) {
-                double h2 = tot[j] * st->s[j];
-                st->H[j * kMaxRestart + k] = st->h1[j] + h2;
-                st->h1[j] = h2;   // h2 kept for the second update
-            }
-        st->counter = 0;
+            if (j <= k) wi -= coef[j] * to_d(V[j * ldv + i]);
+        w[i] = (T)wi;
     }
 }
 
-// Vhat_{k+1} = w - sum_j h2_j V_j ; then Givens update of column k.
+// Vhat_{k+1} = w - sum_j h2_j V_j; partial[block] = sum Vhat_{k+1}^2
 template <typename T, int K>
-__global__ __launch_bounds__(kRedThreads) void k_gm_axpy_norm(int64_t n, int k, T *V, int64_t ldv, const T *w,
-                                                              GmState *st, double *partial)
+__global__ __launch_bounds__(256) void k_gm_axpy_norm(int64_t n, int k, T *V, int64_t ldv, const T *w,
+                                                      const GmState *st, double *partial)
 {
     if (st->done) return;
-    __shared__ double lds[4 * 4];
     __shared__ double coef[K];
+    __shared__ double lds[4];
     if (threadIdx.x < K) coef[threadIdx.x] = (threadIdx.x <= (unsigned)k) ? st->h1[threadIdx.x] * st->s[threadIdx.x] : 0.0;
     __syncthreads();
-    double acc[1] = {0};
     T *Vn = V + (int64_t)(k + 1) * ldv;
+    double acc = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double wi = to_d(w[i]);
 #pragma unroll
@@ -1116,88 +1129,79 @@ __global__ __launch_bounds__(kRedThreads) void k_gm_axpy_norm(int64_t n, int k, 
             if (j <= k) wi -= coef[j] * to_d(V[j * ldv + i]);
         const T wt = (T)wi;
         Vn[i] = wt;
-        acc[0] += to_d(wt) * to_d(wt);
+        acc += to_d(wt) * to_d(wt);
     }
-    block_sum<1>(acc, lds);
-    if (threadIdx.x == 0) partial[blockIdx.x] = acc[0];
-    if (!arrive_last(&st->counter)) return;
-    double tot[1];
-    reduce_partials<1>(partial, gridDim.x, 1, tot, lds);
-    if (threadIdx.x == 0) {
-        const int M = kMaxRestart;
-        double *H = st->H;
-        const double hn = sqrt(tot[0]);
-        H[(k + 1) * M + k] = hn;
-        for (int j = 0; j < k; ++j) {
-            double t = st->cs[j] * H[j * M + k] + st->sn[j] * H[(j + 1) * M + k];
-            H[(j + 1) * M + k] = -st->sn[j] * H[j * M + k] + st->cs[j] * H[(j + 1) * M + k];
-            H[j * M + k] = t;
-        }
-        const double a = H[k * M + k];
-        const double r = hypot(a, hn);
-        const double c = (r > 0) ? a / r : 1.0, sn = (r > 0) ? hn / r : 0.0;
-        st->cs[k] = c;
-        st->sn[k] = sn;
-        H[k * M + k] = r;
-        H[(k + 1) * M + k] = 0.0;
-        st->g[k + 1] = -sn * st->g[k];
-        st->g[k] = c * st->g[k];
-        st->s[k + 1] = hn > 0 ? 1.0 / hn : 0.0;
-        const double res = fabs(st->g[k + 1]);
-        st->resid = res;
-        st->kused = k + 1;
-        const bool bad = !(res == res) || !(r > 0);
-        st->breakdown = bad ? 1 : 0;
-        st->converged = (!bad && res <= st->tol_abs) ? 1 : 0;
-        // a zero new direction means the Krylov space is invariant: the solution is exact
-        if (!bad && hn == 0.0) st->converged = 1;
-        st->done = (st->converged || bad) ? 1 : 0;
-        st->counter = 0;
-    }
+    const double t = block_total(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-#define LX_GM_DISPATCH(KERNEL, T, ...)                                                                         \
+// H[k+1][k] = ||Vhat_{k+1}||, Givens update of column k, convergence test.
+__global__ __launch_bounds__(256) void k_gm_givens(int k, int nb, const double *partial, GmState *st)
+{
+    if (st->done) return;
+    __shared__ double lds[4];
+    const double tot = sum_partials(partial, nb, lds);
+    if (threadIdx.x != 0) return;
+    const int M = kMaxRestart;
+    double *H = st->H;
+    const double hn = sqrt(tot);
+    H[(k + 1) * M + k] = hn;
+    for (int j = 0; j < k; ++j) {
+        const double t = st->cs[j] * H[j * M + k] + st->sn[j] * H[(j + 1) * M + k];
+        H[(j + 1) * M + k] = -st->sn[j] * H[j * M + k] + st->cs[j] * H[(j + 1) * M + k];
+        H[j * M + k] = t;
+    }
+    const double a = H[k * M + k];
+    const double r = hypot(a, hn);
+    const double c = (r > 0) ? a / r : 1.0, sn = (r > 0) ? hn / r : 0.0;
+    st->cs[k] = c;
+    st->sn[k] = sn;
+    H[k * M + k] = r;
+    H[(k + 1) * M + k] = 0.0;
+    st->g[k + 1] = -sn * st->g[k];
+    st->g[k] = c * st->g[k];
+    st->s[k + 1] = hn > 0 ? 1.0 / hn : 0.0;
+    const double res = fabs(st->g[k + 1]);
+    st->resid = res;
+    st->kused = k + 1;
+    const bool bad = !(res == res) || !(r > 0);
+    st->breakdown = bad ? 1 : 0;
+    st->converged = (!bad && res <= st->tol_abs) ? 1 : 0;
+    // a zero new direction means the Krylov space is invariant: the solution is exact
+    if (!bad && hn == 0.0) st->converged = 1;
+    st->done = (st->converged || bad) ? 1 : 0;
+}
+
+#define LX_GM_K_DISPATCH(KERNEL, T, grid, ...)                                                                \
     do {                                                                                                       \
         if (k + 1 <= 8)                                                                                        \
-            hipLaunchKernelGGL((KERNEL<T, 8>), dim3(nb), dim3(kRedThreads), 0, s, __VA_ARGS__);               \
+            hipLaunchKernelGGL((KERNEL<T, 8>), grid, dim3(256), 0, s, __VA_ARGS__);                           \
         else if (k + 1 <= 16)                                                                                  \
-            hipLaunchKernelGGL((KERNEL<T, 16>), dim3(nb), dim3(kRedThreads), 0, s, __VA_ARGS__);              \
+            hipLaunchKernelGGL((KERNEL<T, 16>), grid, dim3(256), 0, s, __VA_ARGS__);                          \
         else if (k + 1 <= 32)                                                                                  \
-            hipLaunchKernelGGL((KERNEL<T, 32>), dim3(nb), dim3(kRedThreads), 0, s, __VA_ARGS__);              \
+            hipLaunchKernelGGL((KERNEL<T, 32>), grid, dim3(256), 0, s, __VA_ARGS__);                          \
         else                                                                                                   \
-            hipLaunchKernelGGL((KERNEL<T, 64>), dim3(nb), dim3(kRedThreads), 0, s, __VA_ARGS__);              \
+            hipLaunchKernelGGL((KERNEL<T, 64>), grid, dim3(256), 0, s, __VA_ARGS__);                          \
     } while (0)
 
+// One Arnoldi step's classical Gram-Schmidt with reorthogonalisation (CGS2) of
+// w against Vhat_0..Vhat_k, then Vhat_{k+1} and the Givens update.
 template <typename T>
-void launch_gm_dot1(int64_t n, int k, const T *V, int64_t ldv, const T *w, GmState *st, double *partial, int nb,
-                    hipStream_t s)
+void launch_gm_orth(int64_t n, int k, T *V, int64_t ldv, T *w, GmState *st, double *partial, hipStream_t s)
 {
-    LX_GM_DISPATCH(k_gm_dot1, T, n, k, V, ldv, w, st, partial);
+    const int nbx = (int)((n + kDotChunk - 1) / kDotChunk);
+    const unsigned nbv = vec_blocks(n);
+    const dim3 gd(nbx, k + 1), gv(nbv);
+    hipLaunchKernelGGL((k_gm_dot<T>), gd, dim3(256), 0, s, n, V, ldv, w, partial, st);
+    hipLaunchKernelGGL(k_gm_fin_dot, dim3(1), dim3(256), 0, s, k, nbx, partial, st, 0);
+    LX_GM_K_DISPATCH(k_gm_axpy, T, gv, n, k, V, ldv, w, st);
+    hipLaunchKernelGGL((k_gm_dot<T>), gd, dim3(256), 0, s, n, V, ldv, w, partial, st);
+    hipLaunchKernelGGL(k_gm_fin_dot, dim3(1), dim3(256), 0, s, k, nbx, partial, st, 1);
+    LX_GM_K_DISPATCH(k_gm_axpy_norm, T, gv, n, k, V, ldv, w, st, partial);
+    hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(256), 0, s, k, (int)nbv, partial, st);
 }
-template <typename T>
-void launch_gm_axpy_dot2(int64_t n, int k, const T *V, int64_t ldv, T *w, GmState *st, double *partial, int nb,
-                         hipStream_t s)
-{
-    LX_GM_DISPATCH(k_gm_axpy_dot2, T, n, k, V, ldv, w, st, partial);
-}
-template <typename T>
-void launch_gm_axpy_norm(int64_t n, int k, T *V, int64_t ldv, const T *w, GmState *st, double *partial, int nb,
-                         hipStream_t s)
-{
-    LX_GM_DISPATCH(k_gm_axpy_norm, T, n, k, V, ldv, w, st, partial);
-}
-template void launch_gm_dot1<double>(int64_t, int, const double *, int64_t, const double *, GmState *, double *,
-                                     int, hipStream_t);
-template void launch_gm_dot1<float>(int64_t, int, const float *, int64_t, const float *, GmState *, double *, int,
-                                    hipStream_t);
-template void launch_gm_axpy_dot2<double>(int64_t, int, const double *, int64_t, double *, GmState *, double *,
-                                          int, hipStream_t);
-template void launch_gm_axpy_dot2<float>(int64_t, int, const float *, int64_t, float *, GmState *, double *, int,
-                                         hipStream_t);
-template void launch_gm_axpy_norm<double>(int64_t, int, double *, int64_t, const double *, GmState *, double *,
-                                          int, hipStream_t);
-template void launch_gm_axpy_norm<float>(int64_t, int, float *, int64_t, const float *, GmState *, double *, int,
-                                         hipStream_t);
+template void launch_gm_orth<double>(int64_t, int, double *, int64_t, double *, GmState *, double *, hipStream_t);
+template void launch_gm_orth<float>(int64_t, int, float *, int64_t, float *, GmState *, double *, hipStream_t);
 
 // y = H^{-1} g over the kused columns (back substitution).
 __global__ void k_gm_solve_y(GmState *st)
@@ -1243,32 +1247,35 @@ template void launch_gm_update<double>(int64_t, const double *, int64_t, const G
 template void launch_gm_update<float>(int64_t, const float *, int64_t, const GmState *, float *, hipStream_t);
 
 template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_norm(int64_t n, const T *x, GmState *st, double rtol,
-                                                      double *partial, int slot)
+__global__ __launch_bounds__(256) void k_sumsq(int64_t n, const T *x, double *partial)
 {
-    __shared__ double lds[4 * 4];
-    double acc[1] = {0};
+    __shared__ double lds[4];
+    double acc = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        acc[0] += to_d(x[i]) * to_d(x[i]);
-    block_sum<1>(acc, lds);
-    if (threadIdx.x == 0) partial[blockIdx.x] = acc[0];
-    if (!arrive_last(&st->counter)) return;
-    double tot[1];
-    reduce_partials<1>(partial, gridDim.x, 1, tot, lds);
+        acc += to_d(x[i]) * to_d(x[i]);
+    const double t = block_total(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_norm_fin(int nb, const double *partial, GmState *st, double rtol, int slot)
+{
+    __shared__ double lds[4];
+    const double tot = sum_partials(partial, nb, lds);
     if (threadIdx.x == 0) {
-        st->norms[slot] = sqrt(tot[0]);
+        st->norms[slot] = sqrt(tot);
         if (rtol > 0) st->tol_abs = rtol * st->norms[slot];
-        st->counter = 0;
     }
 }
 
 template <typename T>
-void launch_norm(int64_t n, const T *x, GmState *st, double rtol, double *partial, int nb, int slot, hipStream_t s)
+void launch_norm(int64_t n, const T *x, GmState *st, double rtol, double *partial, int slot, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_norm<T>), dim3(nb), dim3(kRedThreads), 0, s, n, x, st, rtol, partial, slot);
+    const unsigned nb = vec_blocks(n);
+    hipLaunchKernelGGL((k_sumsq<T>), dim3(nb), dim3(256), 0, s, n, x, partial);
+    hipLaunchKernelGGL(k_norm_fin, dim3(1), dim3(256), 0, s, (int)nb, partial, st, rtol, slot);
 }
-template void launch_norm<double>(int64_t, const double *, GmState *, double, double *, int, int, hipStream_t);
-template void launch_norm<float>(int64_t, const float *, GmState *, double, double *, int, int, hipStream_t);
+template void launch_norm<double>(int64_t, const double *, GmState *, double, double *, int, hipStream_t);
+template void launch_norm<float>(int64_t, const float *, GmState *, double, double *, int, hipStream_t);
 
 // ------------------------------------------------------------------ vector utilities
 

@@ -90,6 +90,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     } else {
         if (sv->f_degree < 0 || sv->f_degree > 8) return fail(LX_EINVAL, "f_degree must be 0..8");
         if (sv->amg_degree < 0 || sv->amg_degree > 8) return fail(LX_EINVAL, "amg_degree must be 0..8");
+        if (sv->amg_cycle < 0 || sv->amg_cycle > 3) return fail(LX_EINVAL, "amg_cycle must be 0..3");
         if (sv->f_ratio != 0.0 && !(sv->f_ratio > 1.0)) return fail(LX_EINVAL, "f_ratio must be 0 or > 1");
         if (sv->amg_ratio != 0.0 && !(sv->amg_ratio > 1.0)) return fail(LX_EINVAL, "amg_ratio must be 0 or > 1");
     }
@@ -99,8 +100,9 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     if (solver.precond == LX_PC_AMG) {
         if (solver.f_degree == 0) solver.f_degree = 3;
         if (solver.amg_degree == 0) solver.amg_degree = 2;
-        if (solver.f_ratio == 0.0) solver.f_ratio = 10.0;
+        if (solver.f_ratio == 0.0) solver.f_ratio = 5.0;
         if (solver.amg_ratio == 0.0) solver.amg_ratio = 30.0;
+        if (solver.amg_cycle == 0) solver.amg_cycle = 2;
     }
     for (int i = 0; i < pr->n_bc; ++i) {
         BCDesc b;
@@ -230,7 +232,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     const int m = solver.restart;
     nb_red = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (N + 2047) / 2048));
     ALLOC(d_st, sizeof(GmState));
-    ALLOC(d_partial, sizeof(double) * nb_red * 64);
+    ALLOC(d_partial, sizeof(double) * std::max<int64_t>((int64_t)nb_red * 64, gm_partial_size(N)));
     LX_HIP(hipHostMalloc((void **)&h_st, sizeof(GmState), hipHostMallocDefault));
     if (solver.precision == LX_FP64) {
         ALLOC(d_val64, sizeof(double) * kPlanes * nblk);
@@ -328,6 +330,7 @@ lx_status Sim::setup_amg(Amg<T> &A)
     A.f_degree = solver.f_degree;
     A.f_ratio = solver.f_ratio;
     A.f_warm = false;
+    A.cycle = solver.amg_cycle;
     const char *env = getenv("LXNS_AMG_LPR");
     const int lpr_env = env ? atoi(env) : 0;
     int64_t maxgrid = (nv * 16 + 255) / 256;
@@ -349,7 +352,7 @@ lx_status Sim::setup_amg(Amg<T> &A)
         L.n = H.n;
         L.nnz = (int64_t)H.col.size();
         const double avg = (double)L.nnz / (double)std::max<int64_t>(L.n, 1);
-        L.lpr = avg >= 40 ? 32 : avg >= 12 ? 16 : avg >= 6 ? 8 : 4;
+        L.lpr = avg >= 12 ? 16 : avg >= 6 ? 8 : 4;
         if (lpr_env == 4 || lpr_env == 8 || lpr_env == 16 || lpr_env == 32) L.lpr = lpr_env;
         maxgrid = std::max<int64_t>(maxgrid, (L.n * L.lpr + 255) / 256);
         CK(up(L.rowptr, H.rowptr));
@@ -386,6 +389,11 @@ lx_status Sim::setup_amg(Amg<T> &A)
     CK(vec(A.fd1, 4 * nv));
     CK(vec(A.fv, 4 * nv));
 #undef CK
+    if (const char *v = getenv("LXNS_VERBOSE"))
+        if (*v && *v != '0')
+            for (int l = 0; l < nl; ++l)
+                fprintf(stderr, "[lxns] AMG level %d%s: %lld rows, %lld entries, lanes/row %d\n", l,
+                        l == A.nlev ? " (dense)" : "", (long long)A.L[l].n, (long long)A.L[l].nnz, A.L[l].lpr);
     LX_HIP(hipMemsetAsync(A.lam, 0, sizeof(double) * kLamSlots, stream));
     LX_HIP(hipMemsetAsync(A.counter, 0, sizeof(uint32_t) * 4, stream));
     launch_fill<T>(4 * nv, A.fr, T(0), stream);
@@ -512,17 +520,17 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
                        solver.schur_ratio, Ops<T>::sw(this), d_st};
     const int m = solver.restart;
     const int64_t ld = N;
-    launch_norm<T>(N, b, d_st, rtol, d_partial, nb_red, 0, stream);
+    launch_norm<T>(N, b, d_st, rtol, d_partial, 0, stream);
     if (x_zero) launch_fill<T>(N, x, T(0), stream);
     int it = 0;
     res = GmResult();
     for (int cycle = 0;; ++cycle) {
         if (x_zero && cycle == 0) {
-            launch_gm_start<T>(N, b, nullptr, V, d_st, d_partial, nb_red, stream);
+            launch_gm_start<T>(N, b, nullptr, V, d_st, d_partial, stream);
         } else {
             auto *tm = timer_begin(0, -1, false);
             launch_spmv<T>(P, val, x, w, nullptr, stream, tm ? tm->first : nullptr, tm ? tm->second : nullptr);
-            launch_gm_start<T>(N, b, w, V, d_st, d_partial, nb_red, stream);
+            launch_gm_start<T>(N, b, w, V, d_st, d_partial, stream);
         }
         const int kmax = std::min(m, max_iters - it);
         for (int k = 0; k < kmax; ++k) {
@@ -534,9 +542,7 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
                 launch_simple_apply<T>(P, SP, V + k * ld, &d_st->s[k], zk, &d_st->done, stream);
             auto *tm = timer_begin(0, k, false);
             launch_spmv<T>(P, val, zk, w, &d_st->done, stream, tm ? tm->first : nullptr, tm ? tm->second : nullptr);
-            launch_gm_dot1<T>(N, k, V, ld, w, d_st, d_partial, nb_red, stream);
-            launch_gm_axpy_dot2<T>(N, k, V, ld, w, d_st, d_partial, nb_red, stream);
-            launch_gm_axpy_norm<T>(N, k, V, ld, w, d_st, d_partial, nb_red, stream);
+            launch_gm_orth<T>(N, k, V, ld, w, d_st, d_partial, stream);
         }
         LX_HIP(hipGetLastError());
         lx_status s = read_state();
@@ -577,7 +583,7 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
         if (it >= max_iters && !h_st->converged) {
             // final true residual
             launch_spmv<T>(P, val, x, w, nullptr, stream);
-            launch_gm_start<T>(N, b, w, V, d_st, d_partial, nb_red, stream);
+            launch_gm_start<T>(N, b, w, V, d_st, d_partial, stream);
             s = read_state();
             if (s != LX_OK) return s;
             res.iters = it;
@@ -775,8 +781,8 @@ lx_status Sim::step(lx_step_stats *out)
         // FP32 matrix and inner GMRES inside FP64 iterative refinement
         st = residual64(C, d_xs, true, t1);
         if (st != LX_OK) return st;
-        launch_norm<double>(N, d_b64, d_st, 0.0, d_partial, nb_red, 1, stream);
-        launch_norm<double>(N, d_r64, d_st, 0.0, d_partial, nb_red, 2, stream);
+        launch_norm<double>(N, d_b64, d_st, 0.0, d_partial, 1, stream);
+        launch_norm<double>(N, d_r64, d_st, 0.0, d_partial, 2, stream);
         st = read_state();
         if (st != LX_OK) return st;
         const double bnorm = h_st->norms[1] > 0 ? h_st->norms[1] : 1.0;
@@ -797,7 +803,7 @@ lx_status Sim::step(lx_step_stats *out)
             ++ir;
             st = residual64(C, d_xs, false, t1);
             if (st != LX_OK) return st;
-            launch_norm<double>(N, d_r64, d_st, 0.0, d_partial, nb_red, 2, stream);
+            launch_norm<double>(N, d_r64, d_st, 0.0, d_partial, 2, stream);
             st = read_state();
             if (st != LX_OK) return st;
             if (verbose())

@@ -76,7 +76,7 @@ class lx_solver(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("restart", c_i32), ("max_iters", c_i32), ("max_ir", c_i32),
                 ("rtol", c_dbl), ("ir_rtol", c_dbl), ("inner_rtol", c_dbl), ("deterministic", c_i32),
                 ("collect_timing", c_i32), ("schur_degree", c_i32), ("asm_fp64", c_i32), ("schur_ratio", c_dbl),
-                ("precond", c_i32), ("f_degree", c_i32), ("amg_degree", c_i32), ("pad", c_i32), ("f_ratio", c_dbl),
+                ("precond", c_i32), ("f_degree", c_i32), ("amg_degree", c_i32), ("amg_cycle", c_i32), ("f_ratio", c_dbl),
                 ("amg_ratio", c_dbl)]
 
 
@@ -246,6 +246,7 @@ class _Marshal:
         s.precond = PRECOND[getattr(solver, "precond", "amg")]
         s.f_degree = int(getattr(solver, "f_degree", 0))
         s.amg_degree = int(getattr(solver, "amg_degree", 0))
+        s.amg_cycle = int(getattr(solver, "amg_cycle", 0))
         s.f_ratio = float(getattr(solver, "f_ratio", 0.0))
         s.amg_ratio = float(getattr(solver, "amg_ratio", 0.0))
         self.solver = s
