@@ -173,7 +173,9 @@ enum { LX_PC_AMG = 0, LX_PC_CHEB_SCHUR = 1 };
 typedef struct {
     int32_t precision, restart, max_iters, max_ir;
     double rtol, ir_rtol, inner_rtol;
-    int32_t deterministic;   /* reserved; the scatter uses device atomics          */
+    int32_t deterministic;   /* reserved: the assembly gathers element records in
+                                a fixed order (no atomics) and every reduction
+                                has a fixed order already                          */
     int32_t collect_timing;  /* 1: record per-kernel HIP events (SpMV, assembly)   */
     int32_t schur_degree;    /* 0..32                                               */
     int32_t asm_fp64;        /* LX_FP32_IR only: 1 = build the FP32 matrix by FP64

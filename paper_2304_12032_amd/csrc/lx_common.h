@@ -88,6 +88,8 @@ struct HostSetup {
     std::vector<int32_t> diag;      // [nv] slot of the diagonal block
     std::vector<int32_t> tslot;     // [nblk] slot of the transposed block
     std::vector<int32_t> eslot;     // [16][nt] slot of block (a,b), index (4a+b)*nt + e
+    std::vector<int32_t> sinc_ptr;  // [nblk+1] incidence of each slot ...
+    std::vector<int32_t> sinc;      // [16 nt]  ... as codes 16 e + 4a + b, by element then (a, b)
     double hmin = 0;
 };
 

@@ -11,11 +11,16 @@ namespace lx {
 // C.  Vectors are [nv][4] = (u_x, u_y, u_z, p) per vertex.
 constexpr int kPlanes = 16;
 
+// Per-element record written by the element pass of the P1 assembly and read
+// by the slot gather (kRec values of T per element).
+constexpr int kRec = 72;
+
 template <typename T>
 struct AsmArgs {
     int64_t nt, nblk;
     const int32_t *tet;    // [4][nt]
-    const int32_t *eslot;  // [16][nt]
+    const int32_t *sinc_ptr, *sinc;   // slot incidence (codes 16 e + 4a + b)
+    T *rec;                // [nt][kRec] element records
     const double *x;       // [nv][3] current coordinates
     const double *xh;      // [nv][3] reference coordinates
     const double *h0, *h1, *h2;  // history levels [nv][4]

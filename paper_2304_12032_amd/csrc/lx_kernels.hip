@@ -11,12 +11,12 @@
 //
 // Unlike a per-entry evaluation, the P1 assembly accumulates a handful of
 // per-element moments over the quadrature points (X_ab, Y_bc, Z_a, W_c, S_b,
-// sum tau_M, sum tau_C and three right-hand-side moments) and expands the 16
-// blocks of the element matrix from them: for P1 every basis gradient is
-// constant on the element, so each stabilised entry factors into a gradient
-// product times a quadrature sum.  That keeps the element in registers with
-// one thread per element; the 16 blocks are added into the block-CSR planes
-// with hardware floating-point atomics.
+// sum tau_M, sum tau_C and three right-hand-side moments): for P1 every basis
+// gradient is constant on the element, so each stabilised entry factors into
+// a gradient product times a quadrature sum.  One thread per element writes
+// these moments as a small record; a second pass, one thread per block of the
+// pattern, expands and sums the records of the elements sharing that block in
+// a fixed order, so the matrix is built without atomics and deterministically.
 #include <hip/hip_ext.h>
 
 #include <cstdlib>
@@ -223,8 +223,26 @@ __device__ inline void eval_qp(const Elem<T> &E, int q, const StepCoef &C, QP<T>
 
 // ------------------------------------------------------------------ assembly
 
+// Record layout (offsets into the kRec values of an element)
+enum : int {
+    kRDphi = 0,   // grad phi_a [4][3]
+    kRX = 12,     // X_ab + mu|K| grad phi_a . grad phi_b  [4][4]
+    kRY = 28,     // Y_b,c [4][3]
+    kRZ = 40,     // Z_a [4]
+    kRS = 44,     // S_b [4]
+    kRW = 48,     // W_c [3]
+    kRTC = 51,    // sum w tau_C
+    kRTM = 52,    // sum w tau_M
+    kRMV = 53,    // mu |K|
+    kRW1 = 54,    // |K| / 4
+    kRRhs = 55    // right-hand side [4][4] (u_x, u_y, u_z, p) of each vertex
+};
+static_assert(kRRhs + 16 <= kRec, "element record too small");
+
+// Element pass of the assembly: one thread per element evaluates the quadrature
+// moments and writes the element's record.
 template <typename T, bool RHS>
-__global__ __launch_bounds__(256) void k_assemble_p1(AsmArgs<T> A, StepCoef C)
+__global__ __launch_bounds__(256) void k_element_p1(AsmArgs<T> A, StepCoef C)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= A.nt) return;
@@ -288,51 +306,117 @@ __global__ __launch_bounds__(256) void k_assemble_p1(AsmArgs<T> A, StepCoef C)
         }
     }
     const T mv = (T)C.mu * E.vol;
-    const T w1 = E.vol * T(0.25);   // integral of one basis function
-    T *val = A.val;
-    const int64_t nb = A.nblk;
+    T *R = A.rec + (int64_t)e * kRec;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) R[kRDphi + 3 * a + d] = E.dphi[a][d];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const T gab = E.dphi[a][0] * E.dphi[b][0] + E.dphi[a][1] * E.dphi[b][1] + E.dphi[a][2] * E.dphi[b][2];
+            R[kRX + 4 * a + b] = X[a][b] + mv * gab;
+        }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int64_t slot = A.eslot[(int64_t)(4 * a + b) * A.nt + e];
-            const T gab = E.dphi[a][0] * E.dphi[b][0] + E.dphi[a][1] * E.dphi[b][1] + E.dphi[a][2] * E.dphi[b][2];
-            const T xab = X[a][b] + mv * gab;
+        for (int c = 0; c < 3; ++c) R[kRY + 3 * a + c] = Y[a][c];
+        R[kRZ + a] = Z[a];
+        R[kRS + a] = S[a];
+    }
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 3; ++c) R[kRW + c] = W[c];
+    R[kRTC] = TC;
+    R[kRTM] = TM;
+    R[kRMV] = mv;
+    R[kRW1] = E.vol * T(0.25);   // integral of one basis function
+    if (RHS) {
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    T F = E.dphi[a][d] * Y[b][c] + TC * E.dphi[a][c] * E.dphi[b][d];
-                    if (c == d) F += xab;
-                    if (C.symgrad) F += mv * E.dphi[b][c] * E.dphi[a][d];
-                    atomic_add(&val[(3 * c + d) * nb + slot], F);
-                }
-                T G = -w1 * E.dphi[a][c] + E.dphi[b][c] * Z[a] + gab * W[c];
-                atomic_add(&val[(9 + c) * nb + slot], G);
-                T B = w1 * E.dphi[b][c] + E.dphi[a][c] * S[b];
-                atomic_add(&val[(12 + c) * nb + slot], B);
-            }
-            atomic_add(&val[15 * nb + slot], TM * gab);
-        }
-        if (RHS) {
-            T *r = A.rhs + 4 * (int64_t)E.v[a];
+        for (int a = 0; a < 4; ++a) {
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                atomic_add(&r[c], KP[a][c] + KW[c][0] * E.dphi[a][0] + KW[c][1] * E.dphi[a][1] +
-                                      KW[c][2] * E.dphi[a][2]);
-            atomic_add(&r[3], KT[0] * E.dphi[a][0] + KT[1] * E.dphi[a][1] + KT[2] * E.dphi[a][2]);
+                R[kRRhs + 4 * a + c] = KP[a][c] + KW[c][0] * E.dphi[a][0] + KW[c][1] * E.dphi[a][1] +
+                                       KW[c][2] * E.dphi[a][2];
+            R[kRRhs + 4 * a + 3] = KT[0] * E.dphi[a][0] + KT[1] * E.dphi[a][1] + KT[2] * E.dphi[a][2];
         }
+    }
+}
+
+// Slot pass: every block (i, j) of the pattern sums, in the fixed order of its
+// incidence list, the 4x4 block (a, b) of each element containing the edge
+// (i, j), expanded from the element's record:
+//   F_cd = dphi_a,d Y_b,c + tau_C dphi_a,c dphi_b,d + [c = d] X_ab (+ mu|K| dphi_b,c dphi_a,d)
+//   G_c  = -|K|/4 dphi_a,c + dphi_b,c Z_a + (dphi_a . dphi_b) W_c
+//   B_c  =  |K|/4 dphi_b,c + dphi_a,c S_b
+//   C    = (sum tau_M w) (dphi_a . dphi_b)
+// Sums run in FP64 and each plane entry is written once (no atomics).  With
+// RHS, the diagonal slot of vertex i also gathers the vertex's right-hand side.
+template <typename T, bool RHS>
+__global__ __launch_bounds__(256) void k_gather_p1(AsmArgs<T> A, int symgrad)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.nblk) return;
+    double acc[16];
+#pragma unroll
+    for (int p = 0; p < 16; ++p) acc[p] = 0;
+    double racc[4] = {0, 0, 0, 0};
+    int32_t vrow = -1;
+    for (int32_t q = A.sinc_ptr[k]; q < A.sinc_ptr[k + 1]; ++q) {
+        const int32_t code = A.sinc[q];
+        const int64_t e = code >> 4;
+        const int a = (code >> 2) & 3, b = code & 3;
+        const T *R = A.rec + e * kRec;
+        double da[3], db[3], Yb[3], W[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            da[c] = R[kRDphi + 3 * a + c];
+            db[c] = R[kRDphi + 3 * b + c];
+            Yb[c] = R[kRY + 3 * b + c];
+            W[c] = R[kRW + c];
+        }
+        const double Xab = R[kRX + 4 * a + b], Za = R[kRZ + a], Sb = R[kRS + b];
+        const double TC = R[kRTC], TM = R[kRTM], w1 = R[kRW1];
+        const double mv = symgrad ? (double)R[kRMV] : 0.0;
+        const double gab = da[0] * db[0] + da[1] * db[1] + da[2] * db[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                double F = da[d] * Yb[c] + TC * da[c] * db[d] + mv * db[c] * da[d];
+                if (c == d) F += Xab;
+                acc[3 * c + d] += F;
+            }
+            acc[9 + c] += -w1 * da[c] + db[c] * Za + gab * W[c];
+            acc[12 + c] += w1 * db[c] + da[c] * Sb;
+        }
+        acc[15] += TM * gab;
+        if (RHS && a == b) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) racc[c] += R[kRRhs + 4 * a + c];
+            vrow = A.tet[(int64_t)a * A.nt + e];
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 16; ++p) A.val[(int64_t)p * A.nblk + k] = (T)acc[p];
+    if (RHS && vrow >= 0) {
+        T *r = A.rhs + 4 * (int64_t)vrow;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) r[c] = (T)racc[c];
     }
 }
 
 template <typename T>
 void launch_assemble_p1(const AsmArgs<T> &a, const StepCoef &c, hipStream_t s)
 {
-    dim3 grid((unsigned)((a.nt + 255) / 256));
-    if (a.rhs)
-        hipLaunchKernelGGL((k_assemble_p1<T, true>), grid, dim3(256), 0, s, a, c);
-    else
-        hipLaunchKernelGGL((k_assemble_p1<T, false>), grid, dim3(256), 0, s, a, c);
+    const dim3 ge((unsigned)((a.nt + 255) / 256)), gs((unsigned)((a.nblk + 255) / 256));
+    if (a.rhs) {
+        hipLaunchKernelGGL((k_element_p1<T, true>), ge, dim3(256), 0, s, a, c);
+        hipLaunchKernelGGL((k_gather_p1<T, true>), gs, dim3(256), 0, s, a, c.symgrad);
+    } else {
+        hipLaunchKernelGGL((k_element_p1<T, false>), ge, dim3(256), 0, s, a, c);
+        hipLaunchKernelGGL((k_gather_p1<T, false>), gs, dim3(256), 0, s, a, c.symgrad);
+    }
 }
 template void launch_assemble_p1<double>(const AsmArgs<double> &, const StepCoef &, hipStream_t);
 template void launch_assemble_p1<float>(const AsmArgs<float> &, const StepCoef &, hipStream_t);

@@ -73,7 +73,8 @@ int64_t estimate_footprint(const Request &r)
     const int64_t N = 4 * nv;
     int64_t b = 0;
     b += nblk * (16 * s + 8);                 // planes + col + tslot
-    b += nt * (16 + 64);                      // connectivity + element slots
+    b += nt * (16 + 64) + 4 * nblk;           // connectivity + slot incidence
+    b += nt * lx::kRec * ((r.solver.precision == LX_FP64 || r.solver.asm_fp64) ? 8 : 4);   // element records
     b += nv * (48 + 16 + 12 * s + 4);         // coords, rowptr/diag/dir index, SIMPLE blocks
     b += N * 8 * (r.problem.bdf_order + 2);   // history + solution (FP64)
     b += N * s * (2 * r.solver.restart + 3);  // basis, preconditioned directions, work

@@ -210,6 +210,20 @@ lx_status build_setup(const lx_mesh *m, HostSetup &hs)
         for (int a = 0; a < 4; ++a)
             for (int b = 0; b < 4; ++b)
                 hs.eslot[(int64_t)(4 * a + b) * nt + e] = find(tsorted[4 * e + a], tsorted[4 * e + b]);
+    // slot -> (element, local block) incidence, ordered by element then local block
+    if (16 * nt >= INT32_MAX) return fail(LX_ENOMEM, "mesh too large for 32-bit incidence codes");
+    hs.sinc_ptr.assign(nblk + 1, 0);
+    for (int64_t q = 0; q < 16 * nt; ++q) ++hs.sinc_ptr[hs.eslot[q] + 1];
+    for (int64_t k = 0; k < nblk; ++k) hs.sinc_ptr[k + 1] += hs.sinc_ptr[k];
+    hs.sinc.assign(16 * nt, 0);
+    {
+        std::vector<int32_t> fill(hs.sinc_ptr.begin(), hs.sinc_ptr.end() - 1);
+        for (int64_t e = 0; e < nt; ++e)
+            for (int ab = 0; ab < 16; ++ab) {
+                const int32_t k = hs.eslot[(int64_t)ab * nt + e];
+                hs.sinc[fill[k]++] = (int32_t)(16 * e + ab);
+            }
+    }
     return LX_OK;
 }
 

@@ -48,7 +48,10 @@ struct Sim {
 
     // device arrays (new numbering)
     double *d_xh = nullptr, *d_x = nullptr;
-    int32_t *d_tet = nullptr, *d_eslot = nullptr, *d_rowptr = nullptr, *d_col = nullptr, *d_diag = nullptr,
+    int32_t *d_sinc_ptr = nullptr, *d_sinc = nullptr;             // slot incidence of the assembly gather
+    double *d_rec64 = nullptr;                                    // element records (FP64 assembly)
+    float *d_rec32 = nullptr;                                     // element records (FP32 assembly)
+    int32_t *d_tet = nullptr, *d_rowptr = nullptr, *d_col = nullptr, *d_diag = nullptr,
             *d_tslot = nullptr;
     int32_t *d_dir_index = nullptr, *d_dir_node = nullptr, *d_dir_bc = nullptr;
     double *d_g = nullptr, *d_gnodal = nullptr, *d_dg = nullptr;

@@ -200,7 +200,8 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     ALLOC(d_xh, sizeof(double) * 3 * nv);
     ALLOC(d_x, sizeof(double) * 3 * nv);
     ALLOC(d_tet, sizeof(int32_t) * 4 * nt);
-    ALLOC(d_eslot, sizeof(int32_t) * 16 * nt);
+    ALLOC(d_sinc_ptr, sizeof(int32_t) * (nblk + 1));
+    ALLOC(d_sinc, sizeof(int32_t) * 16 * nt);
     ALLOC(d_rowptr, sizeof(int32_t) * (nv + 1));
     ALLOC(d_col, sizeof(int32_t) * nblk);
     ALLOC(d_diag, sizeof(int32_t) * nv);
@@ -234,6 +235,10 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     ALLOC(d_st, sizeof(GmState));
     ALLOC(d_partial, sizeof(double) * std::max<int64_t>((int64_t)nb_red * 64, gm_partial_size(N)));
     LX_HIP(hipHostMalloc((void **)&h_st, sizeof(GmState), hipHostMallocDefault));
+    if (solver.precision == LX_FP64 || solver.asm_fp64)
+        ALLOC(d_rec64, sizeof(double) * kRec * nt);
+    else
+        ALLOC(d_rec32, sizeof(float) * kRec * nt);
     if (solver.precision == LX_FP64) {
         ALLOC(d_val64, sizeof(double) * kPlanes * nblk);
         ALLOC(d_rhs64, sizeof(double) * N);
@@ -269,7 +274,9 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     LX_HIP(hipMemcpyAsync(d_xh, hs.xh.data(), sizeof(double) * 3 * nv, hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_x, hs.xh.data(), sizeof(double) * 3 * nv, hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_tet, hs.tet_soa.data(), sizeof(int32_t) * 4 * nt, hipMemcpyHostToDevice, stream));
-    LX_HIP(hipMemcpyAsync(d_eslot, hs.eslot.data(), sizeof(int32_t) * 16 * nt, hipMemcpyHostToDevice, stream));
+    LX_HIP(hipMemcpyAsync(d_sinc_ptr, hs.sinc_ptr.data(), sizeof(int32_t) * (nblk + 1), hipMemcpyHostToDevice,
+                          stream));
+    LX_HIP(hipMemcpyAsync(d_sinc, hs.sinc.data(), sizeof(int32_t) * 16 * nt, hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_rowptr, hs.rowptr.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_col, hs.col.data(), sizeof(int32_t) * nblk, hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_diag, hs.diag.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, stream));
@@ -675,9 +682,9 @@ lx_status Sim::build_system(double t1, StepCoef &C, lx_step_stats &tstats)
     if (ps != LX_OK) return ps;
     const RowPattern P = pattern();
     if (solver.precision == LX_FP64) {
-        launch_fill<double>(kPlanes * nblk, d_val64, 0.0, stream);
         launch_fill<double>(N, d_rhs64, 0.0, stream);
-        AsmArgs<double> A{nt, nblk, d_tet, d_eslot, d_x, d_xh, hist(0), hist(1), hist(2), d_uA, d_f, d_val64, d_rhs64};
+        AsmArgs<double> A{nt, nblk, d_tet, d_sinc_ptr, d_sinc, d_rec64, d_x, d_xh, hist(0), hist(1), hist(2), d_uA,
+                          d_f, d_val64, d_rhs64};
         auto *tm = timer_begin(1, 0);
         launch_assemble_p1<double>(A, C, stream);
         timer_end(tm);
@@ -690,17 +697,15 @@ lx_status Sim::build_system(double t1, StepCoef &C, lx_step_stats &tstats)
             launch_schur_bound<double>(P, d_val64, d_Dinv64, d_Sinv64, d_sw64, d_st, d_partial, nb_red, stream);
     } else {
         if (solver.asm_fp64) {
-            launch_fill<double>(kPlanes * nblk, d_val64, 0.0, stream);
-            AsmArgs<double> A{nt, nblk, d_tet, d_eslot, d_x, d_xh, hist(0), hist(1), hist(2), d_uA, d_f, d_val64,
-                              nullptr};
+            AsmArgs<double> A{nt, nblk, d_tet, d_sinc_ptr, d_sinc, d_rec64, d_x, d_xh, hist(0), hist(1), hist(2),
+                              d_uA, d_f, d_val64, nullptr};
             auto *tm = timer_begin(1, 0);
             launch_assemble_p1<double>(A, C, stream);
             timer_end(tm);
             launch_scale_copy<float, double>(kPlanes * nblk, d_val32, d_val64, 1.0, stream);
         } else {
-            launch_fill<float>(kPlanes * nblk, d_val32, 0.0f, stream);
-            AsmArgs<float> A{nt, nblk, d_tet, d_eslot, d_x, d_xh, hist(0), hist(1), hist(2), d_uA, d_f, d_val32,
-                             nullptr};
+            AsmArgs<float> A{nt, nblk, d_tet, d_sinc_ptr, d_sinc, d_rec32, d_x, d_xh, hist(0), hist(1), hist(2),
+                             d_uA, d_f, d_val32, nullptr};
             auto *tm = timer_begin(1, 0);
             launch_assemble_p1<float>(A, C, stream);
             timer_end(tm);
