@@ -230,6 +230,10 @@ extern "C" lx_status lx_sim_debug_residual(lx_sim *s, const double *u, const dou
         a = s->dalloc((void **)&s->d_b64, sizeof(double) * s->N);
         if (a != LX_OK) return a;
     }
+    if (!s->d_rrec) {
+        lx_status a = s->dalloc((void **)&s->d_rrec, sizeof(double) * lx::kRRec * s->nt);
+        if (a != LX_OK) return a;
+    }
     lx::StepCoef C;
     lx_status st = s->prepare(s->t + s->prob.dt, C);
     if (st != LX_OK) return st;

@@ -30,9 +30,15 @@ struct AsmArgs {
     T *rhs;                // [nv][4] or null
 };
 
+// Per-element record of the FP64 residual: r [4][4], b [4][4], Dirichlet
+// diagonal [4][3] of the element's vertices.
+constexpr int kRRec = 48;
+
 struct ResArgs {
-    int64_t nt;
+    int64_t nt, nv;
     const int32_t *tet;
+    const int32_t *diag, *sinc_ptr, *sinc;   // diagonal slot of each vertex and slot incidence
+    double *rec;             // [nt][kRRec]
     const double *x, *xh, *h0, *h1, *h2, *uA, *f;
     const double *xs;        // iterate [nv][4]
     const int32_t *dir_index;  // [nv] Dirichlet index or -1

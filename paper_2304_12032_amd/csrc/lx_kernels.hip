@@ -425,8 +425,10 @@ template void launch_assemble_p1<float>(const AsmArgs<float> &, const StepCoef &
 
 // r = b - A xs on every row except Dirichlet velocity rows, evaluated element
 // by element at the quadrature points from the strong residual of the iterate
-// (no matrix is formed).  Optionally accumulates b and the FP64 diagonal of
-// the Dirichlet velocity rows.
+// (no matrix is formed).  Optionally also b and the FP64 diagonal of the
+// Dirichlet velocity rows.  The element pass writes each element's vertex
+// contributions to a record; k_residual_gather sums them per vertex in the
+// fixed order of the vertex's incidence list.
 __global__ __launch_bounds__(256) void k_residual_p1(ResArgs A, StepCoef C)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -507,33 +509,68 @@ __global__ __launch_bounds__(256) void k_residual_p1(ResArgs A, StepCoef C)
         }
     }
     const double mv = mu * E.vol;
+    double *R = A.rec + e * kRRec;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        const int64_t v = E.v[a];
-        if (dir[a] < 0) {
+        const bool free_u = dir[a] < 0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) atomic_add(&A.r[4 * v + c], ru[a][c]);
-            if (A.b)
+        for (int c = 0; c < 3; ++c) R[4 * a + c] = free_u ? ru[a][c] : 0.0;
+        R[4 * a + 3] = rp[a];
+        if (A.b) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) atomic_add(&A.b[4 * v + c], bu[a][c]);
-        } else if (A.dg) {
+            for (int c = 0; c < 3; ++c) R[16 + 4 * a + c] = free_u ? bu[a][c] : 0.0;
+            R[16 + 4 * a + 3] = bp[a];
+        }
+        if (A.dg) {
             const double gaa = E.dphi[a][0] * E.dphi[a][0] + E.dphi[a][1] * E.dphi[a][1] + E.dphi[a][2] * E.dphi[a][2];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 double d = dg[a][c] + mv * gaa;
                 if (C.symgrad) d += mv * E.dphi[a][c] * E.dphi[a][c];
-                atomic_add(&A.dg[3 * (int64_t)dir[a] + c], d);
+                R[32 + 3 * a + c] = free_u ? 0.0 : d;
             }
         }
-        atomic_add(&A.r[4 * v + 3], rp[a]);
-        if (A.b) atomic_add(&A.b[4 * v + 3], bp[a]);
     }
+}
+
+// Vertex pass of the residual: sums the records of the elements around each
+// vertex (the incidence list of its diagonal block) and writes r, b and the
+// Dirichlet diagonal once.
+__global__ __launch_bounds__(256) void k_residual_gather(ResArgs A)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.nv) return;
+    const int32_t k = A.diag[i];
+    double r[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0}, d[3] = {0, 0, 0};
+    for (int32_t q = A.sinc_ptr[k]; q < A.sinc_ptr[k + 1]; ++q) {
+        const int32_t code = A.sinc[q];
+        const int64_t e = code >> 4;
+        const int a = code & 3;   // diagonal block: local (a, a)
+        const double *R = A.rec + e * kRRec;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) r[c] += R[4 * a + c];
+        if (A.b)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] += R[16 + 4 * a + c];
+        if (A.dg)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) d[c] += R[32 + 3 * a + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) A.r[4 * i + c] = r[c];
+    if (A.b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) A.b[4 * i + c] = b[c];
+    const int32_t di = A.dir_index[i];
+    if (A.dg && di >= 0)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) A.dg[3 * (int64_t)di + c] = d[c];
 }
 
 void launch_residual_p1(const ResArgs &a, const StepCoef &c, hipStream_t s)
 {
-    dim3 grid((unsigned)((a.nt + 255) / 256));
-    hipLaunchKernelGGL(k_residual_p1, grid, dim3(256), 0, s, a, c);
+    hipLaunchKernelGGL(k_residual_p1, dim3((unsigned)((a.nt + 255) / 256)), dim3(256), 0, s, a, c);
+    hipLaunchKernelGGL(k_residual_gather, dim3((unsigned)((a.nv + 255) / 256)), dim3(256), 0, s, a);
 }
 
 // ------------------------------------------------------------------ boundary data

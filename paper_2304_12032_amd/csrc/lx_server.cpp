@@ -84,7 +84,7 @@ int64_t estimate_footprint(const Request &r)
         b += 4 * nblk * (s + 8) + nv * (22 * s + 24) + (3 << 20);
     else
         b += nv * s * 9;                      // Schur Chebyshev work
-    if (r.solver.precision != LX_FP64) b += N * (8 * 2 + 4 * 2);
+    if (r.solver.precision != LX_FP64) b += N * (8 * 2 + 4 * 2) + nt * lx::kRRec * 8;
     if (r.problem.ale) b += nv * 8 * 3 * 12 + nblk * 16;
     return b + (1 << 20);
 }

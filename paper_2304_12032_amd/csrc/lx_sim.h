@@ -79,6 +79,7 @@ struct Sim {
     float *d_V32 = nullptr, *d_w32 = nullptr, *d_x32 = nullptr, *d_r32 = nullptr, *d_sw32 = nullptr,
           *d_Z32 = nullptr;
     double *d_r64 = nullptr, *d_b64 = nullptr;
+    double *d_rrec = nullptr;                                    // element records of the FP64 residual
     // SIMPLE block approximations of LX_PC_AMG (one of the two, by precision)
     AmgHost amgh;
     Amg<double> amg64;

@@ -263,6 +263,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         ALLOC(d_r32, sizeof(float) * N);
         ALLOC(d_r64, sizeof(double) * N);
         ALLOC(d_b64, sizeof(double) * N);
+        ALLOC(d_rrec, sizeof(double) * kRRec * nt);
     }
 #undef ALLOC
     if (solver.precond == LX_PC_AMG) {
@@ -748,8 +749,8 @@ lx_status Sim::residual64(const StepCoef &C, const double *xs, bool first, doubl
         launch_fill<double>(N, d_b64, 0.0, stream);
         if (n_dir > 0) launch_fill<double>(3 * n_dir, d_dg, 0.0, stream);
     }
-    ResArgs R{nt, d_tet, d_x, d_xh, hist(0), hist(1), hist(2), d_uA, d_f, xs, d_dir_index, d_r64,
-              first ? d_b64 : nullptr, first ? d_dg : nullptr};
+    ResArgs R{nt, nv, d_tet, d_diag, d_sinc_ptr, d_sinc, d_rrec, d_x, d_xh, hist(0), hist(1), hist(2), d_uA, d_f,
+              xs, d_dir_index, d_r64, first ? d_b64 : nullptr, first ? d_dg : nullptr};
     auto *tm = timer_begin(2, 0);
     launch_residual_p1(R, C, stream);
     timer_end(tm);
