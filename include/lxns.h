@@ -194,8 +194,14 @@ typedef struct {
 /* ---------------------------------------------------------------- outputs */
 
 typedef struct {
-    int64_t n_vertices, n_tets, n_u_nodes, n_dofs, n_blocks;
+    int64_t n_vertices, n_tets;
+    int64_t n_u_nodes;       /* velocity nodes: n_vertices (P1-P1) or n_vertices +
+                                n_edges (P2-P1)                                     */
+    int64_t n_dofs;          /* 3 n_u_nodes + n_vertices                            */
+    int64_t n_blocks;        /* vertex pairs of the block pattern                   */
     int64_t device_bytes;    /* device memory held by the simulation              */
+    int64_t n_edges;         /* P2-P1: edge nodes (0 for P1-P1)                     */
+    int64_t n_scalar_nnz;    /* scalar entries of the stored matrix                 */
 } lx_sizes;
 
 typedef struct {
@@ -227,7 +233,13 @@ lx_status lx_sim_create(const lx_device *dev, const lx_mesh *mesh, const lx_prob
 
 lx_status lx_sim_query(const lx_sim *sim, lx_sizes *out);
 
-/* Set history level `level` (0 = u^n, 1 = u^{n-1}, ...): u [n_vertices][3],
+/* P2-P1 velocity nodes: rows [0, n_vertices) of every velocity-node array are
+ * the vertices (caller ids), rows n_vertices + k are the midpoints of the edges
+ * listed here, edges [n_edges][2] as caller vertex ids (Sec. 2.3's quadratic
+ * Lagrange element).  Nothing is written for P1-P1. */
+lx_status lx_sim_get_edges(const lx_sim *sim, int32_t *edges);
+
+/* Set history level `level` (0 = u^n, 1 = u^{n-1}, ...): u [n_u_nodes][3],
  * p [n_vertices], optional ALE displacement d [n_vertices][3] (NULL: 0).
  * The BDF order used at a step is min(bdf_order, levels set or computed). */
 lx_status lx_sim_set_state(lx_sim *sim, int32_t level, const double *u, const double *p,
@@ -235,11 +247,11 @@ lx_status lx_sim_set_state(lx_sim *sim, int32_t level, const double *u, const do
 lx_status lx_sim_set_time(lx_sim *sim, double t);
 
 /* Nodal data for a boundary condition with a nodal profile, at t^{n+1} of the
- * next step: Dirichlet values or Neumann traction vectors, [n_vertices][3]
- * (only the rows of that condition's vertices are read). */
+ * next step: Dirichlet values or Neumann traction vectors, [n_u_nodes][3]
+ * (only the rows of that condition's nodes are read). */
 lx_status lx_sim_set_dirichlet_values(lx_sim *sim, int32_t bc_index, const double *g);
 lx_status lx_sim_set_neumann_traction(lx_sim *sim, int32_t bc_index, const double *h);
-/* Forcing f at t^{n+1}, [n_vertices][3] (problem.forcing = 1). */
+/* Forcing f at t^{n+1}, [n_u_nodes][3] (problem.forcing = 1). */
 lx_status lx_sim_set_forcing(lx_sim *sim, const double *f);
 /* ALE boundary-displacement shape D^ [n_vertices][3] (rows of ALE boundary
  * vertices are read); the displacement at t is ale_law(t) * D^ (Sec. 2.1.1). */
@@ -252,7 +264,7 @@ lx_status lx_sim_set_ale_displacement(lx_sim *sim, const double *d);
  * time are left unchanged.  stats may be NULL. */
 lx_status lx_sim_step(lx_sim *sim, lx_step_stats *stats);
 
-/* Copy the current solution to caller buffers: u [n_vertices][3], p
+/* Copy the current solution to caller buffers: u [n_u_nodes][3], p
  * [n_vertices], t (any may be NULL).  Synchronises the stream. */
 lx_status lx_sim_get_solution(const lx_sim *sim, double *u, double *p, double *t);
 
@@ -263,8 +275,14 @@ lx_status lx_sim_get_solution(const lx_sim *sim, double *u, double *p, double *t
  * FP64 (FP32 matrices are widened).  rhs is zero for FP32 precision. */
 lx_status lx_sim_debug_export(lx_sim *sim, int32_t *brow, int32_t *bcol, double *vals, double *rhs);
 
+/* P2-P1 parity export (tests only): the system of the coming step as scalar
+ * COO (n_scalar_nnz entries) in the caller's dof numbering -- velocity dof
+ * 3 node + c over the velocity nodes, pressure dof 3 n_u_nodes + vertex -- and
+ * rhs [n_dofs] in the same numbering; FP64 in both precisions. */
+lx_status lx_sim_debug_export_p2(lx_sim *sim, int32_t *rows, int32_t *cols, double *vals, double *rhs);
+
 /* FP64 matrix-free residual b - A x of the coming step at the caller's state
- * x = (u [n][3], p [n]), written to r [n_vertices][4] (tests only). */
+ * x = (u [n][3], p [n]), written to r [n_vertices][4] (tests only; P1-P1). */
 lx_status lx_sim_debug_residual(lx_sim *sim, const double *u, const double *p, double *r);
 
 void lx_sim_destroy(lx_sim *sim);
@@ -310,7 +328,7 @@ typedef struct lx_server lx_server;
 
 lx_status lx_server_create(const lx_server_cfg *cfg, lx_server **out);
 /* Copies the request's arrays; returns a ticket.  LX_EBUSY if the request alone
- * exceeds the budget. */
+ * exceeds the budget; LX_EINVAL for a P2-P1 problem (the server runs P1-P1). */
 lx_status lx_server_submit(lx_server *srv, const lx_request *req, int64_t *ticket);
 /* Run one scheduling tick: admit what fits, advance every active simulation by
  * one step, retire finished ones.  *n_active gets the active count afterwards. */

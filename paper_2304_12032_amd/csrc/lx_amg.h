@@ -76,16 +76,54 @@ struct Amg {
     T *fr = nullptr, *fd0 = nullptr, *fd1 = nullptr, *fv = nullptr;   // [nv][4]
 };
 
-// Per-step numeric set-up: forms S~, every coarse level, the dense inverse and
-// the Chebyshev bounds.  Finv / Dinv come from launch_simple_setup.
+// The blocks of the saddle-point matrix as the preconditioner sees them: F as a
+// 3x3 block-CSR over the velocity nodes (9 planes of stride Fp.nblk), G (rows:
+// velocity nodes, columns: pressure rows; 3 planes of stride gs), B (rows:
+// pressure rows, columns: velocity nodes; 3 planes of stride bs) and C (pressure
+// pattern).  For P1-P1 all four share the vertex block pattern; for P2-P1 they
+// are the split parts.  Vectors are [nu][4] with the pressure in component 3
+// of the first np nodes (0 elsewhere).
 template <typename T>
-void launch_amg_setup(const RowPattern &P, const T *val, const T *Finv, const T *Dinv, Amg<T> &A,
-                      hipStream_t s);
+struct SimpleView {
+    int64_t nu, np;
+    RowPattern Fp;
+    const T *F;
+    const int32_t *gptr, *gcol;
+    const T *Gv;
+    int64_t gs;
+    const int32_t *bptr, *bcol;
+    const T *Bv;
+    int64_t bs;
+    const int32_t *cptr, *ccol;
+    const T *Cv;
+};
+
+// View of the P1-P1 block pattern with planes F 0-8, G 9-11, B 12-14, C 15.
+template <typename T>
+inline SimpleView<T> simple_view_p1(const RowPattern &P, const T *val)
+{
+    SimpleView<T> V;
+    V.nu = V.np = P.nv;
+    V.Fp = P;
+    V.F = val;
+    V.gptr = V.bptr = V.cptr = P.rowptr;
+    V.gcol = V.bcol = V.ccol = P.col;
+    V.Gv = val + 9 * P.nblk;
+    V.Bv = val + 12 * P.nblk;
+    V.Cv = val + 15 * P.nblk;
+    V.gs = V.bs = P.nblk;
+    return V;
+}
+
+// Per-step numeric set-up: forms S~, every coarse level, the dense inverse and
+// the Chebyshev bounds.  Finv / Dinv come from the SIMPLE set-up.
+template <typename T>
+void launch_amg_setup(const SimpleView<T> &V, const T *Finv, const T *Dinv, Amg<T> &A, hipStream_t s);
 
 // z <- M^{-1} (scale * r) for the SIMPLE preconditioner with the AMG Schur block
 // and the Chebyshev velocity block.
 template <typename T>
-void launch_simple_amg_apply(const RowPattern &P, const T *val, const T *Finv, const T *Dinv, Amg<T> &A,
-                             const T *r, const double *scale_ptr, T *z, const int32_t *done, hipStream_t s);
+void launch_simple_amg_apply(const SimpleView<T> &V, const T *Finv, const T *Dinv, Amg<T> &A, const T *r,
+                             const double *scale_ptr, T *z, const int32_t *done, hipStream_t s);
 
 }  // namespace lx

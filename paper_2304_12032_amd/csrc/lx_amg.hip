@@ -22,38 +22,46 @@ namespace lx {
 
 // ================================================================== set-up
 
-// S~_ik = C_ik - sum_{j, d} B_ij[d] D^{-1}_j[d] G_jk[d].  One wavefront per row
-// i, lanes over the entries of the row; G_jk is found by binary search in block
-// row j (block columns are sorted).  The sum runs over the block row of i in
-// order, so the result does not depend on scheduling.
+// Position of column k in the sorted CSR row [lo, hi), or -1.
+__device__ inline int32_t find_col(const int32_t *col, int32_t lo, int32_t hi, int32_t k)
+{
+    if (lo >= hi) return -1;
+    --hi;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (col[mid] < k)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return col[lo] == k ? lo : -1;
+}
+
+// S~_ik = C_ik - sum_{j, d} B_ij[d] D^{-1}_j[d] G_jk[d] over the velocity nodes j
+// of B's row i.  One wavefront per row i, lanes over the entries of the row;
+// C_ik and G_jk are found by binary search (sorted columns).  The sum runs over
+// B's row in order, so the result does not depend on scheduling.
 template <typename T>
-__global__ __launch_bounds__(256) void k_schur_form(RowPattern P, const T *__restrict__ val,
-                                                    const T *__restrict__ Dinv, const int32_t *__restrict__ srow,
+__global__ __launch_bounds__(256) void k_schur_form(SimpleView<T> V, const T *__restrict__ Dinv,
+                                                    const int32_t *__restrict__ srow,
                                                     const int32_t *__restrict__ scol, T *__restrict__ sval)
 {
     const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (i >= P.nv) return;
-    const int64_t nb = P.nblk, nv = P.nv;
-    const int32_t b0 = P.rowptr[i], b1 = P.rowptr[i + 1];
+    if (i >= V.np) return;
+    const int64_t nu = V.nu;
+    const int32_t b0 = V.bptr[i], b1 = V.bptr[i + 1];
     for (int32_t e = srow[i] + lane; e < srow[i + 1]; e += 64) {
         const int32_t k = scol[e];
-        double acc = 0;
+        const int32_t kc = find_col(V.ccol, V.cptr[i], V.cptr[i + 1], k);
+        double acc = kc >= 0 ? (double)V.Cv[kc] : 0.0;
         for (int32_t k1 = b0; k1 < b1; ++k1) {
-            const int32_t j = P.col[k1];
-            int32_t lo = P.rowptr[j], hi = P.rowptr[j + 1] - 1;
-            while (lo < hi) {
-                const int32_t mid = (lo + hi) >> 1;
-                if (P.col[mid] < k)
-                    lo = mid + 1;
-                else
-                    hi = mid;
-            }
-            if (P.col[lo] != k) continue;
-            if (j == i) acc += (double)val[15 * nb + lo];
-            acc -= (double)val[12 * nb + k1] * (double)Dinv[j] * (double)val[9 * nb + lo] +
-                   (double)val[13 * nb + k1] * (double)Dinv[nv + j] * (double)val[10 * nb + lo] +
-                   (double)val[14 * nb + k1] * (double)Dinv[2 * nv + j] * (double)val[11 * nb + lo];
+            const int32_t j = V.bcol[k1];
+            const int32_t kg = find_col(V.gcol, V.gptr[j], V.gptr[j + 1], k);
+            if (kg < 0) continue;
+            acc -= (double)V.Bv[k1] * (double)Dinv[j] * (double)V.Gv[kg] +
+                   (double)V.Bv[V.bs + k1] * (double)Dinv[nu + j] * (double)V.Gv[V.gs + kg] +
+                   (double)V.Bv[2 * V.bs + k1] * (double)Dinv[2 * nu + j] * (double)V.Gv[2 * V.gs + kg];
         }
         sval[e] = (T)acc;
     }
@@ -397,21 +405,18 @@ __global__ __launch_bounds__(256) void k_fcheb(RowPattern P, const T *__restrict
 // Schur solve, stored in L0.r; with smoothed levels also the Chebyshev start
 // x0 = d0 = dinv t / theta, res = t.
 template <typename T, int LPR>
-__global__ __launch_bounds__(256) void k_zp_amg(RowPattern P, const T *__restrict__ val, const T *__restrict__ z,
-                                                AmgLevel<T> L, const double *lam, double ratio, int smooth,
-                                                const int32_t *done)
+__global__ __launch_bounds__(256) void k_zp_amg(SimpleView<T> V, const T *__restrict__ z, AmgLevel<T> L,
+                                                const double *lam, double ratio, int smooth, const int32_t *done)
 {
     if (done && *done) return;
     const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
-    if (row >= P.nv) return;
-    const int64_t nb = P.nblk;
-    using V = typename V4<T>::type;
+    if (row >= V.np) return;
+    using VT = typename V4<T>::type;
     double acc = 0;
-    for (int32_t k = P.rowptr[row] + lane; k < P.rowptr[row + 1]; k += LPR) {
-        const V zj = reinterpret_cast<const V *>(z)[P.col[k]];
-        acc += (double)val[12 * nb + k] * zj.v[0] + (double)val[13 * nb + k] * zj.v[1] +
-               (double)val[14 * nb + k] * zj.v[2];
+    for (int32_t k = V.bptr[row] + lane; k < V.bptr[row + 1]; k += LPR) {
+        const VT zj = reinterpret_cast<const VT *>(z)[V.bcol[k]];
+        acc += (double)V.Bv[k] * zj.v[0] + (double)V.Bv[V.bs + k] * zj.v[1] + (double)V.Bv[2 * V.bs + k] * zj.v[2];
     }
     acc = group_sum<double, LPR>(acc);
     if (lane != 0) return;
@@ -427,34 +432,34 @@ __global__ __launch_bounds__(256) void k_zp_amg(RowPattern P, const T *__restric
     }
 }
 
-// z.u -= D^{-1} sum_j G_ij p_j, z.p = p (p: the Schur solution)
+// z.u -= D^{-1} sum_j G_ij p_j, z.p = p on the pressure rows (0 elsewhere)
 template <typename T, int LPR>
-__global__ __launch_bounds__(256) void k_xu_amg(RowPattern P, const T *__restrict__ val, const T *__restrict__ Dinv,
-                                                T *__restrict__ z, const T *__restrict__ p, const int32_t *done)
+__global__ __launch_bounds__(256) void k_xu_amg(SimpleView<T> V, const T *__restrict__ Dinv, T *__restrict__ z,
+                                                const T *__restrict__ p, const int32_t *done)
 {
     if (done && *done) return;
     const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
-    if (row >= P.nv) return;
-    const int64_t nb = P.nblk, nv = P.nv;
+    if (row >= V.nu) return;
+    const int64_t nu = V.nu;
     double a0 = 0, a1 = 0, a2 = 0;
-    for (int32_t k = P.rowptr[row] + lane; k < P.rowptr[row + 1]; k += LPR) {
-        const double pj = p[P.col[k]];
-        a0 += (double)val[9 * nb + k] * pj;
-        a1 += (double)val[10 * nb + k] * pj;
-        a2 += (double)val[11 * nb + k] * pj;
+    for (int32_t k = V.gptr[row] + lane; k < V.gptr[row + 1]; k += LPR) {
+        const double pj = p[V.gcol[k]];
+        a0 += (double)V.Gv[k] * pj;
+        a1 += (double)V.Gv[V.gs + k] * pj;
+        a2 += (double)V.Gv[2 * V.gs + k] * pj;
     }
     a0 = group_sum<double, LPR>(a0);
     a1 = group_sum<double, LPR>(a1);
     a2 = group_sum<double, LPR>(a2);
     if (lane != 0) return;
-    using V = typename V4<T>::type;
-    V zv = reinterpret_cast<V *>(z)[row];
+    using VT = typename V4<T>::type;
+    VT zv = reinterpret_cast<VT *>(z)[row];
     zv.v[0] = (T)((double)zv.v[0] - (double)Dinv[row] * a0);
-    zv.v[1] = (T)((double)zv.v[1] - (double)Dinv[nv + row] * a1);
-    zv.v[2] = (T)((double)zv.v[2] - (double)Dinv[2 * nv + row] * a2);
-    zv.v[3] = p[row];
-    reinterpret_cast<V *>(z)[row] = zv;
+    zv.v[1] = (T)((double)zv.v[1] - (double)Dinv[nu + row] * a1);
+    zv.v[2] = (T)((double)zv.v[2] - (double)Dinv[2 * nu + row] * a2);
+    zv.v[3] = row < V.np ? p[row] : T(0);
+    reinterpret_cast<VT *>(z)[row] = zv;
 }
 
 // Level l > 0 start: r = restriction of the finer residual (sum over the
@@ -611,11 +616,13 @@ static int block_lpr()
     }
 
 template <typename T>
-void launch_amg_setup(const RowPattern &P, const T *val, const T *Finv, const T *Dinv, Amg<T> &A, hipStream_t s)
+void launch_amg_setup(const SimpleView<T> &V, const T *Finv, const T *Dinv, Amg<T> &A, hipStream_t s)
 {
+    const RowPattern &P = V.Fp;
+    const T *val = V.F;
     AmgLevel<T> &L0 = A.L[0];
-    hipLaunchKernelGGL((k_schur_form<T>), dim3(rows_grid(P.nv, 64)), dim3(256), 0, s, P, val, Dinv, L0.rowptr,
-                       L0.col, L0.val);
+    hipLaunchKernelGGL((k_schur_form<T>), dim3(rows_grid(V.np, 64)), dim3(256), 0, s, V, Dinv, L0.rowptr, L0.col,
+                       L0.val);
     for (int l = 0; l < A.nlev; ++l) {
         AmgLevel<T> &L = A.L[l];
         const unsigned g = rows_grid(L.n, L.lpr);
@@ -649,9 +656,9 @@ void launch_amg_setup(const RowPattern &P, const T *val, const T *Finv, const T 
         A.f_warm = true;
     }
 }
-template void launch_amg_setup<double>(const RowPattern &, const double *, const double *, const double *,
-                                       Amg<double> &, hipStream_t);
-template void launch_amg_setup<float>(const RowPattern &, const float *, const float *, const float *, Amg<float> &,
+template void launch_amg_setup<double>(const SimpleView<double> &, const double *, const double *, Amg<double> &,
+                                       hipStream_t);
+template void launch_amg_setup<float>(const SimpleView<float> &, const float *, const float *, Amg<float> &,
                                       hipStream_t);
 
 template <typename T>
@@ -702,9 +709,11 @@ static void vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s)
 }
 
 template <typename T>
-void launch_simple_amg_apply(const RowPattern &P, const T *val, const T *Finv, const T *Dinv, Amg<T> &A,
-                             const T *r, const double *scale_ptr, T *z, const int32_t *done, hipStream_t s)
+void launch_simple_amg_apply(const SimpleView<T> &V, const T *Finv, const T *Dinv, Amg<T> &A, const T *r,
+                             const double *scale_ptr, T *z, const int32_t *done, hipStream_t s)
 {
+    const RowPattern &P = V.Fp;
+    const T *val = V.F;
     const int lpr = block_lpr();
     hipLaunchKernelGGL((k_fz_start<T>), dim3(flat_grid(P.nv)), dim3(256), 0, s, P.nv, Finv, r, scale_ptr, z, A.fr,
                        A.fd0, &A.lam[kLamF], A.f_ratio, A.f_degree, done);
@@ -714,17 +723,16 @@ void launch_simple_amg_apply(const RowPattern &P, const T *val, const T *Finv, c
                                               Finv, z, A.fr, dc, dn, &A.lam[kLamF], A.f_ratio, i, done));
         std::swap(dc, dn);
     }
-    LX_LPR_SWITCH(lpr, hipLaunchKernelGGL((k_zp_amg<T, LP>), dim3(rows_grid(P.nv, LP)), dim3(256), 0, s, P, val, z,
+    LX_LPR_SWITCH(lpr, hipLaunchKernelGGL((k_zp_amg<T, LP>), dim3(rows_grid(V.np, LP)), dim3(256), 0, s, V, z,
                                           A.L[0], &A.lam[0], A.ratio, A.nlev > 0 ? 1 : 0, done));
     vcycle(A, 0, done, s);
-    LX_LPR_SWITCH(lpr, hipLaunchKernelGGL((k_xu_amg<T, LP>), dim3(rows_grid(P.nv, LP)), dim3(256), 0, s, P, val, Dinv,
-                                          z, A.L[0].x1, done));
+    LX_LPR_SWITCH(lpr, hipLaunchKernelGGL((k_xu_amg<T, LP>), dim3(rows_grid(V.nu, LP)), dim3(256), 0, s, V, Dinv, z,
+                                          A.L[0].x1, done));
 }
-template void launch_simple_amg_apply<double>(const RowPattern &, const double *, const double *, const double *,
+template void launch_simple_amg_apply<double>(const SimpleView<double> &, const double *, const double *,
                                               Amg<double> &, const double *, const double *, double *,
                                               const int32_t *, hipStream_t);
-template void launch_simple_amg_apply<float>(const RowPattern &, const float *, const float *, const float *,
-                                             Amg<float> &, const float *, const double *, float *, const int32_t *,
-                                             hipStream_t);
+template void launch_simple_amg_apply<float>(const SimpleView<float> &, const float *, const float *, Amg<float> &,
+                                             const float *, const double *, float *, const int32_t *, hipStream_t);
 
 }  // namespace lx

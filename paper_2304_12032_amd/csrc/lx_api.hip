@@ -39,21 +39,36 @@ extern "C" lx_status lx_sim_query(const lx_sim *s, lx_sizes *out)
     if (!out) return fail(LX_EINVAL, "out is NULL");
     out->n_vertices = s->nv;
     out->n_tets = s->nt;
-    out->n_u_nodes = s->nv;
-    out->n_dofs = s->N;
+    out->n_u_nodes = s->nu;
+    out->n_dofs = 3 * s->nu + s->nv;
     out->n_blocks = s->nblk;
     out->device_bytes = s->device_bytes;
+    out->n_edges = s->nu - s->nv;
+    out->n_scalar_nnz = s->p2 ? 9 * s->s64.nf + 3 * s->s64.ng + 3 * s->s64.nb + s->s64.nc : 16 * s->nblk;
     return LX_OK;
 }
 
-// caller [n][3] + [n] -> internal [nv][4]
+extern "C" lx_status lx_sim_get_edges(const lx_sim *s, int32_t *edges)
+{
+    LX_GUARD(s);
+    if (!edges) return fail(LX_EINVAL, "edges is NULL");
+    if (!s->p2) return LX_OK;
+    for (int64_t k = 0; k < s->p2h.ne; ++k) {
+        const uint64_t key = s->p2h.edge_key[k];
+        edges[2 * k] = s->hs.perm_v[(int64_t)(key >> 32)];
+        edges[2 * k + 1] = s->hs.perm_v[(int64_t)(key & 0xffffffffu)];
+    }
+    return LX_OK;
+}
+
+// caller u [nu][3] + p [nv] -> internal [nu][4]
 static void to_internal(const lx_sim *s, const double *u, const double *p, std::vector<double> &x)
 {
-    x.assign(4 * s->nv, 0.0);
-    for (int64_t i = 0; i < s->nv; ++i) {
-        const int64_t o = s->hs.perm_v[i];
+    x.assign(4 * s->nu, 0.0);
+    for (int64_t i = 0; i < s->nu; ++i) {
+        const int64_t o = s->caller_node(i);
         for (int c = 0; c < 3; ++c) x[4 * i + c] = u ? u[3 * o + c] : 0.0;
-        x[4 * i + 3] = p ? p[o] : 0.0;
+        if (i < s->nv) x[4 * i + 3] = p ? p[o] : 0.0;
     }
 }
 
@@ -94,18 +109,20 @@ extern "C" lx_status lx_sim_set_dirichlet_values(lx_sim *s, int32_t bc, const do
         return fail(LX_EINVAL, "bc %d is not a Dirichlet condition with a nodal profile", bc);
     for (int64_t k = 0; k < s->n_dir; ++k) {
         if (s->h_dir_bc[k] != bc) continue;
-        const int64_t o = s->hs.perm_v[s->h_dir_node[k]];
+        const int64_t o = s->caller_node(s->h_dir_node[k]);
         for (int c = 0; c < 3; ++c) s->h_gnodal[3 * k + c] = g[3 * o + c];
     }
     s->dirty_gnodal = true;
     return LX_OK;
 }
 
-static lx_status upload_nodal3(lx_sim *s, const double *src, double *dst)
+// caller [n][3] over the velocity nodes (vertices only: n = nv) -> device
+static lx_status upload_nodal3(lx_sim *s, const double *src, double *dst, bool vertices_only = false)
 {
-    std::vector<double> h(3 * s->nv);
-    for (int64_t i = 0; i < s->nv; ++i)
-        for (int c = 0; c < 3; ++c) h[3 * i + c] = src[3 * (int64_t)s->hs.perm_v[i] + c];
+    const int64_t n = vertices_only ? s->nv : s->nu;
+    std::vector<double> h(3 * n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) h[3 * i + c] = src[3 * s->caller_node(i) + c];
     LX_HIP(hipMemcpyAsync(dst, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s->stream));
     LX_HIP(hipStreamSynchronize(s->stream));
     return LX_OK;
@@ -140,7 +157,7 @@ extern "C" lx_status lx_sim_set_ale_displacement(lx_sim *s, const double *d)
     if (!s->prob.ale) return fail(LX_ESTATE, "problem was created without ALE");
     if (!d) return fail(LX_EINVAL, "d is NULL");
     (void)hipSetDevice(s->device);
-    lx_status st = upload_nodal3(s, d, s->d_ale_shape);
+    lx_status st = upload_nodal3(s, d, s->d_ale_shape, true);
     if (st == LX_OK) s->ale_ext_valid = false;
     return st;
 }
@@ -159,14 +176,14 @@ extern "C" lx_status lx_sim_get_solution(const lx_sim *s, double *u, double *p, 
 {
     LX_GUARD(s);
     (void)hipSetDevice(s->device);
-    std::vector<double> x(4 * s->nv);
+    std::vector<double> x(4 * s->nu);
     LX_HIP(hipMemcpyAsync(x.data(), s->d_hist[0], sizeof(double) * x.size(), hipMemcpyDeviceToHost, s->stream));
     LX_HIP(hipStreamSynchronize(s->stream));
-    for (int64_t i = 0; i < s->nv; ++i) {
-        const int64_t o = s->hs.perm_v[i];
+    for (int64_t i = 0; i < s->nu; ++i) {
+        const int64_t o = s->caller_node(i);
         if (u)
             for (int c = 0; c < 3; ++c) u[3 * o + c] = x[4 * i + c];
-        if (p) p[o] = x[4 * i + 3];
+        if (p && i < s->nv) p[o] = x[4 * i + 3];
     }
     if (t) *t = s->t;
     return LX_OK;
@@ -184,6 +201,7 @@ static inline int plane_of(int r, int c)
 extern "C" lx_status lx_sim_debug_export(lx_sim *s, int32_t *brow, int32_t *bcol, double *vals, double *rhs)
 {
     LX_GUARD(s);
+    if (s->p2) return fail(LX_EINVAL, "P2-P1 systems are exported by lx_sim_debug_export_p2");
     (void)hipSetDevice(s->device);
     lx::StepCoef C;
     lx_step_stats S;
@@ -219,10 +237,64 @@ extern "C" lx_status lx_sim_debug_export(lx_sim *s, int32_t *brow, int32_t *bcol
     return LX_OK;
 }
 
+// Scalar COO of the P2-P1 system in the caller's numbering: velocity dof 3 node + c
+// (nodes: caller vertex ids, then nv + edge index), pressure dof 3 nu + vertex.
+extern "C" lx_status lx_sim_debug_export_p2(lx_sim *s, int32_t *rows, int32_t *cols, double *vals, double *rhs)
+{
+    LX_GUARD(s);
+    if (!s->p2) return fail(LX_EINVAL, "not a P2-P1 simulation");
+    (void)hipSetDevice(s->device);
+    lx::StepCoef C;
+    lx_step_stats S;
+    memset(&S, 0, sizeof(S));
+    lx_status st = s->build_system(s->t + s->prob.dt, C, S);
+    if (st != LX_OK) return st;
+    const lx::P2Sys<double> &Y = s->s64;
+    std::vector<double> F(9 * Y.nf), G(3 * Y.ng), B(3 * Y.nb), Cc(Y.nc), r(4 * s->nu);
+    LX_HIP(hipMemcpyAsync(F.data(), Y.F, sizeof(double) * F.size(), hipMemcpyDeviceToHost, s->stream));
+    LX_HIP(hipMemcpyAsync(G.data(), Y.G, sizeof(double) * G.size(), hipMemcpyDeviceToHost, s->stream));
+    LX_HIP(hipMemcpyAsync(B.data(), Y.B, sizeof(double) * B.size(), hipMemcpyDeviceToHost, s->stream));
+    LX_HIP(hipMemcpyAsync(Cc.data(), Y.C, sizeof(double) * Cc.size(), hipMemcpyDeviceToHost, s->stream));
+    LX_HIP(hipMemcpyAsync(r.data(), s->d_rhs64, sizeof(double) * r.size(), hipMemcpyDeviceToHost, s->stream));
+    LX_HIP(hipStreamSynchronize(s->stream));
+    const lx::P2Setup &q = s->p2h;
+    const int64_t pu = 3 * s->nu;
+    int64_t o = 0;
+    auto put = [&](int64_t rr, int64_t cc, double v) {
+        if (rows) rows[o] = (int32_t)rr;
+        if (cols) cols[o] = (int32_t)cc;
+        if (vals) vals[o] = v;
+        ++o;
+    };
+    for (int64_t i = 0; i < s->nu; ++i)
+        for (int32_t k = q.fptr[i]; k < q.fptr[i + 1]; ++k)
+            for (int c = 0; c < 3; ++c)
+                for (int d = 0; d < 3; ++d)
+                    put(3 * s->caller_node(i) + c, 3 * s->caller_node(q.fcol[k]) + d, F[(3 * c + d) * Y.nf + k]);
+    for (int64_t i = 0; i < s->nu; ++i)
+        for (int32_t k = q.gptr[i]; k < q.gptr[i + 1]; ++k)
+            for (int c = 0; c < 3; ++c) put(3 * s->caller_node(i) + c, pu + s->hs.perm_v[q.gcol[k]], G[c * Y.ng + k]);
+    for (int64_t i = 0; i < s->nv; ++i)
+        for (int32_t k = q.bptr[i]; k < q.bptr[i + 1]; ++k)
+            for (int d = 0; d < 3; ++d)
+                put(pu + s->hs.perm_v[i], 3 * s->caller_node(q.bcol[k]) + d, B[d * Y.nb + k]);
+    for (int64_t i = 0; i < s->nv; ++i)
+        for (int32_t k = s->hs.rowptr[i]; k < s->hs.rowptr[i + 1]; ++k)
+            put(pu + s->hs.perm_v[i], pu + s->hs.perm_v[s->hs.col[k]], Cc[k]);
+    if (rhs)
+        for (int64_t i = 0; i < s->nu; ++i) {
+            const int64_t oc = s->caller_node(i);
+            for (int c = 0; c < 3; ++c) rhs[3 * oc + c] = r[4 * i + c];
+            if (i < s->nv) rhs[pu + oc] = r[4 * i + 3];
+        }
+    return LX_OK;
+}
+
 extern "C" lx_status lx_sim_debug_residual(lx_sim *s, const double *u, const double *p, double *r)
 {
     LX_GUARD(s);
     if (!r) return fail(LX_EINVAL, "r is NULL");
+    if (s->p2) return fail(LX_EINVAL, "the matrix-free residual is built for the P1-P1 pair");
     (void)hipSetDevice(s->device);
     if (!s->d_r64) {
         lx_status a = s->dalloc((void **)&s->d_r64, sizeof(double) * s->N);

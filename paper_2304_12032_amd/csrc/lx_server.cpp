@@ -135,6 +135,7 @@ extern "C" lx_status lx_server_submit(lx_server *srv, const lx_request *req, int
     const lx_mesh &m = req->mesh;
     if (m.n_vertices <= 0 || m.n_tets <= 0 || !m.coords || !m.tets) return fail(LX_EINVAL, "empty mesh");
     if (req->n_steps < 0) return fail(LX_EINVAL, "n_steps < 0");
+    if (req->problem.fe != LX_P1P1) return fail(LX_EINVAL, "the server runs P1-P1 requests");
     auto r = std::make_unique<Request>();
     r->coords.assign(m.coords, m.coords + 3 * m.n_vertices);
     r->tets.assign(m.tets, m.tets + 4 * m.n_tets);

@@ -7,6 +7,7 @@
 #include "lx_amg.h"
 #include "lx_common.h"
 #include "lx_kernels.h"
+#include "lx_p2.h"
 
 namespace lx {
 
@@ -16,9 +17,9 @@ struct BCDesc {
     lx_boundary spec{};
     std::vector<int32_t> tags;
     int64_t nf = 0;                 // Neumann faces
-    std::vector<int32_t> h_faces;   // [nf][3] new numbering
+    std::vector<int32_t> h_faces;   // [nf][3] new numbering (P2-P1: [nf][6] with the edge nodes)
     int32_t *d_faces = nullptr;
-    double *d_hnodal = nullptr;     // [nv][3] nodal traction (nodal profile)
+    double *d_hnodal = nullptr;     // [nu][3] nodal traction (nodal profile)
     bool nodal_set = false;
 };
 
@@ -42,6 +43,20 @@ struct Sim {
     std::vector<int32_t> ale_tags;
     std::vector<int32_t> h_ale_nodes;
     int64_t nv = 0, nt = 0, nblk = 0, N = 0, n_dir = 0;
+    // P2-P1: velocity nodes (vertices, then edges); nu = nv for P1-P1
+    bool p2 = false;
+    int64_t nu = 0;
+    P2Setup p2h;
+    int32_t *d_nodes = nullptr, *d_fptr = nullptr, *d_fcol = nullptr, *d_fdiag = nullptr, *d_gptr = nullptr,
+            *d_gcol = nullptr, *d_bptr = nullptr, *d_bcol = nullptr, *d_finc_ptr = nullptr, *d_finc = nullptr,
+            *d_ginc_ptr = nullptr, *d_ginc = nullptr, *d_binc_ptr = nullptr, *d_binc = nullptr;
+    double *d_xnode = nullptr;      // [nu][3]
+    P2Rules *d_rules = nullptr;
+    double *d_rec2 = nullptr;       // [nt][kP2Rec] element records
+    P2Sys<double> s64{};            // FP64 split system (both precisions for P2-P1)
+    P2Sys<float> s32{};             // FP32 copy (FP32 + refinement)
+    // caller row of internal node i (vertices are renumbered, edge nodes keep the library order)
+    int64_t caller_node(int64_t i) const { return i < nv ? (int64_t)hs.perm_v[i] : i; }
     std::vector<int32_t> h_dir_index, h_dir_node, h_dir_bc;
     std::vector<double> h_gnodal;
     bool dirty_gnodal = false;
@@ -117,11 +132,16 @@ struct Sim {
     template <typename T>
     lx_status setup_amg(Amg<T> &A);
     template <typename T>
+    SimpleView<T> view();
+    template <typename T>
+    void spmv(const T *x, T *y, const int32_t *done, std::pair<hipEvent_t, hipEvent_t> *tm);
+    template <typename T>
     lx_status gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, GmResult &res,
                     lx_step_stats &tstats, bool inner = false);
     void coefficients(double t1, StepCoef &C, BCSet &B) const;
     lx_status prepare(double t1, StepCoef &C);
     lx_status build_system(double t1, StepCoef &C, lx_step_stats &tstats);
+    lx_status build_system_p2(double t1, StepCoef &C);
     void add_neumann(double t1, double *out0, double *out1);
     lx_status residual64(const StepCoef &C, const double *xs, bool first, double t1);
     lx_status step(lx_step_stats *out);

@@ -74,7 +74,10 @@ Sim::~Sim()
 lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_problem *pr, const lx_solver *sv)
 {
     if (!pr || !sv) return fail(LX_EINVAL, "problem/solver NULL");
-    if (pr->fe != LX_P1P1) return fail(LX_EINVAL, "only the P1-P1 pair is built in this library");
+    if (pr->fe != LX_P1P1 && pr->fe != LX_P2P1) return fail(LX_EINVAL, "fe must be LX_P1P1 or LX_P2P1");
+    if (pr->fe == LX_P2P1 && pr->ale) return fail(LX_EINVAL, "ALE is built for the P1-P1 pair only");
+    if (pr->fe == LX_P2P1 && sv->precond != LX_PC_AMG)
+        return fail(LX_EINVAL, "the P2-P1 pair uses the AMG preconditioner (LX_PC_AMG)");
     if (pr->bdf_order < 1 || pr->bdf_order > 3) return fail(LX_EINVAL, "bdf_order must be 1..3");
     if (!(pr->dt > 0) || !(pr->rho > 0) || !(pr->mu >= 0)) return fail(LX_EINVAL, "dt, rho must be > 0, mu >= 0");
     if (pr->semi_implicit != 1) return fail(LX_EINVAL, "only the semi-implicit formulation is supported");
@@ -120,27 +123,45 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         ale_tags.assign(pr->ale_tags, pr->ale_tags + pr->n_ale_tags);
     }
     prob.ale_tags = nullptr;
-    if (prob.C_r <= 0) prob.C_r = 30.0;
+    if (prob.C_r <= 0) prob.C_r = (prob.fe == LX_P2P1) ? 60.0 : 30.0;
 
     lx_status st = build_setup(mesh, hs);
     if (st != LX_OK) return st;
     nv = hs.nv;
     nt = hs.nt;
     nblk = (int64_t)hs.col.size();
-    N = 4 * nv;
+    p2 = prob.fe == LX_P2P1;
+    if (p2) {
+        st = build_setup_p2(hs, p2h);
+        if (st != LX_OK) return st;
+        nu = p2h.nu;
+    } else {
+        nu = nv;
+    }
+    N = 4 * nu;
 
-    // boundary sets in the new numbering
-    std::vector<int32_t> owner(nv, -1);
+    // boundary sets in the new numbering: face vertices (P2-P1: then the face's
+    // edge nodes (0,1) (1,2) (2,0))
+    std::vector<int32_t> owner(nu, -1);
+    bool edge_missing = false;
     auto face_vertices = [&](const std::vector<int32_t> &tags, std::vector<int32_t> &out_faces) {
         out_faces.clear();
         for (int64_t f = 0; f < mesh->n_bfaces; ++f) {
             int32_t tg = mesh->bface_tag[f];
             if (std::find(tags.begin(), tags.end(), tg) == tags.end()) continue;
+            int32_t w[3];
             for (int k = 0; k < 3; ++k) {
                 int32_t v = mesh->bfaces[3 * f + k];
                 if (v < 0 || v >= nv) return false;
-                out_faces.push_back(hs.iperm_v[v]);
+                w[k] = hs.iperm_v[v];
+                out_faces.push_back(w[k]);
             }
+            if (p2)
+                for (int k = 0; k < 3; ++k) {
+                    const int32_t m = p2_edge_node(p2h, nv, w[k], w[(k + 1) % 3]);
+                    if (m < 0) edge_missing = true;
+                    out_faces.push_back(m < 0 ? 0 : m);
+                }
         }
         return true;
     };
@@ -153,8 +174,8 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
             for (int32_t v : fv)
                 if (owner[v] < 0) owner[v] = i;
         }
-    h_dir_index.assign(nv, -1);
-    for (int64_t v = 0; v < nv; ++v)
+    h_dir_index.assign(nu, -1);
+    for (int64_t v = 0; v < nu; ++v)
         if (owner[v] >= 0) {
             h_dir_index[v] = (int32_t)h_dir_node.size();
             h_dir_node.push_back((int32_t)v);
@@ -165,9 +186,10 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     for (int i = 0; i < (int)bcs.size(); ++i) {
         if (bcs[i].spec.type != LX_BC_NEUMANN) continue;
         if (!face_vertices(bcs[i].tags, fv)) return fail(LX_EMESH, "boundary face vertex out of range");
-        bcs[i].nf = (int64_t)fv.size() / 3;
+        bcs[i].nf = (int64_t)fv.size() / (p2 ? 6 : 3);
         bcs[i].h_faces = fv;
     }
+    if (edge_missing) return fail(LX_EMESH, "a boundary face is not a face of any tetrahedron");
     if (prob.ale) {
         if (!face_vertices(ale_tags, fv)) return fail(LX_EMESH, "boundary face vertex out of range");
         std::vector<char> mark(nv, 0);
@@ -202,11 +224,38 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     ALLOC(d_tet, sizeof(int32_t) * 4 * nt);
     ALLOC(d_sinc_ptr, sizeof(int32_t) * (nblk + 1));
     ALLOC(d_sinc, sizeof(int32_t) * 16 * nt);
+    if (p2) {
+        const P2Setup &q = p2h;
+        ALLOC(d_nodes, sizeof(int32_t) * 10 * nt);
+        ALLOC(d_fptr, sizeof(int32_t) * (nu + 1));
+        ALLOC(d_fcol, sizeof(int32_t) * q.fcol.size());
+        ALLOC(d_fdiag, sizeof(int32_t) * nu);
+        ALLOC(d_gptr, sizeof(int32_t) * (nu + 1));
+        ALLOC(d_gcol, sizeof(int32_t) * q.gcol.size());
+        ALLOC(d_bptr, sizeof(int32_t) * (nv + 1));
+        ALLOC(d_bcol, sizeof(int32_t) * q.bcol.size());
+        ALLOC(d_finc_ptr, sizeof(int32_t) * q.finc_ptr.size());
+        ALLOC(d_finc, sizeof(int32_t) * q.finc.size());
+        ALLOC(d_ginc_ptr, sizeof(int32_t) * q.ginc_ptr.size());
+        ALLOC(d_ginc, sizeof(int32_t) * q.ginc.size());
+        ALLOC(d_binc_ptr, sizeof(int32_t) * q.binc_ptr.size());
+        ALLOC(d_binc, sizeof(int32_t) * q.binc.size());
+        ALLOC(d_xnode, sizeof(double) * 3 * nu);
+        ALLOC(d_rules, sizeof(P2Rules));
+        ALLOC(d_rec2, sizeof(double) * (int64_t)kP2Rec * nt);
+        s64.nv = s32.nv = nv;
+        s64.nu = s32.nu = nu;
+        s64.nt = s32.nt = nt;
+        s64.nf = s32.nf = (int64_t)q.fcol.size();
+        s64.ng = s32.ng = (int64_t)q.gcol.size();
+        s64.nb = s32.nb = (int64_t)q.bcol.size();
+        s64.nc = s32.nc = nblk;
+    }
     ALLOC(d_rowptr, sizeof(int32_t) * (nv + 1));
     ALLOC(d_col, sizeof(int32_t) * nblk);
     ALLOC(d_diag, sizeof(int32_t) * nv);
     ALLOC(d_tslot, sizeof(int32_t) * nblk);
-    ALLOC(d_dir_index, sizeof(int32_t) * nv);
+    ALLOC(d_dir_index, sizeof(int32_t) * nu);
     if (n_dir > 0) {
         ALLOC(d_dir_node, sizeof(int32_t) * n_dir);
         ALLOC(d_dir_bc, sizeof(int32_t) * n_dir);
@@ -217,7 +266,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     const int L = prob.bdf_order;
     for (int l = 0; l < L; ++l) ALLOC(d_hist[l], sizeof(double) * N);
     ALLOC(d_xs, sizeof(double) * N);
-    if (prob.forcing) ALLOC(d_f, sizeof(double) * 3 * nv);
+    if (prob.forcing) ALLOC(d_f, sizeof(double) * 3 * nu);
     if (prob.ale) {
         ALLOC(d_uA, sizeof(double) * 3 * nv);
         for (int l = 0; l < L; ++l) ALLOC(d_dhist[l], sizeof(double) * 3 * nv);
@@ -227,35 +276,57 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     }
     for (auto &b : bcs)
         if (b.spec.type == LX_BC_NEUMANN && b.nf > 0) {
-            ALLOC(b.d_faces, sizeof(int32_t) * 3 * b.nf);
-            if (b.spec.profile.kind == LX_PROFILE_NODAL) ALLOC(b.d_hnodal, sizeof(double) * 3 * nv);
+            ALLOC(b.d_faces, sizeof(int32_t) * b.h_faces.size());
+            if (b.spec.profile.kind == LX_PROFILE_NODAL) ALLOC(b.d_hnodal, sizeof(double) * 3 * nu);
         }
     const int m = solver.restart;
     nb_red = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (N + 2047) / 2048));
     ALLOC(d_st, sizeof(GmState));
     ALLOC(d_partial, sizeof(double) * std::max<int64_t>((int64_t)nb_red * 64, gm_partial_size(N)));
     LX_HIP(hipHostMalloc((void **)&h_st, sizeof(GmState), hipHostMallocDefault));
-    if (solver.precision == LX_FP64 || solver.asm_fp64)
-        ALLOC(d_rec64, sizeof(double) * kRec * nt);
-    else
-        ALLOC(d_rec32, sizeof(float) * kRec * nt);
-    if (solver.precision == LX_FP64) {
-        ALLOC(d_val64, sizeof(double) * kPlanes * nblk);
+    if (p2) {
+        // FP64 split system in both precisions (the refinement residual uses it)
+        ALLOC(s64.F, sizeof(double) * 9 * s64.nf);
+        ALLOC(s64.G, sizeof(double) * 3 * s64.ng);
+        ALLOC(s64.B, sizeof(double) * 3 * s64.nb);
+        ALLOC(s64.C, sizeof(double) * s64.nc);
+        s64.fptr = s32.fptr = d_fptr;
+        s64.fcol = s32.fcol = d_fcol;
+        s64.gptr = s32.gptr = d_gptr;
+        s64.gcol = s32.gcol = d_gcol;
+        s64.bptr = s32.bptr = d_bptr;
+        s64.bcol = s32.bcol = d_bcol;
+        s64.cptr = s32.cptr = d_rowptr;
+        s64.ccol = s32.ccol = d_col;
         ALLOC(d_rhs64, sizeof(double) * N);
-        ALLOC(d_Finv64, sizeof(double) * 9 * nv);
-        ALLOC(d_Dinv64, sizeof(double) * 3 * nv);
+        if (solver.precision != LX_FP64) {
+            ALLOC(s32.F, sizeof(float) * 9 * s32.nf);
+            ALLOC(s32.G, sizeof(float) * 3 * s32.ng);
+            ALLOC(s32.B, sizeof(float) * 3 * s32.nb);
+            ALLOC(s32.C, sizeof(float) * s32.nc);
+        }
+    } else if (solver.precision == LX_FP64 || solver.asm_fp64) {
+        ALLOC(d_rec64, sizeof(double) * kRec * nt);
+    } else {
+        ALLOC(d_rec32, sizeof(float) * kRec * nt);
+    }
+    if (solver.precision == LX_FP64) {
+        if (!p2) ALLOC(d_val64, sizeof(double) * kPlanes * nblk);
+        if (!d_rhs64) ALLOC(d_rhs64, sizeof(double) * N);
+        ALLOC(d_Finv64, sizeof(double) * 9 * nu);
+        ALLOC(d_Dinv64, sizeof(double) * 3 * nu);
         ALLOC(d_Sinv64, sizeof(double) * nv);
         ALLOC(d_V64, sizeof(double) * N * (m + 1));
         ALLOC(d_Z64, sizeof(double) * N * m);
         ALLOC(d_sw64, sizeof(double) * 9 * nv);
         ALLOC(d_w64, sizeof(double) * N);
     } else {
-        ALLOC(d_val32, sizeof(float) * kPlanes * nblk);
-        ALLOC(d_Finv32, sizeof(float) * 9 * nv);
-        ALLOC(d_Dinv32, sizeof(float) * 3 * nv);
+        if (!p2) ALLOC(d_val32, sizeof(float) * kPlanes * nblk);
+        ALLOC(d_Finv32, sizeof(float) * 9 * nu);
+        ALLOC(d_Dinv32, sizeof(float) * 3 * nu);
         ALLOC(d_Sinv32, sizeof(float) * nv);
         ALLOC(d_V32, sizeof(float) * N * (m + 1));
-        if (solver.asm_fp64) ALLOC(d_val64, sizeof(double) * kPlanes * nblk);
+        if (solver.asm_fp64 && !p2) ALLOC(d_val64, sizeof(double) * kPlanes * nblk);
         ALLOC(d_Z32, sizeof(float) * N * m);
         ALLOC(d_sw32, sizeof(float) * 9 * nv);
         ALLOC(d_w32, sizeof(float) * N);
@@ -263,7 +334,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         ALLOC(d_r32, sizeof(float) * N);
         ALLOC(d_r64, sizeof(double) * N);
         ALLOC(d_b64, sizeof(double) * N);
-        ALLOC(d_rrec, sizeof(double) * kRRec * nt);
+        if (!p2) ALLOC(d_rrec, sizeof(double) * kRRec * nt);
     }
 #undef ALLOC
     if (solver.precond == LX_PC_AMG) {
@@ -282,7 +353,32 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     LX_HIP(hipMemcpyAsync(d_col, hs.col.data(), sizeof(int32_t) * nblk, hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_diag, hs.diag.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_tslot, hs.tslot.data(), sizeof(int32_t) * nblk, hipMemcpyHostToDevice, stream));
-    LX_HIP(hipMemcpyAsync(d_dir_index, h_dir_index.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, stream));
+    LX_HIP(hipMemcpyAsync(d_dir_index, h_dir_index.data(), sizeof(int32_t) * nu, hipMemcpyHostToDevice, stream));
+    if (p2) {
+        const P2Setup &q = p2h;
+        auto up = [&](int32_t *d, const std::vector<int32_t> &h) {
+            return hipMemcpyAsync(d, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, stream);
+        };
+        LX_HIP(up(d_nodes, q.nodes));
+        LX_HIP(up(d_fptr, q.fptr));
+        LX_HIP(up(d_fcol, q.fcol));
+        LX_HIP(up(d_fdiag, q.fdiag));
+        LX_HIP(up(d_gptr, q.gptr));
+        LX_HIP(up(d_gcol, q.gcol));
+        LX_HIP(up(d_bptr, q.bptr));
+        LX_HIP(up(d_bcol, q.bcol));
+        LX_HIP(up(d_finc_ptr, q.finc_ptr));
+        LX_HIP(up(d_finc, q.finc));
+        LX_HIP(up(d_ginc_ptr, q.ginc_ptr));
+        LX_HIP(up(d_ginc, q.ginc));
+        LX_HIP(up(d_binc_ptr, q.binc_ptr));
+        LX_HIP(up(d_binc, q.binc));
+        LX_HIP(hipMemcpyAsync(d_xnode, q.xnode.data(), sizeof(double) * 3 * nu, hipMemcpyHostToDevice, stream));
+        P2Rules rules;
+        p2_rules(rules);
+        LX_HIP(hipMemcpyAsync(d_rules, &rules, sizeof(P2Rules), hipMemcpyHostToDevice, stream));
+        LX_HIP(hipStreamSynchronize(stream));   // rules is a stack object
+    }
     if (n_dir > 0) {
         LX_HIP(hipMemcpyAsync(d_dir_node, h_dir_node.data(), sizeof(int32_t) * n_dir, hipMemcpyHostToDevice, stream));
         LX_HIP(hipMemcpyAsync(d_dir_bc, h_dir_bc.data(), sizeof(int32_t) * n_dir, hipMemcpyHostToDevice, stream));
@@ -290,11 +386,11 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     }
     for (auto &b : bcs)
         if (b.d_faces)
-            LX_HIP(hipMemcpyAsync(b.d_faces, b.h_faces.data(), sizeof(int32_t) * 3 * b.nf, hipMemcpyHostToDevice,
-                                  stream));
+            LX_HIP(hipMemcpyAsync(b.d_faces, b.h_faces.data(), sizeof(int32_t) * b.h_faces.size(),
+                                  hipMemcpyHostToDevice, stream));
     for (int l = 0; l < L; ++l) launch_fill<double>(N, d_hist[l], 0.0, stream);
     launch_fill<double>(N, d_xs, 0.0, stream);
-    if (d_f) launch_fill<double>(3 * nv, d_f, 0.0, stream);
+    if (d_f) launch_fill<double>(3 * nu, d_f, 0.0, stream);
     if (prob.ale) {
         launch_fill<double>(3 * nv, d_uA, 0.0, stream);
         for (int l = 0; l < L; ++l) launch_fill<double>(3 * nv, d_dhist[l], 0.0, stream);
@@ -302,7 +398,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         launch_fill<double>(3 * nv, d_ale_shape, 0.0, stream);
     }
     for (auto &b : bcs)
-        if (b.d_hnodal) launch_fill<double>(3 * nv, b.d_hnodal, 0.0, stream);
+        if (b.d_hnodal) launch_fill<double>(3 * nu, b.d_hnodal, 0.0, stream);
     LX_HIP(hipMemsetAsync(d_st, 0, sizeof(GmState), stream));
     LX_HIP(hipEventCreate(&ev_step0));
     LX_HIP(hipEventCreate(&ev_step1));
@@ -341,7 +437,7 @@ lx_status Sim::setup_amg(Amg<T> &A)
     A.cycle = solver.amg_cycle;
     const char *env = getenv("LXNS_AMG_LPR");
     const int lpr_env = env ? atoi(env) : 0;
-    int64_t maxgrid = (nv * 16 + 255) / 256;
+    int64_t maxgrid = (nu * 16 + 255) / 256;
     auto up = [&](int32_t *&d, const std::vector<int32_t> &h) -> lx_status {
         lx_status s = dalloc((void **)&d, sizeof(int32_t) * std::max<size_t>(h.size(), 1));
         if (s != LX_OK) return s;
@@ -392,10 +488,10 @@ lx_status Sim::setup_amg(Amg<T> &A)
     CK(dalloc((void **)&A.lam, sizeof(double) * kLamSlots));
     CK(dalloc((void **)&A.partial, sizeof(double) * (maxgrid + 64)));
     CK(dalloc((void **)&A.counter, sizeof(uint32_t) * 4));
-    CK(vec(A.fr, 4 * nv));
-    CK(vec(A.fd0, 4 * nv));
-    CK(vec(A.fd1, 4 * nv));
-    CK(vec(A.fv, 4 * nv));
+    CK(vec(A.fr, 4 * nu));
+    CK(vec(A.fd0, 4 * nu));
+    CK(vec(A.fd1, 4 * nu));
+    CK(vec(A.fv, 4 * nu));
 #undef CK
     if (const char *v = getenv("LXNS_VERBOSE"))
         if (*v && *v != '0')
@@ -404,10 +500,10 @@ lx_status Sim::setup_amg(Amg<T> &A)
                         l == A.nlev ? " (dense)" : "", (long long)A.L[l].n, (long long)A.L[l].nnz, A.L[l].lpr);
     LX_HIP(hipMemsetAsync(A.lam, 0, sizeof(double) * kLamSlots, stream));
     LX_HIP(hipMemsetAsync(A.counter, 0, sizeof(uint32_t) * 4, stream));
-    launch_fill<T>(4 * nv, A.fr, T(0), stream);
-    launch_fill<T>(4 * nv, A.fd0, T(0), stream);
-    launch_fill<T>(4 * nv, A.fd1, T(0), stream);
-    launch_fill<T>(4 * nv, A.fv, T(0), stream);
+    launch_fill<T>(4 * nu, A.fr, T(0), stream);
+    launch_fill<T>(4 * nu, A.fd0, T(0), stream);
+    launch_fill<T>(4 * nu, A.fd1, T(0), stream);
+    launch_fill<T>(4 * nu, A.fv, T(0), stream);
     return LX_OK;
 }
 
@@ -476,6 +572,7 @@ struct Ops<double> {
     static double *sw(Sim *s) { return s->d_sw64; }
     static double *Z(Sim *s) { return s->d_Z64; }
     static Amg<double> &amg(Sim *s) { return s->amg64; }
+    static P2Sys<double> &sys(Sim *s) { return s->s64; }
 };
 template <>
 struct Ops<float> {
@@ -488,7 +585,49 @@ struct Ops<float> {
     static float *sw(Sim *s) { return s->d_sw32; }
     static float *Z(Sim *s) { return s->d_Z32; }
     static Amg<float> &amg(Sim *s) { return s->amg32; }
+    static P2Sys<float> &sys(Sim *s) { return s->s32; }
 };
+
+// The preconditioner's view of the system in precision T.
+template <typename T>
+SimpleView<T> Sim::view()
+{
+    if (!p2) return simple_view_p1<T>(pattern(), Ops<T>::val(this));
+    const P2Sys<T> &S = Ops<T>::sys(this);
+    SimpleView<T> V;
+    V.nu = nu;
+    V.np = nv;
+    V.Fp.nv = nu;
+    V.Fp.nblk = S.nf;
+    V.Fp.rowptr = S.fptr;
+    V.Fp.col = S.fcol;
+    V.Fp.diag = d_fdiag;
+    V.Fp.tslot = nullptr;
+    V.F = S.F;
+    V.gptr = S.gptr;
+    V.gcol = S.gcol;
+    V.Gv = S.G;
+    V.gs = S.ng;
+    V.bptr = S.bptr;
+    V.bcol = S.bcol;
+    V.Bv = S.B;
+    V.bs = S.nb;
+    V.cptr = S.cptr;
+    V.ccol = S.ccol;
+    V.Cv = S.C;
+    return V;
+}
+
+// y = A x in precision T (tm: events that time the launch, or null)
+template <typename T>
+void Sim::spmv(const T *x, T *y, const int32_t *done, std::pair<hipEvent_t, hipEvent_t> *tm)
+{
+    if (p2)
+        launch_spmv_p2<T>(Ops<T>::sys(this), x, y, done, stream, tm ? tm->first : nullptr, tm ? tm->second : nullptr);
+    else
+        launch_spmv<T>(pattern(), Ops<T>::val(this), x, y, done, stream, tm ? tm->first : nullptr,
+                       tm ? tm->second : nullptr);
+}
 
 lx_status Sim::read_state()
 {
@@ -537,19 +676,19 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
             launch_gm_start<T>(N, b, nullptr, V, d_st, d_partial, stream);
         } else {
             auto *tm = timer_begin(0, -1, false);
-            launch_spmv<T>(P, val, x, w, nullptr, stream, tm ? tm->first : nullptr, tm ? tm->second : nullptr);
+            spmv<T>(x, w, nullptr, tm);
             launch_gm_start<T>(N, b, w, V, d_st, d_partial, stream);
         }
         const int kmax = std::min(m, max_iters - it);
         for (int k = 0; k < kmax; ++k) {
             T *zk = Z + k * ld;
             if (solver.precond == LX_PC_AMG)
-                launch_simple_amg_apply<T>(P, val, SP.Finv, SP.Dinv, Ops<T>::amg(this), V + k * ld, &d_st->s[k], zk,
-                                           &d_st->done, stream);
+                launch_simple_amg_apply<T>(view<T>(), SP.Finv, SP.Dinv, Ops<T>::amg(this), V + k * ld, &d_st->s[k],
+                                           zk, &d_st->done, stream);
             else
                 launch_simple_apply<T>(P, SP, V + k * ld, &d_st->s[k], zk, &d_st->done, stream);
             auto *tm = timer_begin(0, k, false);
-            launch_spmv<T>(P, val, zk, w, &d_st->done, stream, tm ? tm->first : nullptr, tm ? tm->second : nullptr);
+            spmv<T>(zk, w, &d_st->done, tm);
             launch_gm_orth<T>(N, k, V, ld, w, d_st, d_partial, stream);
         }
         LX_HIP(hipGetLastError());
@@ -590,7 +729,7 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
         }
         if (it >= max_iters && !h_st->converged) {
             // final true residual
-            launch_spmv<T>(P, val, x, w, nullptr, stream);
+            spmv<T>(x, w, nullptr, nullptr);
             launch_gm_start<T>(N, b, w, V, d_st, d_partial, stream);
             s = read_state();
             if (s != LX_OK) return s;
@@ -670,7 +809,7 @@ lx_status Sim::prepare(double t1, StepCoef &C)
                                   stream));
             dirty_gnodal = false;
         }
-        launch_dirichlet_values(n_dir, d_dir_node, d_dir_bc, B, d_x, d_uA, d_gnodal, d_g, stream);
+        launch_dirichlet_values(n_dir, d_dir_node, d_dir_bc, B, p2 ? d_xnode : d_x, d_uA, d_gnodal, d_g, stream);
     }
     return LX_OK;
 }
@@ -681,6 +820,7 @@ lx_status Sim::build_system(double t1, StepCoef &C, lx_step_stats &tstats)
     (void)tstats;
     lx_status ps = prepare(t1, C);
     if (ps != LX_OK) return ps;
+    if (p2) return build_system_p2(t1, C);
     const RowPattern P = pattern();
     if (solver.precision == LX_FP64) {
         launch_fill<double>(N, d_rhs64, 0.0, stream);
@@ -693,7 +833,7 @@ lx_status Sim::build_system(double t1, StepCoef &C, lx_step_stats &tstats)
         launch_dirichlet_rows<double>(n_dir, d_dir_node, d_g, P, d_val64, d_rhs64, stream);
         launch_simple_setup<double>(P, d_val64, d_Finv64, d_Dinv64, d_Sinv64, stream);
         if (solver.precond == LX_PC_AMG)
-            launch_amg_setup<double>(P, d_val64, d_Finv64, d_Dinv64, amg64, stream);
+            launch_amg_setup<double>(view<double>(), d_Finv64, d_Dinv64, amg64, stream);
         else if (solver.schur_degree > 0)
             launch_schur_bound<double>(P, d_val64, d_Dinv64, d_Sinv64, d_sw64, d_st, d_partial, nb_red, stream);
     } else {
@@ -714,9 +854,33 @@ lx_status Sim::build_system(double t1, StepCoef &C, lx_step_stats &tstats)
         launch_dirichlet_rows<float>(n_dir, d_dir_node, d_g, P, d_val32, (float *)nullptr, stream);
         launch_simple_setup<float>(P, d_val32, d_Finv32, d_Dinv32, d_Sinv32, stream);
         if (solver.precond == LX_PC_AMG)
-            launch_amg_setup<float>(P, d_val32, d_Finv32, d_Dinv32, amg32, stream);
+            launch_amg_setup<float>(view<float>(), d_Finv32, d_Dinv32, amg32, stream);
         else if (solver.schur_degree > 0)
             launch_schur_bound<float>(P, d_val32, d_Dinv32, d_Sinv32, d_sw32, d_st, d_partial, nb_red, stream);
+    }
+    LX_HIP(hipGetLastError());
+    return LX_OK;
+}
+
+// P2-P1: element records + slot gathers (FP64), Neumann traction, Dirichlet
+// rows, then the SIMPLE blocks and the AMG hierarchy in the solve precision.
+lx_status Sim::build_system_p2(double t1, StepCoef &C)
+{
+    launch_fill<double>(N, d_rhs64, 0.0, stream);
+    P2AsmArgs A{nt, nv, nu, d_tet, d_nodes, d_x, d_xh, hist(0), hist(1), hist(2), d_f, d_rules, d_rec2,
+                d_finc_ptr, d_finc, d_ginc_ptr, d_ginc, d_binc_ptr, d_binc, d_sinc_ptr, d_sinc, d_fdiag, d_diag};
+    auto *tm = timer_begin(1, 0);
+    launch_assemble_p2(A, C, s64, d_rhs64, stream);
+    timer_end(tm);
+    add_neumann(t1, d_rhs64, nullptr);
+    launch_dirichlet_rows_p2<double>(n_dir, d_dir_node, d_g, s64, d_fdiag, d_rhs64, stream);
+    if (solver.precision == LX_FP64) {
+        launch_simple_setup_p2<double>(s64, d_fdiag, d_Finv64, d_Dinv64, stream);
+        launch_amg_setup<double>(view<double>(), d_Finv64, d_Dinv64, amg64, stream);
+    } else {
+        launch_round_p2(s64, s32, stream);
+        launch_simple_setup_p2<float>(s32, d_fdiag, d_Finv32, d_Dinv32, stream);
+        launch_amg_setup<float>(view<float>(), d_Finv32, d_Dinv32, amg32, stream);
     }
     LX_HIP(hipGetLastError());
     return LX_OK;
@@ -737,13 +901,29 @@ void Sim::add_neumann(double t1, double *out0, double *out1)
             if (h == 0.0) continue;
             for (int c = 0; c < 3; ++c) hc[c] = -h * b.spec.profile.normal[c];
         }
-        launch_neumann(b.nf, b.d_faces, d_x, hn, hc, out0, out1, nullptr, stream);
+        if (p2) {
+            launch_neumann_p2(b.nf, b.d_faces, d_xnode, hn, hc, d_rules, out0, stream);
+            if (out1) launch_neumann_p2(b.nf, b.d_faces, d_xnode, hn, hc, d_rules, out1, stream);
+        } else {
+            launch_neumann(b.nf, b.d_faces, d_x, hn, hc, out0, out1, nullptr, stream);
+        }
     }
 }
 
 // FP64 matrix-free residual r = b - A xs (first: also b and the Dirichlet diagonal).
 lx_status Sim::residual64(const StepCoef &C, const double *xs, bool first, double t1)
 {
+    if (p2) {
+        // b is the assembled FP64 right-hand side; r = b - A64 xs by the FP64 SpMV
+        if (first) LX_HIP(hipMemcpyAsync(d_b64, d_rhs64, sizeof(double) * N, hipMemcpyDeviceToDevice, stream));
+        auto *tm = timer_begin(2, 0);
+        launch_spmv_p2<double>(s64, xs, d_r64, nullptr, stream);
+        timer_end(tm);
+        launch_scale_copy<double, double>(N, d_r64, d_r64, -1.0, stream);
+        launch_axpy<double, double>(N, d_r64, d_b64, nullptr, 1.0, stream);
+        LX_HIP(hipGetLastError());
+        return LX_OK;
+    }
     launch_fill<double>(N, d_r64, 0.0, stream);
     if (first) {
         launch_fill<double>(N, d_b64, 0.0, stream);

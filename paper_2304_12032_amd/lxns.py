@@ -82,7 +82,7 @@ class lx_solver(ctypes.Structure):
 
 class lx_sizes(ctypes.Structure):
     _fields_ = [("n_vertices", c_i64), ("n_tets", c_i64), ("n_u_nodes", c_i64), ("n_dofs", c_i64),
-                ("n_blocks", c_i64), ("device_bytes", c_i64)]
+                ("n_blocks", c_i64), ("device_bytes", c_i64), ("n_edges", c_i64), ("n_scalar_nnz", c_i64)]
 
 
 class lx_step_stats(ctypes.Structure):
@@ -120,6 +120,7 @@ SIGNATURES = {
     "lx_last_error": (ctypes.c_char_p, []),
     "lx_sim_create": (c_i32, [P(lx_device), P(lx_mesh), P(lx_problem), P(lx_solver), P(c_vp)]),
     "lx_sim_query": (c_i32, [c_vp, P(lx_sizes)]),
+    "lx_sim_get_edges": (c_i32, [c_vp, c_vp]),
     "lx_sim_set_state": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
     "lx_sim_set_time": (c_i32, [c_vp, c_dbl]),
     "lx_sim_set_dirichlet_values": (c_i32, [c_vp, c_i32, c_vp]),
@@ -129,6 +130,7 @@ SIGNATURES = {
     "lx_sim_step": (c_i32, [c_vp, P(lx_step_stats)]),
     "lx_sim_get_solution": (c_i32, [c_vp, c_vp, c_vp, P(c_dbl)]),
     "lx_sim_debug_export": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "lx_sim_debug_export_p2": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lx_sim_debug_residual": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "lx_sim_destroy": (None, [c_vp]),
     "lx_server_create": (c_i32, [P(lx_server_cfg), P(c_vp)]),
@@ -264,6 +266,7 @@ class Sim:
         check(L.lx_sim_create(ctypes.byref(dev), ctypes.byref(self.m.mesh), ctypes.byref(self.m.problem),
                               ctypes.byref(self.m.solver), ctypes.byref(h)))
         self.h = h
+        self.nu = self.query()["n_u_nodes"]   # velocity nodes (P2-P1: vertices, then edges())
 
     def close(self):
         if getattr(self, "h", None):
@@ -316,8 +319,29 @@ class Sim:
         d["status"] = rc
         return d
 
+    def edges(self):
+        """[n_edges][2] caller vertex ids of the P2 edge nodes, in node order after the vertices."""
+        ne = self.query()["n_edges"]
+        e = np.zeros((ne, 2), dtype=np.int32)
+        if ne:
+            check(lib().lx_sim_get_edges(self.h, e.ctypes.data))
+        return e
+
+    def export_p2(self):
+        """(rows, cols, vals, rhs) of the coming step's P2-P1 system, scalar COO in the caller's
+        dof numbering (velocity 3 node + c, pressure 3 nu + vertex)."""
+        q = self.query()
+        n = q["n_scalar_nnz"]
+        rows = np.zeros(n, dtype=np.int32)
+        cols = np.zeros(n, dtype=np.int32)
+        vals = np.zeros(n)
+        rhs = np.zeros(q["n_dofs"])
+        check(lib().lx_sim_debug_export_p2(self.h, rows.ctypes.data, cols.ctypes.data, vals.ctypes.data,
+                                           rhs.ctypes.data))
+        return rows, cols, vals, rhs
+
     def solution(self):
-        u = np.zeros((self.nv, 3))
+        u = np.zeros((self.nu, 3))
         p = np.zeros(self.nv)
         t = c_dbl()
         check(lib().lx_sim_get_solution(self.h, u.ctypes.data, p.ctypes.data, ctypes.byref(t)))

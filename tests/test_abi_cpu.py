@@ -61,14 +61,44 @@ def test_vertex_out_of_range_rejected():
     assert ei.value.status == -5
 
 
-@pytest.mark.parametrize("field,value", [("bdf_order", 4), ("dt", 0.0), ("fe", "p2p1")])
+@pytest.mark.parametrize("field,value", [("bdf_order", 4), ("dt", 0.0), ("stab", "bogus")])
 def test_bad_problem_rejected(field, value):
     from paper_2304_12032_amd import LxError
     mesh, prob = beltrami_cube_problem(2)
     setattr(prob, field, value)
-    with pytest.raises(LxError) as ei:
+    with pytest.raises((LxError, KeyError)) as ei:
         _create(mesh, prob, SolverCfg())
+    if isinstance(ei.value, LxError):
+        assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("what", ["ale", "cheb_schur"])
+def test_p2p1_unsupported_options_rejected(what):
+    """P2-P1 is built without ALE and with the AMG preconditioner only: both are
+    rejected during validation, before any device call."""
+    from paper_2304_12032_amd import LxError
+    mesh, prob = beltrami_cube_problem(2)
+    prob.fe = "p2p1"
+    sv = SolverCfg()
+    if what == "ale":
+        prob.ale = True
+    else:
+        sv.precond = "cheb_schur"
+    with pytest.raises(LxError) as ei:
+        _create(mesh, prob, sv)
     assert ei.value.status == -1
+
+
+def test_server_rejects_p2p1_request():
+    from paper_2304_12032_amd import Server, LxError
+    m = tube(nxy=4, nz=8, length=2.0)
+    prob = tube_problem(m)
+    prob.fe = "p2p1"
+    srv = Server(hbm_budget_bytes=1 << 34, max_active=4)
+    with pytest.raises(LxError) as ei:
+        srv.submit(m, prob, SolverCfg(), 5)
+    assert ei.value.status == -1
+    srv.close()
 
 
 def test_bad_restart_rejected():
