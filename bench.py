@@ -36,9 +36,11 @@ def parse():
     ap.add_argument("--nxy", type=int, default=32)
     ap.add_argument("--nz", type=int, default=160)
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32_ir"])
+    ap.add_argument("--fe", default="p1p1", choices=["p1p1", "p2p1"],
+                    help="p2p1: the Taylor-Hood pair (use --nxy 22 --nz 104 for the 302k-tet tube)")
     ap.add_argument("--precond", default="amg", choices=["amg", "cheb_schur"])
-    ap.add_argument("--f-degree", type=int, default=3)
-    ap.add_argument("--f-ratio", type=float, default=5.0)
+    ap.add_argument("--f-degree", type=int, default=0, help="0: library default (3 P1-P1, 8 P2-P1)")
+    ap.add_argument("--f-ratio", type=float, default=0.0, help="0: library default (5 P1-P1, 100 P2-P1)")
     ap.add_argument("--amg-degree", type=int, default=2)
     ap.add_argument("--amg-cycle", type=int, default=2)
     ap.add_argument("--amg-ratio", type=float, default=30.0)
@@ -57,6 +59,14 @@ def spmv_bytes(nblk, nv, s):
     """Algorithmic HBM bytes of one block-CSR SpMV: 16 values + 1 column index per
     block, the row pointer, x read once and y written once (N = 4 nv entries)."""
     return nblk * (16 * s + 4) + 4 * (nv + 1) + 2 * 4 * nv * s
+
+
+def spmv_bytes_p2(q, s):
+    """Algorithmic HBM bytes of one split P2-P1 SpMV: every stored value and one
+    column index per slot, the row pointers of the four parts, x read once and
+    y written once ([nu][4] vectors)."""
+    nu, nv = q["n_u_nodes"], q["n_vertices"]
+    return q["n_scalar_nnz"] * s + 4 * q["n_blocks"] + 4 * (2 * (nu + 1) + 2 * (nv + 1)) + 2 * 4 * nu * s
 
 
 def run_precision(mesh, prob, precision, args, stream, torch):
@@ -137,6 +147,7 @@ def main():
     from inputs.problem import tube_problem
     mesh = tube(nxy=args.nxy, nz=args.nz, seed=0)
     prob = tube_problem(mesh)
+    prob.fe = args.fe
     res = {}
     precs = ["fp64", "fp32_ir"] if args.precision == "both" else [args.precision]
     for p in precs:
@@ -146,7 +157,8 @@ def main():
     q = head["q"]
     nv, nblk = q["n_vertices"], q["n_blocks"]
     s = 4 if headp == "fp32_ir" else 8
-    sb = spmv_bytes(nblk, nv, s)
+    p2 = args.fe == "p2p1"
+    sb = spmv_bytes_p2(q, s) if p2 else spmv_bytes(nblk, nv, s)
     achieved = sb / (head["spmv_avg_ms"] * 1e-3) / 1e9
     out = {
         "metric": "Mdof*steps/s at 1M tets (FP32+refine vs FP64) + p50/p99 step latency",
@@ -157,19 +169,21 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64-refinement" if headp == "fp32_ir" else "f64",
         "data": "synthetic",
-        "config": {"workload": "tube R=1 L=10, %d tets, %d vertices, N=%d, P1-P1 VMS-LES BDF2 dt=1e-3 nu=0.035, "
+        "config": {"workload": "tube R=1 L=10, %d tets, %d vertices, N=%d, %s VMS-LES BDF2 dt=1e-3 nu=0.035, "
                                "pulsatile 50 cm/s inflow, RIIS disc R=1e4 eps=0.05, from rest" %
-                               (q["n_tets"], nv, q["n_dofs"]),
+                               (q["n_tets"], nv, q["n_dofs"], "P2-P1" if p2 else "P1-P1"),
                    "precision": headp, "rel_residual_target": 1e-8, "restart": args.restart,
                    "precond": (("amg: F chebyshev deg %d ratio %g, S~ aggregation AMG cycle %d smoothing deg %d "
-                                "ratio %g") % (args.f_degree, args.f_ratio, args.amg_cycle, args.amg_degree,
-                                               args.amg_ratio)) if args.precond == "amg" else
+                                "ratio %g") % (args.f_degree or (8 if p2 else 3), args.f_ratio or (100 if p2 else 5),
+                                               args.amg_cycle, args.amg_degree, args.amg_ratio))
+                              if args.precond == "amg" else
                               ("cheb_schur deg %d ratio %g" % (args.schur_degree, args.schur_ratio)),
                    "asm_fp64": bool(args.asm_fp64), "inner_rtol": args.inner_rtol},
         "p50_ms": round(float(np.percentile(head["lat"], 50)), 3),
         "p99_ms": round(float(np.percentile(head["lat"], 99)), 3),
         "gmres_iters_per_step": head["iters"],
-        "roofline": {"bound": "hbm", "kernel": "k_spmv<%s>" % ("float" if s == 4 else "double"),
+        "roofline": {"bound": "hbm", "kernel": ("k_spmv_p2u+p2p<%s>" if p2 else "k_spmv<%s>") %
+                                                  ("float" if s == 4 else "double"),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": sb, "avg_launch_ms": round(head["spmv_avg_ms"], 5)},
@@ -181,12 +195,13 @@ def main():
                        "p99_ms": round(float(np.percentile(f64["lat"], 99)), 3),
                        "gmres_iters_per_step": f64["iters"], "max_rel_residual": f64["res"],
                        "spmv_avg_ms": round(f64["spmv_avg_ms"], 5),
-                       "spmv_GBps": round(spmv_bytes(nblk, nv, 8) / (f64["spmv_avg_ms"] * 1e-3) / 1e9, 1)}
+                       "spmv_GBps": round((spmv_bytes_p2(q, 8) if p2 else spmv_bytes(nblk, nv, 8)) /
+                                          (f64["spmv_avg_ms"] * 1e-3) / 1e9, 1)}
         out["fp32_ir"] = {"ir_iters_per_step": head["ir"], "max_rel_residual": head["res"],
                           "resid_kernel_avg_ms": round(head["resid_avg_ms"], 4),
                           "asm_kernel_avg_ms": round(head["asm_kernel_ms"], 4)}
         out["speedup_fp32ir_vs_fp64"] = round(res["fp64"]["wall_s"] / head["wall_s"], 3)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.fe == "p1p1":
         it = res["fp64"]["iters"] if "fp64" in res else head["iters"]
         out["cpu_baseline"] = cpu_baseline(mesh, prob, it, args.cpu_iters)
     print(json.dumps(out), flush=True)

@@ -41,7 +41,7 @@ extern "C" lx_status lx_sim_query(const lx_sim *s, lx_sizes *out)
     out->n_tets = s->nt;
     out->n_u_nodes = s->nu;
     out->n_dofs = 3 * s->nu + s->nv;
-    out->n_blocks = s->nblk;
+    out->n_blocks = s->p2 ? s->s64.nf + s->s64.ng + s->s64.nb + s->s64.nc : s->nblk;
     out->device_bytes = s->device_bytes;
     out->n_edges = s->nu - s->nv;
     out->n_scalar_nnz = s->p2 ? 9 * s->s64.nf + 3 * s->s64.ng + 3 * s->s64.nb + s->s64.nc : 16 * s->nblk;

@@ -101,9 +101,12 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     prob = *pr;
     solver = *sv;
     if (solver.precond == LX_PC_AMG) {
-        if (solver.f_degree == 0) solver.f_degree = 3;
+        // the Jacobi-scaled P2 velocity block (mass-dominated) has a wider spectrum
+        // than the P1 one, so its Chebyshev iteration gets more steps and a wider interval
+        const bool q2 = pr->fe == LX_P2P1;
+        if (solver.f_degree == 0) solver.f_degree = q2 ? 8 : 3;
         if (solver.amg_degree == 0) solver.amg_degree = 2;
-        if (solver.f_ratio == 0.0) solver.f_ratio = 5.0;
+        if (solver.f_ratio == 0.0) solver.f_ratio = q2 ? 100.0 : 5.0;
         if (solver.amg_ratio == 0.0) solver.amg_ratio = 30.0;
         if (solver.amg_cycle == 0) solver.amg_cycle = 2;
     }
