@@ -38,9 +38,12 @@ def parse():
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32_ir"])
     ap.add_argument("--fe", default="p1p1", choices=["p1p1", "p2p1"],
                     help="p2p1: the Taylor-Hood pair (use --nxy 22 --nz 104 for the 302k-tet tube)")
+    ap.add_argument("--case", default="tube", choices=["tube", "chamber"],
+                    help="chamber: truncated spheroid with ALE wall motion and two RIIS valves "
+                         "(--nxy 105 --nz 121: 8.0M tets)")
     ap.add_argument("--precond", default="amg", choices=["amg", "cheb_schur"])
-    ap.add_argument("--f-degree", type=int, default=0, help="0: library default (3 P1-P1, 8 P2-P1)")
-    ap.add_argument("--f-ratio", type=float, default=0.0, help="0: library default (5 P1-P1, 100 P2-P1)")
+    ap.add_argument("--f-degree", type=int, default=0, help="0: library default (3 P1-P1, 12 P2-P1)")
+    ap.add_argument("--f-ratio", type=float, default=0.0, help="0: library default (5 P1-P1, 300 P2-P1)")
     ap.add_argument("--amg-degree", type=int, default=2)
     ap.add_argument("--amg-cycle", type=int, default=2)
     ap.add_argument("--amg-ratio", type=float, default=30.0)
@@ -77,7 +80,12 @@ def run_precision(mesh, prob, precision, args, stream, torch):
                    restart=args.restart, asm_fp64=bool(args.asm_fp64), precond=args.precond,
                    f_degree=args.f_degree, f_ratio=args.f_ratio, amg_degree=args.amg_degree,
                    amg_cycle=args.amg_cycle, amg_ratio=args.amg_ratio)
+    if args.verbose:
+        print("[bench] %s: creating the simulation (%d tets)" % (precision, mesh.nt), file=sys.stderr, flush=True)
     sim = Sim(mesh, prob, sv, device=0, stream=stream)
+    if prob.ale:
+        from inputs.problem import chamber_displacement_shape
+        sim.set_ale_displacement(chamber_displacement_shape(mesh))
     q = sim.query()
     for _ in range(args.warmup):
         sim.step()
@@ -144,9 +152,16 @@ def main():
     torch.cuda.init()
     stream = torch.cuda.current_stream(0).cuda_stream
     from inputs import tube
-    from inputs.problem import tube_problem
-    mesh = tube(nxy=args.nxy, nz=args.nz, seed=0)
-    prob = tube_problem(mesh)
+    from inputs.meshes import spheroid
+    from inputs.problem import chamber_problem, tube_problem
+    if args.verbose:
+        print("[bench] building the %s mesh" % args.case, file=sys.stderr, flush=True)
+    if args.case == "chamber":
+        mesh = spheroid(nyz=args.nxy, nx=args.nz, seed=0)
+        prob = chamber_problem(mesh)
+    else:
+        mesh = tube(nxy=args.nxy, nz=args.nz, seed=0)
+        prob = tube_problem(mesh)
     prob.fe = args.fe
     res = {}
     precs = ["fp64", "fp32_ir"] if args.precision == "both" else [args.precision]
@@ -169,12 +184,18 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64-refinement" if headp == "fp32_ir" else "f64",
         "data": "synthetic",
-        "config": {"workload": "tube R=1 L=10, %d tets, %d vertices, N=%d, %s VMS-LES BDF2 dt=1e-3 nu=0.035, "
-                               "pulsatile 50 cm/s inflow, RIIS disc R=1e4 eps=0.05, from rest" %
-                               (q["n_tets"], nv, q["n_dofs"], "P2-P1" if p2 else "P1-P1"),
+        "config": {"workload": (("tube R=1 L=10, %d tets, %d vertices, N=%d, %s VMS-LES BDF2 dt=1e-3 nu=0.035, "
+                                 "pulsatile 50 cm/s inflow, RIIS disc R=1e4 eps=0.05, from rest" %
+                                 (q["n_tets"], nv, q["n_dofs"], "P2-P1" if p2 else "P1-P1"))
+                                if args.case == "tube" else
+                                ("truncated spheroid (4,3,3) |x|<=3.5, %d tets, %d vertices, N=%d, P1-P1 VMS-LES "
+                                 "BDF2 dt=5e-4 nu=0.035, ALE wall contraction 10%% (0.8 s cycle; the harmonic extension of "
+                                 "the shape is scaled by the law each step), two RIIS annular valves R=1e4 eps=0.1, "
+                                 "from rest" %
+                                 (q["n_tets"], nv, q["n_dofs"]))),
                    "precision": headp, "rel_residual_target": 1e-8, "restart": args.restart,
                    "precond": (("amg: F chebyshev deg %d ratio %g, S~ aggregation AMG cycle %d smoothing deg %d "
-                                "ratio %g") % (args.f_degree or (8 if p2 else 3), args.f_ratio or (100 if p2 else 5),
+                                "ratio %g") % (args.f_degree or (12 if p2 else 3), args.f_ratio or (300 if p2 else 5),
                                                args.amg_cycle, args.amg_degree, args.amg_ratio))
                               if args.precond == "amg" else
                               ("cheb_schur deg %d ratio %g" % (args.schur_degree, args.schur_ratio)),
@@ -201,7 +222,7 @@ def main():
                           "resid_kernel_avg_ms": round(head["resid_avg_ms"], 4),
                           "asm_kernel_avg_ms": round(head["asm_kernel_ms"], 4)}
         out["speedup_fp32ir_vs_fp64"] = round(res["fp64"]["wall_s"] / head["wall_s"], 3)
-    if not args.no_cpu_baseline and args.fe == "p1p1":
+    if not args.no_cpu_baseline and args.fe == "p1p1" and args.case == "tube":
         it = res["fp64"]["iters"] if "fp64" in res else head["iters"]
         out["cpu_baseline"] = cpu_baseline(mesh, prob, it, args.cpu_iters)
     print(json.dumps(out), flush=True)

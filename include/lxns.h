@@ -166,8 +166,8 @@ enum { LX_PC_AMG = 0, LX_PC_CHEB_SCHUR = 1 };
  *     (schur_degree = 0) or a Chebyshev iteration of degree schur_degree with
  *     diagonal scaling over [lam / schur_ratio, lam].
  * A zero in f_degree, amg_degree, amg_cycle, f_ratio or amg_ratio selects its
- * default (f_degree 3 for P1-P1 and 8 for P2-P1, amg_degree 2, amg_cycle 2,
- * f_ratio 5 for P1-P1 and 100 for P2-P1, amg_ratio 30).  LX_FP32_IR: FP32 matrix and FP32 inner GMRES inside an
+ * default (f_degree 3 for P1-P1 and 12 for P2-P1, amg_degree 2, amg_cycle 2,
+ * f_ratio 5 for P1-P1 and 300 for P2-P1, amg_ratio 30).  LX_FP32_IR: FP32 matrix and FP32 inner GMRES inside an
  * FP64 iterative refinement loop that stops when the FP64 residual satisfies
  * ir_rtol; inner solves aim at one more refinement step but never tighter
  * than inner_rtol. */
@@ -184,7 +184,7 @@ typedef struct {
                                 0 = FP32 element arithmetic and FP32 scatter       */
     double schur_ratio;      /* > 1                                                  */
     int32_t precond;         /* LX_PC_AMG | LX_PC_CHEB_SCHUR                         */
-    int32_t f_degree;        /* LX_PC_AMG: 0..8 (0: default, see above)              */
+    int32_t f_degree;        /* LX_PC_AMG: 0..16 (0: default, see above)             */
     int32_t amg_degree;      /* LX_PC_AMG: 0..8 (0: default 2)                       */
     int32_t amg_cycle;       /* LX_PC_AMG: coarse corrections per level below the
                                 finest, 0..3 (0: default 2, a W-cycle there)        */

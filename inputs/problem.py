@@ -92,7 +92,7 @@ class SolverCfg:
     asm_fp64: bool = False
     precond: str = "amg"             # amg | cheb_schur
     f_degree: int = 0                # amg: Chebyshev degree on the velocity block (1 = block Jacobi;
-    f_ratio: float = 0.0             #   0 = library default: 3 / ratio 5 for P1-P1, 8 / 100 for P2-P1)
+    f_ratio: float = 0.0             #   0 = library default: 3 / ratio 5 for P1-P1, 12 / 300 for P2-P1)
     amg_degree: int = 2              # amg: Chebyshev smoothing degree per level
     amg_cycle: int = 2               # amg: coarse corrections per level below the finest (2 = W)
     amg_ratio: float = 30.0

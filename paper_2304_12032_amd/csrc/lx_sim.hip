@@ -91,7 +91,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         if (sv->schur_degree < 0 || sv->schur_degree > 32) return fail(LX_EINVAL, "schur_degree must be 0..32");
         if (sv->schur_degree > 0 && !(sv->schur_ratio > 1.0)) return fail(LX_EINVAL, "schur_ratio must be > 1");
     } else {
-        if (sv->f_degree < 0 || sv->f_degree > 8) return fail(LX_EINVAL, "f_degree must be 0..8");
+        if (sv->f_degree < 0 || sv->f_degree > 16) return fail(LX_EINVAL, "f_degree must be 0..16");
         if (sv->amg_degree < 0 || sv->amg_degree > 8) return fail(LX_EINVAL, "amg_degree must be 0..8");
         if (sv->amg_cycle < 0 || sv->amg_cycle > 3) return fail(LX_EINVAL, "amg_cycle must be 0..3");
         if (sv->f_ratio != 0.0 && !(sv->f_ratio > 1.0)) return fail(LX_EINVAL, "f_ratio must be 0 or > 1");
@@ -104,9 +104,9 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         // the Jacobi-scaled P2 velocity block (mass-dominated) has a wider spectrum
         // than the P1 one, so its Chebyshev iteration gets more steps and a wider interval
         const bool q2 = pr->fe == LX_P2P1;
-        if (solver.f_degree == 0) solver.f_degree = q2 ? 8 : 3;
+        if (solver.f_degree == 0) solver.f_degree = q2 ? 12 : 3;
         if (solver.amg_degree == 0) solver.amg_degree = 2;
-        if (solver.f_ratio == 0.0) solver.f_ratio = q2 ? 100.0 : 5.0;
+        if (solver.f_ratio == 0.0) solver.f_ratio = q2 ? 300.0 : 5.0;
         if (solver.amg_ratio == 0.0) solver.amg_ratio = 30.0;
         if (solver.amg_cycle == 0) solver.amg_cycle = 2;
     }
