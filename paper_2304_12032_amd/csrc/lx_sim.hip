@@ -683,7 +683,16 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
             launch_gm_start<T>(N, b, w, V, d_st, d_partial, stream);
         }
         const int kmax = std::min(m, max_iters - it);
+        // Arnoldi steps are queued in chunks; between chunks the host reads the
+        // device's done flag, so a cycle that converges early leaves at most one
+        // chunk of no-op launches behind instead of the rest of the cycle.
+        const int chunk = 10;
         for (int k = 0; k < kmax; ++k) {
+            if (k > 0 && k % chunk == 0) {
+                LX_HIP(hipMemcpyAsync(&h_st->done, &d_st->done, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+                LX_HIP(hipStreamSynchronize(stream));
+                if (h_st->done) break;
+            }
             T *zk = Z + k * ld;
             if (solver.precond == LX_PC_AMG)
                 launch_simple_amg_apply<T>(view<T>(), SP.Finv, SP.Dinv, Ops<T>::amg(this), V + k * ld, &d_st->s[k],
