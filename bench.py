@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the run, copy 256 MiB device-to-device twice (a plain copy kernel of known "
+                         "size, the reference for scaling the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -70,6 +73,30 @@ def spmv_bytes_p2(q, s):
     y written once ([nu][4] vectors)."""
     nu, nv = q["n_u_nodes"], q["n_vertices"]
     return q["n_scalar_nnz"] * s + 4 * q["n_blocks"] + 4 * (2 * (nu + 1) + 2 * (nv + 1)) + 2 * 4 * nu * s
+
+
+def spmv_source_hash():
+    """SHA-256 (first 16 hex digits) of the k_spmv kernel's source text."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2304_12032_amd", "csrc", "lx_kernels.hip")).read()
+    a = src.index("__global__ __launch_bounds__(256) void k_spmv(")
+    a = src.rfind("template", 0, a)
+    b = src.index("\n}\n", a) + 3
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def spmv_traffic():
+    """HBM bytes per FP32 SpMV launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by a plain copy), or None if the kernel changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "tube983k_spmv_fp32_traffic.md")
+    try:
+        kv = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line and
+                  line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256_16"))
+        if kv.get("kernel_source_sha256_16", "").strip() != spmv_source_hash():
+            return None
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def run_precision(mesh, prob, precision, args, stream, torch):
@@ -206,7 +233,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": ("k_spmv_p2u+p2p<%s>" if p2 else "k_spmv<%s>") %
                                                   ("float" if s == 4 else "double"),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": (spmv_traffic() if (s == 4 and not p2 and args.case == "tube" and args.nxy == 32
+                                                    and args.nz == 160) else None),
                      "bytes_per_launch": sb, "avg_launch_ms": round(head["spmv_avg_ms"], 5)},
     }
     if "fp64" in res and "fp32_ir" in res:
@@ -225,6 +254,13 @@ def main():
     if not args.no_cpu_baseline and args.fe == "p1p1" and args.case == "tube":
         it = res["fp64"]["iters"] if "fp64" in res else head["iters"]
         out["cpu_baseline"] = cpu_baseline(mesh, prob, it, args.cpu_iters)
+    if args.calib_copy:
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = a.numel() * 4
     print(json.dumps(out), flush=True)
 
 
