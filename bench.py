@@ -55,6 +55,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="continuous-batching run instead: --serve-requests tube requests arriving as a Poisson "
+                         "process, sizes uniform over [20k, 500k] tets, FP32+IR, --serve-steps steps each")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-steps", type=int, default=100)
+    ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=0.0, help="HBM admission budget (0: 200 GB)")
+    ap.add_argument("--serve-max-active", type=int, default=64)
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy 256 MiB device-to-device twice (a plain copy kernel of known "
                          "size, the reference for scaling the HBM byte counters)")
@@ -76,13 +84,18 @@ def spmv_bytes_p2(q, s):
 
 
 def spmv_source_hash():
-    """SHA-256 (first 16 hex digits) of the k_spmv kernel's source text."""
+    """SHA-256 (first 16 hex digits) of the k_spmv kernel's source text and of the
+    workgroup remap it calls."""
     import hashlib
-    src = open(os.path.join(ROOT, "paper_2304_12032_amd", "csrc", "lx_kernels.hip")).read()
+    csrc = os.path.join(ROOT, "paper_2304_12032_amd", "csrc")
+    src = open(os.path.join(csrc, "lx_kernels.hip")).read()
     a = src.index("__global__ __launch_bounds__(256) void k_spmv(")
     a = src.rfind("template", 0, a)
     b = src.index("\n}\n", a) + 3
-    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+    dev = open(os.path.join(csrc, "lx_device.h")).read()
+    c = dev.index("__device__ inline int64_t xcd_block()")
+    d = dev.index("\n}\n", c) + 3
+    return hashlib.sha256((src[a:b] + dev[c:d]).encode()).hexdigest()[:16]
 
 
 def spmv_traffic():
@@ -168,6 +181,71 @@ def cpu_baseline(mesh, prob, iters_per_step, n_iters):
                       % (mesh.nt, t_asm, n_iters, t_it, iters_per_step)}
 
 
+def serve(args, torch):
+    """Continuous batching: requests are generated ahead (seeded: sizes, viscosity, inflow peak,
+    Poisson arrival times), submitted when their arrival time passes, and stepped by the server's
+    ticks; prints one JSON line with throughput and per-(request, step) latency percentiles."""
+    from paper_2304_12032_amd import Server
+    from inputs.meshes import tube_for_target
+    from inputs.problem import SolverCfg, tube_problem
+    from inputs.rng import uniform01
+    n = args.serve_requests
+    u = uniform01(1, 4 * n).reshape(n, 4)
+    sizes = 20000 + u[:, 0] * 480000
+    nus = 0.02 + u[:, 1] * 0.03
+    peaks = 20.0 + u[:, 2] * 60.0
+    arrivals = np.cumsum(-np.log(1.0 - u[:, 3]) / args.serve_rate)
+    reqs = []
+    for i in range(n):
+        m = tube_for_target(int(sizes[i]), seed=i)
+        reqs.append((m, tube_problem(m, mu=float(nus[i]), peak=float(peaks[i]))))
+        if args.verbose and i % 8 == 0:
+            print("[bench] generated request %d (%d tets)" % (i, m.nt), file=sys.stderr, flush=True)
+    budget = int((args.serve_budget_gb or 200.0) * (1 << 30))
+    srv = Server(hbm_budget_bytes=budget, max_active=args.serve_max_active, n_streams=8)
+    sv = SolverCfg(precision="fp32_ir", rtol=1e-8, ir_rtol=1e-8, max_iters=20000)
+    tickets, done, lat = {}, {}, []
+    nxt, t_print = 0, 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while len(done) < n:
+        now = time.perf_counter() - t0
+        while nxt < n and arrivals[nxt] <= now:
+            m, pr = reqs[nxt]
+            tickets[srv.submit(m, pr, sv, args.serve_steps)] = nxt
+            nxt += 1
+        active = srv.tick()
+        for t, i in list(tickets.items()):
+            if t in done:
+                continue
+            st = srv.poll(t)["state"]
+            if st in ("done", "failed"):
+                _, _, ls = srv.result(t)
+                done[t] = i
+                lat.append(ls)
+        if active == 0 and nxt < n:
+            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+        if args.verbose and time.perf_counter() - t0 >= t_print:
+            t_print += 2.0
+            print("[bench] t=%.1f s: %d submitted, %d active, %d done" % (time.perf_counter() - t0, nxt, active,
+                  len(done)), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dofs = sum(4 * reqs[i][0].nv for i in range(n)) * args.serve_steps
+    out = {"metric": "serving: Mdof*steps/s over all requests + per-(request, step) latency", "unit": "Mdof*steps/s",
+           "value": round(dofs / wall / 1e6, 4), "n_gpus": 1, "data": "synthetic", "dtype": "f32+f64-refinement",
+           "config": {"workload": "%d tube requests, Poisson arrivals %.1f/s, 20k-500k tets, nu U[0.02,0.05], "
+                                  "peak U[20,80] cm/s, %d BDF2 P1-P1 steps each, FP32+IR to 1e-8, budget %.0f GB"
+                                  % (n, args.serve_rate, args.serve_steps, budget / (1 << 30))},
+           "wall_s": round(wall, 3),
+           "step_p50_ms_median_over_requests": round(float(np.median([l["step_p50_ms"] for l in lat])), 3),
+           "step_p99_ms_max_over_requests": round(float(np.max([l["step_p99_ms"] for l in lat])), 3),
+           "admit_wait_ms_p50": round(float(np.median([l["admit_wait_ms"] for l in lat])), 3),
+           "admit_wait_ms_max": round(float(np.max([l["admit_wait_ms"] for l in lat])), 3)}
+    srv.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -177,6 +255,9 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.init()
+    if args.serve:
+        serve(args, torch)
+        return
     stream = torch.cuda.current_stream(0).cuda_stream
     from inputs import tube
     from inputs.meshes import spheroid

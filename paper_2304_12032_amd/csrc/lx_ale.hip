@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_ale_rhs(int64_t nv, const int32_t *rowp
                                                  const double *Lfull, const int32_t *mark, const double *shape,
                                                  double scale, double *rhs, double *d0)
 {
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kAleLPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / kAleLPR;
     const int lane = threadIdx.x % kAleLPR;
     if (row >= nv) return;
     double y[3] = {0, 0, 0};
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_cg_init(int64_t nv, const int32_t *rowp
                                                  double *partial, double rtol)
 {
     __shared__ double lds[4 * 9];
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kAleLPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / kAleLPR;
     const int lane = threadIdx.x % kAleLPR;
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (row < nv) {
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_cg_ap(int64_t nv, const int32_t *rowptr
 {
     if (st->done) return;
     __shared__ double lds[4 * 3];
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kAleLPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / kAleLPR;
     const int lane = threadIdx.x % kAleLPR;
     double acc[3] = {0, 0, 0};
     if (row < nv) {

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void k_schur_form(SimpleView<T> V, const T *__
                                                     const int32_t *__restrict__ srow,
                                                     const int32_t *__restrict__ scol, T *__restrict__ sval)
 {
-    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t i = (xcd_block() * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (i >= V.np) return;
     const int64_t nu = V.nu;
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_amg_rowinfo(int64_t n, const int32_t *_
                                                      T *__restrict__ dinv, double *partial)
 {
     __shared__ double lds[4];
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     double s = 0;
     if (row < n)
@@ -122,7 +122,7 @@ template <typename T>
 __global__ void k_amg_coarsen(int64_t nnzc, const int32_t *__restrict__ cptr, const int32_t *__restrict__ cidx,
                               const T *__restrict__ fval, T *__restrict__ cval)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= nnzc) return;
     double s = 0;
     for (int32_t q = cptr[c]; q < cptr[c + 1]; ++q) s += (double)fval[cidx[q]];
@@ -132,7 +132,7 @@ __global__ void k_amg_coarsen(int64_t nnzc, const int32_t *__restrict__ cptr, co
 // aug = [0 | I] (nc x 2nc, row-major)
 __global__ void k_dense_init(int64_t nc, double *aug)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = xcd_block() * blockDim.x + threadIdx.x;
     if (q >= 2 * nc * nc) return;
     const int64_t r = q / (2 * nc), c = q % (2 * nc);
     aug[q] = (c == nc + r) ? 1.0 : 0.0;
@@ -142,7 +142,7 @@ template <typename T>
 __global__ void k_dense_scatter(int64_t nnz, int64_t nc, const int32_t *__restrict__ crow,
                                 const int32_t *__restrict__ col, const T *__restrict__ val, double *aug)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = xcd_block() * blockDim.x + threadIdx.x;
     if (k >= nnz) return;
     aug[(int64_t)crow[k] * 2 * nc + col[k]] = (double)val[k];
 }
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void k_fpow(RowPattern P, const T *__restrict_
                                               int slot_in, double *partial)
 {
     __shared__ double lds[16];
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     const int64_t nb = P.nblk, nv = P.nv;
     using V = typename V4<T>::type;
@@ -304,7 +304,7 @@ __global__ void k_fz_start(int64_t nv, const T *__restrict__ Finv, const T *__re
                            const double *lamF, double ratio, int degree, const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= nv) return;
     const double sc = scale_ptr ? *scale_ptr : 1.0;
     using V = typename V4<T>::type;
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(256) void k_fcheb(RowPattern P, const T *__restrict
                                                const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= P.nv) return;
     const int64_t nb = P.nblk, nv = P.nv;
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(256) void k_zp_amg(SimpleView<T> V, const T *__rest
                                                 const double *lam, double ratio, int smooth, const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= V.np) return;
     using VT = typename V4<T>::type;
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(256) void k_xu_amg(SimpleView<T> V, const T *__rest
                                                 const T *__restrict__ p, const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= V.nu) return;
     const int64_t nu = V.nu;
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(256) void k_amg_pre(AmgLevel<T> L, const T *__restr
                                                  const double *lam, double ratio, const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t i = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (i >= L.n) return;
     double s = 0;
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void k_amg_cheb(AmgLevel<T> L, T *__restrict__
                                                   const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= L.n) return;
     double q = 0;
@@ -515,7 +515,7 @@ template <typename T, int LPR>
 __global__ __launch_bounds__(256) void k_amg_resid(AmgLevel<T> L, const T *__restrict__ x, const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= L.n) return;
     double q = 0;
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(256) void k_amg_post0(AmgLevel<T> L, const T *__res
                                                    double ratio, const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= L.n) return;
     double q = 0;
@@ -586,12 +586,11 @@ static unsigned flat_grid(int64_t n) { return (unsigned)((n + 255) / 256); }
 // Lanes per block row of the velocity-block passes (LXNS_LPR overrides, 4/8/16).
 static int block_lpr()
 {
-    static int v = 0;
-    if (v == 0) {
+    static const int v = [] {
         const char *e = getenv("LXNS_LPR");
         const int x = e ? atoi(e) : 8;
-        v = (x == 4 || x == 8 || x == 16) ? x : 8;
-    }
+        return (x == 4 || x == 8 || x == 16) ? x : 8;
+    }();
     return v;
 }
 

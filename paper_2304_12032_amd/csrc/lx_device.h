@@ -19,6 +19,18 @@ __device__ inline float lx_sqrt(float x) { return sqrtf(x); }
 __device__ inline void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 __device__ inline void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 
+// Workgroup index with the grid split into 8 contiguous ranges, one per die
+// (XCD): the dispatcher hands workgroups to the dies round-robin, so
+// workgroup w runs on die w % 8, and range w % 8 keeps rows that share
+// gathered data (element records, neighbouring x blocks) in one die's L2
+// rather than fetching them once per die.  A bijection for any grid size.
+__device__ inline int64_t xcd_block()
+{
+    const uint32_t n = gridDim.x, w = blockIdx.x;
+    const uint32_t per = n >> 3, rem = n & 7, die = w & 7, local = w >> 3;
+    return (int64_t)(die < rem ? die * (per + 1) : rem * (per + 1) + (die - rem) * per) + local;
+}
+
 template <typename T, int LPR>
 __device__ inline T group_sum(T v)
 {

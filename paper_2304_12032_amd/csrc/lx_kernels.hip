@@ -244,7 +244,7 @@ static_assert(kRRhs + 16 <= kRec, "element record too small");
 template <typename T, bool RHS>
 __global__ __launch_bounds__(256) void k_element_p1(AsmArgs<T> A, StepCoef C)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = xcd_block() * blockDim.x + threadIdx.x;
     if (e >= A.nt) return;
     Elem<T> E;
     load_elem<T>(E, e, A.nt, A.tet, A.x, A.xh, A.h0, A.h1, A.h2, A.uA, A.f, C);
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(256) void k_element_p1(AsmArgs<T> A, StepCoef C)
 template <typename T, bool RHS>
 __global__ __launch_bounds__(256) void k_gather_p1(AsmArgs<T> A, int symgrad)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = xcd_block() * blockDim.x + threadIdx.x;
     if (k >= A.nblk) return;
     double acc[16];
 #pragma unroll
@@ -431,7 +431,7 @@ template void launch_assemble_p1<float>(const AsmArgs<float> &, const StepCoef &
 // fixed order of the vertex's incidence list.
 __global__ __launch_bounds__(256) void k_residual_p1(ResArgs A, StepCoef C)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = xcd_block() * blockDim.x + threadIdx.x;
     if (e >= A.nt) return;
     Elem<double> E;
     load_elem<double>(E, e, A.nt, A.tet, A.x, A.xh, A.h0, A.h1, A.h2, A.uA, A.f, C);
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(256) void k_residual_p1(ResArgs A, StepCoef C)
 // Dirichlet diagonal once.
 __global__ __launch_bounds__(256) void k_residual_gather(ResArgs A)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= A.nv) return;
     const int32_t k = A.diag[i];
     double r[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0}, d[3] = {0, 0, 0};
@@ -578,7 +578,7 @@ void launch_residual_p1(const ResArgs &a, const StepCoef &c, hipStream_t s)
 __global__ void k_dirichlet_values(int64_t n_dir, const int32_t *dir_node, const int32_t *dir_bc, BCSet S,
                                    const double *x, const double *uA, const double *gnodal, double *g)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = xcd_block() * blockDim.x + threadIdx.x;
     if (k >= n_dir) return;
     const int64_t v = dir_node[k];
     const BCVal &B = S.bc[dir_bc[k]];
@@ -618,7 +618,7 @@ template <typename T>
 __global__ void k_dirichlet_rows(int64_t n_dir, const int32_t *dir_node, const double *g, RowPattern P, T *val,
                                  T *rhs)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = xcd_block() * blockDim.x + threadIdx.x;
     if (k >= n_dir) return;
     const int64_t i = dir_node[k];
     const int64_t dk = P.diag[i];
@@ -650,7 +650,7 @@ template void launch_dirichlet_rows<float>(int64_t, const int32_t *, const doubl
 __global__ void k_dirichlet_residual(int64_t n_dir, const int32_t *dir_node, const double *g, const double *dg,
                                      const double *xs, double *r, double *b)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = xcd_block() * blockDim.x + threadIdx.x;
     if (k >= n_dir) return;
     const int64_t i = dir_node[k];
     for (int c = 0; c < 3; ++c) {
@@ -672,7 +672,7 @@ void launch_dirichlet_residual(int64_t n_dir, const int32_t *dir_node, const dou
 __global__ void k_neumann(int64_t nf, const int32_t *faces, const double *x, const double *hn, double h0,
                           double h1, double h2, double *o0, double *o1, float *o32)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = xcd_block() * blockDim.x + threadIdx.x;
     if (e >= nf) return;
     int64_t v[3] = {faces[3 * e], faces[3 * e + 1], faces[3 * e + 2]};
     double a[3], b[3];
@@ -713,7 +713,7 @@ void launch_neumann(int64_t nf, const int32_t *faces, const double *x, const dou
 template <typename T>
 __global__ void k_simple_setup(RowPattern P, const T *val, T *Finv, T *Dinv, T *Sinv)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= P.nv) return;
     const int64_t nb = P.nblk, nv = P.nv, dk = P.diag[i];
     double A[9];
@@ -753,7 +753,7 @@ constexpr int kLPR = 16;
 template <typename T, int LPR>
 __global__ __launch_bounds__(256) void k_schur_ag(RowPattern P, const T *val, const T *Dinv, T *ag)
 {
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= P.nv) return;
     const int64_t nb = P.nblk, nv = P.nv;
@@ -777,7 +777,7 @@ __global__ __launch_bounds__(256) void k_schur_ag(RowPattern P, const T *val, co
 template <typename T, int LPR>
 __global__ __launch_bounds__(256) void k_schur_gers(RowPattern P, const T *val, const T *Sinv, const T *ag, T *gers)
 {
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= P.nv) return;
     const int64_t nb = P.nblk, nv = P.nv;
@@ -836,7 +836,7 @@ __global__ void k_simple_zu(int64_t nv, const T *Finv, const T *r, const double 
                             const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= nv) return;
     const T sc = scale_ptr ? (T)(*scale_ptr) : T(1);
     using V = typename V4<T>::type;
@@ -858,7 +858,7 @@ __global__ __launch_bounds__(256) void k_simple_zp(RowPattern P, const T *val, c
                                                    const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= P.nv) return;
     const int64_t nb = P.nblk;
@@ -892,7 +892,7 @@ __global__ __launch_bounds__(256) void k_cheb_gd(RowPattern P, const T *val, con
                                                  const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= P.nv) return;
     const int64_t nb = P.nblk, nv = P.nv;
@@ -921,7 +921,7 @@ __global__ __launch_bounds__(256) void k_cheb_step(RowPattern P, const T *val, c
                                                    const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= P.nv) return;
     const int64_t nb = P.nblk;
@@ -951,7 +951,7 @@ __global__ __launch_bounds__(256) void k_simple_xu(RowPattern P, const T *val, c
                                                    const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= P.nv) return;
     const int64_t nb = P.nblk, nv = P.nv;
@@ -976,12 +976,11 @@ __global__ __launch_bounds__(256) void k_simple_xu(RowPattern P, const T *val, c
 // Lanes per block row of the sparse row passes (4, 8 or 16; LXNS_LPR overrides).
 static int lanes_per_row()
 {
-    static int v = 0;
-    if (v == 0) {
+    static const int v = [] {
         const char *e = getenv("LXNS_LPR");
-        int x = e ? atoi(e) : 8;
-        v = (x == 4 || x == 8 || x == 16) ? x : 8;
-    }
+        const int x = e ? atoi(e) : 8;
+        return (x == 4 || x == 8 || x == 16) ? x : 8;
+    }();
     return v;
 }
 
@@ -1030,7 +1029,7 @@ __global__ __launch_bounds__(256) void k_spmv(RowPattern P, const T *__restrict_
                                               T *__restrict__ y, const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= P.nv) return;
     const int64_t nb = P.nblk;
@@ -1066,12 +1065,11 @@ __global__ __launch_bounds__(256) void k_spmv(RowPattern P, const T *__restrict_
 // Lanes per block row of the SpMV (4, 8 or 16; LXNS_LPR_SPMV overrides).
 static int lanes_per_row_spmv()
 {
-    static int v = 0;
-    if (v == 0) {
+    static const int v = [] {
         const char *e = getenv("LXNS_LPR_SPMV");
-        int x = e ? atoi(e) : 16;
-        v = (x == 4 || x == 8 || x == 16) ? x : 16;
-    }
+        const int x = e ? atoi(e) : 16;
+        return (x == 4 || x == 8 || x == 16) ? x : 16;
+    }();
     return v;
 }
 
@@ -1452,7 +1450,7 @@ template void launch_scale_copy<double, float>(int64_t, double *, const float *,
 
 __global__ void k_set_dirichlet_x(int64_t n_dir, const int32_t *dir_node, const double *g, double *xs)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = xcd_block() * blockDim.x + threadIdx.x;
     if (k >= n_dir) return;
     const int64_t i = dir_node[k];
     for (int c = 0; c < 3; ++c) xs[4 * i + c] = g[3 * k + c];

@@ -2,12 +2,14 @@
 //
 // Requests queue in arrival order.  Every tick admits queued requests while
 // the summed device footprint stays under the budget and a slot is free (first
-// come, first served: a request that does not fit blocks the ones behind it),
+// come, first served: a request that does not fit blocks the ones behind it;
+// the admitted ones are set up concurrently),
 // advances every active simulation by one time step -- each simulation on one
 // of a pool of HIP streams, driven by its own host thread so that the device
 // work of different simulations overlaps -- and retires finished requests,
 // freeing their memory and slot for the next tick.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -88,6 +90,9 @@ int64_t estimate_footprint(const Request &r)
     if (r.problem.ale) b += nv * 8 * 3 * 12 + nblk * 16;
     return b + (1 << 20);
 }
+
+// Host threads that create admitted simulations concurrently.
+constexpr int kCreateThreads = 8;
 
 }  // namespace
 
@@ -193,32 +198,60 @@ extern "C" lx_status lx_server_tick(lx_server *srv, int32_t *n_active)
     if (!srv) return fail(LX_EINVAL, "server is NULL");
     lx_status es = ensure_streams(srv);
     if (es != LX_OK) return es;
-    // 1. admission, first come first served
-    while (!srv->queue.empty() && (int)srv->active.size() < srv->cfg.max_active) {
+    // 1. admission, first come first served, by the footprint estimates; the
+    // admitted simulations are then created concurrently (their host set-up
+    // dominates) and charged their real footprint afterwards
+    std::vector<int64_t> admit;
+    int64_t planned = srv->used_bytes;
+    while (!srv->queue.empty() && (int)(srv->active.size() + admit.size()) < srv->cfg.max_active) {
         Request &r = *srv->reqs[srv->queue.front()];
-        if (srv->used_bytes + r.footprint > srv->cfg.hbm_budget_bytes) break;
-        const int64_t ticket = srv->queue.front();
+        if (planned + r.footprint > srv->cfg.hbm_budget_bytes) break;
+        planned += r.footprint;
+        admit.push_back(srv->queue.front());
         srv->queue.pop_front();
-        r.stream_index = srv->next_stream++ % (int)srv->streams.size();
-        lx_device dev{srv->cfg.device.device, (void *)srv->streams[r.stream_index]};
-        lx_mesh m = r.mesh();
-        lx_status st = lx_sim_create(&dev, &m, &r.problem, &r.solver, &r.sim);
-        r.t_admit = Clock::now();
-        srv->used_bytes += r.footprint;
-        if (st != LX_OK) {
-            r.error = lx_last_error();
-            retire(srv, r, false);
-            continue;
+    }
+    if (!admit.empty()) {
+        std::vector<lx_status> cst(admit.size(), LX_OK);
+        std::vector<std::string> cerr(admit.size());
+        for (size_t i = 0; i < admit.size(); ++i) {
+            Request &r = *srv->reqs[admit[i]];
+            r.stream_index = srv->next_stream++ % (int)srv->streams.size();
+            srv->used_bytes += r.footprint;
         }
-        // account the real footprint from now on
-        srv->used_bytes += r.sim->device_bytes - r.footprint;
-        r.footprint = r.sim->device_bytes;
-        r.state = LX_REQ_RUNNING;
-        if (r.n_steps == 0) {
-            retire(srv, r, true);
-            continue;
+        std::atomic<size_t> next{0};
+        auto work = [&]() {
+            (void)hipSetDevice(srv->cfg.device.device);
+            for (size_t i; (i = next.fetch_add(1)) < admit.size();) {
+                Request &r = *srv->reqs[admit[i]];
+                lx_device dev{srv->cfg.device.device, (void *)srv->streams[r.stream_index]};
+                lx_mesh m = r.mesh();
+                cst[i] = lx_sim_create(&dev, &m, &r.problem, &r.solver, &r.sim);
+                if (cst[i] != LX_OK) cerr[i] = lx_last_error();
+                r.t_admit = Clock::now();
+            }
+        };
+        const size_t nw = std::min(admit.size(), (size_t)kCreateThreads);
+        std::vector<std::thread> pool;
+        for (size_t w = 1; w < nw; ++w) pool.emplace_back(work);
+        work();
+        for (auto &t : pool) t.join();
+        for (size_t i = 0; i < admit.size(); ++i) {
+            Request &r = *srv->reqs[admit[i]];
+            if (cst[i] != LX_OK) {
+                r.error = cerr[i];
+                retire(srv, r, false);
+                continue;
+            }
+            // account the real footprint from now on
+            srv->used_bytes += r.sim->device_bytes - r.footprint;
+            r.footprint = r.sim->device_bytes;
+            r.state = LX_REQ_RUNNING;
+            if (r.n_steps == 0) {
+                retire(srv, r, true);
+                continue;
+            }
+            srv->active.push_back(admit[i]);
         }
-        srv->active.push_back(ticket);
     }
     // 2. one step of every active simulation, concurrently
     const Clock::time_point eligible = Clock::now();

@@ -643,12 +643,11 @@ lx_status Sim::read_state()
 
 static bool verbose()
 {
-    static int v = -1;
-    if (v < 0) {
+    static const bool v = [] {
         const char *e = getenv("LXNS_VERBOSE");
-        v = (e && *e && *e != '0') ? 1 : 0;
-    }
-    return v == 1;
+        return e && *e && *e != '0';
+    }();
+    return v;
 }
 
 // Flexible (right-preconditioned) restarted GMRES(m) with CGS2 orthogonalisation:
