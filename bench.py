@@ -55,6 +55,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--t0", type=float, default=0.0, help="tube: start time of the run")
+    ap.add_argument("--init", default="rest", choices=["rest", "poiseuille"],
+                    help="tube: initial state (poiseuille: the Poiseuille field at the inflow rate of t0 and "
+                         "t0 - dt)")
     ap.add_argument("--serve", action="store_true",
                     help="continuous-batching run instead: --serve-requests tube requests arriving as a Poisson "
                          "process, sizes uniform over [20k, 500k] tets, FP32+IR, --serve-steps steps each")
@@ -63,6 +67,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-budget-gb", type=float, default=0.0, help="HBM admission budget (0: 200 GB)")
     ap.add_argument("--serve-max-active", type=int, default=64)
+    ap.add_argument("--serve-verify", type=int, default=4,
+                    help="replay this many requests (the smallest, plus the largest) alone afterwards and "
+                         "compare with their results in the mix")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy 256 MiB device-to-device twice (a plain copy kernel of known "
                          "size, the reference for scaling the HBM byte counters)")
@@ -123,6 +130,10 @@ def run_precision(mesh, prob, precision, args, stream, torch):
     if args.verbose:
         print("[bench] %s: creating the simulation (%d tets)" % (precision, mesh.nt), file=sys.stderr, flush=True)
     sim = Sim(mesh, prob, sv, device=0, stream=stream)
+    if args.init == "poiseuille":
+        from inputs.problem import tube_poiseuille_state
+        for lev in range(prob.bdf_order):
+            sim.set_state(lev, *tube_poiseuille_state(mesh, prob, prob.t0 - lev * prob.dt))
     if prob.ale:
         from inputs.problem import chamber_displacement_shape
         sim.set_ale_displacement(chamber_displacement_shape(mesh))
@@ -156,6 +167,23 @@ def run_precision(mesh, prob, precision, args, stream, torch):
         "resid_avg_ms": sum(s["resid_ms"] for s in stats) / max(sum(s["resid_calls"] for s in stats), 1),
         "asm_kernel_ms": sum(s["asm_ms"] for s in stats) / max(sum(s["asm_calls"] for s in stats), 1),
     }
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (bytes read + bytes written per second, GB/s) of a
+    1 GiB buffer: the attainable-bandwidth reference beside the vendor peak."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbs
 
 
 def cpu_baseline(mesh, prob, iters_per_step, n_iters):
@@ -204,7 +232,9 @@ def serve(args, torch):
     budget = int((args.serve_budget_gb or 200.0) * (1 << 30))
     srv = Server(hbm_budget_bytes=budget, max_active=args.serve_max_active, n_streams=8)
     sv = SolverCfg(precision="fp32_ir", rtol=1e-8, ir_rtol=1e-8, max_iters=20000)
-    tickets, done, lat = {}, {}, []
+    tickets, done, lat, mix, failed = {}, {}, [], {}, []
+    order = np.argsort(sizes, kind="stable")
+    verify = set(order[:args.serve_verify].tolist()) | ({int(order[-1])} if args.serve_verify > 0 else set())
     nxt, t_print = 0, 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -220,9 +250,15 @@ def serve(args, torch):
                 continue
             st = srv.poll(t)["state"]
             if st in ("done", "failed"):
-                _, _, ls = srv.result(t)
                 done[t] = i
+                try:
+                    uu, pp, ls = srv.result(t)
+                except Exception as ex:     # a failed request: reported, not timed
+                    failed.append("request %d: %s" % (i, ex))
+                    continue
                 lat.append(ls)
+                if i in verify:
+                    mix[i] = (uu, pp)
         if active == 0 and nxt < n:
             time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
         if args.verbose and time.perf_counter() - t0 >= t_print:
@@ -241,8 +277,29 @@ def serve(args, torch):
            "step_p50_ms_median_over_requests": round(float(np.median([l["step_p50_ms"] for l in lat])), 3),
            "step_p99_ms_max_over_requests": round(float(np.max([l["step_p99_ms"] for l in lat])), 3),
            "admit_wait_ms_p50": round(float(np.median([l["admit_wait_ms"] for l in lat])), 3),
-           "admit_wait_ms_max": round(float(np.max([l["admit_wait_ms"] for l in lat])), 3)}
+           "admit_wait_ms_max": round(float(np.max([l["admit_wait_ms"] for l in lat])), 3),
+           "failed": failed}
     srv.close()
+    if verify:
+        # the same requests, each alone on a fresh server: deterministic mode makes the
+        # result independent of what else runs
+        n_eq, worst = 0, 0.0
+        for i in sorted(verify):
+            if i not in mix:
+                continue
+            one = Server(hbm_budget_bytes=budget, max_active=1, n_streams=1)
+            m, pr = reqs[i]
+            t = one.submit(m, pr, sv, args.serve_steps)
+            while one.poll(t)["state"] not in ("done", "failed"):
+                one.tick()
+            ua, pa, _ = one.result(t)
+            one.close()
+            um, pm = mix[i]
+            n_eq += int(np.array_equal(ua, um) and np.array_equal(pa, pm))
+            worst = max(worst, float(np.linalg.norm(ua - um) / max(np.linalg.norm(um), 1e-300)),
+                        float(np.linalg.norm(pa - pm) / max(np.linalg.norm(pm), 1e-300)))
+        out["alone_vs_mix"] = {"requests": sorted(int(i) for i in verify), "bitwise_equal": n_eq,
+                               "max_rel_diff": worst}
     print(json.dumps(out), flush=True)
 
 
@@ -269,7 +326,7 @@ def main():
         prob = chamber_problem(mesh)
     else:
         mesh = tube(nxy=args.nxy, nz=args.nz, seed=0)
-        prob = tube_problem(mesh)
+        prob = tube_problem(mesh, t0=args.t0)
     prob.fe = args.fe
     res = {}
     precs = ["fp64", "fp32_ir"] if args.precision == "both" else [args.precision]
@@ -283,6 +340,7 @@ def main():
     p2 = args.fe == "p2p1"
     sb = spmv_bytes_p2(q, s) if p2 else spmv_bytes(nblk, nv, s)
     achieved = sb / (head["spmv_avg_ms"] * 1e-3) / 1e9
+    copy_gbs = copy_bandwidth(torch)
     out = {
         "metric": "Mdof*steps/s at 1M tets (FP32+refine vs FP64) + p50/p99 step latency",
         "value": round(head["mdofs"], 4),
@@ -293,8 +351,10 @@ def main():
         "dtype": "f32+f64-refinement" if headp == "fp32_ir" else "f64",
         "data": "synthetic",
         "config": {"workload": (("tube R=1 L=10, %d tets, %d vertices, N=%d, %s VMS-LES BDF2 dt=1e-3 nu=0.035, "
-                                 "pulsatile 50 cm/s inflow, RIIS disc R=1e4 eps=0.05, from rest" %
-                                 (q["n_tets"], nv, q["n_dofs"], "P2-P1" if p2 else "P1-P1"))
+                                 "pulsatile 50 cm/s inflow, RIIS disc R=1e4 eps=0.05, %s" %
+                                 (q["n_tets"], nv, q["n_dofs"], "P2-P1" if p2 else "P1-P1",
+                                  "from rest" if args.init == "rest" else
+                                  "from the Poiseuille field at t0=%g s" % args.t0))
                                 if args.case == "tube" else
                                 ("truncated spheroid (4,3,3) |x|<=3.5, %d tets, %d vertices, N=%d, P1-P1 VMS-LES "
                                  "BDF2 dt=5e-4 nu=0.035, ALE wall contraction 10%% (0.8 s cycle; the harmonic extension of "
@@ -317,7 +377,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": (spmv_traffic() if (s == 4 and not p2 and args.case == "tube" and args.nxy == 32
                                                     and args.nz == 160) else None),
-                     "bytes_per_launch": sb, "avg_launch_ms": round(head["spmv_avg_ms"], 5)},
+                     "bytes_per_launch": sb, "avg_launch_ms": round(head["spmv_avg_ms"], 5),
+                     "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
     }
     if "fp64" in res and "fp32_ir" in res:
         f64 = res["fp64"]

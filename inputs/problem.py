@@ -134,6 +134,24 @@ def tube_problem(mesh, mu=0.035, dt=1e-3, bdf_order=2, peak=50.0, period=1.0, va
                    bcs=bcs, valves=valves)
 
 
+def tube_poiseuille_state(mesh, prob, t):
+    """Steady Poiseuille field of the tube at the inflow rate of time t (an initial
+    condition, not a solution of the stabilised discrete problem): u_z = 2 g(t) / (pi r^2)
+    (1 - rho^2 / r^2) with g the pulsatile flow-rate law of the inlet, and the matching
+    linear pressure drop 8 mu g(t) / (pi r^4) (L - z) to a zero outlet pressure."""
+    r = mesh.info.get("radius", 1.0)
+    L = mesh.info.get("length", 10.0)
+    inlet = [b for b in prob.bcs if b.type == "dirichlet"][0]
+    gmin, gmax, period = inlet.law.p
+    g = gmin + (gmax - gmin) * 0.5 * (1.0 - np.cos(2.0 * np.pi * t / period))
+    x = mesh.coords
+    rr = np.minimum((x[:, 0] ** 2 + x[:, 1] ** 2) / (r * r), 1.0)
+    u = np.zeros_like(x)
+    u[:, 2] = 2.0 * g / (np.pi * r * r) * (1.0 - rr)
+    p = 8.0 * prob.mu * g / (np.pi * r ** 4) * (L - x[:, 2])
+    return u, p
+
+
 def chamber_problem(mesh, mu=0.035, dt=5e-4, R=1e4, eps=0.1, cycle=0.8):
     """Truncated spheroid with a prescribed 10% radial contraction of the whole boundary
     (d = -0.1 (1 - cos 2 pi t / cycle)/2 (0, y, z), harmonically extended), no-slip wall,

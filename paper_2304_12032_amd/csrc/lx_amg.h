@@ -49,6 +49,30 @@ struct AmgLevel {
     int lpr = 16;
 };
 
+// The coarse end of the hierarchy (from level `first` down to the dense level)
+// runs as one workgroup out of LDS.  Its arrays sit in one device buffer laid
+// out exactly as the LDS image (offsets in bytes, 16-byte aligned): the dense
+// augmented matrix, then per level the values, dinv, row pointers, columns,
+// aggregate map and member lists; the set-up kernels write values, dinv and the
+// dense inverse there, and the cycle copies the image into LDS in one pass.
+// The level vectors follow the image in LDS only.
+constexpr int kTailDepth = 3;          // smoothed levels the one-workgroup cycle may hold
+constexpr int kTailThreads = 1024;
+constexpr int kTailMaxRows = 1024;
+
+struct TailLevelLds {
+    int32_t n = 0, nnz = 0, nn = 0, lanes = 1;   // rows, entries, rows of the next level, lanes per row
+    int32_t o_val = 0, o_dinv = 0, o_rowptr = 0, o_col = 0, o_agg = 0, o_mptr = 0, o_mem = 0;
+    int32_t o_r = 0, o_res = 0, o_x0 = 0, o_x1 = 0, o_d0 = 0, o_d1 = 0;
+};
+
+struct TailLayout {
+    int first = 0, nlev = 0, nc = 0;   // first: 0 = no one-workgroup cycle
+    int32_t o_dense = 0, o_rc = 0, o_xc = 0;
+    int32_t img_bytes = 0, lds_bytes = 0;
+    TailLevelLds lv[kTailDepth];
+};
+
 // Device state of the two block approximations.  Scalar slots of lam:
 // [0, kAmgMaxLevels) Gershgorin bounds of diag(A_l)^{-1} A_l, kLamF the
 // Chebyshev bound of F~^{-1} F, kNormA/kNormB the power-iteration norms.
@@ -74,7 +98,18 @@ struct Amg {
     double f_safety = 1.15;
     bool f_warm = false;                // fv holds the last power-iteration vector
     T *fr = nullptr, *fd0 = nullptr, *fd1 = nullptr, *fv = nullptr;   // [nv][4]
+    TailLayout tail;                    // one-workgroup coarse cycle (tail.first = 0: none)
+    unsigned char *tail_img = nullptr;  // [tail.img_bytes]
 };
+
+// Chooses the first level of the one-workgroup coarse cycle and its LDS layout
+// from the level sizes (n[l], nnz[l] for l = 0..nlev; level nlev dense) for a
+// value size vbytes; tail.first = 0 if no suffix of the hierarchy fits max_lds.
+TailLayout amg_tail_layout(int nlev, const int64_t *n, const int64_t *nnz, int vbytes, int64_t max_lds);
+
+// Lets the one-workgroup cycle kernel use lds_bytes of dynamic LDS.
+template <typename T>
+lx_status amg_tail_prepare(int lds_bytes);
 
 // The blocks of the saddle-point matrix as the preconditioner sees them: F as a
 // 3x3 block-CSR over the velocity nodes (9 planes of stride Fp.nblk), G (rows:

@@ -38,30 +38,148 @@ __device__ inline int32_t find_col(const int32_t *col, int32_t lo, int32_t hi, i
 }
 
 // S~_ik = C_ik - sum_{j, d} B_ij[d] D^{-1}_j[d] G_jk[d] over the velocity nodes j
-// of B's row i.  One wavefront per row i, lanes over the entries of the row;
-// C_ik and G_jk are found by binary search (sorted columns).  The sum runs over
-// B's row in order, so the result does not depend on scheduling.
+// of B's row i.  One wavefront per row i.  The wave first stages, in LDS, C's
+// row and, for every G row j that B's row names (row after row, in B's order),
+// the columns k and the products sum_d B_ij[d] D^{-1}_j[d] G_jk[d]; then lanes
+// take the entries of S~'s row and subtract, for each j in B's order, the
+// staged product whose column matches (binary search in the staged, sorted G
+// row).  The sum runs over B's row in order, so the result does not depend on
+// scheduling.  Rows whose rows do not fit the LDS share search C and G in
+// global memory instead, with the same arithmetic.
+constexpr int kSfWaves = 4;      // waves (rows) per workgroup
+constexpr int kSfRows = 96;      // B (and C) entries per row that fit the LDS share (at most 128)
+constexpr int kSfCap = 640;      // staged products per row that fit the LDS share
+
+__device__ inline int32_t find_col_lds(const int32_t *col, int32_t lo, int32_t hi, int32_t k)
+{
+    if (lo >= hi) return -1;
+    --hi;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (col[mid] < k)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return col[lo] == k ? lo : -1;
+}
+
+template <typename T>
+__device__ inline double schur_term(const SimpleView<T> &V, const T *__restrict__ Dinv, int32_t k1, int32_t j,
+                                    int32_t kg)
+{
+    const int64_t nu = V.nu;
+    return (double)V.Bv[k1] * (double)Dinv[j] * (double)V.Gv[kg] +
+           (double)V.Bv[V.bs + k1] * (double)Dinv[nu + j] * (double)V.Gv[V.gs + kg] +
+           (double)V.Bv[2 * V.bs + k1] * (double)Dinv[2 * nu + j] * (double)V.Gv[2 * V.gs + kg];
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_schur_form(SimpleView<T> V, const T *__restrict__ Dinv,
                                                     const int32_t *__restrict__ srow,
                                                     const int32_t *__restrict__ scol, T *__restrict__ sval)
 {
-    const int64_t i = (xcd_block() * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (i >= V.np) return;
-    const int64_t nu = V.nu;
-    const int32_t b0 = V.bptr[i], b1 = V.bptr[i + 1];
+    __shared__ int32_t s_off[kSfWaves][kSfRows + 1];
+    __shared__ int32_t s_j[kSfWaves][kSfRows];
+    __shared__ int32_t s_gb[kSfWaves][kSfRows];
+    __shared__ int32_t s_cc[kSfWaves][kSfRows];
+    __shared__ double s_cv[kSfWaves][kSfRows];
+    __shared__ int32_t s_col[kSfWaves][kSfCap];
+    __shared__ double s_val[kSfWaves][kSfCap];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i = xcd_block() * kSfWaves + wv;
+    const bool live = i < V.np;
+    const int32_t b0 = live ? V.bptr[i] : 0, b1 = live ? V.bptr[i + 1] : 0;
+    const int32_t c0 = live ? V.cptr[i] : 0, c1 = live ? V.cptr[i + 1] : 0;
+    const int nb = b1 - b0, nc = c1 - c0;
+    bool staged = live && nb <= kSfRows && nc <= kSfRows;   // uniform over the wave
+    int32_t *off = s_off[wv];
+    if (staged) {
+        // B entries: velocity node, start and length of its G row; inclusive scan of
+        // the lengths over the wave (two entries per lane)
+        int32_t len[2] = {0, 0};
+        for (int h = 0; h < 2; ++h) {
+            const int t = lane + 64 * h;
+            if (t < nb) {
+                const int32_t j = V.bcol[b0 + t], g0 = V.gptr[j];
+                s_j[wv][t] = j;
+                s_gb[wv][t] = g0;
+                len[h] = V.gptr[j + 1] - g0;
+            }
+            if (t < nc) {
+                s_cc[wv][t] = V.ccol[c0 + t];
+                s_cv[wv][t] = (double)V.Cv[c0 + t];
+            }
+        }
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t u0 = __shfl_up(len[0], d), u1 = __shfl_up(len[1], d);
+            if (lane >= d) {
+                len[0] += u0;
+                len[1] += u1;
+            }
+        }
+        const int32_t first = __shfl(len[0], 63);
+        if (lane == 0) off[0] = 0;
+        if (lane < nb) off[lane + 1] = len[0];
+        if (lane + 64 < nb) off[lane + 65] = len[1] + first;
+    }
+    __syncthreads();
+    staged = staged && off[nb] <= kSfCap;
+    if (staged) {
+        // four products per lane at a time, so that their gathers are in flight together
+        const int total = off[nb];
+        for (int q0 = 0; q0 < total; q0 += 256) {
+            int32_t kg[4], t[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + 64 * u + lane;
+                int lo = 0, hi = nb - 1;     // the B entry t with off[t] <= q < off[t + 1]
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (off[mid] <= q)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                t[u] = lo;
+                kg[u] = q < total ? s_gb[wv][lo] + (q - off[lo]) : -1;
+            }
+            int32_t col[4];
+            double pv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (kg[u] >= 0) {
+                    col[u] = V.gcol[kg[u]];
+                    pv[u] = schur_term(V, Dinv, b0 + t[u], s_j[wv][t[u]], kg[u]);
+                }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (kg[u] >= 0) {
+                    s_col[wv][q0 + 64 * u + lane] = col[u];
+                    s_val[wv][q0 + 64 * u + lane] = pv[u];
+                }
+        }
+    }
+    __syncthreads();
+    if (!live) return;
     for (int32_t e = srow[i] + lane; e < srow[i + 1]; e += 64) {
         const int32_t k = scol[e];
-        const int32_t kc = find_col(V.ccol, V.cptr[i], V.cptr[i + 1], k);
-        double acc = kc >= 0 ? (double)V.Cv[kc] : 0.0;
-        for (int32_t k1 = b0; k1 < b1; ++k1) {
-            const int32_t j = V.bcol[k1];
-            const int32_t kg = find_col(V.gcol, V.gptr[j], V.gptr[j + 1], k);
-            if (kg < 0) continue;
-            acc -= (double)V.Bv[k1] * (double)Dinv[j] * (double)V.Gv[kg] +
-                   (double)V.Bv[V.bs + k1] * (double)Dinv[nu + j] * (double)V.Gv[V.gs + kg] +
-                   (double)V.Bv[2 * V.bs + k1] * (double)Dinv[2 * nu + j] * (double)V.Gv[2 * V.gs + kg];
+        double acc;
+        if (staged) {
+            const int32_t kc = find_col_lds(s_cc[wv], 0, nc, k);
+            acc = kc >= 0 ? s_cv[wv][kc] : 0.0;
+            for (int t = 0; t < nb; ++t) {
+                const int32_t q = find_col_lds(s_col[wv], off[t], off[t + 1], k);
+                if (q >= 0) acc -= s_val[wv][q];
+            }
+        } else {
+            const int32_t kc = find_col(V.ccol, c0, c1, k);
+            acc = kc >= 0 ? (double)V.Cv[kc] : 0.0;
+            for (int32_t k1 = b0; k1 < b1; ++k1) {
+                const int32_t j = V.bcol[k1];
+                const int32_t kg = find_col(V.gcol, V.gptr[j], V.gptr[j + 1], k);
+                if (kg >= 0) acc -= schur_term(V, Dinv, k1, j, kg);
+            }
         }
         sval[e] = (T)acc;
     }
@@ -117,16 +235,21 @@ __global__ __launch_bounds__(256) void k_max_fin(int nb, const double *partial, 
 }
 
 // Galerkin sum with piecewise-constant prolongation: each coarse entry is the
-// sum, in a fixed order, of the fine entries listed for it.
-template <typename T>
-__global__ void k_amg_coarsen(int64_t nnzc, const int32_t *__restrict__ cptr, const int32_t *__restrict__ cidx,
-                              const T *__restrict__ fval, T *__restrict__ cval)
+// sum of the fine entries listed for it, LPR lanes per coarse entry reading the
+// list with unit stride (each lane's partial sum in list order, then a fixed
+// butterfly over the lanes).
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_amg_coarsen(int64_t nnzc, const int32_t *__restrict__ cptr,
+                                                     const int32_t *__restrict__ cidx, const T *__restrict__ fval,
+                                                     T *__restrict__ cval)
 {
-    const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t c = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
     if (c >= nnzc) return;
     double s = 0;
-    for (int32_t q = cptr[c]; q < cptr[c + 1]; ++q) s += (double)fval[cidx[q]];
-    cval[c] = (T)s;
+    for (int32_t q = cptr[c] + lane; q < cptr[c + 1]; q += LPR) s += (double)fval[cidx[q]];
+    s = group_sum<double, LPR>(s);
+    if (lane == 0) cval[c] = (T)s;
 }
 
 // aug = [0 | I] (nc x 2nc, row-major)
@@ -578,6 +701,296 @@ __global__ __launch_bounds__(256) void k_dense_solve(int nc, const double *__res
     }
 }
 
+// ================================================================== one-workgroup coarse cycle
+
+// The levels from `first` down to the dense one, cycled by one workgroup out of
+// LDS: the same operations as the level kernels above (restriction and first
+// Chebyshev step, Chebyshev steps, residual, coarse correction with the first
+// post-smoothing step, dense solve), each a pass over the rows with a
+// lane group per row, separated by workgroup barriers instead of launches.
+template <typename T>
+struct TailArgs {
+    TailLayout lay;
+    const unsigned char *img;
+    const double *lam;
+    double ratio;
+    int degree, cycle;
+    const T *fres;                       // residual of level first - 1 (global)
+    const int32_t *fmptr, *fmem;         // its member lists (global)
+    T *out;                              // result of level first (global)
+    const int32_t *done;
+};
+
+template <typename T>
+__device__ __forceinline__ T *lds_v(unsigned char *lds, int32_t o)
+{
+    return reinterpret_cast<T *>(lds + o);
+}
+__device__ __forceinline__ int32_t *lds_i(unsigned char *lds, int32_t o)
+{
+    return reinterpret_cast<int32_t *>(lds + o);
+}
+
+__device__ __forceinline__ double lane_sum(double v, int lanes)
+{
+    for (int off = lanes >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, lanes);
+    return v;
+}
+
+// sum_k val[k] x[col[k]] over the lane's share of row `row`
+template <typename T>
+__device__ __forceinline__ double tail_rowdot(const int32_t *rowptr, const int32_t *col, const T *val, const T *x,
+                                              int row, int lane, int lanes)
+{
+    double q = 0;
+    for (int32_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += lanes) q += (double)val[k] * (double)x[col[k]];
+    return lane_sum(q, lanes);
+}
+
+// level start from the global residual of the finer level: r = restriction,
+// x0 = d0 = dinv r / theta, res = r (members gathered eight at a time per lane)
+template <typename T>
+__device__ __forceinline__ void tail_pre_global(const TailArgs<T> &A, const TailLevelLds &L, unsigned char *lds,
+                                                double lam)
+{
+    const int lanes = L.lanes, lane = threadIdx.x & (lanes - 1);
+    T *r = lds_v<T>(lds, L.o_r), *res = lds_v<T>(lds, L.o_res), *x0 = lds_v<T>(lds, L.o_x0),
+      *d0 = lds_v<T>(lds, L.o_d0);
+    const T *dinv = lds_v<T>(lds, L.o_dinv);
+    double theta, a, b;
+    cheb_coef(lam, A.ratio, 0, theta, a, b);
+    for (int i = threadIdx.x / lanes; i < L.n; i += kTailThreads / lanes) {
+        const int32_t q0 = A.fmptr[i], q1 = A.fmptr[i + 1];
+        double s = 0;
+        for (int32_t q = q0 + lane; q < q1; q += 8 * lanes) {
+            int32_t idx[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) idx[u] = q + u * lanes < q1 ? A.fmem[q + u * lanes] : -1;
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = idx[u] >= 0 ? A.fres[idx[u]] : T(0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += (double)v[u];
+        }
+        s = lane_sum(s, lanes);
+        if (lane == 0) {
+            const T x = (T)((double)dinv[i] * s / theta);
+            r[i] = (T)s;
+            res[i] = (T)s;
+            x0[i] = x;
+            d0[i] = x;
+        }
+    }
+}
+
+// the same from the finer level's residual in LDS
+template <typename T>
+__device__ __forceinline__ void tail_pre_lds(const TailArgs<T> &A, const TailLevelLds &F, const TailLevelLds &L,
+                                             unsigned char *lds, double lam)
+{
+    const int lanes = L.lanes, lane = threadIdx.x & (lanes - 1);
+    const T *fres = lds_v<T>(lds, F.o_res);
+    const int32_t *mptr = lds_i(lds, F.o_mptr), *mem = lds_i(lds, F.o_mem);
+    T *r = lds_v<T>(lds, L.o_r), *res = lds_v<T>(lds, L.o_res), *x0 = lds_v<T>(lds, L.o_x0),
+      *d0 = lds_v<T>(lds, L.o_d0);
+    const T *dinv = lds_v<T>(lds, L.o_dinv);
+    double theta, a, b;
+    cheb_coef(lam, A.ratio, 0, theta, a, b);
+    for (int i = threadIdx.x / lanes; i < L.n; i += kTailThreads / lanes) {
+        double s = 0;
+        for (int32_t q = mptr[i] + lane; q < mptr[i + 1]; q += lanes) s += (double)fres[mem[q]];
+        s = lane_sum(s, lanes);
+        if (lane == 0) {
+            const T x = (T)((double)dinv[i] * s / theta);
+            r[i] = (T)s;
+            res[i] = (T)s;
+            x0[i] = x;
+            d0[i] = x;
+        }
+    }
+}
+
+// Chebyshev step: res -= A dc, dn = a dc + b dinv res, x += dn
+template <typename T>
+__device__ __forceinline__ void tail_cheb(const TailArgs<T> &A, const TailLevelLds &L, unsigned char *lds, T *x,
+                                          const T *dc, T *dn, double lam, int step)
+{
+    const int lanes = L.lanes, lane = threadIdx.x & (lanes - 1);
+    const int32_t *rowptr = lds_i(lds, L.o_rowptr), *col = lds_i(lds, L.o_col);
+    const T *val = lds_v<T>(lds, L.o_val), *dinv = lds_v<T>(lds, L.o_dinv);
+    T *res = lds_v<T>(lds, L.o_res);
+    double theta, a, b;
+    cheb_coef(lam, A.ratio, step, theta, a, b);
+    for (int row = threadIdx.x / lanes; row < L.n; row += kTailThreads / lanes) {
+        const double q = tail_rowdot(rowptr, col, val, dc, row, lane, lanes);
+        if (lane == 0) {
+            const double rr = (double)res[row] - q;
+            res[row] = (T)rr;
+            const double d = a * (double)dc[row] + b * (double)dinv[row] * rr;
+            dn[row] = (T)d;
+            x[row] = (T)((double)x[row] + d);
+        }
+    }
+}
+
+// res = r - A x
+template <typename T>
+__device__ __forceinline__ void tail_resid(const TailLevelLds &L, unsigned char *lds, const T *x)
+{
+    const int lanes = L.lanes, lane = threadIdx.x & (lanes - 1);
+    const int32_t *rowptr = lds_i(lds, L.o_rowptr), *col = lds_i(lds, L.o_col);
+    const T *val = lds_v<T>(lds, L.o_val), *r = lds_v<T>(lds, L.o_r);
+    T *res = lds_v<T>(lds, L.o_res);
+    for (int row = threadIdx.x / lanes; row < L.n; row += kTailThreads / lanes) {
+        const double q = tail_rowdot(rowptr, col, val, x, row, lane, lanes);
+        if (lane == 0) res[row] = (T)((double)r[row] - q);
+    }
+}
+
+// y = xa + P e, res = r - A y, d0 = dinv res / theta, xb = y + d0
+template <typename T>
+__device__ __forceinline__ void tail_post0(const TailArgs<T> &A, const TailLevelLds &L, unsigned char *lds,
+                                           const T *xa, T *xb, const T *e, double lam)
+{
+    const int lanes = L.lanes, lane = threadIdx.x & (lanes - 1);
+    const int32_t *rowptr = lds_i(lds, L.o_rowptr), *col = lds_i(lds, L.o_col), *agg = lds_i(lds, L.o_agg);
+    const T *val = lds_v<T>(lds, L.o_val), *dinv = lds_v<T>(lds, L.o_dinv), *r = lds_v<T>(lds, L.o_r);
+    T *res = lds_v<T>(lds, L.o_res), *d0 = lds_v<T>(lds, L.o_d0);
+    double theta, a, b;
+    cheb_coef(lam, A.ratio, 0, theta, a, b);
+    for (int row = threadIdx.x / lanes; row < L.n; row += kTailThreads / lanes) {
+        double q = 0;
+        for (int32_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += lanes) {
+            const int32_t j = col[k];
+            q += (double)val[k] * ((double)xa[j] + (double)e[agg[j]]);
+        }
+        q = lane_sum(q, lanes);
+        if (lane == 0) {
+            const double rr = (double)r[row] - q;
+            const double d = (double)dinv[row] * rr / theta;
+            res[row] = (T)rr;
+            d0[row] = (T)d;
+            xb[row] = (T)((double)xa[row] + (double)e[agg[row]] + d);
+        }
+    }
+}
+
+// dense coarsest solve: rc = restriction of the finer level's residual, xc = A^{-1} rc
+template <typename T>
+__device__ __forceinline__ T *tail_dense(const TailArgs<T> &A, const TailLevelLds &F, unsigned char *lds)
+{
+    const int nc = A.lay.nc;
+    const T *fres = lds_v<T>(lds, F.o_res);
+    const int32_t *mptr = lds_i(lds, F.o_mptr), *mem = lds_i(lds, F.o_mem);
+    double *rc = lds_v<double>(lds, A.lay.o_rc);
+    const double *aug = lds_v<double>(lds, A.lay.o_dense);
+    T *xc = lds_v<T>(lds, A.lay.o_xc);
+    for (int c = threadIdx.x; c < nc; c += kTailThreads) {
+        double s = 0;
+        for (int32_t q = mptr[c]; q < mptr[c + 1]; ++q) s += (double)fres[mem[q]];
+        rc[c] = s;
+    }
+    __syncthreads();
+    const int lanes = 16, lane = threadIdx.x & 15;
+    for (int row = threadIdx.x / lanes; row < nc; row += kTailThreads / lanes) {
+        double s = 0;
+        for (int c = lane; c < nc; c += lanes) s += aug[(int64_t)row * 2 * nc + nc + c] * rc[c];
+        s = lane_sum(s, lanes);
+        if (lane == 0) xc[row] = (T)s;
+    }
+    __syncthreads();
+    return xc;
+}
+
+// One visit of level first + D (the dense level when first + D == nlev); returns
+// where the level's result lies in LDS.
+template <typename T, int D>
+__device__ __forceinline__ T *tail_visit(const TailArgs<T> &A, unsigned char *lds)
+{
+    const TailLayout &Y = A.lay;
+    if constexpr (D > 0) {
+        if (Y.first + D == Y.nlev) return tail_dense(A, Y.lv[D - 1], lds);
+    }
+    if constexpr (D < kTailDepth) {
+        const TailLevelLds &L = Y.lv[D];
+        const double lam = A.lam[Y.first + D];
+        if constexpr (D == 0)
+            tail_pre_global(A, L, lds, lam);
+        else
+            tail_pre_lds(A, Y.lv[D - 1], L, lds, lam);
+        __syncthreads();
+        T *d0 = lds_v<T>(lds, L.o_d0), *d1 = lds_v<T>(lds, L.o_d1);
+        T *dc = d0, *dn = d1;
+        T *xa = lds_v<T>(lds, L.o_x0), *xb = lds_v<T>(lds, L.o_x1);
+        for (int i = 1; i < A.degree; ++i) {
+            tail_cheb(A, L, lds, xa, dc, dn, lam, i);
+            __syncthreads();
+            T *t = dc;
+            dc = dn;
+            dn = t;
+        }
+        for (int c = 0; c < A.cycle; ++c) {
+            tail_resid(L, lds, xa);
+            __syncthreads();
+            const T *e = tail_visit<T, D + 1>(A, lds);
+            tail_post0(A, L, lds, xa, xb, e, lam);
+            __syncthreads();
+            dc = d0;
+            dn = d1;
+            for (int i = 1; i < A.degree; ++i) {
+                tail_cheb(A, L, lds, xb, dc, dn, lam, i);
+                __syncthreads();
+                T *t = dc;
+                dc = dn;
+                dn = t;
+            }
+            if (c + 1 < A.cycle) {
+                T *t = xa;
+                xa = xb;
+                xb = t;
+            }
+        }
+        return xb;
+    }
+    return nullptr;   // not reached: the host limits the depth to kTailDepth smoothed levels
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) void k_amg_tail(TailArgs<T> A)
+{
+    if (A.done && *A.done) return;
+    extern __shared__ __align__(16) unsigned char lds[];
+    // the image, 16-byte words, four per thread in flight
+    const int nw = A.lay.img_bytes >> 4;
+    const uint4 *src = reinterpret_cast<const uint4 *>(A.img);
+    uint4 *dst = reinterpret_cast<uint4 *>(lds);
+    for (int b0 = 0; b0 < nw; b0 += 4 * kTailThreads) {
+        const int w0 = b0 + (int)threadIdx.x, w1 = w0 + kTailThreads, w2 = w1 + kTailThreads,
+                  w3 = w2 + kTailThreads;
+        // loads at clamped (in-bounds) indices, stores only where in range
+        const uint4 v0 = src[min(w0, nw - 1)], v1 = src[min(w1, nw - 1)], v2 = src[min(w2, nw - 1)],
+                    v3 = src[min(w3, nw - 1)];
+        if (w0 < nw) dst[w0] = v0;
+        if (w1 < nw) dst[w1] = v1;
+        if (w2 < nw) dst[w2] = v2;
+        if (w3 < nw) dst[w3] = v3;
+    }
+    __syncthreads();
+    const T *x = tail_visit<T, 0>(A, lds);
+    for (int i = threadIdx.x; i < A.lay.lv[0].n; i += kTailThreads) A.out[i] = x[i];
+}
+
+template <typename T>
+lx_status amg_tail_prepare(int lds_bytes)
+{
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_amg_tail<T>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes) != hipSuccess)
+        return fail(LX_EDEVICE, "cannot reserve %d bytes of LDS for the coarse AMG cycle", lds_bytes);
+    return LX_OK;
+}
+template lx_status amg_tail_prepare<double>(int);
+template lx_status amg_tail_prepare<float>(int);
+
 // ================================================================== launchers
 
 static unsigned rows_grid(int64_t n, int lpr) { return (unsigned)((n * lpr + 255) / 256); }
@@ -620,8 +1033,8 @@ void launch_amg_setup(const SimpleView<T> &V, const T *Finv, const T *Dinv, Amg<
     const RowPattern &P = V.Fp;
     const T *val = V.F;
     AmgLevel<T> &L0 = A.L[0];
-    hipLaunchKernelGGL((k_schur_form<T>), dim3(rows_grid(V.np, 64)), dim3(256), 0, s, V, Dinv, L0.rowptr, L0.col,
-                       L0.val);
+    hipLaunchKernelGGL((k_schur_form<T>), dim3((unsigned)((V.np + kSfWaves - 1) / kSfWaves)), dim3(64 * kSfWaves),
+                       0, s, V, Dinv, L0.rowptr, L0.col, L0.val);
     for (int l = 0; l < A.nlev; ++l) {
         AmgLevel<T> &L = A.L[l];
         const unsigned g = rows_grid(L.n, L.lpr);
@@ -629,8 +1042,8 @@ void launch_amg_setup(const SimpleView<T> &V, const T *Finv, const T *Dinv, Amg<
                                                 L.diag, L.val, L.dinv, A.partial));
         hipLaunchKernelGGL(k_max_fin, dim3(1), dim3(256), 0, s, (int)g, A.partial, &A.lam[l]);
         AmgLevel<T> &C = A.L[l + 1];
-        hipLaunchKernelGGL((k_amg_coarsen<T>), dim3(flat_grid(C.nnz)), dim3(256), 0, s, C.nnz, L.cptr, L.cidx, L.val,
-                           C.val);
+        hipLaunchKernelGGL((k_amg_coarsen<T, 16>), dim3(rows_grid(C.nnz, 16)), dim3(256), 0, s, C.nnz, L.cptr, L.cidx,
+                           L.val, C.val);
     }
     const AmgLevel<T> &D = A.L[A.nlev];
     hipLaunchKernelGGL(k_dense_init, dim3(flat_grid(2 * A.nc * A.nc)), dim3(256), 0, s, A.nc, A.dense);
@@ -663,6 +1076,23 @@ template void launch_amg_setup<float>(const SimpleView<float> &, const float *, 
 template <typename T>
 static void vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s)
 {
+    if (A.tail.first > 0 && l == A.tail.first) {
+        const AmgLevel<T> &F = A.L[l - 1];
+        TailArgs<T> t;
+        t.lay = A.tail;
+        t.img = A.tail_img;
+        t.lam = A.lam;
+        t.ratio = A.ratio;
+        t.degree = A.degree;
+        t.cycle = A.cycle;
+        t.fres = F.res;
+        t.fmptr = F.mptr;
+        t.fmem = F.mem;
+        t.out = A.L[l].x1;
+        t.done = done;
+        hipLaunchKernelGGL((k_amg_tail<T>), dim3(1), dim3(kTailThreads), (size_t)A.tail.lds_bytes, s, t);
+        return;
+    }
     if (l == A.nlev) {
         const bool fine = l == 0;
         const T *fres = fine ? A.L[0].r : A.L[l - 1].res;

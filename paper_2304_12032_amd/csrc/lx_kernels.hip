@@ -709,13 +709,26 @@ void launch_neumann(int64_t nf, const int32_t *faces, const double *x, const dou
 // ------------------------------------------------------------------ SIMPLE
 
 // D = diag(F); F~^{-1}: inverse of the nodal 3x3 diagonal block of F;
-// S~ = diag(C - B D^{-1} G), reading G_ji through the transposed slot.
-template <typename T>
-__global__ void k_simple_setup(RowPattern P, const T *val, T *Finv, T *Dinv, T *Sinv)
+// with Sinv, also S~ = diag(C - B D^{-1} G), reading G_ji through the transposed
+// slot (LPR lanes per row, partial sums combined by a fixed butterfly).
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_simple_setup(RowPattern P, const T *val, T *Finv, T *Dinv, T *Sinv)
 {
-    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t i = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
     if (i >= P.nv) return;
     const int64_t nb = P.nblk, nv = P.nv, dk = P.diag[i];
+    if (Sinv) {
+        double s = 0;
+        for (int64_t k = P.rowptr[i] + lane; k < P.rowptr[i + 1]; k += LPR) {
+            const int64_t j = P.col[k], ts = P.tslot[k], dj = P.diag[j];
+            for (int d = 0; d < 3; ++d)
+                s += (double)val[(12 + d) * nb + k] * (double)val[(9 + d) * nb + ts] / (double)val[(4 * d) * nb + dj];
+        }
+        s = group_sum<double, LPR>(s);
+        if (lane == 0) Sinv[i] = (T)(1.0 / ((double)val[15 * nb + dk] - s));
+    }
+    if (lane != 0) return;
     double A[9];
     for (int p = 0; p < 9; ++p) A[p] = (double)val[p * nb + dk];
     double c0 = A[4] * A[8] - A[5] * A[7], c1 = A[5] * A[6] - A[3] * A[8], c2 = A[3] * A[7] - A[4] * A[6];
@@ -725,20 +738,14 @@ __global__ void k_simple_setup(RowPattern P, const T *val, T *Finv, T *Dinv, T *
                    c2 * id, (A[1] * A[6] - A[0] * A[7]) * id, (A[0] * A[4] - A[1] * A[3]) * id};
     for (int p = 0; p < 9; ++p) Finv[p * nv + i] = (T)B[p];
     for (int c = 0; c < 3; ++c) Dinv[c * nv + i] = (T)(1.0 / A[4 * c]);
-    double s = (double)val[15 * nb + dk];
-    for (int64_t k = P.rowptr[i]; k < P.rowptr[i + 1]; ++k) {
-        const int64_t j = P.col[k], ts = P.tslot[k], dj = P.diag[j];
-        for (int d = 0; d < 3; ++d)
-            s -= (double)val[(12 + d) * nb + k] * (double)val[(9 + d) * nb + ts] / (double)val[(4 * d) * nb + dj];
-    }
-    Sinv[i] = (T)(1.0 / s);
 }
 
+// Sinv may be null (the AMG Schur block does not use diag(S~)).
 template <typename T>
 void launch_simple_setup(const RowPattern &P, const T *val, T *Finv, T *Dinv, T *Sinv, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_simple_setup<T>), dim3((unsigned)((P.nv + 127) / 128)), dim3(128), 0, s, P, val, Finv,
-                       Dinv, Sinv);
+    hipLaunchKernelGGL((k_simple_setup<T, 16>), dim3((unsigned)((P.nv * 16 + 255) / 256)), dim3(256), 0, s, P, val,
+                       Finv, Dinv, Sinv);
 }
 template void launch_simple_setup<double>(const RowPattern &, const double *, double *, double *, double *,
                                           hipStream_t);

@@ -453,6 +453,32 @@ lx_status Sim::setup_amg(Amg<T> &A)
         lx_status _s = (x);            \
         if (_s != LX_OK) return _s;    \
     } while (0)
+    // one-workgroup coarse cycle: the suffix of the hierarchy that fits one
+    // workgroup's LDS (LXNS_AMG_TAIL=0 keeps every level on its own launches)
+    {
+        int64_t ln[kAmgMaxLevels + 1], lnnz[kAmgMaxLevels + 1];
+        for (int l = 0; l < nl; ++l) {
+            ln[l] = amgh.lev[l].n;
+            lnnz[l] = (int64_t)amgh.lev[l].col.size();
+        }
+        int max_lds = 0;
+        LX_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+        const char *te = getenv("LXNS_AMG_TAIL");
+        const bool use_tail = !(te && *te == '0');
+        A.tail = use_tail ? amg_tail_layout(A.nlev, ln, lnnz, (int)sizeof(T), max_lds) : TailLayout();
+        // a device that refuses the LDS reservation runs every level on its own launches
+        if (A.tail.first > 0 && amg_tail_prepare<T>(A.tail.lds_bytes) != LX_OK) A.tail = TailLayout();
+        if (A.tail.first > 0) {
+            CK(dalloc((void **)&A.tail_img, (size_t)A.tail.img_bytes));
+            LX_HIP(hipMemsetAsync(A.tail_img, 0, (size_t)A.tail.img_bytes, stream));
+        }
+    }
+    auto in_img = [&](int l) { return A.tail.first > 0 && l >= A.tail.first && l < A.nlev; };
+    auto img_up = [&](int32_t *&d, int32_t off, const std::vector<int32_t> &h) -> lx_status {
+        d = reinterpret_cast<int32_t *>(A.tail_img + off);
+        if (!h.empty()) LX_HIP(hipMemcpyAsync(d, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, stream));
+        return LX_OK;
+    };
     for (int l = 0; l < nl; ++l) {
         const AmgLevelHost &H = amgh.lev[l];
         AmgLevel<T> &L = A.L[l];
@@ -462,18 +488,33 @@ lx_status Sim::setup_amg(Amg<T> &A)
         L.lpr = avg >= 12 ? 16 : avg >= 6 ? 8 : 4;
         if (lpr_env == 4 || lpr_env == 8 || lpr_env == 16 || lpr_env == 32) L.lpr = lpr_env;
         maxgrid = std::max<int64_t>(maxgrid, (L.n * L.lpr + 255) / 256);
-        CK(up(L.rowptr, H.rowptr));
-        CK(up(L.col, H.col));
+        const bool img = in_img(l);
+        const TailLevelLds *Y = img ? &A.tail.lv[l - A.tail.first] : nullptr;
+        if (img) {
+            CK(img_up(L.rowptr, Y->o_rowptr, H.rowptr));
+            CK(img_up(L.col, Y->o_col, H.col));
+            L.val = reinterpret_cast<T *>(A.tail_img + Y->o_val);
+        } else {
+            CK(up(L.rowptr, H.rowptr));
+            CK(up(L.col, H.col));
+            CK(vec(L.val, L.nnz));
+        }
         CK(up(L.diag, H.diag));
-        CK(vec(L.val, L.nnz));
         CK(vec(L.x1, L.n));
         if (l < A.nlev) {
-            CK(up(L.agg, H.agg));
-            CK(up(L.mptr, H.mptr));
-            CK(up(L.mem, H.mem));
+            if (img) {
+                CK(img_up(L.agg, Y->o_agg, H.agg));
+                CK(img_up(L.mptr, Y->o_mptr, H.mptr));
+                CK(img_up(L.mem, Y->o_mem, H.mem));
+                L.dinv = reinterpret_cast<T *>(A.tail_img + Y->o_dinv);
+            } else {
+                CK(up(L.agg, H.agg));
+                CK(up(L.mptr, H.mptr));
+                CK(up(L.mem, H.mem));
+                CK(vec(L.dinv, L.n));
+            }
             CK(up(L.cptr, H.cptr));
             CK(up(L.cidx, H.cidx));
-            CK(vec(L.dinv, L.n));
             CK(vec(L.x0, L.n));
             CK(vec(L.res, L.n));
             CK(vec(L.d0, L.n));
@@ -487,7 +528,10 @@ lx_status Sim::setup_amg(Amg<T> &A)
     for (int64_t i = 0; i < Hc.n; ++i)
         for (int32_t k = Hc.rowptr[i]; k < Hc.rowptr[i + 1]; ++k) crow[k] = (int32_t)i;
     CK(up(A.crow, crow));
-    CK(dalloc((void **)&A.dense, sizeof(double) * 2 * A.nc * std::max<int64_t>(A.nc, 1)));
+    if (A.tail.first > 0)
+        A.dense = reinterpret_cast<double *>(A.tail_img + A.tail.o_dense);
+    else
+        CK(dalloc((void **)&A.dense, sizeof(double) * 2 * A.nc * std::max<int64_t>(A.nc, 1)));
     CK(dalloc((void **)&A.lam, sizeof(double) * kLamSlots));
     CK(dalloc((void **)&A.partial, sizeof(double) * (maxgrid + 64)));
     CK(dalloc((void **)&A.counter, sizeof(uint32_t) * 4));
@@ -497,10 +541,15 @@ lx_status Sim::setup_amg(Amg<T> &A)
     CK(vec(A.fv, 4 * nu));
 #undef CK
     if (const char *v = getenv("LXNS_VERBOSE"))
-        if (*v && *v != '0')
+        if (*v && *v != '0') {
+            if (A.tail.first > 0)
+                fprintf(stderr, "[lxns] AMG one-workgroup cycle from level %d: %d image bytes, %d LDS bytes\n",
+                        A.tail.first, A.tail.img_bytes, A.tail.lds_bytes);
             for (int l = 0; l < nl; ++l)
-                fprintf(stderr, "[lxns] AMG level %d%s: %lld rows, %lld entries, lanes/row %d\n", l,
-                        l == A.nlev ? " (dense)" : "", (long long)A.L[l].n, (long long)A.L[l].nnz, A.L[l].lpr);
+                fprintf(stderr, "[lxns] AMG level %d%s: %lld rows, %lld entries, lanes/row %d%s\n", l,
+                        l == A.nlev ? " (dense)" : "", (long long)A.L[l].n, (long long)A.L[l].nnz, A.L[l].lpr,
+                        A.tail.first > 0 && l >= A.tail.first ? " (one-workgroup cycle)" : "");
+        }
     LX_HIP(hipMemsetAsync(A.lam, 0, sizeof(double) * kLamSlots, stream));
     LX_HIP(hipMemsetAsync(A.counter, 0, sizeof(uint32_t) * 4, stream));
     launch_fill<T>(4 * nu, A.fr, T(0), stream);
@@ -842,7 +891,8 @@ lx_status Sim::build_system(double t1, StepCoef &C, lx_step_stats &tstats)
         timer_end(tm);
         add_neumann(t1, d_rhs64, nullptr);
         launch_dirichlet_rows<double>(n_dir, d_dir_node, d_g, P, d_val64, d_rhs64, stream);
-        launch_simple_setup<double>(P, d_val64, d_Finv64, d_Dinv64, d_Sinv64, stream);
+        launch_simple_setup<double>(P, d_val64, d_Finv64, d_Dinv64, solver.precond == LX_PC_AMG ? nullptr : d_Sinv64,
+                                  stream);
         if (solver.precond == LX_PC_AMG)
             launch_amg_setup<double>(view<double>(), d_Finv64, d_Dinv64, amg64, stream);
         else if (solver.schur_degree > 0)
@@ -863,7 +913,8 @@ lx_status Sim::build_system(double t1, StepCoef &C, lx_step_stats &tstats)
             timer_end(tm);
         }
         launch_dirichlet_rows<float>(n_dir, d_dir_node, d_g, P, d_val32, (float *)nullptr, stream);
-        launch_simple_setup<float>(P, d_val32, d_Finv32, d_Dinv32, d_Sinv32, stream);
+        launch_simple_setup<float>(P, d_val32, d_Finv32, d_Dinv32, solver.precond == LX_PC_AMG ? nullptr : d_Sinv32,
+                                  stream);
         if (solver.precond == LX_PC_AMG)
             launch_amg_setup<float>(view<float>(), d_Finv32, d_Dinv32, amg32, stream);
         else if (solver.schur_degree > 0)
