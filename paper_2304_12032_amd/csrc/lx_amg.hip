@@ -355,7 +355,7 @@ __global__ __launch_bounds__(256) void k_fpow(RowPattern P, const T *__restrict_
                                               int slot_in, double *partial)
 {
     __shared__ double lds[16];
-    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (grid_block(P.remap) * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     const int64_t nb = P.nblk, nv = P.nv;
     using V = typename V4<T>::type;
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(256) void k_fcheb(RowPattern P, const T *__restrict
                                                const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (grid_block(P.remap) * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= P.nv) return;
     const int64_t nb = P.nblk, nv = P.nv;
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(256) void k_xu_amg(SimpleView<T> V, const T *__rest
                                                 const T *__restrict__ p, const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = (grid_block(V.Fp.remap) * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= V.nu) return;
     const int64_t nu = V.nu;

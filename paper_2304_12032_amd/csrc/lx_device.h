@@ -31,6 +31,10 @@ __device__ inline int64_t xcd_block()
     return (int64_t)(die < rem ? die * (per + 1) : rem * (per + 1) + (die - rem) * per) + local;
 }
 
+// xcd_block() where rows are of similar cost; the plain round-robin order where
+// they are not (contiguous die ranges would then give one die most of the work).
+__device__ inline int64_t grid_block(int32_t remap) { return remap ? xcd_block() : (int64_t)blockIdx.x; }
+
 template <typename T, int LPR>
 __device__ inline T group_sum(T v)
 {

@@ -50,6 +50,7 @@ struct ResArgs {
 struct RowPattern {
     int64_t nv, nblk;
     const int32_t *rowptr, *col, *diag, *tslot;
+    int32_t remap = 1;   // die-contiguous workgroup ranges (0: rows of very unequal length, as P2's)
 };
 
 template <typename T>

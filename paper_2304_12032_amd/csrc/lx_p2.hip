@@ -35,7 +35,7 @@ struct P2Lds {
 __global__ __launch_bounds__(64) void k_element_p2(P2AsmArgs A, StepCoef C, int symgrad)
 {
     __shared__ P2Lds S;
-    const int64_t e = xcd_block();
+    const int64_t e = blockIdx.x;
     const int lane = threadIdx.x;
     if (e >= A.nt) return;
     const int64_t nt = A.nt;
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(64) void k_element_p2(P2AsmArgs A, StepCoef C, int 
 
 __global__ __launch_bounds__(256) void k_gather_p2f(P2AsmArgs A, P2Sys<double> S, double *rhs)
 {
-    const int64_t k = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= S.nf) return;
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, r[3] = {0, 0, 0};
     bool diag = false;
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256) void k_gather_p2f(P2AsmArgs A, P2Sys<double> S
 
 __global__ __launch_bounds__(256) void k_gather_p2g(P2AsmArgs A, P2Sys<double> S)
 {
-    const int64_t k = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= S.ng) return;
     double acc[3] = {0, 0, 0};
     for (int32_t q = A.ginc_ptr[k]; q < A.ginc_ptr[k + 1]; ++q) {
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(256) void k_gather_p2g(P2AsmArgs A, P2Sys<double> S
 
 __global__ __launch_bounds__(256) void k_gather_p2b(P2AsmArgs A, P2Sys<double> S)
 {
-    const int64_t k = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= S.nb) return;
     double acc[3] = {0, 0, 0};
     for (int32_t q = A.binc_ptr[k]; q < A.binc_ptr[k + 1]; ++q) {
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(256) void k_gather_p2b(P2AsmArgs A, P2Sys<double> S
 // C on the vertex pattern (incidence codes 16 e + 4 a + b of the P1 path)
 __global__ __launch_bounds__(256) void k_gather_p2c(P2AsmArgs A, P2Sys<double> S, double *rhs)
 {
-    const int64_t k = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= S.nc) return;
     double acc = 0, r = 0;
     int64_t vert = -1;
@@ -383,7 +383,7 @@ template <typename T>
 __global__ void k_dirichlet_rows_p2(int64_t n_dir, const int32_t *dir_node, const double *g, P2Sys<T> S,
                                     const int32_t *fdiag, T *rhs)
 {
-    const int64_t k = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_dir) return;
     const int64_t i = dir_node[k];
     const int32_t dk = fdiag[i];
@@ -413,7 +413,7 @@ template void launch_dirichlet_rows_p2<double>(int64_t, const int32_t *, const d
 __global__ void k_neumann_p2(int64_t nf, const int32_t *faces6, const double *xn, const double *hn, double h0,
                              double h1, double h2, const P2Rules *R, double *out)
 {
-    const int64_t f = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nf) return;
     int64_t nd[6];
     for (int a = 0; a < 6; ++a) nd[a] = faces6[6 * f + a];
@@ -459,7 +459,7 @@ void launch_neumann_p2(int64_t nf, const int32_t *faces6, const double *xnode, c
 template <typename T>
 __global__ void k_simple_setup_p2(P2Sys<T> S, const int32_t *fdiag, T *Finv, T *Dinv)
 {
-    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S.nu) return;
     const int32_t dk = fdiag[i];
     double A[9];
@@ -490,7 +490,7 @@ __global__ __launch_bounds__(256) void k_spmv_p2u(P2Sys<T> S, const T *__restric
                                                   const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= S.nu) return;
     using V = typename V4<T>::type;
@@ -526,7 +526,7 @@ __global__ __launch_bounds__(256) void k_spmv_p2p(P2Sys<T> S, const T *__restric
                                                   const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= S.nv) return;
     using V = typename V4<T>::type;

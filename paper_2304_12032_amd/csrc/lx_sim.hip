@@ -655,6 +655,7 @@ SimpleView<T> Sim::view()
     V.Fp.col = S.fcol;
     V.Fp.diag = d_fdiag;
     V.Fp.tslot = nullptr;
+    V.Fp.remap = 0;   // vertex rows (many more entries) come first
     V.F = S.F;
     V.gptr = S.gptr;
     V.gcol = S.gcol;
