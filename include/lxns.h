@@ -204,6 +204,11 @@ typedef struct {
     int64_t device_bytes;    /* device memory held by the simulation              */
     int64_t n_edges;         /* P2-P1: edge nodes (0 for P1-P1)                     */
     int64_t n_scalar_nnz;    /* scalar entries of the stored matrix                 */
+    int32_t amg_levels;      /* LX_PC_AMG: levels of the Schur-block hierarchy, the
+                                dense coarsest included (0 for LX_PC_CHEB_SCHUR)    */
+    int32_t amg_tail_level;  /* LX_PC_AMG: first level cycled by one workgroup out
+                                of LDS, down to the dense level (0: none; the
+                                environment variable LXNS_AMG_TAIL=0 turns it off) */
 } lx_sizes;
 
 typedef struct {

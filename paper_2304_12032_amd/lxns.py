@@ -82,7 +82,8 @@ class lx_solver(ctypes.Structure):
 
 class lx_sizes(ctypes.Structure):
     _fields_ = [("n_vertices", c_i64), ("n_tets", c_i64), ("n_u_nodes", c_i64), ("n_dofs", c_i64),
-                ("n_blocks", c_i64), ("device_bytes", c_i64), ("n_edges", c_i64), ("n_scalar_nnz", c_i64)]
+                ("n_blocks", c_i64), ("device_bytes", c_i64), ("n_edges", c_i64), ("n_scalar_nnz", c_i64),
+                ("amg_levels", c_i32), ("amg_tail_level", c_i32)]
 
 
 class lx_step_stats(ctypes.Structure):
