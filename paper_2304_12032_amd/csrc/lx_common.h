@@ -60,7 +60,10 @@ struct GmState {
     int32_t converged;
     int32_t breakdown;
     uint32_t counter;               // last-block arrival counter (reset by the last block)
-    uint32_t pad;
+    double reorth_frac;             // second pass when the first removed more than this share of ||w||^2
+    int32_t reorth;                 // 1: the current Arnoldi step takes a second Gram-Schmidt pass
+    int32_t n_reorth;               // second passes taken in this cycle
+    int32_t pad;
 };
 
 // Host error reporting.

@@ -1161,6 +1161,8 @@ __global__ __launch_bounds__(256) void k_gm_start_fin(int nb, const double *part
         for (int j = 1; j <= kMaxRestart; ++j) st->g[j] = 0;
         st->s[0] = beta > 0 ? 1.0 / beta : 0.0;
         st->kused = 0;
+        st->reorth = 0;
+        st->n_reorth = 0;
         st->converged = (beta <= st->tol_abs) ? 1 : 0;
         st->breakdown = (beta != beta) ? 1 : 0;
         st->done = (st->converged || st->breakdown) ? 1 : 0;
@@ -1179,14 +1181,16 @@ template void launch_gm_start<double>(int64_t, const double *, const double *, d
 template void launch_gm_start<float>(int64_t, const float *, const float *, float *, GmState *, double *,
                                      hipStream_t);
 
-// partial[j * gridDim.x + bx] = <Vhat_j, w> over chunk bx, j = blockIdx.y.
+// partial[j * gridDim.x + bx] = <Vhat_j, w> over chunk bx, j = blockIdx.y; the
+// row j = nv (if the grid has it) is <w, w>.  second: the second Gram-Schmidt
+// pass, skipped unless the first one asked for it.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gm_dot(int64_t n, const T *V, int64_t ldv, const T *w, double *partial,
-                                                const GmState *st)
+                                                const GmState *st, int nv, int second)
 {
-    if (st->done) return;
+    if (st->done || (second && !st->reorth)) return;
     __shared__ double lds[4];
-    const T *v = V + (int64_t)blockIdx.y * ldv;
+    const T *v = (int)blockIdx.y < nv ? V + (int64_t)blockIdx.y * ldv : w;
     const int64_t i0 = (int64_t)blockIdx.x * kDotChunk;
     const int64_t i1 = i0 + kDotChunk < n ? i0 + kDotChunk : n;
     double acc = 0;
@@ -1196,12 +1200,18 @@ __global__ __launch_bounds__(256) void k_gm_dot(int64_t n, const T *V, int64_t l
 }
 
 // dot_j = sum_b partial[j][b] (fixed order, one wavefront per j); with V_j =
-// s_j Vhat_j: mode 0 h1_j = s_j dot_j; mode 1 h2_j = s_j dot_j, H[j][k] = h1_j + h2_j
-// and h1 <- h2 for the second update.
+// s_j Vhat_j: mode 0 h1_j = s_j dot_j = H[j][k], and the second pass is asked for
+// when the projection removed more than the share reorth_frac of ||w||^2 (row
+// k + 1 holds <w, w>; the library sets 0.9: ||w - V h1|| < ||w|| / sqrt(10), a
+// stricter form of the Daniel-Gragg-Kaufman-Stewart test, whose 1/sqrt(2) asks
+// for it at nearly every step of these solves); mode 1 (second pass)
+// h2_j = s_j dot_j, H[j][k] += h2_j, h1 <- h2.
 __global__ __launch_bounds__(256) void k_gm_fin_dot(int k, int nbx, const double *partial, GmState *st, int mode)
 {
-    if (st->done) return;
+    if (st->done || (mode == 1 && !st->reorth)) return;
+    __shared__ double hsq[4];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double proj = 0;
     for (int j = wid; j <= k; j += 4) {
         double s = 0;
         for (int b = lane; b < nbx; b += 64) s += partial[(int64_t)j * nbx + b];
@@ -1211,37 +1221,38 @@ __global__ __launch_bounds__(256) void k_gm_fin_dot(int k, int nbx, const double
             const double h = s * st->s[j];
             if (mode == 0) {
                 st->h1[j] = h;
+                st->H[j * kMaxRestart + k] = h;
+                proj += h * h;
             } else {
-                st->H[j * kMaxRestart + k] = st->h1[j] + h;
+                st->H[j * kMaxRestart + k] += h;
                 st->h1[j] = h;
             }
         }
     }
-}
-
-// w -= sum_j h1_j V_j  (= sum_j h1_j s_j Vhat_j)
-template <typename T, int K>
-__global__ __launch_bounds__(256) void k_gm_axpy(int64_t n, int k, const T *V, int64_t ldv, T *w, const GmState *st)
-{
-    if (st->done) return;
-    __shared__ double coef[K];
-    if (threadIdx.x < K) coef[threadIdx.x] = (threadIdx.x <= (unsigned)k) ? st->h1[threadIdx.x] * st->s[threadIdx.x] : 0.0;
-    __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        double wi = to_d(w[i]);
+    if (mode != 0) return;
+    double ww = 0;
+    if (wid == 0) {
+        for (int b = lane; b < nbx; b += 64) ww += partial[(int64_t)(k + 1) * nbx + b];
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (j <= k) wi -= coef[j] * to_d(V[j * ldv + i]);
-        w[i] = (T)wi;
+        for (int off = 32; off > 0; off >>= 1) ww += __shfl_xor(ww, off);
+    }
+    if (lane == 0) hsq[wid] = proj;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double p = hsq[0] + hsq[1] + hsq[2] + hsq[3];
+        const int again = (p <= st->reorth_frac * ww) ? 0 : 1;   // also taken on a non-finite value
+        st->reorth = again;
+        st->n_reorth += again;
     }
 }
 
-// Vhat_{k+1} = w - sum_j h2_j V_j; partial[block] = sum Vhat_{k+1}^2
+// Vhat_{k+1} = w - sum_j h1_j V_j; partial[block] = sum Vhat_{k+1}^2.  The second
+// pass (second = 1, skipped unless asked for) takes w = Vhat_{k+1} in place.
 template <typename T, int K>
 __global__ __launch_bounds__(256) void k_gm_axpy_norm(int64_t n, int k, T *V, int64_t ldv, const T *w,
-                                                      const GmState *st, double *partial)
+                                                      const GmState *st, double *partial, int second)
 {
-    if (st->done) return;
+    if (st->done || (second && !st->reorth)) return;
     __shared__ double coef[K];
     __shared__ double lds[4];
     if (threadIdx.x < K) coef[threadIdx.x] = (threadIdx.x <= (unsigned)k) ? st->h1[threadIdx.x] * st->s[threadIdx.x] : 0.0;
@@ -1310,20 +1321,23 @@ __global__ __launch_bounds__(256) void k_gm_givens(int k, int nb, const double *
             hipLaunchKernelGGL((KERNEL<T, 64>), grid, dim3(256), 0, s, __VA_ARGS__);                          \
     } while (0)
 
-// One Arnoldi step's classical Gram-Schmidt with reorthogonalisation (CGS2) of
-// w against Vhat_0..Vhat_k, then Vhat_{k+1} and the Givens update.
+// One Arnoldi step's classical Gram-Schmidt of w against Vhat_0..Vhat_k, with a
+// second pass when the first one cancelled much of w (selective
+// reorthogonalisation; the device decides, the second-pass kernels return at
+// once otherwise), then Vhat_{k+1} and the Givens update.
 template <typename T>
 void launch_gm_orth(int64_t n, int k, T *V, int64_t ldv, T *w, GmState *st, double *partial, hipStream_t s)
 {
     const int nbx = (int)((n + kDotChunk - 1) / kDotChunk);
     const unsigned nbv = vec_blocks(n);
-    const dim3 gd(nbx, k + 1), gv(nbv);
-    hipLaunchKernelGGL((k_gm_dot<T>), gd, dim3(256), 0, s, n, V, ldv, w, partial, st);
+    const dim3 gd1(nbx, k + 2), gd2(nbx, k + 1), gv(nbv);
+    T *vn = V + (int64_t)(k + 1) * ldv;
+    hipLaunchKernelGGL((k_gm_dot<T>), gd1, dim3(256), 0, s, n, V, ldv, w, partial, st, k + 1, 0);
     hipLaunchKernelGGL(k_gm_fin_dot, dim3(1), dim3(256), 0, s, k, nbx, partial, st, 0);
-    LX_GM_K_DISPATCH(k_gm_axpy, T, gv, n, k, V, ldv, w, st);
-    hipLaunchKernelGGL((k_gm_dot<T>), gd, dim3(256), 0, s, n, V, ldv, w, partial, st);
+    LX_GM_K_DISPATCH(k_gm_axpy_norm, T, gv, n, k, V, ldv, w, st, partial, 0);
+    hipLaunchKernelGGL((k_gm_dot<T>), gd2, dim3(256), 0, s, n, V, ldv, vn, partial, st, k + 1, 1);
     hipLaunchKernelGGL(k_gm_fin_dot, dim3(1), dim3(256), 0, s, k, nbx, partial, st, 1);
-    LX_GM_K_DISPATCH(k_gm_axpy_norm, T, gv, n, k, V, ldv, w, st, partial);
+    LX_GM_K_DISPATCH(k_gm_axpy_norm, T, gv, n, k, V, ldv, vn, st, partial, 1);
     hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(256), 0, s, k, (int)nbv, partial, st);
 }
 template void launch_gm_orth<double>(int64_t, int, double *, int64_t, double *, GmState *, double *, hipStream_t);

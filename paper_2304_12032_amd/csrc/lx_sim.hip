@@ -403,6 +403,12 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     for (auto &b : bcs)
         if (b.d_hnodal) launch_fill<double>(3 * nu, b.d_hnodal, 0.0, stream);
     LX_HIP(hipMemsetAsync(d_st, 0, sizeof(GmState), stream));
+    {
+        const char *e = getenv("LXNS_REORTH_FRAC");
+        const double frac = e ? atof(e) : 0.9;   // second Gram-Schmidt pass below ||w|| / sqrt(10)
+        LX_HIP(hipMemcpyAsync(&d_st->reorth_frac, &frac, sizeof(double), hipMemcpyHostToDevice, stream));
+        LX_HIP(hipStreamSynchronize(stream));
+    }
     LX_HIP(hipEventCreate(&ev_step0));
     LX_HIP(hipEventCreate(&ev_step1));
     LX_HIP(hipEventCreate(&ev_asm1));
@@ -767,8 +773,9 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
         ++res.restarts;
         it += h_st->kused;
         if (verbose())
-            fprintf(stderr, "[lxns] gmres<%s> cycle %d: k=%d est=%.3e tol=%.3e bnorm=%.3e\n",
-                    sizeof(T) == 4 ? "f32" : "f64", cycle, h_st->kused, h_st->resid, h_st->tol_abs, h_st->norms[0]);
+            fprintf(stderr, "[lxns] gmres<%s> cycle %d: k=%d est=%.3e tol=%.3e bnorm=%.3e second passes %d\n",
+                    sizeof(T) == 4 ? "f32" : "f64", cycle, h_st->kused, h_st->resid, h_st->tol_abs, h_st->norms[0],
+                    h_st->n_reorth);
         launch_gm_solve_y(d_st, stream);
         launch_gm_update<T>(N, Z, ld, d_st, x, stream);
         if (inner && h_st->converged) {
