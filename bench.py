@@ -169,6 +169,80 @@ def run_precision(mesh, prob, precision, args, stream, torch):
     }
 
 
+# VALU flops per element of the assembly passes, from SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS} counters on the
+# 983k-tet tube (64 x (ADD + MUL + TRANS) + 128 x FMA per wave instruction): element + slot gather of the
+# FP64 and of the FP32 path, and one FP64 matrix-free residual evaluation (element pass).
+ASM_FLOPS_PER_TET = {"fp64": {"f64": 2383.0 + 6445.0, "f32": 0.0},
+                     "fp32_ir": {"f64": 206.0 + 6197.0, "f32": 1698.0}}
+RESID_FLOPS_PER_TET = 3216.0
+FP64_PEAK, FP32_PEAK = 78.6e12, 157.3e12
+
+
+def mean_arnoldi_column(iters_per_solve, restart):
+    """Mean column index k of the Arnoldi steps of a solve of that many iterations, restarted every
+    `restart` steps."""
+    n = max(int(round(iters_per_solve)), 1)
+    ks = [j % restart for j in range(n)]
+    return sum(ks) / len(ks)
+
+
+def step_bound(q, prec, iters, ir_iters, args):
+    """Lower bound of one P1-P1 step: algorithmic HBM bytes (what each pass must read and write once)
+    over 8 TB/s plus the assembly and residual VALU flops over the vector peaks.  Per GMRES iteration:
+    SpMV, the AMG-SIMPLE apply (F Chebyshev passes, B pass, the Schur cycle level by level, G pass) and
+    Gram-Schmidt; per step: assembly, preconditioner set-up and (FP32+IR) the FP64 residuals."""
+    s = 4 if prec == "fp32_ir" else 8
+    nv, nblk, nt = q["n_vertices"], q["n_blocks"], q["n_tets"]
+    rows, nnz, nlev, tail = q["amg_level_rows"], q["amg_level_nnz"], q["amg_levels"], q["amg_tail_level"]
+    vec = 4 * nv * s
+    spmv = nblk * (16 * s + 4) + 4 * (nv + 1) + 2 * vec
+    fdeg = args.f_degree or 3
+    fcheb = nblk * (9 * s + 4) + nv * (4 + 33 * s)
+    apply_f = nv * 25 * s + (fdeg - 1) * fcheb
+    zp = nblk * (3 * s + 4) + nv * (4 + 9 * s)
+    xu = nblk * (3 * s + 4) + nv * (4 + 12 * s)
+    deg, cyc = args.amg_degree, args.amg_cycle
+    dense = nlev - 1
+
+    def cheb(l):
+        return nnz[l] * (s + 4) + rows[l] * (4 + 7 * s)
+
+    def visit(l):
+        if l == dense:
+            return rows[l - 1] * (s + 4) + 8 * rows[l] * rows[l]
+        if tail and l == tail:
+            lv = range(l, dense)
+            return (rows[l - 1] * (s + 4) + sum(nnz[m] * (s + 4) + rows[m] * (12 + s) for m in lv)
+                    + 16 * rows[dense] * rows[dense] + rows[l] * s)
+        b = (rows[l - 1] * (s + 4) + rows[l] * 5 * s) if l > 0 else 0
+        b += (deg - 1) * cheb(l)
+        g = cyc if l > 0 else 1
+        b += g * (nnz[l] * (s + 4) + rows[l] * (4 + 3 * s) + visit(l + 1) + nnz[l] * (s + 4) + rows[l] * (8 + 6 * s)
+                  + (deg - 1) * cheb(l))
+        return b
+
+    precond = apply_f + zp + visit(0) + xu
+    solves = max(ir_iters, 1) if prec == "fp32_ir" else 1
+    kbar = mean_arnoldi_column(iters / solves, args.restart)
+    orth = (2 * kbar + 5) * vec
+    per_iter = spmv + precond + orth
+    sa = s if not args.asm_fp64 else 8
+    hist = 2
+    asm = nt * (16 + 72 * sa) + nv * (24 + 32 * hist) + nt * (72 * sa + 64) + nblk * (4 + 16 * sa)
+    setup = (nv * (9 * s + 4) + nv * 12 * s                                    # nodal inverses
+             + 2 * nblk * (3 * s + 4) + nblk * (s + 4) + 3 * nv * s + nnz[0] * (s + 4)   # S~ formation
+             + sum(nnz[l] * (s + 4) + nnz[l + 1] * s + nnz[l] * s for l in range(dense))  # Galerkin sums, bounds
+             + 6 * (nblk * (9 * s + 4) + nv * (4 + 13 * s)))                  # power iterations on F
+    resid = (ir_iters + 1) * (nt * (48 * 8 + 16) * 2 + nv * (32 + 32)) if prec == "fp32_ir" else 0
+    nbytes = iters * per_iter + asm + setup + resid
+    fl = ASM_FLOPS_PER_TET[prec]
+    f64 = nt * fl["f64"] + ((ir_iters + 1) * nt * RESID_FLOPS_PER_TET if prec == "fp32_ir" else 0)
+    f32 = nt * fl["f32"]
+    t = nbytes / (HBM_PEAK_GBS * 1e9) + f64 / FP64_PEAK + f32 / FP32_PEAK
+    return {"bytes_per_step": int(nbytes), "bytes_per_gmres_iter": int(per_iter), "f64_flops": f64, "f32_flops": f32,
+            "bound_ms": round(t * 1e3, 3)}
+
+
 def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
     """Device-to-device copy rate (bytes read + bytes written per second, GB/s) of a
     1 GiB buffer: the attainable-bandwidth reference beside the vendor peak."""
@@ -380,6 +454,10 @@ def main():
                      "bytes_per_launch": sb, "avg_launch_ms": round(head["spmv_avg_ms"], 5),
                      "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
     }
+    if not p2 and args.precond == "amg":
+        sb_ = step_bound(q, headp, head["iters"], head["ir"], args)
+        sb_["frac"] = round(sb_["bound_ms"] / (head["wall_s"] * 1e3 / args.steps), 4)
+        out["step_bound"] = sb_
     if "fp64" in res and "fp32_ir" in res:
         f64 = res["fp64"]
         out["fp64"] = {"value": round(f64["mdofs"], 4), "ms_per_step": round(f64["wall_s"] * 1e3 / args.steps, 3),
@@ -389,6 +467,10 @@ def main():
                        "spmv_avg_ms": round(f64["spmv_avg_ms"], 5),
                        "spmv_GBps": round((spmv_bytes_p2(q, 8) if p2 else spmv_bytes(nblk, nv, 8)) /
                                           (f64["spmv_avg_ms"] * 1e-3) / 1e9, 1)}
+        if not p2 and args.precond == "amg":
+            b64 = step_bound(f64["q"], "fp64", f64["iters"], 0, args)
+            b64["frac"] = round(b64["bound_ms"] / (f64["wall_s"] * 1e3 / args.steps), 4)
+            out["fp64"]["step_bound"] = b64
         out["fp32_ir"] = {"ir_iters_per_step": head["ir"], "max_rel_residual": head["res"],
                           "resid_kernel_avg_ms": round(head["resid_avg_ms"], 4),
                           "asm_kernel_avg_ms": round(head["asm_kernel_ms"], 4)}

@@ -209,6 +209,8 @@ typedef struct {
     int32_t amg_tail_level;  /* LX_PC_AMG: first level cycled by one workgroup out
                                 of LDS, down to the dense level (0: none; the
                                 environment variable LXNS_AMG_TAIL=0 turns it off) */
+    int64_t amg_level_rows[8];   /* LX_PC_AMG: rows of levels 0..7 (0 past the last)   */
+    int64_t amg_level_nnz[8];    /* LX_PC_AMG: stored entries of levels 0..7           */
 } lx_sizes;
 
 typedef struct {

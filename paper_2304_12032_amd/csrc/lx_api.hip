@@ -47,10 +47,15 @@ extern "C" lx_status lx_sim_query(const lx_sim *s, lx_sizes *out)
     out->n_scalar_nnz = s->p2 ? 9 * s->s64.nf + 3 * s->s64.ng + 3 * s->s64.nb + s->s64.nc : 16 * s->nblk;
     out->amg_levels = 0;
     out->amg_tail_level = 0;
+    for (int l = 0; l < 8; ++l) out->amg_level_rows[l] = out->amg_level_nnz[l] = 0;
     if (s->solver.precond == LX_PC_AMG) {
         const bool f64 = s->solver.precision == LX_FP64;
         out->amg_levels = 1 + (f64 ? s->amg64.nlev : s->amg32.nlev);
         out->amg_tail_level = f64 ? s->amg64.tail.first : s->amg32.tail.first;
+        for (int l = 0; l < out->amg_levels && l < 8; ++l) {
+            out->amg_level_rows[l] = f64 ? s->amg64.L[l].n : s->amg32.L[l].n;
+            out->amg_level_nnz[l] = f64 ? s->amg64.L[l].nnz : s->amg32.L[l].nnz;
+        }
     }
     return LX_OK;
 }

@@ -83,7 +83,8 @@ class lx_solver(ctypes.Structure):
 class lx_sizes(ctypes.Structure):
     _fields_ = [("n_vertices", c_i64), ("n_tets", c_i64), ("n_u_nodes", c_i64), ("n_dofs", c_i64),
                 ("n_blocks", c_i64), ("device_bytes", c_i64), ("n_edges", c_i64), ("n_scalar_nnz", c_i64),
-                ("amg_levels", c_i32), ("amg_tail_level", c_i32)]
+                ("amg_levels", c_i32), ("amg_tail_level", c_i32),
+                ("amg_level_rows", c_i64 * 8), ("amg_level_nnz", c_i64 * 8)]
 
 
 class lx_step_stats(ctypes.Structure):
@@ -283,7 +284,11 @@ class Sim:
     def query(self):
         s = lx_sizes()
         check(lib().lx_sim_query(self.h, ctypes.byref(s)))
-        return {k: getattr(s, k) for k, _ in s._fields_}
+        out = {}
+        for k, _ in s._fields_:
+            v = getattr(s, k)
+            out[k] = list(v) if isinstance(v, ctypes.Array) else v
+        return out
 
     def set_state(self, level, u, p, d=None):
         u = np.ascontiguousarray(u, dtype=np.float64)
