@@ -93,6 +93,8 @@ struct HostSetup {
     std::vector<int32_t> eslot;     // [16][nt] slot of block (a,b), index (4a+b)*nt + e
     std::vector<int32_t> sinc_ptr;  // [nblk+1] incidence of each slot ...
     std::vector<int32_t> sinc;      // [16 nt]  ... as codes 16 e + 4a + b, by element then (a, b)
+    std::vector<int32_t> vinc_ptr;  // [nv+1] vertex incidence: the diagonal slots' lists in vertex order
+    std::vector<int32_t> vpos;      // [4][nt] position of (element, local vertex) in that order
     double hmin = 0;
 };
 

@@ -30,15 +30,16 @@ struct AsmArgs {
     T *rhs;                // [nv][4] or null
 };
 
-// Per-element record of the FP64 residual: r [4][4], b [4][4], Dirichlet
-// diagonal [4][3] of the element's vertices.
+// Contributions of the FP64 residual, one per (element, local vertex), stored in
+// vertex-incidence order: r [4 nt][4], then b [4 nt][4], then the Dirichlet
+// diagonal [4 nt][4] (3 used): kRRec doubles per element in all.
 constexpr int kRRec = 48;
 
 struct ResArgs {
     int64_t nt, nv;
     const int32_t *tet;
-    const int32_t *diag, *sinc_ptr, *sinc;   // diagonal slot of each vertex and slot incidence
-    double *rec;             // [nt][kRRec]
+    const int32_t *vinc_ptr, *vpos;   // vertex incidence ranges; position of (element, local vertex)
+    double *rec;             // [3][4 nt][4]
     const double *x, *xh, *h0, *h1, *h2, *uA, *f;
     const double *xs;        // iterate [nv][4]
     const int32_t *dir_index;  // [nv] Dirichlet index or -1

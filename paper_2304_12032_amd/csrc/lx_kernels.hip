@@ -509,17 +509,18 @@ __global__ __launch_bounds__(256) void k_residual_p1(ResArgs A, StepCoef C)
         }
     }
     const double mv = mu * E.vol;
-    double *R = A.rec + e * kRRec;
+    const int64_t n4 = 4 * A.nt;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         const bool free_u = dir[a] < 0;
+        double *R = A.rec + 4 * (int64_t)A.vpos[(int64_t)a * A.nt + e];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) R[4 * a + c] = free_u ? ru[a][c] : 0.0;
-        R[4 * a + 3] = rp[a];
+        for (int c = 0; c < 3; ++c) R[c] = free_u ? ru[a][c] : 0.0;
+        R[3] = rp[a];
         if (A.b) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) R[16 + 4 * a + c] = free_u ? bu[a][c] : 0.0;
-            R[16 + 4 * a + 3] = bp[a];
+            for (int c = 0; c < 3; ++c) R[4 * n4 + c] = free_u ? bu[a][c] : 0.0;
+            R[4 * n4 + 3] = bp[a];
         }
         if (A.dg) {
             const double gaa = E.dphi[a][0] * E.dphi[a][0] + E.dphi[a][1] * E.dphi[a][1] + E.dphi[a][2] * E.dphi[a][2];
@@ -527,34 +528,36 @@ __global__ __launch_bounds__(256) void k_residual_p1(ResArgs A, StepCoef C)
             for (int c = 0; c < 3; ++c) {
                 double d = dg[a][c] + mv * gaa;
                 if (C.symgrad) d += mv * E.dphi[a][c] * E.dphi[a][c];
-                R[32 + 3 * a + c] = free_u ? 0.0 : d;
+                R[8 * n4 + c] = free_u ? 0.0 : d;
             }
         }
     }
 }
 
-// Vertex pass of the residual: sums the records of the elements around each
-// vertex (the incidence list of its diagonal block) and writes r, b and the
+// Vertex pass of the residual: sums the contributions of the elements around
+// each vertex, which lie one after the other in vertex-incidence order (the
+// order of the vertex's diagonal-block incidence list), and writes r, b and the
 // Dirichlet diagonal once.
 __global__ __launch_bounds__(256) void k_residual_gather(ResArgs A)
 {
     const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= A.nv) return;
-    const int32_t k = A.diag[i];
+    const int64_t n4 = 4 * A.nt;
     double r[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0}, d[3] = {0, 0, 0};
-    for (int32_t q = A.sinc_ptr[k]; q < A.sinc_ptr[k + 1]; ++q) {
-        const int32_t code = A.sinc[q];
-        const int64_t e = code >> 4;
-        const int a = code & 3;   // diagonal block: local (a, a)
-        const double *R = A.rec + e * kRRec;
+    for (int32_t q = A.vinc_ptr[i]; q < A.vinc_ptr[i + 1]; ++q) {
+        const double *R = A.rec + 4 * (int64_t)q;
+        using V = typename V4<double>::type;
+        const V rv = *reinterpret_cast<const V *>(R);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) r[c] += R[4 * a + c];
-        if (A.b)
+        for (int c = 0; c < 4; ++c) r[c] += rv.v[c];
+        if (A.b) {
+            const V bv = *reinterpret_cast<const V *>(R + 4 * n4);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] += R[16 + 4 * a + c];
+            for (int c = 0; c < 4; ++c) b[c] += bv.v[c];
+        }
         if (A.dg)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) d[c] += R[32 + 3 * a + c];
+            for (int c = 0; c < 3; ++c) d[c] += R[8 * n4 + c];
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) A.r[4 * i + c] = r[c];

@@ -76,6 +76,7 @@ int64_t estimate_footprint(const Request &r)
     int64_t b = 0;
     b += nblk * (16 * s + 8);                 // planes + col + tslot
     b += nt * (16 + 64) + 4 * nblk;           // connectivity + slot incidence
+    b += nt * 16 + 4 * (nv + 1);              // vertex incidence of the residual pass
     b += nt * lx::kRec * ((r.solver.precision == LX_FP64 || r.solver.asm_fp64) ? 8 : 4);   // element records
     b += nv * (48 + 16 + 12 * s + 4);         // coords, rowptr/diag/dir index, SIMPLE blocks
     b += N * 8 * (r.problem.bdf_order + 2);   // history + solution (FP64)

@@ -224,6 +224,21 @@ lx_status build_setup(const lx_mesh *m, HostSetup &hs)
                 hs.sinc[fill[k]++] = (int32_t)(16 * e + ab);
             }
     }
+    // vertex incidence for the residual pass: the diagonal slots' lists one after
+    // the other, and where each (element, local vertex) lands in them
+    hs.vinc_ptr.assign(nv + 1, 0);
+    for (int64_t v = 0; v < nv; ++v)
+        hs.vinc_ptr[v + 1] = hs.vinc_ptr[v] + (hs.sinc_ptr[hs.diag[v] + 1] - hs.sinc_ptr[hs.diag[v]]);
+    hs.vpos.assign(4 * nt, -1);
+    for (int64_t v = 0; v < nv; ++v) {
+        const int32_t k = hs.diag[v];
+        for (int32_t q = hs.sinc_ptr[k]; q < hs.sinc_ptr[k + 1]; ++q) {
+            const int32_t code = hs.sinc[q];
+            hs.vpos[(int64_t)((code >> 2) & 3) * nt + (code >> 4)] = hs.vinc_ptr[v] + (q - hs.sinc_ptr[k]);
+        }
+    }
+    if (hs.vinc_ptr[nv] != 4 * nt || std::find(hs.vpos.begin(), hs.vpos.end(), -1) != hs.vpos.end())
+        return fail(LX_EMESH, "inconsistent vertex incidence");
     return LX_OK;
 }
 

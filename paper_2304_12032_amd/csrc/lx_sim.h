@@ -64,6 +64,7 @@ struct Sim {
     // device arrays (new numbering)
     double *d_xh = nullptr, *d_x = nullptr;
     int32_t *d_sinc_ptr = nullptr, *d_sinc = nullptr;             // slot incidence of the assembly gather
+    int32_t *d_vinc_ptr = nullptr, *d_vpos = nullptr;             // vertex incidence of the residual pass
     double *d_rec64 = nullptr;                                    // element records (FP64 assembly)
     float *d_rec32 = nullptr;                                     // element records (FP32 assembly)
     int32_t *d_tet = nullptr, *d_rowptr = nullptr, *d_col = nullptr, *d_diag = nullptr,

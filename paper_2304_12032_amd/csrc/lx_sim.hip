@@ -227,6 +227,10 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     ALLOC(d_tet, sizeof(int32_t) * 4 * nt);
     ALLOC(d_sinc_ptr, sizeof(int32_t) * (nblk + 1));
     ALLOC(d_sinc, sizeof(int32_t) * 16 * nt);
+    if (!p2) {
+        ALLOC(d_vinc_ptr, sizeof(int32_t) * (nv + 1));
+        ALLOC(d_vpos, sizeof(int32_t) * 4 * nt);
+    }
     if (p2) {
         const P2Setup &q = p2h;
         ALLOC(d_nodes, sizeof(int32_t) * 10 * nt);
@@ -352,6 +356,11 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     LX_HIP(hipMemcpyAsync(d_sinc_ptr, hs.sinc_ptr.data(), sizeof(int32_t) * (nblk + 1), hipMemcpyHostToDevice,
                           stream));
     LX_HIP(hipMemcpyAsync(d_sinc, hs.sinc.data(), sizeof(int32_t) * 16 * nt, hipMemcpyHostToDevice, stream));
+    if (!p2) {
+        LX_HIP(hipMemcpyAsync(d_vinc_ptr, hs.vinc_ptr.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice,
+                              stream));
+        LX_HIP(hipMemcpyAsync(d_vpos, hs.vpos.data(), sizeof(int32_t) * 4 * nt, hipMemcpyHostToDevice, stream));
+    }
     LX_HIP(hipMemcpyAsync(d_rowptr, hs.rowptr.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_col, hs.col.data(), sizeof(int32_t) * nblk, hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_diag, hs.diag.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, stream));
@@ -999,7 +1008,7 @@ lx_status Sim::residual64(const StepCoef &C, const double *xs, bool first, doubl
         launch_fill<double>(N, d_b64, 0.0, stream);
         if (n_dir > 0) launch_fill<double>(3 * n_dir, d_dg, 0.0, stream);
     }
-    ResArgs R{nt, nv, d_tet, d_diag, d_sinc_ptr, d_sinc, d_rrec, d_x, d_xh, hist(0), hist(1), hist(2), d_uA, d_f,
+    ResArgs R{nt, nv, d_tet, d_vinc_ptr, d_vpos, d_rrec, d_x, d_xh, hist(0), hist(1), hist(2), d_uA, d_f,
               xs, d_dir_index, d_r64, first ? d_b64 : nullptr, first ? d_dg : nullptr};
     auto *tm = timer_begin(2, 0);
     launch_residual_p1(R, C, stream);
