@@ -46,9 +46,10 @@ __device__ inline int32_t find_col(const int32_t *col, int32_t lo, int32_t hi, i
 // row).  The sum runs over B's row in order, so the result does not depend on
 // scheduling.  Rows whose rows do not fit the LDS share search C and G in
 // global memory instead, with the same arithmetic.
+// The LDS share per row is a template pair (B and C entries at most ROWS <= 128,
+// staged products at most CAP): a small one for P1-P1, whose rows are short,
+// keeps more workgroups per compute unit; P2-P1 rows need the large one.
 constexpr int kSfWaves = 4;      // waves (rows) per workgroup
-constexpr int kSfRows = 96;      // B (and C) entries per row that fit the LDS share (at most 128)
-constexpr int kSfCap = 640;      // staged products per row that fit the LDS share
 
 __device__ inline int32_t find_col_lds(const int32_t *col, int32_t lo, int32_t hi, int32_t k)
 {
@@ -74,7 +75,7 @@ __device__ inline double schur_term(const SimpleView<T> &V, const T *__restrict_
            (double)V.Bv[2 * V.bs + k1] * (double)Dinv[2 * nu + j] * (double)V.Gv[2 * V.gs + kg];
 }
 
-template <typename T>
+template <typename T, int kSfRows, int kSfCap>
 __global__ __launch_bounds__(256) void k_schur_form(SimpleView<T> V, const T *__restrict__ Dinv,
                                                     const int32_t *__restrict__ srow,
                                                     const int32_t *__restrict__ scol, T *__restrict__ sval)
@@ -1033,8 +1034,11 @@ void launch_amg_setup(const SimpleView<T> &V, const T *Finv, const T *Dinv, Amg<
     const RowPattern &P = V.Fp;
     const T *val = V.F;
     AmgLevel<T> &L0 = A.L[0];
-    hipLaunchKernelGGL((k_schur_form<T>), dim3((unsigned)((V.np + kSfWaves - 1) / kSfWaves)), dim3(64 * kSfWaves),
-                       0, s, V, Dinv, L0.rowptr, L0.col, L0.val);
+    const dim3 gsf((unsigned)((V.np + kSfWaves - 1) / kSfWaves)), bsf(64 * kSfWaves);
+    if (V.nu == V.np)
+        hipLaunchKernelGGL((k_schur_form<T, 48, 384>), gsf, bsf, 0, s, V, Dinv, L0.rowptr, L0.col, L0.val);
+    else
+        hipLaunchKernelGGL((k_schur_form<T, 96, 640>), gsf, bsf, 0, s, V, Dinv, L0.rowptr, L0.col, L0.val);
     for (int l = 0; l < A.nlev; ++l) {
         AmgLevel<T> &L = A.L[l];
         const unsigned g = rows_grid(L.n, L.lpr);
