@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-budget-gb", type=float, default=0.0, help="HBM admission budget (0: 200 GB)")
     ap.add_argument("--serve-max-active", type=int, default=64)
+    ap.add_argument("--serve-streams", type=int, default=8, help="HIP streams of the server")
     ap.add_argument("--serve-verify", type=int, default=4,
                     help="replay this many requests (the smallest, plus the largest) alone afterwards and "
                          "compare with their results in the mix")
@@ -304,7 +305,7 @@ def serve(args, torch):
         if args.verbose and i % 8 == 0:
             print("[bench] generated request %d (%d tets)" % (i, m.nt), file=sys.stderr, flush=True)
     budget = int((args.serve_budget_gb or 200.0) * (1 << 30))
-    srv = Server(hbm_budget_bytes=budget, max_active=args.serve_max_active, n_streams=8)
+    srv = Server(hbm_budget_bytes=budget, max_active=args.serve_max_active, n_streams=args.serve_streams)
     sv = SolverCfg(precision="fp32_ir", rtol=1e-8, ir_rtol=1e-8, max_iters=20000)
     tickets, done, lat, mix, failed = {}, {}, [], {}, []
     order = np.argsort(sizes, kind="stable")

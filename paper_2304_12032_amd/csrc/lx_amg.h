@@ -47,7 +47,19 @@ struct AmgLevel {
     int32_t *agg = nullptr, *mptr = nullptr, *mem = nullptr, *cptr = nullptr, *cidx = nullptr;
     T *r = nullptr, *x0 = nullptr, *x1 = nullptr, *res = nullptr, *d0 = nullptr, *d1 = nullptr;
     int lpr = 16;
+    // Sliced-ELL storage (the finest level): rows in slices of 64, entry j of row i
+    // at soff[i / 64] + 64 j + i % 64, slices as wide as their longest row, the
+    // padding a zero value in the row's own column.  val and scol then hold
+    // that layout (rowptr/col keep the CSR pattern); soff = null: plain CSR.
+    int32_t *soff = nullptr, *swid = nullptr, *scol = nullptr;
+    int64_t nsell = 0;
 };
+
+// Position of CSR entry e of row i in the sliced-ELL layout.
+inline int64_t sell_pos(const std::vector<int32_t> &soff, const std::vector<int32_t> &rowptr, int64_t i, int64_t e)
+{
+    return (int64_t)soff[i >> 6] + (e - rowptr[i]) * 64 + (i & 63);
+}
 
 // The coarse end of the hierarchy (from level `first` down to the dense level)
 // runs as one workgroup out of LDS.  Its arrays sit in one device buffer laid

@@ -78,7 +78,8 @@ __device__ inline double schur_term(const SimpleView<T> &V, const T *__restrict_
 template <typename T, int kSfRows, int kSfCap>
 __global__ __launch_bounds__(256) void k_schur_form(SimpleView<T> V, const T *__restrict__ Dinv,
                                                     const int32_t *__restrict__ srow,
-                                                    const int32_t *__restrict__ scol, T *__restrict__ sval)
+                                                    const int32_t *__restrict__ scol, T *__restrict__ sval,
+                                                    const int32_t *__restrict__ soff)
 {
     __shared__ int32_t s_off[kSfWaves][kSfRows + 1];
     __shared__ int32_t s_j[kSfWaves][kSfRows];
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(256) void k_schur_form(SimpleView<T> V, const T *__
                 if (kg >= 0) acc -= schur_term(V, Dinv, k1, j, kg);
             }
         }
-        sval[e] = (T)acc;
+        sval[soff ? (int64_t)soff[i >> 6] + (int64_t)(e - srow[i]) * 64 + (i & 63) : (int64_t)e] = (T)acc;
     }
 }
 
@@ -702,6 +703,97 @@ __global__ __launch_bounds__(256) void k_dense_solve(int nc, const double *__res
     }
 }
 
+// ---- the finest level in sliced-ELL order: one lane per row, the entries of 64
+// consecutive rows side by side, so every load of a step over j is one
+// contiguous 256-byte run; each row's sum runs over its entries in order.
+
+template <typename T>
+__device__ __forceinline__ double sell_row_dot(const AmgLevel<T> &L, const T *__restrict__ x, int64_t row)
+{
+    const int64_t base = L.soff[row >> 6] + (row & 63);
+    const int w = L.swid[row >> 6];
+    double q = 0;
+#pragma unroll 8
+    for (int j = 0; j < w; ++j) {
+        const int64_t p = base + 64 * (int64_t)j;
+        q += (double)L.val[p] * (double)x[L.scol[p]];
+    }
+    return q;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_amg_rowinfo_sell(AmgLevel<T> L, double *partial)
+{
+    __shared__ double lds[4];
+    const int64_t row = xcd_block() * blockDim.x + threadIdx.x;
+    double g = 0;
+    if (row < L.n) {
+        const int64_t base = L.soff[row >> 6] + (row & 63);
+        const int w = L.swid[row >> 6];
+        double s = 0;
+        for (int j = 0; j < w; ++j) s += fabs((double)L.val[base + 64 * (int64_t)j]);
+        const int32_t dk = L.diag[row];
+        const double a = dk >= 0 ? (double)L.val[base + 64 * (int64_t)(dk - L.rowptr[row])] : 0.0;
+        const double di = a != 0.0 ? 1.0 / a : 0.0;
+        L.dinv[row] = (T)di;
+        g = s * fabs(di);
+    }
+    const double m = block_max(g, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_amg_cheb_sell(AmgLevel<T> L, T *__restrict__ x, const T *__restrict__ dcur,
+                                                       T *__restrict__ dnext, const double *lam, double ratio, int step,
+                                                       const int32_t *done)
+{
+    if (done && *done) return;
+    const int64_t row = xcd_block() * blockDim.x + threadIdx.x;
+    if (row >= L.n) return;
+    const double q = sell_row_dot(L, dcur, row);
+    double theta, a, b;
+    cheb_coef(*lam, ratio, step, theta, a, b);
+    const double r = (double)L.res[row] - q;
+    L.res[row] = (T)r;
+    const double dn = a * (double)dcur[row] + b * (double)L.dinv[row] * r;
+    dnext[row] = (T)dn;
+    x[row] = (T)((double)x[row] + dn);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_amg_resid_sell(AmgLevel<T> L, const T *__restrict__ x, const int32_t *done)
+{
+    if (done && *done) return;
+    const int64_t row = xcd_block() * blockDim.x + threadIdx.x;
+    if (row >= L.n) return;
+    L.res[row] = (T)((double)L.r[row] - sell_row_dot(L, x, row));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_amg_post0_sell(AmgLevel<T> L, const T *__restrict__ e, const double *lam,
+                                                        double ratio, const int32_t *done)
+{
+    if (done && *done) return;
+    const int64_t row = xcd_block() * blockDim.x + threadIdx.x;
+    if (row >= L.n) return;
+    const int64_t base = L.soff[row >> 6] + (row & 63);
+    const int w = L.swid[row >> 6];
+    double q = 0;
+#pragma unroll 8
+    for (int j = 0; j < w; ++j) {
+        const int64_t p = base + 64 * (int64_t)j;
+        const int32_t c = L.scol[p];
+        q += (double)L.val[p] * ((double)L.x0[c] + (double)e[L.agg[c]]);
+    }
+    double theta, a, b;
+    cheb_coef(*lam, ratio, 0, theta, a, b);
+    const double r = (double)L.r[row] - q;
+    const double d = (double)L.dinv[row] * r / theta;
+    L.res[row] = (T)r;
+    L.d0[row] = (T)d;
+    L.x1[row] = (T)((double)L.x0[row] + (double)e[L.agg[row]] + d);
+}
+
 // ================================================================== one-workgroup coarse cycle
 
 // The levels from `first` down to the dense one, cycled by one workgroup out of
@@ -1036,14 +1128,20 @@ void launch_amg_setup(const SimpleView<T> &V, const T *Finv, const T *Dinv, Amg<
     AmgLevel<T> &L0 = A.L[0];
     const dim3 gsf((unsigned)((V.np + kSfWaves - 1) / kSfWaves)), bsf(64 * kSfWaves);
     if (V.nu == V.np)
-        hipLaunchKernelGGL((k_schur_form<T, 48, 384>), gsf, bsf, 0, s, V, Dinv, L0.rowptr, L0.col, L0.val);
+        hipLaunchKernelGGL((k_schur_form<T, 48, 384>), gsf, bsf, 0, s, V, Dinv, L0.rowptr, L0.col, L0.val, L0.soff);
     else
-        hipLaunchKernelGGL((k_schur_form<T, 96, 640>), gsf, bsf, 0, s, V, Dinv, L0.rowptr, L0.col, L0.val);
+        hipLaunchKernelGGL((k_schur_form<T, 96, 640>), gsf, bsf, 0, s, V, Dinv, L0.rowptr, L0.col, L0.val, L0.soff);
     for (int l = 0; l < A.nlev; ++l) {
         AmgLevel<T> &L = A.L[l];
-        const unsigned g = rows_grid(L.n, L.lpr);
-        LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_rowinfo<T, LP>), dim3(g), dim3(256), 0, s, L.n, L.rowptr,
-                                                L.diag, L.val, L.dinv, A.partial));
+        unsigned g;
+        if (L.soff) {
+            g = flat_grid(L.n);
+            hipLaunchKernelGGL((k_amg_rowinfo_sell<T>), dim3(g), dim3(256), 0, s, L, A.partial);
+        } else {
+            g = rows_grid(L.n, L.lpr);
+            LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_rowinfo<T, LP>), dim3(g), dim3(256), 0, s, L.n, L.rowptr,
+                                                    L.diag, L.val, L.dinv, A.partial));
+        }
         hipLaunchKernelGGL(k_max_fin, dim3(1), dim3(256), 0, s, (int)g, A.partial, &A.lam[l]);
         AmgLevel<T> &C = A.L[l + 1];
         hipLaunchKernelGGL((k_amg_coarsen<T, 16>), dim3(rows_grid(C.nnz, 16)), dim3(256), 0, s, C.nnz, L.cptr, L.cidx,
@@ -1112,26 +1210,40 @@ static void vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s)
         hipLaunchKernelGGL((k_amg_pre<T, 16>), dim3(rows_grid(L.n, 16)), dim3(256), 0, s, L, F.res, F.mptr, F.mem,
                            lam, A.ratio, done);
     }
+    const dim3 gsell(flat_grid(L.n));
     T *dc = L.d0, *dn = L.d1;
     for (int i = 1; i < A.degree; ++i) {
-        LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_cheb<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s, L,
-                                                L.x0, dc, dn, lam, A.ratio, i, done));
+        if (L.soff)
+            hipLaunchKernelGGL((k_amg_cheb_sell<T>), gsell, dim3(256), 0, s, L, L.x0, dc, dn, lam, A.ratio, i, done);
+        else
+            LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_cheb<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s,
+                                                    L, L.x0, dc, dn, lam, A.ratio, i, done));
         std::swap(dc, dn);
     }
     // gamma coarse corrections (1: V-cycle, 2: W-cycle below the finest level),
     // each followed by post-smoothing; the iterate alternates between x0 and x1
     const int gamma = l > 0 ? A.cycle : 1;
     for (int c = 0; c < gamma; ++c) {
-        LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_resid<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s, L,
-                                                L.x0, done));
+        if (L.soff)
+            hipLaunchKernelGGL((k_amg_resid_sell<T>), gsell, dim3(256), 0, s, L, L.x0, done);
+        else
+            LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_resid<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s,
+                                                    L, L.x0, done));
         vcycle(A, l + 1, done, s);
-        LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_post0<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s, L,
-                                                A.L[l + 1].x1, lam, A.ratio, done));
+        if (L.soff)
+            hipLaunchKernelGGL((k_amg_post0_sell<T>), gsell, dim3(256), 0, s, L, A.L[l + 1].x1, lam, A.ratio, done);
+        else
+            LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_post0<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s,
+                                                    L, A.L[l + 1].x1, lam, A.ratio, done));
         dc = L.d0;
         dn = L.d1;
         for (int i = 1; i < A.degree; ++i) {
-            LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_cheb<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s,
-                                                    L, L.x1, dc, dn, lam, A.ratio, i, done));
+            if (L.soff)
+                hipLaunchKernelGGL((k_amg_cheb_sell<T>), gsell, dim3(256), 0, s, L, L.x1, dc, dn, lam, A.ratio, i,
+                                   done);
+            else
+                LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_cheb<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0,
+                                                        s, L, L.x1, dc, dn, lam, A.ratio, i, done));
             std::swap(dc, dn);
         }
         if (c + 1 < gamma) std::swap(L.x0, L.x1);

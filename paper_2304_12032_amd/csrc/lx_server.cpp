@@ -84,7 +84,8 @@ int64_t estimate_footprint(const Request &r)
     if (r.solver.precond == LX_PC_AMG)
         // S~ on the vertex 2-ring (about 4x the block count) with its coarsening
         // lists, level vectors, velocity-block Chebyshev work, coarse levels
-        b += 4 * nblk * (s + 8) + nv * (22 * s + 24) + (3 << 20);
+        // (the finest level also in sliced-ELL order: about 10% padding)
+        b += 4 * nblk * (s + s / 4 + 14) + nv * (22 * s + 24) + (3 << 20);
     else
         b += nv * s * 9;                      // Schur Chebyshev work
     if (r.solver.precision != LX_FP64) b += N * (8 * 2 + 4 * 2) + nt * lx::kRRec * 8;

@@ -489,6 +489,10 @@ lx_status Sim::setup_amg(Amg<T> &A)
         }
     }
     auto in_img = [&](int l) { return A.tail.first > 0 && l >= A.tail.first && l < A.nlev; };
+    // the finest smoothed level in sliced-ELL order (LXNS_AMG_SELL=0: plain CSR)
+    const char *se = getenv("LXNS_AMG_SELL");
+    const bool sell0 = A.nlev > 0 && !(se && *se == '0');
+    std::vector<int32_t> soff0;
     auto img_up = [&](int32_t *&d, int32_t off, const std::vector<int32_t> &h) -> lx_status {
         d = reinterpret_cast<int32_t *>(A.tail_img + off);
         if (!h.empty()) LX_HIP(hipMemcpyAsync(d, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, stream));
@@ -512,7 +516,35 @@ lx_status Sim::setup_amg(Amg<T> &A)
         } else {
             CK(up(L.rowptr, H.rowptr));
             CK(up(L.col, H.col));
-            CK(vec(L.val, L.nnz));
+            if (l == 0 && sell0) {
+                // the finest level in sliced-ELL order (padding: zero values, own column)
+                const int64_t n = H.n, ns = (n + 63) / 64;
+                soff0.assign(ns + 1, 0);
+                std::vector<int32_t> swid(ns, 0);
+                for (int64_t s = 0; s < ns; ++s) {
+                    int32_t w = 0;
+                    for (int64_t i = 64 * s; i < std::min<int64_t>(n, 64 * s + 64); ++i)
+                        w = std::max(w, H.rowptr[i + 1] - H.rowptr[i]);
+                    swid[s] = w;
+                    soff0[s + 1] = soff0[s] + 64 * w;
+                }
+                L.nsell = soff0[ns];
+                std::vector<int32_t> scol(L.nsell);
+                for (int64_t i = 0; i < n; ++i) {
+                    const int64_t base = soff0[i >> 6] + (i & 63);
+                    const int32_t len = H.rowptr[i + 1] - H.rowptr[i];
+                    for (int32_t j = 0; j < swid[i >> 6]; ++j)
+                        scol[base + 64 * (int64_t)j] = j < len ? H.col[H.rowptr[i] + j] : (int32_t)i;
+                }
+                // lanes of the last slice past row n - 1 hold padding and are never read
+                CK(up(L.soff, soff0));
+                CK(up(L.swid, swid));
+                CK(up(L.scol, scol));
+                CK(vec(L.val, L.nsell));
+                LX_HIP(hipMemsetAsync(L.val, 0, sizeof(T) * L.nsell, stream));
+            } else {
+                CK(vec(L.val, L.nnz));
+            }
         }
         CK(up(L.diag, H.diag));
         CK(vec(L.x1, L.n));
@@ -529,7 +561,18 @@ lx_status Sim::setup_amg(Amg<T> &A)
                 CK(vec(L.dinv, L.n));
             }
             CK(up(L.cptr, H.cptr));
-            CK(up(L.cidx, H.cidx));
+            if (l == 0 && sell0) {
+                // coarse entries sum the finest level's entries at their sliced-ELL positions
+                std::vector<int32_t> row_of(H.col.size());
+                for (int64_t i = 0; i < H.n; ++i)
+                    for (int32_t k = H.rowptr[i]; k < H.rowptr[i + 1]; ++k) row_of[k] = (int32_t)i;
+                std::vector<int32_t> cidx(H.cidx.size());
+                for (size_t q = 0; q < H.cidx.size(); ++q)
+                    cidx[q] = (int32_t)sell_pos(soff0, H.rowptr, row_of[H.cidx[q]], H.cidx[q]);
+                CK(up(L.cidx, cidx));
+            } else {
+                CK(up(L.cidx, H.cidx));
+            }
             CK(vec(L.x0, L.n));
             CK(vec(L.res, L.n));
             CK(vec(L.d0, L.n));

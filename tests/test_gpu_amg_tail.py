@@ -1,5 +1,6 @@
-"""The one-workgroup coarse AMG cycle, against the oracle and against the same
-hierarchy cycled level by level.
+"""The one-workgroup coarse AMG cycle and the sliced-ELL finest level, against
+the oracle and against the plain layouts (every level cycled by its own
+launches; the finest level in CSR).
 
 The small parity cases have a two-level Schur hierarchy (one smoothed level
 and the dense one), where the coarse cycle does not apply.  This tube is large
@@ -36,20 +37,23 @@ def _case():
     return tube_valve(12, 60, length=6.0, seed=11)
 
 
-def _gpu(case, stream, precision, tail=True):
+def _gpu(case, stream, precision, tail=True, sell=True):
     from paper_2304_12032_amd import Sim
     rtol = 1e-14 if precision == "fp64" else 1e-13
     sv = SolverCfg(precision=precision, rtol=rtol, ir_rtol=rtol, max_iters=20000)
-    old = os.environ.get("LXNS_AMG_TAIL")
-    if not tail:
-        os.environ["LXNS_AMG_TAIL"] = "0"
+    env = {"LXNS_AMG_TAIL": tail, "LXNS_AMG_SELL": sell}
+    old = {k: os.environ.get(k) for k in env}
+    for k, on in env.items():
+        if not on:
+            os.environ[k] = "0"
     try:
         g = Sim(case.mesh, case.prob, sv, device=0, stream=stream)
     finally:
-        if old is None:
-            os.environ.pop("LXNS_AMG_TAIL", None)
-        else:
-            os.environ["LXNS_AMG_TAIL"] = old
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
     q = g.query()
     print("%s: %d vertices, AMG levels %d, coarse cycle from level %d" % (precision, case.mesh.nv, q["amg_levels"],
                                                                          q["amg_tail_level"]), flush=True)
@@ -111,5 +115,22 @@ def test_coarse_cycle_matches_level_kernels(stream):
         eu, ep = rel_l2(u1, u0), rel_l2(p1, p0)
         print("step %d: iterations %d (one workgroup) / %d (level kernels), diff u %.2e p %.2e" % (k, i1, i0, eu, ep),
               flush=True)
+        assert abs(i1 - i0) <= 2
+        assert eu < 1e-10 and ep < 1e-10, (eu, ep)
+
+
+def test_sell_matches_csr(stream):
+    """The finest level in sliced-ELL order against the same level in CSR."""
+    case = _case()
+    g1, _ = _gpu(case, stream, "fp64")
+    a = _run(g1, case, STEPS)
+    g1.close()
+    g0, _ = _gpu(case, stream, "fp64", sell=False)
+    b = _run(g0, case, STEPS)
+    g0.close()
+    for k in range(STEPS):
+        (u1, p1, i1), (u0, p0, i0) = a[k], b[k]
+        eu, ep = rel_l2(u1, u0), rel_l2(p1, p0)
+        print("step %d: iterations %d (sliced ELL) / %d (CSR), diff u %.2e p %.2e" % (k, i1, i0, eu, ep), flush=True)
         assert abs(i1 - i0) <= 2
         assert eu < 1e-10 and ep < 1e-10, (eu, ep)
