@@ -1089,15 +1089,18 @@ template lx_status amg_tail_prepare<float>(int);
 static unsigned rows_grid(int64_t n, int lpr) { return (unsigned)((n * lpr + 255) / 256); }
 static unsigned flat_grid(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-// Lanes per block row of the velocity-block passes (LXNS_LPR overrides, 4/8/16).
-static int block_lpr()
+// Lanes per block row of the velocity-block passes: 8 for the P1-P1 vertex
+// pattern (about 15 blocks a row), 16 for denser patterns such as P2-P1's
+// (about 28); LXNS_LPR (4, 8, 16 or 32) overrides.
+static int block_lpr(const RowPattern &P)
 {
-    static const int v = [] {
+    static const int env = [] {
         const char *e = getenv("LXNS_LPR");
-        const int x = e ? atoi(e) : 8;
-        return (x == 4 || x == 8 || x == 16) ? x : 8;
+        const int x = e ? atoi(e) : 0;
+        return (x == 4 || x == 8 || x == 16 || x == 32) ? x : 0;
     }();
-    return v;
+    if (env) return env;
+    return P.nblk >= 20 * P.nv ? 16 : 8;
 }
 
 #define LX_LPR_SWITCH(lpr, CALL) \
@@ -1155,7 +1158,7 @@ void launch_amg_setup(const SimpleView<T> &V, const T *Finv, const T *Dinv, Amg<
     if (A.f_degree > 1) {
         // power iterations alternate fv -> fd1 -> fv; an even count ends in fv
         const int iters = A.f_warm ? A.f_pow_iters : A.f_pow_first;
-        const int lpr = block_lpr();
+        const int lpr = block_lpr(P);
         for (int it = 0; it < iters; ++it) {
             const bool even = (it % 2) == 0;
             const T *vin = (it == 0 && !A.f_warm) ? nullptr : (even ? A.fv : A.fd1);
@@ -1259,7 +1262,7 @@ void launch_simple_amg_apply(const SimpleView<T> &V, const T *Finv, const T *Din
 {
     const RowPattern &P = V.Fp;
     const T *val = V.F;
-    const int lpr = block_lpr();
+    const int lpr = block_lpr(P);
     hipLaunchKernelGGL((k_fz_start<T>), dim3(flat_grid(P.nv)), dim3(256), 0, s, P.nv, Finv, r, scale_ptr, z, A.fr,
                        A.fd0, &A.lam[kLamF], A.f_ratio, A.f_degree, done);
     T *dc = A.fd0, *dn = A.fd1;
