@@ -64,7 +64,8 @@ inline int64_t sell_pos(const std::vector<int32_t> &soff, const std::vector<int3
 // The coarse end of the hierarchy (from level `first` down to the dense level)
 // runs as one workgroup out of LDS.  Its arrays sit in one device buffer laid
 // out exactly as the LDS image (offsets in bytes, 16-byte aligned): the dense
-// augmented matrix, then per level the values, dinv, row pointers, columns,
+// augmented matrix, the member lists of level first - 1 (for the restriction
+// onto level first; left in global memory when they would not fit), then per level the values, dinv, row pointers, columns,
 // aggregate map and member lists; the set-up kernels write values, dinv and the
 // dense inverse there, and the cycle copies the image into LDS in one pass.
 // The level vectors follow the image in LDS only.
@@ -81,6 +82,7 @@ struct TailLevelLds {
 struct TailLayout {
     int first = 0, nlev = 0, nc = 0;   // first: 0 = no one-workgroup cycle
     int32_t o_dense = 0, o_rc = 0, o_xc = 0;
+    int32_t o_fmptr = -1, o_fmem = -1; // member lists of level first - 1 in the image (-1: read globally)
     int32_t img_bytes = 0, lds_bytes = 0;
     TailLevelLds lv[kTailDepth];
 };

@@ -809,7 +809,7 @@ struct TailArgs {
     double ratio;
     int degree, cycle;
     const T *fres;                       // residual of level first - 1 (global)
-    const int32_t *fmptr, *fmem;         // its member lists (global)
+    const int32_t *fmptr, *fmem;         // its member lists (global; the image's copy when it has one)
     T *out;                              // result of level first (global)
     const int32_t *done;
 };
@@ -840,7 +840,8 @@ __device__ __forceinline__ double tail_rowdot(const int32_t *rowptr, const int32
     return lane_sum(q, lanes);
 }
 
-// level start from the global residual of the finer level: r = restriction,
+// level start from the global residual of the finer level (its member lists in
+// LDS, the residual gathered from global memory): r = restriction,
 // x0 = d0 = dinv r / theta, res = r (members gathered eight at a time per lane)
 template <typename T>
 __device__ __forceinline__ void tail_pre_global(const TailArgs<T> &A, const TailLevelLds &L, unsigned char *lds,
@@ -852,13 +853,16 @@ __device__ __forceinline__ void tail_pre_global(const TailArgs<T> &A, const Tail
     const T *dinv = lds_v<T>(lds, L.o_dinv);
     double theta, a, b;
     cheb_coef(lam, A.ratio, 0, theta, a, b);
+    const bool in_lds = A.lay.o_fmem >= 0;
+    const int32_t *fmptr = in_lds ? lds_i(lds, A.lay.o_fmptr) : A.fmptr;
+    const int32_t *fmem = in_lds ? lds_i(lds, A.lay.o_fmem) : A.fmem;
     for (int i = threadIdx.x / lanes; i < L.n; i += kTailThreads / lanes) {
-        const int32_t q0 = A.fmptr[i], q1 = A.fmptr[i + 1];
+        const int32_t q0 = fmptr[i], q1 = fmptr[i + 1];
         double s = 0;
         for (int32_t q = q0 + lane; q < q1; q += 8 * lanes) {
             int32_t idx[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) idx[u] = q + u * lanes < q1 ? A.fmem[q + u * lanes] : -1;
+            for (int u = 0; u < 8; ++u) idx[u] = q + u * lanes < q1 ? fmem[q + u * lanes] : -1;
             T v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) v[u] = idx[u] >= 0 ? A.fres[idx[u]] : T(0);
@@ -1057,16 +1061,21 @@ __global__ __launch_bounds__(kTailThreads) void k_amg_tail(TailArgs<T> A)
     const int nw = A.lay.img_bytes >> 4;
     const uint4 *src = reinterpret_cast<const uint4 *>(A.img);
     uint4 *dst = reinterpret_cast<uint4 *>(lds);
-    for (int b0 = 0; b0 < nw; b0 += 4 * kTailThreads) {
-        const int w0 = b0 + (int)threadIdx.x, w1 = w0 + kTailThreads, w2 = w1 + kTailThreads,
-                  w3 = w2 + kTailThreads;
+    for (int b0 = 0; b0 < nw; b0 += 8 * kTailThreads) {
+        const int w = b0 + (int)threadIdx.x;
         // loads at clamped (in-bounds) indices, stores only where in range
-        const uint4 v0 = src[min(w0, nw - 1)], v1 = src[min(w1, nw - 1)], v2 = src[min(w2, nw - 1)],
-                    v3 = src[min(w3, nw - 1)];
-        if (w0 < nw) dst[w0] = v0;
-        if (w1 < nw) dst[w1] = v1;
-        if (w2 < nw) dst[w2] = v2;
-        if (w3 < nw) dst[w3] = v3;
+        const uint4 v0 = src[min(w, nw - 1)], v1 = src[min(w + kTailThreads, nw - 1)],
+                    v2 = src[min(w + 2 * kTailThreads, nw - 1)], v3 = src[min(w + 3 * kTailThreads, nw - 1)],
+                    v4 = src[min(w + 4 * kTailThreads, nw - 1)], v5 = src[min(w + 5 * kTailThreads, nw - 1)],
+                    v6 = src[min(w + 6 * kTailThreads, nw - 1)], v7 = src[min(w + 7 * kTailThreads, nw - 1)];
+        if (w < nw) dst[w] = v0;
+        if (w + kTailThreads < nw) dst[w + kTailThreads] = v1;
+        if (w + 2 * kTailThreads < nw) dst[w + 2 * kTailThreads] = v2;
+        if (w + 3 * kTailThreads < nw) dst[w + 3 * kTailThreads] = v3;
+        if (w + 4 * kTailThreads < nw) dst[w + 4 * kTailThreads] = v4;
+        if (w + 5 * kTailThreads < nw) dst[w + 5 * kTailThreads] = v5;
+        if (w + 6 * kTailThreads < nw) dst[w + 6 * kTailThreads] = v6;
+        if (w + 7 * kTailThreads < nw) dst[w + 7 * kTailThreads] = v7;
     }
     __syncthreads();
     const T *x = tail_visit<T, 0>(A, lds);

@@ -177,50 +177,58 @@ TailLayout amg_tail_layout(int nlev, const int64_t *n, const int64_t *nnz, int v
         bool small = true;
         for (int m = first; m < nlev; ++m) small = small && n[m] <= kTailMaxRows;
         if (!small) continue;
-        TailLayout T;
-        T.first = first;
-        T.nlev = nlev;
-        T.nc = (int)n[nlev];
-        int64_t o = 0;
-        T.o_dense = 0;
-        o = align16(o + 8 * 2 * n[nlev] * n[nlev]);
-        for (int m = first; m < nlev; ++m) {
-            TailLevelLds &L = T.lv[m - first];
-            L.n = (int32_t)n[m];
-            L.nnz = (int32_t)nnz[m];
-            L.nn = (int32_t)n[m + 1];
-            L.lanes = 1;
-            while (L.lanes < 16 && (int64_t)L.n * L.lanes * 2 <= kTailThreads) L.lanes *= 2;
-            L.o_val = (int32_t)o;
-            o = align16(o + (int64_t)vbytes * L.nnz);
-            L.o_dinv = (int32_t)o;
-            o = align16(o + (int64_t)vbytes * L.n);
-            L.o_rowptr = (int32_t)o;
-            o = align16(o + 4 * ((int64_t)L.n + 1));
-            L.o_col = (int32_t)o;
-            o = align16(o + 4 * (int64_t)L.nnz);
-            L.o_agg = (int32_t)o;
-            o = align16(o + 4 * (int64_t)L.n);
-            L.o_mptr = (int32_t)o;
-            o = align16(o + 4 * ((int64_t)L.nn + 1));
-            L.o_mem = (int32_t)o;
-            o = align16(o + 4 * (int64_t)L.n);
-        }
-        T.img_bytes = (int32_t)o;
-        for (int m = first; m < nlev; ++m) {
-            TailLevelLds &L = T.lv[m - first];
-            int32_t *vo[6] = {&L.o_r, &L.o_res, &L.o_x0, &L.o_x1, &L.o_d0, &L.o_d1};
-            for (int v = 0; v < 6; ++v) {
-                *vo[v] = (int32_t)o;
-                o = align16(o + (int64_t)vbytes * L.n);
+        for (int lists = 1; lists >= 0; --lists) {
+            TailLayout T;
+            T.first = first;
+            T.nlev = nlev;
+            T.nc = (int)n[nlev];
+            int64_t o = 0;
+            T.o_dense = 0;
+            o = align16(o + 8 * 2 * n[nlev] * n[nlev]);
+            if (lists) {
+                T.o_fmptr = (int32_t)o;
+                o = align16(o + 4 * (n[first] + 1));
+                T.o_fmem = (int32_t)o;
+                o = align16(o + 4 * n[first - 1]);
             }
+            for (int m = first; m < nlev; ++m) {
+                TailLevelLds &L = T.lv[m - first];
+                L.n = (int32_t)n[m];
+                L.nnz = (int32_t)nnz[m];
+                L.nn = (int32_t)n[m + 1];
+                L.lanes = 1;
+                while (L.lanes < 16 && (int64_t)L.n * L.lanes * 2 <= kTailThreads) L.lanes *= 2;
+                L.o_val = (int32_t)o;
+                o = align16(o + (int64_t)vbytes * L.nnz);
+                L.o_dinv = (int32_t)o;
+                o = align16(o + (int64_t)vbytes * L.n);
+                L.o_rowptr = (int32_t)o;
+                o = align16(o + 4 * ((int64_t)L.n + 1));
+                L.o_col = (int32_t)o;
+                o = align16(o + 4 * (int64_t)L.nnz);
+                L.o_agg = (int32_t)o;
+                o = align16(o + 4 * (int64_t)L.n);
+                L.o_mptr = (int32_t)o;
+                o = align16(o + 4 * ((int64_t)L.nn + 1));
+                L.o_mem = (int32_t)o;
+                o = align16(o + 4 * (int64_t)L.n);
+            }
+            T.img_bytes = (int32_t)o;
+            for (int m = first; m < nlev; ++m) {
+                TailLevelLds &L = T.lv[m - first];
+                int32_t *vo[6] = {&L.o_r, &L.o_res, &L.o_x0, &L.o_x1, &L.o_d0, &L.o_d1};
+                for (int v = 0; v < 6; ++v) {
+                    *vo[v] = (int32_t)o;
+                    o = align16(o + (int64_t)vbytes * L.n);
+                }
+            }
+            T.o_rc = (int32_t)o;
+            o = align16(o + 8 * n[nlev]);
+            T.o_xc = (int32_t)o;
+            o = align16(o + (int64_t)vbytes * n[nlev]);
+            T.lds_bytes = (int32_t)o;
+            if (o <= max_lds) return T;
         }
-        T.o_rc = (int32_t)o;
-        o = align16(o + 8 * n[nlev]);
-        T.o_xc = (int32_t)o;
-        o = align16(o + (int64_t)vbytes * n[nlev]);
-        T.lds_bytes = (int32_t)o;
-        if (o <= max_lds) return T;
     }
     return TailLayout();
 }

@@ -586,10 +586,17 @@ lx_status Sim::setup_amg(Amg<T> &A)
     for (int64_t i = 0; i < Hc.n; ++i)
         for (int32_t k = Hc.rowptr[i]; k < Hc.rowptr[i + 1]; ++k) crow[k] = (int32_t)i;
     CK(up(A.crow, crow));
-    if (A.tail.first > 0)
+    if (A.tail.first > 0) {
         A.dense = reinterpret_cast<double *>(A.tail_img + A.tail.o_dense);
-    else
+        if (A.tail.o_fmem >= 0) {
+            const AmgLevelHost &Hf = amgh.lev[A.tail.first - 1];
+            int32_t *dm = nullptr;
+            CK(img_up(dm, A.tail.o_fmptr, Hf.mptr));
+            CK(img_up(dm, A.tail.o_fmem, Hf.mem));
+        }
+    } else {
         CK(dalloc((void **)&A.dense, sizeof(double) * 2 * A.nc * std::max<int64_t>(A.nc, 1)));
+    }
     CK(dalloc((void **)&A.lam, sizeof(double) * kLamSlots));
     CK(dalloc((void **)&A.partial, sizeof(double) * (maxgrid + 64)));
     CK(dalloc((void **)&A.counter, sizeof(uint32_t) * 4));
