@@ -120,6 +120,8 @@ void launch_norm(int64_t n, const T *x, GmState *st, double rtol, double *partia
 // vector utilities
 template <typename T>
 void launch_fill(int64_t n, T *x, T v, hipStream_t s);
+void launch_extrapolate(int64_t n, double *x, const double *h0, const double *h1, const double *h2, double g0,
+                        double g1, double g2, hipStream_t s);
 template <typename TD, typename TS>
 void launch_axpy(int64_t n, TD *y, const TS *x, const double *scale_ptr, double scale, hipStream_t s);
 // dst = (TD)(src * factor)

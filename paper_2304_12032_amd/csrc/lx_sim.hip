@@ -1081,8 +1081,18 @@ lx_status Sim::step(lx_step_stats *out)
     lx_status st = build_system(t1, C, S);
     if (st != LX_OK) return st;
     LX_HIP(hipEventRecord(ev_asm1, stream));
-    // initial guess: previous solution with the new Dirichlet values
-    LX_HIP(hipMemcpyAsync(d_xs, d_hist[0], sizeof(double) * N, hipMemcpyDeviceToDevice, stream));
+    // initial guess: the extrapolation of the history with the step's BDF
+    // weights (u_EXT, p_EXT; LXNS_X0=prev: the previous solution), with the new
+    // Dirichlet values
+    static const bool extrap = [] {
+        const char *e = getenv("LXNS_X0");
+        return !(e && strcmp(e, "prev") == 0);
+    }();
+    if (extrap)
+        launch_extrapolate(N, d_xs, d_hist[0], C.gamma[1] != 0 ? d_hist[1] : nullptr,
+                           C.gamma[2] != 0 ? d_hist[2] : nullptr, C.gamma[0], C.gamma[1], C.gamma[2], stream);
+    else
+        LX_HIP(hipMemcpyAsync(d_xs, d_hist[0], sizeof(double) * N, hipMemcpyDeviceToDevice, stream));
     launch_set_dirichlet_x(n_dir, d_dir_node, d_g, d_xs, stream);
     GmResult gr;
     if (solver.precision == LX_FP64) {
