@@ -51,7 +51,10 @@ struct AmgLevel {
     // at soff[i / 64] + 64 j + i % 64, slices as wide as their longest row, the
     // padding a zero value in the row's own column.  val and scol then hold
     // that layout (rowptr/col keep the CSR pattern); soff = null: plain CSR.
+    // Columns are stored as 16-bit offsets from the row (sdel) when every one
+    // fits, else as 32-bit indices (scol).
     int32_t *soff = nullptr, *swid = nullptr, *scol = nullptr;
+    int16_t *sdel = nullptr;
     int64_t nsell = 0;
 };
 

@@ -707,7 +707,16 @@ __global__ __launch_bounds__(256) void k_dense_solve(int nc, const double *__res
 // consecutive rows side by side, so every load of a step over j is one
 // contiguous 256-byte run; each row's sum runs over its entries in order.
 
-template <typename T>
+template <typename T, bool D16>
+__device__ __forceinline__ int32_t sell_col(const AmgLevel<T> &L, int64_t p, int64_t row)
+{
+    if constexpr (D16)
+        return (int32_t)row + (int32_t)L.sdel[p];
+    else
+        return L.scol[p];
+}
+
+template <typename T, bool D16>
 __device__ __forceinline__ double sell_row_dot(const AmgLevel<T> &L, const T *__restrict__ x, int64_t row)
 {
     const int64_t base = L.soff[row >> 6] + (row & 63);
@@ -716,7 +725,7 @@ __device__ __forceinline__ double sell_row_dot(const AmgLevel<T> &L, const T *__
 #pragma unroll 8
     for (int j = 0; j < w; ++j) {
         const int64_t p = base + 64 * (int64_t)j;
-        q += (double)L.val[p] * (double)x[L.scol[p]];
+        q += (double)L.val[p] * (double)x[sell_col<T, D16>(L, p, row)];
     }
     return q;
 }
@@ -742,7 +751,7 @@ __global__ __launch_bounds__(256) void k_amg_rowinfo_sell(AmgLevel<T> L, double 
     if (threadIdx.x == 0) partial[blockIdx.x] = m;
 }
 
-template <typename T>
+template <typename T, bool D16>
 __global__ __launch_bounds__(256) void k_amg_cheb_sell(AmgLevel<T> L, T *__restrict__ x, const T *__restrict__ dcur,
                                                        T *__restrict__ dnext, const double *lam, double ratio, int step,
                                                        const int32_t *done)
@@ -750,7 +759,7 @@ __global__ __launch_bounds__(256) void k_amg_cheb_sell(AmgLevel<T> L, T *__restr
     if (done && *done) return;
     const int64_t row = xcd_block() * blockDim.x + threadIdx.x;
     if (row >= L.n) return;
-    const double q = sell_row_dot(L, dcur, row);
+    const double q = sell_row_dot<T, D16>(L, dcur, row);
     double theta, a, b;
     cheb_coef(*lam, ratio, step, theta, a, b);
     const double r = (double)L.res[row] - q;
@@ -760,16 +769,16 @@ __global__ __launch_bounds__(256) void k_amg_cheb_sell(AmgLevel<T> L, T *__restr
     x[row] = (T)((double)x[row] + dn);
 }
 
-template <typename T>
+template <typename T, bool D16>
 __global__ __launch_bounds__(256) void k_amg_resid_sell(AmgLevel<T> L, const T *__restrict__ x, const int32_t *done)
 {
     if (done && *done) return;
     const int64_t row = xcd_block() * blockDim.x + threadIdx.x;
     if (row >= L.n) return;
-    L.res[row] = (T)((double)L.r[row] - sell_row_dot(L, x, row));
+    L.res[row] = (T)((double)L.r[row] - sell_row_dot<T, D16>(L, x, row));
 }
 
-template <typename T>
+template <typename T, bool D16>
 __global__ __launch_bounds__(256) void k_amg_post0_sell(AmgLevel<T> L, const T *__restrict__ e, const double *lam,
                                                         double ratio, const int32_t *done)
 {
@@ -782,7 +791,7 @@ __global__ __launch_bounds__(256) void k_amg_post0_sell(AmgLevel<T> L, const T *
 #pragma unroll 8
     for (int j = 0; j < w; ++j) {
         const int64_t p = base + 64 * (int64_t)j;
-        const int32_t c = L.scol[p];
+        const int32_t c = sell_col<T, D16>(L, p, row);
         q += (double)L.val[p] * ((double)L.x0[c] + (double)e[L.agg[c]]);
     }
     double theta, a, b;
@@ -1095,6 +1104,15 @@ template lx_status amg_tail_prepare<float>(int);
 
 // ================================================================== launchers
 
+// Sliced-ELL level kernels come in two forms, 16-bit column offsets or 32-bit columns.
+#define LX_SELL_LAUNCH(LV, KERNEL, GRID, ...)                                          \
+    do {                                                                             \
+        if ((LV).sdel)                                                               \
+            hipLaunchKernelGGL((KERNEL<T, true>), GRID, dim3(256), 0, s, __VA_ARGS__);  \
+        else                                                                         \
+            hipLaunchKernelGGL((KERNEL<T, false>), GRID, dim3(256), 0, s, __VA_ARGS__); \
+    } while (0)
+
 static unsigned rows_grid(int64_t n, int lpr) { return (unsigned)((n * lpr + 255) / 256); }
 static unsigned flat_grid(int64_t n) { return (unsigned)((n + 255) / 256); }
 
@@ -1226,7 +1244,7 @@ static void vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s)
     T *dc = L.d0, *dn = L.d1;
     for (int i = 1; i < A.degree; ++i) {
         if (L.soff)
-            hipLaunchKernelGGL((k_amg_cheb_sell<T>), gsell, dim3(256), 0, s, L, L.x0, dc, dn, lam, A.ratio, i, done);
+            LX_SELL_LAUNCH(L, k_amg_cheb_sell, gsell, L, L.x0, dc, dn, lam, A.ratio, i, done);
         else
             LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_cheb<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s,
                                                     L, L.x0, dc, dn, lam, A.ratio, i, done));
@@ -1237,13 +1255,13 @@ static void vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s)
     const int gamma = l > 0 ? A.cycle : 1;
     for (int c = 0; c < gamma; ++c) {
         if (L.soff)
-            hipLaunchKernelGGL((k_amg_resid_sell<T>), gsell, dim3(256), 0, s, L, L.x0, done);
+            LX_SELL_LAUNCH(L, k_amg_resid_sell, gsell, L, L.x0, done);
         else
             LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_resid<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s,
                                                     L, L.x0, done));
         vcycle(A, l + 1, done, s);
         if (L.soff)
-            hipLaunchKernelGGL((k_amg_post0_sell<T>), gsell, dim3(256), 0, s, L, A.L[l + 1].x1, lam, A.ratio, done);
+            LX_SELL_LAUNCH(L, k_amg_post0_sell, gsell, L, A.L[l + 1].x1, lam, A.ratio, done);
         else
             LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_post0<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s,
                                                     L, A.L[l + 1].x1, lam, A.ratio, done));
@@ -1251,8 +1269,7 @@ static void vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s)
         dn = L.d1;
         for (int i = 1; i < A.degree; ++i) {
             if (L.soff)
-                hipLaunchKernelGGL((k_amg_cheb_sell<T>), gsell, dim3(256), 0, s, L, L.x1, dc, dn, lam, A.ratio, i,
-                                   done);
+                LX_SELL_LAUNCH(L, k_amg_cheb_sell, gsell, L, L.x1, dc, dn, lam, A.ratio, i, done);
             else
                 LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_cheb<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0,
                                                         s, L, L.x1, dc, dn, lam, A.ratio, i, done));

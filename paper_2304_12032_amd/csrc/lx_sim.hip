@@ -530,16 +530,34 @@ lx_status Sim::setup_amg(Amg<T> &A)
                 }
                 L.nsell = soff0[ns];
                 std::vector<int32_t> scol(L.nsell);
+                bool d16 = true;
                 for (int64_t i = 0; i < n; ++i) {
                     const int64_t base = soff0[i >> 6] + (i & 63);
                     const int32_t len = H.rowptr[i + 1] - H.rowptr[i];
-                    for (int32_t j = 0; j < swid[i >> 6]; ++j)
-                        scol[base + 64 * (int64_t)j] = j < len ? H.col[H.rowptr[i] + j] : (int32_t)i;
+                    for (int32_t j = 0; j < swid[i >> 6]; ++j) {
+                        const int32_t c = j < len ? H.col[H.rowptr[i] + j] : (int32_t)i;
+                        scol[base + 64 * (int64_t)j] = c;
+                        d16 = d16 && c - i >= -32768 && c - i <= 32767;
+                    }
                 }
                 // lanes of the last slice past row n - 1 hold padding and are never read
                 CK(up(L.soff, soff0));
                 CK(up(L.swid, swid));
-                CK(up(L.scol, scol));
+                if (d16) {
+                    // every column within 32767 of its row: 16-bit offsets
+                    std::vector<int16_t> sdel(L.nsell, 0);
+                    for (int64_t i = 0; i < n; ++i) {
+                        const int64_t base = soff0[i >> 6] + (i & 63);
+                        for (int32_t j = 0; j < swid[i >> 6]; ++j)
+                            sdel[base + 64 * (int64_t)j] = (int16_t)(scol[base + 64 * (int64_t)j] - i);
+                    }
+                    CK(dalloc((void **)&L.sdel, sizeof(int16_t) * sdel.size()));
+                    LX_HIP(hipMemcpyAsync(L.sdel, sdel.data(), sizeof(int16_t) * sdel.size(), hipMemcpyHostToDevice,
+                                          stream));
+                } else {
+                    CK(up(L.scol, scol));
+                }
+                LX_HIP(hipStreamSynchronize(stream));   // swid, scol and sdel are local vectors
                 CK(vec(L.val, L.nsell));
                 LX_HIP(hipMemsetAsync(L.val, 0, sizeof(T) * L.nsell, stream));
             } else {
