@@ -49,7 +49,6 @@ struct GmState {
     double cs[kMaxRestart], sn[kMaxRestart];
     double g[kMaxRestart + 1];
     double s[kMaxRestart + 1];      // V_j = s[j] * Vhat_j
-    double h1[kMaxRestart + 1];
     double y[kMaxRestart];          // least-squares solution of the cycle
     double tol_abs;                 // stop when |g_{k+1}| <= tol_abs
     double resid;                   // current residual estimate (or true at start)

@@ -1202,106 +1202,105 @@ __global__ __launch_bounds__(256) void k_gm_dot(int64_t n, const T *V, int64_t l
     if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
 }
 
-// dot_j = sum_b partial[j][b] (fixed order, one wavefront per j); with V_j =
-// s_j Vhat_j: mode 0 h1_j = s_j dot_j = H[j][k], and the second pass is asked for
-// when the projection removed more than the share reorth_frac of ||w||^2 (row
-// k + 1 holds <w, w>; the library sets 0.9: ||w - V h1|| < ||w|| / sqrt(10), a
-// stricter form of the Daniel-Gragg-Kaufman-Stewart test, whose 1/sqrt(2) asks
-// for it at nearly every step of these solves); mode 1 (second pass)
-// h2_j = s_j dot_j, H[j][k] += h2_j, h1 <- h2.
-__global__ __launch_bounds__(256) void k_gm_fin_dot(int k, int nbx, const double *partial, GmState *st, int mode)
+// The rest of one Gram-Schmidt pass, in every block: dot_j = sum_b partial[j][b]
+// (fixed order, one wavefront per j, the same in every block), h_j = s_j dot_j
+// with V_j = s_j Vhat_j, and the block's share of Vhat_{k+1} = w - sum_j h_j V_j
+// (the second pass, second = 1, takes w = Vhat_{k+1} in place).  Block 0 also
+// keeps the books: the first pass writes H[j][k] = h_j and asks for the second
+// one when the projection removed more than the share reorth_frac of ||w||^2
+// (row k + 1 of the partials holds <w, w>; the library sets 0.9, i.e.
+// ||w - V h|| < ||w|| / sqrt(10), a stricter form of the
+// Daniel-Gragg-Kaufman-Stewart test, whose 1/sqrt(2) asks for it at nearly
+// every step of these solves); the second pass adds its h_j to H[j][k].  The
+// pass that ends the step takes ||Vhat_{k+1}||^2 = <w, w> - sum_j h_j^2 (the
+// basis is orthonormal to working precision; the test above keeps the
+// difference at least a tenth of <w, w>), and applies the Givens update of
+// column k and the convergence test.  A block that starts after block 0 has
+// ended the cycle returns at once: Vhat_{k+1} is then never read.
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_gm_axpy_fin(int64_t n, int k, int nbx, T *V, int64_t ldv, const T *w,
+                                                     GmState *st, const double *partial, int second)
 {
-    if (st->done || (mode == 1 && !st->reorth)) return;
-    __shared__ double hsq[4];
+    if (st->done || (second && !st->reorth)) return;
+    __shared__ double red[K + 1];
+    __shared__ double coef[K];
+    __shared__ double col[K + 1];
+    __shared__ double gcs[K], gsn[K];
+    __shared__ int again;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    double proj = 0;
-    for (int j = wid; j <= k; j += 4) {
+    for (int j = wid; j <= k + 1; j += 4) {
         double s = 0;
         for (int b = lane; b < nbx; b += 64) s += partial[(int64_t)j * nbx + b];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0) {
-            const double h = s * st->s[j];
-            if (mode == 0) {
-                st->h1[j] = h;
-                st->H[j * kMaxRestart + k] = h;
-                proj += h * h;
-            } else {
-                st->H[j * kMaxRestart + k] += h;
-                st->h1[j] = h;
-            }
-        }
+        if (lane == 0) red[j] = s;
     }
-    if (mode != 0) return;
-    double ww = 0;
-    if (wid == 0) {
-        for (int b = lane; b < nbx; b += 64) ww += partial[(int64_t)(k + 1) * nbx + b];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) ww += __shfl_xor(ww, off);
-    }
-    if (lane == 0) hsq[wid] = proj;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const double p = hsq[0] + hsq[1] + hsq[2] + hsq[3];
-        const int again = (p <= st->reorth_frac * ww) ? 0 : 1;   // also taken on a non-finite value
-        st->reorth = again;
-        st->n_reorth += again;
+    if (threadIdx.x < K) {
+        const int j = threadIdx.x;
+        const double sj = j <= k ? st->s[j] : 0.0;
+        const double h = j <= k ? red[j] * sj : 0.0;
+        coef[j] = h * sj;
+        red[j] = j <= k ? h : red[j];   // rows 0..k now hold h_j; row k + 1 keeps <w, w>
     }
-}
-
-// Vhat_{k+1} = w - sum_j h1_j V_j; partial[block] = sum Vhat_{k+1}^2.  The second
-// pass (second = 1, skipped unless asked for) takes w = Vhat_{k+1} in place.
-template <typename T, int K>
-__global__ __launch_bounds__(256) void k_gm_axpy_norm(int64_t n, int k, T *V, int64_t ldv, const T *w,
-                                                      const GmState *st, double *partial, int second)
-{
-    if (st->done || (second && !st->reorth)) return;
-    __shared__ double coef[K];
-    __shared__ double lds[4];
-    if (threadIdx.x < K) coef[threadIdx.x] = (threadIdx.x <= (unsigned)k) ? st->h1[threadIdx.x] * st->s[threadIdx.x] : 0.0;
     __syncthreads();
     T *Vn = V + (int64_t)(k + 1) * ldv;
-    double acc = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double wi = to_d(w[i]);
 #pragma unroll
         for (int j = 0; j < K; ++j)
             if (j <= k) wi -= coef[j] * to_d(V[j * ldv + i]);
-        const T wt = (T)wi;
-        Vn[i] = wt;
-        acc += to_d(wt) * to_d(wt);
+        Vn[i] = (T)wi;
     }
-    const double t = block_total(acc, lds);
-    if (threadIdx.x == 0) partial[blockIdx.x] = t;
-}
-
-// H[k+1][k] = ||Vhat_{k+1}||, Givens update of column k, convergence test.
-__global__ __launch_bounds__(256) void k_gm_givens(int k, int nb, const double *partial, GmState *st)
-{
-    if (st->done) return;
-    __shared__ double lds[4];
-    const double tot = sum_partials(partial, nb, lds);
-    if (threadIdx.x != 0) return;
+    if (blockIdx.x != 0) return;
+    // ---- block 0: Hessenberg column k, second-pass decision, Givens update
     const int M = kMaxRestart;
     double *H = st->H;
-    const double hn = sqrt(tot);
-    H[(k + 1) * M + k] = hn;
-    for (int j = 0; j < k; ++j) {
-        const double t = st->cs[j] * H[j * M + k] + st->sn[j] * H[(j + 1) * M + k];
-        H[(j + 1) * M + k] = -st->sn[j] * H[j * M + k] + st->cs[j] * H[(j + 1) * M + k];
-        H[j * M + k] = t;
+    if (threadIdx.x <= (unsigned)k) {
+        const int j = threadIdx.x;
+        const double hj = second ? H[j * M + k] + red[j] : red[j];
+        H[j * M + k] = hj;
+        col[j] = hj;
+        if (j < k) {
+            gcs[j] = st->cs[j];
+            gsn[j] = st->sn[j];
+        }
     }
-    const double a = H[k * M + k];
+    if (threadIdx.x == 0) {
+        double p = 0;
+        for (int j = 0; j <= k; ++j) p += red[j] * red[j];
+        const double ww = red[k + 1];
+        int a = 0;
+        if (!second) {
+            a = (p <= st->reorth_frac * ww) ? 0 : 1;   // also taken on a non-finite value
+            st->reorth = a;
+            st->n_reorth += a;
+        }
+        const double d = ww - p;
+        col[k + 1] = d > 0 ? sqrt(d) : 0.0;
+        again = a;
+    }
+    __syncthreads();
+    if (again || threadIdx.x != 0) return;
+    const double hn = col[k + 1];
+    for (int j = 0; j < k; ++j) {
+        const double t = gcs[j] * col[j] + gsn[j] * col[j + 1];
+        col[j + 1] = -gsn[j] * col[j] + gcs[j] * col[j + 1];
+        col[j] = t;
+    }
+    const double a = col[k];
     const double r = hypot(a, hn);
     const double c = (r > 0) ? a / r : 1.0, sn = (r > 0) ? hn / r : 0.0;
-    st->cs[k] = c;
-    st->sn[k] = sn;
+    for (int j = 0; j < k; ++j) H[j * M + k] = col[j];
     H[k * M + k] = r;
     H[(k + 1) * M + k] = 0.0;
-    st->g[k + 1] = -sn * st->g[k];
-    st->g[k] = c * st->g[k];
+    st->cs[k] = c;
+    st->sn[k] = sn;
+    const double gk = st->g[k];
+    st->g[k + 1] = -sn * gk;
+    st->g[k] = c * gk;
     st->s[k + 1] = hn > 0 ? 1.0 / hn : 0.0;
-    const double res = fabs(st->g[k + 1]);
+    const double res = fabs(sn * gk);
     st->resid = res;
     st->kused = k + 1;
     const bool bad = !(res == res) || !(r > 0);
@@ -1333,15 +1332,12 @@ void launch_gm_orth(int64_t n, int k, T *V, int64_t ldv, T *w, GmState *st, doub
 {
     const int nbx = (int)((n + kDotChunk - 1) / kDotChunk);
     const unsigned nbv = vec_blocks(n);
-    const dim3 gd1(nbx, k + 2), gd2(nbx, k + 1), gv(nbv);
+    const dim3 gd(nbx, k + 2), gv(nbv);
     T *vn = V + (int64_t)(k + 1) * ldv;
-    hipLaunchKernelGGL((k_gm_dot<T>), gd1, dim3(256), 0, s, n, V, ldv, w, partial, st, k + 1, 0);
-    hipLaunchKernelGGL(k_gm_fin_dot, dim3(1), dim3(256), 0, s, k, nbx, partial, st, 0);
-    LX_GM_K_DISPATCH(k_gm_axpy_norm, T, gv, n, k, V, ldv, w, st, partial, 0);
-    hipLaunchKernelGGL((k_gm_dot<T>), gd2, dim3(256), 0, s, n, V, ldv, vn, partial, st, k + 1, 1);
-    hipLaunchKernelGGL(k_gm_fin_dot, dim3(1), dim3(256), 0, s, k, nbx, partial, st, 1);
-    LX_GM_K_DISPATCH(k_gm_axpy_norm, T, gv, n, k, V, ldv, vn, st, partial, 1);
-    hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(256), 0, s, k, (int)nbv, partial, st);
+    hipLaunchKernelGGL((k_gm_dot<T>), gd, dim3(256), 0, s, n, V, ldv, w, partial, st, k + 1, 0);
+    LX_GM_K_DISPATCH(k_gm_axpy_fin, T, gv, n, k, nbx, V, ldv, w, st, partial, 0);
+    hipLaunchKernelGGL((k_gm_dot<T>), gd, dim3(256), 0, s, n, V, ldv, vn, partial, st, k + 1, 1);
+    LX_GM_K_DISPATCH(k_gm_axpy_fin, T, gv, n, k, nbx, V, ldv, vn, st, partial, 1);
 }
 template void launch_gm_orth<double>(int64_t, int, double *, int64_t, double *, GmState *, double *, hipStream_t);
 template void launch_gm_orth<float>(int64_t, int, float *, int64_t, float *, GmState *, double *, hipStream_t);
