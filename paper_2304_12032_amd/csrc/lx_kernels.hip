@@ -425,10 +425,12 @@ template void launch_assemble_p1<float>(const AsmArgs<float> &, const StepCoef &
 
 // r = b - A xs on every row except Dirichlet velocity rows, evaluated element
 // by element at the quadrature points from the strong residual of the iterate
-// (no matrix is formed).  Optionally also b and the FP64 diagonal of the
-// Dirichlet velocity rows.  The element pass writes each element's vertex
+// (no matrix is formed).  FULL: also b and the FP64 diagonal of the Dirichlet
+// velocity rows (a separate instance, so the plain residual keeps fewer
+// registers live).  The element pass writes each element's vertex
 // contributions to a record; k_residual_gather sums them per vertex in the
 // fixed order of the vertex's incidence list.
+template <bool FULL>
 __global__ __launch_bounds__(256) void k_residual_p1(ResArgs A, StepCoef C)
 {
     const int64_t e = xcd_block() * blockDim.x + threadIdx.x;
@@ -497,15 +499,15 @@ __global__ __launch_bounds__(256) void k_residual_p1(ResArgs A, StepCoef C)
                     gal -= mu * (gX[0][c] * E.dphi[a][0] + gX[1][c] * E.dphi[a][1] + gX[2][c] * E.dphi[a][2]);
                 double st = -Q.tauM * (rho * ad * rM[c] + Q.dv[c] * rMd) - Q.tauC * divX * E.dphi[a][c];
                 ru[a][c] += w * (gal + st);
-                if (A.b) bu[a][c] += w * (Q.Kv[c] * la + Q.tauM * (rho * ad * Q.Kv[c] + Q.dv[c] * Kd));
-                if (A.dg && dir[a] >= 0) {
+                if (FULL) bu[a][c] += w * (Q.Kv[c] * la + Q.tauM * (rho * ad * Q.Kv[c] + Q.dv[c] * Kd));
+                if (FULL && dir[a] >= 0) {
                     const double dca = E.dphi[a][c];
                     dg[a][c] += w * (Q.Aq * la * la + rho * la * ad +
                                      Q.tauM * Q.s[a] * (rho * ad + Q.dv[c] * dca) + Q.tauC * dca * dca);
                 }
             }
             rp[a] += w * (-la * divX - Q.tauM * rMd);
-            if (A.b) bp[a] += w * Q.tauM * Kd;
+            if (FULL) bp[a] += w * Q.tauM * Kd;
         }
     }
     const double mv = mu * E.vol;
@@ -517,12 +519,12 @@ __global__ __launch_bounds__(256) void k_residual_p1(ResArgs A, StepCoef C)
 #pragma unroll
         for (int c = 0; c < 3; ++c) R[c] = free_u ? ru[a][c] : 0.0;
         R[3] = rp[a];
-        if (A.b) {
+        if (FULL) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) R[4 * n4 + c] = free_u ? bu[a][c] : 0.0;
             R[4 * n4 + 3] = bp[a];
         }
-        if (A.dg) {
+        if (FULL) {
             const double gaa = E.dphi[a][0] * E.dphi[a][0] + E.dphi[a][1] * E.dphi[a][1] + E.dphi[a][2] * E.dphi[a][2];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -572,7 +574,11 @@ __global__ __launch_bounds__(256) void k_residual_gather(ResArgs A)
 
 void launch_residual_p1(const ResArgs &a, const StepCoef &c, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_residual_p1, dim3((unsigned)((a.nt + 255) / 256)), dim3(256), 0, s, a, c);
+    const dim3 g((unsigned)((a.nt + 255) / 256));
+    if (a.b)
+        hipLaunchKernelGGL(k_residual_p1<true>, g, dim3(256), 0, s, a, c);
+    else
+        hipLaunchKernelGGL(k_residual_p1<false>, g, dim3(256), 0, s, a, c);
     hipLaunchKernelGGL(k_residual_gather, dim3((unsigned)((a.nv + 255) / 256)), dim3(256), 0, s, a);
 }
 

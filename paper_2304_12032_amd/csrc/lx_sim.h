@@ -114,6 +114,13 @@ struct Sim {
     std::vector<std::pair<int, int>> ev_tag;
     size_t ev_used = 0;
     hipEvent_t ev_step0 = nullptr, ev_step1 = nullptr, ev_asm1 = nullptr;
+    // convergence checks inside an Arnoldi cycle: the done flag copied to pinned
+    // host memory behind an event, one check in flight (ping-pong slots)
+    int32_t *h_flag = nullptr;
+    hipEvent_t ev_chk[2] = {nullptr, nullptr};
+    // columns used by cycle c of the last solve of each kind (0: unknown), where
+    // the next solve of that kind starts checking every step
+    int32_t k_hint[8][8] = {};
 
     double t = 0;
     int nlev = 0;
@@ -138,7 +145,7 @@ struct Sim {
     void spmv(const T *x, T *y, const int32_t *done, std::pair<hipEvent_t, hipEvent_t> *tm);
     template <typename T>
     lx_status gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, GmResult &res,
-                    lx_step_stats &tstats, bool inner = false);
+                    lx_step_stats &tstats, bool inner = false, int kind = 0);
     void coefficients(double t1, StepCoef &C, BCSet &B) const;
     lx_status prepare(double t1, StepCoef &C);
     lx_status build_system(double t1, StepCoef &C, lx_step_stats &tstats);

@@ -59,6 +59,9 @@ Sim::~Sim()
     if (stream) (void)hipStreamSynchronize(stream);
     for (void *p : allocs) (void)hipFree(p);
     if (h_st) (void)hipHostFree(h_st);
+    if (h_flag) (void)hipHostFree(h_flag);
+    for (auto &ev : ev_chk)
+        if (ev) (void)hipEventDestroy(ev);
     for (auto &ev : ev_pool) {
         (void)hipEventDestroy(ev.first);
         (void)hipEventDestroy(ev.second);
@@ -291,6 +294,8 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     ALLOC(d_st, sizeof(GmState));
     ALLOC(d_partial, sizeof(double) * std::max<int64_t>((int64_t)nb_red * 64, gm_partial_size(N)));
     LX_HIP(hipHostMalloc((void **)&h_st, sizeof(GmState), hipHostMallocDefault));
+    LX_HIP(hipHostMalloc((void **)&h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
+    for (auto &ev : ev_chk) LX_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     if (p2) {
         // FP64 split system in both precisions (the refinement residual uses it)
         ALLOC(s64.F, sizeof(double) * 9 * s64.nf);
@@ -793,7 +798,7 @@ static bool verbose()
 // the correction, so the true residual is not re-verified in low precision.
 template <typename T>
 lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, GmResult &res,
-                     lx_step_stats &tstats, bool inner)
+                     lx_step_stats &tstats, bool inner, int kind)
 {
     const RowPattern P = pattern();
     const T *val = Ops<T>::val(this);
@@ -815,16 +820,16 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
             launch_gm_start<T>(N, b, w, V, d_st, d_partial, stream);
         }
         const int kmax = std::min(m, max_iters - it);
-        // Arnoldi steps are queued in chunks; between chunks the host reads the
-        // device's done flag, so a cycle that converges early leaves at most one
-        // chunk of no-op launches behind instead of the rest of the cycle.
-        const int chunk = 10;
+        // The host learns of convergence from the done flag, copied to pinned
+        // memory behind an event after chosen Arnoldi steps and read one step
+        // later, while the next step is already queued: the device never waits
+        // for the host, and a converged cycle leaves one step of early-exit
+        // launches behind.  Steps are checked from two before the column count
+        // of the same cycle in the last solve of this kind, every step if that
+        // is unknown, and every eighth step in any case.
+        const int kp = (kind >= 0 && kind < 8 && cycle < 8) ? k_hint[kind][cycle] : 0;
+        int pending = -1;
         for (int k = 0; k < kmax; ++k) {
-            if (k > 0 && k % chunk == 0) {
-                LX_HIP(hipMemcpyAsync(&h_st->done, &d_st->done, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-                LX_HIP(hipStreamSynchronize(stream));
-                if (h_st->done) break;
-            }
             T *zk = Z + k * ld;
             if (solver.precond == LX_PC_AMG)
                 launch_simple_amg_apply<T>(view<T>(), SP.Finv, SP.Dinv, Ops<T>::amg(this), V + k * ld, &d_st->s[k],
@@ -834,11 +839,24 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
             auto *tm = timer_begin(0, k, false);
             spmv<T>(zk, w, &d_st->done, tm);
             launch_gm_orth<T>(N, k, V, ld, w, d_st, d_partial, stream);
+            if (pending >= 0) {
+                LX_HIP(hipEventSynchronize(ev_chk[pending & 1]));
+                const bool stop = h_flag[pending & 1] != 0;
+                pending = -1;
+                if (stop) break;
+            }
+            const bool check = kp > 0 ? (k + 2 >= kp || (k + 1) % 8 == 0) : true;
+            if (check && k + 1 < kmax) {
+                LX_HIP(hipMemcpyAsync(&h_flag[k & 1], &d_st->done, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+                LX_HIP(hipEventRecord(ev_chk[k & 1], stream));
+                pending = k;
+            }
         }
         LX_HIP(hipGetLastError());
         lx_status s = read_state();
         if (s != LX_OK) return s;
         timer_flush(h_st->kused, tstats);
+        if (kind >= 0 && kind < 8 && cycle < 8) k_hint[kind][cycle] = h_st->kused;
         res.bnorm = h_st->norms[0];
         if (h_st->kused == 0) {
             // the cycle start found the true residual below tolerance (or broke down)
@@ -887,9 +905,9 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
     }
 }
 template lx_status Sim::gmres<double>(const double *, double *, bool, double, int, GmResult &, lx_step_stats &,
-                                      bool);
+                                      bool, int);
 template lx_status Sim::gmres<float>(const float *, float *, bool, double, int, GmResult &, lx_step_stats &,
-                                     bool);
+                                     bool, int);
 
 // ------------------------------------------------------------------ step
 
@@ -1071,11 +1089,8 @@ lx_status Sim::residual64(const StepCoef &C, const double *xs, bool first, doubl
         LX_HIP(hipGetLastError());
         return LX_OK;
     }
-    launch_fill<double>(N, d_r64, 0.0, stream);
-    if (first) {
-        launch_fill<double>(N, d_b64, 0.0, stream);
-        if (n_dir > 0) launch_fill<double>(3 * n_dir, d_dg, 0.0, stream);
-    }
+    // the vertex pass writes every row of r (and of b); Dirichlet diagonals are summed into dg
+    if (first && n_dir > 0) launch_fill<double>(3 * n_dir, d_dg, 0.0, stream);
     ResArgs R{nt, nv, d_tet, d_vinc_ptr, d_vpos, d_rrec, d_x, d_xh, hist(0), hist(1), hist(2), d_uA, d_f,
               xs, d_dir_index, d_r64, first ? d_b64 : nullptr, first ? d_dg : nullptr};
     auto *tm = timer_begin(2, 0);
@@ -1138,7 +1153,7 @@ lx_status Sim::step(lx_step_stats *out)
             double rin = std::max(solver.inner_rtol, std::min(want, 0.5));
             launch_scale_copy<float, double>(N, d_r32, d_r64, 1.0 / rnorm, stream);
             GmResult g32;
-            st = gmres<float>(d_r32, d_x32, true, rin, solver.max_iters - total, g32, S, true);
+            st = gmres<float>(d_r32, d_x32, true, rin, solver.max_iters - total, g32, S, true, std::min(ir + 1, 7));
             if (st != LX_OK) return st;
             total += g32.iters;
             S.restarts += g32.restarts;
