@@ -177,7 +177,10 @@ typedef struct {
     int32_t deterministic;   /* reserved: the assembly gathers element records in
                                 a fixed order (no atomics) and every reduction
                                 has a fixed order already                          */
-    int32_t collect_timing;  /* 1: record per-kernel HIP events (SpMV, assembly)   */
+    int32_t collect_timing;  /* n >= 1: HIP events stamped by every n-th SpMV
+                                launch inside an Arnoldi cycle, by every
+                                cycle-start SpMV and around every assembly and
+                                FP64 residual pass; 0: none                      */
     int32_t schur_degree;    /* 0..32                                               */
     int32_t asm_fp64;        /* LX_FP32_IR only: 1 = build the FP32 matrix by FP64
                                 element arithmetic and scatter, rounded to FP32;
@@ -222,9 +225,9 @@ typedef struct {
     double t_step_ms;         /* wall time of the step on the stream (HIP events)     */
     double t_assembly_ms;     /* assembly + scatter + Dirichlet + SIMPLE setup        */
     double t_solve_ms;
-    double spmv_ms;           /* summed SpMV kernel time (collect_timing = 1)         */
+    double spmv_ms;           /* summed time of the timed SpMV launches (collect_timing) */
     int64_t spmv_calls;
-    double asm_ms;            /* assembly-kernel time (collect_timing = 1)            */
+    double asm_ms;            /* assembly-kernel time (collect_timing >= 1)           */
     int64_t asm_calls;
     double resid_ms;          /* FP64 matrix-free residual kernel time                */
     int64_t resid_calls;

@@ -86,7 +86,7 @@ class SolverCfg:
     ir_rtol: float = 1e-8
     inner_rtol: float = 1e-4
     deterministic: bool = True
-    collect_timing: bool = False
+    collect_timing: int = 0          # n >= 1: time every n-th in-cycle SpMV launch (and every assembly pass)
     schur_degree: int = 16           # precond = "cheb_schur" only
     schur_ratio: float = 300.0
     asm_fp64: bool = False

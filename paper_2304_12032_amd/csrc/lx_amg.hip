@@ -703,9 +703,9 @@ __global__ __launch_bounds__(256) void k_dense_solve(int nc, const double *__res
     }
 }
 
-// ---- the finest level in sliced-ELL order: one lane per row, the entries of 64
-// consecutive rows side by side, so every load of a step over j is one
-// contiguous 256-byte run; each row's sum runs over its entries in order.
+// ---- the finest level in sliced-ELL order: the entries of 64 consecutive rows
+// side by side (entry j of the slice's rows is one contiguous run), so a
+// wavefront's load of entry j over its 64 rows is one coalesced access.
 
 template <typename T, bool D16>
 __device__ __forceinline__ int32_t sell_col(const AmgLevel<T> &L, int64_t p, int64_t row)
@@ -714,20 +714,6 @@ __device__ __forceinline__ int32_t sell_col(const AmgLevel<T> &L, int64_t p, int
         return (int32_t)row + (int32_t)L.sdel[p];
     else
         return L.scol[p];
-}
-
-template <typename T, bool D16>
-__device__ __forceinline__ double sell_row_dot(const AmgLevel<T> &L, const T *__restrict__ x, int64_t row)
-{
-    const int64_t base = L.soff[row >> 6] + (row & 63);
-    const int w = L.swid[row >> 6];
-    double q = 0;
-#pragma unroll 8
-    for (int j = 0; j < w; ++j) {
-        const int64_t p = base + 64 * (int64_t)j;
-        q += (double)L.val[p] * (double)x[sell_col<T, D16>(L, p, row)];
-    }
-    return q;
 }
 
 template <typename T>
@@ -751,15 +737,47 @@ __global__ __launch_bounds__(256) void k_amg_rowinfo_sell(AmgLevel<T> L, double 
     if (threadIdx.x == 0) partial[blockIdx.x] = m;
 }
 
-template <typename T, bool D16>
-__global__ __launch_bounds__(256) void k_amg_cheb_sell(AmgLevel<T> L, T *__restrict__ x, const T *__restrict__ dcur,
-                                                       T *__restrict__ dnext, const double *lam, double ratio, int step,
-                                                       const int32_t *done)
+// The smoothing passes run SW = kSellWaves wavefronts per slice of 64 rows (one
+// workgroup per slice): wavefront v takes the entries j = v, v + SW, ... of
+// every row, and wavefront 0 adds the SW partial sums in order and finishes the
+// row, so that several loads per row are in flight at once.
+constexpr int kSellWaves = 4;
+
+template <typename T, bool D16, int SW, typename X>
+__device__ __forceinline__ double sell_slice_dot(const AmgLevel<T> &L, int64_t slice, X xval, double (*part)[64])
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t row = slice * 64 + lane;
+    double q = 0;
+    if (row < L.n) {
+        const int64_t base = L.soff[slice] + lane;
+        const int w = L.swid[slice];
+#pragma unroll 4
+        for (int j = wv; j < w; j += SW) {
+            const int64_t p = base + 64 * (int64_t)j;
+            q += (double)L.val[p] * xval(sell_col<T, D16>(L, p, row));
+        }
+    }
+    part[wv][lane] = q;
+    __syncthreads();
+    double t = part[0][lane];
+#pragma unroll
+    for (int v = 1; v < SW; ++v) t += part[v][lane];
+    return t;
+}
+
+template <typename T, bool D16, int SW>
+__global__ __launch_bounds__(64 * SW) void k_amg_cheb_sell(AmgLevel<T> L, T *__restrict__ x,
+                                                            const T *__restrict__ dcur, T *__restrict__ dnext,
+                                                            const double *lam, double ratio, int step,
+                                                            const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = xcd_block() * blockDim.x + threadIdx.x;
-    if (row >= L.n) return;
-    const double q = sell_row_dot<T, D16>(L, dcur, row);
+    __shared__ double part[SW][64];
+    const int64_t slice = xcd_block();
+    const double q = sell_slice_dot<T, D16, SW>(L, slice, [&](int32_t c) { return (double)dcur[c]; }, part);
+    const int64_t row = slice * 64 + (threadIdx.x & 63);
+    if (threadIdx.x >= 64 || row >= L.n) return;
     double theta, a, b;
     cheb_coef(*lam, ratio, step, theta, a, b);
     const double r = (double)L.res[row] - q;
@@ -769,31 +787,32 @@ __global__ __launch_bounds__(256) void k_amg_cheb_sell(AmgLevel<T> L, T *__restr
     x[row] = (T)((double)x[row] + dn);
 }
 
-template <typename T, bool D16>
-__global__ __launch_bounds__(256) void k_amg_resid_sell(AmgLevel<T> L, const T *__restrict__ x, const int32_t *done)
+template <typename T, bool D16, int SW>
+__global__ __launch_bounds__(64 * SW) void k_amg_resid_sell(AmgLevel<T> L, const T *__restrict__ x,
+                                                             const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = xcd_block() * blockDim.x + threadIdx.x;
-    if (row >= L.n) return;
-    L.res[row] = (T)((double)L.r[row] - sell_row_dot<T, D16>(L, x, row));
+    __shared__ double part[SW][64];
+    const int64_t slice = xcd_block();
+    const double q = sell_slice_dot<T, D16, SW>(L, slice, [&](int32_t c) { return (double)x[c]; }, part);
+    const int64_t row = slice * 64 + (threadIdx.x & 63);
+    if (threadIdx.x >= 64 || row >= L.n) return;
+    L.res[row] = (T)((double)L.r[row] - q);
 }
 
-template <typename T, bool D16>
-__global__ __launch_bounds__(256) void k_amg_post0_sell(AmgLevel<T> L, const T *__restrict__ e, const double *lam,
-                                                        double ratio, const int32_t *done)
+template <typename T, bool D16, int SW>
+__global__ __launch_bounds__(64 * SW) void k_amg_post0_sell(AmgLevel<T> L, const T *__restrict__ e,
+                                                             const double *lam, double ratio, const int32_t *done)
 {
     if (done && *done) return;
-    const int64_t row = xcd_block() * blockDim.x + threadIdx.x;
-    if (row >= L.n) return;
-    const int64_t base = L.soff[row >> 6] + (row & 63);
-    const int w = L.swid[row >> 6];
-    double q = 0;
-#pragma unroll 8
-    for (int j = 0; j < w; ++j) {
-        const int64_t p = base + 64 * (int64_t)j;
-        const int32_t c = sell_col<T, D16>(L, p, row);
-        q += (double)L.val[p] * ((double)L.x0[c] + (double)e[L.agg[c]]);
-    }
+    __shared__ double part[SW][64];
+    const int64_t slice = xcd_block();
+    const T *x0 = L.x0;
+    const int32_t *agg = L.agg;
+    const double q = sell_slice_dot<T, D16, SW>(
+        L, slice, [&](int32_t c) { return (double)x0[c] + (double)e[agg[c]]; }, part);
+    const int64_t row = slice * 64 + (threadIdx.x & 63);
+    if (threadIdx.x >= 64 || row >= L.n) return;
     double theta, a, b;
     cheb_coef(*lam, ratio, 0, theta, a, b);
     const double r = (double)L.r[row] - q;
@@ -1104,13 +1123,13 @@ template lx_status amg_tail_prepare<float>(int);
 
 // ================================================================== launchers
 
-// Sliced-ELL level kernels come in two forms, 16-bit column offsets or 32-bit columns.
-#define LX_SELL_LAUNCH(LV, KERNEL, GRID, ...)                                          \
-    do {                                                                             \
-        if ((LV).sdel)                                                               \
-            hipLaunchKernelGGL((KERNEL<T, true>), GRID, dim3(256), 0, s, __VA_ARGS__);  \
-        else                                                                         \
-            hipLaunchKernelGGL((KERNEL<T, false>), GRID, dim3(256), 0, s, __VA_ARGS__); \
+// Sliced-ELL passes come in two forms, 16-bit column offsets or 32-bit columns; one workgroup per slice.
+#define LX_SELL_LAUNCH(LV, KERNEL, GRID, ...)                                                                   \
+    do {                                                                                                      \
+        if ((LV).sdel)                                                                                        \
+            hipLaunchKernelGGL((KERNEL<T, true, kSellWaves>), GRID, dim3(64 * kSellWaves), 0, s, __VA_ARGS__);  \
+        else                                                                                                  \
+            hipLaunchKernelGGL((KERNEL<T, false, kSellWaves>), GRID, dim3(64 * kSellWaves), 0, s, __VA_ARGS__); \
     } while (0)
 
 static unsigned rows_grid(int64_t n, int lpr) { return (unsigned)((n * lpr + 255) / 256); }
@@ -1240,7 +1259,7 @@ static void vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s)
         hipLaunchKernelGGL((k_amg_pre<T, 16>), dim3(rows_grid(L.n, 16)), dim3(256), 0, s, L, F.res, F.mptr, F.mem,
                            lam, A.ratio, done);
     }
-    const dim3 gsell(flat_grid(L.n));
+    const dim3 gsell((unsigned)((L.n + 63) / 64));
     T *dc = L.d0, *dn = L.d1;
     for (int i = 1; i < A.degree; ++i) {
         if (L.soff)

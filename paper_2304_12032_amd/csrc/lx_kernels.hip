@@ -1348,18 +1348,25 @@ void launch_gm_orth(int64_t n, int k, T *V, int64_t ldv, T *w, GmState *st, doub
 template void launch_gm_orth<double>(int64_t, int, double *, int64_t, double *, GmState *, double *, hipStream_t);
 template void launch_gm_orth<float>(int64_t, int, float *, int64_t, float *, GmState *, double *, hipStream_t);
 
-// y = H^{-1} g over the kused columns (back substitution).
-__global__ void k_gm_solve_y(GmState *st)
+// y = H^{-1} g over the kused columns: back substitution by one wavefront, the
+// triangle staged in LDS; lane j keeps g_j minus the terms of the y found so
+// far and holds y_j once its turn has come.
+__global__ __launch_bounds__(64) void k_gm_solve_y(GmState *st)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int M = kMaxRestart, k = st->kused;
-    double y[kMaxRestart];
-    for (int i = k - 1; i >= 0; --i) {
-        double s = st->g[i];
-        for (int j = i + 1; j < k; ++j) s -= st->H[i * M + j] * y[j];
-        y[i] = s / st->H[i * M + i];
+    __shared__ double Hs[kMaxRestart][kMaxRestart + 1];
+    const int M = kMaxRestart, k = st->kused, lane = threadIdx.x;
+    for (int idx = lane; idx < k * k; idx += 64) {
+        const int i = idx / k, j = idx - i * k;
+        Hs[i][j] = st->H[i * M + j];
     }
-    for (int j = 0; j < k; ++j) st->y[j] = y[j];
+    double gl = lane < k ? st->g[lane] : 0.0;
+    __syncthreads();
+    for (int i = k - 1; i >= 0; --i) {
+        const double yi = __shfl(gl, i) / Hs[i][i];
+        if (lane < i) gl -= Hs[lane][i] * yi;
+        if (lane == i) gl = yi;
+    }
+    if (lane < k) st->y[lane] = gl;
 }
 
 void launch_gm_solve_y(GmState *st, hipStream_t s)

@@ -113,6 +113,7 @@ struct Sim {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
     std::vector<std::pair<int, int>> ev_tag;
     size_t ev_used = 0;
+    int64_t spmv_seq = 0;   // in-cycle SpMV launches so far (every collect_timing-th one is timed)
     hipEvent_t ev_step0 = nullptr, ev_step1 = nullptr, ev_asm1 = nullptr;
     // convergence checks inside an Arnoldi cycle: the done flag copied to pinned
     // host memory behind an event, one check in flight (ping-pong slots)

@@ -654,7 +654,8 @@ lx_status Sim::setup_amg(Amg<T> &A)
 // to hipExtLaunchKernelGGL, which stamps the kernel's own start and end.
 std::pair<hipEvent_t, hipEvent_t> *Sim::timer_begin(int kind, int iter, bool record)
 {
-    if (!solver.collect_timing) return nullptr;
+    if (solver.collect_timing <= 0) return nullptr;
+    if (kind == 0 && iter >= 0 && (spmv_seq++ % solver.collect_timing) != 0) return nullptr;
     if (ev_used >= ev_pool.size()) {
         hipEvent_t a, b;
         if (hipEventCreate(&a) != hipSuccess) return nullptr;

@@ -243,7 +243,7 @@ class _Marshal:
         s.max_ir = solver.max_ir
         s.rtol, s.ir_rtol, s.inner_rtol = solver.rtol, solver.ir_rtol, solver.inner_rtol
         s.deterministic = int(bool(getattr(solver, "deterministic", True)))
-        s.collect_timing = int(bool(getattr(solver, "collect_timing", False)))
+        s.collect_timing = max(0, int(getattr(solver, "collect_timing", 0)))
         s.schur_degree = int(getattr(solver, "schur_degree", 8))
         s.schur_ratio = float(getattr(solver, "schur_ratio", 100.0))
         s.asm_fp64 = int(bool(getattr(solver, "asm_fp64", False)))
