@@ -524,13 +524,13 @@ __global__ __launch_bounds__(256) void k_residual_p1(ResArgs A, StepCoef C)
             for (int c = 0; c < 3; ++c) R[4 * n4 + c] = free_u ? bu[a][c] : 0.0;
             R[4 * n4 + 3] = bp[a];
         }
-        if (FULL) {
+        if (FULL && !free_u) {   // read back for Dirichlet vertices only
             const double gaa = E.dphi[a][0] * E.dphi[a][0] + E.dphi[a][1] * E.dphi[a][1] + E.dphi[a][2] * E.dphi[a][2];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 double d = dg[a][c] + mv * gaa;
                 if (C.symgrad) d += mv * E.dphi[a][c] * E.dphi[a][c];
-                R[8 * n4 + c] = free_u ? 0.0 : d;
+                R[8 * n4 + c] = d;
             }
         }
     }
@@ -545,6 +545,8 @@ __global__ __launch_bounds__(256) void k_residual_gather(ResArgs A)
     const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= A.nv) return;
     const int64_t n4 = 4 * A.nt;
+    const int32_t di = A.dir_index[i];
+    const bool want_dg = A.dg && di >= 0;
     double r[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0}, d[3] = {0, 0, 0};
     for (int32_t q = A.vinc_ptr[i]; q < A.vinc_ptr[i + 1]; ++q) {
         const double *R = A.rec + 4 * (int64_t)q;
@@ -557,7 +559,7 @@ __global__ __launch_bounds__(256) void k_residual_gather(ResArgs A)
 #pragma unroll
             for (int c = 0; c < 4; ++c) b[c] += bv.v[c];
         }
-        if (A.dg)
+        if (want_dg)
 #pragma unroll
             for (int c = 0; c < 3; ++c) d[c] += R[8 * n4 + c];
     }
@@ -566,8 +568,7 @@ __global__ __launch_bounds__(256) void k_residual_gather(ResArgs A)
     if (A.b)
 #pragma unroll
         for (int c = 0; c < 4; ++c) A.b[4 * i + c] = b[c];
-    const int32_t di = A.dir_index[i];
-    if (A.dg && di >= 0)
+    if (want_dg)
 #pragma unroll
         for (int c = 0; c < 3; ++c) A.dg[3 * (int64_t)di + c] = d[c];
 }
