@@ -635,6 +635,41 @@ __global__ __launch_bounds__(256) void k_amg_cheb(AmgLevel<T> L, T *__restrict__
     x[row] = (T)((double)x[row] + dn);
 }
 
+// The last Chebyshev step of a coarse level's visit, which also hands the finer
+// level its corrected iterate: xp[m] = fx0[m] + x_new[row] for every member m
+// of the row's aggregate (fx0: the finer level's iterate before the coarse
+// correction), so that the finer level's first post-smoothing pass reads one
+// vector instead of gathering the coarse correction entry by entry.
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_amg_cheb_prolong(AmgLevel<T> L, T *__restrict__ x, const T *__restrict__ dcur,
+                                                          T *__restrict__ dnext, const double *lam, double ratio,
+                                                          int step, const int32_t *done, const T *__restrict__ fx0,
+                                                          T *__restrict__ xp, const int32_t *__restrict__ fmptr,
+                                                          const int32_t *__restrict__ fmem)
+{
+    if (done && *done) return;
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= L.n) return;
+    double q = 0;
+    for (int32_t k = L.rowptr[row] + lane; k < L.rowptr[row + 1]; k += LPR)
+        q += (double)L.val[k] * (double)dcur[L.col[k]];
+    q = group_sum<double, LPR>(q);   // every lane of the group holds the sum
+    double theta, a, b;
+    cheb_coef(*lam, ratio, step, theta, a, b);
+    const double r = (double)L.res[row] - q;
+    const double dn = a * (double)dcur[row] + b * (double)L.dinv[row] * r;
+    const T xn = (T)((double)x[row] + dn);
+    for (int32_t k = fmptr[row] + lane; k < fmptr[row + 1]; k += LPR) {
+        const int32_t m = fmem[k];
+        xp[m] = (T)((double)fx0[m] + (double)xn);
+    }
+    if (lane != 0) return;
+    L.res[row] = (T)r;
+    dnext[row] = (T)dn;
+    x[row] = xn;
+}
+
 // res = r - A x
 template <typename T, int LPR>
 __global__ __launch_bounds__(256) void k_amg_resid(AmgLevel<T> L, const T *__restrict__ x, const int32_t *done)
@@ -820,6 +855,27 @@ __global__ __launch_bounds__(64 * SW) void k_amg_post0_sell(AmgLevel<T> L, const
     L.res[row] = (T)r;
     L.d0[row] = (T)d;
     L.x1[row] = (T)((double)L.x0[row] + (double)e[L.agg[row]] + d);
+}
+
+// The same with the corrected iterate xp = x0 + P e already formed by the
+// coarser level's last pass.
+template <typename T, bool D16, int SW>
+__global__ __launch_bounds__(64 * SW) void k_amg_post0_sell_xp(AmgLevel<T> L, const T *__restrict__ xp,
+                                                               const double *lam, double ratio, const int32_t *done)
+{
+    if (done && *done) return;
+    __shared__ double part[SW][64];
+    const int64_t slice = xcd_block();
+    const double q = sell_slice_dot<T, D16, SW>(L, slice, [&](int32_t c) { return (double)xp[c]; }, part);
+    const int64_t row = slice * 64 + (threadIdx.x & 63);
+    if (threadIdx.x >= 64 || row >= L.n) return;
+    double theta, a, b;
+    cheb_coef(*lam, ratio, 0, theta, a, b);
+    const double r = (double)L.r[row] - q;
+    const double d = (double)L.dinv[row] * r / theta;
+    L.res[row] = (T)r;
+    L.d0[row] = (T)d;
+    L.x1[row] = (T)((double)xp[row] + d);
 }
 
 // ================================================================== one-workgroup coarse cycle
@@ -1225,7 +1281,10 @@ template void launch_amg_setup<float>(const SimpleView<float> &, const float *, 
                                       hipStream_t);
 
 template <typename T>
-static void vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s)
+// prolong (optional): where the level's last pass also writes the finer level's
+// corrected iterate fx0 + P x (returns true if it did).
+static bool vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s, T *prolong = nullptr,
+                   const T *fx0 = nullptr)
 {
     if (A.tail.first > 0 && l == A.tail.first) {
         const AmgLevel<T> &F = A.L[l - 1];
@@ -1242,7 +1301,7 @@ static void vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s)
         t.out = A.L[l].x1;
         t.done = done;
         hipLaunchKernelGGL((k_amg_tail<T>), dim3(1), dim3(kTailThreads), (size_t)A.tail.lds_bytes, s, t);
-        return;
+        return false;
     }
     if (l == A.nlev) {
         const bool fine = l == 0;
@@ -1250,7 +1309,7 @@ static void vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s)
         const int32_t *mptr = fine ? nullptr : A.L[l - 1].mptr, *mem = fine ? nullptr : A.L[l - 1].mem;
         hipLaunchKernelGGL((k_dense_solve<T>), dim3(1), dim3(256), 0, s, (int)A.nc, A.dense, fres, mptr, mem,
                            A.L[l].x1, done);
-        return;
+        return false;
     }
     AmgLevel<T> L = A.L[l];
     const double *lam = &A.lam[l];
@@ -1272,14 +1331,19 @@ static void vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s)
     // gamma coarse corrections (1: V-cycle, 2: W-cycle below the finest level),
     // each followed by post-smoothing; the iterate alternates between x0 and x1
     const int gamma = l > 0 ? A.cycle : 1;
+    bool prolonged = false;
     for (int c = 0; c < gamma; ++c) {
         if (L.soff)
             LX_SELL_LAUNCH(L, k_amg_resid_sell, gsell, L, L.x0, done);
         else
             LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_resid<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s,
                                                     L, L.x0, done));
-        vcycle(A, l + 1, done, s);
-        if (L.soff)
+        // a sliced-ELL level takes its corrected iterate from the coarser level's last pass, in d1
+        // (free until the post-smoothing Chebyshev step writes it)
+        const bool xp = vcycle(A, l + 1, done, s, L.soff ? L.d1 : nullptr, L.x0);
+        if (L.soff && xp)
+            LX_SELL_LAUNCH(L, k_amg_post0_sell_xp, gsell, L, L.d1, lam, A.ratio, done);
+        else if (L.soff)
             LX_SELL_LAUNCH(L, k_amg_post0_sell, gsell, L, A.L[l + 1].x1, lam, A.ratio, done);
         else
             LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_post0<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0, s,
@@ -1287,9 +1351,16 @@ static void vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s)
         dc = L.d0;
         dn = L.d1;
         for (int i = 1; i < A.degree; ++i) {
+            const bool last = c + 1 == gamma && i + 1 == A.degree;
             if (L.soff)
                 LX_SELL_LAUNCH(L, k_amg_cheb_sell, gsell, L, L.x1, dc, dn, lam, A.ratio, i, done);
-            else
+            else if (last && prolong && fx0 && l > 0) {
+                const AmgLevel<T> &F = A.L[l - 1];
+                LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_cheb_prolong<T, LP>), dim3(rows_grid(L.n, LP)),
+                                                        dim3(256), 0, s, L, L.x1, dc, dn, lam, A.ratio, i, done,
+                                                        fx0, prolong, F.mptr, F.mem));
+                prolonged = true;
+            } else
                 LX_LPR_SWITCH(L.lpr, hipLaunchKernelGGL((k_amg_cheb<T, LP>), dim3(rows_grid(L.n, LP)), dim3(256), 0,
                                                         s, L, L.x1, dc, dn, lam, A.ratio, i, done));
             std::swap(dc, dn);
@@ -1299,6 +1370,7 @@ static void vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s)
     // the level's result is read from x1
     A.L[l].x0 = L.x0;
     A.L[l].x1 = L.x1;
+    return prolonged;
 }
 
 template <typename T>
