@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--f-ratio", type=float, default=0.0, help="0: library default (5 P1-P1, 300 P2-P1)")
     ap.add_argument("--amg-degree", type=int, default=2)
     ap.add_argument("--amg-cycle", type=int, default=2)
+    ap.add_argument("--amg-coarse-cycle", type=int, default=3,
+                    help="coarse corrections per level on the AMG levels held in one workgroup's LDS")
     ap.add_argument("--amg-ratio", type=float, default=30.0)
     ap.add_argument("--schur-degree", type=int, default=16)
     ap.add_argument("--schur-ratio", type=float, default=300.0)
@@ -132,7 +134,7 @@ def run_precision(mesh, prob, precision, args, stream, torch):
                    collect_timing=SPMV_TIMING_STRIDE, schur_degree=args.schur_degree, schur_ratio=args.schur_ratio,
                    restart=args.restart, asm_fp64=bool(args.asm_fp64), precond=args.precond,
                    f_degree=args.f_degree, f_ratio=args.f_ratio, amg_degree=args.amg_degree,
-                   amg_cycle=args.amg_cycle, amg_ratio=args.amg_ratio)
+                   amg_cycle=args.amg_cycle, amg_ratio=args.amg_ratio, amg_coarse_cycle=args.amg_coarse_cycle)
     if args.verbose:
         print("[bench] %s: creating the simulation (%d tets)" % (precision, mesh.nt), file=sys.stderr, flush=True)
     sim = Sim(mesh, prob, sv, device=0, stream=stream)
@@ -442,9 +444,10 @@ def main():
                                  "from rest" %
                                  (q["n_tets"], nv, q["n_dofs"]))),
                    "precision": headp, "rel_residual_target": 1e-8, "restart": args.restart,
-                   "precond": (("amg: F chebyshev deg %d ratio %g, S~ aggregation AMG cycle %d smoothing deg %d "
-                                "ratio %g") % (args.f_degree or (12 if p2 else 3), args.f_ratio or (300 if p2 else 5),
-                                               args.amg_cycle, args.amg_degree, args.amg_ratio))
+                   "precond": (("amg: F chebyshev deg %d ratio %g, S~ aggregation AMG cycle %d (%d on the levels in "
+                                "LDS) smoothing deg %d ratio %g") %
+                               (args.f_degree or (12 if p2 else 3), args.f_ratio or (300 if p2 else 5),
+                                args.amg_cycle, args.amg_coarse_cycle, args.amg_degree, args.amg_ratio))
                               if args.precond == "amg" else
                               ("cheb_schur deg %d ratio %g" % (args.schur_degree, args.schur_ratio)),
                    "asm_fp64": bool(args.asm_fp64), "inner_rtol": args.inner_rtol},

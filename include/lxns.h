@@ -165,9 +165,9 @@ enum { LX_PC_AMG = 0, LX_PC_CHEB_SCHUR = 1 };
  *   LX_PC_CHEB_SCHUR: F by F~^{-1}; S~ (not formed) by diag(S~)^{-1}
  *     (schur_degree = 0) or a Chebyshev iteration of degree schur_degree with
  *     diagonal scaling over [lam / schur_ratio, lam].
- * A zero in f_degree, amg_degree, amg_cycle, f_ratio or amg_ratio selects its
+ * A zero in f_degree, amg_degree, amg_cycle, f_ratio, amg_ratio or amg_coarse_cycle selects its
  * default (f_degree 3 for P1-P1 and 12 for P2-P1, amg_degree 2, amg_cycle 2,
- * f_ratio 5 for P1-P1 and 300 for P2-P1, amg_ratio 30).  LX_FP32_IR: FP32 matrix and FP32 inner GMRES inside an
+ * f_ratio 5 for P1-P1 and 300 for P2-P1, amg_ratio 30, amg_coarse_cycle 3).  LX_FP32_IR: FP32 matrix and FP32 inner GMRES inside an
  * FP64 iterative refinement loop that stops when the FP64 residual satisfies
  * ir_rtol; inner solves aim at one more refinement step but never tighter
  * than inner_rtol. */
@@ -193,6 +193,9 @@ typedef struct {
                                 finest, 0..3 (0: default 2, a W-cycle there)        */
     double f_ratio;          /* LX_PC_AMG: 0 (default, see above) or > 1             */
     double amg_ratio;        /* LX_PC_AMG: 0 (default 30) or > 1                     */
+    int32_t amg_coarse_cycle;   /* LX_PC_AMG: coarse corrections per level on the
+                                   coarse levels that fit one workgroup's LDS, 0..6
+                                   (0: default 3); amg_cycle applies above them      */
 } lx_solver;
 
 /* ---------------------------------------------------------------- outputs */

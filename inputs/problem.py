@@ -96,6 +96,7 @@ class SolverCfg:
     amg_degree: int = 2              # amg: Chebyshev smoothing degree per level
     amg_cycle: int = 2               # amg: coarse corrections per level below the finest (2 = W)
     amg_ratio: float = 30.0
+    amg_coarse_cycle: int = 0        # amg: coarse corrections per level on the levels held in LDS (0 = 3)
 
 
 # ----------------------------------------------------------------- configs

@@ -108,6 +108,8 @@ struct Amg {
     int nb = 1;                         // reduction blocks
     int degree = 2;                     // Chebyshev smoothing degree (pre and post)
     int cycle = 1;                      // coarse corrections per level below the finest (1 V, 2 W)
+    int cycle_coarse = 1;               // the same on the levels from coarse_from on
+    int coarse_from = 1 << 20;          // first level that fits one workgroup's LDS
     double ratio = 30.0;                // smoothing interval [lam / ratio, lam]
     int f_degree = 3;                   // Chebyshev degree on F (1: plain block Jacobi)
     double f_ratio = 10.0;

@@ -1294,7 +1294,7 @@ static bool vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s, T *prol
         t.lam = A.lam;
         t.ratio = A.ratio;
         t.degree = A.degree;
-        t.cycle = A.cycle;
+        t.cycle = A.cycle_coarse;
         t.fres = F.res;
         t.fmptr = F.mptr;
         t.fmem = F.mem;
@@ -1328,9 +1328,12 @@ static bool vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s, T *prol
                                                     L, L.x0, dc, dn, lam, A.ratio, i, done));
         std::swap(dc, dn);
     }
-    // gamma coarse corrections (1: V-cycle, 2: W-cycle below the finest level),
-    // each followed by post-smoothing; the iterate alternates between x0 and x1
-    const int gamma = l > 0 ? A.cycle : 1;
+    // gamma coarse corrections (1 on the finest level; cycle below it, 2 being a
+    // W-cycle; cycle_coarse on the levels small enough for one workgroup's LDS,
+    // where a correction costs barriers rather than launches and more of them
+    // bring the coarse solve closer to exact), each followed by post-smoothing;
+    // the iterate alternates between x0 and x1
+    const int gamma = l == 0 ? 1 : l >= A.coarse_from ? A.cycle_coarse : A.cycle;
     bool prolonged = false;
     for (int c = 0; c < gamma; ++c) {
         if (L.soff)

@@ -97,6 +97,8 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         if (sv->f_degree < 0 || sv->f_degree > 16) return fail(LX_EINVAL, "f_degree must be 0..16");
         if (sv->amg_degree < 0 || sv->amg_degree > 8) return fail(LX_EINVAL, "amg_degree must be 0..8");
         if (sv->amg_cycle < 0 || sv->amg_cycle > 3) return fail(LX_EINVAL, "amg_cycle must be 0..3");
+        if (sv->amg_coarse_cycle < 0 || sv->amg_coarse_cycle > 6)
+            return fail(LX_EINVAL, "amg_coarse_cycle must be 0..6");
         if (sv->f_ratio != 0.0 && !(sv->f_ratio > 1.0)) return fail(LX_EINVAL, "f_ratio must be 0 or > 1");
         if (sv->amg_ratio != 0.0 && !(sv->amg_ratio > 1.0)) return fail(LX_EINVAL, "amg_ratio must be 0 or > 1");
     }
@@ -112,6 +114,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         if (solver.f_ratio == 0.0) solver.f_ratio = q2 ? 300.0 : 5.0;
         if (solver.amg_ratio == 0.0) solver.amg_ratio = 30.0;
         if (solver.amg_cycle == 0) solver.amg_cycle = 2;
+        if (solver.amg_coarse_cycle == 0) solver.amg_coarse_cycle = 3;
     }
     for (int i = 0; i < pr->n_bc; ++i) {
         BCDesc b;
@@ -458,6 +461,7 @@ lx_status Sim::setup_amg(Amg<T> &A)
     A.f_ratio = solver.f_ratio;
     A.f_warm = false;
     A.cycle = solver.amg_cycle;
+    A.cycle_coarse = solver.amg_coarse_cycle;
     const char *env = getenv("LXNS_AMG_LPR");
     const int lpr_env = env ? atoi(env) : 0;
     int64_t maxgrid = (nu * 16 + 255) / 256;
@@ -485,7 +489,10 @@ lx_status Sim::setup_amg(Amg<T> &A)
         LX_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
         const char *te = getenv("LXNS_AMG_TAIL");
         const bool use_tail = !(te && *te == '0');
-        A.tail = use_tail ? amg_tail_layout(A.nlev, ln, lnnz, (int)sizeof(T), max_lds) : TailLayout();
+        // the levels that fit take cycle_coarse coarse corrections, whichever kernels cycle them
+        const TailLayout fit = amg_tail_layout(A.nlev, ln, lnnz, (int)sizeof(T), max_lds);
+        A.coarse_from = fit.first > 0 ? fit.first : A.nlev + 1;
+        A.tail = use_tail ? fit : TailLayout();
         // a device that refuses the LDS reservation runs every level on its own launches
         if (A.tail.first > 0 && amg_tail_prepare<T>(A.tail.lds_bytes) != LX_OK) A.tail = TailLayout();
         if (A.tail.first > 0) {

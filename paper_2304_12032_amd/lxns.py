@@ -77,7 +77,7 @@ class lx_solver(ctypes.Structure):
                 ("rtol", c_dbl), ("ir_rtol", c_dbl), ("inner_rtol", c_dbl), ("deterministic", c_i32),
                 ("collect_timing", c_i32), ("schur_degree", c_i32), ("asm_fp64", c_i32), ("schur_ratio", c_dbl),
                 ("precond", c_i32), ("f_degree", c_i32), ("amg_degree", c_i32), ("amg_cycle", c_i32), ("f_ratio", c_dbl),
-                ("amg_ratio", c_dbl)]
+                ("amg_ratio", c_dbl), ("amg_coarse_cycle", c_i32)]
 
 
 class lx_sizes(ctypes.Structure):
@@ -253,6 +253,7 @@ class _Marshal:
         s.amg_cycle = int(getattr(solver, "amg_cycle", 0))
         s.f_ratio = float(getattr(solver, "f_ratio", 0.0))
         s.amg_ratio = float(getattr(solver, "amg_ratio", 0.0))
+        s.amg_coarse_cycle = int(getattr(solver, "amg_coarse_cycle", 0))
         self.solver = s
 
 
