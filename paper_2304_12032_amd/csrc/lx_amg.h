@@ -86,6 +86,7 @@ struct TailLayout {
     int first = 0, nlev = 0, nc = 0;   // first: 0 = no one-workgroup cycle
     int32_t o_dense = 0, o_rc = 0, o_xc = 0;
     int32_t o_fmptr = -1, o_fmem = -1; // member lists of level first - 1 in the image (-1: read globally)
+    int32_t o_fstage = -1;             // LDS copy of level first - 1's residual in member order (-1: none)
     int32_t img_bytes = 0, lds_bytes = 0;
     TailLevelLds lv[kTailDepth];
 };

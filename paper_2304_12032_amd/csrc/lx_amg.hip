@@ -940,6 +940,39 @@ __device__ __forceinline__ void tail_pre_global(const TailArgs<T> &A, const Tail
     const bool in_lds = A.lay.o_fmem >= 0;
     const int32_t *fmptr = in_lds ? lds_i(lds, A.lay.o_fmptr) : A.fmptr;
     const int32_t *fmem = in_lds ? lds_i(lds, A.lay.o_fmem) : A.fmem;
+    if (A.lay.o_fstage >= 0) {
+        // the finer residual gathered in member order by all threads at once
+        // (eight loads each in flight), then each row sums a contiguous range
+        T *stage = lds_v<T>(lds, A.lay.o_fstage);
+        const int32_t nf = fmptr[L.n];
+        for (int32_t q0 = 0; q0 < nf; q0 += 8 * kTailThreads) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int32_t q = q0 + u * kTailThreads + (int32_t)threadIdx.x;
+                v[u] = q < nf ? A.fres[fmem[q]] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int32_t q = q0 + u * kTailThreads + (int32_t)threadIdx.x;
+                if (q < nf) stage[q] = v[u];
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x / lanes; i < L.n; i += kTailThreads / lanes) {
+            double s = 0;
+            for (int32_t q = fmptr[i] + lane; q < fmptr[i + 1]; q += lanes) s += (double)stage[q];
+            s = lane_sum(s, lanes);
+            if (lane == 0) {
+                const T x = (T)((double)dinv[i] * s / theta);
+                r[i] = (T)s;
+                res[i] = (T)s;
+                x0[i] = x;
+                d0[i] = x;
+            }
+        }
+        return;
+    }
     for (int i = threadIdx.x / lanes; i < L.n; i += kTailThreads / lanes) {
         const int32_t q0 = fmptr[i], q1 = fmptr[i + 1];
         double s = 0;
@@ -1066,13 +1099,15 @@ __device__ __forceinline__ T *tail_dense(const TailArgs<T> &A, const TailLevelLd
     double *rc = lds_v<double>(lds, A.lay.o_rc);
     const double *aug = lds_v<double>(lds, A.lay.o_dense);
     T *xc = lds_v<T>(lds, A.lay.o_xc);
-    for (int c = threadIdx.x; c < nc; c += kTailThreads) {
+    // restriction: sixteen lanes per coarse row
+    const int lanes = 16, lane = threadIdx.x & 15;
+    for (int c = threadIdx.x / lanes; c < nc; c += kTailThreads / lanes) {
         double s = 0;
-        for (int32_t q = mptr[c]; q < mptr[c + 1]; ++q) s += (double)fres[mem[q]];
-        rc[c] = s;
+        for (int32_t q = mptr[c] + lane; q < mptr[c + 1]; q += lanes) s += (double)fres[mem[q]];
+        s = lane_sum(s, lanes);
+        if (lane == 0) rc[c] = s;
     }
     __syncthreads();
-    const int lanes = 16, lane = threadIdx.x & 15;
     for (int row = threadIdx.x / lanes; row < nc; row += kTailThreads / lanes) {
         double s = 0;
         for (int c = lane; c < nc; c += lanes) s += aug[(int64_t)row * 2 * nc + nc + c] * rc[c];

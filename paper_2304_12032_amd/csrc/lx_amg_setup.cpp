@@ -177,7 +177,10 @@ TailLayout amg_tail_layout(int nlev, const int64_t *n, const int64_t *nnz, int v
         bool small = true;
         for (int m = first; m < nlev; ++m) small = small && n[m] <= kTailMaxRows;
         if (!small) continue;
-        for (int lists = 1; lists >= 0; --lists) {
+        // with the member lists in the image, and space to stage the finer residual
+        // in member order; with the lists only; with neither
+        for (int variant = 0; variant < 3; ++variant) {
+            const bool lists = variant < 2, stage = variant == 0;
             TailLayout T;
             T.first = first;
             T.nlev = nlev;
@@ -226,6 +229,10 @@ TailLayout amg_tail_layout(int nlev, const int64_t *n, const int64_t *nnz, int v
             o = align16(o + 8 * n[nlev]);
             T.o_xc = (int32_t)o;
             o = align16(o + (int64_t)vbytes * n[nlev]);
+            if (stage) {
+                T.o_fstage = (int32_t)o;
+                o = align16(o + (int64_t)vbytes * n[first - 1]);
+            }
             T.lds_bytes = (int32_t)o;
             if (o <= max_lds) return T;
         }
