@@ -179,10 +179,12 @@ def run_precision(mesh, prob, precision, args, stream, torch):
 
 # VALU flops per element of the assembly passes, from SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS} counters on the
 # 983k-tet tube (64 x (ADD + MUL + TRANS) + 128 x FMA per wave instruction): element + slot gather of the
-# FP64 and of the FP32 path, and one FP64 matrix-free residual evaluation (element pass).
+# FP64 and of the FP32 path, and the FP64 matrix-free residual's element pass (the step's first
+# evaluation also forms b and the Dirichlet diagonal).
 ASM_FLOPS_PER_TET = {"fp64": {"f64": 2383.0 + 6445.0, "f32": 0.0},
                      "fp32_ir": {"f64": 206.0 + 6197.0, "f32": 1698.0}}
-RESID_FLOPS_PER_TET = 3216.0
+RESID_FIRST_FLOPS_PER_TET = 3670.0
+RESID_FLOPS_PER_TET = 2764.0
 FP64_PEAK, FP32_PEAK = 78.6e12, 157.3e12
 
 
@@ -241,10 +243,15 @@ def step_bound(q, prec, iters, ir_iters, args):
              + 2 * nblk * (3 * s + 4) + nblk * (s + 4) + 3 * nv * s + nnz[0] * (s + 4)   # S~ formation
              + sum(nnz[l] * (s + 4) + nnz[l + 1] * s + nnz[l] * s for l in range(dense))  # Galerkin sums, bounds
              + 6 * (nblk * (9 * s + 4) + nv * (4 + 13 * s)))                  # power iterations on F
-    resid = (ir_iters + 1) * (nt * (48 * 8 + 16) * 2 + nv * (32 + 32)) if prec == "fp32_ir" else 0
+    # FP64 residuals: connectivity, the vertex data, each element's contributions written and read once
+    # (r and b at the first evaluation of a step, r alone afterwards) and the summed rows
+    vin = nv * (24 + 24 + 32 * hist + 32)
+    resid = ((nt * (16 + 2 * 32 * 8) + vin + nv * 64) + ir_iters * (nt * (16 + 2 * 16 * 8) + vin + nv * 32)
+             if prec == "fp32_ir" else 0)
     nbytes = iters * per_iter + asm + setup + resid
     fl = ASM_FLOPS_PER_TET[prec]
-    f64 = nt * fl["f64"] + ((ir_iters + 1) * nt * RESID_FLOPS_PER_TET if prec == "fp32_ir" else 0)
+    f64 = nt * fl["f64"] + (nt * (RESID_FIRST_FLOPS_PER_TET + ir_iters * RESID_FLOPS_PER_TET)
+                            if prec == "fp32_ir" else 0)
     f32 = nt * fl["f32"]
     t = nbytes / (HBM_PEAK_GBS * 1e9) + f64 / FP64_PEAK + f32 / FP32_PEAK
     return {"bytes_per_step": int(nbytes), "bytes_per_gmres_iter": int(per_iter), "f64_flops": f64, "f32_flops": f32,
