@@ -109,6 +109,17 @@ def test_bad_restart_rejected():
     assert ei.value.status == -1
 
 
+@pytest.mark.parametrize("field,value", [("amg_coarse_cycle", 7), ("amg_coarse_cycle", -1), ("amg_cycle", 4),
+                                         ("amg_degree", 9), ("f_degree", 17), ("amg_ratio", 0.5)])
+def test_bad_amg_parameters_rejected(field, value):
+    """The solver checks the multigrid parameters before touching a device."""
+    from paper_2304_12032_amd import LxError
+    mesh, prob = beltrami_cube_problem(2)
+    with pytest.raises(LxError) as ei:
+        _create(mesh, prob, SolverCfg(**{field: value}))
+    assert ei.value.status == -1
+
+
 def test_server_rejects_request_over_budget():
     from paper_2304_12032_amd import Server, LxError
     m = tube(nxy=4, nz=8, length=2.0)
