@@ -39,16 +39,19 @@ __device__ inline int32_t find_col(const int32_t *col, int32_t lo, int32_t hi, i
 
 // S~_ik = C_ik - sum_{j, d} B_ij[d] D^{-1}_j[d] G_jk[d] over the velocity nodes j
 // of B's row i.  One wavefront per row i.  The wave first stages, in LDS, C's
-// row and, for every G row j that B's row names (row after row, in B's order),
-// the columns k and the products sum_d B_ij[d] D^{-1}_j[d] G_jk[d]; then lanes
-// take the entries of S~'s row and subtract, for each j in B's order, the
-// staged product whose column matches (binary search in the staged, sorted G
-// row).  The sum runs over B's row in order, so the result does not depend on
-// scheduling.  Rows whose rows do not fit the LDS share search C and G in
-// global memory instead, with the same arithmetic.
+// row, S~'s columns and, for every G row j that B's row names (row after row,
+// in B's order), the products sum_d B_ij[d] D^{-1}_j[d] G_jk[d] with the
+// position of their column k in S~'s row (binary search in the staged row).
+// The accumulator of each entry starts at C_ik; then the G rows are taken in
+// B's order, each lane subtracting one product of the row from its entry (the
+// columns of one G row are distinct, so no two lanes meet).  The sum runs over
+// B's row in order, so the result does not depend on scheduling.  Rows whose
+// rows do not fit the LDS share search C and G in global memory instead, with
+// the same arithmetic.
 // The LDS share per row is a template pair (B and C entries at most ROWS <= 128,
-// staged products at most CAP): a small one for P1-P1, whose rows are short,
-// keeps more workgroups per compute unit; P2-P1 rows need the large one.
+// staged products at most CAP, entries of S~'s row at most 2 ROWS + 32): a small
+// one for P1-P1, whose rows are short, keeps more workgroups per compute unit;
+// P2-P1 rows need the large one.
 constexpr int kSfWaves = 4;      // waves (rows) per workgroup
 
 __device__ inline int32_t find_col_lds(const int32_t *col, int32_t lo, int32_t hi, int32_t k)
@@ -81,20 +84,24 @@ __global__ __launch_bounds__(256) void k_schur_form(SimpleView<T> V, const T *__
                                                     const int32_t *__restrict__ scol, T *__restrict__ sval,
                                                     const int32_t *__restrict__ soff)
 {
+    constexpr int kSfOut = 2 * kSfRows + 32;
     __shared__ int32_t s_off[kSfWaves][kSfRows + 1];
     __shared__ int32_t s_j[kSfWaves][kSfRows];
     __shared__ int32_t s_gb[kSfWaves][kSfRows];
     __shared__ int32_t s_cc[kSfWaves][kSfRows];
     __shared__ double s_cv[kSfWaves][kSfRows];
-    __shared__ int32_t s_col[kSfWaves][kSfCap];
+    __shared__ int32_t s_sc[kSfWaves][kSfOut];
+    __shared__ double s_acc[kSfWaves][kSfOut];
+    __shared__ int32_t s_tgt[kSfWaves][kSfCap];
     __shared__ double s_val[kSfWaves][kSfCap];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t i = xcd_block() * kSfWaves + wv;
     const bool live = i < V.np;
     const int32_t b0 = live ? V.bptr[i] : 0, b1 = live ? V.bptr[i + 1] : 0;
     const int32_t c0 = live ? V.cptr[i] : 0, c1 = live ? V.cptr[i + 1] : 0;
-    const int nb = b1 - b0, nc = c1 - c0;
-    bool staged = live && nb <= kSfRows && nc <= kSfRows;   // uniform over the wave
+    const int32_t e0 = live ? srow[i] : 0, e1 = live ? srow[i + 1] : 0;
+    const int nb = b1 - b0, nc = c1 - c0, ns = e1 - e0;
+    bool staged = live && nb <= kSfRows && nc <= kSfRows && ns <= kSfOut;   // uniform over the wave
     int32_t *off = s_off[wv];
     if (staged) {
         // B entries: velocity node, start and length of its G row; inclusive scan of
@@ -113,6 +120,7 @@ __global__ __launch_bounds__(256) void k_schur_form(SimpleView<T> V, const T *__
                 s_cv[wv][t] = (double)V.Cv[c0 + t];
             }
         }
+        for (int e = lane; e < ns; e += 64) s_sc[wv][e] = scol[e0 + e];
         for (int d = 1; d < 64; d <<= 1) {
             const int32_t u0 = __shfl_up(len[0], d), u1 = __shfl_up(len[1], d);
             if (lane >= d) {
@@ -128,6 +136,11 @@ __global__ __launch_bounds__(256) void k_schur_form(SimpleView<T> V, const T *__
     __syncthreads();
     staged = staged && off[nb] <= kSfCap;
     if (staged) {
+        // every entry's accumulator starts at C_ik (0 where C has no entry)
+        for (int e = lane; e < ns; e += 64) {
+            const int32_t kc = find_col_lds(s_cc[wv], 0, nc, s_sc[wv][e]);
+            s_acc[wv][e] = kc >= 0 ? s_cv[wv][kc] : 0.0;
+        }
         // four products per lane at a time, so that their gathers are in flight together
         const int total = off[nb];
         for (int q0 = 0; q0 < total; q0 += 256) {
@@ -157,33 +170,39 @@ __global__ __launch_bounds__(256) void k_schur_form(SimpleView<T> V, const T *__
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (kg[u] >= 0) {
-                    s_col[wv][q0 + 64 * u + lane] = col[u];
+                    // S~'s pattern holds every column of every G row that B's row names
+                    s_tgt[wv][q0 + 64 * u + lane] = find_col_lds(s_sc[wv], 0, ns, col[u]);
                     s_val[wv][q0 + 64 * u + lane] = pv[u];
                 }
         }
     }
     __syncthreads();
     if (!live) return;
-    for (int32_t e = srow[i] + lane; e < srow[i + 1]; e += 64) {
-        const int32_t k = scol[e];
-        double acc;
-        if (staged) {
-            const int32_t kc = find_col_lds(s_cc[wv], 0, nc, k);
-            acc = kc >= 0 ? s_cv[wv][kc] : 0.0;
-            for (int t = 0; t < nb; ++t) {
-                const int32_t q = find_col_lds(s_col[wv], off[t], off[t + 1], k);
-                if (q >= 0) acc -= s_val[wv][q];
+    if (staged) {
+        // G rows in B's order; within one row the targets are distinct.  The wave's
+        // LDS accesses complete in program order, so row t + 1 sees row t's updates.
+        for (int t = 0; t < nb; ++t) {
+            for (int q = off[t] + lane; q < off[t + 1]; q += 64) {
+                const int32_t e = s_tgt[wv][q];
+                if (e >= 0) s_acc[wv][e] -= s_val[wv][q];
             }
-        } else {
-            const int32_t kc = find_col(V.ccol, c0, c1, k);
-            acc = kc >= 0 ? (double)V.Cv[kc] : 0.0;
-            for (int32_t k1 = b0; k1 < b1; ++k1) {
-                const int32_t j = V.bcol[k1];
-                const int32_t kg = find_col(V.gcol, V.gptr[j], V.gptr[j + 1], k);
-                if (kg >= 0) acc -= schur_term(V, Dinv, k1, j, kg);
-            }
+            __builtin_amdgcn_wave_barrier();
         }
-        sval[soff ? (int64_t)soff[i >> 6] + (int64_t)(e - srow[i]) * 64 + (i & 63) : (int64_t)e] = (T)acc;
+        __builtin_amdgcn_wave_barrier();
+        for (int e = lane; e < ns; e += 64)
+            sval[soff ? (int64_t)soff[i >> 6] + (int64_t)e * 64 + (i & 63) : (int64_t)(e0 + e)] = (T)s_acc[wv][e];
+        return;
+    }
+    for (int32_t e = e0 + lane; e < e1; e += 64) {
+        const int32_t k = scol[e];
+        const int32_t kc = find_col(V.ccol, c0, c1, k);
+        double acc = kc >= 0 ? (double)V.Cv[kc] : 0.0;
+        for (int32_t k1 = b0; k1 < b1; ++k1) {
+            const int32_t j = V.bcol[k1];
+            const int32_t kg = find_col(V.gcol, V.gptr[j], V.gptr[j + 1], k);
+            if (kg >= 0) acc -= schur_term(V, Dinv, k1, j, kg);
+        }
+        sval[soff ? (int64_t)soff[i >> 6] + (int64_t)(e - e0) * 64 + (i & 63) : (int64_t)e] = (T)acc;
     }
 }
 
