@@ -177,8 +177,26 @@ void launch_amg_setup(const SimpleView<T> &V, const T *Finv, const T *Dinv, Amg<
 
 // z <- M^{-1} (scale * r) for the SIMPLE preconditioner with the AMG Schur block
 // and the Chebyshev velocity block.
+// start_done: z.u, z.p and the Chebyshev start of the velocity block were
+// already written (by the Gram-Schmidt pass that formed r, see amg_fz_start).
 template <typename T>
 void launch_simple_amg_apply(const SimpleView<T> &V, const T *Finv, const T *Dinv, Amg<T> &A, const T *r,
-                             const double *scale_ptr, T *z, const int32_t *done, hipStream_t s);
+                             const double *scale_ptr, T *z, const int32_t *done, hipStream_t s,
+                             bool start_done = false);
+
+// The velocity block's start for a direction whose preconditioned vector goes to z.
+template <typename T>
+inline FzStart<T> amg_fz_start(const Amg<T> &A, const T *Finv, T *z)
+{
+    FzStart<T> f;
+    f.Finv = Finv;
+    f.z = z;
+    f.fr = A.fr;
+    f.fd = A.fd0;
+    f.lamF = &A.lam[kLamF];
+    f.ratio = A.f_ratio;
+    f.degree = A.f_degree;
+    return f;
+}
 
 }  // namespace lx

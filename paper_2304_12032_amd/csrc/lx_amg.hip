@@ -1432,13 +1432,14 @@ static bool vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s, T *prol
 
 template <typename T>
 void launch_simple_amg_apply(const SimpleView<T> &V, const T *Finv, const T *Dinv, Amg<T> &A, const T *r,
-                             const double *scale_ptr, T *z, const int32_t *done, hipStream_t s)
+                             const double *scale_ptr, T *z, const int32_t *done, hipStream_t s, bool start_done)
 {
     const RowPattern &P = V.Fp;
     const T *val = V.F;
     const int lpr = block_lpr(P);
-    hipLaunchKernelGGL((k_fz_start<T>), dim3(flat_grid(P.nv)), dim3(256), 0, s, P.nv, Finv, r, scale_ptr, z, A.fr,
-                       A.fd0, &A.lam[kLamF], A.f_ratio, A.f_degree, done);
+    if (!start_done)
+        hipLaunchKernelGGL((k_fz_start<T>), dim3(flat_grid(P.nv)), dim3(256), 0, s, P.nv, Finv, r, scale_ptr, z,
+                           A.fr, A.fd0, &A.lam[kLamF], A.f_ratio, A.f_degree, done);
     T *dc = A.fd0, *dn = A.fd1;
     for (int i = 1; i < A.f_degree; ++i) {
         LX_LPR_SWITCH(lpr, hipLaunchKernelGGL((k_fcheb<T, LP>), dim3(rows_grid(P.nv, LP)), dim3(256), 0, s, P, val,
@@ -1453,8 +1454,9 @@ void launch_simple_amg_apply(const SimpleView<T> &V, const T *Finv, const T *Din
 }
 template void launch_simple_amg_apply<double>(const SimpleView<double> &, const double *, const double *,
                                               Amg<double> &, const double *, const double *, double *,
-                                              const int32_t *, hipStream_t);
+                                              const int32_t *, hipStream_t, bool);
 template void launch_simple_amg_apply<float>(const SimpleView<float> &, const float *, const float *, Amg<float> &,
-                                             const float *, const double *, float *, const int32_t *, hipStream_t);
+                                             const float *, const double *, float *, const int32_t *, hipStream_t,
+                                             bool);
 
 }  // namespace lx

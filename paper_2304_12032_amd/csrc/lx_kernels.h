@@ -106,9 +106,23 @@ int64_t gm_partial_size(int64_t n);
 // r = b - Ax (Ax null: r = b), V0 = r, beta = ||r||; starts a cycle or marks it done
 template <typename T>
 void launch_gm_start(int64_t n, const T *b, const T *Ax, T *V0, GmState *st, double *partial, hipStream_t s);
-// CGS2 of w against Vhat_0..Vhat_k, Vhat_{k+1}, Hessenberg column k and its Givens update
+// The first pass of the velocity block's Chebyshev iteration on the next Arnoldi
+// direction r = V_{k+1}, done by the Gram-Schmidt pass that completes it:
+// z.u = F~^{-1} r.u / theta with fr = r.u and fd = z.u (degree > 1), or
+// z.u = F~^{-1} r.u (degree 1); z.p = r.p.  Vectors [nv][4], Finv [9][nv].
 template <typename T>
-void launch_gm_orth(int64_t n, int k, T *V, int64_t ldv, T *w, GmState *st, double *partial, hipStream_t s);
+struct FzStart {
+    const T *Finv = nullptr;
+    T *z = nullptr, *fr = nullptr, *fd = nullptr;
+    const double *lamF = nullptr;   // Chebyshev bound of F~^{-1} F
+    double ratio = 1.0;
+    int degree = 1;
+};
+// CGS2 of w against Vhat_0..Vhat_k, Vhat_{k+1}, Hessenberg column k and its Givens
+// update; fz (optional): also the velocity block's start on V_{k+1}
+template <typename T>
+void launch_gm_orth(int64_t n, int k, T *V, int64_t ldv, T *w, GmState *st, double *partial, hipStream_t s,
+                    const FzStart<T> *fz = nullptr);
 void launch_gm_solve_y(GmState *st, hipStream_t s);
 // x += sum_j y_j Z_j (flexible GMRES solution update)
 template <typename T>

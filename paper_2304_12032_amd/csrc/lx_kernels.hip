@@ -1222,18 +1222,21 @@ __global__ __launch_bounds__(256) void k_gm_dot(int64_t n, const T *V, int64_t l
 // pass that ends the step takes ||Vhat_{k+1}||^2 = <w, w> - sum_j h_j^2 (the
 // basis is orthonormal to working precision; the test above keeps the
 // difference at least a tenth of <w, w>), and applies the Givens update of
-// column k and the convergence test.  A block that starts after block 0 has
-// ended the cycle returns at once: Vhat_{k+1} is then never read.
+// column k and the convergence test; with fz, it also starts the velocity
+// block's Chebyshev iteration on V_{k+1} = s_{k+1} Vhat_{k+1} (every block knows
+// ||Vhat_{k+1}|| from the same sums).  One thread per node (4-vector).  A block
+// that starts after block 0 has ended the cycle returns at once: Vhat_{k+1} is
+// then never read.
 template <typename T, int K>
 __global__ __launch_bounds__(256) void k_gm_axpy_fin(int64_t n, int k, int nbx, T *V, int64_t ldv, const T *w,
-                                                     GmState *st, const double *partial, int second)
+                                                     GmState *st, const double *partial, int second, FzStart<T> fz)
 {
     if (st->done || (second && !st->reorth)) return;
     __shared__ double red[K + 1];
     __shared__ double coef[K];
     __shared__ double col[K + 1];
     __shared__ double gcs[K], gsn[K];
-    __shared__ int again;
+    __shared__ double fin[2];   // ||Vhat_{k+1}|| if this pass ends the step; 1 if the step needs another pass
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int j = wid; j <= k + 1; j += 4) {
         double s = 0;
@@ -1251,13 +1254,75 @@ __global__ __launch_bounds__(256) void k_gm_axpy_fin(int64_t n, int k, int nbx, 
         red[j] = j <= k ? h : red[j];   // rows 0..k now hold h_j; row k + 1 keeps <w, w>
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        double p = 0;
+        for (int j = 0; j <= k; ++j) p += red[j] * red[j];
+        const double ww = red[k + 1];
+        const double d = ww - p;
+        fin[0] = d > 0 ? sqrt(d) : 0.0;
+        fin[1] = (second || p <= st->reorth_frac * ww) ? 0.0 : 1.0;   // also taken on a non-finite value
+    }
+    __syncthreads();
+    const double hn = fin[0];
+    const bool again = fin[1] != 0.0;
+    using VT = typename V4<T>::type;
     T *Vn = V + (int64_t)(k + 1) * ldv;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        double wi = to_d(w[i]);
+    const bool start = fz.z && !again;
+    const double sc = hn > 0 ? 1.0 / hn : 0.0;   // s_{k+1}, as block 0 stores it
+    double theta = 1.0, ca, cb;
+    if (start && fz.degree > 1) cheb_coef(*fz.lamF, fz.ratio, 0, theta, ca, cb);
+    const int64_t nv = n >> 2;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        const VT wv = reinterpret_cast<const VT *>(w)[v];
+        double a[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a[c] = to_d(wv.v[c]);
 #pragma unroll
         for (int j = 0; j < K; ++j)
-            if (j <= k) wi -= coef[j] * to_d(V[j * ldv + i]);
-        Vn[i] = (T)wi;
+            if (j <= k) {
+                const VT x = reinterpret_cast<const VT *>(V + j * ldv)[v];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) a[c] -= coef[j] * to_d(x.v[c]);
+            }
+        VT o;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o.v[c] = (T)a[c];
+        reinterpret_cast<VT *>(Vn)[v] = o;
+        if (start) {
+            const double r0 = to_d(o.v[0]) * sc, r1 = to_d(o.v[1]) * sc, r2 = to_d(o.v[2]) * sc;
+            double fi[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) fi[q] = to_d(fz.Finv[q * nv + v]);
+            double y0 = fi[0] * r0 + fi[1] * r1 + fi[2] * r2;
+            double y1 = fi[3] * r0 + fi[4] * r1 + fi[5] * r2;
+            double y2 = fi[6] * r0 + fi[7] * r1 + fi[8] * r2;
+            VT zv;
+            if (fz.degree > 1) {
+                y0 /= theta;
+                y1 /= theta;
+                y2 /= theta;
+                VT f, d;
+                f.v[0] = (T)r0;
+                f.v[1] = (T)r1;
+                f.v[2] = (T)r2;
+                f.v[3] = T(0);
+                reinterpret_cast<VT *>(fz.fr)[v] = f;
+                d.v[0] = (T)y0;
+                d.v[1] = (T)y1;
+                d.v[2] = (T)y2;
+                d.v[3] = T(0);
+                reinterpret_cast<VT *>(fz.fd)[v] = d;
+                zv.v[0] = d.v[0];
+                zv.v[1] = d.v[1];
+                zv.v[2] = d.v[2];
+            } else {
+                zv.v[0] = (T)y0;
+                zv.v[1] = (T)y1;
+                zv.v[2] = (T)y2;
+            }
+            zv.v[3] = (T)(to_d(o.v[3]) * sc);
+            reinterpret_cast<VT *>(fz.z)[v] = zv;
+        }
     }
     if (blockIdx.x != 0) return;
     // ---- block 0: Hessenberg column k, second-pass decision, Givens update
@@ -1273,23 +1338,12 @@ __global__ __launch_bounds__(256) void k_gm_axpy_fin(int64_t n, int k, int nbx, 
             gsn[j] = st->sn[j];
         }
     }
-    if (threadIdx.x == 0) {
-        double p = 0;
-        for (int j = 0; j <= k; ++j) p += red[j] * red[j];
-        const double ww = red[k + 1];
-        int a = 0;
-        if (!second) {
-            a = (p <= st->reorth_frac * ww) ? 0 : 1;   // also taken on a non-finite value
-            st->reorth = a;
-            st->n_reorth += a;
-        }
-        const double d = ww - p;
-        col[k + 1] = d > 0 ? sqrt(d) : 0.0;
-        again = a;
+    if (threadIdx.x == 0 && !second) {
+        st->reorth = again ? 1 : 0;
+        st->n_reorth += again ? 1 : 0;
     }
     __syncthreads();
     if (again || threadIdx.x != 0) return;
-    const double hn = col[k + 1];
     for (int j = 0; j < k; ++j) {
         const double t = gcs[j] * col[j] + gsn[j] * col[j + 1];
         col[j + 1] = -gsn[j] * col[j] + gcs[j] * col[j + 1];
@@ -1306,7 +1360,7 @@ __global__ __launch_bounds__(256) void k_gm_axpy_fin(int64_t n, int k, int nbx, 
     const double gk = st->g[k];
     st->g[k + 1] = -sn * gk;
     st->g[k] = c * gk;
-    st->s[k + 1] = hn > 0 ? 1.0 / hn : 0.0;
+    st->s[k + 1] = sc;
     const double res = fabs(sn * gk);
     st->resid = res;
     st->kused = k + 1;
@@ -1335,19 +1389,23 @@ __global__ __launch_bounds__(256) void k_gm_axpy_fin(int64_t n, int k, int nbx, 
 // reorthogonalisation; the device decides, the second-pass kernels return at
 // once otherwise), then Vhat_{k+1} and the Givens update.
 template <typename T>
-void launch_gm_orth(int64_t n, int k, T *V, int64_t ldv, T *w, GmState *st, double *partial, hipStream_t s)
+void launch_gm_orth(int64_t n, int k, T *V, int64_t ldv, T *w, GmState *st, double *partial, hipStream_t s,
+                    const FzStart<T> *fz)
 {
     const int nbx = (int)((n + kDotChunk - 1) / kDotChunk);
-    const unsigned nbv = vec_blocks(n);
+    const unsigned nbv = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n / 4 + 255) / 256, 4096));
     const dim3 gd(nbx, k + 2), gv(nbv);
     T *vn = V + (int64_t)(k + 1) * ldv;
+    const FzStart<T> f = fz ? *fz : FzStart<T>();
     hipLaunchKernelGGL((k_gm_dot<T>), gd, dim3(256), 0, s, n, V, ldv, w, partial, st, k + 1, 0);
-    LX_GM_K_DISPATCH(k_gm_axpy_fin, T, gv, n, k, nbx, V, ldv, w, st, partial, 0);
+    LX_GM_K_DISPATCH(k_gm_axpy_fin, T, gv, n, k, nbx, V, ldv, w, st, partial, 0, f);
     hipLaunchKernelGGL((k_gm_dot<T>), gd, dim3(256), 0, s, n, V, ldv, vn, partial, st, k + 1, 1);
-    LX_GM_K_DISPATCH(k_gm_axpy_fin, T, gv, n, k, nbx, V, ldv, vn, st, partial, 1);
+    LX_GM_K_DISPATCH(k_gm_axpy_fin, T, gv, n, k, nbx, V, ldv, vn, st, partial, 1, f);
 }
-template void launch_gm_orth<double>(int64_t, int, double *, int64_t, double *, GmState *, double *, hipStream_t);
-template void launch_gm_orth<float>(int64_t, int, float *, int64_t, float *, GmState *, double *, hipStream_t);
+template void launch_gm_orth<double>(int64_t, int, double *, int64_t, double *, GmState *, double *, hipStream_t,
+                                     const FzStart<double> *);
+template void launch_gm_orth<float>(int64_t, int, float *, int64_t, float *, GmState *, double *, hipStream_t,
+                                    const FzStart<float> *);
 
 // y = H^{-1} g over the kused columns: back substitution by one wavefront, the
 // triangle staged in LDS; lane j keeps g_j minus the terms of the y found so

@@ -839,14 +839,19 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
         int pending = -1;
         for (int k = 0; k < kmax; ++k) {
             T *zk = Z + k * ld;
-            if (solver.precond == LX_PC_AMG)
+            const bool amg = solver.precond == LX_PC_AMG;
+            // from the second step on, the Gram-Schmidt pass that formed V_k already
+            // started the velocity block on it
+            if (amg)
                 launch_simple_amg_apply<T>(view<T>(), SP.Finv, SP.Dinv, Ops<T>::amg(this), V + k * ld, &d_st->s[k],
-                                           zk, &d_st->done, stream);
+                                           zk, &d_st->done, stream, k > 0);
             else
                 launch_simple_apply<T>(P, SP, V + k * ld, &d_st->s[k], zk, &d_st->done, stream);
             auto *tm = timer_begin(0, k, false);
             spmv<T>(zk, w, &d_st->done, tm);
-            launch_gm_orth<T>(N, k, V, ld, w, d_st, d_partial, stream);
+            FzStart<T> fz;
+            if (amg) fz = amg_fz_start(Ops<T>::amg(this), SP.Finv, Z + (k + 1) * ld);
+            launch_gm_orth<T>(N, k, V, ld, w, d_st, d_partial, stream, amg && k + 1 < kmax ? &fz : nullptr);
             if (pending >= 0) {
                 LX_HIP(hipEventSynchronize(ev_chk[pending & 1]));
                 const bool stop = h_flag[pending & 1] != 0;
