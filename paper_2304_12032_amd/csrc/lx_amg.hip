@@ -499,14 +499,15 @@ __global__ __launch_bounds__(256) void k_fcheb(RowPattern P, const T *__restrict
                                                T *__restrict__ dnext, const double *lamF, double ratio, int step,
                                                const int32_t *done)
 {
-    if (done && *done) return;
     const int64_t row = (grid_block(P.remap) * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= P.nv) return;
+    const int32_t beg = P.rowptr[row], end = P.rowptr[row + 1];
+    if (done_with(done, end)) return;
     const int64_t nb = P.nblk, nv = P.nv;
     using V = typename V4<T>::type;
     double t0 = 0, t1 = 0, t2 = 0;
-    for (int32_t k = P.rowptr[row] + lane; k < P.rowptr[row + 1]; k += LPR) {
+    for (int32_t k = beg + lane; k < end; k += LPR) {
         const V xv = reinterpret_cast<const V *>(dcur)[P.col[k]];
         const double x0 = xv.v[0], x1 = xv.v[1], x2 = xv.v[2];
         double a[9];
@@ -552,13 +553,14 @@ template <typename T, int LPR>
 __global__ __launch_bounds__(256) void k_zp_amg(SimpleView<T> V, const T *__restrict__ z, AmgLevel<T> L,
                                                 const double *lam, double ratio, int smooth, const int32_t *done)
 {
-    if (done && *done) return;
     const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= V.np) return;
+    const int32_t beg = V.bptr[row], end = V.bptr[row + 1];
+    if (done_with(done, end)) return;
     using VT = typename V4<T>::type;
     double acc = 0;
-    for (int32_t k = V.bptr[row] + lane; k < V.bptr[row + 1]; k += LPR) {
+    for (int32_t k = beg + lane; k < end; k += LPR) {
         const VT zj = reinterpret_cast<const VT *>(z)[V.bcol[k]];
         acc += (double)V.Bv[k] * zj.v[0] + (double)V.Bv[V.bs + k] * zj.v[1] + (double)V.Bv[2 * V.bs + k] * zj.v[2];
     }
@@ -581,13 +583,14 @@ template <typename T, int LPR>
 __global__ __launch_bounds__(256) void k_xu_amg(SimpleView<T> V, const T *__restrict__ Dinv, T *__restrict__ z,
                                                 const T *__restrict__ p, const int32_t *done)
 {
-    if (done && *done) return;
     const int64_t row = (grid_block(V.Fp.remap) * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= V.nu) return;
+    const int32_t beg = V.gptr[row], end = V.gptr[row + 1];
+    if (done_with(done, end)) return;
     const int64_t nu = V.nu;
     double a0 = 0, a1 = 0, a2 = 0;
-    for (int32_t k = V.gptr[row] + lane; k < V.gptr[row + 1]; k += LPR) {
+    for (int32_t k = beg + lane; k < end; k += LPR) {
         const double pj = p[V.gcol[k]];
         a0 += (double)V.Gv[k] * pj;
         a1 += (double)V.Gv[V.gs + k] * pj;
@@ -613,12 +616,13 @@ __global__ __launch_bounds__(256) void k_amg_pre(AmgLevel<T> L, const T *__restr
                                                  const int32_t *__restrict__ mptr, const int32_t *__restrict__ mem,
                                                  const double *lam, double ratio, const int32_t *done)
 {
-    if (done && *done) return;
     const int64_t i = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (i >= L.n) return;
+    const int32_t beg = mptr[i], end = mptr[i + 1];
+    if (done_with(done, end)) return;
     double s = 0;
-    for (int32_t q = mptr[i] + lane; q < mptr[i + 1]; q += LPR) s += (double)fres[mem[q]];
+    for (int32_t q = beg + lane; q < end; q += LPR) s += (double)fres[mem[q]];
     s = group_sum<double, LPR>(s);
     if (lane != 0) return;
     double theta, a, b;
@@ -636,12 +640,13 @@ __global__ __launch_bounds__(256) void k_amg_cheb(AmgLevel<T> L, T *__restrict__
                                                   T *__restrict__ dnext, const double *lam, double ratio, int step,
                                                   const int32_t *done)
 {
-    if (done && *done) return;
     const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= L.n) return;
+    const int32_t beg = L.rowptr[row], end = L.rowptr[row + 1];
+    if (done_with(done, end)) return;
     double q = 0;
-    for (int32_t k = L.rowptr[row] + lane; k < L.rowptr[row + 1]; k += LPR)
+    for (int32_t k = beg + lane; k < end; k += LPR)
         q += (double)L.val[k] * (double)dcur[L.col[k]];
     q = group_sum<double, LPR>(q);
     if (lane != 0) return;
@@ -666,12 +671,13 @@ __global__ __launch_bounds__(256) void k_amg_cheb_prolong(AmgLevel<T> L, T *__re
                                                           T *__restrict__ xp, const int32_t *__restrict__ fmptr,
                                                           const int32_t *__restrict__ fmem)
 {
-    if (done && *done) return;
     const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= L.n) return;
+    const int32_t beg = L.rowptr[row], end = L.rowptr[row + 1];
+    if (done_with(done, end)) return;
     double q = 0;
-    for (int32_t k = L.rowptr[row] + lane; k < L.rowptr[row + 1]; k += LPR)
+    for (int32_t k = beg + lane; k < end; k += LPR)
         q += (double)L.val[k] * (double)dcur[L.col[k]];
     q = group_sum<double, LPR>(q);   // every lane of the group holds the sum
     double theta, a, b;
@@ -693,12 +699,13 @@ __global__ __launch_bounds__(256) void k_amg_cheb_prolong(AmgLevel<T> L, T *__re
 template <typename T, int LPR>
 __global__ __launch_bounds__(256) void k_amg_resid(AmgLevel<T> L, const T *__restrict__ x, const int32_t *done)
 {
-    if (done && *done) return;
     const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= L.n) return;
+    const int32_t beg = L.rowptr[row], end = L.rowptr[row + 1];
+    if (done_with(done, end)) return;
     double q = 0;
-    for (int32_t k = L.rowptr[row] + lane; k < L.rowptr[row + 1]; k += LPR)
+    for (int32_t k = beg + lane; k < end; k += LPR)
         q += (double)L.val[k] * (double)x[L.col[k]];
     q = group_sum<double, LPR>(q);
     if (lane == 0) L.res[row] = (T)((double)L.r[row] - q);
@@ -710,12 +717,13 @@ template <typename T, int LPR>
 __global__ __launch_bounds__(256) void k_amg_post0(AmgLevel<T> L, const T *__restrict__ e, const double *lam,
                                                    double ratio, const int32_t *done)
 {
-    if (done && *done) return;
     const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= L.n) return;
+    const int32_t beg = L.rowptr[row], end = L.rowptr[row + 1];
+    if (done_with(done, end)) return;
     double q = 0;
-    for (int32_t k = L.rowptr[row] + lane; k < L.rowptr[row + 1]; k += LPR) {
+    for (int32_t k = beg + lane; k < end; k += LPR) {
         const int32_t j = L.col[k];
         q += (double)L.val[k] * ((double)L.x0[j] + (double)e[L.agg[j]]);
     }
@@ -798,14 +806,14 @@ __global__ __launch_bounds__(256) void k_amg_rowinfo_sell(AmgLevel<T> L, double 
 constexpr int kSellWaves = 4;
 
 template <typename T, bool D16, int SW, typename X>
-__device__ __forceinline__ double sell_slice_dot(const AmgLevel<T> &L, int64_t slice, X xval, double (*part)[64])
+__device__ __forceinline__ double sell_slice_dot(const AmgLevel<T> &L, int64_t slice, int64_t sbase, int w, X xval,
+                                                 double (*part)[64])
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t row = slice * 64 + lane;
     double q = 0;
     if (row < L.n) {
-        const int64_t base = L.soff[slice] + lane;
-        const int w = L.swid[slice];
+        const int64_t base = sbase + lane;
 #pragma unroll 4
         for (int j = wv; j < w; j += SW) {
             const int64_t p = base + 64 * (int64_t)j;
@@ -826,10 +834,13 @@ __global__ __launch_bounds__(64 * SW) void k_amg_cheb_sell(AmgLevel<T> L, T *__r
                                                             const double *lam, double ratio, int step,
                                                             const int32_t *done)
 {
-    if (done && *done) return;
     __shared__ double part[SW][64];
     const int64_t slice = xcd_block();
-    const double q = sell_slice_dot<T, D16, SW>(L, slice, [&](int32_t c) { return (double)dcur[c]; }, part);
+    const int64_t sbase = L.soff[slice];
+    const int sw = L.swid[slice];
+    if (done_with(done, sw + (int32_t)sbase)) return;
+    const double q =
+        sell_slice_dot<T, D16, SW>(L, slice, sbase, sw, [&](int32_t c) { return (double)dcur[c]; }, part);
     const int64_t row = slice * 64 + (threadIdx.x & 63);
     if (threadIdx.x >= 64 || row >= L.n) return;
     double theta, a, b;
@@ -845,10 +856,12 @@ template <typename T, bool D16, int SW>
 __global__ __launch_bounds__(64 * SW) void k_amg_resid_sell(AmgLevel<T> L, const T *__restrict__ x,
                                                              const int32_t *done)
 {
-    if (done && *done) return;
     __shared__ double part[SW][64];
     const int64_t slice = xcd_block();
-    const double q = sell_slice_dot<T, D16, SW>(L, slice, [&](int32_t c) { return (double)x[c]; }, part);
+    const int64_t sbase = L.soff[slice];
+    const int sw = L.swid[slice];
+    if (done_with(done, sw + (int32_t)sbase)) return;
+    const double q = sell_slice_dot<T, D16, SW>(L, slice, sbase, sw, [&](int32_t c) { return (double)x[c]; }, part);
     const int64_t row = slice * 64 + (threadIdx.x & 63);
     if (threadIdx.x >= 64 || row >= L.n) return;
     L.res[row] = (T)((double)L.r[row] - q);
@@ -858,13 +871,15 @@ template <typename T, bool D16, int SW>
 __global__ __launch_bounds__(64 * SW) void k_amg_post0_sell(AmgLevel<T> L, const T *__restrict__ e,
                                                              const double *lam, double ratio, const int32_t *done)
 {
-    if (done && *done) return;
     __shared__ double part[SW][64];
     const int64_t slice = xcd_block();
+    const int64_t sbase = L.soff[slice];
+    const int sw = L.swid[slice];
+    if (done_with(done, sw + (int32_t)sbase)) return;
     const T *x0 = L.x0;
     const int32_t *agg = L.agg;
     const double q = sell_slice_dot<T, D16, SW>(
-        L, slice, [&](int32_t c) { return (double)x0[c] + (double)e[agg[c]]; }, part);
+        L, slice, sbase, sw, [&](int32_t c) { return (double)x0[c] + (double)e[agg[c]]; }, part);
     const int64_t row = slice * 64 + (threadIdx.x & 63);
     if (threadIdx.x >= 64 || row >= L.n) return;
     double theta, a, b;
@@ -882,10 +897,13 @@ template <typename T, bool D16, int SW>
 __global__ __launch_bounds__(64 * SW) void k_amg_post0_sell_xp(AmgLevel<T> L, const T *__restrict__ xp,
                                                                const double *lam, double ratio, const int32_t *done)
 {
-    if (done && *done) return;
     __shared__ double part[SW][64];
     const int64_t slice = xcd_block();
-    const double q = sell_slice_dot<T, D16, SW>(L, slice, [&](int32_t c) { return (double)xp[c]; }, part);
+    const int64_t sbase = L.soff[slice];
+    const int sw = L.swid[slice];
+    if (done_with(done, sw + (int32_t)sbase)) return;
+    const double q =
+        sell_slice_dot<T, D16, SW>(L, slice, sbase, sw, [&](int32_t c) { return (double)xp[c]; }, part);
     const int64_t row = slice * 64 + (threadIdx.x & 63);
     if (threadIdx.x >= 64 || row >= L.n) return;
     double theta, a, b;

@@ -19,6 +19,15 @@ __device__ inline float lx_sqrt(float x) { return sqrtf(x); }
 __device__ inline void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 __device__ inline void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 
+// True if the device's done flag is set.  dep is a value the caller has just
+// loaded: testing it in the same expression keeps that load ahead of the
+// branch, so the flag's memory latency overlaps the load's instead of adding to
+// it at the start of every kernel.
+__device__ __forceinline__ bool done_with(const int32_t *done, int32_t dep)
+{
+    return done != nullptr && ((done[0] != 0) & (dep != INT32_MIN));
+}
+
 // Workgroup index with the grid split into 8 contiguous ranges, one per die
 // (XCD): the dispatcher hands workgroups to the dies round-robin, so
 // workgroup w runs on die w % 8, and range w % 8 keeps rows that share

@@ -1045,12 +1045,12 @@ template <typename T, int LPR>
 __global__ __launch_bounds__(256) void k_spmv(RowPattern P, const T *__restrict__ val, const T *__restrict__ x,
                                               T *__restrict__ y, const int32_t *done)
 {
-    if (done && *done) return;
     const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= P.nv) return;
     const int64_t nb = P.nblk;
     const int32_t beg = P.rowptr[row], end = P.rowptr[row + 1];
+    if (done_with(done, end)) return;
     using V = typename V4<T>::type;
     // products of two T values are exact in FP64; sums are accumulated in FP64
     double y0 = 0, y1 = 0, y2 = 0, y3 = 0;
