@@ -95,7 +95,7 @@ def spmv_bytes_p2(q, s):
 
 def spmv_source_hash():
     """SHA-256 (first 16 hex digits) of the k_spmv kernel's source text and of the
-    workgroup remap it calls."""
+    device helpers it calls (workgroup remap, done-flag test)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2304_12032_amd", "csrc")
     src = open(os.path.join(csrc, "lx_kernels.hip")).read()
@@ -103,9 +103,11 @@ def spmv_source_hash():
     a = src.rfind("template", 0, a)
     b = src.index("\n}\n", a) + 3
     dev = open(os.path.join(csrc, "lx_device.h")).read()
-    c = dev.index("__device__ inline int64_t xcd_block()")
-    d = dev.index("\n}\n", c) + 3
-    return hashlib.sha256((src[a:b] + dev[c:d]).encode()).hexdigest()[:16]
+    text = src[a:b]
+    for head in ("__device__ __forceinline__ bool done_with(", "__device__ inline int64_t xcd_block()"):
+        c = dev.index(head)
+        text += dev[c:dev.index("\n}\n", c) + 3]
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def spmv_traffic():
