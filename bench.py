@@ -244,7 +244,7 @@ def step_bound(q, prec, iters, ir_iters, args):
     setup = (nv * (9 * s + 4) + nv * 12 * s                                    # nodal inverses
              + 2 * nblk * (3 * s + 4) + nblk * (s + 4) + 3 * nv * s + nnz[0] * (s + 4)   # S~ formation
              + sum(nnz[l] * (s + 4) + nnz[l + 1] * s + nnz[l] * s for l in range(dense))  # Galerkin sums, bounds
-             + 6 * (nblk * (9 * s + 4) + nv * (4 + 13 * s)))                  # power iterations on F
+             + 2 * (nblk * (9 * s + 4) + nv * (4 + 13 * s)))                  # power iterations on F
     # FP64 residuals: connectivity, the vertex data, each element's contributions written and read once
     # (r and b at the first evaluation of a step, r alone afterwards) and the summed rows
     vin = nv * (24 + 24 + 32 * hist + 32)

@@ -114,7 +114,7 @@ struct Amg {
     double ratio = 30.0;                // smoothing interval [lam / ratio, lam]
     int f_degree = 3;                   // Chebyshev degree on F (1: plain block Jacobi)
     double f_ratio = 10.0;
-    int f_pow_first = 16, f_pow_iters = 6;   // power iterations for the bound of F~^{-1} F
+    int f_pow_first = 16, f_pow_iters = 2;   // power iterations for the bound of F~^{-1} F (first step; later, warm)
     double f_safety = 1.15;
     bool f_warm = false;                // fv holds the last power-iteration vector
     T *fr = nullptr, *fd0 = nullptr, *fd1 = nullptr, *fv = nullptr;   // [nv][4]
