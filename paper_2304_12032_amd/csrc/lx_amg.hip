@@ -361,6 +361,87 @@ __global__ __launch_bounds__(1024) void k_dense_gj(int nc, double *aug)
     }
 }
 
+// The same elimination for a small dense level (nc <= kGjLdsMax), held in LDS:
+// wavefront 0 finds the pivot (largest magnitude, lowest row on ties) and the
+// row factors by shuffles, then the block swaps and scales the pivot row and
+// eliminates, with three barriers per column instead of a tree reduction and
+// global-memory passes.  Same operations and order of each entry's update as
+// k_dense_gj, so the inverse is the same.
+constexpr int kGjLdsMax = 48;
+
+__global__ __launch_bounds__(1024) void k_dense_gj_lds(int nc, double *aug)
+{
+    __shared__ double a[kGjLdsMax * 2 * kGjLdsMax];
+    __shared__ double fac[kGjLdsMax];
+    __shared__ double red[16];
+    __shared__ int s_pr;
+    __shared__ double s_inv;
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wid = tid >> 6;
+    const int w = 2 * nc;
+    double m = 0;
+    for (int q = tid; q < nc * w; q += nth) {
+        const double v = aug[q];
+        a[q] = v;
+        if (q % w < nc) m = fmax(m, fabs(v));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if (lane == 0) red[wid] = m;
+    __syncthreads();
+    double mx = 0;
+    for (int i = 0; i < (nth >> 6); ++i) mx = fmax(mx, red[i]);
+    const double tiny = 1e-14 * mx;
+    for (int p = 0; p < nc; ++p) {
+        if (wid == 0) {
+            // pivot: the largest |a[r][p]|, r >= p, lowest r on ties
+            double bv = (lane >= p && lane < nc) ? fabs(a[lane * w + p]) : -1.0;
+            int bi = (lane >= p && lane < nc) ? lane : nc;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(bv, off);
+                const int oi = __shfl_xor(bi, off);
+                if (ov > bv || (ov == bv && oi < bi)) {
+                    bv = ov;
+                    bi = oi;
+                }
+            }
+            const int pr = bi;
+            const bool ok = bv > tiny;
+            // factors of the rows after the swap: row r holds old row (r == p ? pr : r == pr ? p : r)
+            if (lane < nc) {
+                const int src = lane == p ? pr : (lane == pr ? p : lane);
+                fac[lane] = (lane == p || !ok) ? 0.0 : a[src * w + p];
+            }
+            if (lane == 0) {
+                s_pr = ok ? pr : -1;
+                s_inv = ok ? 1.0 / a[pr * w + p] : 0.0;
+            }
+        }
+        __syncthreads();
+        const int pr = s_pr;
+        if (pr < 0) {
+            for (int c = tid; c < w; c += nth) a[p * w + c] = 0.0;
+            __syncthreads();
+            continue;
+        }
+        const double inv = s_inv;
+        for (int c = tid; c < w; c += nth) {
+            const double vp = a[p * w + c], vr = a[pr * w + c];
+            a[p * w + c] = vr * inv;
+            if (pr != p) a[pr * w + c] = vp;
+        }
+        __syncthreads();
+        // columns left of p in the left half are already eliminated in row p
+        const int c0 = p, wc = w - c0;
+        for (int q = tid; q < nc * wc; q += nth) {
+            const int r = q / wc, c = c0 + q % wc;
+            if (r != p) a[r * w + c] -= fac[r] * a[p * w + c];
+        }
+        __syncthreads();
+    }
+    for (int q = tid; q < nc * w; q += nth) aug[q] = a[q];
+}
+
 // One power step w = F~^{-1} F v / ||v|| (velocity block, [nv][4] vectors),
 // ||v||^2 read from lam[slot_in]; partial[block] = the block's part of ||w||^2.
 // v = null: the start vector of +-1 entries from a multiplicative hash of the
@@ -1328,7 +1409,10 @@ void launch_amg_setup(const SimpleView<T> &V, const T *Finv, const T *Dinv, Amg<
     hipLaunchKernelGGL(k_dense_init, dim3(flat_grid(2 * A.nc * A.nc)), dim3(256), 0, s, A.nc, A.dense);
     hipLaunchKernelGGL((k_dense_scatter<T>), dim3(flat_grid(D.nnz)), dim3(256), 0, s, D.nnz, A.nc, A.crow, D.col,
                        D.val, A.dense);
-    hipLaunchKernelGGL(k_dense_gj, dim3(1), dim3(1024), 0, s, (int)A.nc, A.dense);
+    if (A.nc <= kGjLdsMax)
+        hipLaunchKernelGGL(k_dense_gj_lds, dim3(1), dim3(1024), 0, s, (int)A.nc, A.dense);
+    else
+        hipLaunchKernelGGL(k_dense_gj, dim3(1), dim3(1024), 0, s, (int)A.nc, A.dense);
     if (A.f_degree > 1) {
         // power iterations alternate fv -> fd1 -> fv; an even count ends in fv
         const int iters = A.f_warm ? A.f_pow_iters : A.f_pow_first;
