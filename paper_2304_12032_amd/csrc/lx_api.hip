@@ -102,6 +102,8 @@ extern "C" lx_status lx_sim_set_state(lx_sim *s, int32_t level, const double *u,
     }
     LX_HIP(hipStreamSynchronize(s->stream));
     s->nlev = std::max(s->nlev, level + 1);
+    // guess history: only levels the caller can set count, stale deeper ones are dropped
+    s->nhist = std::min(std::max(s->nhist, level + 1), (int)s->prob.bdf_order);
     return LX_OK;
 }
 

@@ -134,8 +134,9 @@ void launch_norm(int64_t n, const T *x, GmState *st, double rtol, double *partia
 // vector utilities
 template <typename T>
 void launch_fill(int64_t n, T *x, T v, hipStream_t s);
+// x = g0 h0 + g1 h1 + g2 h2 + g3 h3 (null levels left out)
 void launch_extrapolate(int64_t n, double *x, const double *h0, const double *h1, const double *h2, double g0,
-                        double g1, double g2, hipStream_t s);
+                        double g1, double g2, hipStream_t s, const double *h3 = nullptr, double g3 = 0.0);
 template <typename TD, typename TS>
 void launch_axpy(int64_t n, TD *y, const TS *x, const double *scale_ptr, double scale, hipStream_t s);
 // dst = (TD)(src * factor)

@@ -1525,22 +1525,23 @@ template void launch_axpy<float, float>(int64_t, float *, const float *, const d
 template void launch_axpy<double, float>(int64_t, double *, const float *, const double *, double, hipStream_t);
 
 // x = g0 h0 + g1 h1 + g2 h2 (h1, h2 may be null when their weight is 0)
-__global__ void k_extrapolate(int64_t n, double *x, const double *h0, const double *h1, const double *h2, double g0,
-                              double g1, double g2)
+__global__ void k_extrapolate(int64_t n, double *x, const double *h0, const double *h1, const double *h2,
+                              const double *h3, double g0, double g1, double g2, double g3)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double v = g0 * h0[i];
         if (h1) v += g1 * h1[i];
         if (h2) v += g2 * h2[i];
+        if (h3) v += g3 * h3[i];
         x[i] = v;
     }
 }
 
 void launch_extrapolate(int64_t n, double *x, const double *h0, const double *h1, const double *h2, double g0,
-                        double g1, double g2, hipStream_t s)
+                        double g1, double g2, hipStream_t s, const double *h3, double g3)
 {
     unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_extrapolate, dim3(g), dim3(256), 0, s, n, x, h0, h1, h2, g0, g1, g2);
+    hipLaunchKernelGGL(k_extrapolate, dim3(g), dim3(256), 0, s, n, x, h0, h1, h2, h3, g0, g1, g2, g3);
 }
 
 template <typename TD, typename TS>

@@ -125,6 +125,7 @@ struct Sim {
 
     double t = 0;
     int nlev = 0;
+    int nhist = 0;   // valid solution levels in d_hist (up to max(bdf_order, 4); the guess may use four)
     int64_t step_index = 0;
 
     ~Sim();

@@ -277,7 +277,8 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         ALLOC(d_dg, sizeof(double) * 3 * n_dir);
     }
     const int L = prob.bdf_order;
-    for (int l = 0; l < L; ++l) ALLOC(d_hist[l], sizeof(double) * N);
+    // more levels than BDF2 needs: the initial guess extrapolates up to four solutions
+    for (int l = 0; l < std::max(L, 4); ++l) ALLOC(d_hist[l], sizeof(double) * N);
     ALLOC(d_xs, sizeof(double) * N);
     if (prob.forcing) ALLOC(d_f, sizeof(double) * 3 * nu);
     if (prob.ale) {
@@ -408,7 +409,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         if (b.d_faces)
             LX_HIP(hipMemcpyAsync(b.d_faces, b.h_faces.data(), sizeof(int32_t) * b.h_faces.size(),
                                   hipMemcpyHostToDevice, stream));
-    for (int l = 0; l < L; ++l) launch_fill<double>(N, d_hist[l], 0.0, stream);
+    for (int l = 0; l < std::max(L, 4); ++l) launch_fill<double>(N, d_hist[l], 0.0, stream);
     launch_fill<double>(N, d_xs, 0.0, stream);
     if (d_f) launch_fill<double>(3 * nu, d_f, 0.0, stream);
     if (prob.ale) {
@@ -1127,14 +1128,29 @@ lx_status Sim::step(lx_step_stats *out)
     lx_status st = build_system(t1, C, S);
     if (st != LX_OK) return st;
     LX_HIP(hipEventRecord(ev_asm1, stream));
-    // initial guess: the extrapolation of the history with the step's BDF
-    // weights (u_EXT, p_EXT; LXNS_X0=prev: the previous solution), with the new
-    // Dirichlet values
+    // initial guess, with the new Dirichlet values: the polynomial through the
+    // last four (three) solutions evaluated at t^{n+1} once that many exist,
+    // before then the extrapolation with the step's BDF weights (u_EXT, p_EXT).
+    // The guess sets only where GMRES starts; it stops on ||b - A x|| <= rtol ||b||
+    // whatever the start. LXNS_X0_ORDER=2|3 caps the levels used, LXNS_X0=prev
+    // starts from the previous solution.
     static const bool extrap = [] {
         const char *e = getenv("LXNS_X0");
         return !(e && strcmp(e, "prev") == 0);
     }();
-    if (extrap)
+    static const int xorder = [] {
+        const char *e = getenv("LXNS_X0_ORDER");
+        const int k = e ? atoi(e) : 4;
+        return k >= 2 && k <= 4 ? k : 4;
+    }();
+    const int K = std::min(xorder, nhist);
+    if (extrap && K == 4)
+        // the cubic through the last four solutions at t^{n+1} (constant step)
+        launch_extrapolate(N, d_xs, d_hist[0], d_hist[1], d_hist[2], 4.0, -6.0, 4.0, stream, d_hist[3], -1.0);
+    else if (extrap && K == 3)
+        // the quadratic through the last three solutions at t^{n+1} (constant step)
+        launch_extrapolate(N, d_xs, d_hist[0], d_hist[1], d_hist[2], 3.0, -3.0, 1.0, stream);
+    else if (extrap)
         launch_extrapolate(N, d_xs, d_hist[0], C.gamma[1] != 0 ? d_hist[1] : nullptr,
                            C.gamma[2] != 0 ? d_hist[2] : nullptr, C.gamma[0], C.gamma[1], C.gamma[2], stream);
     else
@@ -1204,12 +1220,14 @@ lx_status Sim::step(lx_step_stats *out)
         return fail(LX_ENOCONV, "step did not converge: rel. residual %.3e after %d iterations", S.rel_residual,
                     S.gmres_iters);
     // commit: rotate history (u^n -> u^{n-1}, ...) and advance time
-    double *oldest = d_hist[L - 1];
-    for (int l = L - 1; l > 0; --l) d_hist[l] = d_hist[l - 1];
+    const int Lh = std::max(L, 4);
+    double *oldest = d_hist[Lh - 1];
+    for (int l = Lh - 1; l > 0; --l) d_hist[l] = d_hist[l - 1];
     d_hist[0] = d_xs;
     d_xs = oldest;
     if (prob.ale) ale_commit();
     nlev = std::min(std::max(nlev, 1) + 1, L);
+    nhist = std::min(nhist + 1, Lh);
     t = t1;
     ++step_index;
     return LX_OK;
