@@ -134,6 +134,13 @@ void launch_norm(int64_t n, const T *x, GmState *st, double rtol, double *partia
 // vector utilities
 template <typename T>
 void launch_fill(int64_t n, T *x, T v, hipStream_t s);
+// out[0..2] = squared 2-norm errors of the BDF (gamma), quadratic (nk >= 2) and
+// cubic (nk >= 3) extrapolations of h[0..3] against x; all four h are read
+// (allocated, finite); partial: 3 * 256 doubles.
+constexpr int kGuessErrPartial = 3 * 256;
+void launch_guess_err(int64_t n, int nk, const double *x, const double *const *h, const double *gamma,
+                      double *partial, double *out, hipStream_t s);
+
 // x = g0 h0 + g1 h1 + g2 h2 + g3 h3 (null levels left out)
 void launch_extrapolate(int64_t n, double *x, const double *h0, const double *h1, const double *h2, double g0,
                         double g1, double g2, hipStream_t s, const double *h3 = nullptr, double g3 = 0.0);

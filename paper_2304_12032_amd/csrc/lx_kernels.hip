@@ -1574,4 +1574,67 @@ void launch_set_dirichlet_x(int64_t n_dir, const int32_t *dir_node, const double
                        g, xs);
 }
 
+
+// How well each initial guess would have predicted the solution x just
+// computed from the history h_0..h_3 (newest first): sums of squares of
+// x - (g0 h0 + g1 h1 + g2 h2) (the BDF extrapolation), x - (3h0 - 3h1 + h2)
+// (quadratic, nk >= 2) and x - (4h0 - 6h1 + 4h2 - h3) (cubic, nk >= 3).
+// Per-block partials, then one wave sums them in a fixed order into out[0..2].
+constexpr int kGuessErrBlocks = 256;
+__global__ __launch_bounds__(256) void k_guess_err(int64_t n, int nk, const double *x, const double *h0,
+                                                   const double *h1, const double *h2, const double *h3, double g0,
+                                                   double g1, double g2, double *partial)
+{
+    double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = x[i], a = h0[i], b = h1[i], c = h2[i];
+        const double d0 = v - (g0 * a + g1 * b + g2 * c);
+        e0 += d0 * d0;
+        if (nk >= 2) {
+            const double d1 = v - (3.0 * (a - b) + c);
+            e1 += d1 * d1;
+        }
+        if (nk >= 3) {
+            const double d2 = v - (4.0 * (a + c) - 6.0 * b - h3[i]);
+            e2 += d2 * d2;
+        }
+    }
+    __shared__ double red[3][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) {
+        e0 += __shfl_down(e0, o, 64);
+        e1 += __shfl_down(e1, o, 64);
+        e2 += __shfl_down(e2, o, 64);
+    }
+    if (lane == 0) {
+        red[0][wv] = e0;
+        red[1][wv] = e1;
+        red[2][wv] = e2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int q = threadIdx.x;
+        partial[blockIdx.x * 3 + q] = ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3];
+    }
+}
+
+__global__ void k_guess_err_sum(int nblk, const double *partial, double *out)
+{
+    for (int q = 0; q < 3; ++q) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += 64) v += partial[b * 3 + q];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if (threadIdx.x == 0) out[q] = v;
+    }
+}
+
+void launch_guess_err(int64_t n, int nk, const double *x, const double *const *h, const double *gamma,
+                      double *partial, double *out, hipStream_t s)
+{
+    const int nblk = (int)std::min<int64_t>((n + 255) / 256, kGuessErrBlocks);
+    hipLaunchKernelGGL(k_guess_err, dim3(nblk), dim3(256), 0, s, n, nk, x, h[0], h[1], h[2], h[3], gamma[0],
+                       gamma[1], gamma[2], partial);
+    hipLaunchKernelGGL(k_guess_err_sum, dim3(1), dim3(64), 0, s, nblk, partial, out);
+}
+
 }  // namespace lx

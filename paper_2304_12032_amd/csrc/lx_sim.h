@@ -118,6 +118,9 @@ struct Sim {
     // convergence checks inside an Arnoldi cycle: the done flag copied to pinned
     // host memory behind an event, one check in flight (ping-pong slots)
     int32_t *h_flag = nullptr;
+    double *h_gerr = nullptr;  // pinned: errors of the guess orders on the last step
+    double *d_gerr = nullptr;  // their partial sums, then the three sums
+    int x_order = 4;           // extrapolation order of the next guess (2: BDF weights, 3, 4)
     hipEvent_t ev_chk[2] = {nullptr, nullptr};
     // columns used by cycle c of the last solve of each kind (0: unknown), where
     // the next solve of that kind starts checking every step

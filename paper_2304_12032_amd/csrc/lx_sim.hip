@@ -60,6 +60,7 @@ Sim::~Sim()
     for (void *p : allocs) (void)hipFree(p);
     if (h_st) (void)hipHostFree(h_st);
     if (h_flag) (void)hipHostFree(h_flag);
+    if (h_gerr) (void)hipHostFree(h_gerr);
     for (auto &ev : ev_chk)
         if (ev) (void)hipEventDestroy(ev);
     for (auto &ev : ev_pool) {
@@ -299,6 +300,8 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     ALLOC(d_partial, sizeof(double) * std::max<int64_t>((int64_t)nb_red * 64, gm_partial_size(N)));
     LX_HIP(hipHostMalloc((void **)&h_st, sizeof(GmState), hipHostMallocDefault));
     LX_HIP(hipHostMalloc((void **)&h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
+    LX_HIP(hipHostMalloc((void **)&h_gerr, 4 * sizeof(double), hipHostMallocDefault));
+    ALLOC(d_gerr, sizeof(double) * (kGuessErrPartial + 4));
     for (auto &ev : ev_chk) LX_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     if (p2) {
         // FP64 split system in both precisions (the refinement residual uses it)
@@ -1129,11 +1132,13 @@ lx_status Sim::step(lx_step_stats *out)
     if (st != LX_OK) return st;
     LX_HIP(hipEventRecord(ev_asm1, stream));
     // initial guess, with the new Dirichlet values: the polynomial through the
-    // last four (three) solutions evaluated at t^{n+1} once that many exist,
-    // before then the extrapolation with the step's BDF weights (u_EXT, p_EXT).
-    // The guess sets only where GMRES starts; it stops on ||b - A x|| <= rtol ||b||
-    // whatever the start. LXNS_X0_ORDER=2|3 caps the levels used, LXNS_X0=prev
-    // starts from the previous solution.
+    // last four (three) solutions evaluated at t^{n+1}, or the extrapolation
+    // with the step's BDF weights (u_EXT, p_EXT); x_order picks the one that
+    // best predicted the previous step's solution (measured after each step),
+    // limited by the levels that exist.  The guess sets only where GMRES
+    // starts; it stops on ||b - A x|| <= rtol ||b|| whatever the start.
+    // LXNS_X0_ORDER=2|3 caps the order, LXNS_X0=prev starts from the previous
+    // solution.
     static const bool extrap = [] {
         const char *e = getenv("LXNS_X0");
         return !(e && strcmp(e, "prev") == 0);
@@ -1143,7 +1148,7 @@ lx_status Sim::step(lx_step_stats *out)
         const int k = e ? atoi(e) : 4;
         return k >= 2 && k <= 4 ? k : 4;
     }();
-    const int K = std::min(xorder, nhist);
+    const int K = std::min(std::min(x_order, xorder), nhist);
     if (extrap && K == 4)
         // the cubic through the last four solutions at t^{n+1} (constant step)
         launch_extrapolate(N, d_xs, d_hist[0], d_hist[1], d_hist[2], 4.0, -6.0, 4.0, stream, d_hist[3], -1.0);
@@ -1207,6 +1212,13 @@ lx_status Sim::step(lx_step_stats *out)
         S.converged = conv;
         timer_flush(0, S);
     }
+    // score the guess orders against the solution just found (read after the sync below)
+    const int nk = extrap ? std::min(nhist, 4) - 1 : 0;
+    if (nk >= 2) {
+        const double *h[4] = {d_hist[0], d_hist[1], d_hist[2], d_hist[3]};
+        launch_guess_err(N, nk, d_xs, h, C.gamma, d_gerr, d_gerr + kGuessErrPartial, stream);
+        LX_HIP(hipMemcpyAsync(h_gerr, d_gerr + kGuessErrPartial, 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    }
     LX_HIP(hipEventRecord(ev_step1, stream));
     LX_HIP(hipEventSynchronize(ev_step1));
     float ms = 0, ma = 0;
@@ -1219,6 +1231,15 @@ lx_status Sim::step(lx_step_stats *out)
     if (!S.converged)
         return fail(LX_ENOCONV, "step did not converge: rel. residual %.3e after %d iterations", S.rel_residual,
                     S.gmres_iters);
+    if (nk >= 2) {
+        // the best predictor among those scored; if it is the highest scored,
+        // the next step (with one more level) may go one order higher
+        int best = 2;
+        double eb = h_gerr[0];
+        for (int k = 1; k <= nk - 1; ++k)
+            if (h_gerr[k] < eb) eb = h_gerr[k], best = k + 2;
+        x_order = best == nk + 1 ? std::min(best + 1, 4) : best;
+    }
     // commit: rotate history (u^n -> u^{n-1}, ...) and advance time
     const int Lh = std::max(L, 4);
     double *oldest = d_hist[Lh - 1];
