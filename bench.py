@@ -250,7 +250,10 @@ def step_bound(q, prec, iters, ir_iters, args):
     vin = nv * (24 + 24 + 32 * hist + 32)
     resid = ((nt * (16 + 2 * 32 * 8) + vin + nv * 64) + ir_iters * (nt * (16 + 2 * 16 * 8) + vin + nv * 32)
              if prec == "fp32_ir" else 0)
-    nbytes = iters * per_iter + asm + setup + resid
+    # initial guess, FP64: extrapolation (four history levels read, the guess written) and the
+    # scoring of the extrapolation orders against the new solution (five vectors read)
+    guess = 10 * 8 * 4 * nv
+    nbytes = iters * per_iter + asm + setup + resid + guess
     fl = ASM_FLOPS_PER_TET[prec]
     f64 = nt * fl["f64"] + (nt * (RESID_FIRST_FLOPS_PER_TET + ir_iters * RESID_FLOPS_PER_TET)
                             if prec == "fp32_ir" else 0)
