@@ -275,8 +275,13 @@ lx_status lx_sim_set_ale_displacement(lx_sim *sim, const double *d);
 /* Advance one time step (paper's fully discrete problem, Sec. 2.3): boundary
  * data at t^{n+1}, ALE lifting and mesh velocity, element assembly and
  * scatter, Dirichlet rows, SIMPLE setup, GMRES (or FP32 GMRES inside FP64
- * refinement), history rotation.  Transactional: on LX_ENOCONV the state and
- * time are left unchanged.  stats may be NULL. */
+ * refinement), history rotation.  The solve starts from an extrapolation of
+ * the last solutions to t^{n+1} (the BDF extrapolation weights, or the
+ * quadratic or cubic through the last three or four solutions, whichever
+ * predicted the previous step's solution best); the stopping test does not
+ * depend on it.  Levels set by lx_sim_set_state count as history; older
+ * computed levels are then dropped.  Transactional: on LX_ENOCONV the state
+ * and time are left unchanged.  stats may be NULL. */
 lx_status lx_sim_step(lx_sim *sim, lx_step_stats *stats);
 
 /* Copy the current solution to caller buffers: u [n_u_nodes][3], p
