@@ -115,6 +115,10 @@ struct Sim {
     size_t ev_used = 0;
     int64_t spmv_seq = 0;   // in-cycle SpMV launches so far (every collect_timing-th one is timed)
     hipEvent_t ev_step0 = nullptr, ev_step1 = nullptr, ev_asm1 = nullptr;
+    // P1-P1 FP32 + refinement on meshes of 2^19 tets and more: a second stream on which the FP64
+    // residual of the initial guess runs while the FP32 system is assembled
+    hipStream_t stream_aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // convergence checks inside an Arnoldi cycle: the done flag copied to pinned
     // host memory behind an event, one check in flight (ping-pong slots)
     int32_t *h_flag = nullptr;
@@ -154,6 +158,7 @@ struct Sim {
     void coefficients(double t1, StepCoef &C, BCSet &B) const;
     lx_status prepare(double t1, StepCoef &C);
     lx_status build_system(double t1, StepCoef &C, lx_step_stats &tstats);
+    lx_status assemble_system(double t1, StepCoef &C);
     lx_status build_system_p2(double t1, StepCoef &C);
     void add_neumann(double t1, double *out0, double *out1);
     lx_status residual64(const StepCoef &C, const double *xs, bool first, double t1);

@@ -70,6 +70,9 @@ Sim::~Sim()
     if (ev_step0) (void)hipEventDestroy(ev_step0);
     if (ev_step1) (void)hipEventDestroy(ev_step1);
     if (ev_asm1) (void)hipEventDestroy(ev_asm1);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (stream_aux) (void)hipStreamDestroy(stream_aux);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -433,6 +436,17 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     LX_HIP(hipEventCreate(&ev_step0));
     LX_HIP(hipEventCreate(&ev_step1));
     LX_HIP(hipEventCreate(&ev_asm1));
+    {
+        static const bool overlap = [] {
+            const char *e = getenv("LXNS_OVERLAP");
+            return !(e && strcmp(e, "0") == 0);
+        }();
+        if (overlap && !p2 && solver.precision != LX_FP64 && !solver.asm_fp64 && nt >= (1 << 19)) {
+            LX_HIP(hipStreamCreateWithFlags(&stream_aux, hipStreamNonBlocking));
+            LX_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+            LX_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+        }
+    }
     LX_HIP(hipStreamSynchronize(stream));
     LX_HIP(hipGetLastError());
     t = prob.t0;
@@ -1000,6 +1014,12 @@ lx_status Sim::build_system(double t1, StepCoef &C, lx_step_stats &tstats)
     (void)tstats;
     lx_status ps = prepare(t1, C);
     if (ps != LX_OK) return ps;
+    return assemble_system(t1, C);
+}
+
+// The system at t1 after prepare(): assembly, Dirichlet rows, preconditioner set-up.
+lx_status Sim::assemble_system(double t1, StepCoef &C)
+{
     if (p2) return build_system_p2(t1, C);
     const RowPattern P = pattern();
     if (solver.precision == LX_FP64) {
@@ -1128,9 +1148,10 @@ lx_status Sim::step(lx_step_stats *out)
     const int L = prob.bdf_order;
     LX_HIP(hipEventRecord(ev_step0, stream));
     StepCoef C;
-    lx_status st = build_system(t1, C, S);
+    const bool overlap = stream_aux != nullptr;
+    lx_status st = overlap ? prepare(t1, C) : build_system(t1, C, S);
     if (st != LX_OK) return st;
-    LX_HIP(hipEventRecord(ev_asm1, stream));
+    if (!overlap) LX_HIP(hipEventRecord(ev_asm1, stream));
     // initial guess, with the new Dirichlet values: the polynomial through the
     // last four (three) solutions evaluated at t^{n+1}, or the extrapolation
     // with the step's BDF weights (u_EXT, p_EXT); x_order picks the one that
@@ -1161,6 +1182,23 @@ lx_status Sim::step(lx_step_stats *out)
     else
         LX_HIP(hipMemcpyAsync(d_xs, d_hist[0], sizeof(double) * N, hipMemcpyDeviceToDevice, stream));
     launch_set_dirichlet_x(n_dir, d_dir_node, d_g, d_xs, stream);
+    if (overlap) {
+        // The FP64 residual of the guess (matrix-free, from the element data and the
+        // history) does not read the FP32 system: it runs on the second stream while
+        // the FP32 matrix is assembled and the preconditioner set up.  The two share
+        // no buffer that either writes.
+        LX_HIP(hipEventRecord(ev_fork, stream));
+        LX_HIP(hipStreamWaitEvent(stream_aux, ev_fork, 0));
+        std::swap(stream, stream_aux);
+        st = residual64(C, d_xs, true, t1);
+        std::swap(stream, stream_aux);
+        if (st != LX_OK) return st;
+        LX_HIP(hipEventRecord(ev_join, stream_aux));
+        st = assemble_system(t1, C);
+        if (st != LX_OK) return st;
+        LX_HIP(hipEventRecord(ev_asm1, stream));
+        LX_HIP(hipStreamWaitEvent(stream, ev_join, 0));
+    }
     GmResult gr;
     if (solver.precision == LX_FP64) {
         st = gmres<double>(d_rhs64, d_xs, false, solver.rtol, solver.max_iters, gr, S);
@@ -1171,8 +1209,10 @@ lx_status Sim::step(lx_step_stats *out)
         S.converged = gr.converged;
     } else {
         // FP32 matrix and inner GMRES inside FP64 iterative refinement
-        st = residual64(C, d_xs, true, t1);
-        if (st != LX_OK) return st;
+        if (!overlap) {
+            st = residual64(C, d_xs, true, t1);
+            if (st != LX_OK) return st;
+        }
         launch_norm<double>(N, d_b64, d_st, 0.0, d_partial, 1, stream);
         launch_norm<double>(N, d_r64, d_st, 0.0, d_partial, 2, stream);
         st = read_state();
