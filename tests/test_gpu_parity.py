@@ -112,3 +112,42 @@ def test_steps_parity(mk, steps, precision, stream):
               "err u %.2e p %.2e" % (eu, ep), flush=True)
     assert worst[0] < tol and worst[1] < tol, worst
     g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_restart_matches_continuation(precision, stream):
+    """A simulation restarted from two stored levels (set_state, set_time) continues the
+    uninterrupted trajectory to the solver's tolerance.  The restarted one holds only the
+    levels it was given, so its first steps start from the BDF extrapolation while the
+    uninterrupted one, with five and more steps behind it, extrapolates from four levels:
+    the stopping test, not the start, fixes the solution."""
+    case = tube_valve(4, 8)
+    print("case", case.name, precision, flush=True)
+    rtol = 1e-14 if precision == "fp64" else 1e-13
+    a = _gpu(case, stream, precision, rtol=rtol)
+    case.init(a)
+    traj = []
+    for k in range(9):
+        t1 = a.solution()[2] + case.prob.dt
+        case.drive(a, t1)
+        a.step()
+        traj.append(a.solution())
+    a.close()
+    b = _gpu(case, stream, precision, rtol=rtol)
+    (u4, p4, _), (u5, p5, t5) = traj[4], traj[5]
+    b.set_state(0, u5, p5)
+    b.set_state(1, u4, p4)
+    b.set_time(t5)
+    worst = 0.0
+    for k in range(6, 9):
+        t1 = t5 + (k - 5) * case.prob.dt
+        case.drive(b, t1)
+        st = b.step()
+        ub, pb, tb = b.solution()
+        ua, pa, ta = traj[k]
+        assert abs(tb - ta) < 1e-12
+        e = max(rel_l2(ub, ua), rel_l2(pb, pa))
+        worst = max(worst, e)
+        print("step %d: %d iterations, difference %.2e" % (k, st["gmres_iters"], e), flush=True)
+    b.close()
+    assert worst < (1e-10 if precision == "fp64" else 1e-8), worst
