@@ -158,7 +158,7 @@ struct Sim {
     void coefficients(double t1, StepCoef &C, BCSet &B) const;
     lx_status prepare(double t1, StepCoef &C);
     lx_status build_system(double t1, StepCoef &C, lx_step_stats &tstats);
-    lx_status assemble_system(double t1, StepCoef &C);
+    lx_status assemble_system(double t1, StepCoef &C, bool fork_residual = false);
     lx_status build_system_p2(double t1, StepCoef &C);
     void add_neumann(double t1, double *out0, double *out1);
     lx_status residual64(const StepCoef &C, const double *xs, bool first, double t1);

@@ -1018,7 +1018,10 @@ lx_status Sim::build_system(double t1, StepCoef &C, lx_step_stats &tstats)
 }
 
 // The system at t1 after prepare(): assembly, Dirichlet rows, preconditioner set-up.
-lx_status Sim::assemble_system(double t1, StepCoef &C)
+// fork_residual (P1-P1 FP32 with the second stream): once the FP32 matrix is
+// assembled, the FP64 residual of the guess d_xs starts on the second stream and
+// runs beside the preconditioner set-up; ev_join marks its end.
+lx_status Sim::assemble_system(double t1, StepCoef &C, bool fork_residual)
 {
     if (p2) return build_system_p2(t1, C);
     const RowPattern P = pattern();
@@ -1053,6 +1056,17 @@ lx_status Sim::assemble_system(double t1, StepCoef &C)
             timer_end(tm);
         }
         launch_dirichlet_rows<float>(n_dir, d_dir_node, d_g, P, d_val32, (float *)nullptr, stream);
+        if (fork_residual) {
+            // the residual reads the element data and the history, not the FP32
+            // system; it shares no buffer that either side writes
+            LX_HIP(hipEventRecord(ev_fork, stream));
+            LX_HIP(hipStreamWaitEvent(stream_aux, ev_fork, 0));
+            std::swap(stream, stream_aux);
+            const lx_status rs = residual64(C, d_xs, true, t1);
+            std::swap(stream, stream_aux);
+            if (rs != LX_OK) return rs;
+            LX_HIP(hipEventRecord(ev_join, stream_aux));
+        }
         launch_simple_setup<float>(P, d_val32, d_Finv32, d_Dinv32, solver.precond == LX_PC_AMG ? nullptr : d_Sinv32,
                                   stream);
         if (solver.precond == LX_PC_AMG)
@@ -1185,16 +1199,8 @@ lx_status Sim::step(lx_step_stats *out)
     if (overlap) {
         // The FP64 residual of the guess (matrix-free, from the element data and the
         // history) does not read the FP32 system: it runs on the second stream while
-        // the FP32 matrix is assembled and the preconditioner set up.  The two share
-        // no buffer that either writes.
-        LX_HIP(hipEventRecord(ev_fork, stream));
-        LX_HIP(hipStreamWaitEvent(stream_aux, ev_fork, 0));
-        std::swap(stream, stream_aux);
-        st = residual64(C, d_xs, true, t1);
-        std::swap(stream, stream_aux);
-        if (st != LX_OK) return st;
-        LX_HIP(hipEventRecord(ev_join, stream_aux));
-        st = assemble_system(t1, C);
+        // the preconditioner is set up.
+        st = assemble_system(t1, C, true);
         if (st != LX_OK) return st;
         LX_HIP(hipEventRecord(ev_asm1, stream));
         LX_HIP(hipStreamWaitEvent(stream, ev_join, 0));
