@@ -69,8 +69,11 @@ enum {
     LX_LAW_CONSTANT = 0,  /* p = {g}                                                  */
     LX_LAW_PULSATILE = 1, /* p = {gmin, gmax, period}: gmin + (gmax-gmin)(1-cos 2pi t/T)/2 */
     LX_LAW_RAMP = 2,      /* p = {g0, g1, t0, tL}: sinusoidal ramp from g0 to g1         */
-    LX_LAW_RAMP2 = 3      /* p = {g0, g1, t_open, dur_open, t_close, dur_close, period}:
+    LX_LAW_RAMP2 = 3,     /* p = {g0, g1, t_open, dur_open, t_close, dur_close, period}:
                              ramp up then back down, repeated every period if > 0      */
+    LX_LAW_LINEAR = 4,    /* p = {g0, g1}: g0 + g1 t (rigid mesh translation)           */
+    LX_LAW_SINE = 5       /* p = {A, w, phi}: A sin(w t + phi) (the time factor of the
+                             ALE verification displacement, Appendix A)                 */
 };
 typedef struct {
     int32_t kind;

@@ -14,7 +14,8 @@ from .meshes import Mesh, cube_kuhn, tube, spheroid, TUBE_TAGS, SPHEROID_TAGS, C
 @dataclass
 class TimeLaw:
     """constant: p=(v,)  pulsatile: p=(gmin, gmax, period)  ramp: p=(g0, g1, t0, tL)
-    ramp2 (open then close): p=(g0, g1, t_open, dur_open, t_close, dur_close, period)."""
+    ramp2 (open then close): p=(g0, g1, t_open, dur_open, t_close, dur_close, period)
+    linear: p=(g0, g1) -> g0 + g1 t   sine: p=(A, w, phi) -> A sin(w t + phi)."""
     kind: str = "constant"
     p: Tuple[float, ...] = (0.0,)
 

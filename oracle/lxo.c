@@ -27,9 +27,19 @@
  * vertex order as given; the P1 quadrature is the symmetric 4-point degree-2
  * rule; the valve distance is measured at the quadrature point's reference
  * position; u_Sigma = 0.
+ *
+ * Threads: with OpenMP the element loop computes element matrices of a chunk
+ * of elements in parallel and adds them into the global system serially in
+ * element order; row loops (products, preconditioner set-up and apply) and
+ * element-wise vector updates run in parallel; dot products sum fixed blocks
+ * of 4096 entries in parallel and then the block sums in order.  Every result
+ * is therefore bitwise the same for any number of threads.
  */
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -360,39 +370,53 @@ int64_t orc_assemble_p1(int64_t nv, int64_t nt, const double *x, const double *x
                         const double *pE, const double *f, const orc_params *P,
                         const int64_t *rowptr, const int32_t *col, double *val, double *rhs)
 {
-    for (int64_t e = 0; e < nt; ++e) {
-        double X[4][3], Xh[4][3], ue[4][3], ub[4][3], ua[4][3], pe[4], fe[4][3];
-        int32_t v[4];
-        for (int a = 0; a < 4; ++a) {
-            v[a] = tets[4 * e + a];
-            for (int c = 0; c < 3; ++c) {
-                X[a][c] = x[3 * v[a] + c];
-                Xh[a][c] = xh[3 * v[a] + c];
-                ue[a][c] = uE[3 * v[a] + c];
-                ub[a][c] = uB[3 * v[a] + c];
-                ua[a][c] = uA ? uA[3 * v[a] + c] : 0.0;
-                fe[a][c] = f ? f[3 * v[a] + c] : 0.0;
+    enum { CHUNK = 8192 };
+    double (*Kc)[16][16] = malloc(sizeof(double) * 256 * CHUNK);
+    double (*Fc)[16] = malloc(sizeof(double) * 16 * CHUNK);
+    double *detc = malloc(sizeof(double) * CHUNK);
+    if (!Kc || !Fc || !detc) { free(Kc); free(Fc); free(detc); return -(nt + 1); }
+    int64_t rc = 0;
+    for (int64_t e0 = 0; e0 < nt && rc == 0; e0 += CHUNK) {
+        const int64_t ne = (nt - e0 < CHUNK) ? nt - e0 : CHUNK;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < ne; ++i) {
+            const int64_t e = e0 + i;
+            double X[4][3], Xh[4][3], ue[4][3], ub[4][3], ua[4][3], pe[4], fe[4][3];
+            for (int a = 0; a < 4; ++a) {
+                const int32_t va = tets[4 * e + a];
+                for (int c = 0; c < 3; ++c) {
+                    X[a][c] = x[3 * va + c];
+                    Xh[a][c] = xh[3 * va + c];
+                    ue[a][c] = uE[3 * va + c];
+                    ub[a][c] = uB[3 * va + c];
+                    ua[a][c] = uA ? uA[3 * va + c] : 0.0;
+                    fe[a][c] = f ? f[3 * va + c] : 0.0;
+                }
+                pe[a] = pE[va];
             }
-            pe[a] = pE[v[a]];
+            detc[i] = orc_element_p1(X, Xh, ue, ub, ua, pe, fe, P, Kc[i], Fc[i]);
         }
-        double Ke[16][16], Fe[16];
-        double det = orc_element_p1(X, Xh, ue, ub, ua, pe, fe, P, Ke, Fe);
-        if (!(fabs(det) > 0.0)) return -(e + 1);
-        int64_t gdof[16];
-        for (int a = 0; a < 4; ++a) {
-            for (int c = 0; c < 3; ++c) gdof[3 * a + c] = 3 * (int64_t)v[a] + c;
-            gdof[12 + a] = 3 * nv + v[a];
-        }
-        for (int i = 0; i < 16; ++i) {
-            rhs[gdof[i]] += Fe[i];
-            for (int j = 0; j < 16; ++j) {
-                int64_t k = find_col(rowptr, col, gdof[i], (int32_t)gdof[j]);
-                if (k < 0) return -(e + 1);
-                val[k] += Ke[i][j];
+        for (int64_t i = 0; i < ne && rc == 0; ++i) {
+            const int64_t e = e0 + i;
+            if (!(fabs(detc[i]) > 0.0)) { rc = -(e + 1); break; }
+            int64_t gdof[16];
+            for (int a = 0; a < 4; ++a) {
+                const int32_t va = tets[4 * e + a];
+                for (int c = 0; c < 3; ++c) gdof[3 * a + c] = 3 * (int64_t)va + c;
+                gdof[12 + a] = 3 * nv + va;
+            }
+            for (int r = 0; r < 16 && rc == 0; ++r) {
+                rhs[gdof[r]] += Fc[i][r];
+                for (int j = 0; j < 16; ++j) {
+                    int64_t k = find_col(rowptr, col, gdof[r], (int32_t)gdof[j]);
+                    if (k < 0) { rc = -(e + 1); break; }
+                    val[k] += Kc[i][r][j];
+                }
             }
         }
     }
-    return 0;
+    free(Kc); free(Fc); free(detc);
+    return rc;
 }
 
 /*
@@ -445,6 +469,7 @@ void orc_dirichlet_rows(int64_t nrows, const int64_t *rows, const double *g, con
 static void csr_mv(int64_t N, const int64_t *rowptr, const int32_t *col, const double *val,
                    const double *x, double *y)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t r = 0; r < N; ++r) {
         double s = 0.0;
         for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) s += val[p] * x[col[p]];
@@ -452,10 +477,25 @@ static void csr_mv(int64_t N, const int64_t *rowptr, const int32_t *col, const d
     }
 }
 
+/* Sum over fixed blocks of 4096 entries, then the block sums in order: the
+   same rounding for any number of threads. */
 static double dot(int64_t N, const double *a, const double *b)
 {
+    enum { BLK = 4096 };
+    const int64_t nb = (N + BLK - 1) / BLK;
+    double part[256];
     double s = 0.0;
-    for (int64_t i = 0; i < N; ++i) s += a[i] * b[i];
+    for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+        const int64_t n = (nb - b0 < 256) ? nb - b0 : 256;
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < n; ++k) {
+            const int64_t lo = (b0 + k) * BLK, hi = (lo + BLK < N) ? lo + BLK : N;
+            double t = 0.0;
+            for (int64_t i = lo; i < hi; ++i) t += a[i] * b[i];
+            part[k] = t;
+        }
+        for (int64_t k = 0; k < n; ++k) s += part[k];
+    }
     return s;
 }
 
@@ -497,6 +537,7 @@ static int simple_setup(simple_t *S)
     const int64_t *rp = S->rowptr;
     const int32_t *col = S->col;
     const double *val = S->val;
+#pragma omp parallel for schedule(static)
     for (int64_t v = 0; v < nv; ++v) {
         double blk[9];
         for (int c = 0; c < 3; ++c)
@@ -507,6 +548,7 @@ static int simple_setup(simple_t *S)
         for (int c = 0; c < 3; ++c) S->Dinv[3 * v + c] = 1.0 / blk[4 * c];
         inv3(blk, S->Finv + 9 * v);
     }
+#pragma omp parallel for schedule(static)
     for (int64_t v = 0; v < nv; ++v) {
         int64_t r = 3 * nv + v;
         double s = 0.0, cvv = 0.0;
@@ -526,20 +568,24 @@ static int simple_setup(simple_t *S)
     S->lam_max = 0.0;
     if (S->degree > 0) {
         double *ag = S->cw;   /* [3nv] */
+#pragma omp parallel for schedule(static)
         for (int64_t r = 0; r < 3 * nv; ++r) {
             double a = 0.0;
             for (int64_t p = rp[r]; p < rp[r + 1]; ++p)
                 if (col[p] >= 3 * nv) a += fabs(val[p]);
             ag[r] = a * fabs(S->Dinv[r]);
         }
+        double lam = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : lam)
         for (int64_t v = 0; v < nv; ++v) {
             int64_t r = 3 * nv + v;
             double a = 0.0;
             for (int64_t p = rp[r]; p < rp[r + 1]; ++p)
                 a += (col[p] >= 3 * nv) ? fabs(val[p]) : fabs(val[p]) * ag[col[p]];
             a *= fabs(S->Sinv[v]);
-            if (a > S->lam_max) S->lam_max = a;
+            if (a > lam) lam = a;
         }
+        S->lam_max = lam;
     }
     return 0;
 }
@@ -551,12 +597,14 @@ static void schur_mv(const simple_t *S, const double *d, double *gu, double *y)
     const int64_t *rp = S->rowptr;
     const int32_t *col = S->col;
     const double *val = S->val;
+#pragma omp parallel for schedule(static)
     for (int64_t r = 0; r < 3 * nv; ++r) {
         double a = 0.0;
         for (int64_t p = rp[r]; p < rp[r + 1]; ++p)
             if (col[p] >= 3 * nv) a += val[p] * d[col[p] - 3 * nv];
         gu[r] = S->Dinv[r] * a;
     }
+#pragma omp parallel for schedule(static)
     for (int64_t v = 0; v < nv; ++v) {
         int64_t r = 3 * nv + v;
         double a = 0.0;
@@ -576,6 +624,7 @@ static void schur_cheb(const simple_t *S, const double *t, double *z)
     double lmax = S->lam_max, lmin = lmax / S->ratio;
     double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
     double sigma = theta / delta, rho = 1.0 / sigma;
+#pragma omp parallel for schedule(static)
     for (int64_t v = 0; v < nv; ++v) {
         r[v] = t[v];
         d[v] = S->Sinv[v] * r[v] / theta;
@@ -584,6 +633,7 @@ static void schur_cheb(const simple_t *S, const double *t, double *z)
     for (int i = 1; i < S->degree; ++i) {
         schur_mv(S, d, gu, q);
         double rho_new = 1.0 / (2.0 * sigma - rho);
+#pragma omp parallel for schedule(static)
         for (int64_t v = 0; v < nv; ++v) {
             r[v] -= q[v];
             d[v] = rho_new * rho * d[v] + 2.0 * rho_new / delta * S->Sinv[v] * r[v];
@@ -601,12 +651,14 @@ static void simple_apply(const simple_t *S, const double *r, double *x)
     const int32_t *col = S->col;
     const double *val = S->val;
     double *zu = S->tmp;
+#pragma omp parallel for schedule(static)
     for (int64_t v = 0; v < nv; ++v)
         for (int c = 0; c < 3; ++c) {
             double s = 0.0;
             for (int d = 0; d < 3; ++d) s += S->Finv[9 * v + 3 * c + d] * r[3 * v + d];
             zu[3 * v + c] = s;
         }
+#pragma omp parallel for schedule(static)
     for (int64_t v = 0; v < nv; ++v) {
         int64_t row = 3 * nv + v;
         double s = r[row];
@@ -621,6 +673,7 @@ static void simple_apply(const simple_t *S, const double *r, double *x)
     } else {
         for (int64_t v = 0; v < nv; ++v) x[3 * nv + v] *= S->Sinv[v];
     }
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < 3 * nv; ++i) {
         double s = 0.0;
         for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
@@ -662,10 +715,12 @@ int64_t orc_gmres_simple(int64_t nv, const int64_t *rowptr, const int32_t *col, 
     double rel = 0.0;
     for (;;) {
         csr_mv(N, rowptr, col, val, x, w);
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < N; ++i) w[i] = b[i] - w[i];
         double beta = sqrt(dot(N, w, w));
         rel = beta / bnorm;
         if (rel <= rtol || it >= max_iters) break;
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < N; ++i) V[i] = w[i] / beta;
         memset(gv, 0, sizeof(double) * (m + 1));
         gv[0] = beta;
@@ -679,12 +734,14 @@ int64_t orc_gmres_simple(int64_t nv, const int64_t *rowptr, const int32_t *col, 
                 for (int j = 0; j <= k; ++j) h1[j] = dot(N, V + (size_t)j * N, w);
                 for (int j = 0; j <= k; ++j) {
                     const double *vj = V + (size_t)j * N;
+#pragma omp parallel for schedule(static)
                     for (int64_t i = 0; i < N; ++i) w[i] -= h1[j] * vj[i];
                     H[j * m + k] += h1[j];
                 }
             }
             double hn = sqrt(dot(N, w, w));
             H[(k + 1) * m + k] = hn;
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < N; ++i) vn[i] = (hn > 0.0) ? w[i] / hn : 0.0;
             for (int j = 0; j < k; ++j) {
                 double t = cs[j] * H[j * m + k] + sn[j] * H[(j + 1) * m + k];
@@ -709,9 +766,11 @@ int64_t orc_gmres_simple(int64_t nv, const int64_t *rowptr, const int32_t *col, 
         memset(w, 0, sizeof(double) * N);
         for (int j = 0; j < k; ++j) {
             const double *vj = V + (size_t)j * N;
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < N; ++i) w[i] += y[j] * vj[i];
         }
         simple_apply(&S, w, z);
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < N; ++i) x[i] += z[i];
     }
     if (res_out) *res_out = rel;
@@ -885,6 +944,8 @@ int64_t orc_elements_p2(int64_t nt, const double *x, const double *xh, const int
                         const double *pE, const double *f, const orc_params *P, int32_t nq,
                         const double *qlam, const double *qw, double *Ke_all, double *Fe_all)
 {
+    int64_t bad = nt;   /* first degenerate element, nt if none */
+#pragma omp parallel for schedule(static) reduction(min : bad)
     for (int64_t e = 0; e < nt; ++e) {
         double X[4][3], Xh[4][3], ue[10][3], ub[10][3], ua[10][3], pe[4], fe[10][3];
         for (int a = 0; a < 4; ++a) {
@@ -906,7 +967,19 @@ int64_t orc_elements_p2(int64_t nt, const double *x, const double *xh, const int
         }
         double det = orc_element_p2(X, Xh, ue, ub, ua, pe, fe, P, nq, qlam, qw,
                                     (double(*)[34])(Ke_all + (size_t)e * 34 * 34), Fe_all + (size_t)e * 34);
-        if (!(fabs(det) > 0.0)) return -(e + 1);
+        if (!(fabs(det) > 0.0) && e < bad) bad = e;
     }
-    return 0;
+    return bad < nt ? -(bad + 1) : 0;
+}
+
+/* Threads used by the parallel loops (OpenMP builds); returns the count in effect. */
+int32_t orc_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return (int32_t)omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

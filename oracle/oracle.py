@@ -42,10 +42,11 @@ def lib_path():
 
 
 def build(quiet=True):
-    """Compile lxo.c into liblxo.so with gcc (plain C, -O2)."""
+    """Compile lxo.c into liblxo.so with gcc (plain C, -O2, OpenMP loops)."""
     import subprocess
     src = os.path.join(_HERE, "lxo.c")
-    cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-o", lib_path(), src, "-lm"]
+    cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC", "-shared", "-o", lib_path(), src,
+           "-lm"]
     subprocess.check_call(cmd)
 
 
@@ -79,6 +80,8 @@ def lib():
         L.orc_valve_distance.argtypes = [vp, vp]
         L.orc_quad_p1.restype = None
         L.orc_quad_p1.argtypes = [vp, vp]
+        L.orc_set_threads.restype = I32
+        L.orc_set_threads.argtypes = [I32]
         _LIB = L
     return _LIB
 
@@ -87,14 +90,26 @@ def _p(a):
     return a.ctypes.data if a is not None else None
 
 
+def set_threads(n):
+    """Threads of the oracle's parallel loops (0: leave as is); returns the count in effect.
+    Results do not depend on it."""
+    return int(lib().orc_set_threads(int(n)))
+
+
 # ---------------------------------------------------------------- boundary data
 
 def time_law(law, t):
     """g(t) of Sec. 2.2.1: constant, pulsatile, sinusoidal ramp, and an open-then-close
-    pair of ramps (optionally periodic) for valve schedules."""
+    pair of ramps (optionally periodic) for valve schedules; also linear g0 + g1 t and
+    sine A sin(w t + phi), the time factors of the rigid-translation and ALE-Beltrami
+    mesh motions (Appendix A)."""
     k, p = law.kind, law.p
     if k == "constant":
         return p[0]
+    if k == "linear":
+        return p[0] + p[1] * t
+    if k == "sine":
+        return p[0] * np.sin(p[1] * t + p[2])
     if k == "pulsatile":
         gmin, gmax, T = p[:3]
         return gmin + (gmax - gmin) * 0.5 * (1.0 - np.cos(2.0 * np.pi * t / T))

@@ -34,6 +34,10 @@ double law_value(const lx_time_law &L, double t)
         if (tau < p[4] + p[5]) return p[1] + 0.5 * (p[0] - p[1]) * (1.0 - std::cos(M_PI * (tau - p[4]) / p[5]));
         return p[0];
     }
+    case LX_LAW_LINEAR:
+        return p[0] + p[1] * t;
+    case LX_LAW_SINE:
+        return p[0] * std::sin(p[1] * t + p[2]);
     }
     return 0.0;
 }

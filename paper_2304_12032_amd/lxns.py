@@ -21,7 +21,7 @@ P = ctypes.POINTER
 LX_OK, LX_EINVAL, LX_ENOMEM, LX_EDEVICE, LX_ENOCONV, LX_EMESH, LX_EBUSY, LX_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "LX_OK", -1: "LX_EINVAL", -2: "LX_ENOMEM", -3: "LX_EDEVICE", -4: "LX_ENOCONV",
                 -5: "LX_EMESH", -6: "LX_EBUSY", -7: "LX_ESTATE"}
-LAW = {"constant": 0, "pulsatile": 1, "ramp": 2, "ramp2": 3}
+LAW = {"constant": 0, "pulsatile": 1, "ramp": 2, "ramp2": 3, "linear": 4, "sine": 5}
 PROFILE = {"uniform": 0, "parabolic": 1, "nodal": 2}
 BC = {"noslip": 0, "dirichlet": 1, "neumann": 2}
 FE = {"p1p1": 1, "p2p1": 2}
