@@ -48,9 +48,21 @@ const char *lx_last_error(void);
 
 /* ------------------------------------------------------------------ inputs */
 
+/* Where an object runs: the device, the stream its work is queued on, and
+ * optionally the caller's device allocator (PyTorch's caching allocator plugs
+ * in here).  With alloc/free set, every device buffer of the object comes from
+ * alloc(bytes, ctx) -- device memory on `device`, usable on hip_stream, at
+ * least 256-byte aligned, NULL on failure (the call then returns LX_ENOMEM) --
+ * and goes back through free(ptr, ctx) when the object is destroyed; both are
+ * called from the thread that makes the library call (for a server: its worker
+ * threads).  With both NULL the library uses hipMalloc / hipFree.  Pinned host
+ * staging (a few hundred bytes per object) always comes from hipHostMalloc. */
 typedef struct {
     int32_t device;      /* HIP device ordinal                                       */
     void *hip_stream;    /* hipStream_t to queue work on, or NULL                    */
+    void *(*alloc)(size_t bytes, void *ctx);   /* optional device allocator          */
+    void (*free)(void *ptr, void *ctx);        /* its release; both or neither       */
+    void *ctx;                                 /* passed back to alloc / free        */
 } lx_device;
 
 /* Mesh (the paper's mesh input, Sec. 3.1): reference configuration x^ and a
@@ -274,6 +286,13 @@ lx_status lx_sim_set_forcing(lx_sim *sim, const double *f);
 /* ALE boundary-displacement shape D^ [n_vertices][3] (rows of ALE boundary
  * vertices are read); the displacement at t is ale_law(t) * D^ (Sec. 2.1.1). */
 lx_status lx_sim_set_ale_displacement(lx_sim *sim, const double *d);
+/* Boundary displacement d^ at t^{n+1} of the coming step, [n_vertices][3] (rows
+ * of ALE boundary vertices are read; Sec. 2.1.1's data on the moving boundary).
+ * From this call on, every step solves the lifting problem for the values last
+ * set (CG on the reference-mesh Laplacian, started from the extrapolation of the
+ * displacement history, to a relative residual of 1e-13) instead of scaling the
+ * extension of a shape; lx_sim_set_ale_displacement switches back. */
+lx_status lx_sim_set_boundary_displacement(lx_sim *sim, const double *d);
 
 /* Advance one time step (paper's fully discrete problem, Sec. 2.3): boundary
  * data at t^{n+1}, ALE lifting and mesh velocity, element assembly and
@@ -286,6 +305,22 @@ lx_status lx_sim_set_ale_displacement(lx_sim *sim, const double *d);
  * computed levels are then dropped.  Transactional: on LX_ENOCONV the state
  * and time are left unchanged.  stats may be NULL. */
 lx_status lx_sim_step(lx_sim *sim, lx_step_stats *stats);
+
+/* Checkpoint and restore (stop-and-restart serialisation of Sec. 3.1).  The
+ * state is everything the next step reads besides the mesh, problem and solver
+ * given at creation: time and step counters, every stored solution level (the
+ * BDF history and the levels the initial guess extrapolates from) and the
+ * choice of extrapolation order, the ALE displacement history and lifting,
+ * the nodal boundary data, forcing and displacement last set, and the warm
+ * start of the preconditioner's power iterations.  lx_sim_state_size gives the
+ * byte count; lx_sim_get_state writes an opaque blob of exactly that size into
+ * caller memory (synchronising the stream); lx_sim_restore_state loads it into a
+ * simulation created with the same mesh, problem and solver (LX_EINVAL on a size
+ * or fingerprint mismatch, the simulation unchanged).  A restored simulation
+ * continues bitwise as the saved one would have. */
+lx_status lx_sim_state_size(const lx_sim *sim, int64_t *bytes);
+lx_status lx_sim_get_state(const lx_sim *sim, void *blob, int64_t bytes);
+lx_status lx_sim_restore_state(lx_sim *sim, const void *blob, int64_t bytes);
 
 /* Copy the current solution to caller buffers: u [n_u_nodes][3], p
  * [n_vertices], t (any may be NULL).  Synchronises the stream. */

@@ -191,6 +191,7 @@ class OracleSim:
         self.neu_nodal = {}          # bc index -> [nv][3] traction at t^{n+1}
         self.forcing = None
         self.ale_shape = np.zeros((nv, 3))
+        self.ale_nodal = None
         L = lib()
         self.vptr = np.zeros(nv + 1, dtype=np.int64)
         nadj = L.orc_vertex_graph(nv, mesh.nt, 4, _p(self.tets), None, None)
@@ -230,6 +231,11 @@ class OracleSim:
 
     def set_ale_displacement(self, d):
         self.ale_shape = np.array(d, dtype=np.float64).reshape(self.nv, 3)
+        self.ale_nodal = None
+
+    def set_boundary_displacement(self, d):
+        """Boundary displacement at t^{n+1} (used from now on instead of law(t) * shape)."""
+        self.ale_nodal = np.array(d, dtype=np.float64).reshape(self.nv, 3)
 
     # ---- one step
     def _coeffs(self):
@@ -249,7 +255,7 @@ class OracleSim:
         from scipy.sparse import coo_matrix
         from scipy.sparse.linalg import spsolve
         prob, m = self.prob, self.mesh
-        dB = time_law(prob.ale_law, t1) * self.ale_shape
+        dB = self.ale_nodal if self.ale_nodal is not None else time_law(prob.ale_law, t1) * self.ale_shape
         faces = m.bfaces[np.isin(m.btags, prob.ale_tags)]
         bnodes = np.unique(faces.reshape(-1))
         K = self.laplacian()

@@ -5,6 +5,6 @@ The numerical work runs in the HIP library liblxns.so (C ABI in
 include/lxns.h); this package holds its sources, the build script and a
 ctypes binding.
 """
-from .lxns import Sim, Server, LxError, lib, check, LIB_PATH
+from .lxns import Sim, Server, LxError, lib, check, LIB_PATH, torch_allocator
 
-__all__ = ["Sim", "Server", "LxError", "lib", "check", "LIB_PATH"]
+__all__ = ["Sim", "Server", "LxError", "lib", "check", "LIB_PATH", "torch_allocator"]

@@ -4,10 +4,14 @@
 // for the three components at once; then x^{n+1} = x^ + d^{n+1} and
 // u_ALE = (alpha d^{n+1} - sum_l beta_l d^{n-l}) / dt at the vertices.
 //
-// The boundary data is d^ = law(t) D^ with a fixed shape D^; the extension
-// operator is linear, so the extension of D^ is computed once per shape and
-// scaled by law(t) every step (identical to solving the lifting problem with
-// the scaled data).  Setting a new shape triggers a new solve.
+// Two ways to give the boundary data:
+//  * d^ = law(t) D^ with a fixed shape D^: the extension operator is linear,
+//    so the extension of D^ is computed once per shape and scaled by law(t)
+//    every step (identical to solving the lifting problem with the scaled
+//    data); setting a new shape triggers a new solve;
+//  * nodal boundary displacements set for each step: the lifting problem is
+//    solved every step, by CG started from the extrapolation of the
+//    displacement history to t^{n+1} (the step's EXT weights).
 #include <cmath>
 #include <vector>
 
@@ -193,6 +197,18 @@ __global__ void k_cg_dir(int64_t nv, const double *z, double *p, const CgState *
         for (int c = 0; c < 3; ++c) p[3 * i + c] = z[3 * i + c] + b[c] * p[3 * i + c];
 }
 
+// Initial guess of a per-step lifting solve: d = sum_l gamma_l d^{n-l}
+__global__ void k_ale_guess(int64_t nv, const double *d0, const double *d1, const double *d2, StepCoef C,
+                            double *ext)
+{
+    const double *D[3] = {d0, d1, d2};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * nv; i += (int64_t)gridDim.x * blockDim.x) {
+        double e = 0;
+        for (int l = 0; l < C.nlev; ++l) e += C.gamma[l] * D[l][i];
+        ext[i] = e;
+    }
+}
+
 // x = x^ + d_new; uA = (alpha d_new - sum beta_l d^{n-l}) / dt; d_new = scale * ext
 __global__ void k_ale_mesh(int64_t nv, const double *xh, const double *ext, double scale, const double *d0,
                            const double *d1, const double *d2, StepCoef C, double *dnew, double *x, double *uA)
@@ -263,6 +279,7 @@ lx_status Sim::ale_setup()
     ALLOC(d_ale_mark, sizeof(int32_t) * nv);
     ALLOC(d_cg, sizeof(double) * 3 * nv * 6 + sizeof(CgState));
     ALLOC(d_dnew, sizeof(double) * 3 * nv);
+    ALLOC(d_dbnd, sizeof(double) * 3 * nv);
 #undef ALLOC
     LX_HIP(hipMemcpyAsync(d_lap, Le.data(), sizeof(double) * nblk, hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_lapfull, L.data(), sizeof(double) * nblk, hipMemcpyHostToDevice, stream));
@@ -274,8 +291,9 @@ lx_status Sim::ale_setup()
     return LX_OK;
 }
 
-// Harmonic extension of the current shape into d_cg[ext] (CG to rtol 1e-13).
-lx_status Sim::ale_extend()
+// Harmonic extension into d_cg[ext] (CG to rtol 1e-13): of the shape D^ (data =
+// nullptr), or of nodal boundary data starting from the guess already in ext.
+lx_status Sim::ale_extend(const double *data)
 {
     double *ext = d_cg, *rhs = d_cg + 3 * nv, *r = d_cg + 6 * nv, *z = d_cg + 9 * nv, *p = d_cg + 12 * nv,
            *q = d_cg + 15 * nv;
@@ -283,7 +301,7 @@ lx_status Sim::ale_extend()
     const unsigned grow = (unsigned)((nv * kAleLPR + 255) / 256);
     const unsigned gvec = (unsigned)std::min<int64_t>((nv + 255) / 256, 1024);
     hipLaunchKernelGGL(k_ale_rhs, dim3(grow), dim3(256), 0, stream, nv, d_rowptr, d_col, d_lapfull, d_ale_mark,
-                       d_ale_shape, 1.0, rhs, ext);
+                       data ? data : d_ale_shape, 1.0, rhs, ext);
     double *part = d_partial;   // grow blocks * 9 doubles: use a dedicated region if larger
     if ((int64_t)grow * 9 > (int64_t)nb_red * 64) {
         if (!d_cg_partial) {
@@ -312,17 +330,27 @@ lx_status Sim::ale_extend()
         if (it >= max_it) return fail(LX_ENOCONV, "ALE lifting CG did not converge");
     }
     ale_iters = h.iters;
-    ale_ext_valid = true;
+    ale_ext_valid = data == nullptr;
     return LX_OK;
 }
 
 lx_status Sim::ale_update(double t1, const StepCoef &C)
 {
-    if (!ale_ext_valid) {
-        lx_status s = ale_extend();
+    double scale = 1.0;
+    if (ale_nodal) {
+        const unsigned g = (unsigned)std::min<int64_t>((3 * nv + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_ale_guess, dim3(g), dim3(256), 0, stream, nv, d_dhist[0],
+                           prob.bdf_order > 1 ? d_dhist[1] : d_dhist[0], prob.bdf_order > 2 ? d_dhist[2] : d_dhist[0],
+                           C, d_cg);
+        lx_status s = ale_extend(d_dbnd);
         if (s != LX_OK) return s;
+    } else {
+        if (!ale_ext_valid) {
+            lx_status s = ale_extend(nullptr);
+            if (s != LX_OK) return s;
+        }
+        scale = law_value(prob.ale_law, t1);
     }
-    const double scale = law_value(prob.ale_law, t1);
     const unsigned g = (unsigned)std::min<int64_t>((3 * nv + 255) / 256, 4096);
     hipLaunchKernelGGL(k_ale_mesh, dim3(g), dim3(256), 0, stream, nv, d_xh, d_cg, scale, d_dhist[0],
                        prob.bdf_order > 1 ? d_dhist[1] : d_dhist[0], prob.bdf_order > 2 ? d_dhist[2] : d_dhist[0],

@@ -172,7 +172,21 @@ extern "C" lx_status lx_sim_set_ale_displacement(lx_sim *s, const double *d)
     if (!d) return fail(LX_EINVAL, "d is NULL");
     (void)hipSetDevice(s->device);
     lx_status st = upload_nodal3(s, d, s->d_ale_shape, true);
-    if (st == LX_OK) s->ale_ext_valid = false;
+    if (st == LX_OK) {
+        s->ale_ext_valid = false;
+        s->ale_nodal = false;
+    }
+    return st;
+}
+
+extern "C" lx_status lx_sim_set_boundary_displacement(lx_sim *s, const double *d)
+{
+    LX_GUARD(s);
+    if (!s->prob.ale) return fail(LX_ESTATE, "problem was created without ALE");
+    if (!d) return fail(LX_EINVAL, "d is NULL");
+    (void)hipSetDevice(s->device);
+    lx_status st = upload_nodal3(s, d, s->d_dbnd, true);
+    if (st == LX_OK) s->ale_nodal = true;
     return st;
 }
 
@@ -183,6 +197,34 @@ extern "C" lx_status lx_sim_step(lx_sim *s, lx_step_stats *stats)
         return s->step(stats);
     } catch (const std::bad_alloc &) {
         return fail(LX_ENOMEM, "host allocation failed");
+    }
+}
+
+extern "C" lx_status lx_sim_state_size(const lx_sim *s, int64_t *bytes)
+{
+    LX_GUARD(s);
+    if (!bytes) return fail(LX_EINVAL, "bytes is NULL");
+    *bytes = s->state_bytes();
+    return LX_OK;
+}
+
+extern "C" lx_status lx_sim_get_state(const lx_sim *s, void *blob, int64_t bytes)
+{
+    LX_GUARD(s);
+    try {
+        return const_cast<lx_sim *>(s)->save_state(blob, bytes);
+    } catch (const std::exception &e) {
+        return fail(LX_ENOMEM, "checkpoint failed: %s", e.what());
+    }
+}
+
+extern "C" lx_status lx_sim_restore_state(lx_sim *s, const void *blob, int64_t bytes)
+{
+    LX_GUARD(s);
+    try {
+        return s->load_state(blob, bytes);
+    } catch (const std::exception &e) {
+        return fail(LX_ENOMEM, "restore failed: %s", e.what());
     }
 }
 

@@ -86,6 +86,8 @@ struct Sim {
     double *d_cg = nullptr;                                      // CG work: 6 vectors [nv][3] + state
     double *d_cg_partial = nullptr;
     bool ale_ext_valid = false;
+    double *d_dbnd = nullptr;                                    // [nv][3] nodal boundary displacement at t^{n+1}
+    bool ale_nodal = false;                                      // lifting of d_dbnd solved every step
     int ale_iters = 0;
     // FP64 system
     double *d_val64 = nullptr, *d_rhs64 = nullptr, *d_Finv64 = nullptr, *d_Dinv64 = nullptr, *d_Sinv64 = nullptr;
@@ -130,6 +132,11 @@ struct Sim {
     // the next solve of that kind starts checking every step
     int32_t k_hint[8][8] = {};
 
+    // caller allocator for device memory (lx_device.alloc / free); NULL: hipMalloc / hipFree
+    void *(*alloc_fn)(size_t, void *) = nullptr;
+    void (*free_fn)(void *, void *) = nullptr;
+    void *alloc_ctx = nullptr;
+
     double t = 0;
     int nlev = 0;
     int nhist = 0;   // valid solution levels in d_hist (up to max(bdf_order, 4); the guess may use four)
@@ -164,8 +171,13 @@ struct Sim {
     lx_status residual64(const StepCoef &C, const double *xs, bool first, double t1);
     lx_status step(lx_step_stats *out);
 
+    // checkpoint of everything the next step reads besides mesh, problem and solver
+    int64_t state_bytes() const;
+    lx_status save_state(void *blob, int64_t bytes);
+    lx_status load_state(const void *blob, int64_t bytes);
+
     lx_status ale_setup();
-    lx_status ale_extend();
+    lx_status ale_extend(const double *data);
     lx_status ale_update(double t1, const StepCoef &C);
     void ale_commit();
 };

@@ -50,8 +50,13 @@ lx_status Sim::dalloc(void **p, size_t bytes)
 {
     *p = nullptr;
     if (bytes == 0) return LX_OK;
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) return fail(LX_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    if (alloc_fn) {
+        *p = alloc_fn(bytes, alloc_ctx);
+        if (!*p) return fail(LX_ENOMEM, "caller allocator returned NULL for %zu bytes", bytes);
+    } else {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) return fail(LX_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
     allocs.push_back(*p);
     device_bytes += (int64_t)bytes;
     return LX_OK;
@@ -61,7 +66,10 @@ Sim::~Sim()
 {
     if (device >= 0) (void)hipSetDevice(device);
     if (stream) (void)hipStreamSynchronize(stream);
-    for (void *p : allocs) (void)hipFree(p);
+    for (void *p : allocs) {
+        if (free_fn) free_fn(p, alloc_ctx);
+        else (void)hipFree(p);
+    }
     if (h_st) (void)hipHostFree(h_st);
     if (h_flag) (void)hipHostFree(h_flag);
     if (h_gerr) (void)hipHostFree(h_gerr);
@@ -222,6 +230,12 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
 
     // ---- device side: everything above is host-only validation and setup
     device = dev ? dev->device : 0;
+    if (dev && (!dev->alloc) != (!dev->free)) return fail(LX_EINVAL, "lx_device: set both alloc and free, or neither");
+    if (dev && dev->alloc) {
+        alloc_fn = dev->alloc;
+        free_fn = dev->free;
+        alloc_ctx = dev->ctx;
+    }
     LX_HIP(hipSetDevice(device));
     if (dev && dev->hip_stream) {
         stream = (hipStream_t)dev->hip_stream;
@@ -1301,6 +1315,164 @@ lx_status Sim::step(lx_step_stats *out)
     nhist = std::min(nhist + 1, Lh);
     t = t1;
     ++step_index;
+    return LX_OK;
+}
+
+// ------------------------------------------------------------------ checkpoint
+
+namespace {
+struct CkHead {
+    char magic[8];
+    int64_t bytes;
+    int64_t nv, nt, nu, N, nblk, n_dir;
+    int32_t fe, bdf_order, precision, ale, forcing, n_bc, precond, f_degree;
+    int32_t levels, nlev, nhist, x_order;
+    int32_t f_warm, ale_ext_valid, fv_elem, ale_nodal;
+    double t;
+    int64_t step_index;
+};
+const char kCkMagic[8] = {'L', 'X', 'N', 'S', 'C', 'K', '0', '1'};
+}  // namespace
+
+// The blob: header, then the solution levels, the nodal Dirichlet values, per
+// nodal Neumann condition its flag and traction, the forcing, the ALE
+// displacement history, lifting and shape, and the power-iteration vector.
+int64_t Sim::state_bytes() const
+{
+    const int L = prob.bdf_order, Lh = std::max(L, 4);
+    int64_t b = sizeof(CkHead);
+    b += (int64_t)Lh * N * 8;
+    b += (int64_t)h_gnodal.size() * 8;
+    for (const auto &bc : bcs)
+        if (bc.d_hnodal) b += 8 + 3 * nu * 8;
+    if (d_f) b += 3 * nu * 8;
+    if (prob.ale) b += (int64_t)(L + 3) * 3 * nv * 8;
+    const bool f64 = solver.precision == LX_FP64;
+    if (solver.precond == LX_PC_AMG && (f64 ? amg64.fv : (void *)amg32.fv))
+        b += 4 * nu * (f64 ? 8 : 4);
+    return b;
+}
+
+lx_status Sim::save_state(void *blob, int64_t bytes)
+{
+    const int64_t need = state_bytes();
+    if (!blob || bytes != need) return fail(LX_EINVAL, "state blob needs exactly %lld bytes", (long long)need);
+    LX_HIP(hipSetDevice(device));
+    const int L = prob.bdf_order, Lh = std::max(L, 4);
+    const bool f64 = solver.precision == LX_FP64;
+    void *fv = solver.precond == LX_PC_AMG ? (f64 ? (void *)amg64.fv : (void *)amg32.fv) : nullptr;
+    CkHead h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.magic, kCkMagic, 8);
+    h.bytes = need;
+    h.nv = nv, h.nt = nt, h.nu = nu, h.N = N, h.nblk = nblk, h.n_dir = n_dir;
+    h.fe = prob.fe, h.bdf_order = L, h.precision = solver.precision, h.ale = prob.ale, h.forcing = prob.forcing;
+    h.n_bc = (int32_t)bcs.size(), h.precond = solver.precond, h.f_degree = solver.f_degree;
+    h.levels = Lh, h.nlev = nlev, h.nhist = nhist, h.x_order = x_order;
+    h.f_warm = fv ? (f64 ? amg64.f_warm : amg32.f_warm) : 0;
+    h.ale_ext_valid = ale_ext_valid;
+    h.ale_nodal = ale_nodal;
+    h.fv_elem = fv ? (f64 ? 8 : 4) : 0;
+    h.t = t;
+    h.step_index = step_index;
+    char *o = (char *)blob;
+    memcpy(o, &h, sizeof(h));
+    o += sizeof(h);
+    auto d2h = [&](const void *src, int64_t n) -> lx_status {
+        LX_HIP(hipMemcpyAsync(o, src, (size_t)n, hipMemcpyDeviceToHost, stream));
+        o += n;
+        return LX_OK;
+    };
+#define CK(x)                       \
+    do {                            \
+        lx_status _s = (x);         \
+        if (_s != LX_OK) return _s; \
+    } while (0)
+    for (int l = 0; l < Lh; ++l) CK(d2h(d_hist[l], N * 8));
+    memcpy(o, h_gnodal.data(), h_gnodal.size() * 8);
+    o += h_gnodal.size() * 8;
+    for (const auto &bc : bcs)
+        if (bc.d_hnodal) {
+            const double flag = bc.nodal_set ? 1.0 : 0.0;
+            memcpy(o, &flag, 8);
+            o += 8;
+            CK(d2h(bc.d_hnodal, 3 * nu * 8));
+        }
+    if (d_f) CK(d2h(d_f, 3 * nu * 8));
+    if (prob.ale) {
+        for (int l = 0; l < L; ++l) CK(d2h(d_dhist[l], 3 * nv * 8));
+        CK(d2h(d_cg, 3 * nv * 8));
+        CK(d2h(d_ale_shape, 3 * nv * 8));
+        CK(d2h(d_dbnd, 3 * nv * 8));
+    }
+    if (fv) CK(d2h(fv, 4 * nu * h.fv_elem));
+#undef CK
+    LX_HIP(hipStreamSynchronize(stream));
+    return LX_OK;
+}
+
+lx_status Sim::load_state(const void *blob, int64_t bytes)
+{
+    const int64_t need = state_bytes();
+    if (!blob || bytes != need) return fail(LX_EINVAL, "state blob of %lld bytes, this simulation needs %lld",
+                                            (long long)bytes, (long long)need);
+    CkHead h;
+    memcpy(&h, blob, sizeof(h));
+    const int L = prob.bdf_order, Lh = std::max(L, 4);
+    const bool f64 = solver.precision == LX_FP64;
+    void *fv = solver.precond == LX_PC_AMG ? (f64 ? (void *)amg64.fv : (void *)amg32.fv) : nullptr;
+    if (memcmp(h.magic, kCkMagic, 8) != 0 || h.bytes != need || h.nv != nv || h.nt != nt || h.nu != nu ||
+        h.N != N || h.nblk != nblk || h.n_dir != n_dir || h.fe != prob.fe || h.bdf_order != L ||
+        h.precision != solver.precision || h.ale != prob.ale || h.forcing != prob.forcing ||
+        h.n_bc != (int32_t)bcs.size() || h.precond != solver.precond || h.f_degree != solver.f_degree ||
+        h.levels != Lh || h.fv_elem != (fv ? (f64 ? 8 : 4) : 0))
+        return fail(LX_EINVAL, "state blob was saved by a simulation of another mesh, problem or solver");
+    if (h.nlev < 0 || h.nlev > L || h.nhist < 0 || h.nhist > Lh || h.x_order < 2 || h.x_order > 4)
+        return fail(LX_EINVAL, "state blob holds invalid counters");
+    LX_HIP(hipSetDevice(device));
+    const char *o = (const char *)blob + sizeof(h);
+    auto h2d = [&](void *dst, int64_t n) -> lx_status {
+        LX_HIP(hipMemcpyAsync(dst, o, (size_t)n, hipMemcpyHostToDevice, stream));
+        o += n;
+        return LX_OK;
+    };
+#define CK(x)                       \
+    do {                            \
+        lx_status _s = (x);         \
+        if (_s != LX_OK) return _s; \
+    } while (0)
+    for (int l = 0; l < Lh; ++l) CK(h2d(d_hist[l], N * 8));
+    memcpy(h_gnodal.data(), o, h_gnodal.size() * 8);
+    o += h_gnodal.size() * 8;
+    dirty_gnodal = true;
+    for (auto &bc : bcs)
+        if (bc.d_hnodal) {
+            double flag;
+            memcpy(&flag, o, 8);
+            o += 8;
+            bc.nodal_set = flag != 0.0;
+            CK(h2d(bc.d_hnodal, 3 * nu * 8));
+        }
+    if (d_f) CK(h2d(d_f, 3 * nu * 8));
+    if (prob.ale) {
+        for (int l = 0; l < L; ++l) CK(h2d(d_dhist[l], 3 * nv * 8));
+        CK(h2d(d_cg, 3 * nv * 8));
+        CK(h2d(d_ale_shape, 3 * nv * 8));
+        CK(h2d(d_dbnd, 3 * nv * 8));
+        ale_ext_valid = h.ale_ext_valid != 0;
+        ale_nodal = h.ale_nodal != 0;
+    }
+    if (fv) {
+        CK(h2d(fv, 4 * nu * h.fv_elem));
+        (f64 ? amg64.f_warm : amg32.f_warm) = h.f_warm != 0;
+    }
+#undef CK
+    LX_HIP(hipStreamSynchronize(stream));
+    t = h.t;
+    step_index = h.step_index;
+    nlev = h.nlev;
+    nhist = h.nhist;
+    x_order = h.x_order;
     return LX_OK;
 }
 

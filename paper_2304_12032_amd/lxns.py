@@ -38,8 +38,30 @@ class LxError(RuntimeError):
         self.status = status
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(c_vp, ctypes.c_size_t, c_vp)
+FREE_FN = ctypes.CFUNCTYPE(None, c_vp, c_vp)
+
+
 class lx_device(ctypes.Structure):
-    _fields_ = [("device", c_i32), ("hip_stream", c_vp)]
+    _fields_ = [("device", c_i32), ("hip_stream", c_vp), ("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", c_vp)]
+
+
+def torch_allocator(device=0, stream=None):
+    """(alloc, free) callbacks that take device memory from PyTorch's caching allocator on
+    `device` and `stream` (a hipStream_t as int, or None for the current stream).  Keep the
+    returned pair alive as long as the object that uses it."""
+    import torch
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+        except Exception:   # out of memory: the library reports LX_ENOMEM
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return ALLOC_FN(_alloc), FREE_FN(_free)
 
 
 class lx_mesh(ctypes.Structure):
@@ -129,8 +151,12 @@ SIGNATURES = {
     "lx_sim_set_neumann_traction": (c_i32, [c_vp, c_i32, c_vp]),
     "lx_sim_set_forcing": (c_i32, [c_vp, c_vp]),
     "lx_sim_set_ale_displacement": (c_i32, [c_vp, c_vp]),
+    "lx_sim_set_boundary_displacement": (c_i32, [c_vp, c_vp]),
     "lx_sim_step": (c_i32, [c_vp, P(lx_step_stats)]),
     "lx_sim_get_solution": (c_i32, [c_vp, c_vp, c_vp, P(c_dbl)]),
+    "lx_sim_state_size": (c_i32, [c_vp, P(c_i64)]),
+    "lx_sim_get_state": (c_i32, [c_vp, c_vp, c_i64]),
+    "lx_sim_restore_state": (c_i32, [c_vp, c_vp, c_i64]),
     "lx_sim_debug_export": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lx_sim_debug_export_p2": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lx_sim_debug_residual": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
@@ -260,11 +286,16 @@ class _Marshal:
 class Sim:
     """One simulation on one device (lx_sim_*)."""
 
-    def __init__(self, mesh, prob, solver, device=0, stream=None):
+    def __init__(self, mesh, prob, solver, device=0, stream=None, allocator=None):
+        """allocator: None (the library's hipMalloc) or an (alloc, free) pair of callbacks such as
+        torch_allocator(device, stream), kept alive with the object."""
         L = lib()
         self.m = _Marshal(mesh, prob, solver)
         self.nv = mesh.coords.shape[0]
+        self._allocator = allocator
         dev = lx_device(device, stream)
+        if allocator is not None:
+            dev.alloc, dev.free = allocator
         h = c_vp()
         check(L.lx_sim_create(ctypes.byref(dev), ctypes.byref(self.m.mesh), ctypes.byref(self.m.problem),
                               ctypes.byref(self.m.solver), ctypes.byref(h)))
@@ -317,6 +348,10 @@ class Sim:
         d = np.ascontiguousarray(d, dtype=np.float64)
         check(lib().lx_sim_set_ale_displacement(self.h, d.ctypes.data))
 
+    def set_boundary_displacement(self, d):
+        d = np.ascontiguousarray(d, dtype=np.float64)
+        check(lib().lx_sim_set_boundary_displacement(self.h, d.ctypes.data))
+
     def step(self, raise_on_fail=True):
         st = lx_step_stats()
         rc = lib().lx_sim_step(self.h, ctypes.byref(st))
@@ -346,6 +381,18 @@ class Sim:
         check(lib().lx_sim_debug_export_p2(self.h, rows.ctypes.data, cols.ctypes.data, vals.ctypes.data,
                                            rhs.ctypes.data))
         return rows, cols, vals, rhs
+
+    def get_state(self):
+        """Checkpoint blob (bytes) of the full time-stepping state."""
+        n = c_i64()
+        check(lib().lx_sim_state_size(self.h, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        check(lib().lx_sim_get_state(self.h, buf, n.value))
+        return buf.raw
+
+    def restore_state(self, blob):
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        check(lib().lx_sim_restore_state(self.h, buf, len(blob)))
 
     def solution(self):
         u = np.zeros((self.nu, 3))

@@ -142,3 +142,32 @@ def tube_ale_curved(nxy=4, nz=6, length=1.5, seed=2):
         pass
 
     return Case(mesh, prob, init, drive, "tube_ale_curved")
+
+
+def beltrami_ale(n=4, c=0.5, dt=0.01, nodal=True):
+    """The paper's ALE verification (Appendix A) on the unit cube: Beltrami flow on a mesh
+    moved by the harmonic extension of d^ = c sin(t) (sin pi x^, sin pi y^, sin pi z^)
+    (tangential on every face).  nodal: the boundary displacement is set for every step
+    (the lifting problem is solved each step); otherwise the sine law scales the shape."""
+    from inputs.meshes import CUBE_TAGS
+    mesh, prob = beltrami_cube_problem(n, dt=dt)
+    prob.ale = True
+    prob.ale_tags = tuple(CUBE_TAGS.values())
+    prob.ale_law = TimeLaw("constant", (1.0,)) if nodal else TimeLaw("sine", (c, 1.0, 0.0))
+    ex = exact.Beltrami(mu=prob.mu)
+    X = mesh.coords
+    D = np.sin(np.pi * X)
+
+    def init(s):
+        if not nodal:
+            s.set_ale_displacement(D)
+        s.set_state(0, ex.velocity(X, 0.0), ex.pressure(X, 0.0), np.zeros_like(X))
+
+    def drive(s, t1):
+        Xb = X + c * np.sin(t1) * D
+        if nodal:
+            s.set_boundary_displacement(c * np.sin(t1) * D)
+        s.set_dirichlet_values(0, ex.velocity(Xb, t1))
+        s.set_neumann_traction(1, ex.traction(Xb, t1, (-1, 0, 0)))
+
+    return Case(mesh, prob, init, drive, "beltrami_ale%d%s" % (n, "_nodal" if nodal else ""))

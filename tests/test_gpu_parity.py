@@ -151,3 +151,126 @@ def test_restart_matches_continuation(precision, stream):
         print("step %d: %d iterations, difference %.2e" % (k, st["gmres_iters"], e), flush=True)
     b.close()
     assert worst < (1e-10 if precision == "fp64" else 1e-8), worst
+
+
+# ------------------------------------------------------------------ C1 exactly
+
+def test_c1_beltrami_cube_fp64(stream):
+    """The Beltrami unit cube exactly as configured: 8^3 hexahedra Kuhn-split into 3,072
+    tets (729 vertices, N = 2,916), P1-P1 VMS-LES, nu = 0.01, BDF1, dt = 0.01, 10 steps.
+    Device GMRES at rtol 1e-14 against the oracle's dense LU, every step <= 1e-10 for u and
+    p separately; the device's final errors against the exact solution equal the oracle's."""
+    from oracle.errors import p1_errors
+    from inputs import exact
+    case = beltrami(8)
+    assert case.mesh.nt == 3072 and case.mesh.nv == 729
+    g = _gpu(case, stream, "fp64", rtol=1e-14)
+    o = OracleSim(case.mesh, case.prob, solve="dense")
+    for s in (g, o):
+        case.init(s)
+    worst = (0.0, 0.0)
+    for k in range(10):
+        t1 = o.t + case.prob.dt
+        for s in (g, o):
+            case.drive(s, t1)
+        st = g.step()
+        uo, po = o.step()
+        ug, pg, _ = g.solution()
+        eu, ep = rel_l2(ug, uo), rel_l2(pg, po)
+        worst = (max(worst[0], eu), max(worst[1], ep))
+        print("step", k, "iters", st["gmres_iters"], "res %.2e" % st["rel_residual"], "err u %.2e p %.2e" % (eu, ep),
+              flush=True)
+    g.close()
+    assert worst[0] < 1e-10 and worst[1] < 1e-10, worst
+    ex = exact.Beltrami(mu=case.prob.mu)
+    eg = np.array(p1_errors(case.mesh.coords, case.mesh.tets, ug, pg, ex, o.t))
+    eo = np.array(p1_errors(case.mesh.coords, case.mesh.tets, uo, po, ex, o.t))
+    print("errors vs exact (u L2, u H1, p L2): device", eg, "oracle", eo, flush=True)
+    assert np.abs(eg - eo).max() < 1e-8 * np.abs(eo).max()
+
+
+def test_beltrami_rates_on_device(stream):
+    """The device alone reproduces the expected space orders of the paper's Test I between
+    h = 1/4 and h = 1/8 (e_L2^u ~ 2, e_H1^u ~ 1, e_L2^p ~ 2)."""
+    import json
+    import os
+    from oracle.errors import p1_errors
+    from inputs import exact
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "convergence_orders.json")))["p1p1"]
+    errs = []
+    for n in (4, 8):
+        case = beltrami(n)
+        g = _gpu(case, stream, "fp32_ir", rtol=1e-10)
+        case.init(g)
+        for _ in range(10):
+            t1 = g.solution()[2] + case.prob.dt
+            case.drive(g, t1)
+            g.step()
+        u, p, t = g.solution()
+        g.close()
+        errs.append(np.array(p1_errors(case.mesh.coords, case.mesh.tets, u, p, exact.Beltrami(mu=case.prob.mu), t)))
+    rates = np.log2(errs[0] / errs[1])
+    print("device rates", rates, flush=True)
+    assert rates[0] > golden["u_L2"] - 0.15 and rates[1] > golden["u_H1"] - 0.1 and rates[2] > golden["p_L2"] - 0.2
+
+
+# ------------------------------------------------- the other preconditioners / assembly
+
+@pytest.mark.parametrize("schur_degree", [0, 16], ids=["plain_simple", "chebyshev_schur"])
+@pytest.mark.parametrize("mk", [CASES[0], CASES[1]], ids=IDS[:2])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_steps_parity_cheb_schur(mk, schur_degree, precision, stream):
+    """LX_PC_CHEB_SCHUR: block-Jacobi F~ with diag(S~)^{-1} (schur_degree 0, the plain
+    block-Jacobi SIMPLE of Sec. 2.4) or a Chebyshev iteration on S~."""
+    case = mk()
+    print("case", case.name, precision, "schur_degree", schur_degree, flush=True)
+    g = _gpu(case, stream, precision, rtol=1e-14 if precision == "fp64" else 1e-13, precond="cheb_schur",
+             schur_degree=schur_degree, schur_ratio=300.0)
+    o = OracleSim(case.mesh, case.prob)
+    for s in (g, o):
+        case.init(s)
+    worst = (0.0, 0.0)
+    for k in range(3):
+        t1 = o.t + case.prob.dt
+        for s in (g, o):
+            case.drive(s, t1)
+        st = g.step()
+        uo, po = o.step()
+        ug, pg, _ = g.solution()
+        eu, ep = rel_l2(ug, uo), rel_l2(pg, po)
+        worst = (max(worst[0], eu), max(worst[1], ep))
+        print("step", k, "iters", st["gmres_iters"], "err u %.2e p %.2e" % (eu, ep), flush=True)
+    g.close()
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    assert worst[0] < tol and worst[1] < tol, worst
+
+
+@pytest.mark.parametrize("mk", CASES[:3], ids=IDS[:3])
+def test_asm_fp64_parity(mk, stream):
+    """FP32 + refinement with the FP32 matrix built by FP64 element arithmetic and rounded
+    (asm_fp64): the matrix is the oracle's rounded to FP32 (<= 1e-7 row-wise) and the
+    refined steps match the oracle to <= 1e-8."""
+    case = mk()
+    print("case", case.name, flush=True)
+    g = _gpu(case, stream, "fp32_ir", rtol=1e-13, asm_fp64=True)
+    o = OracleSim(case.mesh, case.prob)
+    for s in (g, o):
+        case.init(s)
+        case.drive(s, case.prob.t0 + case.prob.dt)
+    br, bc, vals, _ = g.export()
+    o.assemble()
+    err = rowwise_rel_err(oracle_matrix_from_blocks(br, bc, vals, case.mesh.nv), o.matrix())
+    print("FP32 matrix from FP64 arithmetic: row-wise %.2e" % err, flush=True)
+    assert err < 1e-7, err
+    worst = (0.0, 0.0)
+    for k in range(3):
+        t1 = o.t + case.prob.dt
+        for s in (g, o):
+            case.drive(s, t1)
+        g.step()
+        uo, po = o.step()
+        ug, pg, _ = g.solution()
+        worst = (max(worst[0], rel_l2(ug, uo)), max(worst[1], rel_l2(pg, po)))
+    g.close()
+    print("steps: worst err u %.2e p %.2e" % worst, flush=True)
+    assert worst[0] < 1e-8 and worst[1] < 1e-8, worst
