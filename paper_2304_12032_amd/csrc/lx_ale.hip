@@ -280,6 +280,8 @@ lx_status Sim::ale_setup()
     ALLOC(d_cg, sizeof(double) * 3 * nv * 6 + sizeof(CgState));
     ALLOC(d_dnew, sizeof(double) * 3 * nv);
     ALLOC(d_dbnd, sizeof(double) * 3 * nv);
+    // reduction partials of the lifting CG (one row of 9 per workgroup of the row kernels)
+    ALLOC(d_cg_partial, sizeof(double) * 9 * ((nv * kAleLPR + 255) / 256));
 #undef ALLOC
     LX_HIP(hipMemcpyAsync(d_lap, Le.data(), sizeof(double) * nblk, hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_lapfull, L.data(), sizeof(double) * nblk, hipMemcpyHostToDevice, stream));
@@ -302,14 +304,7 @@ lx_status Sim::ale_extend(const double *data)
     const unsigned gvec = (unsigned)std::min<int64_t>((nv + 255) / 256, 1024);
     hipLaunchKernelGGL(k_ale_rhs, dim3(grow), dim3(256), 0, stream, nv, d_rowptr, d_col, d_lapfull, d_ale_mark,
                        data ? data : d_ale_shape, 1.0, rhs, ext);
-    double *part = d_partial;   // grow blocks * 9 doubles: use a dedicated region if larger
-    if ((int64_t)grow * 9 > (int64_t)nb_red * 64) {
-        if (!d_cg_partial) {
-            lx_status s = dalloc((void **)&d_cg_partial, sizeof(double) * grow * 9);
-            if (s != LX_OK) return s;
-        }
-        part = d_cg_partial;
-    }
+    double *part = d_cg_partial;   // grow blocks * 9 doubles
     hipLaunchKernelGGL(k_cg_init, dim3(grow), dim3(256), 0, stream, nv, d_rowptr, d_col, d_lap, d_lapdinv, rhs, ext,
                        r, z, p, cst, part, 1e-13);
     CgState h;

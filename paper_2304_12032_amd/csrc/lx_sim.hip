@@ -1349,7 +1349,7 @@ int64_t Sim::state_bytes() const
     if (prob.ale) b += (int64_t)(L + 3) * 3 * nv * 8;
     const bool f64 = solver.precision == LX_FP64;
     if (solver.precond == LX_PC_AMG && (f64 ? amg64.fv : (void *)amg32.fv))
-        b += 4 * nu * (f64 ? 8 : 4);
+        b += 4 * nu * (f64 ? 8 : 4) + kLamSlots * 8;   // the vector and the norm slots it is read with
     return b;
 }
 
@@ -1405,7 +1405,10 @@ lx_status Sim::save_state(void *blob, int64_t bytes)
         CK(d2h(d_ale_shape, 3 * nv * 8));
         CK(d2h(d_dbnd, 3 * nv * 8));
     }
-    if (fv) CK(d2h(fv, 4 * nu * h.fv_elem));
+    if (fv) {
+        CK(d2h(fv, 4 * nu * h.fv_elem));
+        CK(d2h(f64 ? amg64.lam : amg32.lam, kLamSlots * 8));
+    }
 #undef CK
     LX_HIP(hipStreamSynchronize(stream));
     return LX_OK;
@@ -1464,6 +1467,7 @@ lx_status Sim::load_state(const void *blob, int64_t bytes)
     }
     if (fv) {
         CK(h2d(fv, 4 * nu * h.fv_elem));
+        CK(h2d(f64 ? amg64.lam : amg32.lam, kLamSlots * 8));
         (f64 ? amg64.f_warm : amg32.f_warm) = h.f_warm != 0;
     }
 #undef CK

@@ -3,8 +3,8 @@ three steps of the 983,040-tet tube (the benchmark's mesh and problem) started
 from the Poiseuille field of the inflow rate at t0 = 0.25 s.
 
 Calls only the oracle (its assembly and its own GMRES + SIMPLE solve to a
-relative residual of 1e-13) and the seeded input generators.  A direct solve at
-this size is out of reach, so the oracle's iterative solve at 1e-13 stands in
+relative residual of 1e-14) and the seeded input generators.  A direct solve at
+this size is out of reach, so the oracle's iterative solve at 1e-14 stands in
 for x = A^{-1} b (Sec. 2.4 solver, run to a tolerance far below the parity
 bound).  Stored per step: the values at 2048 seeded vertices (u and p), the full
 L2 norms of u and p, the oracle's iteration count and final residual.
@@ -26,7 +26,7 @@ from inputs.problem import tube_problem, tube_poiseuille_state  # noqa: E402
 from inputs.rng import permutation                             # noqa: E402
 from oracle import OracleSim                                   # noqa: E402
 
-T0, STEPS, NSAMPLE, SAMPLE_SEED, RTOL = 0.25, 3, 2048, 77, 1e-13
+T0, STEPS, NSAMPLE, SAMPLE_SEED, RTOL = 0.25, 3, 2048, 77, 1e-14
 
 
 def main():
@@ -47,7 +47,7 @@ def main():
                       "u_norm": float(np.linalg.norm(u)), "p_norm": float(np.linalg.norm(p)),
                       "u": [[float(c) for c in u[v]] for v in sample], "p": [float(p[v]) for v in sample]})
     doc = {"_source": "oracle only: make_tube983k_oracle.py (tube 32x32x160 seed 0, tube_problem(t0=0.25), "
-                      "Poiseuille history at t0 and t0 - dt, oracle GMRES+SIMPLE to rtol 1e-13)",
+                      "Poiseuille history at t0 and t0 - dt, oracle GMRES+SIMPLE to rtol 1e-14)",
            "mesh": {"nxy": 32, "nz": 160, "seed": 0, "n_tets": int(mesh.nt), "n_vertices": int(mesh.nv)},
            "t0": T0, "oracle_rtol": RTOL, "sample_seed": SAMPLE_SEED,
            "vertices": [int(v) for v in sample], "steps": steps}

@@ -9,10 +9,13 @@ right-hand side are active (a start from rest leaves u* = 0 and r~ = 0 there).
     contributions that cancel, the bound is 1e-12 of the typical row maximum; the
     right-hand sides agree to <= 1e-12 (relative L2).
   * The first three steps against the oracle's own GMRES + SIMPLE solve at a
-    relative residual of 1e-13 (stored by tests/golden/make_tube983k_oracle.py,
+    relative residual of 1e-14 (stored by tests/golden/make_tube983k_oracle.py,
     which calls only the oracle): at 2048 seeded vertices and in the norms of the
-    whole fields, FP64 (device rtol 1e-13) <= 1e-10 and FP32 + FP64 refinement
-    (refined to 1e-12) <= 1e-8, u and p separately.
+    whole fields, FP64 (device rtol 1e-14) <= 1e-10 and FP32 + FP64 refinement
+    (refined to 1e-12) <= 1e-8, u and p separately.  Two solves at a relative
+    residual eps differ by about 1e3 eps in the pressure on this mesh (the RIIS
+    layer is thinner than the elements), and the difference carries over to the
+    next steps through the history, hence the tight solves.
   * At the benchmark's tolerance (1e-8) the FP64 and FP32 + refinement solutions
     of the first step solve the oracle's system: ||b - A x|| <= 2e-8 ||b|| with the
     oracle's A and b.
@@ -99,7 +102,7 @@ def test_fullsize_steps_match_oracle_solve(stream, precision):
     mesh = tube(nxy=32, nz=160, seed=0)
     assert mesh.nt == ref["mesh"]["n_tets"] and mesh.nv == ref["mesh"]["n_vertices"]
     prob = tube_problem(mesh, t0=T0)
-    g = _sim(mesh, prob, stream, precision, rtol=1e-13 if precision == "fp64" else 1e-12)
+    g = _sim(mesh, prob, stream, precision, rtol=1e-14 if precision == "fp64" else 1e-12)
     vs = np.array(ref["vertices"])
     tol = 1e-10 if precision == "fp64" else 1e-8
     worst = 0.0
