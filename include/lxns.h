@@ -343,6 +343,23 @@ lx_status lx_sim_debug_export_p2(lx_sim *sim, int32_t *rows, int32_t *cols, doub
  * x = (u [n][3], p [n]), written to r [n_vertices][4] (tests only; P1-P1). */
 lx_status lx_sim_debug_residual(lx_sim *sim, const double *u, const double *p, double *r);
 
+/* Allocation-free variant of lx_sim_debug_residual, for callers that cannot
+ * allocate device memory (code under stream or graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same FP64 matrix-free residual
+ * b - A x of the coming step (P1-P1), with u [n_vertices][3], p [n_vertices] and
+ * the output r [n_vertices][4] as DEVICE pointers on the simulation's device in
+ * the caller's numbering.  The work is queued on the simulation's stream (the
+ * call returns without waiting, except that an ALE lifting solve waits for its
+ * own convergence checks); read r after synchronising that stream.  The iterate,
+ * residual, right-hand side and element contributions live in a fixed 64 MiB
+ * device array that the library holds on every device it runs on until the
+ * process ends: meshes needing more (96 n_vertices + 384 n_tets bytes; about
+ * 160k tets) are rejected with LX_EINVAL.  All calls on one device share that
+ * array, which keeps the last call's contents: calls that overlap on one device
+ * (other streams, other threads) race and must be serialised by the caller.
+ * Nothing is allocated: no hipMalloc, hipFree or caller allocator call. */
+lx_status lx_sim_residual_noalloc(lx_sim *sim, const double *u, const double *p, double *r);
+
 void lx_sim_destroy(lx_sim *sim);
 
 /* ---------------------------------------------------------------- serving */

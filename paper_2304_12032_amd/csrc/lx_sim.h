@@ -70,6 +70,7 @@ struct Sim {
     int32_t *d_tet = nullptr, *d_rowptr = nullptr, *d_col = nullptr, *d_diag = nullptr,
             *d_tslot = nullptr;
     int32_t *d_dir_index = nullptr, *d_dir_node = nullptr, *d_dir_bc = nullptr;
+    int32_t *d_perm = nullptr;                                    // [nv] caller id of internal vertex i
     double *d_g = nullptr, *d_gnodal = nullptr, *d_dg = nullptr;
     double *d_hist[4] = {nullptr, nullptr, nullptr, nullptr};   // [nv][4] u^n, u^{n-1}, ...
     double *d_xs = nullptr;                                      // solution of the step in progress
@@ -169,6 +170,8 @@ struct Sim {
     lx_status build_system_p2(double t1, StepCoef &C);
     void add_neumann(double t1, double *out0, double *out1);
     lx_status residual64(const StepCoef &C, const double *xs, bool first, double t1);
+    lx_status residual64_into(const StepCoef &C, const double *xs, bool first, double t1, double *rec, double *r,
+                              double *b, bool timed);
     lx_status step(lx_step_stats *out);
 
     // checkpoint of everything the next step reads besides mesh, problem and solver
@@ -182,6 +185,12 @@ struct Sim {
     void ale_commit();
 };
 
+}  // namespace lx
+
+namespace lx {
+// Resolves, once per device (that device current), the device address of the
+// allocation-free entry point's static scratch array.
+lx_status noalloc_init(int device);
 }  // namespace lx
 
 struct lx_sim : public lx::Sim {};

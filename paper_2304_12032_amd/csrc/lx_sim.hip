@@ -237,6 +237,8 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         alloc_ctx = dev->ctx;
     }
     LX_HIP(hipSetDevice(device));
+    st = noalloc_init(device);
+    if (st != LX_OK) return st;
     if (dev && dev->hip_stream) {
         stream = (hipStream_t)dev->hip_stream;
         own_stream = false;
@@ -291,6 +293,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     ALLOC(d_diag, sizeof(int32_t) * nv);
     ALLOC(d_tslot, sizeof(int32_t) * nblk);
     ALLOC(d_dir_index, sizeof(int32_t) * nu);
+    ALLOC(d_perm, sizeof(int32_t) * nv);
     if (n_dir > 0) {
         ALLOC(d_dir_node, sizeof(int32_t) * n_dir);
         ALLOC(d_dir_bc, sizeof(int32_t) * n_dir);
@@ -399,6 +402,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     LX_HIP(hipMemcpyAsync(d_diag, hs.diag.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_tslot, hs.tslot.data(), sizeof(int32_t) * nblk, hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_dir_index, h_dir_index.data(), sizeof(int32_t) * nu, hipMemcpyHostToDevice, stream));
+    LX_HIP(hipMemcpyAsync(d_perm, hs.perm_v.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, stream));
     if (p2) {
         const P2Setup &q = p2h;
         auto up = [&](int32_t *d, const std::vector<int32_t> &h) {
@@ -1158,15 +1162,24 @@ lx_status Sim::residual64(const StepCoef &C, const double *xs, bool first, doubl
         LX_HIP(hipGetLastError());
         return LX_OK;
     }
+    return residual64_into(C, xs, first, t1, d_rrec, d_r64, d_b64, true);
+}
+
+// P1-P1 FP64 matrix-free residual into given buffers: element contributions in
+// rec [kRRec nt], r = b - A xs [nv][4] and (first) b [nv][4]; every entry of the
+// three is written before it is read.  timed: stamp the pass (collect_timing).
+lx_status Sim::residual64_into(const StepCoef &C, const double *xs, bool first, double t1, double *rec, double *r,
+                               double *b, bool timed)
+{
     // the vertex pass writes every row of r (and of b); Dirichlet diagonals are summed into dg
     if (first && n_dir > 0) launch_fill<double>(3 * n_dir, d_dg, 0.0, stream);
-    ResArgs R{nt, nv, d_tet, d_vinc_ptr, d_vpos, d_rrec, d_x, d_xh, hist(0), hist(1), hist(2), d_uA, d_f,
-              xs, d_dir_index, d_r64, first ? d_b64 : nullptr, first ? d_dg : nullptr};
-    auto *tm = timer_begin(2, 0);
+    ResArgs R{nt, nv, d_tet, d_vinc_ptr, d_vpos, rec, d_x, d_xh, hist(0), hist(1), hist(2), d_uA, d_f,
+              xs, d_dir_index, r, first ? b : nullptr, first ? d_dg : nullptr};
+    auto *tm = timed ? timer_begin(2, 0) : nullptr;
     launch_residual_p1(R, C, stream);
     timer_end(tm);
-    add_neumann(t1, d_r64, first ? d_b64 : nullptr);
-    launch_dirichlet_residual(n_dir, d_dir_node, d_g, d_dg, xs, d_r64, first ? d_b64 : nullptr, stream);
+    add_neumann(t1, r, first ? b : nullptr);
+    launch_dirichlet_residual(n_dir, d_dir_node, d_g, d_dg, xs, r, first ? b : nullptr, stream);
     LX_HIP(hipGetLastError());
     return LX_OK;
 }

@@ -160,6 +160,7 @@ SIGNATURES = {
     "lx_sim_debug_export": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lx_sim_debug_export_p2": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lx_sim_debug_residual": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
+    "lx_sim_residual_noalloc": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "lx_sim_destroy": (None, [c_vp]),
     "lx_server_create": (c_i32, [P(lx_server_cfg), P(c_vp)]),
     "lx_server_submit": (c_i32, [c_vp, P(lx_request), P(c_i64)]),
@@ -417,6 +418,12 @@ class Sim:
         r = np.zeros((self.nv, 4))
         check(lib().lx_sim_debug_residual(self.h, u.ctypes.data, p.ctypes.data, r.ctypes.data))
         return r
+
+
+def residual_noalloc(sim, u_dev, p_dev, r_dev):
+    """lx_sim_residual_noalloc on device pointers (ints): u [nv][3], p [nv], r [nv][4], caller
+    numbering; queued on the simulation's stream."""
+    check(lib().lx_sim_residual_noalloc(sim.h, c_vp(u_dev), c_vp(p_dev), c_vp(r_dev)))
 
 
 class Server:
