@@ -7,7 +7,10 @@
 //  * the velocity block F is approximated by a Chebyshev iteration on
 //    F~^{-1} F, F~ its nodal 3x3 diagonal blocks, whose upper bound comes from
 //    a few power iterations warm-started from the previous step.
-// Row kernels use LPR lanes per row and accumulate in FP64; every apply-phase
+// Row kernels use LPR lanes per row and accumulate in the working precision T
+// (FP32 for the inner solves of FP32 + refinement); FP64 stays in the scalar
+// bounds that place the Chebyshev intervals (Gershgorin maxima, power-iteration
+// norms) and in the dense inverse of the coarsest level.  Every apply-phase
 // kernel honours the GMRES done flag.
 #include <hip/hip_runtime.h>
 
@@ -69,13 +72,11 @@ __device__ inline int32_t find_col_lds(const int32_t *col, int32_t lo, int32_t h
 }
 
 template <typename T>
-__device__ inline double schur_term(const SimpleView<T> &V, const T *__restrict__ Dinv, int32_t k1, int32_t j,
-                                    int32_t kg)
+__device__ inline T schur_term(const SimpleView<T> &V, const T *__restrict__ Dinv, int32_t k1, int32_t j, int32_t kg)
 {
     const int64_t nu = V.nu;
-    return (double)V.Bv[k1] * (double)Dinv[j] * (double)V.Gv[kg] +
-           (double)V.Bv[V.bs + k1] * (double)Dinv[nu + j] * (double)V.Gv[V.gs + kg] +
-           (double)V.Bv[2 * V.bs + k1] * (double)Dinv[2 * nu + j] * (double)V.Gv[2 * V.gs + kg];
+    return V.Bv[k1] * Dinv[j] * V.Gv[kg] + V.Bv[V.bs + k1] * Dinv[nu + j] * V.Gv[V.gs + kg] +
+           V.Bv[2 * V.bs + k1] * Dinv[2 * nu + j] * V.Gv[2 * V.gs + kg];
 }
 
 template <typename T, int kSfRows, int kSfCap>
@@ -89,11 +90,11 @@ __global__ __launch_bounds__(256) void k_schur_form(SimpleView<T> V, const T *__
     __shared__ int32_t s_j[kSfWaves][kSfRows];
     __shared__ int32_t s_gb[kSfWaves][kSfRows];
     __shared__ int32_t s_cc[kSfWaves][kSfRows];
-    __shared__ double s_cv[kSfWaves][kSfRows];
+    __shared__ T s_cv[kSfWaves][kSfRows];
     __shared__ int32_t s_sc[kSfWaves][kSfOut];
-    __shared__ double s_acc[kSfWaves][kSfOut];
+    __shared__ T s_acc[kSfWaves][kSfOut];
     __shared__ int32_t s_tgt[kSfWaves][kSfCap];
-    __shared__ double s_val[kSfWaves][kSfCap];
+    __shared__ T s_val[kSfWaves][kSfCap];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t i = xcd_block() * kSfWaves + wv;
     const bool live = i < V.np;
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(256) void k_schur_form(SimpleView<T> V, const T *__
             }
             if (t < nc) {
                 s_cc[wv][t] = V.ccol[c0 + t];
-                s_cv[wv][t] = (double)V.Cv[c0 + t];
+                s_cv[wv][t] = V.Cv[c0 + t];
             }
         }
         for (int e = lane; e < ns; e += 64) s_sc[wv][e] = scol[e0 + e];
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(256) void k_schur_form(SimpleView<T> V, const T *__
                 kg[u] = q < total ? s_gb[wv][lo] + (q - off[lo]) : -1;
             }
             int32_t col[4];
-            double pv[4];
+            T pv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (kg[u] >= 0) {
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(256) void k_schur_form(SimpleView<T> V, const T *__
     for (int32_t e = e0 + lane; e < e1; e += 64) {
         const int32_t k = scol[e];
         const int32_t kc = find_col(V.ccol, c0, c1, k);
-        double acc = kc >= 0 ? (double)V.Cv[kc] : 0.0;
+        T acc = kc >= 0 ? V.Cv[kc] : 0.0;
         for (int32_t k1 = b0; k1 < b1; ++k1) {
             const int32_t j = V.bcol[k1];
             const int32_t kg = find_col(V.gcol, V.gptr[j], V.gptr[j + 1], k);
@@ -229,17 +230,17 @@ __global__ __launch_bounds__(256) void k_amg_rowinfo(int64_t n, const int32_t *_
     __shared__ double lds[4];
     const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
-    double s = 0;
+    T s = 0;
     if (row < n)
-        for (int32_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += LPR) s += fabs((double)val[k]);
-    s = group_sum<double, LPR>(s);
+        for (int32_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += LPR) s += fabs(val[k]);
+    s = group_sum<T, LPR>(s);
     double g = 0;
     if (row < n && lane == 0) {
         const int32_t dk = diag[row];
-        const double a = dk >= 0 ? (double)val[dk] : 0.0;
-        const double di = a != 0.0 ? 1.0 / a : 0.0;
-        dinv[row] = (T)di;
-        g = s * fabs(di);
+        const T a = dk >= 0 ? val[dk] : T(0);
+        const T di = a != T(0) ? T(1) / a : T(0);
+        dinv[row] = di;
+        g = (double)(s * fabs(di));
     }
     const double m = block_max(g, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = m;
@@ -267,9 +268,9 @@ __global__ __launch_bounds__(256) void k_amg_coarsen(int64_t nnzc, const int32_t
     const int64_t c = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (c >= nnzc) return;
-    double s = 0;
-    for (int32_t q = cptr[c] + lane; q < cptr[c + 1]; q += LPR) s += (double)fval[cidx[q]];
-    s = group_sum<double, LPR>(s);
+    T s = 0;
+    for (int32_t q = cptr[c] + lane; q < cptr[c + 1]; q += LPR) s += fval[cidx[q]];
+    s = group_sum<T, LPR>(s);
     if (lane == 0) cval[c] = (T)s;
 }
 
@@ -461,12 +462,12 @@ __global__ __launch_bounds__(256) void k_fpow(RowPattern P, const T *__restrict_
     const int lane = threadIdx.x % LPR;
     const int64_t nb = P.nblk, nv = P.nv;
     using V = typename V4<T>::type;
-    const double nin = v ? sqrt(lam[slot_in]) : sqrt(3.0 * (double)nv);
-    double t0 = 0, t1 = 0, t2 = 0;
+    const T nin = (T)(v ? sqrt(lam[slot_in]) : sqrt(3.0 * (double)nv));
+    T t0 = 0, t1 = 0, t2 = 0;
     if (row < nv)
         for (int32_t k = P.rowptr[row] + lane; k < P.rowptr[row + 1]; k += LPR) {
             const int32_t j = P.col[k];
-            double x0, x1, x2;
+            T x0, x1, x2;
             if (v) {
                 const V xv = reinterpret_cast<const V *>(v)[j];
                 x0 = xv.v[0];
@@ -477,21 +478,21 @@ __global__ __launch_bounds__(256) void k_fpow(RowPattern P, const T *__restrict_
                 x1 = pm_one(3u * (uint32_t)j + 1u);
                 x2 = pm_one(3u * (uint32_t)j + 2u);
             }
-            double a[9];
+            T a[9];
 #pragma unroll
-            for (int p = 0; p < 9; ++p) a[p] = (double)val[p * nb + k];
+            for (int p = 0; p < 9; ++p) a[p] = val[p * nb + k];
             t0 += a[0] * x0 + a[1] * x1 + a[2] * x2;
             t1 += a[3] * x0 + a[4] * x1 + a[5] * x2;
             t2 += a[6] * x0 + a[7] * x1 + a[8] * x2;
         }
-    t0 = group_sum<double, LPR>(t0);
-    t1 = group_sum<double, LPR>(t1);
-    t2 = group_sum<double, LPR>(t2);
+    t0 = group_sum<T, LPR>(t0);
+    t1 = group_sum<T, LPR>(t1);
+    t2 = group_sum<T, LPR>(t2);
     double acc[1] = {0.0};
     if (row < nv && lane == 0) {
-        double fi[9];
+        T fi[9];
 #pragma unroll
-        for (int p = 0; p < 9; ++p) fi[p] = (double)Finv[p * nv + row];
+        for (int p = 0; p < 9; ++p) fi[p] = Finv[p * nv + row];
         V o;
         o.v[0] = (T)((fi[0] * t0 + fi[1] * t1 + fi[2] * t2) / nin);
         o.v[1] = (T)((fi[3] * t0 + fi[4] * t1 + fi[5] * t2) / nin);
@@ -531,20 +532,20 @@ __global__ void k_fz_start(int64_t nv, const T *__restrict__ Finv, const T *__re
     if (done && *done) return;
     const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= nv) return;
-    const double sc = scale_ptr ? *scale_ptr : 1.0;
+    const T sc = scale_ptr ? *scale_ptr : 1.0;
     using V = typename V4<T>::type;
     const V rv = reinterpret_cast<const V *>(r)[i];
-    const double r0 = rv.v[0] * sc, r1 = rv.v[1] * sc, r2 = rv.v[2] * sc;
-    double fi[9];
+    const T r0 = rv.v[0] * sc, r1 = rv.v[1] * sc, r2 = rv.v[2] * sc;
+    T fi[9];
 #pragma unroll
-    for (int p = 0; p < 9; ++p) fi[p] = (double)Finv[p * nv + i];
-    double y0 = fi[0] * r0 + fi[1] * r1 + fi[2] * r2;
-    double y1 = fi[3] * r0 + fi[4] * r1 + fi[5] * r2;
-    double y2 = fi[6] * r0 + fi[7] * r1 + fi[8] * r2;
+    for (int p = 0; p < 9; ++p) fi[p] = Finv[p * nv + i];
+    T y0 = fi[0] * r0 + fi[1] * r1 + fi[2] * r2;
+    T y1 = fi[3] * r0 + fi[4] * r1 + fi[5] * r2;
+    T y2 = fi[6] * r0 + fi[7] * r1 + fi[8] * r2;
     V zv;
     if (degree > 1) {
-        double theta, a, b;
-        cheb_coef(*lamF, ratio, 0, theta, a, b);
+        T theta, a, b;
+        cheb_coef_t(*lamF, ratio, 0, theta, a, b);
         y0 /= theta;
         y1 /= theta;
         y2 /= theta;
@@ -587,32 +588,32 @@ __global__ __launch_bounds__(256) void k_fcheb(RowPattern P, const T *__restrict
     if (done_with(done, end)) return;
     const int64_t nb = P.nblk, nv = P.nv;
     using V = typename V4<T>::type;
-    double t0 = 0, t1 = 0, t2 = 0;
+    T t0 = 0, t1 = 0, t2 = 0;
     for (int32_t k = beg + lane; k < end; k += LPR) {
         const V xv = reinterpret_cast<const V *>(dcur)[P.col[k]];
-        const double x0 = xv.v[0], x1 = xv.v[1], x2 = xv.v[2];
-        double a[9];
+        const T x0 = xv.v[0], x1 = xv.v[1], x2 = xv.v[2];
+        T a[9];
 #pragma unroll
-        for (int p = 0; p < 9; ++p) a[p] = (double)val[p * nb + k];
+        for (int p = 0; p < 9; ++p) a[p] = val[p * nb + k];
         t0 += a[0] * x0 + a[1] * x1 + a[2] * x2;
         t1 += a[3] * x0 + a[4] * x1 + a[5] * x2;
         t2 += a[6] * x0 + a[7] * x1 + a[8] * x2;
     }
-    t0 = group_sum<double, LPR>(t0);
-    t1 = group_sum<double, LPR>(t1);
-    t2 = group_sum<double, LPR>(t2);
+    t0 = group_sum<T, LPR>(t0);
+    t1 = group_sum<T, LPR>(t1);
+    t2 = group_sum<T, LPR>(t2);
     if (lane != 0) return;
-    double theta, a, b;
-    cheb_coef(*lamF, ratio, step, theta, a, b);
+    T theta, a, b;
+    cheb_coef_t(*lamF, ratio, step, theta, a, b);
     V f = reinterpret_cast<V *>(fr)[row];
-    const double e0 = f.v[0] - t0, e1 = f.v[1] - t1, e2 = f.v[2] - t2;
+    const T e0 = f.v[0] - t0, e1 = f.v[1] - t1, e2 = f.v[2] - t2;
     f.v[0] = (T)e0;
     f.v[1] = (T)e1;
     f.v[2] = (T)e2;
     reinterpret_cast<V *>(fr)[row] = f;
-    double fi[9];
+    T fi[9];
 #pragma unroll
-    for (int p = 0; p < 9; ++p) fi[p] = (double)Finv[p * nv + row];
+    for (int p = 0; p < 9; ++p) fi[p] = Finv[p * nv + row];
     const V dc = reinterpret_cast<const V *>(dcur)[row];
     V dn;
     dn.v[0] = (T)(a * dc.v[0] + b * (fi[0] * e0 + fi[1] * e1 + fi[2] * e2));
@@ -621,9 +622,9 @@ __global__ __launch_bounds__(256) void k_fcheb(RowPattern P, const T *__restrict
     dn.v[3] = T(0);
     reinterpret_cast<V *>(dnext)[row] = dn;
     V zv = reinterpret_cast<V *>(z)[row];
-    zv.v[0] = (T)((double)zv.v[0] + dn.v[0]);
-    zv.v[1] = (T)((double)zv.v[1] + dn.v[1]);
-    zv.v[2] = (T)((double)zv.v[2] + dn.v[2]);
+    zv.v[0] = (T)(zv.v[0] + dn.v[0]);
+    zv.v[1] = (T)(zv.v[1] + dn.v[1]);
+    zv.v[2] = (T)(zv.v[2] + dn.v[2]);
     reinterpret_cast<V *>(z)[row] = zv;
 }
 
@@ -640,19 +641,19 @@ __global__ __launch_bounds__(256) void k_zp_amg(SimpleView<T> V, const T *__rest
     const int32_t beg = V.bptr[row], end = V.bptr[row + 1];
     if (done_with(done, end)) return;
     using VT = typename V4<T>::type;
-    double acc = 0;
+    T acc = 0;
     for (int32_t k = beg + lane; k < end; k += LPR) {
         const VT zj = reinterpret_cast<const VT *>(z)[V.bcol[k]];
-        acc += (double)V.Bv[k] * zj.v[0] + (double)V.Bv[V.bs + k] * zj.v[1] + (double)V.Bv[2 * V.bs + k] * zj.v[2];
+        acc += V.Bv[k] * zj.v[0] + V.Bv[V.bs + k] * zj.v[1] + V.Bv[2 * V.bs + k] * zj.v[2];
     }
-    acc = group_sum<double, LPR>(acc);
+    acc = group_sum<T, LPR>(acc);
     if (lane != 0) return;
-    const double t = (double)z[4 * row + 3] - acc;
+    const T t = z[4 * row + 3] - acc;
     L.r[row] = (T)t;
     if (smooth) {
-        double theta, a, b;
-        cheb_coef(*lam, ratio, 0, theta, a, b);
-        const T x = (T)((double)L.dinv[row] * t / theta);
+        T theta, a, b;
+        cheb_coef_t(*lam, ratio, 0, theta, a, b);
+        const T x = (T)(L.dinv[row] * t / theta);
         L.res[row] = (T)t;
         L.x0[row] = x;
         L.d0[row] = x;
@@ -670,22 +671,22 @@ __global__ __launch_bounds__(256) void k_xu_amg(SimpleView<T> V, const T *__rest
     const int32_t beg = V.gptr[row], end = V.gptr[row + 1];
     if (done_with(done, end)) return;
     const int64_t nu = V.nu;
-    double a0 = 0, a1 = 0, a2 = 0;
+    T a0 = 0, a1 = 0, a2 = 0;
     for (int32_t k = beg + lane; k < end; k += LPR) {
-        const double pj = p[V.gcol[k]];
-        a0 += (double)V.Gv[k] * pj;
-        a1 += (double)V.Gv[V.gs + k] * pj;
-        a2 += (double)V.Gv[2 * V.gs + k] * pj;
+        const T pj = p[V.gcol[k]];
+        a0 += V.Gv[k] * pj;
+        a1 += V.Gv[V.gs + k] * pj;
+        a2 += V.Gv[2 * V.gs + k] * pj;
     }
-    a0 = group_sum<double, LPR>(a0);
-    a1 = group_sum<double, LPR>(a1);
-    a2 = group_sum<double, LPR>(a2);
+    a0 = group_sum<T, LPR>(a0);
+    a1 = group_sum<T, LPR>(a1);
+    a2 = group_sum<T, LPR>(a2);
     if (lane != 0) return;
     using VT = typename V4<T>::type;
     VT zv = reinterpret_cast<VT *>(z)[row];
-    zv.v[0] = (T)((double)zv.v[0] - (double)Dinv[row] * a0);
-    zv.v[1] = (T)((double)zv.v[1] - (double)Dinv[nu + row] * a1);
-    zv.v[2] = (T)((double)zv.v[2] - (double)Dinv[2 * nu + row] * a2);
+    zv.v[0] = (T)(zv.v[0] - Dinv[row] * a0);
+    zv.v[1] = (T)(zv.v[1] - Dinv[nu + row] * a1);
+    zv.v[2] = (T)(zv.v[2] - Dinv[2 * nu + row] * a2);
     zv.v[3] = row < V.np ? p[row] : T(0);
     reinterpret_cast<VT *>(z)[row] = zv;
 }
@@ -702,13 +703,13 @@ __global__ __launch_bounds__(256) void k_amg_pre(AmgLevel<T> L, const T *__restr
     if (i >= L.n) return;
     const int32_t beg = mptr[i], end = mptr[i + 1];
     if (done_with(done, end)) return;
-    double s = 0;
-    for (int32_t q = beg + lane; q < end; q += LPR) s += (double)fres[mem[q]];
-    s = group_sum<double, LPR>(s);
+    T s = 0;
+    for (int32_t q = beg + lane; q < end; q += LPR) s += fres[mem[q]];
+    s = group_sum<T, LPR>(s);
     if (lane != 0) return;
-    double theta, a, b;
-    cheb_coef(*lam, ratio, 0, theta, a, b);
-    const T x = (T)((double)L.dinv[i] * s / theta);
+    T theta, a, b;
+    cheb_coef_t(*lam, ratio, 0, theta, a, b);
+    const T x = (T)(L.dinv[i] * s / theta);
     L.r[i] = (T)s;
     L.res[i] = (T)s;
     L.x0[i] = x;
@@ -726,18 +727,18 @@ __global__ __launch_bounds__(256) void k_amg_cheb(AmgLevel<T> L, T *__restrict__
     if (row >= L.n) return;
     const int32_t beg = L.rowptr[row], end = L.rowptr[row + 1];
     if (done_with(done, end)) return;
-    double q = 0;
+    T q = 0;
     for (int32_t k = beg + lane; k < end; k += LPR)
-        q += (double)L.val[k] * (double)dcur[L.col[k]];
-    q = group_sum<double, LPR>(q);
+        q += L.val[k] * dcur[L.col[k]];
+    q = group_sum<T, LPR>(q);
     if (lane != 0) return;
-    double theta, a, b;
-    cheb_coef(*lam, ratio, step, theta, a, b);
-    const double r = (double)L.res[row] - q;
+    T theta, a, b;
+    cheb_coef_t(*lam, ratio, step, theta, a, b);
+    const T r = L.res[row] - q;
     L.res[row] = (T)r;
-    const double dn = a * (double)dcur[row] + b * (double)L.dinv[row] * r;
+    const T dn = a * dcur[row] + b * L.dinv[row] * r;
     dnext[row] = (T)dn;
-    x[row] = (T)((double)x[row] + dn);
+    x[row] = (T)(x[row] + dn);
 }
 
 // The last Chebyshev step of a coarse level's visit, which also hands the finer
@@ -757,18 +758,18 @@ __global__ __launch_bounds__(256) void k_amg_cheb_prolong(AmgLevel<T> L, T *__re
     if (row >= L.n) return;
     const int32_t beg = L.rowptr[row], end = L.rowptr[row + 1];
     if (done_with(done, end)) return;
-    double q = 0;
+    T q = 0;
     for (int32_t k = beg + lane; k < end; k += LPR)
-        q += (double)L.val[k] * (double)dcur[L.col[k]];
-    q = group_sum<double, LPR>(q);   // every lane of the group holds the sum
-    double theta, a, b;
-    cheb_coef(*lam, ratio, step, theta, a, b);
-    const double r = (double)L.res[row] - q;
-    const double dn = a * (double)dcur[row] + b * (double)L.dinv[row] * r;
-    const T xn = (T)((double)x[row] + dn);
+        q += L.val[k] * dcur[L.col[k]];
+    q = group_sum<T, LPR>(q);   // every lane of the group holds the sum
+    T theta, a, b;
+    cheb_coef_t(*lam, ratio, step, theta, a, b);
+    const T r = L.res[row] - q;
+    const T dn = a * dcur[row] + b * L.dinv[row] * r;
+    const T xn = (T)(x[row] + dn);
     for (int32_t k = fmptr[row] + lane; k < fmptr[row + 1]; k += LPR) {
         const int32_t m = fmem[k];
-        xp[m] = (T)((double)fx0[m] + (double)xn);
+        xp[m] = (T)(fx0[m] + xn);
     }
     if (lane != 0) return;
     L.res[row] = (T)r;
@@ -785,11 +786,11 @@ __global__ __launch_bounds__(256) void k_amg_resid(AmgLevel<T> L, const T *__res
     if (row >= L.n) return;
     const int32_t beg = L.rowptr[row], end = L.rowptr[row + 1];
     if (done_with(done, end)) return;
-    double q = 0;
+    T q = 0;
     for (int32_t k = beg + lane; k < end; k += LPR)
-        q += (double)L.val[k] * (double)x[L.col[k]];
-    q = group_sum<double, LPR>(q);
-    if (lane == 0) L.res[row] = (T)((double)L.r[row] - q);
+        q += L.val[k] * x[L.col[k]];
+    q = group_sum<T, LPR>(q);
+    if (lane == 0) L.res[row] = (T)(L.r[row] - q);
 }
 
 // Coarse correction and first post-smoothing step: y = x0 + P e,
@@ -803,20 +804,20 @@ __global__ __launch_bounds__(256) void k_amg_post0(AmgLevel<T> L, const T *__res
     if (row >= L.n) return;
     const int32_t beg = L.rowptr[row], end = L.rowptr[row + 1];
     if (done_with(done, end)) return;
-    double q = 0;
+    T q = 0;
     for (int32_t k = beg + lane; k < end; k += LPR) {
         const int32_t j = L.col[k];
-        q += (double)L.val[k] * ((double)L.x0[j] + (double)e[L.agg[j]]);
+        q += L.val[k] * (L.x0[j] + e[L.agg[j]]);
     }
-    q = group_sum<double, LPR>(q);
+    q = group_sum<T, LPR>(q);
     if (lane != 0) return;
-    double theta, a, b;
-    cheb_coef(*lam, ratio, 0, theta, a, b);
-    const double r = (double)L.r[row] - q;
-    const double d = (double)L.dinv[row] * r / theta;
+    T theta, a, b;
+    cheb_coef_t(*lam, ratio, 0, theta, a, b);
+    const T r = L.r[row] - q;
+    const T d = L.dinv[row] * r / theta;
     L.res[row] = (T)r;
     L.d0[row] = (T)d;
-    L.x1[row] = (T)((double)L.x0[row] + (double)e[L.agg[row]] + d);
+    L.x1[row] = (T)(L.x0[row] + e[L.agg[row]] + d);
 }
 
 // Dense coarsest solve out = A^{-1} rc, rc the restriction of the finer
@@ -868,13 +869,13 @@ __global__ __launch_bounds__(256) void k_amg_rowinfo_sell(AmgLevel<T> L, double 
     if (row < L.n) {
         const int64_t base = L.soff[row >> 6] + (row & 63);
         const int w = L.swid[row >> 6];
-        double s = 0;
-        for (int j = 0; j < w; ++j) s += fabs((double)L.val[base + 64 * (int64_t)j]);
+        T s = 0;
+        for (int j = 0; j < w; ++j) s += fabs(L.val[base + 64 * (int64_t)j]);
         const int32_t dk = L.diag[row];
-        const double a = dk >= 0 ? (double)L.val[base + 64 * (int64_t)(dk - L.rowptr[row])] : 0.0;
-        const double di = a != 0.0 ? 1.0 / a : 0.0;
-        L.dinv[row] = (T)di;
-        g = s * fabs(di);
+        const T a = dk >= 0 ? L.val[base + 64 * (int64_t)(dk - L.rowptr[row])] : T(0);
+        const T di = a != T(0) ? T(1) / a : T(0);
+        L.dinv[row] = di;
+        g = (double)(s * fabs(di));
     }
     const double m = block_max(g, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = m;
@@ -887,23 +888,23 @@ __global__ __launch_bounds__(256) void k_amg_rowinfo_sell(AmgLevel<T> L, double 
 constexpr int kSellWaves = 4;
 
 template <typename T, bool D16, int SW, typename X>
-__device__ __forceinline__ double sell_slice_dot(const AmgLevel<T> &L, int64_t slice, int64_t sbase, int w, X xval,
-                                                 double (*part)[64])
+__device__ __forceinline__ T sell_slice_dot(const AmgLevel<T> &L, int64_t slice, int64_t sbase, int w, X xval,
+                                            T (*part)[64])
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t row = slice * 64 + lane;
-    double q = 0;
+    T q = 0;
     if (row < L.n) {
         const int64_t base = sbase + lane;
 #pragma unroll 4
         for (int j = wv; j < w; j += SW) {
             const int64_t p = base + 64 * (int64_t)j;
-            q += (double)L.val[p] * xval(sell_col<T, D16>(L, p, row));
+            q += L.val[p] * xval(sell_col<T, D16>(L, p, row));
         }
     }
     part[wv][lane] = q;
     __syncthreads();
-    double t = part[0][lane];
+    T t = part[0][lane];
 #pragma unroll
     for (int v = 1; v < SW; ++v) t += part[v][lane];
     return t;
@@ -915,61 +916,61 @@ __global__ __launch_bounds__(64 * SW) void k_amg_cheb_sell(AmgLevel<T> L, T *__r
                                                             const double *lam, double ratio, int step,
                                                             const int32_t *done)
 {
-    __shared__ double part[SW][64];
+    __shared__ T part[SW][64];
     const int64_t slice = xcd_block();
     const int64_t sbase = L.soff[slice];
     const int sw = L.swid[slice];
     if (done_with(done, sw + (int32_t)sbase)) return;
-    const double q =
-        sell_slice_dot<T, D16, SW>(L, slice, sbase, sw, [&](int32_t c) { return (double)dcur[c]; }, part);
+    const T q =
+        sell_slice_dot<T, D16, SW>(L, slice, sbase, sw, [&](int32_t c) { return dcur[c]; }, part);
     const int64_t row = slice * 64 + (threadIdx.x & 63);
     if (threadIdx.x >= 64 || row >= L.n) return;
-    double theta, a, b;
-    cheb_coef(*lam, ratio, step, theta, a, b);
-    const double r = (double)L.res[row] - q;
+    T theta, a, b;
+    cheb_coef_t(*lam, ratio, step, theta, a, b);
+    const T r = L.res[row] - q;
     L.res[row] = (T)r;
-    const double dn = a * (double)dcur[row] + b * (double)L.dinv[row] * r;
+    const T dn = a * dcur[row] + b * L.dinv[row] * r;
     dnext[row] = (T)dn;
-    x[row] = (T)((double)x[row] + dn);
+    x[row] = (T)(x[row] + dn);
 }
 
 template <typename T, bool D16, int SW>
 __global__ __launch_bounds__(64 * SW) void k_amg_resid_sell(AmgLevel<T> L, const T *__restrict__ x,
                                                              const int32_t *done)
 {
-    __shared__ double part[SW][64];
+    __shared__ T part[SW][64];
     const int64_t slice = xcd_block();
     const int64_t sbase = L.soff[slice];
     const int sw = L.swid[slice];
     if (done_with(done, sw + (int32_t)sbase)) return;
-    const double q = sell_slice_dot<T, D16, SW>(L, slice, sbase, sw, [&](int32_t c) { return (double)x[c]; }, part);
+    const T q = sell_slice_dot<T, D16, SW>(L, slice, sbase, sw, [&](int32_t c) { return x[c]; }, part);
     const int64_t row = slice * 64 + (threadIdx.x & 63);
     if (threadIdx.x >= 64 || row >= L.n) return;
-    L.res[row] = (T)((double)L.r[row] - q);
+    L.res[row] = (T)(L.r[row] - q);
 }
 
 template <typename T, bool D16, int SW>
 __global__ __launch_bounds__(64 * SW) void k_amg_post0_sell(AmgLevel<T> L, const T *__restrict__ e,
                                                              const double *lam, double ratio, const int32_t *done)
 {
-    __shared__ double part[SW][64];
+    __shared__ T part[SW][64];
     const int64_t slice = xcd_block();
     const int64_t sbase = L.soff[slice];
     const int sw = L.swid[slice];
     if (done_with(done, sw + (int32_t)sbase)) return;
     const T *x0 = L.x0;
     const int32_t *agg = L.agg;
-    const double q = sell_slice_dot<T, D16, SW>(
-        L, slice, sbase, sw, [&](int32_t c) { return (double)x0[c] + (double)e[agg[c]]; }, part);
+    const T q = sell_slice_dot<T, D16, SW>(
+        L, slice, sbase, sw, [&](int32_t c) { return x0[c] + e[agg[c]]; }, part);
     const int64_t row = slice * 64 + (threadIdx.x & 63);
     if (threadIdx.x >= 64 || row >= L.n) return;
-    double theta, a, b;
-    cheb_coef(*lam, ratio, 0, theta, a, b);
-    const double r = (double)L.r[row] - q;
-    const double d = (double)L.dinv[row] * r / theta;
+    T theta, a, b;
+    cheb_coef_t(*lam, ratio, 0, theta, a, b);
+    const T r = L.r[row] - q;
+    const T d = L.dinv[row] * r / theta;
     L.res[row] = (T)r;
     L.d0[row] = (T)d;
-    L.x1[row] = (T)((double)L.x0[row] + (double)e[L.agg[row]] + d);
+    L.x1[row] = (T)(L.x0[row] + e[L.agg[row]] + d);
 }
 
 // The same with the corrected iterate xp = x0 + P e already formed by the
@@ -978,22 +979,22 @@ template <typename T, bool D16, int SW>
 __global__ __launch_bounds__(64 * SW) void k_amg_post0_sell_xp(AmgLevel<T> L, const T *__restrict__ xp,
                                                                const double *lam, double ratio, const int32_t *done)
 {
-    __shared__ double part[SW][64];
+    __shared__ T part[SW][64];
     const int64_t slice = xcd_block();
     const int64_t sbase = L.soff[slice];
     const int sw = L.swid[slice];
     if (done_with(done, sw + (int32_t)sbase)) return;
-    const double q =
-        sell_slice_dot<T, D16, SW>(L, slice, sbase, sw, [&](int32_t c) { return (double)xp[c]; }, part);
+    const T q =
+        sell_slice_dot<T, D16, SW>(L, slice, sbase, sw, [&](int32_t c) { return xp[c]; }, part);
     const int64_t row = slice * 64 + (threadIdx.x & 63);
     if (threadIdx.x >= 64 || row >= L.n) return;
-    double theta, a, b;
-    cheb_coef(*lam, ratio, 0, theta, a, b);
-    const double r = (double)L.r[row] - q;
-    const double d = (double)L.dinv[row] * r / theta;
+    T theta, a, b;
+    cheb_coef_t(*lam, ratio, 0, theta, a, b);
+    const T r = L.r[row] - q;
+    const T d = L.dinv[row] * r / theta;
     L.res[row] = (T)r;
     L.d0[row] = (T)d;
-    L.x1[row] = (T)((double)xp[row] + d);
+    L.x1[row] = (T)(xp[row] + d);
 }
 
 // ================================================================== one-workgroup coarse cycle
@@ -1026,7 +1027,8 @@ __device__ __forceinline__ int32_t *lds_i(unsigned char *lds, int32_t o)
     return reinterpret_cast<int32_t *>(lds + o);
 }
 
-__device__ __forceinline__ double lane_sum(double v, int lanes)
+template <typename S>
+__device__ __forceinline__ S lane_sum(S v, int lanes)
 {
     for (int off = lanes >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, lanes);
     return v;
@@ -1034,11 +1036,11 @@ __device__ __forceinline__ double lane_sum(double v, int lanes)
 
 // sum_k val[k] x[col[k]] over the lane's share of row `row`
 template <typename T>
-__device__ __forceinline__ double tail_rowdot(const int32_t *rowptr, const int32_t *col, const T *val, const T *x,
-                                              int row, int lane, int lanes)
+__device__ __forceinline__ T tail_rowdot(const int32_t *rowptr, const int32_t *col, const T *val, const T *x, int row,
+                                         int lane, int lanes)
 {
-    double q = 0;
-    for (int32_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += lanes) q += (double)val[k] * (double)x[col[k]];
+    T q = 0;
+    for (int32_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += lanes) q += val[k] * x[col[k]];
     return lane_sum(q, lanes);
 }
 
@@ -1053,8 +1055,8 @@ __device__ __forceinline__ void tail_pre_global(const TailArgs<T> &A, const Tail
     T *r = lds_v<T>(lds, L.o_r), *res = lds_v<T>(lds, L.o_res), *x0 = lds_v<T>(lds, L.o_x0),
       *d0 = lds_v<T>(lds, L.o_d0);
     const T *dinv = lds_v<T>(lds, L.o_dinv);
-    double theta, a, b;
-    cheb_coef(lam, A.ratio, 0, theta, a, b);
+    T theta, a, b;
+    cheb_coef_t(lam, A.ratio, 0, theta, a, b);
     const bool in_lds = A.lay.o_fmem >= 0;
     const int32_t *fmptr = in_lds ? lds_i(lds, A.lay.o_fmptr) : A.fmptr;
     const int32_t *fmem = in_lds ? lds_i(lds, A.lay.o_fmem) : A.fmem;
@@ -1078,11 +1080,11 @@ __device__ __forceinline__ void tail_pre_global(const TailArgs<T> &A, const Tail
         }
         __syncthreads();
         for (int i = threadIdx.x / lanes; i < L.n; i += kTailThreads / lanes) {
-            double s = 0;
-            for (int32_t q = fmptr[i] + lane; q < fmptr[i + 1]; q += lanes) s += (double)stage[q];
+            T s = 0;
+            for (int32_t q = fmptr[i] + lane; q < fmptr[i + 1]; q += lanes) s += stage[q];
             s = lane_sum(s, lanes);
             if (lane == 0) {
-                const T x = (T)((double)dinv[i] * s / theta);
+                const T x = (T)(dinv[i] * s / theta);
                 r[i] = (T)s;
                 res[i] = (T)s;
                 x0[i] = x;
@@ -1093,7 +1095,7 @@ __device__ __forceinline__ void tail_pre_global(const TailArgs<T> &A, const Tail
     }
     for (int i = threadIdx.x / lanes; i < L.n; i += kTailThreads / lanes) {
         const int32_t q0 = fmptr[i], q1 = fmptr[i + 1];
-        double s = 0;
+        T s = 0;
         for (int32_t q = q0 + lane; q < q1; q += 8 * lanes) {
             int32_t idx[8];
 #pragma unroll
@@ -1102,11 +1104,11 @@ __device__ __forceinline__ void tail_pre_global(const TailArgs<T> &A, const Tail
 #pragma unroll
             for (int u = 0; u < 8; ++u) v[u] = idx[u] >= 0 ? A.fres[idx[u]] : T(0);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) s += (double)v[u];
+            for (int u = 0; u < 8; ++u) s += v[u];
         }
         s = lane_sum(s, lanes);
         if (lane == 0) {
-            const T x = (T)((double)dinv[i] * s / theta);
+            const T x = (T)(dinv[i] * s / theta);
             r[i] = (T)s;
             res[i] = (T)s;
             x0[i] = x;
@@ -1126,14 +1128,14 @@ __device__ __forceinline__ void tail_pre_lds(const TailArgs<T> &A, const TailLev
     T *r = lds_v<T>(lds, L.o_r), *res = lds_v<T>(lds, L.o_res), *x0 = lds_v<T>(lds, L.o_x0),
       *d0 = lds_v<T>(lds, L.o_d0);
     const T *dinv = lds_v<T>(lds, L.o_dinv);
-    double theta, a, b;
-    cheb_coef(lam, A.ratio, 0, theta, a, b);
+    T theta, a, b;
+    cheb_coef_t(lam, A.ratio, 0, theta, a, b);
     for (int i = threadIdx.x / lanes; i < L.n; i += kTailThreads / lanes) {
-        double s = 0;
-        for (int32_t q = mptr[i] + lane; q < mptr[i + 1]; q += lanes) s += (double)fres[mem[q]];
+        T s = 0;
+        for (int32_t q = mptr[i] + lane; q < mptr[i + 1]; q += lanes) s += fres[mem[q]];
         s = lane_sum(s, lanes);
         if (lane == 0) {
-            const T x = (T)((double)dinv[i] * s / theta);
+            const T x = (T)(dinv[i] * s / theta);
             r[i] = (T)s;
             res[i] = (T)s;
             x0[i] = x;
@@ -1151,16 +1153,16 @@ __device__ __forceinline__ void tail_cheb(const TailArgs<T> &A, const TailLevelL
     const int32_t *rowptr = lds_i(lds, L.o_rowptr), *col = lds_i(lds, L.o_col);
     const T *val = lds_v<T>(lds, L.o_val), *dinv = lds_v<T>(lds, L.o_dinv);
     T *res = lds_v<T>(lds, L.o_res);
-    double theta, a, b;
-    cheb_coef(lam, A.ratio, step, theta, a, b);
+    T theta, a, b;
+    cheb_coef_t(lam, A.ratio, step, theta, a, b);
     for (int row = threadIdx.x / lanes; row < L.n; row += kTailThreads / lanes) {
-        const double q = tail_rowdot(rowptr, col, val, dc, row, lane, lanes);
+        const T q = tail_rowdot(rowptr, col, val, dc, row, lane, lanes);
         if (lane == 0) {
-            const double rr = (double)res[row] - q;
+            const T rr = res[row] - q;
             res[row] = (T)rr;
-            const double d = a * (double)dc[row] + b * (double)dinv[row] * rr;
+            const T d = a * dc[row] + b * dinv[row] * rr;
             dn[row] = (T)d;
-            x[row] = (T)((double)x[row] + d);
+            x[row] = (T)(x[row] + d);
         }
     }
 }
@@ -1174,8 +1176,8 @@ __device__ __forceinline__ void tail_resid(const TailLevelLds &L, unsigned char 
     const T *val = lds_v<T>(lds, L.o_val), *r = lds_v<T>(lds, L.o_r);
     T *res = lds_v<T>(lds, L.o_res);
     for (int row = threadIdx.x / lanes; row < L.n; row += kTailThreads / lanes) {
-        const double q = tail_rowdot(rowptr, col, val, x, row, lane, lanes);
-        if (lane == 0) res[row] = (T)((double)r[row] - q);
+        const T q = tail_rowdot(rowptr, col, val, x, row, lane, lanes);
+        if (lane == 0) res[row] = (T)(r[row] - q);
     }
 }
 
@@ -1188,21 +1190,21 @@ __device__ __forceinline__ void tail_post0(const TailArgs<T> &A, const TailLevel
     const int32_t *rowptr = lds_i(lds, L.o_rowptr), *col = lds_i(lds, L.o_col), *agg = lds_i(lds, L.o_agg);
     const T *val = lds_v<T>(lds, L.o_val), *dinv = lds_v<T>(lds, L.o_dinv), *r = lds_v<T>(lds, L.o_r);
     T *res = lds_v<T>(lds, L.o_res), *d0 = lds_v<T>(lds, L.o_d0);
-    double theta, a, b;
-    cheb_coef(lam, A.ratio, 0, theta, a, b);
+    T theta, a, b;
+    cheb_coef_t(lam, A.ratio, 0, theta, a, b);
     for (int row = threadIdx.x / lanes; row < L.n; row += kTailThreads / lanes) {
-        double q = 0;
+        T q = 0;
         for (int32_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += lanes) {
             const int32_t j = col[k];
-            q += (double)val[k] * ((double)xa[j] + (double)e[agg[j]]);
+            q += val[k] * (xa[j] + e[agg[j]]);
         }
         q = lane_sum(q, lanes);
         if (lane == 0) {
-            const double rr = (double)r[row] - q;
-            const double d = (double)dinv[row] * rr / theta;
+            const T rr = r[row] - q;
+            const T d = dinv[row] * rr / theta;
             res[row] = (T)rr;
             d0[row] = (T)d;
-            xb[row] = (T)((double)xa[row] + (double)e[agg[row]] + d);
+            xb[row] = (T)(xa[row] + e[agg[row]] + d);
         }
     }
 }

@@ -120,6 +120,17 @@ __device__ inline void cheb_coef(double lmax, double ratio, int i, double &theta
     b = 2.0 * rho / delta;
 }
 
+// The same scalars rounded to the working precision T of the pass that uses them.
+template <typename T>
+__device__ inline void cheb_coef_t(double lmax, double ratio, int i, T &theta, T &a, T &b)
+{
+    double t, x, y;
+    cheb_coef(lmax, ratio, i, t, x, y);
+    theta = (T)t;
+    a = (T)x;
+    b = (T)y;
+}
+
 template <typename T>
 __device__ inline double to_d(T v) { return (double)v; }
 

@@ -350,24 +350,24 @@ __global__ __launch_bounds__(256) void k_element_p1(AsmArgs<T> A, StepCoef C)
 //   G_c  = -|K|/4 dphi_a,c + dphi_b,c Z_a + (dphi_a . dphi_b) W_c
 //   B_c  =  |K|/4 dphi_b,c + dphi_a,c S_b
 //   C    = (sum tau_M w) (dphi_a . dphi_b)
-// Sums run in FP64 and each plane entry is written once (no atomics).  With
+// Sums run in T (the assembly precision) and each plane entry is written once (no atomics).  With
 // RHS, the diagonal slot of vertex i also gathers the vertex's right-hand side.
 template <typename T, bool RHS>
 __global__ __launch_bounds__(256) void k_gather_p1(AsmArgs<T> A, int symgrad)
 {
     const int64_t k = xcd_block() * blockDim.x + threadIdx.x;
     if (k >= A.nblk) return;
-    double acc[16];
+    T acc[16];
 #pragma unroll
     for (int p = 0; p < 16; ++p) acc[p] = 0;
-    double racc[4] = {0, 0, 0, 0};
+    T racc[4] = {0, 0, 0, 0};
     int32_t vrow = -1;
     for (int32_t q = A.sinc_ptr[k]; q < A.sinc_ptr[k + 1]; ++q) {
         const int32_t code = A.sinc[q];
         const int64_t e = code >> 4;
         const int a = (code >> 2) & 3, b = code & 3;
         const T *R = A.rec + e * kRec;
-        double da[3], db[3], Yb[3], W[3];
+        T da[3], db[3], Yb[3], W[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             da[c] = R[kRDphi + 3 * a + c];
@@ -375,15 +375,15 @@ __global__ __launch_bounds__(256) void k_gather_p1(AsmArgs<T> A, int symgrad)
             Yb[c] = R[kRY + 3 * b + c];
             W[c] = R[kRW + c];
         }
-        const double Xab = R[kRX + 4 * a + b], Za = R[kRZ + a], Sb = R[kRS + b];
-        const double TC = R[kRTC], TM = R[kRTM], w1 = R[kRW1];
-        const double mv = symgrad ? (double)R[kRMV] : 0.0;
-        const double gab = da[0] * db[0] + da[1] * db[1] + da[2] * db[2];
+        const T Xab = R[kRX + 4 * a + b], Za = R[kRZ + a], Sb = R[kRS + b];
+        const T TC = R[kRTC], TM = R[kRTM], w1 = R[kRW1];
+        const T mv = symgrad ? R[kRMV] : T(0);
+        const T gab = da[0] * db[0] + da[1] * db[1] + da[2] * db[2];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                double F = da[d] * Yb[c] + TC * da[c] * db[d] + mv * db[c] * da[d];
+                T F = da[d] * Yb[c] + TC * da[c] * db[d] + mv * db[c] * da[d];
                 if (c == d) F += Xab;
                 acc[3 * c + d] += F;
             }
@@ -729,25 +729,25 @@ __global__ __launch_bounds__(256) void k_simple_setup(RowPattern P, const T *val
     if (i >= P.nv) return;
     const int64_t nb = P.nblk, nv = P.nv, dk = P.diag[i];
     if (Sinv) {
-        double s = 0;
+        T s = 0;
         for (int64_t k = P.rowptr[i] + lane; k < P.rowptr[i + 1]; k += LPR) {
             const int64_t j = P.col[k], ts = P.tslot[k], dj = P.diag[j];
             for (int d = 0; d < 3; ++d)
-                s += (double)val[(12 + d) * nb + k] * (double)val[(9 + d) * nb + ts] / (double)val[(4 * d) * nb + dj];
+                s += val[(12 + d) * nb + k] * val[(9 + d) * nb + ts] / val[(4 * d) * nb + dj];
         }
-        s = group_sum<double, LPR>(s);
-        if (lane == 0) Sinv[i] = (T)(1.0 / ((double)val[15 * nb + dk] - s));
+        s = group_sum<T, LPR>(s);
+        if (lane == 0) Sinv[i] = T(1) / (val[15 * nb + dk] - s);
     }
     if (lane != 0) return;
-    double A[9];
-    for (int p = 0; p < 9; ++p) A[p] = (double)val[p * nb + dk];
-    double c0 = A[4] * A[8] - A[5] * A[7], c1 = A[5] * A[6] - A[3] * A[8], c2 = A[3] * A[7] - A[4] * A[6];
-    double id = 1.0 / (A[0] * c0 + A[1] * c1 + A[2] * c2);
-    double B[9] = {c0 * id, (A[2] * A[7] - A[1] * A[8]) * id, (A[1] * A[5] - A[2] * A[4]) * id,
-                   c1 * id, (A[0] * A[8] - A[2] * A[6]) * id, (A[2] * A[3] - A[0] * A[5]) * id,
-                   c2 * id, (A[1] * A[6] - A[0] * A[7]) * id, (A[0] * A[4] - A[1] * A[3]) * id};
+    T A[9];
+    for (int p = 0; p < 9; ++p) A[p] = val[p * nb + dk];
+    T c0 = A[4] * A[8] - A[5] * A[7], c1 = A[5] * A[6] - A[3] * A[8], c2 = A[3] * A[7] - A[4] * A[6];
+    T id = T(1) / (A[0] * c0 + A[1] * c1 + A[2] * c2);
+    T B[9] = {c0 * id, (A[2] * A[7] - A[1] * A[8]) * id, (A[1] * A[5] - A[2] * A[4]) * id,
+              c1 * id, (A[0] * A[8] - A[2] * A[6]) * id, (A[2] * A[3] - A[0] * A[5]) * id,
+              c2 * id, (A[1] * A[6] - A[0] * A[7]) * id, (A[0] * A[4] - A[1] * A[3]) * id};
     for (int p = 0; p < 9; ++p) Finv[p * nv + i] = (T)B[p];
-    for (int c = 0; c < 3; ++c) Dinv[c * nv + i] = (T)(1.0 / A[4 * c]);
+    for (int c = 0; c < 3; ++c) Dinv[c * nv + i] = T(1) / A[4 * c];
 }
 
 // Sinv may be null (the AMG Schur block does not use diag(S~)).
@@ -881,21 +881,20 @@ __global__ __launch_bounds__(256) void k_simple_zp(RowPattern P, const T *val, c
     const int64_t nb = P.nblk;
     const int32_t beg = P.rowptr[row], end = P.rowptr[row + 1];
     using V = typename V4<T>::type;
-    double acc = 0;
+    T acc = 0;
     for (int32_t k = beg + lane; k < end; k += LPR) {
         const V zj = reinterpret_cast<const V *>(z)[P.col[k]];
-        acc += (double)val[12 * nb + k] * zj.v[0] + (double)val[13 * nb + k] * zj.v[1] +
-               (double)val[14 * nb + k] * zj.v[2];
+        acc += val[12 * nb + k] * zj.v[0] + val[13 * nb + k] * zj.v[1] + val[14 * nb + k] * zj.v[2];
     }
-    acc = group_sum<double, LPR>(acc);
+    acc = group_sum<T, LPR>(acc);
     if (lane == 0) {
-        const T t = (T)((double)z[4 * row + 3] - acc);
+        const T t = (T)(z[4 * row + 3] - acc);
         if (degree == 0) {
             z[4 * row + 3] = Sinv[row] * t;
         } else {
             double theta, a, b;
             cheb_coef(st->lam_max, ratio, 0, theta, a, b);
-            const T d = (T)((double)(Sinv[row] * t) / theta);
+            const T d = Sinv[row] * t / (T)theta;
             rc[row] = t;
             cur[4 * row + 3] = d;
             z[4 * row + 3] = d;
@@ -913,20 +912,20 @@ __global__ __launch_bounds__(256) void k_cheb_gd(RowPattern P, const T *val, con
     const int lane = threadIdx.x % LPR;
     if (row >= P.nv) return;
     const int64_t nb = P.nblk, nv = P.nv;
-    double a0 = 0, a1 = 0, a2 = 0;
+    T a0 = 0, a1 = 0, a2 = 0;
     for (int32_t k = P.rowptr[row] + lane; k < P.rowptr[row + 1]; k += LPR) {
-        const double dj = cur[4 * (int64_t)P.col[k] + 3];
-        a0 += (double)val[9 * nb + k] * dj;
-        a1 += (double)val[10 * nb + k] * dj;
-        a2 += (double)val[11 * nb + k] * dj;
+        const T dj = cur[4 * (int64_t)P.col[k] + 3];
+        a0 += val[9 * nb + k] * dj;
+        a1 += val[10 * nb + k] * dj;
+        a2 += val[11 * nb + k] * dj;
     }
-    a0 = group_sum<double, LPR>(a0);
-    a1 = group_sum<double, LPR>(a1);
-    a2 = group_sum<double, LPR>(a2);
+    a0 = group_sum<T, LPR>(a0);
+    a1 = group_sum<T, LPR>(a1);
+    a2 = group_sum<T, LPR>(a2);
     if (lane == 0) {
-        cur[4 * row + 0] = (T)((double)Dinv[row] * a0);
-        cur[4 * row + 1] = (T)((double)Dinv[nv + row] * a1);
-        cur[4 * row + 2] = (T)((double)Dinv[2 * nv + row] * a2);
+        cur[4 * row + 0] = (T)(Dinv[row] * a0);
+        cur[4 * row + 1] = (T)(Dinv[nv + row] * a1);
+        cur[4 * row + 2] = (T)(Dinv[2 * nv + row] * a2);
     }
 }
 
@@ -943,22 +942,21 @@ __global__ __launch_bounds__(256) void k_cheb_step(RowPattern P, const T *val, c
     if (row >= P.nv) return;
     const int64_t nb = P.nblk;
     using V = typename V4<T>::type;
-    double q = 0;
+    T q = 0;
     for (int32_t k = P.rowptr[row] + lane; k < P.rowptr[row + 1]; k += LPR) {
         const V c = reinterpret_cast<const V *>(cur)[P.col[k]];
-        q += (double)val[15 * nb + k] * c.v[3] - ((double)val[12 * nb + k] * c.v[0] +
-                                                  (double)val[13 * nb + k] * c.v[1] +
-                                                  (double)val[14 * nb + k] * c.v[2]);
+        q += val[15 * nb + k] * c.v[3] -
+             (val[12 * nb + k] * c.v[0] + val[13 * nb + k] * c.v[1] + val[14 * nb + k] * c.v[2]);
     }
-    q = group_sum<double, LPR>(q);
+    q = group_sum<T, LPR>(q);
     if (lane == 0) {
         double theta, a, b;
         cheb_coef(st->lam_max, ratio, i, theta, a, b);
-        const double r = (double)rc[row] - q;
-        rc[row] = (T)r;
-        const double dnew = a * (double)cur[4 * row + 3] + b * (double)Sinv[row] * r;
+        const T r = rc[row] - q;
+        rc[row] = r;
+        const T dnew = (T)a * cur[4 * row + 3] + (T)b * Sinv[row] * r;
         next[4 * row + 3] = (T)dnew;
-        z[4 * row + 3] = (T)((double)z[4 * row + 3] + dnew);
+        z[4 * row + 3] = (T)(z[4 * row + 3] + dnew);
     }
 }
 
@@ -973,20 +971,20 @@ __global__ __launch_bounds__(256) void k_simple_xu(RowPattern P, const T *val, c
     if (row >= P.nv) return;
     const int64_t nb = P.nblk, nv = P.nv;
     const int32_t beg = P.rowptr[row], end = P.rowptr[row + 1];
-    double a0 = 0, a1 = 0, a2 = 0;
+    T a0 = 0, a1 = 0, a2 = 0;
     for (int32_t k = beg + lane; k < end; k += LPR) {
-        const double zp = z[4 * (int64_t)P.col[k] + 3];
-        a0 += (double)val[9 * nb + k] * zp;
-        a1 += (double)val[10 * nb + k] * zp;
-        a2 += (double)val[11 * nb + k] * zp;
+        const T zp = z[4 * (int64_t)P.col[k] + 3];
+        a0 += val[9 * nb + k] * zp;
+        a1 += val[10 * nb + k] * zp;
+        a2 += val[11 * nb + k] * zp;
     }
-    a0 = group_sum<double, LPR>(a0);
-    a1 = group_sum<double, LPR>(a1);
-    a2 = group_sum<double, LPR>(a2);
+    a0 = group_sum<T, LPR>(a0);
+    a1 = group_sum<T, LPR>(a1);
+    a2 = group_sum<T, LPR>(a2);
     if (lane == 0) {
-        z[4 * row + 0] = (T)((double)z[4 * row + 0] - (double)Dinv[row] * a0);
-        z[4 * row + 1] = (T)((double)z[4 * row + 1] - (double)Dinv[nv + row] * a1);
-        z[4 * row + 2] = (T)((double)z[4 * row + 2] - (double)Dinv[2 * nv + row] * a2);
+        z[4 * row + 0] = (T)(z[4 * row + 0] - Dinv[row] * a0);
+        z[4 * row + 1] = (T)(z[4 * row + 1] - Dinv[nv + row] * a1);
+        z[4 * row + 2] = (T)(z[4 * row + 2] - Dinv[2 * nv + row] * a2);
     }
 }
 
@@ -1052,23 +1050,23 @@ __global__ __launch_bounds__(256) void k_spmv(RowPattern P, const T *__restrict_
     const int32_t beg = P.rowptr[row], end = P.rowptr[row + 1];
     if (done_with(done, end)) return;
     using V = typename V4<T>::type;
-    // products of two T values are exact in FP64; sums are accumulated in FP64
-    double y0 = 0, y1 = 0, y2 = 0, y3 = 0;
+    // sums in the working precision T (FP32 inner solves accumulate in FP32)
+    T y0 = 0, y1 = 0, y2 = 0, y3 = 0;
     for (int32_t k = beg + lane; k < end; k += LPR) {
         const V xv = reinterpret_cast<const V *>(x)[P.col[k]];
-        const double x0 = xv.v[0], x1 = xv.v[1], x2 = xv.v[2], x3 = xv.v[3];
-        double a[16];
+        const T x0 = xv.v[0], x1 = xv.v[1], x2 = xv.v[2], x3 = xv.v[3];
+        T a[16];
 #pragma unroll
-        for (int p = 0; p < 16; ++p) a[p] = (double)val[p * nb + k];
+        for (int p = 0; p < 16; ++p) a[p] = val[p * nb + k];
         y0 += a[0] * x0 + a[1] * x1 + a[2] * x2 + a[9] * x3;
         y1 += a[3] * x0 + a[4] * x1 + a[5] * x2 + a[10] * x3;
         y2 += a[6] * x0 + a[7] * x1 + a[8] * x2 + a[11] * x3;
         y3 += a[12] * x0 + a[13] * x1 + a[14] * x2 + a[15] * x3;
     }
-    y0 = group_sum<double, LPR>(y0);
-    y1 = group_sum<double, LPR>(y1);
-    y2 = group_sum<double, LPR>(y2);
-    y3 = group_sum<double, LPR>(y3);
+    y0 = group_sum<T, LPR>(y0);
+    y1 = group_sum<T, LPR>(y1);
+    y2 = group_sum<T, LPR>(y2);
+    y3 = group_sum<T, LPR>(y3);
     if (lane == 0) {
         V out;
         out.v[0] = (T)y0;

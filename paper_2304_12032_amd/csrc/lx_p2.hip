@@ -462,15 +462,15 @@ __global__ void k_simple_setup_p2(P2Sys<T> S, const int32_t *fdiag, T *Finv, T *
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S.nu) return;
     const int32_t dk = fdiag[i];
-    double A[9];
-    for (int p = 0; p < 9; ++p) A[p] = (double)S.F[(int64_t)p * S.nf + dk];
-    const double c0 = A[4] * A[8] - A[5] * A[7], c1 = A[5] * A[6] - A[3] * A[8], c2 = A[3] * A[7] - A[4] * A[6];
-    const double id = 1.0 / (A[0] * c0 + A[1] * c1 + A[2] * c2);
-    const double Bm[9] = {c0 * id, (A[2] * A[7] - A[1] * A[8]) * id, (A[1] * A[5] - A[2] * A[4]) * id,
+    T A[9];
+    for (int p = 0; p < 9; ++p) A[p] = S.F[(int64_t)p * S.nf + dk];
+    const T c0 = A[4] * A[8] - A[5] * A[7], c1 = A[5] * A[6] - A[3] * A[8], c2 = A[3] * A[7] - A[4] * A[6];
+    const T id = T(1) / (A[0] * c0 + A[1] * c1 + A[2] * c2);
+    const T Bm[9] = {c0 * id, (A[2] * A[7] - A[1] * A[8]) * id, (A[1] * A[5] - A[2] * A[4]) * id,
                           c1 * id, (A[0] * A[8] - A[2] * A[6]) * id, (A[2] * A[3] - A[0] * A[5]) * id,
                           c2 * id, (A[1] * A[6] - A[0] * A[7]) * id, (A[0] * A[4] - A[1] * A[3]) * id};
     for (int p = 0; p < 9; ++p) Finv[(int64_t)p * S.nu + i] = (T)Bm[p];
-    for (int c = 0; c < 3; ++c) Dinv[(int64_t)c * S.nu + i] = (T)(1.0 / A[4 * c]);
+    for (int c = 0; c < 3; ++c) Dinv[(int64_t)c * S.nu + i] = (T)(T(1) / A[4 * c]);
 }
 
 template <typename T>
@@ -494,25 +494,25 @@ __global__ __launch_bounds__(256) void k_spmv_p2u(P2Sys<T> S, const T *__restric
     const int lane = threadIdx.x % LPR;
     if (row >= S.nu) return;
     using V = typename V4<T>::type;
-    double y0 = 0, y1 = 0, y2 = 0;
+    T y0 = 0, y1 = 0, y2 = 0;
     for (int32_t k = S.fptr[row] + lane; k < S.fptr[row + 1]; k += LPR) {
         const V xv = reinterpret_cast<const V *>(x)[S.fcol[k]];
-        double a[9];
+        T a[9];
 #pragma unroll
-        for (int p = 0; p < 9; ++p) a[p] = (double)S.F[(int64_t)p * S.nf + k];
+        for (int p = 0; p < 9; ++p) a[p] = S.F[(int64_t)p * S.nf + k];
         y0 += a[0] * xv.v[0] + a[1] * xv.v[1] + a[2] * xv.v[2];
         y1 += a[3] * xv.v[0] + a[4] * xv.v[1] + a[5] * xv.v[2];
         y2 += a[6] * xv.v[0] + a[7] * xv.v[1] + a[8] * xv.v[2];
     }
     for (int32_t k = S.gptr[row] + lane; k < S.gptr[row + 1]; k += LPR) {
-        const double xp = x[4 * (int64_t)S.gcol[k] + 3];
-        y0 += (double)S.G[k] * xp;
-        y1 += (double)S.G[S.ng + k] * xp;
-        y2 += (double)S.G[2 * S.ng + k] * xp;
+        const T xp = x[4 * (int64_t)S.gcol[k] + 3];
+        y0 += S.G[k] * xp;
+        y1 += S.G[S.ng + k] * xp;
+        y2 += S.G[2 * S.ng + k] * xp;
     }
-    y0 = group_sum<double, LPR>(y0);
-    y1 = group_sum<double, LPR>(y1);
-    y2 = group_sum<double, LPR>(y2);
+    y0 = group_sum<T, LPR>(y0);
+    y1 = group_sum<T, LPR>(y1);
+    y2 = group_sum<T, LPR>(y2);
     if (lane == 0) {
         y[4 * row] = (T)y0;
         y[4 * row + 1] = (T)y1;
@@ -530,14 +530,14 @@ __global__ __launch_bounds__(256) void k_spmv_p2p(P2Sys<T> S, const T *__restric
     const int lane = threadIdx.x % LPR;
     if (row >= S.nv) return;
     using V = typename V4<T>::type;
-    double acc = 0;
+    T acc = 0;
     for (int32_t k = S.bptr[row] + lane; k < S.bptr[row + 1]; k += LPR) {
         const V xv = reinterpret_cast<const V *>(x)[S.bcol[k]];
-        acc += (double)S.B[k] * xv.v[0] + (double)S.B[S.nb + k] * xv.v[1] + (double)S.B[2 * S.nb + k] * xv.v[2];
+        acc += S.B[k] * xv.v[0] + S.B[S.nb + k] * xv.v[1] + S.B[2 * S.nb + k] * xv.v[2];
     }
     for (int32_t k = S.cptr[row] + lane; k < S.cptr[row + 1]; k += LPR)
-        acc += (double)S.C[k] * (double)x[4 * (int64_t)S.ccol[k] + 3];
-    acc = group_sum<double, LPR>(acc);
+        acc += S.C[k] * x[4 * (int64_t)S.ccol[k] + 3];
+    acc = group_sum<T, LPR>(acc);
     if (lane == 0) y[4 * row + 3] = (T)acc;
 }
 
