@@ -120,6 +120,13 @@ struct Amg {
     T *fr = nullptr, *fd0 = nullptr, *fd1 = nullptr, *fv = nullptr;   // [nv][4]
     TailLayout tail;                    // one-workgroup coarse cycle (tail.first = 0: none)
     unsigned char *tail_img = nullptr;  // [tail.img_bytes]
+    // The one-workgroup cycle is linear in the restricted residual it starts
+    // from, so each step its operator is tabulated, column j = the cycle applied
+    // to the unit vector e_j ([n][n], column-major, n the rows of level
+    // tail.first), and every visit is then the restriction and one dense
+    // product instead of a chain of workgroup barriers (null: cycle each visit).
+    T *tail_op = nullptr;
+    T *tail_rc = nullptr;               // [n] the restricted residual a tabulated visit starts from
 };
 
 // Chooses the first level of the one-workgroup coarse cycle and its LDS layout

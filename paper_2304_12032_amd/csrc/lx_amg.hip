@@ -1015,6 +1015,7 @@ struct TailArgs {
     const int32_t *fmptr, *fmem;         // its member lists (global; the image's copy when it has one)
     T *out;                              // result of level first (global)
     const int32_t *done;
+    int32_t basis;                       // 1: workgroup j cycles the unit vector e_j into out + j n
 };
 
 template <typename T>
@@ -1057,6 +1058,18 @@ __device__ __forceinline__ void tail_pre_global(const TailArgs<T> &A, const Tail
     const T *dinv = lds_v<T>(lds, L.o_dinv);
     T theta, a, b;
     cheb_coef_t(lam, A.ratio, 0, theta, a, b);
+    if (A.basis) {
+        // tabulating the cycle's operator: the restricted residual is e_j, j the workgroup
+        for (int i = threadIdx.x; i < L.n; i += kTailThreads) {
+            const T s = i == (int)blockIdx.x ? T(1) : T(0);
+            const T x = dinv[i] * s / theta;
+            r[i] = s;
+            res[i] = s;
+            x0[i] = x;
+            d0[i] = x;
+        }
+        return;
+    }
     const bool in_lds = A.lay.o_fmem >= 0;
     const int32_t *fmptr = in_lds ? lds_i(lds, A.lay.o_fmptr) : A.fmptr;
     const int32_t *fmem = in_lds ? lds_i(lds, A.lay.o_fmem) : A.fmem;
@@ -1318,7 +1331,53 @@ __global__ __launch_bounds__(kTailThreads) void k_amg_tail(TailArgs<T> A)
     }
     __syncthreads();
     const T *x = tail_visit<T, 0>(A, lds);
-    for (int i = threadIdx.x; i < A.lay.lv[0].n; i += kTailThreads) A.out[i] = x[i];
+    const int n = A.lay.lv[0].n;
+    T *out = A.basis ? A.out + (int64_t)blockIdx.x * n : A.out;
+    for (int i = threadIdx.x; i < n; i += kTailThreads) out[i] = x[i];
+}
+
+// One visit of the one-workgroup levels through their tabulated operator, in
+// two launches.  k_tail_restrict: rc = the finer residual restricted onto the n
+// rows of level first (LPR lanes per row, each summing every LPR-th member in
+// list order, then a fixed butterfly).  k_tail_apply: every workgroup reads rc
+// into LDS and its 64 rows take out_i = sum_j op[j][i] rc_j, the four
+// wavefronts summing every fourth column and adding their partial sums in order.
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_tail_restrict(int n, const T *__restrict__ fres,
+                                                       const int32_t *__restrict__ fmptr,
+                                                       const int32_t *__restrict__ fmem, T *__restrict__ rc,
+                                                       const int32_t *done)
+{
+    const int i = (int)((blockIdx.x * blockDim.x + threadIdx.x) / LPR);
+    const int lane = threadIdx.x % LPR;
+    if (i >= n) return;
+    const int32_t beg = fmptr[i], end = fmptr[i + 1];
+    if (done_with(done, end)) return;
+    T s = 0;
+    for (int32_t q = beg + lane; q < end; q += LPR) s += fres[fmem[q]];
+    s = group_sum<T, LPR>(s);
+    if (lane == 0) rc[i] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tail_apply(int n, const T *__restrict__ rcg, const T *__restrict__ op,
+                                                    T *__restrict__ out, const int32_t *done)
+{
+    if (done && *done) return;
+    __shared__ T rc[kTailMaxRows];
+    __shared__ T part[4][64];
+    for (int i = threadIdx.x; i < n; i += 256) rc[i] = rcg[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    T acc = 0;
+    if (i < n) {
+#pragma unroll 8
+        for (int j = wv; j < n; j += 4) acc += op[(int64_t)j * n + i] * rc[j];
+    }
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && i < n) out[i] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 }
 
 template <typename T>
@@ -1432,6 +1491,25 @@ void launch_amg_setup(const SimpleView<T> &V, const T *Finv, const T *Dinv, Amg<
         }
         A.f_warm = true;
     }
+    if (A.tail_op) {
+        // the operator of the one-workgroup cycle: one workgroup per unit vector
+        const AmgLevel<T> &F = A.L[A.tail.first - 1];
+        TailArgs<T> t;
+        t.lay = A.tail;
+        t.img = A.tail_img;
+        t.lam = A.lam;
+        t.ratio = A.ratio;
+        t.degree = A.degree;
+        t.cycle = A.cycle_coarse;
+        t.fres = F.res;
+        t.fmptr = F.mptr;
+        t.fmem = F.mem;
+        t.out = A.tail_op;
+        t.done = nullptr;
+        t.basis = 1;
+        hipLaunchKernelGGL((k_amg_tail<T>), dim3((unsigned)A.tail.lv[0].n), dim3(kTailThreads),
+                           (size_t)A.tail.lds_bytes, s, t);
+    }
 }
 template void launch_amg_setup<double>(const SimpleView<double> &, const double *, const double *, Amg<double> &,
                                        hipStream_t);
@@ -1458,7 +1536,16 @@ static bool vcycle(Amg<T> &A, int l, const int32_t *done, hipStream_t s, T *prol
         t.fmem = F.mem;
         t.out = A.L[l].x1;
         t.done = done;
-        hipLaunchKernelGGL((k_amg_tail<T>), dim3(1), dim3(kTailThreads), (size_t)A.tail.lds_bytes, s, t);
+        t.basis = 0;
+        if (A.tail_op) {
+            const int n = A.tail.lv[0].n;
+            hipLaunchKernelGGL((k_tail_restrict<T, 16>), dim3((unsigned)((n * 16 + 255) / 256)), dim3(256), 0, s, n,
+                               F.res, F.mptr, F.mem, A.tail_rc, done);
+            hipLaunchKernelGGL((k_tail_apply<T>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, n, A.tail_rc,
+                               A.tail_op, A.L[l].x1, done);
+        } else {
+            hipLaunchKernelGGL((k_amg_tail<T>), dim3(1), dim3(kTailThreads), (size_t)A.tail.lds_bytes, s, t);
+        }
         return false;
     }
     if (l == A.nlev) {

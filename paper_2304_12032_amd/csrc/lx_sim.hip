@@ -538,6 +538,13 @@ lx_status Sim::setup_amg(Amg<T> &A)
         if (A.tail.first > 0) {
             CK(dalloc((void **)&A.tail_img, (size_t)A.tail.img_bytes));
             LX_HIP(hipMemsetAsync(A.tail_img, 0, (size_t)A.tail.img_bytes, stream));
+            // the tabulated operator of that cycle (LXNS_TAIL_OP=0: cycle at every visit)
+            const char *to = getenv("LXNS_TAIL_OP");
+            if (!(to && *to == '0')) {
+                const int64_t n = A.tail.lv[0].n;
+                CK(dalloc((void **)&A.tail_op, sizeof(T) * (size_t)(n * n)));
+                CK(dalloc((void **)&A.tail_rc, sizeof(T) * (size_t)n));
+            }
         }
     }
     auto in_img = [&](int l) { return A.tail.first > 0 && l >= A.tail.first && l < A.nlev; };

@@ -1,6 +1,7 @@
 """The one-workgroup coarse AMG cycle and the sliced-ELL finest level, against
 the oracle and against the plain layouts (every level cycled by its own
-launches; the finest level in CSR).
+launches; the finest level in CSR), and the tabulated operator of the coarse
+cycle against cycling it at every visit.
 
 The small parity cases have a two-level Schur hierarchy (one smoothed level
 and the dense one), where the coarse cycle does not apply.  This tube is large
@@ -37,11 +38,11 @@ def _case():
     return tube_valve(12, 60, length=6.0, seed=11)
 
 
-def _gpu(case, stream, precision, tail=True, sell=True):
+def _gpu(case, stream, precision, tail=True, sell=True, op=True):
     from paper_2304_12032_amd import Sim
     rtol = 1e-14 if precision == "fp64" else 1e-13
     sv = SolverCfg(precision=precision, rtol=rtol, ir_rtol=rtol, max_iters=20000)
-    env = {"LXNS_AMG_TAIL": tail, "LXNS_AMG_SELL": sell}
+    env = {"LXNS_AMG_TAIL": tail, "LXNS_AMG_SELL": sell, "LXNS_TAIL_OP": op}
     old = {k: os.environ.get(k) for k in env}
     for k, on in env.items():
         if not on:
@@ -134,3 +135,27 @@ def test_sell_matches_csr(stream):
         print("step %d: iterations %d (sliced ELL) / %d (CSR), diff u %.2e p %.2e" % (k, i1, i0, eu, ep), flush=True)
         assert abs(i1 - i0) <= 2
         assert eu < 1e-10 and ep < 1e-10, (eu, ep)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_tail_operator_matches_cycle(precision, stream):
+    """The coarse cycle's operator, tabulated once per step by cycling the unit vectors and
+    applied as one dense product per visit, against running the cycle at every visit: the
+    same linear map in another summation order, so the same iteration counts (within 1) and
+    fields that agree to the solve tolerance."""
+    case = _case()
+    g1, q1 = _gpu(case, stream, precision, op=True)
+    a = _run(g1, case, 2)
+    g1.close()
+    g0, _ = _gpu(case, stream, precision, op=False)
+    b = _run(g0, case, 2)
+    g0.close()
+    assert q1["amg_tail_level"] >= 1
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    for k in range(2):
+        (u1, p1, i1), (u0, p0, i0) = a[k], b[k]
+        eu, ep = rel_l2(u1, u0), rel_l2(p1, p0)
+        print("step %d: iterations %d (tabulated) / %d (cycled), diff u %.2e p %.2e" % (k, i1, i0, eu, ep),
+              flush=True)
+        assert abs(i1 - i0) <= 1
+        assert eu < tol and ep < tol, (eu, ep)
