@@ -223,19 +223,19 @@ __device__ inline void eval_qp(const Elem<T> &E, int q, const StepCoef &C, QP<T>
 
 // ------------------------------------------------------------------ assembly
 
-// Record layout (offsets into the kRec values of an element)
+// Record layout: groups of four values, so that the slot gather reads each with
+// one vector load (offsets into the kRec values of an element):
+//   D_v = (grad phi_v, Z_v), E_v = (Y_v, S_v), X_v = (X_v0 .. X_v3) with
+//   X_ab = X_ab + mu|K| grad phi_a . grad phi_b, G1 = (W, sum w tau_C),
+//   G2 = (sum w tau_M, mu|K|, |K|/4, 0), then the right-hand side (u_x, u_y, u_z, p)
+//   of each vertex.
 enum : int {
-    kRDphi = 0,   // grad phi_a [4][3]
-    kRX = 12,     // X_ab + mu|K| grad phi_a . grad phi_b  [4][4]
-    kRY = 28,     // Y_b,c [4][3]
-    kRZ = 40,     // Z_a [4]
-    kRS = 44,     // S_b [4]
-    kRW = 48,     // W_c [3]
-    kRTC = 51,    // sum w tau_C
-    kRTM = 52,    // sum w tau_M
-    kRMV = 53,    // mu |K|
-    kRW1 = 54,    // |K| / 4
-    kRRhs = 55    // right-hand side [4][4] (u_x, u_y, u_z, p) of each vertex
+    kRD = 0,      // D_v [4][4]
+    kRE = 16,     // E_v [4][4]
+    kRX = 32,     // X_v [4][4]
+    kRG1 = 48,    // W[3], sum w tau_C
+    kRG2 = 52,    // sum w tau_M, mu|K|, |K|/4, 0
+    kRRhs = 56    // right-hand side [4][4]
 };
 static_assert(kRRhs + 16 <= kRec, "element record too small");
 
@@ -308,9 +308,15 @@ __global__ __launch_bounds__(256) void k_element_p1(AsmArgs<T> A, StepCoef C)
     const T mv = (T)C.mu * E.vol;
     T *R = A.rec + (int64_t)e * kRec;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) R[kRDphi + 3 * a + d] = E.dphi[a][d];
+        for (int d = 0; d < 3; ++d) {
+            R[kRD + 4 * a + d] = E.dphi[a][d];
+            R[kRE + 4 * a + d] = Y[a][d];
+        }
+        R[kRD + 4 * a + 3] = Z[a];
+        R[kRE + 4 * a + 3] = S[a];
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -319,18 +325,12 @@ __global__ __launch_bounds__(256) void k_element_p1(AsmArgs<T> A, StepCoef C)
             R[kRX + 4 * a + b] = X[a][b] + mv * gab;
         }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) R[kRY + 3 * a + c] = Y[a][c];
-        R[kRZ + a] = Z[a];
-        R[kRS + a] = S[a];
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) R[kRW + c] = W[c];
-    R[kRTC] = TC;
-    R[kRTM] = TM;
-    R[kRMV] = mv;
-    R[kRW1] = E.vol * T(0.25);   // integral of one basis function
+    for (int c = 0; c < 3; ++c) R[kRG1 + c] = W[c];
+    R[kRG1 + 3] = TC;
+    R[kRG2] = TM;
+    R[kRG2 + 1] = mv;
+    R[kRG2 + 2] = E.vol * T(0.25);   // integral of one basis function
+    R[kRG2 + 3] = T(0);
     if (RHS) {
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
@@ -366,18 +366,15 @@ __global__ __launch_bounds__(256) void k_gather_p1(AsmArgs<T> A, int symgrad)
         const int32_t code = A.sinc[q];
         const int64_t e = code >> 4;
         const int a = (code >> 2) & 3, b = code & 3;
-        const T *R = A.rec + e * kRec;
-        T da[3], db[3], Yb[3], W[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            da[c] = R[kRDphi + 3 * a + c];
-            db[c] = R[kRDphi + 3 * b + c];
-            Yb[c] = R[kRY + 3 * b + c];
-            W[c] = R[kRW + c];
-        }
-        const T Xab = R[kRX + 4 * a + b], Za = R[kRZ + a], Sb = R[kRS + b];
-        const T TC = R[kRTC], TM = R[kRTM], w1 = R[kRW1];
-        const T mv = symgrad ? R[kRMV] : T(0);
+        using V = typename V4<T>::type;
+        const V *R = reinterpret_cast<const V *>(A.rec + e * kRec);
+        const V Da = R[kRD / 4 + a], Db = R[kRD / 4 + b], Eb = R[kRE / 4 + b], Xa = R[kRX / 4 + a];
+        const V G1 = R[kRG1 / 4], G2 = R[kRG2 / 4];
+        const T da[3] = {Da.v[0], Da.v[1], Da.v[2]}, db[3] = {Db.v[0], Db.v[1], Db.v[2]};
+        const T Yb[3] = {Eb.v[0], Eb.v[1], Eb.v[2]}, W[3] = {G1.v[0], G1.v[1], G1.v[2]};
+        const T Xab = Xa.v[b], Za = Da.v[3], Sb = Eb.v[3];
+        const T TC = G1.v[3], TM = G2.v[0], w1 = G2.v[2];
+        const T mv = symgrad ? G2.v[1] : T(0);
         const T gab = da[0] * db[0] + da[1] * db[1] + da[2] * db[2];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -392,8 +389,9 @@ __global__ __launch_bounds__(256) void k_gather_p1(AsmArgs<T> A, int symgrad)
         }
         acc[15] += TM * gab;
         if (RHS && a == b) {
+            const V Rh = R[kRRhs / 4 + a];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) racc[c] += R[kRRhs + 4 * a + c];
+            for (int c = 0; c < 4; ++c) racc[c] += Rh.v[c];
             vrow = A.tet[(int64_t)a * A.nt + e];
         }
     }
