@@ -129,6 +129,15 @@ struct Sim {
     double *d_gerr = nullptr;  // their partial sums, then the three sums
     int x_order = 4;           // extrapolation order of the next guess (2: BDF weights, 3, 4)
     hipEvent_t ev_chk[2] = {nullptr, nullptr};
+    // HIP graphs of the Arnoldi steps: step k's preconditioner apply, product and
+    // Gram-Schmidt pass, one graph per (k, whether the step ends the cycle),
+    // captured on a private stream the first time it is needed and replayed on
+    // every later solve (their launches take fixed buffers); LXNS_GRAPH=0 launches
+    // the kernels one by one instead
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    std::vector<hipGraph_t> g_step;
+    std::vector<hipGraphExec_t> gx_step;   // [2 kMaxRestart]
     // columns used by cycle c of the last solve of each kind (0: unknown), where
     // the next solve of that kind starts checking every step
     int32_t k_hint[8][8] = {};
@@ -159,7 +168,8 @@ struct Sim {
     template <typename T>
     SimpleView<T> view();
     template <typename T>
-    void spmv(const T *x, T *y, const int32_t *done, std::pair<hipEvent_t, hipEvent_t> *tm);
+    void spmv(const T *x, T *y, const int32_t *done, std::pair<hipEvent_t, hipEvent_t> *tm,
+              hipStream_t s = nullptr);
     template <typename T>
     lx_status gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, GmResult &res,
                     lx_step_stats &tstats, bool inner = false, int kind = 0);

@@ -85,6 +85,11 @@ Sim::~Sim()
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (stream_aux) (void)hipStreamDestroy(stream_aux);
+    for (auto &g : gx_step)
+        if (g) (void)hipGraphExecDestroy(g);
+    for (auto &g : g_step)
+        if (g) (void)hipGraphDestroy(g);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -327,6 +332,15 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     LX_HIP(hipHostMalloc((void **)&h_gerr, 4 * sizeof(double), hipHostMallocDefault));
     ALLOC(d_gerr, sizeof(double) * (kGuessErrPartial + 4));
     for (auto &ev : ev_chk) LX_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    {
+        const char *ge = getenv("LXNS_GRAPH");
+        use_graphs = !(ge && *ge == '0');
+        if (use_graphs) {
+            LX_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+            g_step.assign(2 * kMaxRestart, nullptr);
+            gx_step.assign(2 * kMaxRestart, nullptr);
+        }
+    }
     if (p2) {
         // FP64 split system in both precisions (the refinement residual uses it)
         ALLOC(s64.F, sizeof(double) * 9 * s64.nf);
@@ -816,12 +830,13 @@ SimpleView<T> Sim::view()
 
 // y = A x in precision T (tm: events that time the launch, or null)
 template <typename T>
-void Sim::spmv(const T *x, T *y, const int32_t *done, std::pair<hipEvent_t, hipEvent_t> *tm)
+void Sim::spmv(const T *x, T *y, const int32_t *done, std::pair<hipEvent_t, hipEvent_t> *tm, hipStream_t s)
 {
+    if (!s) s = stream;
     if (p2)
-        launch_spmv_p2<T>(Ops<T>::sys(this), x, y, done, stream, tm ? tm->first : nullptr, tm ? tm->second : nullptr);
+        launch_spmv_p2<T>(Ops<T>::sys(this), x, y, done, s, tm ? tm->first : nullptr, tm ? tm->second : nullptr);
     else
-        launch_spmv<T>(pattern(), Ops<T>::val(this), x, y, done, stream, tm ? tm->first : nullptr,
+        launch_spmv<T>(pattern(), Ops<T>::val(this), x, y, done, s, tm ? tm->first : nullptr,
                        tm ? tm->second : nullptr);
 }
 
@@ -887,18 +902,32 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
         for (int k = 0; k < kmax; ++k) {
             T *zk = Z + k * ld;
             const bool amg = solver.precond == LX_PC_AMG;
-            // from the second step on, the Gram-Schmidt pass that formed V_k already
-            // started the velocity block on it
-            if (amg)
-                launch_simple_amg_apply<T>(view<T>(), SP.Finv, SP.Dinv, Ops<T>::amg(this), V + k * ld, &d_st->s[k],
-                                           zk, &d_st->done, stream, k > 0);
-            else
-                launch_simple_apply<T>(P, SP, V + k * ld, &d_st->s[k], zk, &d_st->done, stream);
-            auto *tm = timer_begin(0, k, false);
-            spmv<T>(zk, w, &d_st->done, tm);
-            FzStart<T> fz;
-            if (amg) fz = amg_fz_start(Ops<T>::amg(this), SP.Finv, Z + (k + 1) * ld);
-            launch_gm_orth<T>(N, k, V, ld, w, d_st, d_partial, stream, amg && k + 1 < kmax ? &fz : nullptr);
+            // Arnoldi step k: z_k = M^{-1} v_k, w = A z_k, Gram-Schmidt (from the second
+            // step on, the pass that formed v_k already started the velocity block on it)
+            auto arnoldi = [&](hipStream_t s, bool timed) {
+                if (amg)
+                    launch_simple_amg_apply<T>(view<T>(), SP.Finv, SP.Dinv, Ops<T>::amg(this), V + k * ld,
+                                               &d_st->s[k], zk, &d_st->done, s, k > 0);
+                else
+                    launch_simple_apply<T>(P, SP, V + k * ld, &d_st->s[k], zk, &d_st->done, s);
+                auto *tm = timed ? timer_begin(0, k, false) : nullptr;
+                spmv<T>(zk, w, &d_st->done, tm, s);
+                FzStart<T> fz;
+                if (amg) fz = amg_fz_start(Ops<T>::amg(this), SP.Finv, Z + (k + 1) * ld);
+                launch_gm_orth<T>(N, k, V, ld, w, d_st, d_partial, s, amg && k + 1 < kmax ? &fz : nullptr);
+            };
+            if (use_graphs) {
+                const int key = 2 * k + (k + 1 < kmax ? 0 : 1);
+                if (!gx_step[key]) {
+                    LX_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+                    arnoldi(cap_stream, false);
+                    LX_HIP(hipStreamEndCapture(cap_stream, &g_step[key]));
+                    LX_HIP(hipGraphInstantiate(&gx_step[key], g_step[key], nullptr, nullptr, 0));
+                }
+                LX_HIP(hipGraphLaunch(gx_step[key], stream));
+            } else {
+                arnoldi(stream, true);
+            }
             if (pending >= 0) {
                 LX_HIP(hipEventSynchronize(ev_chk[pending & 1]));
                 const bool stop = h_flag[pending & 1] != 0;

@@ -1,0 +1,59 @@
+"""The Arnoldi steps replayed from HIP graphs against the same kernels launched
+one by one (LXNS_GRAPH=0): every graph is captured once and replayed at every
+later step of every solve, with the eager cycle-start, refinement and set-up
+work of the step in between, so the fields must agree bitwise after several
+steps, in FP64 and in FP32 + FP64 refinement, on a tube whose Schur hierarchy
+has a one-workgroup coarse cycle and on the small parity tube."""
+import os
+
+import numpy as np
+import pytest
+
+from inputs.problem import SolverCfg
+from tests._cases import tube_valve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def stream():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.init()
+    return torch.cuda.current_stream(0).cuda_stream
+
+
+def _run(case, stream, precision, graphs, steps):
+    from paper_2304_12032_amd import Sim
+    old = os.environ.get("LXNS_GRAPH")
+    if not graphs:
+        os.environ["LXNS_GRAPH"] = "0"
+    try:
+        sv = SolverCfg(precision=precision, rtol=1e-12, ir_rtol=1e-12, max_iters=20000)
+        g = Sim(case.mesh, case.prob, sv, device=0, stream=stream)
+    finally:
+        if old is None:
+            os.environ.pop("LXNS_GRAPH", None)
+        else:
+            os.environ["LXNS_GRAPH"] = old
+    case.init(g)
+    out, iters = [], []
+    for k in range(steps):
+        case.drive(g, case.prob.t0 + (k + 1) * case.prob.dt)
+        st = g.step()
+        iters.append(st["gmres_iters"])
+        out.append(g.solution()[:2])
+    g.close()
+    return out, iters
+
+
+@pytest.mark.parametrize("name", ["tube4x8", "tube12x60"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_graph_replay_bitwise(name, precision, stream):
+    case = tube_valve(4, 8) if name == "tube4x8" else tube_valve(12, 60, length=6.0, seed=11)
+    a, ia = _run(case, stream, precision, True, 4)
+    b, ib = _run(case, stream, precision, False, 4)
+    print("%s %s: iterations graphs %s, eager %s" % (name, precision, ia, ib), flush=True)
+    assert ia == ib
+    for (ua, pa), (ub, pb) in zip(a, b):
+        assert np.array_equal(ua, ub) and np.array_equal(pa, pb)
