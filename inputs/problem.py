@@ -31,14 +31,19 @@ class Profile:
 
 @dataclass
 class Boundary:
-    """type: noslip | dirichlet | neumann.  Dirichlet: u = theta g(t) s(x).
+    """type: noslip | dirichlet | neumann | resistance.  Dirichlet: u = theta g(t) s(x).
     Neumann: sigma n = -theta h(t) n (profile.kind == 'nodal' means a nodal traction
-    vector is supplied per step instead)."""
+    vector is supplied per step instead).  Resistance: sigma n = -(theta p0(t) +
+    resistance * int (u - u_ALE) . n) n with p0 = law; profile.normal orients the face
+    normals outward.  backflow > 0 (neumann, resistance): inertial backflow
+    stabilisation, the traction gains backflow * rho/2 min(u . n, 0) u."""
     type: str
     tags: Tuple[int, ...]
     theta: float = 1.0
     law: TimeLaw = field(default_factory=TimeLaw)
     profile: Profile = field(default_factory=Profile)
+    resistance: float = 0.0
+    backflow: float = 0.0
 
 
 @dataclass

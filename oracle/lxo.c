@@ -16,6 +16,9 @@
  *   - strong residuals r_M, r_C and tau_M, tau_C, G, g: Sec. 2.3
  *   - RIIS term and smoothed delta: Sec. 2.1.2, eq. (riis)
  *   - Neumann data: Sec. 2.2.3, eq. (bcs-neumann)
+ *   - inertial backflow stabilisation and resistance conditions: Sec. 2.2
+ *     (Neumann and resistance boundary conditions); flow-rate and pressure
+ *     integrals over boundary portions: Sec. 4
  *   - GMRES with the SIMPLE preconditioner: Sec. 2.4
  *
  * Readings where the paper is silent (kept identical on the device side and
@@ -446,6 +449,102 @@ void orc_neumann_p1(int64_t nv, int64_t nf, const double *x, const int32_t *face
                 rhs[3 * (int64_t)v[j] + c] += area / 3.0 * hq * 0.5;
             }
         }
+    }
+}
+
+/* ------------------------------------------------ outflow boundary terms */
+
+/* Outward unit normal and area of boundary triangle v[0..2] on configuration x:
+ * the triangle's own normal, its sign chosen to agree with the condition's
+ * outward direction dir (kept as given where dir is zero or orthogonal). */
+static double face_normal(const double *x, const int32_t *v, const double *dir, double n[3])
+{
+    double a[3], b[3];
+    for (int c = 0; c < 3; ++c) {
+        a[c] = x[3 * v[1] + c] - x[3 * v[0] + c];
+        b[c] = x[3 * v[2] + c] - x[3 * v[0] + c];
+    }
+    n[0] = a[1] * b[2] - a[2] * b[1];
+    n[1] = a[2] * b[0] - a[0] * b[2];
+    n[2] = a[0] * b[1] - a[1] * b[0];
+    double len = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    double s = (n[0] * dir[0] + n[1] * dir[1] + n[2] * dir[2]) < 0.0 ? -1.0 : 1.0;
+    for (int c = 0; c < 3; ++c) n[c] = s * n[c] / len;
+    return 0.5 * len;
+}
+
+/* Resistance condition (Sec. 2.2, resistance boundary conditions): the flux
+ * functional Q(u) = int_Gamma u . n is w . u with w[3v+c] = int_Gamma phi_v n_c,
+ * which for P1 and flat faces is area/3 n_c per face corner.  w is added into. */
+void orc_flux_weights(int64_t nf, const double *x, const int32_t *faces, const double *dir, double *w)
+{
+    for (int64_t f = 0; f < nf; ++f) {
+        const int32_t *v = faces + 3 * f;
+        double n[3];
+        double area = face_normal(x, v, dir, n);
+        for (int l = 0; l < 3; ++l)
+            for (int c = 0; c < 3; ++c) w[3 * (int64_t)v[l] + c] += area / 3.0 * n[c];
+    }
+}
+
+/* Inertial backflow stabilisation (Sec. 2.2, Neumann conditions): the traction
+ * gains beta rho/2 min(u . n, 0) u, taken semi-implicitly as
+ * min(u_EXT . n, 0) u^{n+1}; on the left-hand side of the momentum equation
+ * this is  - beta rho/2 int_Gamma min(u_EXT . n, 0) phi_b phi_a  in every
+ * velocity component, integrated with the edge-midpoint rule (exact for
+ * quadratics).  coef = beta rho / 2; rows of vertices with skip[v] != 0
+ * (Dirichlet vertices) get nothing. */
+void orc_backflow_p1(int64_t nf, const double *x, const int32_t *faces, const double *dir, const double *uE,
+                     double coef, const char *skip, const int64_t *rowptr, const int32_t *col, double *val)
+{
+    for (int64_t f = 0; f < nf; ++f) {
+        const int32_t *v = faces + 3 * f;
+        double n[3];
+        double area = face_normal(x, v, dir, n);
+        for (int m = 0; m < 3; ++m) {
+            /* midpoint of the edge (v[m], v[m+1]): phi = 1/2 on its two ends, 0 on the third */
+            int i = m, j = (m + 1) % 3;
+            double un = 0.0;
+            for (int c = 0; c < 3; ++c) un += 0.5 * (uE[3 * v[i] + c] + uE[3 * v[j] + c]) * n[c];
+            double neg = un < 0.0 ? un : 0.0;
+            if (neg == 0.0) continue;
+            int ends[2] = {i, j};
+            for (int p = 0; p < 2; ++p)
+                for (int q = 0; q < 2; ++q) {
+                    int64_t a = v[ends[p]], b = v[ends[q]];
+                    if (skip[a]) continue;
+                    double add = -coef * (area / 3.0) * neg * 0.25;
+                    for (int c = 0; c < 3; ++c) {
+                        int64_t r = 3 * a + c, cc = 3 * b + c;
+                        for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k)
+                            if (col[k] == cc) {
+                                val[k] += add;
+                                break;
+                            }
+                    }
+                }
+        }
+    }
+}
+
+/* Boundary integrals over faces (Sec. 4, flow rates and section pressures):
+ * out[0] = int (u - u_ALE) . n (flux through the moving surface; uA may be
+ * NULL), out[1] = int p, out[2] = area.  P1 data: area/3 times the corner sums. */
+void orc_boundary_integrals(int64_t nf, const double *x, const int32_t *faces, const double *dir, const double *u,
+                            const double *uA, const double *p, double *out)
+{
+    out[0] = out[1] = out[2] = 0.0;
+    for (int64_t f = 0; f < nf; ++f) {
+        const int32_t *v = faces + 3 * f;
+        double n[3];
+        double area = face_normal(x, v, dir, n);
+        for (int l = 0; l < 3; ++l) {
+            double un = 0.0;
+            for (int c = 0; c < 3; ++c) un += (u[3 * v[l] + c] - (uA ? uA[3 * v[l] + c] : 0.0)) * n[c];
+            out[0] += area / 3.0 * un;
+            out[1] += area / 3.0 * p[v[l]];
+        }
+        out[2] += area;
     }
 }
 

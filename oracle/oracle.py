@@ -9,7 +9,9 @@ What it computes per step (paper Sec. 2.3 and 2.4; readings listed in lxo.c):
      u_BDF = sum beta_i u^{n-i}, u_EXT = sum gamma_i u^{n-i}, p_EXT likewise.
   2. ALE (if on): boundary displacement at t^{n+1}, harmonic extension on the
      reference mesh, x^{n+1} = x^ + d^{n+1}, u_ALE = (alpha d^{n+1} - d_BDF)/dt.
-  3. Element assembly on x^{n+1} (lxo.c), Neumann face terms, Dirichlet rows.
+  3. Element assembly on x^{n+1} (lxo.c), Neumann face terms, backflow
+     stabilisation and resistance conditions (the latter a rank-1 term
+     C_R w w^T kept beside the sparse matrix), Dirichlet rows.
   4. Solve A x = b exactly (dense LU, or sparse LU), or by the oracle's own
      GMRES + SIMPLE for large systems; rotate the history.
 """
@@ -68,6 +70,12 @@ def lib():
         L.orc_assemble_p1.argtypes = [I64, I64] + [vp] * 8 + [P(OrcParams)] + [vp] * 4
         L.orc_neumann_p1.restype = None
         L.orc_neumann_p1.argtypes = [I64, I64, vp, vp, vp, vp]
+        L.orc_flux_weights.restype = None
+        L.orc_flux_weights.argtypes = [I64, vp, vp, vp, vp]
+        L.orc_backflow_p1.restype = None
+        L.orc_backflow_p1.argtypes = [I64, vp, vp, vp, vp, D, vp, vp, vp, vp]
+        L.orc_boundary_integrals.restype = None
+        L.orc_boundary_integrals.argtypes = [I64, vp, vp, vp, vp, vp, vp, vp]
         L.orc_dirichlet_rows.restype = None
         L.orc_dirichlet_rows.argtypes = [I64, vp, vp, vp, vp, vp, vp]
         L.orc_gmres_simple.restype = I64
@@ -346,6 +354,29 @@ class OracleSim:
                 h = np.broadcast_to(-hv * np.asarray(b.profile.normal, float), (self.nv, 3))
             h = np.ascontiguousarray(h, dtype=np.float64)
             L.orc_neumann_p1(self.nv, len(faces), _p(np.ascontiguousarray(x)), _p(faces), _p(h), _p(self.rhs))
+        # outflow conditions: backflow stabilisation (into the matrix) and resistance
+        # conditions (right-hand side here, the rank-1 term in matrix())
+        skip = np.ascontiguousarray((self.owner >= 0).astype(np.int8))
+        self.rank1 = []
+        for i, b in enumerate(prob.bcs):
+            if b.type not in ("neumann", "resistance"):
+                continue
+            faces = self.bc_faces(i)
+            dirv = np.ascontiguousarray(b.profile.normal, dtype=np.float64)
+            xc = np.ascontiguousarray(x)
+            if b.backflow > 0.0:
+                L.orc_backflow_p1(len(faces), _p(xc), _p(faces), _p(dirv), _p(np.ascontiguousarray(uE)),
+                                  0.5 * b.backflow * prob.rho, _p(skip), _p(self.rowptr), _p(self.col),
+                                  _p(self.val))
+            if b.type == "resistance":
+                w = np.zeros(3 * self.nv)
+                L.orc_flux_weights(len(faces), _p(xc), _p(faces), _p(dirv), _p(w))
+                w_row = w.reshape(self.nv, 3).copy()
+                w_row[self.owner >= 0] = 0.0
+                w_row = w_row.reshape(-1)
+                p0 = b.theta * time_law(b.law, t1)
+                self.rhs[:3 * self.nv] += w_row * (-p0 + b.resistance * float(w @ uA.reshape(-1)))
+                self.rank1.append((b.resistance, w_row, w))
         # Dirichlet rows
         rows, gvals = self.dirichlet_rows(t1, x, uA)
         L.orc_dirichlet_rows(len(rows), _p(rows), _p(gvals), _p(self.rowptr), _p(self.col),
@@ -374,10 +405,38 @@ class OracleSim:
         rows = (3 * vs[:, None] + np.arange(3)[None, :]).reshape(-1).astype(np.int64)
         return np.ascontiguousarray(rows), np.ascontiguousarray(g[vs].reshape(-1))
 
-    def matrix(self):
-        from scipy.sparse import csr_matrix
+    def bc_faces(self, i):
+        b = self.prob.bcs[i]
+        return np.ascontiguousarray(self.mesh.bfaces[np.isin(self.mesh.btags, b.tags)], dtype=np.int32)
+
+    def matrix(self, rank1=True):
+        """The assembled sparse matrix; rank1: plus C_R w_row w^T of every resistance
+        condition (velocity rows and columns; w_row is w with Dirichlet rows zeroed)."""
+        from scipy.sparse import csr_matrix, coo_matrix
         N = 4 * self.nv
-        return csr_matrix((self.val.copy(), self.col.copy(), self.rowptr.copy()), shape=(N, N))
+        A = csr_matrix((self.val.copy(), self.col.copy(), self.rowptr.copy()), shape=(N, N))
+        if rank1:
+            for cr, w_row, w in getattr(self, "rank1", []):
+                r = np.nonzero(w_row)[0]
+                c = np.nonzero(w)[0]
+                R, Cc = np.meshgrid(r, c, indexing="ij")
+                A = A + coo_matrix((cr * np.outer(w_row[r], w[c]).reshape(-1), (R.reshape(-1), Cc.reshape(-1))),
+                                   shape=(N, N)).tocsr()
+        return A
+
+    def boundary_integrals(self, bc_index):
+        """(int (u - u_ALE) . n, int p, area) over condition bc_index's faces on the
+        configuration and with the solution of the last step."""
+        b = self.prob.bcs[bc_index]
+        faces = self.bc_faces(bc_index)
+        out = np.zeros(3)
+        uA = getattr(self, "uA", None) if self.prob.ale else None
+        lib().orc_boundary_integrals(len(faces), _p(np.ascontiguousarray(self.x)), _p(faces),
+                                     _p(np.ascontiguousarray(b.profile.normal, dtype=np.float64)),
+                                     _p(np.ascontiguousarray(self.u_hist[0])),
+                                     _p(None if uA is None else np.ascontiguousarray(uA)),
+                                     _p(np.ascontiguousarray(self.p_hist[0])), _p(out))
+        return out
 
     def solve(self, x0=None):
         N = 4 * self.nv
@@ -393,6 +452,9 @@ class OracleSim:
             sol = spsolve(self.matrix().tocsc(), self.rhs)
             self.last_iters, self.last_res = 0, 0.0
         else:
+            if getattr(self, "rank1", []):
+                raise ValueError("the oracle's GMRES takes the sparse matrix only: resistance conditions need "
+                                 "solve='dense' or 'direct'")
             sol = np.ascontiguousarray(x0.copy() if x0 is not None else np.zeros(N))
             res = ctypes.c_double(0.0)
             it = lib().orc_gmres_simple(self.nv, _p(self.rowptr), _p(self.col), _p(self.val),
