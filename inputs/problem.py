@@ -72,6 +72,15 @@ class Problem:
     ale: bool = False
     ale_tags: Tuple[int, ...] = ()
     ale_law: TimeLaw = field(default_factory=lambda: TimeLaw("constant", (1.0,)))
+    # lifting problem of the ALE displacement: harmonic | elastic (E, nu); stiffening
+    # alpha per element: none | jacobian (J0, chi): (J0/J)^chi | boundary (beta, gamma):
+    # max(d, beta)^-gamma with d the distance of the element's centroid to the faces
+    # tagged ale_tags (reference configuration)
+    lifting: str = "harmonic"
+    lift_E: float = 1.0
+    lift_nu: float = 0.3
+    stiffening: str = "none"
+    stiff_p: Tuple[float, float] = (1.0, 1.0)
     forcing: bool = False
     bcs: List[Boundary] = field(default_factory=list)
     valves: List[Valve] = field(default_factory=list)

@@ -16,6 +16,8 @@
  *   - strong residuals r_M, r_C and tau_M, tau_C, G, g: Sec. 2.3
  *   - RIIS term and smoothed delta: Sec. 2.1.2, eq. (riis)
  *   - Neumann data: Sec. 2.2.3, eq. (bcs-neumann)
+ *   - lifting problem (harmonic or linear elasticity, Jacobian- or
+ *     boundary-based stiffening): Sec. 2.1.1, eq. (lifting)
  *   - inertial backflow stabilisation and resistance conditions: Sec. 2.2
  *     (Neumann and resistance boundary conditions); flow-rate and pressure
  *     integrals over boundary portions: Sec. 4
@@ -1069,6 +1071,164 @@ int64_t orc_elements_p2(int64_t nt, const double *x, const double *xh, const int
         if (!(fabs(det) > 0.0) && e < bad) bad = e;
     }
     return bad < nt ? -(bad + 1) : 0;
+}
+
+/* ------------------------------------------------------------ mesh lifting */
+
+/* Lifting problem of Sec. 2.1.1, eq. (lifting): -div(alpha sigma_L(d)) = 0 on the
+ * reference mesh.  P1 element stiffness (12 x 12, index 3a+c) of
+ *   harmonic (kind 0):  sigma_L = grad d
+ *     K[3a+c][3b+d] = alpha vol delta_cd grad phi_a . grad phi_b
+ *   linear elasticity (kind 1): sigma_L = E/(1+nu) sym grad d + E nu/((1+nu)(1-2nu)) div d I
+ *     K[3a+c][3b+d] = alpha vol ( E/(1+nu) (delta_cd grad phi_a . grad phi_b
+ *                                           + d_d phi_a d_c phi_b) / 2
+ *                                 + E nu/((1+nu)(1-2nu)) d_c phi_a d_d phi_b )
+ * (test function phi_a e_c, trial function phi_b e_d; the gradients are
+ * constant on the element, so the one-point rule is exact).  Returns the volume. */
+double orc_lifting_element(const double X[4][3], int32_t kind, double E, double nu, double alpha, double K[12][12])
+{
+    double M[4][4], Mi[4][4];
+    /* barycentric gradients from the 4x4 system [1 x y z]: Mi rows 1..3 */
+    for (int a = 0; a < 4; ++a) {
+        M[a][0] = 1.0;
+        for (int c = 0; c < 3; ++c) M[a][c + 1] = X[a][c];
+    }
+    /* Gauss-Jordan inverse with partial pivoting */
+    double A[4][8];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 8; ++j) A[i][j] = j < 4 ? M[i][j] : (j - 4 == i ? 1.0 : 0.0);
+    double det = 1.0;
+    for (int c = 0; c < 4; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 4; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        if (piv != c) {
+            for (int j = 0; j < 8; ++j) {
+                double t = A[c][j];
+                A[c][j] = A[piv][j];
+                A[piv][j] = t;
+            }
+            det = -det;
+        }
+        det *= A[c][c];
+        double inv = 1.0 / A[c][c];
+        for (int j = 0; j < 8; ++j) A[c][j] *= inv;
+        for (int r = 0; r < 4; ++r)
+            if (r != c) {
+                double f = A[r][c];
+                for (int j = 0; j < 8; ++j) A[r][j] -= f * A[c][j];
+            }
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) Mi[i][j] = A[i][j + 4];
+    double g[4][3];   /* grad phi_a = column a of Mi, rows 1..3 */
+    for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 3; ++c) g[a][c] = Mi[c + 1][a];
+    double vol = fabs(det) / 6.0;
+    double mu2 = E / (1.0 + nu), lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 3; ++c)
+            for (int b = 0; b < 4; ++b)
+                for (int d = 0; d < 3; ++d) {
+                    double gg = g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2];
+                    double v;
+                    if (kind == 0)
+                        v = (c == d) ? gg : 0.0;
+                    else
+                        v = mu2 * 0.5 * ((c == d ? gg : 0.0) + g[a][d] * g[b][c]) + lam * g[a][c] * g[b][d];
+                    K[3 * a + c][3 * b + d] = alpha * vol * v;
+                }
+    return vol;
+}
+
+/* Every element's lifting stiffness on the reference coordinates xh, in COO
+ * triplets (144 per element, element by element). */
+void orc_lifting_matrix(int64_t nt, const double *xh, const int32_t *tets, int32_t kind, double E, double nu,
+                        const double *alpha, int64_t *rows, int64_t *cols, double *vals)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < nt; ++e) {
+        double X[4][3], K[12][12];
+        for (int a = 0; a < 4; ++a)
+            for (int c = 0; c < 3; ++c) X[a][c] = xh[3 * (int64_t)tets[4 * e + a] + c];
+        orc_lifting_element(X, kind, E, nu, alpha[e], K);
+        for (int i = 0; i < 12; ++i)
+            for (int j = 0; j < 12; ++j) {
+                int64_t k = 144 * e + 12 * i + j;
+                rows[k] = 3 * (int64_t)tets[4 * e + i / 3] + i % 3;
+                cols[k] = 3 * (int64_t)tets[4 * e + j / 3] + j % 3;
+                vals[k] = K[i][j];
+            }
+    }
+}
+
+/* Distance from point p to triangle (a, b, c): if the projection of p on the
+ * triangle's plane lies inside the triangle, the distance to the plane;
+ * otherwise the smallest distance to its three edges (as segments). */
+static double seg_dist2(const double *p, const double *a, const double *b)
+{
+    double ab[3], ap[3];
+    for (int k = 0; k < 3; ++k) {
+        ab[k] = b[k] - a[k];
+        ap[k] = p[k] - a[k];
+    }
+    double t = (ap[0] * ab[0] + ap[1] * ab[1] + ap[2] * ab[2]) / (ab[0] * ab[0] + ab[1] * ab[1] + ab[2] * ab[2]);
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double q = ap[k] - t * ab[k];
+        d2 += q * q;
+    }
+    return d2;
+}
+
+double orc_point_triangle_distance(const double *p, const double *a, const double *b, const double *c)
+{
+    double u[3], v[3], w[3];
+    for (int k = 0; k < 3; ++k) {
+        u[k] = b[k] - a[k];
+        v[k] = c[k] - a[k];
+        w[k] = p[k] - a[k];
+    }
+    /* barycentric coordinates of the projection: solve [u.u u.v; u.v v.v] (s, t) = (w.u, w.v) */
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2], vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    double uv = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+    double wu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2], wv = w[0] * v[0] + w[1] * v[1] + w[2] * v[2];
+    double den = uu * vv - uv * uv;
+    double s = (vv * wu - uv * wv) / den, t = (uu * wv - uv * wu) / den;
+    if (s >= 0.0 && t >= 0.0 && s + t <= 1.0) {
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            double q = w[k] - s * u[k] - t * v[k];
+            d2 += q * q;
+        }
+        return sqrt(d2);
+    }
+    double d2 = seg_dist2(p, a, b), e2 = seg_dist2(p, b, c), f2 = seg_dist2(p, c, a);
+    if (e2 < d2) d2 = e2;
+    if (f2 < d2) d2 = f2;
+    return sqrt(d2);
+}
+
+/* Boundary-based stiffening (Sec. 2.1.1): distance from each element's
+ * centroid (reference coordinates) to the nearest of the nf boundary faces. */
+void orc_boundary_distance(int64_t nt, const double *xh, const int32_t *tets, int64_t nf, const int32_t *faces,
+                           double *dist)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < nt; ++e) {
+        double p[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < 4; ++a)
+            for (int c = 0; c < 3; ++c) p[c] += 0.25 * xh[3 * (int64_t)tets[4 * e + a] + c];
+        double best = INFINITY;
+        for (int64_t f = 0; f < nf; ++f) {
+            double d = orc_point_triangle_distance(p, xh + 3 * (int64_t)faces[3 * f], xh + 3 * (int64_t)faces[3 * f + 1],
+                                                   xh + 3 * (int64_t)faces[3 * f + 2]);
+            if (d < best) best = d;
+        }
+        dist[e] = best;
+    }
 }
 
 /* Threads used by the parallel loops (OpenMP builds); returns the count in effect. */

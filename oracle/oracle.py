@@ -88,6 +88,14 @@ def lib():
         L.orc_valve_distance.argtypes = [vp, vp]
         L.orc_quad_p1.restype = None
         L.orc_quad_p1.argtypes = [vp, vp]
+        L.orc_lifting_element.restype = D
+        L.orc_lifting_element.argtypes = [vp, I32, D, D, D, vp]
+        L.orc_lifting_matrix.restype = None
+        L.orc_lifting_matrix.argtypes = [I64, vp, vp, I32, D, D, vp, vp, vp, vp]
+        L.orc_point_triangle_distance.restype = D
+        L.orc_point_triangle_distance.argtypes = [vp, vp, vp, vp]
+        L.orc_boundary_distance.restype = None
+        L.orc_boundary_distance.argtypes = [I64, vp, vp, I64, vp, vp]
         L.orc_set_threads.restype = I32
         L.orc_set_threads.argtypes = [I32]
         _LIB = L
@@ -258,29 +266,65 @@ class OracleSim:
         return out
 
     def _ale_update(self, t1, alpha, beta):
-        """Harmonic extension (alpha = 1 stiffening) of the boundary displacement on the
-        reference mesh; returns d^{n+1} and u_ALE."""
-        from scipy.sparse import coo_matrix
+        """Lifting of the boundary displacement on the reference mesh (Sec. 2.1.1, eq.
+        (lifting)): harmonic extension or linear elasticity, with the stiffening
+        coefficient per element; Dirichlet rows on the vertices of the ale_tags faces.
+        Returns d^{n+1} and u_ALE."""
         from scipy.sparse.linalg import spsolve
         prob, m = self.prob, self.mesh
         dB = self.ale_nodal if self.ale_nodal is not None else time_law(prob.ale_law, t1) * self.ale_shape
         faces = m.bfaces[np.isin(m.btags, prob.ale_tags)]
         bnodes = np.unique(faces.reshape(-1))
-        K = self.laplacian()
-        K = K.tolil()
-        rhs = np.zeros((self.nv, 3))
+        K = self.lifting_matrix().tolil()
+        rhs = np.zeros(3 * self.nv)
         diag = K.diagonal()
         for v in bnodes:
-            K.rows[v] = [v]
-            K.data[v] = [diag[v]]
-            rhs[v] = diag[v] * dB[v]
-        K = K.tocsc()
-        d = np.zeros((self.nv, 3))
-        for c in range(3):
-            d[:, c] = spsolve(K, rhs[:, c])
+            for c in range(3):
+                r = 3 * v + c
+                K.rows[r] = [r]
+                K.data[r] = [diag[r]]
+                rhs[r] = diag[r] * dB[v, c]
+        d = spsolve(K.tocsc(), rhs).reshape(self.nv, 3)
         dbdf = self._combo(self.d_hist, beta)
         uale = (alpha * d - dbdf) / prob.dt
         return d, uale
+
+    def lifting_alpha(self):
+        """Stiffening coefficient per element (Sec. 2.1.1): 1, (J0 / J)^chi with J the
+        Jacobian determinant of the map from the unit simplex to the element (6 times
+        its volume), or max(d, beta)^-gamma with d the distance from the element's
+        centroid to the ale_tags faces, all on the reference mesh."""
+        prob, m = self.prob, self.mesh
+        if prob.stiffening == "none":
+            return np.ones(m.nt)
+        if prob.stiffening == "jacobian":
+            J0, chi = prob.stiff_p
+            X = self.xhat[self.tets]
+            J = np.abs(np.linalg.det(np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=2)))
+            return (J0 / J) ** chi
+        if prob.stiffening == "boundary":
+            beta, gamma = prob.stiff_p
+            return np.maximum(self.boundary_distance(), beta) ** (-gamma)
+        raise ValueError(prob.stiffening)
+
+    def boundary_distance(self):
+        m = self.mesh
+        faces = np.ascontiguousarray(m.bfaces[np.isin(m.btags, self.prob.ale_tags)], dtype=np.int32)
+        dist = np.zeros(m.nt)
+        lib().orc_boundary_distance(m.nt, _p(self.xhat), _p(self.tets), len(faces), _p(faces), _p(dist))
+        return dist
+
+    def lifting_matrix(self):
+        """[3 nv]^2 stiffness of the lifting problem, index 3v+c, on the reference mesh."""
+        from scipy.sparse import coo_matrix
+        prob, m = self.prob, self.mesh
+        kind = {"harmonic": 0, "elastic": 1}[prob.lifting]
+        a = np.ascontiguousarray(self.lifting_alpha(), dtype=np.float64)
+        n = 144 * m.nt
+        rows, cols, vals = np.zeros(n, dtype=np.int64), np.zeros(n, dtype=np.int64), np.zeros(n)
+        lib().orc_lifting_matrix(m.nt, _p(self.xhat), _p(self.tets), kind, prob.lift_E, prob.lift_nu, _p(a),
+                                 _p(rows), _p(cols), _p(vals))
+        return coo_matrix((vals, (rows, cols)), shape=(3 * self.nv, 3 * self.nv)).tocsr()
 
     def laplacian(self):
         """P1 stiffness matrix on the reference mesh: int grad phi_a . grad phi_b."""
