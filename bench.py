@@ -426,6 +426,8 @@ def serve(args, torch):
            "step_p99_ms_max_over_requests": round(float(np.max([l["step_p99_ms"] for l in lat])), 3),
            "admit_wait_ms_p50": round(float(np.median([l["admit_wait_ms"] for l in lat])), 3),
            "admit_wait_ms_max": round(float(np.max([l["admit_wait_ms"] for l in lat])), 3),
+           "setup_ms_p50": round(float(np.median([l["setup_ms"] for l in lat])), 3),
+           "setup_ms_max": round(float(np.max([l["setup_ms"] for l in lat])), 3),
            "failed": failed}
     srv.close()
     if verify:
