@@ -111,8 +111,21 @@ typedef struct {
 /* Boundary conditions, Sec. 2.2: no-slip u = u_ALE (or 0), Dirichlet
  * u = theta g(t) s(x), Neumann sigma(u,p) n = -theta h(t) n (uniform profile)
  * or a nodal traction vector (nodal profile).  Where conditions share a
- * vertex, no-slip wins, then the first Dirichlet condition in the list. */
-enum { LX_BC_NOSLIP = 0, LX_BC_DIRICHLET = 1, LX_BC_NEUMANN = 2 };
+ * vertex, no-slip wins, then the first Dirichlet condition in the list.
+ *
+ * Resistance (Sec. 2.2, resistance boundary conditions; P1-P1):
+ *   sigma(u,p) n = -(theta p0(t) + C_R int_Gamma (u - u_ALE) . n) n,
+ * p0 = law, C_R = resistance >= 0, taken implicitly: the flux functional
+ * w . u (w_v = int_Gamma phi_v n, face normals oriented along profile.normal)
+ * couples the condition's vertices through the rank-1 term C_R w w^T, applied
+ * beside the sparse matrix in every operator product (rows of Dirichlet
+ * vertices excluded), and lx_sim_debug_export leaves it out.
+ * Inertial backflow stabilisation (Sec. 2.2, Neumann conditions; P1-P1):
+ * backflow = beta > 0 on a Neumann or resistance condition adds
+ * beta rho/2 min(u . n, 0) u to the traction, semi-implicitly as
+ * min(u_EXT . n, 0) u^{n+1} (a boundary mass term, edge-midpoint rule), to the
+ * rows of its non-Dirichlet vertices. */
+enum { LX_BC_NOSLIP = 0, LX_BC_DIRICHLET = 1, LX_BC_NEUMANN = 2, LX_BC_RESISTANCE = 3 };
 typedef struct {
     int32_t type;
     int32_t n_tags;
@@ -120,6 +133,8 @@ typedef struct {
     double theta;
     lx_time_law law;
     lx_profile profile;
+    double resistance;       /* C_R of a resistance condition                        */
+    double backflow;         /* beta of the backflow stabilisation (0: off)          */
 } lx_boundary;
 
 /* RIIS immersed surface (Sec. 2.1.2, eq. (riis)): an annular disc (center, unit
@@ -360,15 +375,29 @@ lx_status lx_sim_debug_residual(lx_sim *sim, const double *u, const double *p, d
  * Nothing is allocated: no hipMalloc, hipFree or caller allocator call. */
 lx_status lx_sim_residual_noalloc(lx_sim *sim, const double *u, const double *p, double *r);
 
+/* Flow rate and pressure over the faces of condition `bc` (any type; Sec. 4's
+ * section diagnostics), on the configuration and with the solution of the
+ * last step: out[0] = int (u - u_ALE) . n (the flux through the moving
+ * surface; normals oriented along the condition's profile.normal, or as the
+ * faces are listed where that is zero), out[1] = int p, out[2] = area (the
+ * mean pressure is out[1] / out[2]).  P1-P1; host array of 3; synchronises
+ * the simulation's stream.  LX_EINVAL for a bad index or a P2-P1 problem. */
+lx_status lx_sim_boundary_integrals(lx_sim *sim, int32_t bc, double *out);
+
 void lx_sim_destroy(lx_sim *sim);
 
 /* ---------------------------------------------------------------- serving */
 
 /* A continuous-batching server: requests (mesh + problem + solver + step
- * count) are admitted while the device-memory budget and the active-slot limit
- * allow, stepped together on the device with their work interleaved on a pool
- * of streams, and retired when done; new requests are admitted as memory and
- * slots free up. */
+ * count) are admitted in arrival order while the device-memory budget and the
+ * active-slot limit allow, set up by a pool of host threads on streams of their
+ * own, then stepped by one persistent worker thread per stream (each worker
+ * steps its simulations in turn, one time step each, so that the device work of
+ * the streams overlaps), and retired by their worker when done; new requests
+ * are admitted as memory and slots free up.  Every simulation's arithmetic is
+ * independent of what else runs (fixed-order reductions), so a served result
+ * is bitwise the one the same request gives alone.  The server's simulations
+ * allocate with hipMalloc (cfg.device.alloc / free must be NULL). */
 typedef struct {
     lx_device device;
     int64_t hbm_budget_bytes;   /* admission limit on summed simulation footprints */
@@ -384,7 +413,9 @@ typedef struct {
     int32_t pad;
 } lx_request;
 
-enum { LX_REQ_QUEUED = 0, LX_REQ_RUNNING = 1, LX_REQ_DONE = 2, LX_REQ_FAILED = 3 };
+/* QUEUED: waiting for admission; SETUP: admitted (memory reserved), being set up;
+ * RUNNING: stepping; DONE / FAILED: final, until lx_server_result releases it. */
+enum { LX_REQ_QUEUED = 0, LX_REQ_RUNNING = 1, LX_REQ_DONE = 2, LX_REQ_FAILED = 3, LX_REQ_SETUP = 4 };
 typedef struct {
     int32_t state;
     int32_t steps_done;
@@ -393,6 +424,7 @@ typedef struct {
 
 typedef struct {
     double admit_wait_ms;       /* submission to admission                          */
+    double setup_ms;            /* admission to the first step's eligibility (set-up) */
     double total_ms;            /* submission to completion                         */
     double step_p50_ms, step_p99_ms;  /* per step: eligible -> completed            */
     int32_t n_steps;
@@ -402,11 +434,19 @@ typedef struct {
 typedef struct lx_server lx_server;
 
 lx_status lx_server_create(const lx_server_cfg *cfg, lx_server **out);
-/* Copies the request's arrays; returns a ticket.  LX_EBUSY if the request alone
- * exceeds the budget; LX_EINVAL for a P2-P1 problem (the server runs P1-P1). */
+/* Copies the request's arrays; returns a ticket.  LX_EBUSY if the request's
+ * footprint estimate alone exceeds the budget; LX_EINVAL for a P2-P1 problem
+ * (the server runs P1-P1).  Admission reserves the estimate; once the
+ * simulation exists its measured footprint replaces it, and if that breaks the
+ * budget the simulation is released and the request queued again at the front
+ * with the measured figure (FAILED if that alone exceeds the budget).  All
+ * lx_server_* calls are thread-safe and return LX_ENOMEM / LX_EDEVICE on a host
+ * exception instead of throwing. */
 lx_status lx_server_submit(lx_server *srv, const lx_request *req, int64_t *ticket);
-/* Run one scheduling tick: admit what fits, advance every active simulation by
- * one step, retire finished ones.  *n_active gets the active count afterwards. */
+/* The first tick starts the server's streams and threads.  A tick admits what
+ * fits, then waits until a step, set-up or retirement completes (at most 20 ms;
+ * with nothing admitted it returns at once) and admits again.  Stepping does not
+ * wait for ticks.  *n_active gets the admitted count (set-up + running). */
 lx_status lx_server_tick(lx_server *srv, int32_t *n_active);
 lx_status lx_server_poll(lx_server *srv, int64_t ticket, lx_request_status *st);
 /* Copy a finished request's solution (u [n][3], p [n], caller numbering) and

@@ -380,4 +380,24 @@ extern "C" lx_status lx_sim_debug_residual(lx_sim *s, const double *u, const dou
     return LX_OK;
 }
 
+extern "C" lx_status lx_sim_boundary_integrals(lx_sim *s, int32_t bc, double *out)
+{
+    LX_GUARD(s);
+    if (!out) return fail(LX_EINVAL, "out is NULL");
+    if (s->p2) return fail(LX_EINVAL, "boundary integrals are built for the P1-P1 pair");
+    if (bc < 0 || bc >= (int32_t)s->bcs.size()) return fail(LX_EINVAL, "bad boundary condition index %d", bc);
+    const lx::BCDesc &B = s->bcs[bc];
+    if (B.nf == 0 || !B.d_faces) {
+        out[0] = out[1] = out[2] = 0.0;
+        return LX_OK;
+    }
+    (void)hipSetDevice(s->device);
+    lx::launch_boundary_integrals(B.nf, B.d_faces, s->d_x, B.spec.profile.normal, s->d_hist[0],
+                                  s->prob.ale ? s->d_uA : nullptr, s->d_bint, s->stream);
+    LX_HIP(hipGetLastError());
+    LX_HIP(hipMemcpyAsync(out, s->d_bint, sizeof(double) * 3, hipMemcpyDeviceToHost, s->stream));
+    LX_HIP(hipStreamSynchronize(s->stream));
+    return LX_OK;
+}
+
 extern "C" void lx_sim_destroy(lx_sim *s) { delete s; }

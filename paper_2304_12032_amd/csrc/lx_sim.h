@@ -7,6 +7,7 @@
 #include "lx_amg.h"
 #include "lx_common.h"
 #include "lx_kernels.h"
+#include "lx_outflow.h"
 #include "lx_p2.h"
 
 namespace lx {
@@ -60,6 +61,10 @@ struct Sim {
     std::vector<int32_t> h_dir_index, h_dir_node, h_dir_bc;
     std::vector<double> h_gnodal;
     bool dirty_gnodal = false;
+    // outflow conditions with a resistance or backflow term (P1-P1), and the
+    // device result of lx_sim_boundary_integrals
+    std::vector<OutflowDev> outflow;
+    double *d_bint = nullptr;
 
     // device arrays (new numbering)
     double *d_xh = nullptr, *d_x = nullptr;
@@ -179,6 +184,8 @@ struct Sim {
     lx_status assemble_system(double t1, StepCoef &C, bool fork_residual = false);
     lx_status build_system_p2(double t1, StepCoef &C);
     void add_neumann(double t1, double *out0, double *out1);
+    lx_status outflow_setup();
+    double outflow_p0(const OutflowDev &o, double t1) const;
     lx_status residual64(const StepCoef &C, const double *xs, bool first, double t1);
     lx_status residual64_into(const StepCoef &C, const double *xs, bool first, double t1, double *rec, double *r,
                               double *b, bool timed);

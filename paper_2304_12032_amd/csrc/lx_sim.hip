@@ -143,7 +143,13 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         if (b.spec.n_tags > 0 && !b.spec.tags) return fail(LX_EINVAL, "bc %d: tags NULL", i);
         b.tags.assign(b.spec.tags, b.spec.tags + b.spec.n_tags);
         b.spec.tags = nullptr;
-        if (b.spec.type < 0 || b.spec.type > 2) return fail(LX_EINVAL, "bc %d: bad type", i);
+        if (b.spec.type < 0 || b.spec.type > 3) return fail(LX_EINVAL, "bc %d: bad type", i);
+        if (b.spec.resistance < 0 || b.spec.backflow < 0)
+            return fail(LX_EINVAL, "bc %d: negative resistance or backflow coefficient", i);
+        if (b.spec.backflow > 0 && b.spec.type != LX_BC_NEUMANN && b.spec.type != LX_BC_RESISTANCE)
+            return fail(LX_EINVAL, "bc %d: backflow stabilisation applies to Neumann and resistance conditions", i);
+        if (pr->fe == LX_P2P1 && (b.spec.type == LX_BC_RESISTANCE || b.spec.backflow > 0))
+            return fail(LX_EINVAL, "bc %d: resistance and backflow terms are built for P1-P1", i);
         bcs.push_back(b);
     }
     prob.bc = nullptr;
@@ -213,8 +219,9 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         }
     n_dir = (int64_t)h_dir_node.size();
     h_gnodal.assign(3 * std::max<int64_t>(n_dir, 1), 0.0);
+    // faces of the Neumann conditions (P1-P1: of every condition, for the boundary integrals)
     for (int i = 0; i < (int)bcs.size(); ++i) {
-        if (bcs[i].spec.type != LX_BC_NEUMANN) continue;
+        if (bcs[i].spec.type != LX_BC_NEUMANN && p2) continue;
         if (!face_vertices(bcs[i].tags, fv)) return fail(LX_EMESH, "boundary face vertex out of range");
         bcs[i].nf = (int64_t)fv.size() / (p2 ? 6 : 3);
         bcs[i].h_faces = fv;
@@ -319,7 +326,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         if (s2 != LX_OK) return s2;
     }
     for (auto &b : bcs)
-        if (b.spec.type == LX_BC_NEUMANN && b.nf > 0) {
+        if ((b.spec.type == LX_BC_NEUMANN || !p2) && b.nf > 0) {
             ALLOC(b.d_faces, sizeof(int32_t) * b.h_faces.size());
             if (b.spec.profile.kind == LX_PROFILE_NODAL) ALLOC(b.d_hnodal, sizeof(double) * 3 * nu);
         }
@@ -451,6 +458,10 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         if (b.d_faces)
             LX_HIP(hipMemcpyAsync(b.d_faces, b.h_faces.data(), sizeof(int32_t) * b.h_faces.size(),
                                   hipMemcpyHostToDevice, stream));
+    if (!p2) {
+        lx_status so = outflow_setup();
+        if (so != LX_OK) return so;
+    }
     for (int l = 0; l < std::max(L, 4); ++l) launch_fill<double>(N, d_hist[l], 0.0, stream);
     launch_fill<double>(N, d_xs, 0.0, stream);
     if (d_f) launch_fill<double>(3 * nu, d_f, 0.0, stream);
@@ -838,6 +849,7 @@ void Sim::spmv(const T *x, T *y, const int32_t *done, std::pair<hipEvent_t, hipE
     else
         launch_spmv<T>(pattern(), Ops<T>::val(this), x, y, done, s, tm ? tm->first : nullptr,
                        tm ? tm->second : nullptr);
+    for (const OutflowDev &o : outflow) launch_rank1<T>(o, x, y, done, s);
 }
 
 lx_status Sim::read_state()
@@ -1055,6 +1067,8 @@ lx_status Sim::prepare(double t1, StepCoef &C)
         lx_status s = ale_update(t1, C);
         if (s != LX_OK) return s;
     }
+    for (const OutflowDev &o : outflow)
+        launch_outflow_prepare(o, d_x, hist(0), hist(1), hist(2), C.gamma, prob.rho, stream);
     if (n_dir > 0) {
         if (dirty_gnodal) {
             LX_HIP(hipMemcpyAsync(d_gnodal, h_gnodal.data(), sizeof(double) * 3 * n_dir, hipMemcpyHostToDevice,
@@ -1091,6 +1105,10 @@ lx_status Sim::assemble_system(double t1, StepCoef &C, bool fork_residual)
         launch_assemble_p1<double>(A, C, stream);
         timer_end(tm);
         add_neumann(t1, d_rhs64, nullptr);
+        for (const OutflowDev &o : outflow) {
+            launch_backflow_add<double>(o, nblk, d_val64, stream);
+            launch_outflow_rhs(o, outflow_p0(o, t1), prob.ale ? d_uA : nullptr, d_rhs64, stream);
+        }
         launch_dirichlet_rows<double>(n_dir, d_dir_node, d_g, P, d_val64, d_rhs64, stream);
         launch_simple_setup<double>(P, d_val64, d_Finv64, d_Dinv64, solver.precond == LX_PC_AMG ? nullptr : d_Sinv64,
                                   stream);
@@ -1113,6 +1131,7 @@ lx_status Sim::assemble_system(double t1, StepCoef &C, bool fork_residual)
             launch_assemble_p1<float>(A, C, stream);
             timer_end(tm);
         }
+        for (const OutflowDev &o : outflow) launch_backflow_add<float>(o, nblk, d_val32, stream);
         launch_dirichlet_rows<float>(n_dir, d_dir_node, d_g, P, d_val32, (float *)nullptr, stream);
         if (fork_residual) {
             // the residual reads the element data and the history, not the FP32
@@ -1158,6 +1177,112 @@ lx_status Sim::build_system_p2(double t1, StepCoef &C)
     }
     LX_HIP(hipGetLastError());
     return LX_OK;
+}
+
+// Host lists of the outflow conditions (resistance, backflow): boundary vertices
+// with their face incidences, and the backflow vertex pairs with their blocks.
+lx_status Sim::outflow_setup()
+{
+    lx_status a = dalloc((void **)&d_bint, sizeof(double) * 4);
+    if (a != LX_OK) return a;
+    std::vector<std::vector<int32_t>> keep_alive;
+    auto up32 = [&](int32_t **dst, std::vector<int32_t> v) -> lx_status {
+        if (v.empty()) v.push_back(0);
+        lx_status r = dalloc((void **)dst, sizeof(int32_t) * v.size());
+        if (r != LX_OK) return r;
+        keep_alive.push_back(std::move(v));
+        const auto &h = keep_alive.back();
+        LX_HIP(hipMemcpyAsync(*dst, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, stream));
+        return LX_OK;
+    };
+    for (int i = 0; i < (int)bcs.size(); ++i) {
+        const BCDesc &B = bcs[i];
+        const bool res = B.spec.type == LX_BC_RESISTANCE && B.spec.resistance > 0;
+        const bool back = B.spec.backflow > 0;
+        if ((!res && !back) || B.nf == 0) continue;
+        OutflowDev o;
+        o.bc = i;
+        for (int c = 0; c < 3; ++c) o.dir[c] = B.spec.profile.normal[c];
+        o.cr = res ? B.spec.resistance : 0.0;
+        o.beta = back ? B.spec.backflow : 0.0;
+        o.nf = B.nf;
+        o.faces = B.d_faces;
+        const std::vector<int32_t> &F = B.h_faces;
+        // boundary vertices and their face corners (codes 3 f + l, ascending f)
+        std::vector<int32_t> bv(F.begin(), F.end());
+        std::sort(bv.begin(), bv.end());
+        bv.erase(std::unique(bv.begin(), bv.end()), bv.end());
+        o.nbv = (int64_t)bv.size();
+        auto slot = [&](int32_t v) { return (int64_t)(std::lower_bound(bv.begin(), bv.end(), v) - bv.begin()); };
+        std::vector<int32_t> vptr(o.nbv + 1, 0), vinc(3 * o.nf), keep(o.nbv);
+        for (int64_t k = 0; k < 3 * o.nf; ++k) vptr[slot(F[k]) + 1]++;
+        for (int64_t j = 0; j < o.nbv; ++j) vptr[j + 1] += vptr[j];
+        {
+            std::vector<int32_t> fill(vptr.begin(), vptr.end() - 1);
+            for (int64_t k = 0; k < 3 * o.nf; ++k) vinc[fill[slot(F[k])]++] = (int32_t)k;
+        }
+        for (int64_t j = 0; j < o.nbv; ++j) keep[j] = h_dir_index[bv[j]] < 0 ? 1 : 0;
+        // backflow pairs (a, b), a kept: incidences in ascending face order
+        std::vector<std::pair<std::pair<int32_t, int32_t>, int32_t>> inc;   // ((a, b), code)
+        if (back)
+            for (int64_t f = 0; f < o.nf; ++f)
+                for (int la = 0; la < 3; ++la)
+                    for (int lb = 0; lb < 3; ++lb) {
+                        const int32_t va = F[3 * f + la], vb = F[3 * f + lb];
+                        if (h_dir_index[va] >= 0) continue;
+                        inc.push_back({{va, vb}, (int32_t)((f << 4) | (la << 2) | lb)});
+                    }
+        std::stable_sort(inc.begin(), inc.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+        std::vector<int32_t> pblk, pcol, pptr{0}, pinc, rptr{0}, rvert;
+        for (size_t k = 0; k < inc.size(); ++k) {
+            const bool new_pair = k == 0 || inc[k].first != inc[k - 1].first;
+            if (new_pair) {
+                const int32_t va = inc[k].first.first, vb = inc[k].first.second;
+                int32_t blk = -1;
+                for (int32_t q = hs.rowptr[va]; q < hs.rowptr[va + 1]; ++q)
+                    if (hs.col[q] == vb) blk = q;
+                if (blk < 0) return fail(LX_EMESH, "bc %d: boundary face edge missing from the matrix pattern", i);
+                if (k > 0) pptr.push_back((int32_t)k);
+                if (rvert.empty() || rvert.back() != va) {
+                    if (!rvert.empty()) rptr.push_back((int32_t)pblk.size());
+                    rvert.push_back(va);
+                }
+                pblk.push_back(blk);
+                pcol.push_back(vb);
+            }
+            pinc.push_back(inc[k].second);
+        }
+        pptr.push_back((int32_t)inc.size());
+        rptr.push_back((int32_t)pblk.size());
+        o.npair = (int64_t)pblk.size();
+        o.nrow = (int64_t)rvert.size();
+        if (o.npair == 0) {
+            pptr.assign(1, 0);
+            rptr.assign(1, 0);
+        }
+        lx_status r;
+        if ((r = up32(&o.bv, bv)) != LX_OK || (r = up32(&o.vptr, vptr)) != LX_OK ||
+            (r = up32(&o.vinc, vinc)) != LX_OK || (r = up32(&o.keep, keep)) != LX_OK ||
+            (r = up32(&o.pblk, pblk)) != LX_OK || (r = up32(&o.pcol, pcol)) != LX_OK ||
+            (r = up32(&o.pptr, pptr)) != LX_OK || (r = up32(&o.pinc, pinc)) != LX_OK ||
+            (r = up32(&o.rptr, rptr)) != LX_OK || (r = up32(&o.rvert, rvert)) != LX_OK)
+            return r;
+        if ((r = dalloc((void **)&o.geom, sizeof(double) * 4 * o.nf)) != LX_OK ||
+            (r = dalloc((void **)&o.w, sizeof(double) * 3 * o.nbv)) != LX_OK ||
+            (r = dalloc((void **)&o.pcoef, sizeof(double) * std::max<int64_t>(o.npair, 1))) != LX_OK)
+            return r;
+        launch_fill<double>(3 * o.nbv, o.w, 0.0, stream);
+        launch_fill<double>(std::max<int64_t>(o.npair, 1), o.pcoef, 0.0, stream);
+        outflow.push_back(o);
+    }
+    LX_HIP(hipStreamSynchronize(stream));   // the host lists are local
+    return LX_OK;
+}
+
+double Sim::outflow_p0(const OutflowDev &o, double t1) const
+{
+    const lx_boundary &b = bcs[o.bc].spec;
+    return b.type == LX_BC_RESISTANCE ? b.theta * law_value(b.law, t1) : 0.0;
 }
 
 void Sim::add_neumann(double t1, double *out0, double *out1)
@@ -1215,6 +1340,8 @@ lx_status Sim::residual64_into(const StepCoef &C, const double *xs, bool first, 
     launch_residual_p1(R, C, stream);
     timer_end(tm);
     add_neumann(t1, r, first ? b : nullptr);
+    for (const OutflowDev &o : outflow)
+        launch_outflow_residual(o, outflow_p0(o, t1), prob.ale ? d_uA : nullptr, xs, r, first ? b : nullptr, stream);
     launch_dirichlet_residual(n_dir, d_dir_node, d_g, d_dg, xs, r, first ? b : nullptr, stream);
     LX_HIP(hipGetLastError());
     return LX_OK;

@@ -23,13 +23,13 @@ STATUS_NAMES = {0: "LX_OK", -1: "LX_EINVAL", -2: "LX_ENOMEM", -3: "LX_EDEVICE", 
                 -5: "LX_EMESH", -6: "LX_EBUSY", -7: "LX_ESTATE"}
 LAW = {"constant": 0, "pulsatile": 1, "ramp": 2, "ramp2": 3, "linear": 4, "sine": 5}
 PROFILE = {"uniform": 0, "parabolic": 1, "nodal": 2}
-BC = {"noslip": 0, "dirichlet": 1, "neumann": 2}
+BC = {"noslip": 0, "dirichlet": 1, "neumann": 2, "resistance": 3}
 FE = {"p1p1": 1, "p2p1": 2}
 DIFF = {"gradgrad": 0, "symgrad": 1}
 STAB = {"none": 0, "supg_pspg": 1, "vms_les": 2}
 PREC = {"fp64": 0, "fp32_ir": 1}
 PRECOND = {"amg": 0, "cheb_schur": 1}
-REQ_STATE = {0: "queued", 1: "running", 2: "done", 3: "failed"}
+REQ_STATE = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "setup"}
 
 
 class LxError(RuntimeError):
@@ -79,7 +79,7 @@ class lx_profile(ctypes.Structure):
 
 class lx_boundary(ctypes.Structure):
     _fields_ = [("type", c_i32), ("n_tags", c_i32), ("tags", P(c_i32)), ("theta", c_dbl), ("law", lx_time_law),
-                ("profile", lx_profile)]
+                ("profile", lx_profile), ("resistance", c_dbl), ("backflow", c_dbl)]
 
 
 class lx_riis(ctypes.Structure):
@@ -133,7 +133,7 @@ class lx_request_status(ctypes.Structure):
 
 
 class lx_latency_stats(ctypes.Structure):
-    _fields_ = [("admit_wait_ms", c_dbl), ("total_ms", c_dbl), ("step_p50_ms", c_dbl), ("step_p99_ms", c_dbl),
+    _fields_ = [("admit_wait_ms", c_dbl), ("setup_ms", c_dbl), ("total_ms", c_dbl), ("step_p50_ms", c_dbl), ("step_p99_ms", c_dbl),
                 ("n_steps", c_i32), ("gmres_iters", c_i32)]
 
     def as_dict(self):
@@ -160,6 +160,7 @@ SIGNATURES = {
     "lx_sim_debug_export": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lx_sim_debug_export_p2": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lx_sim_debug_residual": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
+    "lx_sim_boundary_integrals": (c_i32, [c_vp, c_i32, c_vp]),
     "lx_sim_residual_noalloc": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "lx_sim_destroy": (None, [c_vp]),
     "lx_server_create": (c_i32, [P(lx_server_cfg), P(c_vp)]),
@@ -235,6 +236,8 @@ class _Marshal:
             pr.normal[:] = list(b.profile.normal)
             pr.radius = b.profile.radius
             bcs[i].profile = pr
+            bcs[i].resistance = getattr(b, "resistance", 0.0)
+            bcs[i].backflow = getattr(b, "backflow", 0.0)
         rs = (lx_riis * max(1, len(prob.valves)))()
         for i, v in enumerate(prob.valves):
             rs[i].center[:] = list(v.center)
@@ -411,6 +414,12 @@ class Sim:
         rhs = np.zeros((self.nv, 4))
         check(lib().lx_sim_debug_export(self.h, br.ctypes.data, bc.ctypes.data, vals.ctypes.data, rhs.ctypes.data))
         return br, bc, vals, rhs
+
+    def boundary_integrals(self, bc_index):
+        """(int (u - u_ALE) . n, int p, area) over condition bc_index's faces, last step."""
+        out = np.zeros(3)
+        check(lib().lx_sim_boundary_integrals(self.h, int(bc_index), out.ctypes.data))
+        return out
 
     def residual(self, u, p):
         u = np.ascontiguousarray(u, dtype=np.float64)

@@ -171,3 +171,40 @@ def beltrami_ale(n=4, c=0.5, dt=0.01, nodal=True):
         s.set_neumann_traction(1, ex.traction(Xb, t1, (-1, 0, 0)))
 
     return Case(mesh, prob, init, drive, "beltrami_ale%d%s" % (n, "_nodal" if nodal else ""))
+
+
+def tube_outflow(nxy=4, nz=8, length=2.0, kind="resistance", cr=40.0, beta=1.0, p0=2.0, ale=False, seed=13,
+                 bdf=2):
+    """Tube whose outlet carries a resistance condition (p0 constant, C_R = cr) or a plain
+    Neumann one, with inertial backflow stabilisation (beta); random history whose axial
+    velocity is negative over part of the outlet, so that the backflow term is active;
+    optional ALE with an axially stretching outlet."""
+    from inputs.problem import Boundary, Profile, TimeLaw
+    mesh = tube(nxy=nxy, nz=nz, radius=1.0, length=length, seed=seed)
+    prob = tube_problem(mesh, dt=2e-3, bdf_order=bdf, peak=30.0, valve=False)
+    prob.bcs[2] = Boundary(kind, (TUBE_TAGS["outlet"],), law=TimeLaw("constant", (p0,)),
+                           profile=Profile("uniform", normal=(0.0, 0.0, 1.0)), resistance=cr, backflow=beta)
+    rng = np.random.default_rng(seed)
+    X = mesh.coords
+    hist = []
+    for _ in range(bdf):
+        u = rng.normal(size=(mesh.nv, 3))
+        u[:, 2] += 3.0 * np.sin(2.0 * X[:, 0]) + 1.0      # inflow and outflow across the outlet
+        hist.append((u, rng.normal(size=mesh.nv) * 10.0))
+    shape = np.zeros_like(X)
+    shape[:, 2] = 0.05 * X[:, 2] * (1.0 + 0.3 * X[:, 0])
+    if ale:
+        prob.ale = True
+        prob.ale_tags = (TUBE_TAGS["outlet"], TUBE_TAGS["inlet"], TUBE_TAGS["wall"])
+        prob.ale_law = TimeLaw("linear", (0.0, 5.0))
+
+    def init(s):
+        for lev in range(bdf):
+            s.set_state(lev, *hist[lev])
+        if ale:
+            s.set_ale_displacement(shape)
+
+    def drive(s, t1):
+        pass
+
+    return Case(mesh, prob, init, drive, "tube_%s%s" % (kind, "_ale" if ale else ""))

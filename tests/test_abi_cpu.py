@@ -133,3 +133,29 @@ def test_server_rejects_request_over_budget():
     assert srv2.poll(t)["footprint_bytes"] > 0
     srv.close()
     srv2.close()
+
+
+@pytest.mark.parametrize("what", ["p2_resistance", "p2_backflow", "negative_resistance", "backflow_on_dirichlet"])
+def test_bad_outflow_conditions_rejected(what):
+    """Resistance and backflow terms are built for P1-P1 Neumann-type conditions with
+    non-negative coefficients; anything else is rejected during validation."""
+    from paper_2304_12032_amd import LxError
+    from inputs.meshes import TUBE_TAGS
+    from inputs.problem import Boundary, Profile, TimeLaw
+    m = tube(nxy=3, nz=4, length=1.0)
+    prob = tube_problem(m, valve=False)
+    out = Boundary("resistance", (TUBE_TAGS["outlet"],), law=TimeLaw("constant", (0.0,)),
+                   profile=Profile("uniform", normal=(0.0, 0.0, 1.0)), resistance=10.0)
+    if what == "p2_resistance":
+        prob.fe = "p2p1"
+    elif what == "p2_backflow":
+        prob.fe = "p2p1"
+        out.type, out.resistance, out.backflow = "neumann", 0.0, 1.0
+    elif what == "negative_resistance":
+        out.resistance = -1.0
+    else:
+        prob.bcs[1].backflow = 1.0
+    prob.bcs[2] = out
+    with pytest.raises(LxError) as ei:
+        _create(m, prob, SolverCfg())
+    assert ei.value.status == -1
