@@ -154,11 +154,22 @@ enum { LX_P1P1 = 1, LX_P2P1 = 2 };
 enum { LX_DIFF_GRADGRAD = 0, LX_DIFF_SYMGRAD = 1 };              /* eq. (diffusion-term) */
 enum { LX_STAB_NONE = 0, LX_STAB_SUPG_PSPG = 1, LX_STAB_VMS_LES = 2 };
 
+/* Lifting problem of the ALE displacement (Sec. 2.1.1, eq. (lifting)):
+ * -div(alpha sigma_L(d)) = 0 on the reference mesh, d given on the vertices of
+ * the ale_tags faces, zero traction elsewhere.  sigma_L = grad d (harmonic) or
+ * E/(1+nu) sym grad d + E nu/((1+nu)(1-2nu)) div d I (linear elasticity,
+ * moduli lift_E > 0, 0 <= lift_nu < 1/2).  Stiffening alpha, constant per
+ * element: 1; (J0/J)^chi with J = |det| of the map from the unit simplex to
+ * the element (stiff_p = {J0, chi}); or max(d, beta)^-gamma with d the distance
+ * from the element's centroid to the ale_tags faces (stiff_p = {beta, gamma}). */
+enum { LX_LIFT_HARMONIC = 0, LX_LIFT_ELASTIC = 1 };
+enum { LX_STIFF_NONE = 0, LX_STIFF_JACOBIAN = 1, LX_STIFF_BOUNDARY = 2 };
+
 /* The problem of Sec. 2.1-2.3: FE pair, BDF order (1..3) and time step (eq. (bdf)),
  * density and viscosity, diffusion form, stabilisation with constant C_r of
  * tau_M, semi-implicit advection (the only mode), ALE on/off with the boundary
  * displacement d^ = ale_law(t) * D^(x^) on the vertices of faces tagged ale_tags
- * (D^ set by lx_sim_set_ale_displacement), nodal forcing on/off. */
+ * (D^ set by lx_sim_set_ale_displacement) and its lifting, nodal forcing on/off. */
 typedef struct {
     int32_t fe, bdf_order;
     double dt, t0, rho, mu;
@@ -174,6 +185,10 @@ typedef struct {
     const lx_riis *riis;
     const int32_t *ale_tags;
     lx_time_law ale_law;
+    int32_t lifting;         /* LX_LIFT_*                                            */
+    int32_t stiffening;      /* LX_STIFF_*                                           */
+    double lift_E, lift_nu;  /* elasticity moduli (LX_LIFT_ELASTIC)                  */
+    double stiff_p[2];       /* {J0, chi} or {beta, gamma}                           */
 } lx_problem;
 
 enum { LX_FP64 = 0, LX_FP32_IR = 1 };

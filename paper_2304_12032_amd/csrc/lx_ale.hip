@@ -1,7 +1,13 @@
 // ALE mesh motion (paper Sec. 2.1.1 and the discrete mesh velocity of Sec. 2.3):
-// harmonic extension of the boundary displacement on the reference mesh with
-// a P1 Laplacian (stiffening alpha = 1), solved by Jacobi-preconditioned CG
-// for the three components at once; then x^{n+1} = x^ + d^{n+1} and
+// lifting of the boundary displacement on the reference mesh, eq. (lifting),
+// with a P1 stiffness assembled once: the harmonic extension (a scalar
+// Laplacian per block slot, the three components solved as three CGs side by
+// side, Jacobi-preconditioned) or linear elasticity (3x3 blocks coupling the
+// components, one CG, block-Jacobi-preconditioned), each weighted per element
+// by the stiffening coefficient: 1, the Jacobian-based (J0/J)^chi, or the
+// boundary-based max(d, beta)^-gamma with d the distance from the element's
+// centroid to the moving boundary's faces (one pass over all faces per element
+// on the device, at set-up).  Then x^{n+1} = x^ + d^{n+1} and
 // u_ALE = (alpha d^{n+1} - sum_l beta_l d^{n-l}) / dt at the vertices.
 //
 // Two ways to give the boundary data:
@@ -26,40 +32,77 @@ struct CgState {
     uint32_t counter, pad;
 };
 
-// y = L x for [nv][3] vectors, scalar values per block slot
-template <int LPR>
-__device__ inline void lap_row(int64_t row, int lane, const int32_t *rowptr, const int32_t *col, const double *L,
-                               const double *x, double &y0, double &y1, double &y2)
+// The lifting operator on [nv][3] vectors: VEC = false, one scalar per block
+// slot applied to each component (harmonic); VEC = true, 3x3 blocks stored as
+// nine planes of length nblk, plane 3c+d (elasticity).
+struct LiftOp {
+    const int32_t *rowptr, *col;
+    const double *K;
+    int64_t nblk;
+};
+
+template <int LPR, bool VEC>
+__device__ inline void lift_row(int64_t row, int lane, const LiftOp &A, const double *x, double y[3])
 {
-    y0 = y1 = y2 = 0;
-    for (int32_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += LPR) {
-        const double a = L[k];
-        const double *xj = x + 3 * (int64_t)col[k];
-        y0 += a * xj[0];
-        y1 += a * xj[1];
-        y2 += a * xj[2];
+    y[0] = y[1] = y[2] = 0;
+    for (int32_t k = A.rowptr[row] + lane; k < A.rowptr[row + 1]; k += LPR) {
+        const double *xj = x + 3 * (int64_t)A.col[k];
+        if (VEC) {
+            for (int c = 0; c < 3; ++c)
+                for (int d = 0; d < 3; ++d) y[c] += A.K[(int64_t)(3 * c + d) * A.nblk + k] * xj[d];
+        } else {
+            const double a = A.K[k];
+            for (int c = 0; c < 3; ++c) y[c] += a * xj[c];
+        }
     }
-    y0 = group_sum<double, LPR>(y0);
-    y1 = group_sum<double, LPR>(y1);
-    y2 = group_sum<double, LPR>(y2);
+    for (int c = 0; c < 3; ++c) y[c] = group_sum<double, LPR>(y[c]);
+}
+
+// z = P r at one vertex: P = 1 / diagonal (scalar) or the inverse 3x3 diagonal block
+template <bool VEC>
+__device__ inline void lift_prec(int64_t row, const double *dinv, const double r[3], double z[3])
+{
+    if (VEC) {
+        const double *D = dinv + 9 * row;
+        for (int c = 0; c < 3; ++c) z[c] = D[3 * c] * r[0] + D[3 * c + 1] * r[1] + D[3 * c + 2] * r[2];
+    } else {
+        for (int c = 0; c < 3; ++c) z[c] = dinv[row] * r[c];
+    }
+}
+
+// One CG for the coupled system: the three per-component sums become one.
+template <bool VEC, int K>
+__device__ inline void lift_combine(double (&tot)[K], int first)
+{
+    if (VEC) {
+        const double s = tot[first] + tot[first + 1] + tot[first + 2];
+        tot[first] = tot[first + 1] = tot[first + 2] = s;
+    }
 }
 
 constexpr int kAleLPR = 16;
 
 // rhs: boundary rows d_B; interior rows -sum_{j in B} Lfull_ij d_B(j).  d0: initial
 // guess with boundary rows set.
-__global__ __launch_bounds__(256) void k_ale_rhs(int64_t nv, const int32_t *rowptr, const int32_t *col,
-                                                 const double *Lfull, const int32_t *mark, const double *shape,
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_ale_rhs(int64_t nv, LiftOp Afull, const int32_t *mark, const double *shape,
                                                  double scale, double *rhs, double *d0)
 {
     const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / kAleLPR;
     const int lane = threadIdx.x % kAleLPR;
     if (row >= nv) return;
     double y[3] = {0, 0, 0};
-    for (int32_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += kAleLPR) {
-        const int64_t j = col[k];
-        if (mark[j])
-            for (int c = 0; c < 3; ++c) y[c] += Lfull[k] * scale * shape[3 * j + c];
+    for (int32_t k = Afull.rowptr[row] + lane; k < Afull.rowptr[row + 1]; k += kAleLPR) {
+        const int64_t j = Afull.col[k];
+        if (mark[j]) {
+            if (VEC) {
+                for (int c = 0; c < 3; ++c)
+                    for (int d = 0; d < 3; ++d)
+                        y[c] += Afull.K[(int64_t)(3 * c + d) * Afull.nblk + k] * scale * shape[3 * j + d];
+            } else {
+                for (int c = 0; c < 3; ++c) y[c] += Afull.K[k] * scale * shape[3 * j + c];
+            }
+        }
     }
     for (int c = 0; c < 3; ++c) y[c] = group_sum<double, kAleLPR>(y[c]);
     if (lane == 0) {
@@ -75,8 +118,8 @@ __global__ __launch_bounds__(256) void k_ale_rhs(int64_t nv, const int32_t *rowp
 }
 
 // r = rhs - L d; z = Dinv r; p = z; rz, rr, tolerance
-__global__ __launch_bounds__(256) void k_cg_init(int64_t nv, const int32_t *rowptr, const int32_t *col,
-                                                 const double *L, const double *dinv, const double *rhs,
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_cg_init(int64_t nv, LiftOp A, const double *dinv, const double *rhs,
                                                  const double *d, double *r, double *z, double *p, CgState *st,
                                                  double *partial, double rtol)
 {
@@ -86,18 +129,20 @@ __global__ __launch_bounds__(256) void k_cg_init(int64_t nv, const int32_t *rowp
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (row < nv) {
         double y[3];
-        lap_row<kAleLPR>(row, lane, rowptr, col, L, d, y[0], y[1], y[2]);
-        if (lane == 0)
+        lift_row<kAleLPR, VEC>(row, lane, A, d, y);
+        if (lane == 0) {
+            double rr[3], zz[3];
+            for (int c = 0; c < 3; ++c) rr[c] = rhs[3 * row + c] - y[c];
+            lift_prec<VEC>(row, dinv, rr, zz);
             for (int c = 0; c < 3; ++c) {
-                double rc = rhs[3 * row + c] - y[c];
-                double zc = dinv[row] * rc;
-                r[3 * row + c] = rc;
-                z[3 * row + c] = zc;
-                p[3 * row + c] = zc;
-                acc[c] = rc * zc;
-                acc[3 + c] = rc * rc;
+                r[3 * row + c] = rr[c];
+                z[3 * row + c] = zz[c];
+                p[3 * row + c] = zz[c];
+                acc[c] = rr[c] * zz[c];
+                acc[3 + c] = rr[c] * rr[c];
                 acc[6 + c] = rhs[3 * row + c] * rhs[3 * row + c];
             }
+        }
     }
     block_sum<9>(acc, lds);
     if (threadIdx.x == 0)
@@ -105,6 +150,9 @@ __global__ __launch_bounds__(256) void k_cg_init(int64_t nv, const int32_t *rowp
     if (!arrive_last(&st->counter)) return;
     double tot[9];
     reduce_partials<9>(partial, gridDim.x, 9, tot, lds);
+    lift_combine<VEC>(tot, 0);
+    lift_combine<VEC>(tot, 3);
+    lift_combine<VEC>(tot, 6);
     if (threadIdx.x == 0) {
         bool done = true;
         for (int c = 0; c < 3; ++c) {
@@ -120,8 +168,8 @@ __global__ __launch_bounds__(256) void k_cg_init(int64_t nv, const int32_t *rowp
 }
 
 // q = L p, alpha = rz / (p.q)
-__global__ __launch_bounds__(256) void k_cg_ap(int64_t nv, const int32_t *rowptr, const int32_t *col,
-                                               const double *L, const double *p, double *q, CgState *st,
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_cg_ap(int64_t nv, LiftOp A, const double *p, double *q, CgState *st,
                                                double *partial)
 {
     if (st->done) return;
@@ -131,7 +179,7 @@ __global__ __launch_bounds__(256) void k_cg_ap(int64_t nv, const int32_t *rowptr
     double acc[3] = {0, 0, 0};
     if (row < nv) {
         double y[3];
-        lap_row<kAleLPR>(row, lane, rowptr, col, L, p, y[0], y[1], y[2]);
+        lift_row<kAleLPR, VEC>(row, lane, A, p, y);
         if (lane == 0)
             for (int c = 0; c < 3; ++c) {
                 q[3 * row + c] = y[c];
@@ -144,6 +192,7 @@ __global__ __launch_bounds__(256) void k_cg_ap(int64_t nv, const int32_t *rowptr
     if (!arrive_last(&st->counter)) return;
     double tot[3];
     reduce_partials<3>(partial, gridDim.x, 3, tot, lds);
+    lift_combine<VEC>(tot, 0);
     if (threadIdx.x == 0) {
         for (int c = 0; c < 3; ++c) st->alpha[c] = tot[c] > 0 ? st->rz[c] / tot[c] : 0.0;
         st->counter = 0;
@@ -151,6 +200,7 @@ __global__ __launch_bounds__(256) void k_cg_ap(int64_t nv, const int32_t *rowptr
 }
 
 // d += alpha p; r -= alpha q; z = Dinv r; beta = rz_new / rz
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_cg_update(int64_t nv, const double *dinv, const double *p,
                                                    const double *q, double *d, double *r, double *z, CgState *st,
                                                    double *partial)
@@ -159,22 +209,28 @@ __global__ __launch_bounds__(256) void k_cg_update(int64_t nv, const double *din
     __shared__ double lds[4 * 6];
     double acc[6] = {0, 0, 0, 0, 0, 0};
     const double a[3] = {st->alpha[0], st->alpha[1], st->alpha[2]};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
+        double rr[3], zz[3];
         for (int c = 0; c < 3; ++c) {
             d[3 * i + c] += a[c] * p[3 * i + c];
-            double rc = r[3 * i + c] - a[c] * q[3 * i + c];
-            double zc = dinv[i] * rc;
-            r[3 * i + c] = rc;
-            z[3 * i + c] = zc;
-            acc[c] += rc * zc;
-            acc[3 + c] += rc * rc;
+            rr[c] = r[3 * i + c] - a[c] * q[3 * i + c];
         }
+        lift_prec<VEC>(i, dinv, rr, zz);
+        for (int c = 0; c < 3; ++c) {
+            r[3 * i + c] = rr[c];
+            z[3 * i + c] = zz[c];
+            acc[c] += rr[c] * zz[c];
+            acc[3 + c] += rr[c] * rr[c];
+        }
+    }
     block_sum<6>(acc, lds);
     if (threadIdx.x == 0)
         for (int j = 0; j < 6; ++j) partial[(int64_t)blockIdx.x * 6 + j] = acc[j];
     if (!arrive_last(&st->counter)) return;
     double tot[6];
     reduce_partials<6>(partial, gridDim.x, 6, tot, lds);
+    lift_combine<VEC>(tot, 0);
+    lift_combine<VEC>(tot, 3);
     if (threadIdx.x == 0) {
         bool done = true;
         for (int c = 0; c < 3; ++c) {
@@ -195,6 +251,74 @@ __global__ void k_cg_dir(int64_t nv, const double *z, double *p, const CgState *
     const double b[3] = {st->beta[0], st->beta[1], st->beta[2]};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x)
         for (int c = 0; c < 3; ++c) p[3 * i + c] = z[3 * i + c] + b[c] * p[3 * i + c];
+}
+
+// Distance from p to triangle (a, b, c): the closest point is found from the
+// Voronoi regions of the triangle's vertices, edges and interior (the method of
+// Ericson, Real-Time Collision Detection, Sec. 5.1.5).
+__device__ inline double tri_dist(const double *p, const double *a, const double *b, const double *c)
+{
+    double ab[3], ac[3], ap[3], q[3];
+    for (int k = 0; k < 3; ++k) {
+        ab[k] = b[k] - a[k];
+        ac[k] = c[k] - a[k];
+        ap[k] = p[k] - a[k];
+    }
+    auto dot = [](const double *u, const double *v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; };
+    auto at = [&](const double *o, double s, const double *u, double t, const double *v) {
+        for (int k = 0; k < 3; ++k) q[k] = o[k] + s * u[k] + t * v[k];
+    };
+    const double d1 = dot(ab, ap), d2 = dot(ac, ap);
+    double bp[3], cp[3];
+    for (int k = 0; k < 3; ++k) {
+        bp[k] = p[k] - b[k];
+        cp[k] = p[k] - c[k];
+    }
+    const double d3 = dot(ab, bp), d4 = dot(ac, bp), d5 = dot(ab, cp), d6 = dot(ac, cp);
+    const double vc = d1 * d4 - d3 * d2, vb = d5 * d2 - d1 * d6, va = d3 * d6 - d5 * d4;
+    if (d1 <= 0.0 && d2 <= 0.0) {
+        at(a, 0.0, ab, 0.0, ac);                                  // vertex a
+    } else if (d3 >= 0.0 && d4 <= d3) {
+        at(b, 0.0, ab, 0.0, ac);                                  // vertex b
+    } else if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+        at(a, d1 / (d1 - d3), ab, 0.0, ac);                       // edge ab
+    } else if (d6 >= 0.0 && d5 <= d6) {
+        at(c, 0.0, ab, 0.0, ac);                                  // vertex c
+    } else if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+        at(a, 0.0, ab, d2 / (d2 - d6), ac);                       // edge ac
+    } else if (va <= 0.0 && d4 - d3 >= 0.0 && d5 - d6 >= 0.0) {
+        double bc[3];
+        for (int k = 0; k < 3; ++k) bc[k] = c[k] - b[k];
+        at(b, (d4 - d3) / ((d4 - d3) + (d5 - d6)), bc, 0.0, ac);  // edge bc
+    } else {
+        const double den = 1.0 / (va + vb + vc);
+        at(a, vb * den, ab, vc * den, ac);                        // interior
+    }
+    double d2s = 0.0;
+    for (int k = 0; k < 3; ++k) d2s += (p[k] - q[k]) * (p[k] - q[k]);
+    return sqrt(d2s);
+}
+
+// dist[e] = distance from centroid e to the nearest of nf faces (corner
+// coordinates fx [nf][9]); the faces pass through LDS in tiles.
+__global__ __launch_bounds__(256) void k_boundary_distance(int64_t nt, const double *__restrict__ cent, int64_t nf,
+                                                           const double *__restrict__ fx, double *__restrict__ dist)
+{
+    __shared__ double tile[256 * 9];
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double p[3] = {0, 0, 0};
+    if (e < nt)
+        for (int k = 0; k < 3; ++k) p[k] = cent[3 * e + k];
+    double best = INFINITY;
+    for (int64_t f0 = 0; f0 < nf; f0 += 256) {
+        const int n = (int)min((int64_t)256, nf - f0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < 9 * n; i += blockDim.x) tile[i] = fx[9 * f0 + i];
+        __syncthreads();
+        if (e < nt)
+            for (int f = 0; f < n; ++f) best = fmin(best, tri_dist(p, tile + 9 * f, tile + 9 * f + 3, tile + 9 * f + 6));
+    }
+    if (e < nt) dist[e] = best;
 }
 
 // Initial guess of a per-step lifting solve: d = sum_l gamma_l d^{n-l}
@@ -228,8 +352,20 @@ __global__ void k_ale_mesh(int64_t nv, const double *xh, const double *ext, doub
 
 lx_status Sim::ale_setup()
 {
-    // P1 Laplacian on the reference mesh: int grad phi_a . grad phi_b
-    std::vector<double> L(nblk, 0.0);
+    // stiffening coefficient per element (reference mesh)
+    std::vector<double> alpha(nt, 1.0);
+    if (prob.stiffening == LX_STIFF_BOUNDARY) {
+        lx_status s = ale_boundary_distance(alpha);
+        if (s != LX_OK) return s;
+        for (int64_t e = 0; e < nt; ++e) alpha[e] = std::pow(std::max(alpha[e], prob.stiff_p[0]), -prob.stiff_p[1]);
+    }
+    lift_vec = prob.lifting == LX_LIFT_ELASTIC;
+    const int np = lift_vec ? 9 : 1;
+    const double mu2 = prob.lift_E / (1.0 + prob.lift_nu);
+    const double lam = prob.lift_E * prob.lift_nu / ((1.0 + prob.lift_nu) * (1.0 - 2.0 * prob.lift_nu));
+    // P1 stiffness on the reference mesh: harmonic alpha int grad phi_a . grad phi_b, or the
+    // elastic 3x3 blocks alpha vol (mu2 (delta_cd g_a.g_b + g_a[d] g_b[c]) / 2 + lam g_a[c] g_b[d])
+    std::vector<double> L((size_t)np * nblk, 0.0);
     for (int64_t e = 0; e < nt; ++e) {
         int32_t v[4];
         for (int a = 0; a < 4; ++a) v[a] = hs.tet_soa[a * nt + e];
@@ -252,30 +388,67 @@ lx_status Sim::ale_setup()
             gr[3][j] = Ji[2][j];
             gr[0][j] = -(Ji[0][j] + Ji[1][j] + Ji[2][j]);
         }
-        double vol = std::fabs(det) / 6.0;
+        if (prob.stiffening == LX_STIFF_JACOBIAN) alpha[e] = std::pow(prob.stiff_p[0] / std::fabs(det), prob.stiff_p[1]);
+        const double w = alpha[e] * std::fabs(det) / 6.0;
         for (int a = 0; a < 4; ++a)
-            for (int b = 0; b < 4; ++b)
-                L[hs.eslot[(int64_t)(4 * a + b) * nt + e]] +=
-                    vol * (gr[a][0] * gr[b][0] + gr[a][1] * gr[b][1] + gr[a][2] * gr[b][2]);
+            for (int b = 0; b < 4; ++b) {
+                const int64_t slot = hs.eslot[(int64_t)(4 * a + b) * nt + e];
+                const double gg = gr[a][0] * gr[b][0] + gr[a][1] * gr[b][1] + gr[a][2] * gr[b][2];
+                if (!lift_vec) {
+                    L[slot] += w * gg;
+                    continue;
+                }
+                for (int c = 0; c < 3; ++c)
+                    for (int d = 0; d < 3; ++d)
+                        L[(size_t)(3 * c + d) * nblk + slot] +=
+                            w * (mu2 * 0.5 * ((c == d ? gg : 0.0) + gr[a][d] * gr[b][c]) + lam * gr[a][c] * gr[b][d]);
+            }
     }
     std::vector<int32_t> mark(nv, 0);
     for (int32_t v : h_ale_nodes) mark[v] = 1;
-    std::vector<double> Le(L), dinv(nv);
+    // rows and columns of the boundary vertices eliminated (identity diagonal block): the
+    // operator stays symmetric; the eliminated columns move to the right-hand side
+    std::vector<double> Le(L), dinv((size_t)np * nv);
     for (int64_t i = 0; i < nv; ++i)
         for (int32_t k = hs.rowptr[i]; k < hs.rowptr[i + 1]; ++k) {
             const int32_t j = hs.col[k];
-            if (mark[i]) Le[k] = (j == i) ? 1.0 : 0.0;
-            else if (mark[j]) Le[k] = 0.0;
+            for (int q = 0; q < np; ++q) {
+                const bool diag_entry = j == i && (np == 1 || q % 4 == 0);
+                if (mark[i]) Le[(size_t)q * nblk + k] = diag_entry ? 1.0 : 0.0;
+                else if (mark[j]) Le[(size_t)q * nblk + k] = 0.0;
+            }
         }
-    for (int64_t i = 0; i < nv; ++i) dinv[i] = 1.0 / Le[hs.diag[i]];
+    for (int64_t i = 0; i < nv; ++i) {
+        const int64_t k = hs.diag[i];
+        if (!lift_vec) {
+            dinv[i] = 1.0 / Le[k];
+            continue;
+        }
+        double A[3][3], det3;
+        for (int c = 0; c < 3; ++c)
+            for (int d = 0; d < 3; ++d) A[c][d] = Le[(size_t)(3 * c + d) * nblk + k];
+        det3 = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+               A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+        if (!(std::fabs(det3) > 0)) return fail(LX_EMESH, "singular lifting block at vertex %lld", (long long)i);
+        double *D = &dinv[9 * i];
+        D[0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) / det3;
+        D[1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det3;
+        D[2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det3;
+        D[3] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) / det3;
+        D[4] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det3;
+        D[5] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det3;
+        D[6] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) / det3;
+        D[7] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det3;
+        D[8] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det3;
+    }
 #define ALLOC(ptr, bytes)                                \
     do {                                                 \
         lx_status _s = dalloc((void **)&(ptr), (bytes)); \
         if (_s != LX_OK) return _s;                      \
     } while (0)
-    ALLOC(d_lap, sizeof(double) * nblk);
-    ALLOC(d_lapfull, sizeof(double) * nblk);
-    ALLOC(d_lapdinv, sizeof(double) * nv);
+    ALLOC(d_lap, sizeof(double) * np * nblk);
+    ALLOC(d_lapfull, sizeof(double) * np * nblk);
+    ALLOC(d_lapdinv, sizeof(double) * np * nv);
     ALLOC(d_ale_mark, sizeof(int32_t) * nv);
     ALLOC(d_cg, sizeof(double) * 3 * nv * 6 + sizeof(CgState));
     ALLOC(d_dnew, sizeof(double) * 3 * nv);
@@ -283,9 +456,9 @@ lx_status Sim::ale_setup()
     // reduction partials of the lifting CG (one row of 9 per workgroup of the row kernels)
     ALLOC(d_cg_partial, sizeof(double) * 9 * ((nv * kAleLPR + 255) / 256));
 #undef ALLOC
-    LX_HIP(hipMemcpyAsync(d_lap, Le.data(), sizeof(double) * nblk, hipMemcpyHostToDevice, stream));
-    LX_HIP(hipMemcpyAsync(d_lapfull, L.data(), sizeof(double) * nblk, hipMemcpyHostToDevice, stream));
-    LX_HIP(hipMemcpyAsync(d_lapdinv, dinv.data(), sizeof(double) * nv, hipMemcpyHostToDevice, stream));
+    LX_HIP(hipMemcpyAsync(d_lap, Le.data(), sizeof(double) * Le.size(), hipMemcpyHostToDevice, stream));
+    LX_HIP(hipMemcpyAsync(d_lapfull, L.data(), sizeof(double) * L.size(), hipMemcpyHostToDevice, stream));
+    LX_HIP(hipMemcpyAsync(d_lapdinv, dinv.data(), sizeof(double) * dinv.size(), hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_ale_mark, mark.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemsetAsync(d_cg, 0, sizeof(double) * 3 * nv * 6 + sizeof(CgState), stream));
     LX_HIP(hipStreamSynchronize(stream));
@@ -293,8 +466,61 @@ lx_status Sim::ale_setup()
     return LX_OK;
 }
 
-// Harmonic extension into d_cg[ext] (CG to rtol 1e-13): of the shape D^ (data =
-// nullptr), or of nodal boundary data starting from the guess already in ext.
+// Distance from every element's centroid (reference mesh) to the nearest face of
+// the moving boundary, into dist[nt]; device temporaries come from the caller's
+// allocator (or hipMalloc) and are released before returning.
+lx_status Sim::ale_boundary_distance(std::vector<double> &dist)
+{
+    const int64_t nf = (int64_t)h_ale_faces.size() / 3;
+    if (nf == 0) return fail(LX_EINVAL, "boundary-based stiffening needs faces with the ALE tags");
+    std::vector<double> cent(3 * nt), fx(9 * nf);
+    for (int64_t e = 0; e < nt; ++e)
+        for (int k = 0; k < 3; ++k) {
+            double c = 0;
+            for (int a = 0; a < 4; ++a) c += 0.25 * hs.xh[3 * hs.tet_soa[a * nt + e] + k];
+            cent[3 * e + k] = c;
+        }
+    for (int64_t f = 0; f < nf; ++f)
+        for (int l = 0; l < 3; ++l)
+            for (int k = 0; k < 3; ++k) fx[9 * f + 3 * l + k] = hs.xh[3 * h_ale_faces[3 * f + l] + k];
+    auto talloc = [&](size_t bytes) -> void * {
+        void *p = nullptr;
+        if (alloc_fn) p = alloc_fn(bytes, alloc_ctx);
+        else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+        return p;
+    };
+    auto tfree = [&](void *p) {
+        if (!p) return;
+        if (free_fn) free_fn(p, alloc_ctx);
+        else (void)hipFree(p);
+    };
+    double *dc = (double *)talloc(sizeof(double) * cent.size()), *df = (double *)talloc(sizeof(double) * fx.size()),
+           *dd = (double *)talloc(sizeof(double) * nt);
+    lx_status st = LX_OK;
+    if (!dc || !df || !dd) {
+        st = fail(LX_ENOMEM, "device memory for the boundary distances");
+    } else if (hipMemcpyAsync(dc, cent.data(), sizeof(double) * cent.size(), hipMemcpyHostToDevice, stream) !=
+                   hipSuccess ||
+               hipMemcpyAsync(df, fx.data(), sizeof(double) * fx.size(), hipMemcpyHostToDevice, stream) != hipSuccess) {
+        st = fail(LX_EDEVICE, "upload of the boundary-distance inputs failed");
+    } else {
+        hipLaunchKernelGGL(k_boundary_distance, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, stream, nt, dc, nf,
+                           df, dd);
+        dist.assign(nt, 0.0);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(dist.data(), dd, sizeof(double) * nt, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            st = fail(LX_EDEVICE, "boundary-distance kernel failed");
+    }
+    (void)hipStreamSynchronize(stream);
+    tfree(dc);
+    tfree(df);
+    tfree(dd);
+    return st;
+}
+
+// Lifting into d_cg[ext] (CG to rtol 1e-13): of the shape D^ (data = nullptr),
+// or of nodal boundary data starting from the guess already in ext.
 lx_status Sim::ale_extend(const double *data)
 {
     double *ext = d_cg, *rhs = d_cg + 3 * nv, *r = d_cg + 6 * nv, *z = d_cg + 9 * nv, *p = d_cg + 12 * nv,
@@ -302,19 +528,33 @@ lx_status Sim::ale_extend(const double *data)
     CgState *cst = (CgState *)(d_cg + 18 * nv);
     const unsigned grow = (unsigned)((nv * kAleLPR + 255) / 256);
     const unsigned gvec = (unsigned)std::min<int64_t>((nv + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_ale_rhs, dim3(grow), dim3(256), 0, stream, nv, d_rowptr, d_col, d_lapfull, d_ale_mark,
-                       data ? data : d_ale_shape, 1.0, rhs, ext);
+    const LiftOp Afull{d_rowptr, d_col, d_lapfull, nblk}, A{d_rowptr, d_col, d_lap, nblk};
     double *part = d_cg_partial;   // grow blocks * 9 doubles
-    hipLaunchKernelGGL(k_cg_init, dim3(grow), dim3(256), 0, stream, nv, d_rowptr, d_col, d_lap, d_lapdinv, rhs, ext,
-                       r, z, p, cst, part, 1e-13);
+    if (lift_vec) {
+        hipLaunchKernelGGL(k_ale_rhs<true>, dim3(grow), dim3(256), 0, stream, nv, Afull, d_ale_mark,
+                           data ? data : d_ale_shape, 1.0, rhs, ext);
+        hipLaunchKernelGGL(k_cg_init<true>, dim3(grow), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z, p, cst,
+                           part, 1e-13);
+    } else {
+        hipLaunchKernelGGL(k_ale_rhs<false>, dim3(grow), dim3(256), 0, stream, nv, Afull, d_ale_mark,
+                           data ? data : d_ale_shape, 1.0, rhs, ext);
+        hipLaunchKernelGGL(k_cg_init<false>, dim3(grow), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z, p,
+                           cst, part, 1e-13);
+    }
     CgState h;
     const int max_it = 50000;
     int it = 0;
     for (;;) {
         for (int k = 0; k < 25; ++k) {
-            hipLaunchKernelGGL(k_cg_ap, dim3(grow), dim3(256), 0, stream, nv, d_rowptr, d_col, d_lap, p, q, cst, part);
-            hipLaunchKernelGGL(k_cg_update, dim3(gvec), dim3(256), 0, stream, nv, d_lapdinv, p, q, ext, r, z, cst,
-                               part);
+            if (lift_vec) {
+                hipLaunchKernelGGL(k_cg_ap<true>, dim3(grow), dim3(256), 0, stream, nv, A, p, q, cst, part);
+                hipLaunchKernelGGL(k_cg_update<true>, dim3(gvec), dim3(256), 0, stream, nv, d_lapdinv, p, q, ext, r, z,
+                                   cst, part);
+            } else {
+                hipLaunchKernelGGL(k_cg_ap<false>, dim3(grow), dim3(256), 0, stream, nv, A, p, q, cst, part);
+                hipLaunchKernelGGL(k_cg_update<false>, dim3(gvec), dim3(256), 0, stream, nv, d_lapdinv, p, q, ext, r,
+                                   z, cst, part);
+            }
             hipLaunchKernelGGL(k_cg_dir, dim3(gvec), dim3(256), 0, stream, nv, z, p, cst);
         }
         it += 25;

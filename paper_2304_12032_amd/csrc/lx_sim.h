@@ -84,9 +84,14 @@ struct Sim {
     double *d_dhist[4] = {nullptr, nullptr, nullptr, nullptr};  // [nv][3] displacement history
     double *d_dnew = nullptr;                                    // displacement at t^{n+1}
     double *d_ale_shape = nullptr;                               // [nv][3] D^
-    double *d_lap = nullptr;                                     // [nblk] P1 Laplacian on x^ (eliminated)
-    double *d_lapfull = nullptr;                                 // [nblk] P1 Laplacian on x^
-    double *d_lapdinv = nullptr;                                 // [nv]
+    // lifting stiffness on x^: [nblk] scalars (harmonic) or [9][nblk] 3x3 blocks (elasticity),
+    // as assembled (full) and with the boundary rows and columns eliminated; its (block) Jacobi
+    // inverse [nv] or [nv][9]
+    bool lift_vec = false;
+    double *d_lap = nullptr;
+    double *d_lapfull = nullptr;
+    double *d_lapdinv = nullptr;
+    std::vector<int32_t> h_ale_faces;                            // [n][3] faces with the ALE tags
     int32_t *d_ale_nodes = nullptr;
     int32_t *d_ale_mark = nullptr;                               // [nv] 1 on ALE boundary
     double *d_cg = nullptr;                                      // CG work: 6 vectors [nv][3] + state
@@ -197,6 +202,7 @@ struct Sim {
     lx_status load_state(const void *blob, int64_t bytes);
 
     lx_status ale_setup();
+    lx_status ale_boundary_distance(std::vector<double> &dist);
     lx_status ale_extend(const double *data);
     lx_status ale_update(double t1, const StepCoef &C);
     void ale_commit();

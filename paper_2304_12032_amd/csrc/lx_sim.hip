@@ -157,6 +157,14 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     prob.riis = nullptr;
     if (pr->ale) {
         ale_tags.assign(pr->ale_tags, pr->ale_tags + pr->n_ale_tags);
+        if (pr->lifting != LX_LIFT_HARMONIC && pr->lifting != LX_LIFT_ELASTIC)
+            return fail(LX_EINVAL, "lifting must be LX_LIFT_HARMONIC or LX_LIFT_ELASTIC");
+        if (pr->lifting == LX_LIFT_ELASTIC && !(pr->lift_E > 0 && pr->lift_nu >= 0 && pr->lift_nu < 0.5))
+            return fail(LX_EINVAL, "elastic lifting needs lift_E > 0 and 0 <= lift_nu < 1/2");
+        if (pr->stiffening < LX_STIFF_NONE || pr->stiffening > LX_STIFF_BOUNDARY)
+            return fail(LX_EINVAL, "stiffening must be LX_STIFF_NONE, _JACOBIAN or _BOUNDARY");
+        if (pr->stiffening != LX_STIFF_NONE && !(pr->stiff_p[0] > 0 && pr->stiff_p[1] > 0))
+            return fail(LX_EINVAL, "stiffening parameters must be positive");
     }
     prob.ale_tags = nullptr;
     if (prob.C_r <= 0) prob.C_r = (prob.fe == LX_P2P1) ? 60.0 : 30.0;
@@ -229,6 +237,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     if (edge_missing) return fail(LX_EMESH, "a boundary face is not a face of any tetrahedron");
     if (prob.ale) {
         if (!face_vertices(ale_tags, fv)) return fail(LX_EMESH, "boundary face vertex out of range");
+        h_ale_faces = fv;
         std::vector<char> mark(nv, 0);
         for (int32_t v : fv) mark[v] = 1;
         for (int64_t v = 0; v < nv; ++v)

@@ -24,6 +24,8 @@ STATUS_NAMES = {0: "LX_OK", -1: "LX_EINVAL", -2: "LX_ENOMEM", -3: "LX_EDEVICE", 
 LAW = {"constant": 0, "pulsatile": 1, "ramp": 2, "ramp2": 3, "linear": 4, "sine": 5}
 PROFILE = {"uniform": 0, "parabolic": 1, "nodal": 2}
 BC = {"noslip": 0, "dirichlet": 1, "neumann": 2, "resistance": 3}
+LIFT = {"harmonic": 0, "elastic": 1}
+STIFF = {"none": 0, "jacobian": 1, "boundary": 2}
 FE = {"p1p1": 1, "p2p1": 2}
 DIFF = {"gradgrad": 0, "symgrad": 1}
 STAB = {"none": 0, "supg_pspg": 1, "vms_les": 2}
@@ -91,7 +93,9 @@ class lx_problem(ctypes.Structure):
     _fields_ = [("fe", c_i32), ("bdf_order", c_i32), ("dt", c_dbl), ("t0", c_dbl), ("rho", c_dbl), ("mu", c_dbl),
                 ("diffusion", c_i32), ("stab", c_i32), ("C_r", c_dbl), ("semi_implicit", c_i32), ("ale", c_i32),
                 ("forcing", c_i32), ("n_bc", c_i32), ("bc", P(lx_boundary)), ("n_riis", c_i32),
-                ("n_ale_tags", c_i32), ("riis", P(lx_riis)), ("ale_tags", P(c_i32)), ("ale_law", lx_time_law)]
+                ("n_ale_tags", c_i32), ("riis", P(lx_riis)), ("ale_tags", P(c_i32)), ("ale_law", lx_time_law),
+                ("lifting", c_i32), ("stiffening", c_i32), ("lift_E", c_dbl), ("lift_nu", c_dbl),
+                ("stiff_p", c_dbl * 2)]
 
 
 class lx_solver(ctypes.Structure):
@@ -265,6 +269,11 @@ class _Marshal:
         p.n_ale_tags = len(prob.ale_tags) if prob.ale else 0
         p.ale_tags = _ip(at)
         p.ale_law = _law(prob.ale_law)
+        p.lifting = LIFT[getattr(prob, "lifting", "harmonic")]
+        p.stiffening = STIFF[getattr(prob, "stiffening", "none")]
+        p.lift_E = float(getattr(prob, "lift_E", 1.0))
+        p.lift_nu = float(getattr(prob, "lift_nu", 0.3))
+        p.stiff_p[:] = [float(v) for v in getattr(prob, "stiff_p", (1.0, 1.0))]
         self.problem = p
         s = lx_solver()
         s.precision = PREC[solver.precision]

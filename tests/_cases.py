@@ -208,3 +208,30 @@ def tube_outflow(nxy=4, nz=8, length=2.0, kind="resistance", cr=40.0, beta=1.0, 
         pass
 
     return Case(mesh, prob, init, drive, "tube_%s%s" % (kind, "_ale" if ale else ""))
+
+
+def tube_lifting(lifting="elastic", stiffening="none", stiff_p=(1.0, 1.0), nxy=4, nz=6, length=1.5, seed=6):
+    """ALE tube whose wall bulges non-linearly (d^ = law(t) 0.05 sin(pi z/L) (x, y, 0), plus an
+    axial shift of the outlet) lifted by the chosen operator and stiffening; every boundary
+    face carries the displacement."""
+    mesh = tube(nxy=nxy, nz=nz, radius=1.0, length=length, seed=seed)
+    prob = tube_problem(mesh, dt=2e-3, bdf_order=2, peak=20.0, valve=False)
+    prob.ale = True
+    prob.ale_tags = (TUBE_TAGS["wall"], TUBE_TAGS["inlet"], TUBE_TAGS["outlet"])
+    prob.ale_law = TimeLaw("ramp", (0.0, 1.0, 0.0, 0.01))
+    prob.lifting, prob.lift_E, prob.lift_nu = lifting, 2.0, 0.3
+    prob.stiffening, prob.stiff_p = stiffening, stiff_p
+    X = mesh.coords
+    shape = np.zeros_like(X)
+    bump = 0.05 * np.sin(np.pi * X[:, 2] / length)
+    shape[:, 0] = bump * X[:, 0]
+    shape[:, 1] = bump * X[:, 1]
+    shape[:, 2] = 0.03 * X[:, 2] * X[:, 2] / length
+
+    def init(s):
+        s.set_ale_displacement(shape)
+
+    def drive(s, t1):
+        pass
+
+    return Case(mesh, prob, init, drive, "tube_lift_%s_%s" % (lifting, stiffening))

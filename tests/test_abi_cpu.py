@@ -159,3 +159,24 @@ def test_bad_outflow_conditions_rejected(what):
     with pytest.raises(LxError) as ei:
         _create(m, prob, SolverCfg())
     assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("what", ["nu_half", "E_zero", "stiff_negative"])
+def test_bad_lifting_parameters_rejected(what):
+    """The lifting moduli and stiffening parameters are checked before any device call."""
+    from paper_2304_12032_amd import LxError
+    from inputs.meshes import TUBE_TAGS
+    m = tube(nxy=3, nz=4, length=1.0)
+    prob = tube_problem(m, valve=False)
+    prob.ale = True
+    prob.ale_tags = (TUBE_TAGS["wall"],)
+    prob.lifting = "elastic"
+    if what == "nu_half":
+        prob.lift_nu = 0.5
+    elif what == "E_zero":
+        prob.lift_E = 0.0
+    else:
+        prob.stiffening, prob.stiff_p = "boundary", (0.1, -1.0)
+    with pytest.raises(LxError) as ei:
+        _create(m, prob, SolverCfg())
+    assert ei.value.status == -1
