@@ -69,6 +69,8 @@ class Problem:
     diffusion: str = "gradgrad"      # gradgrad | symgrad
     stab: str = "vms_les"            # none | supg_pspg | vms_les
     C_r: Optional[float] = None      # None -> 30 (P1) / 60 (P2)
+    implicit: bool = False           # fully implicit formulation (u* = u^{n+1} - u_ALE, implicit
+                                     # LES term) solved by Newton's method; else semi-implicit
     ale: bool = False
     ale_tags: Tuple[int, ...] = ()
     ale_law: TimeLaw = field(default_factory=lambda: TimeLaw("constant", (1.0,)))

@@ -12,7 +12,9 @@
  *   - fully discrete weak form: Sec. 2.3, eq. (fullydiscrete_ns_ale_riis...)
  *   - diffusion forms: Sec. 2.3, eq. (diffusion-term)
  *   - SUPG-PSPG and VMS terms: Sec. 2.3, eqs. (stabilization_form_SUPG/VMS)
- *   - semi-implicit LES term: Sec. 2.3, eq. (stabilization_form_LES), 2nd case
+ *   - semi-implicit LES term: Sec. 2.3, eq. (stabilization_form_LES), 2nd case;
+ *     the implicit formulation (its 1st case, u* = u^{n+1} - u_ALE) with
+ *     Newton's method (Sec. 2.4), its Jacobian by the complex step
  *   - strong residuals r_M, r_C and tau_M, tau_C, G, g: Sec. 2.3
  *   - RIIS term and smoothed delta: Sec. 2.1.2, eq. (riis)
  *   - Neumann data: Sec. 2.2.3, eq. (bcs-neumann)
@@ -40,6 +42,7 @@
  * of 4096 entries in parallel and then the block sums in order.  Every result
  * is therefore bitwise the same for any number of threads.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #ifdef _OPENMP
@@ -283,6 +286,148 @@ double orc_element_p1(const double X[4][3], const double Xh[4][3], const double 
     return det;
 }
 
+/* ----------------------------------------- fully implicit formulation */
+
+/*
+ * Element residual R(u, p) (16 entries, local index 3a+c, then 12+a) of the
+ * fully implicit formulation (Sec. 2.3, eq. (fullydiscrete_ns_ale_riis...) with
+ * u* = u^{n+1} - u_ALE and the implicit case of eq. (stabilization_form_LES)):
+ * the same weak form as orc_element_p1 with every occurrence of u_EXT, p_EXT
+ * replaced by the unknowns, so that the residual of the semi-implicit system
+ * is Ke x - Fe.  Written in complex arithmetic and analytic in (u, p) (the
+ * geometry, the valve distances and the data are real), so that the
+ * complex-step derivative Im R(x + i h e_j) / h gives the Jacobian column j
+ * to rounding (Squire and Trapp, SIAM Review 1998).
+ */
+typedef double complex orc_cplx;
+
+static void residual_implicit(const double X[4][3], const double Xh[4][3], const orc_cplx u[4][3],
+                              const orc_cplx p[4], const double uB[4][3], const double uA[4][3],
+                              const double f[4][3], const orc_params *P, orc_cplx R[16])
+{
+    double Jinv[3][3];
+    double det = jacobian(X, Jinv);
+    double vol = fabs(det) / 6.0;
+    double dphi[4][3];
+    for (int j = 0; j < 3; ++j) {
+        dphi[1][j] = Jinv[0][j];
+        dphi[2][j] = Jinv[1][j];
+        dphi[3][j] = Jinv[2][j];
+        dphi[0][j] = -(Jinv[0][j] + Jinv[1][j] + Jinv[2][j]);
+    }
+    double G[3][3], g[3], GG = 0.0, gg = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        g[i] = Jinv[0][i] + Jinv[1][i] + Jinv[2][i];
+        gg += g[i] * g[i];
+        for (int j = 0; j < 3; ++j) {
+            G[i][j] = Jinv[0][i] * Jinv[0][j] + Jinv[1][i] * Jinv[1][j] + Jinv[2][i] * Jinv[2][j];
+        }
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) GG += G[i][j] * G[i][j];
+    for (int i = 0; i < 16; ++i) R[i] = 0.0;
+    double lam[4][4], wq[4];
+    orc_quad_p1(lam, wq);
+    const double rho = P->rho, mu = P->mu, dt = P->dt, alpha = P->alpha;
+    for (int q = 0; q < 4; ++q) {
+        const double *phi = lam[q];
+        double w = wq[q] * vol;
+        orc_cplx uq[3] = {0, 0, 0}, gradU[3][3] = {{0}}, pq = 0.0, gradP[3] = {0, 0, 0};
+        double uBq[3] = {0}, uAq[3] = {0}, fq[3] = {0}, xh[3] = {0};
+        for (int a = 0; a < 4; ++a) {
+            pq += phi[a] * p[a];
+            for (int c = 0; c < 3; ++c) {
+                uq[c] += phi[a] * u[a][c];
+                uBq[c] += phi[a] * uB[a][c];
+                uAq[c] += phi[a] * uA[a][c];
+                fq[c] += phi[a] * f[a][c];
+                xh[c] += phi[a] * Xh[a][c];
+                gradP[c] += p[a] * dphi[a][c];
+                for (int j = 0; j < 3; ++j) gradU[c][j] += u[a][c] * dphi[a][j];
+            }
+        }
+        double sigR = 0.0, riis2 = 0.0;
+        for (int k = 0; k < P->n_riis; ++k) {
+            const double *v = P->riis + 10 * k;
+            double Rk = v[8], eps = v[9];
+            double dl = orc_delta(orc_valve_distance(xh, v), eps);
+            sigR += Rk / eps * dl;
+            riis2 += (Rk * Rk) / (eps * eps) * dl * dl;
+        }
+        orc_cplx us[3];
+        for (int c = 0; c < 3; ++c) us[c] = uq[c] - uAq[c];
+        orc_cplx tauM = 0.0, tauC = 0.0;
+        if (P->stab != ORC_STAB_NONE) {
+            orc_cplx uGu = 0.0;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) uGu += us[i] * G[i][j] * us[j];
+            orc_cplx sM = P->sigma * P->sigma * rho * rho / (dt * dt) + rho * rho * uGu + P->C_r * mu * mu * GG + riis2;
+            tauM = 1.0 / csqrt(sM);
+            tauC = 1.0 / (tauM * gg);
+        }
+        double Kv[3];
+        for (int c = 0; c < 3; ++c) Kv[c] = fq[c] + rho * uBq[c] / dt + sigR * uAq[c];
+        /* strong momentum residual r_M(u, p) (mu Lap u = 0 for P1) and div u */
+        orc_cplx r[3], adv[3], divu = gradU[0][0] + gradU[1][1] + gradU[2][2];
+        for (int c = 0; c < 3; ++c) {
+            adv[c] = us[0] * gradU[c][0] + us[1] * gradU[c][1] + us[2] * gradU[c][2];
+            r[c] = rho * (alpha * uq[c] / dt + adv[c]) + gradP[c] + sigR * uq[c] - Kv[c];
+        }
+        for (int a = 0; a < 4; ++a) {
+            orc_cplx adv_phi = us[0] * dphi[a][0] + us[1] * dphi[a][1] + us[2] * dphi[a][2];
+            for (int c = 0; c < 3; ++c) {
+                orc_cplx v = (rho * alpha / dt + sigR) * uq[c] * phi[a] + rho * adv[c] * phi[a];
+                for (int j = 0; j < 3; ++j) v += mu * gradU[c][j] * dphi[a][j];
+                if (P->symgrad)
+                    for (int d = 0; d < 3; ++d) v += mu * gradU[d][c] * dphi[a][d];
+                v += -pq * dphi[a][c] - Kv[c] * phi[a];
+                /* SUPG (tau_M r_M, rho u* . grad v), VMS (tau_M r_M, rho u* . (grad v)^T) and
+                 * implicit LES -(tau_M r_M (x) tau_M r_M, rho grad v), v = phi_a e_c */
+                for (int j = 0; j < 3; ++j) {
+                    orc_cplx t = (c == j) ? adv_phi : 0.0;
+                    if (P->stab == ORC_STAB_VMS_LES) t += us[c] * dphi[a][j] - tauM * r[c] * dphi[a][j];
+                    v += tauM * r[j] * rho * t;
+                }
+                v += tauC * divu * dphi[a][c];
+                R[3 * a + c] += w * v;
+            }
+            orc_cplx vq = divu * phi[a];
+            for (int j = 0; j < 3; ++j) vq += tauM * r[j] * dphi[a][j];
+            R[12 + a] += w * vq;
+        }
+    }
+}
+
+/*
+ * Newton element system of the implicit formulation at the state (u, p):
+ * Re = R(u, p) and Ke = dR/d(u, p), column j by the complex step of size h
+ * (1e-30 by default).  Returns det J.
+ */
+double orc_newton_element_p1(const double X[4][3], const double Xh[4][3], const double u[4][3], const double p[4],
+                             const double uB[4][3], const double uA[4][3], const double f[4][3], const orc_params *P,
+                             double h, double Ke[16][16], double Re[16])
+{
+    double Jinv[3][3];
+    double det = jacobian(X, Jinv);
+    if (!(h > 0.0)) h = 1e-30;
+    orc_cplx uc[4][3], pc[4], R[16];
+    for (int a = 0; a < 4; ++a) {
+        pc[a] = p[a];
+        for (int c = 0; c < 3; ++c) uc[a][c] = u[a][c];
+    }
+    residual_implicit(X, Xh, uc, pc, uB, uA, f, P, R);
+    for (int i = 0; i < 16; ++i) Re[i] = creal(R[i]);
+    for (int j = 0; j < 16; ++j) {
+        if (j < 12) uc[j / 3][j % 3] += I * h;
+        else pc[j - 12] += I * h;
+        residual_implicit(X, Xh, uc, pc, uB, uA, f, P, R);
+        for (int i = 0; i < 16; ++i) Ke[i][j] = cimag(R[i]) / h;
+        if (j < 12) uc[j / 3][j % 3] = u[j / 3][j % 3];
+        else pc[j - 12] = p[j - 12];
+    }
+    return det;
+}
+
 /* ------------------------------------------------------- global assembly */
 
 static int cmp_i32(const void *a, const void *b)
@@ -412,6 +557,66 @@ int64_t orc_assemble_p1(int64_t nv, int64_t nt, const double *x, const double *x
             }
             for (int r = 0; r < 16 && rc == 0; ++r) {
                 rhs[gdof[r]] += Fc[i][r];
+                for (int j = 0; j < 16; ++j) {
+                    int64_t k = find_col(rowptr, col, gdof[r], (int32_t)gdof[j]);
+                    if (k < 0) { rc = -(e + 1); break; }
+                    val[k] += Kc[i][r][j];
+                }
+            }
+        }
+    }
+    free(Kc); free(Fc); free(detc);
+    return rc;
+}
+
+/*
+ * Global Newton system of the implicit formulation at the state (u [nv][3],
+ * p [nv]): val += dR/dx, rhs -= R (so that J dx = rhs is the Newton update),
+ * element systems computed in parallel chunks and added in element order.
+ * Returns 0, or -(e+1) for a degenerate element or a missing pattern entry.
+ */
+int64_t orc_assemble_p1_newton(int64_t nv, int64_t nt, const double *x, const double *xh, const int32_t *tets,
+                               const double *u, const double *p, const double *uB, const double *uA, const double *f,
+                               const orc_params *P, const int64_t *rowptr, const int32_t *col, double *val,
+                               double *rhs)
+{
+    enum { CHUNK = 4096 };
+    double (*Kc)[16][16] = malloc(sizeof(double) * 256 * CHUNK);
+    double (*Fc)[16] = malloc(sizeof(double) * 16 * CHUNK);
+    double *detc = malloc(sizeof(double) * CHUNK);
+    if (!Kc || !Fc || !detc) { free(Kc); free(Fc); free(detc); return -(nt + 1); }
+    int64_t rc = 0;
+    for (int64_t e0 = 0; e0 < nt && rc == 0; e0 += CHUNK) {
+        const int64_t ne = (nt - e0 < CHUNK) ? nt - e0 : CHUNK;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < ne; ++i) {
+            const int64_t e = e0 + i;
+            double X[4][3], Xh[4][3], ue[4][3], ub[4][3], ua[4][3], pe[4], fe[4][3];
+            for (int a = 0; a < 4; ++a) {
+                const int32_t va = tets[4 * e + a];
+                for (int c = 0; c < 3; ++c) {
+                    X[a][c] = x[3 * va + c];
+                    Xh[a][c] = xh[3 * va + c];
+                    ue[a][c] = u[3 * va + c];
+                    ub[a][c] = uB[3 * va + c];
+                    ua[a][c] = uA ? uA[3 * va + c] : 0.0;
+                    fe[a][c] = f ? f[3 * va + c] : 0.0;
+                }
+                pe[a] = p[va];
+            }
+            detc[i] = orc_newton_element_p1(X, Xh, ue, pe, ub, ua, fe, P, 0.0, Kc[i], Fc[i]);
+        }
+        for (int64_t i = 0; i < ne && rc == 0; ++i) {
+            const int64_t e = e0 + i;
+            if (!(fabs(detc[i]) > 0.0)) { rc = -(e + 1); break; }
+            int64_t gdof[16];
+            for (int a = 0; a < 4; ++a) {
+                const int32_t va = tets[4 * e + a];
+                for (int c = 0; c < 3; ++c) gdof[3 * a + c] = 3 * (int64_t)va + c;
+                gdof[12 + a] = 3 * nv + va;
+            }
+            for (int r = 0; r < 16 && rc == 0; ++r) {
+                rhs[gdof[r]] -= Fc[i][r];
                 for (int j = 0; j < 16; ++j) {
                     int64_t k = find_col(rowptr, col, gdof[r], (int32_t)gdof[j]);
                     if (k < 0) { rc = -(e + 1); break; }

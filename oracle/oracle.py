@@ -14,6 +14,10 @@ What it computes per step (paper Sec. 2.3 and 2.4; readings listed in lxo.c):
      C_R w w^T kept beside the sparse matrix), Dirichlet rows.
   4. Solve A x = b exactly (dense LU, or sparse LU), or by the oracle's own
      GMRES + SIMPLE for large systems; rotate the history.
+  Fully implicit formulation (Sec. 2.3, u* = u^{n+1} - u_ALE, implicit LES term):
+  steps 3-4 become Newton's method (Sec. 2.4) on the nonlinear residual, its
+  Jacobian by the complex step, each update solved exactly, from the step's
+  starting state until ||R|| <= newton_rtol ||R_0||.
 """
 import ctypes
 import os
@@ -76,6 +80,10 @@ def lib():
         L.orc_backflow_p1.argtypes = [I64, vp, vp, vp, vp, D, vp, vp, vp, vp]
         L.orc_boundary_integrals.restype = None
         L.orc_boundary_integrals.argtypes = [I64, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_newton_element_p1.restype = D
+        L.orc_newton_element_p1.argtypes = [vp] * 7 + [P(OrcParams), D, vp, vp]
+        L.orc_assemble_p1_newton.restype = I64
+        L.orc_assemble_p1_newton.argtypes = [I64, I64] + [vp] * 8 + [P(OrcParams)] + [vp] * 4
         L.orc_dirichlet_rows.restype = None
         L.orc_dirichlet_rows.argtypes = [I64, vp, vp, vp, vp, vp, vp]
         L.orc_gmres_simple.restype = I64
@@ -510,12 +518,87 @@ class OracleSim:
             self.last_iters, self.last_res = int(it), res.value
         return sol
 
-    def step(self):
-        t1 = self.assemble()
-        x0 = np.concatenate([self.u_hist[0].reshape(-1), self.p_hist[0]])
-        sol = self.solve(x0)
-        u = sol[:3 * self.nv].reshape(self.nv, 3).copy()
-        p = sol[3 * self.nv:].copy()
+    def newton_system(self, u, p):
+        """Newton system at the state (u, p) of the coming step (implicit formulation): the
+        Jacobian in self.val and -R in self.rhs, Neumann data included, Dirichlet rows as
+        a_ii dx_i = a_ii (g_i - u_i).  Returns t^{n+1}."""
+        L = lib()
+        prob = self.prob
+        t1 = self.t + prob.dt
+        order, alpha, beta, gamma = self._coeffs()
+        uB = self._combo(self.u_hist, beta)
+        if getattr(self, "_newton_t1", None) != t1:
+            if prob.ale:
+                d1, uA = self._ale_update(t1, alpha, beta)
+                x = self.xhat + d1
+            else:
+                d1, uA = None, np.zeros((self.nv, 3))
+                x = self.xhat
+            self._pending_d, self.x_next, self.uA, self._newton_t1 = d1, x, uA, t1
+        x, uA = self.x_next, self.uA
+        P = self.params(order, alpha, t1)
+        self.val[:] = 0.0
+        self.rhs[:] = 0.0
+        f = self.forcing if prob.forcing else None
+        rc = L.orc_assemble_p1_newton(self.nv, self.mesh.nt, _p(np.ascontiguousarray(x)), _p(self.xhat),
+                                      _p(self.tets), _p(np.ascontiguousarray(u)), _p(np.ascontiguousarray(p)),
+                                      _p(np.ascontiguousarray(uB)), _p(np.ascontiguousarray(uA)),
+                                      _p(None if f is None else np.ascontiguousarray(f)), ctypes.byref(P),
+                                      _p(self.rowptr), _p(self.col), _p(self.val), _p(self.rhs))
+        if rc != 0:
+            raise RuntimeError("oracle Newton assembly failed at element %d" % (-rc - 1))
+        for i, b in enumerate(prob.bcs):
+            if b.type != "neumann":
+                continue
+            faces = self.bc_faces(i)
+            if b.profile.kind == "nodal":
+                h = self.neu_nodal.get(i)
+                if h is None:
+                    continue
+            else:
+                hv = b.theta * time_law(b.law, t1)
+                if hv == 0.0:
+                    continue
+                h = np.broadcast_to(-hv * np.asarray(b.profile.normal, float), (self.nv, 3))
+            L.orc_neumann_p1(self.nv, len(faces), _p(np.ascontiguousarray(x)), _p(faces),
+                             _p(np.ascontiguousarray(h, dtype=np.float64)), _p(self.rhs))
+        rows, gvals = self.dirichlet_rows(t1, x, uA)
+        cur = np.concatenate([u.reshape(-1), p])[rows]
+        L.orc_dirichlet_rows(len(rows), _p(rows), _p(np.ascontiguousarray(gvals - cur)), _p(self.rowptr),
+                             _p(self.col), _p(self.val), _p(self.rhs))
+        self.rank1 = []
+        return t1
+
+    def step_implicit(self, newton_rtol=1e-12, max_newton=30, x0=None):
+        """One step of the fully implicit formulation by Newton's method from x0 (default:
+        the previous solution); the updates are solved directly.  Stops when ||R|| <=
+        newton_rtol ||R_0|| or the last update is below newton_rtol ||x||.  Records the
+        nonlinear residual norms in self.newton_norms."""
+        if any(b.type == "resistance" or b.backflow > 0 for b in self.prob.bcs):
+            raise ValueError("the implicit formulation is built without outflow terms")
+        nv = self.nv
+        x = np.concatenate([self.u_hist[0].reshape(-1), self.p_hist[0]]) if x0 is None else np.array(x0, float)
+        self._newton_t1 = None
+        norms, dx = [], None
+        for it in range(max_newton + 1):
+            t1 = self.newton_system(x[:3 * nv].reshape(nv, 3), x[3 * nv:])
+            norms.append(float(np.linalg.norm(self.rhs)))
+            # converged: the residual fell by newton_rtol, or the last update was that small
+            # against the state (a start already at the solution leaves only rounding)
+            if norms[-1] <= newton_rtol * norms[0] or norms[-1] == 0.0 or \
+                    (dx is not None and np.linalg.norm(dx) <= newton_rtol * np.linalg.norm(x)):
+                break
+            if it == max_newton:
+                raise RuntimeError("oracle Newton did not converge: %s" % norms)
+            dx = self.solve()
+            x = x + dx
+        self.newton_norms = norms
+        u = x[:3 * nv].reshape(nv, 3).copy()
+        p = x[3 * nv:].copy()
+        self._commit(u, p, t1)
+        return u, p
+
+    def _commit(self, u, p, t1):
         self.u_hist = [u] + self.u_hist[: self.prob.bdf_order - 1]
         self.p_hist = [p] + self.p_hist[: self.prob.bdf_order - 1]
         if self.prob.ale:
@@ -524,6 +607,16 @@ class OracleSim:
         self.n_levels = min(max(self.n_levels, 1) + 1, self.prob.bdf_order)
         self.t = t1
         self.step_index += 1
+
+    def step(self):
+        if getattr(self.prob, "implicit", False):
+            return self.step_implicit()
+        t1 = self.assemble()
+        x0 = np.concatenate([self.u_hist[0].reshape(-1), self.p_hist[0]])
+        sol = self.solve(x0)
+        u = sol[:3 * self.nv].reshape(self.nv, 3).copy()
+        p = sol[3 * self.nv:].copy()
+        self._commit(u, p, t1)
         return u, p
 
     def solution(self):
@@ -543,3 +636,18 @@ def element_p1(X, Xh, uE, uB, uA, pE, f, alpha=1.0, sigma=1.0, dt=0.01, rho=1.0,
     Fe = np.zeros(16)
     det = lib().orc_element_p1(*[_p(a) for a in arrs], ctypes.byref(P), _p(Ke), _p(Fe))
     return Ke, Fe, det
+
+
+def newton_element_p1(X, Xh, u, p, uB, uA, f, alpha=1.0, sigma=1.0, dt=0.01, rho=1.0, mu=0.01, C_r=30.0,
+                      stab="vms_les", symgrad=False, valves=(), h=0.0):
+    """Residual (16) and Jacobian (16x16) of the implicit formulation on one P1 element at the
+    state (u, p), for unit tests.  h: complex-step size (0: the default)."""
+    riis = np.array([x for v in valves for x in v] or [0.0], dtype=np.float64)
+    P = OrcParams(alpha=alpha, sigma=sigma, dt=dt, rho=rho, mu=mu, C_r=C_r, stab=STAB[stab],
+                  symgrad=int(symgrad), n_riis=len(valves), pad=0,
+                  riis=riis.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in (X, Xh, u, p, uB, uA, f)]
+    Ke = np.zeros((16, 16))
+    Re = np.zeros(16)
+    lib().orc_newton_element_p1(*[_p(a) for a in arrs], ctypes.byref(P), float(h), _p(Ke), _p(Re))
+    return Re, Ke

@@ -348,7 +348,7 @@ def test_discrete_gradient_of_constants():
 
 # ------------------------------------------------------------- full steps
 
-def _patch_run(field, bdf_order=1, steps=2, solve="dense", history=None):
+def _patch_run(field, bdf_order=1, steps=2, solve="dense", history=None, implicit=False):
     """Run a jittered, shuffled tube with Dirichlet data from `field` on inlet and wall and
     its exact traction on the outlet.  Returns max nodal errors (u, p)."""
     mesh = tube(nxy=3, nz=4, radius=1.0, length=2.0, seed=11)
@@ -356,7 +356,7 @@ def _patch_run(field, bdf_order=1, steps=2, solve="dense", history=None):
     bcs = [Boundary("dirichlet", (TUBE_TAGS["inlet"], TUBE_TAGS["wall"]), profile=Profile("nodal")),
            Boundary("neumann", (TUBE_TAGS["outlet"],), profile=Profile("nodal", normal=(0, 0, 1)))]
     prob = Problem(bdf_order=bdf_order, dt=0.05, rho=field.rho, mu=field.mu, stab="vms_les",
-                   forcing=True, bcs=bcs)
+                   forcing=True, bcs=bcs, implicit=implicit)
     sim = OracleSim(mesh, prob, solve=solve)
     for lev in range(bdf_order):
         tl = -lev * prob.dt
