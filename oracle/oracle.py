@@ -111,7 +111,9 @@ def lib():
 
 
 def _p(a):
-    return a.ctypes.data if a is not None else None
+    """Pointer argument for the C routines; the pointer object holds a reference to the
+    array, so a temporary passed inline stays alive for the duration of the call."""
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
 
 
 def set_threads(n):
