@@ -80,6 +80,13 @@ def parse():
     ap.add_argument("--serve-verify", type=int, default=4,
                     help="replay this many requests (the smallest, plus the largest) alone afterwards and "
                          "compare with their results in the mix")
+    ap.add_argument("--features", action="store_true",
+                    help="measurement run of the adjacent features on the tube from the Poiseuille field at "
+                         "t0 = 0.25 s: resistance + backflow outlet, elastic lifting with boundary stiffening "
+                         "solved every step, and the fully implicit formulation with Newton; one JSON line")
+    ap.add_argument("--features-steps", type=int, default=5)
+    ap.add_argument("--features-only", default="plain,outflow,lifting,implicit",
+                    help="comma-separated subset of the --features configurations")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy 256 MiB device-to-device twice (a plain copy kernel of known "
                          "size, the reference for scaling the HBM byte counters)")
@@ -453,6 +460,83 @@ def serve(args, torch):
     print(json.dumps(out), flush=True)
 
 
+def features(args, torch):
+    """Measurement of the adjacent features on the benchmark tube started from the Poiseuille field at
+    t0 = 0.25 s (a developed flow): each configuration is created (host clock around the set-up), run
+    for one warm-up step and then timed over --features-steps steps."""
+    from paper_2304_12032_amd import Sim
+    from inputs import tube
+    from inputs.meshes import TUBE_TAGS
+    from inputs.problem import Boundary, Profile, SolverCfg, TimeLaw, tube_poiseuille_state, tube_problem
+    stream = torch.cuda.current_stream(0).cuda_stream
+    mesh = tube(nxy=args.nxy, nz=args.nz, seed=0)
+    X = mesh.coords
+    L = 10.0
+    shape = np.zeros_like(X)
+    bump = 0.05 * np.sin(np.pi * X[:, 2] / L)
+    shape[:, 0], shape[:, 1] = bump * X[:, 0], bump * X[:, 1]
+
+    def make(kind):
+        prob = tube_problem(mesh, t0=0.25)
+        sv = SolverCfg(precision="fp32_ir", rtol=1e-8, ir_rtol=1e-8, max_iters=20000)
+        if kind == "outflow":
+            prob.bcs[2] = Boundary("resistance", (TUBE_TAGS["outlet"],), law=TimeLaw("constant", (0.0,)),
+                                   profile=Profile("uniform", normal=(0.0, 0.0, 1.0)), resistance=5.0, backflow=1.0)
+        elif kind == "lifting":
+            prob.ale = True
+            prob.ale_tags = (TUBE_TAGS["wall"], TUBE_TAGS["inlet"], TUBE_TAGS["outlet"])
+            prob.lifting, prob.lift_E, prob.lift_nu = "elastic", 1.0, 0.3
+            prob.stiffening, prob.stiff_p = "boundary", (0.05, 2.0)
+        elif kind == "implicit":
+            prob.implicit = True
+            sv = SolverCfg(precision="fp64", rtol=1e-8, ir_rtol=1e-8, max_ir=20, max_iters=20000)
+        return prob, sv
+
+    out = {"metric": "adjacent features: ms/step on the 983k-tet tube from the Poiseuille field (t0 = 0.25 s)",
+           "unit": "ms/step", "n_gpus": 1, "data": "synthetic", "steps": args.features_steps, "warmup": 1,
+           "config": {"workload": "tube R=1 L=10, %d tets, N=%d, P1-P1 VMS-LES BDF2 dt=1e-3, RIIS disc" %
+                                  (mesh.nt, 4 * mesh.nv)}}
+    for kind in [k for k in ("plain", "outflow", "lifting", "implicit") if k in args.features_only.split(",")]:
+        prob, sv = make(kind)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim = Sim(mesh, prob, sv, device=0, stream=stream)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        for lev in range(prob.bdf_order):
+            sim.set_state(lev, *tube_poiseuille_state(mesh, prob, prob.t0 - lev * prob.dt))
+        tcur = [prob.t0]
+
+        def drive():
+            tcur[0] += prob.dt
+            if kind == "lifting":
+                # the wall bulge ramped in over 50 ms, given per step: every step solves the lifting problem
+                sim.set_boundary_displacement(min(1.0, (tcur[0] - prob.t0) / 0.05) * shape)
+
+        drive()
+        sim.step()
+        torch.cuda.synchronize()
+        stats, t0 = [], time.perf_counter()
+        for _ in range(args.features_steps):
+            drive()
+            stats.append(sim.step())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        r = {"ms_per_step": round(wall * 1e3 / args.features_steps, 3), "setup_s": round(setup_s, 3),
+             "gmres_iters_per_step": float(np.mean([s_["gmres_iters"] for s_ in stats])),
+             "max_rel_residual": float(max(s_["rel_residual"] for s_ in stats)), "precision": sv.precision}
+        if kind == "implicit":
+            r["newton_iters_per_step"] = float(np.mean([s_["newton_iters"] for s_ in stats]))
+        if kind == "outflow":
+            q_, pint, area = sim.boundary_integrals(2)
+            r["outlet_flux"], r["outlet_mean_pressure"] = q_, pint / area
+        sim.close()
+        out[kind] = r
+        if args.verbose:
+            print("[bench] %s: %s" % (kind, r), file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -464,6 +548,9 @@ def main():
     torch.cuda.init()
     if args.serve:
         serve(args, torch)
+        return
+    if args.features:
+        features(args, torch)
         return
     stream = torch.cuda.current_stream(0).cuda_stream
     from inputs import tube

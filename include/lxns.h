@@ -175,7 +175,15 @@ typedef struct {
     double dt, t0, rho, mu;
     int32_t diffusion, stab;
     double C_r;
-    int32_t semi_implicit;   /* must be 1                                            */
+    int32_t semi_implicit;   /* 1: u* = u_EXT - u_ALE, semi-implicit LES term (one
+                                linear solve per step); 0: the fully implicit
+                                formulation (u* = u^{n+1} - u_ALE, implicit LES term,
+                                Sec. 2.3) solved by Newton's method with the consistent
+                                Jacobian (Sec. 2.4): P1-P1, LX_FP64, no resistance or
+                                backflow terms; lx_solver.max_ir caps the Newton
+                                updates and ir_rtol is their tolerance (||R|| <= ir_rtol
+                                ||R_0||, or an update below ir_rtol ||x||); rtol is each
+                                update's linear tolerance                           */
     int32_t ale;             /* 0 | 1                                                */
     int32_t forcing;         /* 0: f = 0; 1: nodal f from lx_sim_set_forcing        */
     int32_t n_bc;
@@ -279,6 +287,8 @@ typedef struct {
     int64_t asm_calls;
     double resid_ms;          /* FP64 matrix-free residual kernel time                */
     int64_t resid_calls;
+    int32_t newton_iters;     /* Newton updates of an implicit step (0 semi-implicit)  */
+    int32_t pad;
 } lx_step_stats;
 
 typedef struct lx_sim lx_sim;
@@ -360,7 +370,9 @@ lx_status lx_sim_get_solution(const lx_sim *sim, double *u, double *p, double *t
  * solving and copy it out in the caller's numbering as block COO with 4x4
  * blocks (row-major within the block: rows u_x,u_y,u_z,p; cols likewise):
  * brow/bcol [n_blocks], vals [n_blocks][16], rhs [n_vertices][4].  Values are
- * FP64 (FP32 matrices are widened).  rhs is zero for FP32 precision. */
+ * FP64 (FP32 matrices are widened).  rhs is zero for FP32 precision.  With the
+ * implicit formulation: the Newton system (Jacobian and -R, Dirichlet rows set
+ * to the update g - x) at the last solution. */
 lx_status lx_sim_debug_export(lx_sim *sim, int32_t *brow, int32_t *bcol, double *vals, double *rhs);
 
 /* P2-P1 parity export (tests only): the system of the coming step as scalar

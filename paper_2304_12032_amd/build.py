@@ -14,7 +14,7 @@ SRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "liblxns.so")
 SOURCES = ["lx_setup.cpp", "lx_amg_setup.cpp", "lx_setup_p2.cpp", "lx_kernels.hip", "lx_amg.hip", "lx_p2.hip",
-           "lx_ale.hip", "lx_outflow.hip", "lx_sim.hip", "lx_api.hip", "lx_noalloc.hip", "lx_server.cpp"]
+           "lx_ale.hip", "lx_outflow.hip", "lx_newton.hip", "lx_sim.hip", "lx_api.hip", "lx_noalloc.hip", "lx_server.cpp"]
 ARCH = os.environ.get("LXNS_ARCH", "gfx950")
 
 

@@ -262,7 +262,19 @@ extern "C" lx_status lx_sim_debug_export(lx_sim *s, int32_t *brow, int32_t *bcol
     lx::StepCoef C;
     lx_step_stats S;
     memset(&S, 0, sizeof(S));
-    lx_status st = s->build_system(s->t + s->prob.dt, C, S);
+    lx_status st;
+    if (s->prob.semi_implicit) {
+        st = s->build_system(s->t + s->prob.dt, C, S);
+    } else {
+        // implicit formulation: the Newton system at the last solution (Dirichlet rows set
+        // to the update g - x)
+        st = s->prepare(s->t + s->prob.dt, C);
+        if (st == LX_OK) {
+            LX_HIP(hipMemcpyAsync(s->d_xs, s->d_hist[0], sizeof(double) * s->N, hipMemcpyDeviceToDevice, s->stream));
+            s->newton_system(s->t + s->prob.dt, C);
+            LX_HIP(hipGetLastError());
+        }
+    }
     if (st != LX_OK) return st;
     const int64_t nb = s->nblk;
     std::vector<double> planes(16 * nb);

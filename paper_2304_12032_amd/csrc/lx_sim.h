@@ -7,6 +7,7 @@
 #include "lx_amg.h"
 #include "lx_common.h"
 #include "lx_kernels.h"
+#include "lx_newton.h"
 #include "lx_outflow.h"
 #include "lx_p2.h"
 
@@ -109,6 +110,8 @@ struct Sim {
           *d_Z32 = nullptr;
     double *d_r64 = nullptr, *d_b64 = nullptr;
     double *d_rrec = nullptr;                                    // element records of the FP64 residual
+    // implicit formulation: element Newton records [nt][kNewtonRec], the update, its Dirichlet values
+    double *d_nrec = nullptr, *d_dx = nullptr, *d_gdelta = nullptr;
     // SIMPLE block approximations of LX_PC_AMG (one of the two, by precision)
     AmgHost amgh;
     Amg<double> amg64;
@@ -185,6 +188,8 @@ struct Sim {
                     lx_step_stats &tstats, bool inner = false, int kind = 0);
     void coefficients(double t1, StepCoef &C, BCSet &B) const;
     lx_status prepare(double t1, StepCoef &C);
+    lx_status newton(double t1, const StepCoef &C, lx_step_stats &S);
+    void newton_system(double t1, const StepCoef &C);
     lx_status build_system(double t1, StepCoef &C, lx_step_stats &tstats);
     lx_status assemble_system(double t1, StepCoef &C, bool fork_residual = false);
     lx_status build_system_p2(double t1, StepCoef &C);

@@ -104,7 +104,15 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         return fail(LX_EINVAL, "the P2-P1 pair uses the AMG preconditioner (LX_PC_AMG)");
     if (pr->bdf_order < 1 || pr->bdf_order > 3) return fail(LX_EINVAL, "bdf_order must be 1..3");
     if (!(pr->dt > 0) || !(pr->rho > 0) || !(pr->mu >= 0)) return fail(LX_EINVAL, "dt, rho must be > 0, mu >= 0");
-    if (pr->semi_implicit != 1) return fail(LX_EINVAL, "only the semi-implicit formulation is supported");
+    if (pr->semi_implicit != 0 && pr->semi_implicit != 1) return fail(LX_EINVAL, "semi_implicit must be 0 or 1");
+    if (pr->semi_implicit == 0) {
+        if (pr->fe != LX_P1P1) return fail(LX_EINVAL, "the implicit formulation is built for the P1-P1 pair");
+        if (sv->precision != LX_FP64) return fail(LX_EINVAL, "the implicit formulation runs in FP64 (LX_FP64)");
+        for (int i = 0; i < pr->n_bc; ++i)
+            if (pr->bc[i].type == LX_BC_RESISTANCE || pr->bc[i].backflow > 0)
+                return fail(LX_EINVAL, "the implicit formulation is built without resistance or backflow terms");
+        if (sv->max_ir < 1) return fail(LX_EINVAL, "implicit formulation: max_ir (Newton updates) must be >= 1");
+    }
     if (pr->n_riis < 0 || pr->n_riis > kMaxValves) return fail(LX_EINVAL, "at most %d RIIS surfaces", kMaxValves);
     if (pr->n_bc < 0 || pr->n_bc > kMaxBC) return fail(LX_EINVAL, "at most %d boundary conditions", kMaxBC);
     if (sv->restart < 1 || sv->restart > kMaxRestart) return fail(LX_EINVAL, "restart must be 1..%d", kMaxRestart);
@@ -382,6 +390,11 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         ALLOC(d_rec64, sizeof(double) * kRec * nt);
     } else {
         ALLOC(d_rec32, sizeof(float) * kRec * nt);
+    }
+    if (!prob.semi_implicit) {
+        ALLOC(d_nrec, sizeof(double) * kNewtonRec * nt);
+        ALLOC(d_dx, sizeof(double) * N);
+        ALLOC(d_gdelta, sizeof(double) * 3 * std::max<int64_t>(n_dir, 1));
     }
     if (solver.precision == LX_FP64) {
         if (!p2) ALLOC(d_val64, sizeof(double) * kPlanes * nblk);
@@ -1356,6 +1369,76 @@ lx_status Sim::residual64_into(const StepCoef &C, const double *xs, bool first, 
     return LX_OK;
 }
 
+// Newton's method for the implicit formulation, from the guess in d_xs: at each
+// iterate the Jacobian and -R are assembled (Neumann data, Dirichlet rows set to
+// the update g - x), the SIMPLE/AMG preconditioner is built on the Jacobian and
+// GMRES solves the update (to rtol, or to a tenth of the Newton target near the
+// end).  Stops when ||R|| <= ir_rtol ||R_0|| or the last update is below
+// ir_rtol ||x||.
+// The Newton system at the iterate d_xs: Jacobian in d_val64, -R in d_rhs64 (after prepare()).
+void Sim::newton_system(double t1, const StepCoef &C)
+{
+    const RowPattern P = pattern();
+    NewtonArgs A{nt, nblk, d_tet, d_sinc_ptr, d_sinc, d_x, d_xh, d_xs, hist(0), hist(1), hist(2),
+                 prob.ale ? d_uA : nullptr, d_f, d_nrec, d_val64, d_rhs64};
+    launch_fill<double>(N, d_rhs64, 0.0, stream);
+    auto *tm = timer_begin(1, 0);
+    launch_newton_p1(A, C, stream);
+    timer_end(tm);
+    add_neumann(t1, d_rhs64, nullptr);
+    launch_dirichlet_delta(n_dir, d_dir_node, d_g, d_xs, d_gdelta, stream);
+    launch_dirichlet_rows<double>(n_dir, d_dir_node, d_gdelta, P, d_val64, d_rhs64, stream);
+}
+
+lx_status Sim::newton(double t1, const StepCoef &C, lx_step_stats &S)
+{
+    const RowPattern P = pattern();
+    double r0 = 0.0, rn = 0.0;
+    bool conv = false;
+    int it = 0, total = 0;
+    for (;; ++it) {
+        newton_system(t1, C);
+        launch_norm<double>(N, d_rhs64, d_st, 0.0, d_partial, 1, stream);
+        if (it > 0) {
+            launch_norm<double>(N, d_dx, d_st, 0.0, d_partial, 2, stream);
+            launch_norm<double>(N, d_xs, d_st, 0.0, d_partial, 3, stream);
+        }
+        lx_status st = read_state();
+        if (st != LX_OK) return st;
+        rn = h_st->norms[1];
+        if (it == 0) r0 = rn;
+        if (verbose())
+            fprintf(stderr, "[lxns] Newton %d: ||R|| %.3e (%.3e of the start)\n", it, rn, r0 > 0 ? rn / r0 : 0.0);
+        if (!(rn == rn)) break;
+        if (rn <= solver.ir_rtol * r0 || rn == 0.0 || (it > 0 && h_st->norms[2] <= solver.ir_rtol * h_st->norms[3])) {
+            conv = true;
+            break;
+        }
+        if (it >= solver.max_ir || total >= solver.max_iters) break;
+        launch_simple_setup<double>(P, d_val64, d_Finv64, d_Dinv64, solver.precond == LX_PC_AMG ? nullptr : d_Sinv64,
+                                    stream);
+        if (solver.precond == LX_PC_AMG)
+            launch_amg_setup<double>(view<double>(), d_Finv64, d_Dinv64, amg64, stream);
+        else if (solver.schur_degree > 0)
+            launch_schur_bound<double>(P, d_val64, d_Dinv64, d_Sinv64, d_sw64, d_st, d_partial, nb_red, stream);
+        // each update to rtol, but no tighter than the Newton test needs: a residual already near
+        // ir_rtol ||R_0|| is solved only to a tenth of that level (inexact Newton), so that the
+        // linear tolerance never falls below what the Jacobian's conditioning allows
+        const double lin = std::min(0.5, std::max(solver.rtol, 0.1 * solver.ir_rtol * r0 / rn));
+        GmResult gr;
+        st = gmres<double>(d_rhs64, d_dx, true, lin, solver.max_iters - total, gr, S);
+        if (st != LX_OK) return st;
+        total += gr.iters;
+        S.restarts += gr.restarts;
+        launch_axpy<double, double>(N, d_xs, d_dx, nullptr, 1.0, stream);
+    }
+    S.gmres_iters = total;
+    S.newton_iters = it;
+    S.rel_residual = r0 > 0 ? rn / r0 : rn;
+    S.converged = conv;
+    return LX_OK;
+}
+
 lx_status Sim::step(lx_step_stats *out)
 {
     LX_HIP(hipSetDevice(device));
@@ -1366,7 +1449,8 @@ lx_status Sim::step(lx_step_stats *out)
     LX_HIP(hipEventRecord(ev_step0, stream));
     StepCoef C;
     const bool overlap = stream_aux != nullptr;
-    lx_status st = overlap ? prepare(t1, C) : build_system(t1, C, S);
+    // the implicit formulation assembles its Newton systems inside the Newton loop
+    lx_status st = (overlap || !prob.semi_implicit) ? prepare(t1, C) : build_system(t1, C, S);
     if (st != LX_OK) return st;
     if (!overlap) LX_HIP(hipEventRecord(ev_asm1, stream));
     // initial guess, with the new Dirichlet values: the polynomial through the
@@ -1409,7 +1493,10 @@ lx_status Sim::step(lx_step_stats *out)
         LX_HIP(hipStreamWaitEvent(stream, ev_join, 0));
     }
     GmResult gr;
-    if (solver.precision == LX_FP64) {
+    if (!prob.semi_implicit) {
+        st = newton(t1, C, S);
+        if (st != LX_OK) return st;
+    } else if (solver.precision == LX_FP64) {
         st = gmres<double>(d_rhs64, d_xs, false, solver.rtol, solver.max_iters, gr, S);
         if (st != LX_OK) return st;
         S.gmres_iters = gr.iters;
