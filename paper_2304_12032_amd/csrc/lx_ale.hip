@@ -120,8 +120,7 @@ __global__ __launch_bounds__(256) void k_ale_rhs(int64_t nv, LiftOp Afull, const
 // r = rhs - L d; z = Dinv r; p = z; rz, rr, tolerance
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_cg_init(int64_t nv, LiftOp A, const double *dinv, const double *rhs,
-                                                 const double *d, double *r, double *z, double *p, CgState *st,
-                                                 double *partial, double rtol)
+                                                 const double *d, double *r, double *z, double *p, double *partial)
 {
     __shared__ double lds[4 * 9];
     const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / kAleLPR;
@@ -147,9 +146,17 @@ __global__ __launch_bounds__(256) void k_cg_init(int64_t nv, LiftOp A, const dou
     block_sum<9>(acc, lds);
     if (threadIdx.x == 0)
         for (int j = 0; j < 9; ++j) partial[(int64_t)blockIdx.x * 9 + j] = acc[j];
-    if (!arrive_last(&st->counter)) return;
+}
+
+// One workgroup: the sums of k_cg_init's partials (fixed order) -> rz, rr, tolerance.
+// Partials are finished by a kernel of their own rather than by the last block to
+// arrive, which would cost every block a device-wide fence.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_cg_init_fin(int nb, CgState *st, const double *partial, double rtol)
+{
+    __shared__ double lds[4 * 9];
     double tot[9];
-    reduce_partials<9>(partial, gridDim.x, 9, tot, lds);
+    reduce_partials<9>(partial, nb, 9, tot, lds);
     lift_combine<VEC>(tot, 0);
     lift_combine<VEC>(tot, 3);
     lift_combine<VEC>(tot, 6);
@@ -189,9 +196,16 @@ __global__ __launch_bounds__(256) void k_cg_ap(int64_t nv, LiftOp A, const doubl
     block_sum<3>(acc, lds);
     if (threadIdx.x == 0)
         for (int j = 0; j < 3; ++j) partial[(int64_t)blockIdx.x * 3 + j] = acc[j];
-    if (!arrive_last(&st->counter)) return;
+}
+
+// One workgroup: alpha = rz / (p . q) from k_cg_ap's partials.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_cg_ap_fin(int nb, CgState *st, const double *partial)
+{
+    if (st->done) return;
+    __shared__ double lds[4 * 3];
     double tot[3];
-    reduce_partials<3>(partial, gridDim.x, 3, tot, lds);
+    reduce_partials<3>(partial, nb, 3, tot, lds);
     lift_combine<VEC>(tot, 0);
     if (threadIdx.x == 0) {
         for (int c = 0; c < 3; ++c) st->alpha[c] = tot[c] > 0 ? st->rz[c] / tot[c] : 0.0;
@@ -226,9 +240,16 @@ __global__ __launch_bounds__(256) void k_cg_update(int64_t nv, const double *din
     block_sum<6>(acc, lds);
     if (threadIdx.x == 0)
         for (int j = 0; j < 6; ++j) partial[(int64_t)blockIdx.x * 6 + j] = acc[j];
-    if (!arrive_last(&st->counter)) return;
+}
+
+// One workgroup: beta, rz, rr and the convergence test from k_cg_update's partials.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_cg_update_fin(int nb, CgState *st, const double *partial)
+{
+    if (st->done) return;
+    __shared__ double lds[4 * 6];
     double tot[6];
-    reduce_partials<6>(partial, gridDim.x, 6, tot, lds);
+    reduce_partials<6>(partial, nb, 6, tot, lds);
     lift_combine<VEC>(tot, 0);
     lift_combine<VEC>(tot, 3);
     if (threadIdx.x == 0) {
@@ -533,13 +554,15 @@ lx_status Sim::ale_extend(const double *data)
     if (lift_vec) {
         hipLaunchKernelGGL(k_ale_rhs<true>, dim3(grow), dim3(256), 0, stream, nv, Afull, d_ale_mark,
                            data ? data : d_ale_shape, 1.0, rhs, ext);
-        hipLaunchKernelGGL(k_cg_init<true>, dim3(grow), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z, p, cst,
-                           part, 1e-13);
+        hipLaunchKernelGGL(k_cg_init<true>, dim3(grow), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z, p,
+                           part);
+        hipLaunchKernelGGL(k_cg_init_fin<true>, dim3(1), dim3(256), 0, stream, (int)grow, cst, part, 1e-13);
     } else {
         hipLaunchKernelGGL(k_ale_rhs<false>, dim3(grow), dim3(256), 0, stream, nv, Afull, d_ale_mark,
                            data ? data : d_ale_shape, 1.0, rhs, ext);
         hipLaunchKernelGGL(k_cg_init<false>, dim3(grow), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z, p,
-                           cst, part, 1e-13);
+                           part);
+        hipLaunchKernelGGL(k_cg_init_fin<false>, dim3(1), dim3(256), 0, stream, (int)grow, cst, part, 1e-13);
     }
     CgState h;
     const int max_it = 50000;
@@ -548,12 +571,16 @@ lx_status Sim::ale_extend(const double *data)
         for (int k = 0; k < 25; ++k) {
             if (lift_vec) {
                 hipLaunchKernelGGL(k_cg_ap<true>, dim3(grow), dim3(256), 0, stream, nv, A, p, q, cst, part);
+                hipLaunchKernelGGL(k_cg_ap_fin<true>, dim3(1), dim3(256), 0, stream, (int)grow, cst, part);
                 hipLaunchKernelGGL(k_cg_update<true>, dim3(gvec), dim3(256), 0, stream, nv, d_lapdinv, p, q, ext, r, z,
                                    cst, part);
+                hipLaunchKernelGGL(k_cg_update_fin<true>, dim3(1), dim3(256), 0, stream, (int)gvec, cst, part);
             } else {
                 hipLaunchKernelGGL(k_cg_ap<false>, dim3(grow), dim3(256), 0, stream, nv, A, p, q, cst, part);
+                hipLaunchKernelGGL(k_cg_ap_fin<false>, dim3(1), dim3(256), 0, stream, (int)grow, cst, part);
                 hipLaunchKernelGGL(k_cg_update<false>, dim3(gvec), dim3(256), 0, stream, nv, d_lapdinv, p, q, ext, r,
                                    z, cst, part);
+                hipLaunchKernelGGL(k_cg_update_fin<false>, dim3(1), dim3(256), 0, stream, (int)gvec, cst, part);
             }
             hipLaunchKernelGGL(k_cg_dir, dim3(gvec), dim3(256), 0, stream, nv, z, p, cst);
         }
