@@ -109,7 +109,7 @@ def spmv_bytes_p2(q, s):
 
 def spmv_source_hash():
     """SHA-256 (first 16 hex digits) of the k_spmv kernel's source text and of the
-    device helpers it calls (workgroup remap, done-flag test)."""
+    device helpers it calls (workgroup remap, done-flag test, matrix loads)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2304_12032_amd", "csrc")
     src = open(os.path.join(csrc, "lx_kernels.hip")).read()
@@ -118,7 +118,8 @@ def spmv_source_hash():
     b = src.index("\n}\n", a) + 3
     dev = open(os.path.join(csrc, "lx_device.h")).read()
     text = src[a:b]
-    for head in ("__device__ __forceinline__ bool done_with(", "__device__ inline int64_t xcd_block()"):
+    for head in ("__device__ __forceinline__ bool done_with(", "__device__ inline int64_t xcd_block()",
+                 "__device__ __forceinline__ T ld_mat("):
         c = dev.index(head)
         text += dev[c:dev.index("\n}\n", c) + 3]
     return hashlib.sha256(text.encode()).hexdigest()[:16]

@@ -231,9 +231,10 @@ typedef struct {
                                 a fixed order (no atomics) and every reduction
                                 has a fixed order already                          */
     int32_t collect_timing;  /* n >= 1: HIP events stamped by every n-th SpMV
-                                launch inside an Arnoldi cycle, by every
-                                cycle-start SpMV and around every assembly and
-                                FP64 residual pass; 0: none                      */
+                                launch of the solves (Arnoldi steps and cycle
+                                starts alike; a timed Arnoldi step launches its
+                                product outside the step's HIP graph) and around
+                                every assembly and FP64 residual pass; 0: none  */
     int32_t schur_degree;    /* 0..32                                               */
     int32_t asm_fp64;        /* LX_FP32_IR only: 1 = build the FP32 matrix by FP64
                                 element arithmetic and scatter, rounded to FP32;

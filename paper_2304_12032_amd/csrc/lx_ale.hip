@@ -41,12 +41,17 @@ struct LiftOp {
     int64_t nblk;
 };
 
-template <int LPR, bool VEC>
-__device__ inline void lift_row(int64_t row, int lane, const LiftOp &A, const double *x, double y[3])
+// y = K x at one row.  DIR: x = z + beta p_old, the CG direction formed on the fly
+// from the preconditioned residual and the previous direction (x = z, p = p_old).
+template <int LPR, bool VEC, bool DIR = false>
+__device__ inline void lift_row(int64_t row, int lane, const LiftOp &A, const double *x, double y[3],
+                                const double *p = nullptr, const double *beta = nullptr)
 {
     y[0] = y[1] = y[2] = 0;
     for (int32_t k = A.rowptr[row] + lane; k < A.rowptr[row + 1]; k += LPR) {
-        const double *xj = x + 3 * (int64_t)A.col[k];
+        const int64_t j = 3 * (int64_t)A.col[k];
+        double xj[3];
+        for (int c = 0; c < 3; ++c) xj[c] = DIR ? x[j + c] + beta[c] * p[j + c] : x[j + c];
         if (VEC) {
             for (int c = 0; c < 3; ++c)
                 for (int d = 0; d < 3; ++d) y[c] += A.K[(int64_t)(3 * c + d) * A.nblk + k] * xj[d];
@@ -80,7 +85,16 @@ __device__ inline void lift_combine(double (&tot)[K], int first)
     }
 }
 
-constexpr int kAleLPR = 16;
+// Lanes per row of the lifting products: a scalar (harmonic) row has one value per
+// neighbour, so four lanes share a row and each walks about four neighbours with
+// independent loads; a 3x3-block (elastic) row has nine, and takes eight lanes.
+// The CG's row passes (k_cg_init, k_cg_ap) stride over the rows with at most
+// kLiftBlocks workgroups, so that the one-workgroup kernels finishing their dot
+// products add at most that many partial sums.
+constexpr int kLiftBlocks = 2048;
+template <bool VEC> constexpr int lift_lpr() { return VEC ? 8 : 4; }
+template <bool VEC> unsigned lift_blocks(int64_t nv) { return (unsigned)((nv * lift_lpr<VEC>() + 255) / 256); }
+template <bool VEC> unsigned lift_grid(int64_t nv) { return std::min<unsigned>(lift_blocks<VEC>(nv), kLiftBlocks); }
 
 // rhs: boundary rows d_B; interior rows -sum_{j in B} Lfull_ij d_B(j).  d0: initial
 // guess with boundary rows set.
@@ -88,11 +102,12 @@ template <bool VEC>
 __global__ __launch_bounds__(256) void k_ale_rhs(int64_t nv, LiftOp Afull, const int32_t *mark, const double *shape,
                                                  double scale, double *rhs, double *d0)
 {
-    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / kAleLPR;
-    const int lane = threadIdx.x % kAleLPR;
+    constexpr int LPR = lift_lpr<VEC>();
+    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
     if (row >= nv) return;
     double y[3] = {0, 0, 0};
-    for (int32_t k = Afull.rowptr[row] + lane; k < Afull.rowptr[row + 1]; k += kAleLPR) {
+    for (int32_t k = Afull.rowptr[row] + lane; k < Afull.rowptr[row + 1]; k += LPR) {
         const int64_t j = Afull.col[k];
         if (mark[j]) {
             if (VEC) {
@@ -104,7 +119,7 @@ __global__ __launch_bounds__(256) void k_ale_rhs(int64_t nv, LiftOp Afull, const
             }
         }
     }
-    for (int c = 0; c < 3; ++c) y[c] = group_sum<double, kAleLPR>(y[c]);
+    for (int c = 0; c < 3; ++c) y[c] = group_sum<double, LPR>(y[c]);
     if (lane == 0) {
         for (int c = 0; c < 3; ++c) {
             if (mark[row]) {
@@ -122,13 +137,13 @@ template <bool VEC>
 __global__ __launch_bounds__(256) void k_cg_init(int64_t nv, LiftOp A, const double *dinv, const double *rhs,
                                                  const double *d, double *r, double *z, double *p, double *partial)
 {
+    constexpr int LPR = lift_lpr<VEC>(), RPB = 256 / LPR;
     __shared__ double lds[4 * 9];
-    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / kAleLPR;
-    const int lane = threadIdx.x % kAleLPR;
+    const int lane = threadIdx.x % LPR;
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (row < nv) {
+    for (int64_t row = xcd_block() * RPB + threadIdx.x / LPR; row < nv; row += (int64_t)gridDim.x * RPB) {
         double y[3];
-        lift_row<kAleLPR, VEC>(row, lane, A, d, y);
+        lift_row<LPR, VEC>(row, lane, A, d, y);
         if (lane == 0) {
             double rr[3], zz[3];
             for (int c = 0; c < 3; ++c) rr[c] = rhs[3 * row + c] - y[c];
@@ -137,9 +152,9 @@ __global__ __launch_bounds__(256) void k_cg_init(int64_t nv, LiftOp A, const dou
                 r[3 * row + c] = rr[c];
                 z[3 * row + c] = zz[c];
                 p[3 * row + c] = zz[c];
-                acc[c] = rr[c] * zz[c];
-                acc[3 + c] = rr[c] * rr[c];
-                acc[6 + c] = rhs[3 * row + c] * rhs[3 * row + c];
+                acc[c] += rr[c] * zz[c];
+                acc[3 + c] += rr[c] * rr[c];
+                acc[6 + c] += rhs[3 * row + c] * rhs[3 * row + c];
             }
         }
     }
@@ -166,6 +181,7 @@ __global__ __launch_bounds__(256) void k_cg_init_fin(int nb, CgState *st, const 
             st->rz[c] = tot[c];
             st->rr[c] = tot[3 + c];
             st->tol2[c] = rtol * rtol * tot[6 + c];
+            st->beta[c] = 0.0;   // the first direction is z (k_cg_init also stores it as p_old)
             if (st->rr[c] > st->tol2[c]) done = false;
         }
         st->done = done ? 1 : 0;
@@ -174,23 +190,27 @@ __global__ __launch_bounds__(256) void k_cg_init_fin(int nb, CgState *st, const 
     }
 }
 
-// q = L p, alpha = rz / (p.q)
+// p = z + beta p_old (written to pn; p_old stays for the rows still gathering it),
+// q = L p, partial sums of p.q for alpha = rz / (p.q)
 template <bool VEC>
-__global__ __launch_bounds__(256) void k_cg_ap(int64_t nv, LiftOp A, const double *p, double *q, CgState *st,
-                                               double *partial)
+__global__ __launch_bounds__(256) void k_cg_ap(int64_t nv, LiftOp A, const double *z, const double *pold, double *pn,
+                                               double *q, CgState *st, double *partial)
 {
     if (st->done) return;
+    constexpr int LPR = lift_lpr<VEC>(), RPB = 256 / LPR;
     __shared__ double lds[4 * 3];
-    const int64_t row = (xcd_block() * blockDim.x + threadIdx.x) / kAleLPR;
-    const int lane = threadIdx.x % kAleLPR;
+    const double beta[3] = {st->beta[0], st->beta[1], st->beta[2]};
+    const int lane = threadIdx.x % LPR;
     double acc[3] = {0, 0, 0};
-    if (row < nv) {
+    for (int64_t row = xcd_block() * RPB + threadIdx.x / LPR; row < nv; row += (int64_t)gridDim.x * RPB) {
         double y[3];
-        lift_row<kAleLPR, VEC>(row, lane, A, p, y);
+        lift_row<LPR, VEC, true>(row, lane, A, z, y, pold, beta);
         if (lane == 0)
             for (int c = 0; c < 3; ++c) {
+                const double pc = z[3 * row + c] + beta[c] * pold[3 * row + c];
+                pn[3 * row + c] = pc;
                 q[3 * row + c] = y[c];
-                acc[c] = p[3 * row + c] * y[c];
+                acc[c] += pc * y[c];
             }
     }
     block_sum<3>(acc, lds);
@@ -264,14 +284,6 @@ __global__ __launch_bounds__(256) void k_cg_update_fin(int nb, CgState *st, cons
         st->iters += 1;
         st->counter = 0;
     }
-}
-
-__global__ void k_cg_dir(int64_t nv, const double *z, double *p, const CgState *st)
-{
-    if (st->done) return;
-    const double b[3] = {st->beta[0], st->beta[1], st->beta[2]};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x)
-        for (int c = 0; c < 3; ++c) p[3 * i + c] = z[3 * i + c] + b[c] * p[3 * i + c];
 }
 
 // Distance from p to triangle (a, b, c): the closest point is found from the
@@ -471,17 +483,17 @@ lx_status Sim::ale_setup()
     ALLOC(d_lapfull, sizeof(double) * np * nblk);
     ALLOC(d_lapdinv, sizeof(double) * np * nv);
     ALLOC(d_ale_mark, sizeof(int32_t) * nv);
-    ALLOC(d_cg, sizeof(double) * 3 * nv * 6 + sizeof(CgState));
+    ALLOC(d_cg, sizeof(double) * 3 * nv * 7 + sizeof(CgState));
     ALLOC(d_dnew, sizeof(double) * 3 * nv);
     ALLOC(d_dbnd, sizeof(double) * 3 * nv);
     // reduction partials of the lifting CG (one row of 9 per workgroup of the row kernels)
-    ALLOC(d_cg_partial, sizeof(double) * 9 * ((nv * kAleLPR + 255) / 256));
+    ALLOC(d_cg_partial, sizeof(double) * 9 * std::max(kLiftBlocks, 1024));
 #undef ALLOC
     LX_HIP(hipMemcpyAsync(d_lap, Le.data(), sizeof(double) * Le.size(), hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_lapfull, L.data(), sizeof(double) * L.size(), hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_lapdinv, dinv.data(), sizeof(double) * dinv.size(), hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_ale_mark, mark.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, stream));
-    LX_HIP(hipMemsetAsync(d_cg, 0, sizeof(double) * 3 * nv * 6 + sizeof(CgState), stream));
+    LX_HIP(hipMemsetAsync(d_cg, 0, sizeof(double) * 3 * nv * 7 + sizeof(CgState), stream));
     LX_HIP(hipStreamSynchronize(stream));
     ale_ext_valid = false;
     return LX_OK;
@@ -541,50 +553,61 @@ lx_status Sim::ale_boundary_distance(std::vector<double> &dist)
 }
 
 // Lifting into d_cg[ext] (CG to rtol 1e-13): of the shape D^ (data = nullptr),
-// or of nodal boundary data starting from the guess already in ext.
+// or of nodal boundary data starting from the guess already in ext.  The
+// directions alternate between two buffers (k_cg_ap forms the next one from the
+// previous); the iterations run in batches of kLiftBatch, with the host reading
+// the state after each batch.
+constexpr int kLiftBatch = 24;   // even: each batch ends on the buffer it started from
+template <bool VEC>
+static void lift_iteration(int64_t nv, const LiftOp &A, const double *dinv, double *ext, double *r, double *z,
+                           const double *pold, double *pn, double *q, CgState *cst, double *part, unsigned gcg,
+                           unsigned gvec, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_ap<VEC>, dim3(gcg), dim3(256), 0, s, nv, A, z, pold, pn, q, cst, part);
+    hipLaunchKernelGGL(k_cg_ap_fin<VEC>, dim3(1), dim3(256), 0, s, (int)gcg, cst, part);
+    hipLaunchKernelGGL(k_cg_update<VEC>, dim3(gvec), dim3(256), 0, s, nv, dinv, pn, q, ext, r, z, cst, part);
+    hipLaunchKernelGGL(k_cg_update_fin<VEC>, dim3(1), dim3(256), 0, s, (int)gvec, cst, part);
+}
+
 lx_status Sim::ale_extend(const double *data)
 {
-    double *ext = d_cg, *rhs = d_cg + 3 * nv, *r = d_cg + 6 * nv, *z = d_cg + 9 * nv, *p = d_cg + 12 * nv,
-           *q = d_cg + 15 * nv;
-    CgState *cst = (CgState *)(d_cg + 18 * nv);
-    const unsigned grow = (unsigned)((nv * kAleLPR + 255) / 256);
+    double *ext = d_cg, *rhs = d_cg + 3 * nv, *r = d_cg + 6 * nv, *z = d_cg + 9 * nv, *q = d_cg + 15 * nv;
+    double *pb[2] = {d_cg + 12 * nv, d_cg + 18 * nv};
+    CgState *cst = (CgState *)(d_cg + 21 * nv);
+    const unsigned grow = lift_vec ? lift_blocks<true>(nv) : lift_blocks<false>(nv);   // k_ale_rhs
+    const unsigned gcg = lift_vec ? lift_grid<true>(nv) : lift_grid<false>(nv);        // CG row passes
     const unsigned gvec = (unsigned)std::min<int64_t>((nv + 255) / 256, 1024);
     const LiftOp Afull{d_rowptr, d_col, d_lapfull, nblk}, A{d_rowptr, d_col, d_lap, nblk};
-    double *part = d_cg_partial;   // grow blocks * 9 doubles
+    double *part = d_cg_partial;   // gcg (or gvec) blocks * 9 doubles
     if (lift_vec) {
         hipLaunchKernelGGL(k_ale_rhs<true>, dim3(grow), dim3(256), 0, stream, nv, Afull, d_ale_mark,
                            data ? data : d_ale_shape, 1.0, rhs, ext);
-        hipLaunchKernelGGL(k_cg_init<true>, dim3(grow), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z, p,
-                           part);
-        hipLaunchKernelGGL(k_cg_init_fin<true>, dim3(1), dim3(256), 0, stream, (int)grow, cst, part, 1e-13);
+        hipLaunchKernelGGL(k_cg_init<true>, dim3(gcg), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z,
+                           pb[0], part);
+        hipLaunchKernelGGL(k_cg_init_fin<true>, dim3(1), dim3(256), 0, stream, (int)gcg, cst, part, 1e-13);
     } else {
         hipLaunchKernelGGL(k_ale_rhs<false>, dim3(grow), dim3(256), 0, stream, nv, Afull, d_ale_mark,
                            data ? data : d_ale_shape, 1.0, rhs, ext);
-        hipLaunchKernelGGL(k_cg_init<false>, dim3(grow), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z, p,
-                           part);
-        hipLaunchKernelGGL(k_cg_init_fin<false>, dim3(1), dim3(256), 0, stream, (int)grow, cst, part, 1e-13);
+        hipLaunchKernelGGL(k_cg_init<false>, dim3(gcg), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z,
+                           pb[0], part);
+        hipLaunchKernelGGL(k_cg_init_fin<false>, dim3(1), dim3(256), 0, stream, (int)gcg, cst, part, 1e-13);
     }
+    auto batch = [&](hipStream_t s) {
+        for (int k = 0; k < kLiftBatch; ++k) {
+            const double *pold = pb[k & 1];
+            double *pn = pb[(k + 1) & 1];
+            if (lift_vec)
+                lift_iteration<true>(nv, A, d_lapdinv, ext, r, z, pold, pn, q, cst, part, gcg, gvec, s);
+            else
+                lift_iteration<false>(nv, A, d_lapdinv, ext, r, z, pold, pn, q, cst, part, gcg, gvec, s);
+        }
+    };
     CgState h;
     const int max_it = 50000;
     int it = 0;
     for (;;) {
-        for (int k = 0; k < 25; ++k) {
-            if (lift_vec) {
-                hipLaunchKernelGGL(k_cg_ap<true>, dim3(grow), dim3(256), 0, stream, nv, A, p, q, cst, part);
-                hipLaunchKernelGGL(k_cg_ap_fin<true>, dim3(1), dim3(256), 0, stream, (int)grow, cst, part);
-                hipLaunchKernelGGL(k_cg_update<true>, dim3(gvec), dim3(256), 0, stream, nv, d_lapdinv, p, q, ext, r, z,
-                                   cst, part);
-                hipLaunchKernelGGL(k_cg_update_fin<true>, dim3(1), dim3(256), 0, stream, (int)gvec, cst, part);
-            } else {
-                hipLaunchKernelGGL(k_cg_ap<false>, dim3(grow), dim3(256), 0, stream, nv, A, p, q, cst, part);
-                hipLaunchKernelGGL(k_cg_ap_fin<false>, dim3(1), dim3(256), 0, stream, (int)grow, cst, part);
-                hipLaunchKernelGGL(k_cg_update<false>, dim3(gvec), dim3(256), 0, stream, nv, d_lapdinv, p, q, ext, r,
-                                   z, cst, part);
-                hipLaunchKernelGGL(k_cg_update_fin<false>, dim3(1), dim3(256), 0, stream, (int)gvec, cst, part);
-            }
-            hipLaunchKernelGGL(k_cg_dir, dim3(gvec), dim3(256), 0, stream, nv, z, p, cst);
-        }
-        it += 25;
+        batch(stream);
+        it += kLiftBatch;
         LX_HIP(hipGetLastError());
         LX_HIP(hipMemcpyAsync(&h, cst, sizeof(CgState), hipMemcpyDeviceToHost, stream));
         LX_HIP(hipStreamSynchronize(stream));

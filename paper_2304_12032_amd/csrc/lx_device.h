@@ -1,6 +1,8 @@
 // Device-side helpers shared by the kernel translation units.
 #pragma once
 
+#include <type_traits>
+
 #include "lx_common.h"
 
 namespace lx {
@@ -26,6 +28,27 @@ __device__ inline void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ bool done_with(const int32_t *done, int32_t dep)
 {
     return done != nullptr && ((done[0] != 0) & (dep != INT32_MIN));
+}
+
+// Bytes of one MI355X's last-level cache (the 256 MB MALL in front of HBM).  The
+// SpMV's planes, when larger than that, are streamed from HBM by every product,
+// and its loads are non-temporal (ld_mat<true>), leaving the caches to the
+// gathered vector blocks: 65 -> 57 us per FP64 product on the 983k-tet tube (347
+// MB of planes), no change on the 8M-tet chamber.  The other streamed passes keep
+// ordinary loads, as measured: non-temporal loads slowed the velocity-block
+// Chebyshev pass of the chamber (FP64 step 589 -> 640 ms) and, with the
+// round-robin row order of P2-P1, its Chebyshev pass (234 -> 305 us) and SpMV.
+// LXNS_STREAM_LOADS=0 turns them off.
+constexpr int64_t kLastLevelCacheBytes = int64_t(256) << 20;
+bool streamed(int64_t bytes);
+
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_mat(const T *p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
 }
 
 // Workgroup index with the grid split into 8 contiguous ranges, one per die

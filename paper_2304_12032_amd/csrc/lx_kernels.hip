@@ -1036,8 +1036,9 @@ template void launch_simple_apply<float>(const RowPattern &, const Simple<float>
 
 // y = A x over the block-CSR planes: LPR lanes per block row, each lane one
 // 4x4 block per iteration (16 unit-stride plane loads + one gathered 4-vector),
-// then a cross-lane reduction of the 4 row sums.
-template <typename T, int LPR>
+// then a cross-lane reduction of the 4 row sums.  NT: the planes exceed the
+// last-level cache (ld_mat).
+template <typename T, int LPR, bool NT>
 __global__ __launch_bounds__(256) void k_spmv(RowPattern P, const T *__restrict__ val, const T *__restrict__ x,
                                               T *__restrict__ y, const int32_t *done)
 {
@@ -1055,7 +1056,7 @@ __global__ __launch_bounds__(256) void k_spmv(RowPattern P, const T *__restrict_
         const T x0 = xv.v[0], x1 = xv.v[1], x2 = xv.v[2], x3 = xv.v[3];
         T a[16];
 #pragma unroll
-        for (int p = 0; p < 16; ++p) a[p] = val[p * nb + k];
+        for (int p = 0; p < 16; ++p) a[p] = ld_mat<NT>(&val[p * nb + k]);
         y0 += a[0] * x0 + a[1] * x1 + a[2] * x2 + a[9] * x3;
         y1 += a[3] * x0 + a[4] * x1 + a[5] * x2 + a[10] * x3;
         y2 += a[6] * x0 + a[7] * x1 + a[8] * x2 + a[11] * x3;
@@ -1073,6 +1074,15 @@ __global__ __launch_bounds__(256) void k_spmv(RowPattern P, const T *__restrict_
         out.v[3] = (T)y3;
         reinterpret_cast<V *>(y)[row] = out;
     }
+}
+
+bool streamed(int64_t bytes)
+{
+    static const bool on = [] {
+        const char *e = getenv("LXNS_STREAM_LOADS");
+        return !(e && *e == '0');
+    }();
+    return on && bytes > kLastLevelCacheBytes;
 }
 
 // Lanes per block row of the SpMV (4, 8 or 16; LXNS_LPR_SPMV overrides).
@@ -1093,12 +1103,19 @@ void launch_spmv(const RowPattern &P, const T *val, const T *x, T *y, const int3
 {
     const int lpr = lanes_per_row_spmv();
     const unsigned g = (unsigned)((P.nv * lpr + 255) / 256);
-    if (lpr == 4)
-        hipExtLaunchKernelGGL((k_spmv<T, 4>), dim3(g), dim3(256), 0, s, ev0, ev1, 0, P, val, x, y, done);
-    else if (lpr == 8)
-        hipExtLaunchKernelGGL((k_spmv<T, 8>), dim3(g), dim3(256), 0, s, ev0, ev1, 0, P, val, x, y, done);
+    auto go = [&](auto nt) {
+        constexpr bool NT = decltype(nt)::value;
+        if (lpr == 4)
+            hipExtLaunchKernelGGL((k_spmv<T, 4, NT>), dim3(g), dim3(256), 0, s, ev0, ev1, 0, P, val, x, y, done);
+        else if (lpr == 8)
+            hipExtLaunchKernelGGL((k_spmv<T, 8, NT>), dim3(g), dim3(256), 0, s, ev0, ev1, 0, P, val, x, y, done);
+        else
+            hipExtLaunchKernelGGL((k_spmv<T, 16, NT>), dim3(g), dim3(256), 0, s, ev0, ev1, 0, P, val, x, y, done);
+    };
+    if (streamed(16 * P.nblk * (int64_t)sizeof(T)))
+        go(std::true_type{});
     else
-        hipExtLaunchKernelGGL((k_spmv<T, 16>), dim3(g), dim3(256), 0, s, ev0, ev1, 0, P, val, x, y, done);
+        go(std::false_type{});
 }
 template void launch_spmv<double>(const RowPattern &, const double *, const double *, double *, const int32_t *,
                                   hipStream_t, hipEvent_t, hipEvent_t);

@@ -95,7 +95,7 @@ struct Sim {
     std::vector<int32_t> h_ale_faces;                            // [n][3] faces with the ALE tags
     int32_t *d_ale_nodes = nullptr;
     int32_t *d_ale_mark = nullptr;                               // [nv] 1 on ALE boundary
-    double *d_cg = nullptr;                                      // CG work: 6 vectors [nv][3] + state
+    double *d_cg = nullptr;                                      // CG work: 7 vectors [nv][3] + state
     double *d_cg_partial = nullptr;
     bool ale_ext_valid = false;
     double *d_dbnd = nullptr;                                    // [nv][3] nodal boundary displacement at t^{n+1}
@@ -129,7 +129,7 @@ struct Sim {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
     std::vector<std::pair<int, int>> ev_tag;
     size_t ev_used = 0;
-    int64_t spmv_seq = 0;   // in-cycle SpMV launches so far (every collect_timing-th one is timed)
+    int64_t spmv_seq = 0;   // SpMV launches of the solves so far (every collect_timing-th one is timed)
     hipEvent_t ev_step0 = nullptr, ev_step1 = nullptr, ev_asm1 = nullptr;
     // P1-P1 FP32 + refinement on meshes of 2^19 tets and more: a second stream on which the FP64
     // residual of the initial guess runs while the FP32 system is assembled
@@ -146,11 +146,13 @@ struct Sim {
     // Gram-Schmidt pass, one graph per (k, whether the step ends the cycle),
     // captured on a private stream the first time it is needed and replayed on
     // every later solve (their launches take fixed buffers); LXNS_GRAPH=0 launches
-    // the kernels one by one instead
+    // the kernels one by one instead.  Steps whose product is timed replay the
+    // apply (slot 2 kMaxRestart + k) and the Gram-Schmidt pass (4 kMaxRestart + key)
+    // as graphs of their own and launch the product between them
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
     std::vector<hipGraph_t> g_step;
-    std::vector<hipGraphExec_t> gx_step;   // [2 kMaxRestart]
+    std::vector<hipGraphExec_t> gx_step;   // [6 kMaxRestart]
     // columns used by cycle c of the last solve of each kind (0: unknown), where
     // the next solve of that kind starts checking every step
     int32_t k_hint[8][8] = {};

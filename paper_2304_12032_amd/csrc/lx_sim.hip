@@ -361,8 +361,8 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         use_graphs = !(ge && *ge == '0');
         if (use_graphs) {
             LX_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
-            g_step.assign(2 * kMaxRestart, nullptr);
-            gx_step.assign(2 * kMaxRestart, nullptr);
+            g_step.assign(6 * kMaxRestart, nullptr);
+            gx_step.assign(6 * kMaxRestart, nullptr);
         }
     }
     if (p2) {
@@ -756,7 +756,7 @@ lx_status Sim::setup_amg(Amg<T> &A)
 std::pair<hipEvent_t, hipEvent_t> *Sim::timer_begin(int kind, int iter, bool record)
 {
     if (solver.collect_timing <= 0) return nullptr;
-    if (kind == 0 && iter >= 0 && (spmv_seq++ % solver.collect_timing) != 0) return nullptr;
+    if (kind == 0 && (spmv_seq++ % solver.collect_timing) != 0) return nullptr;
     if (ev_used >= ev_pool.size()) {
         hipEvent_t a, b;
         if (hipEventCreate(&a) != hipSuccess) return nullptr;
@@ -938,29 +938,51 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
             const bool amg = solver.precond == LX_PC_AMG;
             // Arnoldi step k: z_k = M^{-1} v_k, w = A z_k, Gram-Schmidt (from the second
             // step on, the pass that formed v_k already started the velocity block on it)
-            auto arnoldi = [&](hipStream_t s, bool timed) {
+            // The Arnoldi step in two parts around the product: the preconditioner
+            // apply, and the Gram-Schmidt pass (with the next step's head start)
+            auto pre = [&](hipStream_t s) {
                 if (amg)
                     launch_simple_amg_apply<T>(view<T>(), SP.Finv, SP.Dinv, Ops<T>::amg(this), V + k * ld,
                                                &d_st->s[k], zk, &d_st->done, s, k > 0);
                 else
                     launch_simple_apply<T>(P, SP, V + k * ld, &d_st->s[k], zk, &d_st->done, s);
-                auto *tm = timed ? timer_begin(0, k, false) : nullptr;
-                spmv<T>(zk, w, &d_st->done, tm, s);
+            };
+            auto post = [&](hipStream_t s) {
                 FzStart<T> fz;
                 if (amg) fz = amg_fz_start(Ops<T>::amg(this), SP.Finv, Z + (k + 1) * ld);
                 launch_gm_orth<T>(N, k, V, ld, w, d_st, d_partial, s, amg && k + 1 < kmax ? &fz : nullptr);
             };
+            auto replay = [&](int slot, auto &&part) {
+                if (!gx_step[slot]) {
+                    LX_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+                    part(cap_stream);
+                    LX_HIP(hipStreamEndCapture(cap_stream, &g_step[slot]));
+                    LX_HIP(hipGraphInstantiate(&gx_step[slot], g_step[slot], nullptr, nullptr, 0));
+                }
+                LX_HIP(hipGraphLaunch(gx_step[slot], stream));
+                return LX_OK;
+            };
             if (use_graphs) {
                 const int key = 2 * k + (k + 1 < kmax ? 0 : 1);
-                if (!gx_step[key]) {
-                    LX_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-                    arnoldi(cap_stream, false);
-                    LX_HIP(hipStreamEndCapture(cap_stream, &g_step[key]));
-                    LX_HIP(hipGraphInstantiate(&gx_step[key], g_step[key], nullptr, nullptr, 0));
+                // a timed step replays its two parts as graphs of their own around
+                // the product, launched directly so that its events stamp the kernel
+                auto *tm = timer_begin(0, k, false);
+                if (tm) {
+                    if (lx_status e = replay(2 * kMaxRestart + k, pre); e != LX_OK) return e;
+                    spmv<T>(zk, w, &d_st->done, tm, stream);
+                    if (lx_status e = replay(4 * kMaxRestart + key, post); e != LX_OK) return e;
+                } else {
+                    auto whole = [&](hipStream_t s) {
+                        pre(s);
+                        spmv<T>(zk, w, &d_st->done, nullptr, s);
+                        post(s);
+                    };
+                    if (lx_status e = replay(key, whole); e != LX_OK) return e;
                 }
-                LX_HIP(hipGraphLaunch(gx_step[key], stream));
             } else {
-                arnoldi(stream, true);
+                pre(stream);
+                spmv<T>(zk, w, &d_st->done, timer_begin(0, k, false), stream);
+                post(stream);
             }
             if (pending >= 0) {
                 LX_HIP(hipEventSynchronize(ev_chk[pending & 1]));

@@ -184,6 +184,14 @@ def lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("liblxns.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        # PyTorch ships its own HIP runtime under the same soname as ROCm's.  Loaded
+        # first, it is the process's runtime and the library binds to it, so torch's
+        # streams and memory are valid in the library; loaded after the library, it
+        # would be a second runtime in the process, which then finds no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

@@ -28,6 +28,19 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, s), s
 
 
+def test_binding_loads_torch_before_the_library():
+    """The library must bind to the HIP runtime PyTorch ships (same soname as ROCm's):
+    loading the library first would bring a second runtime into the process, and
+    torch would then find no device.  A fresh interpreter that only loads the library
+    has torch loaded before it."""
+    import subprocess
+    import sys
+    code = ("import sys; from paper_2304_12032_amd import lxns; assert 'torch' not in sys.modules; "
+            "lxns.lib(); assert 'torch' in sys.modules")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+
+
 def test_binding_signatures_cover_header():
     from paper_2304_12032_amd.lxns import SIGNATURES
     assert set(declared_symbols()) == set(SIGNATURES)
