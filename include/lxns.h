@@ -289,7 +289,8 @@ typedef struct {
     double resid_ms;          /* FP64 matrix-free residual kernel time                */
     int64_t resid_calls;
     int32_t newton_iters;     /* Newton updates of an implicit step (0 semi-implicit)  */
-    int32_t pad;
+    int32_t lift_iters;       /* lifting CG iterations of the step (0 when the step
+                                 solved no lifting problem)                       */
 } lx_step_stats;
 
 typedef struct lx_sim lx_sim;
@@ -330,8 +331,9 @@ lx_status lx_sim_set_ale_displacement(lx_sim *sim, const double *d);
 /* Boundary displacement d^ at t^{n+1} of the coming step, [n_vertices][3] (rows
  * of ALE boundary vertices are read; Sec. 2.1.1's data on the moving boundary).
  * From this call on, every step solves the lifting problem for the values last
- * set (CG on the reference-mesh Laplacian, started from the extrapolation of the
- * displacement history, to a relative residual of 1e-13) instead of scaling the
+ * set (CG on the reference-mesh lifting operator to a relative residual of 1e-13,
+ * started from the extrapolation of the displacement history corrected by its
+ * projection onto up to 8 earlier lifting solutions) instead of scaling the
  * extension of a shape; lx_sim_set_ale_displacement switches back. */
 lx_status lx_sim_set_boundary_displacement(lx_sim *sim, const double *d);
 

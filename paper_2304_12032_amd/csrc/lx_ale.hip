@@ -96,8 +96,8 @@ template <bool VEC> constexpr int lift_lpr() { return VEC ? 8 : 4; }
 template <bool VEC> unsigned lift_blocks(int64_t nv) { return (unsigned)((nv * lift_lpr<VEC>() + 255) / 256); }
 template <bool VEC> unsigned lift_grid(int64_t nv) { return std::min<unsigned>(lift_blocks<VEC>(nv), kLiftBlocks); }
 
-// rhs: boundary rows d_B; interior rows -sum_{j in B} Lfull_ij d_B(j).  d0: initial
-// guess with boundary rows set.
+// rhs: boundary rows d_B; interior rows -sum_{j in B} Lfull_ij d_B(j).  d0 (may be
+// null): initial guess whose boundary rows are set to d_B.
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_ale_rhs(int64_t nv, LiftOp Afull, const int32_t *mark, const double *shape,
                                                  double scale, double *rhs, double *d0)
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_ale_rhs(int64_t nv, LiftOp Afull, const
         for (int c = 0; c < 3; ++c) {
             if (mark[row]) {
                 rhs[3 * row + c] = scale * shape[3 * row + c];
-                d0[3 * row + c] = scale * shape[3 * row + c];
+                if (d0) d0[3 * row + c] = scale * shape[3 * row + c];
             } else {
                 rhs[3 * row + c] = -y[c];
             }
@@ -381,6 +381,109 @@ __global__ void k_ale_mesh(int64_t nv, const double *xh, const double *ext, doub
     }
 }
 
+// ---- projection onto earlier lifting solutions (LXNS_LIFT_PROJ=0 at creation
+// turns it off)
+//
+// With nodal boundary data the lifting operator K stays the same from step to
+// step and only the right-hand side changes, so the earlier solutions span a
+// space where the new one nearly lies (exactly, for a motion that is a fixed
+// shape times a time law).  Following the projection method for successive
+// right-hand sides (Fischer, Comput. Methods Appl. Mech. Engrg. 163, 1998), the
+// committed solutions are kept K-orthonormalised (Q, [kProjMax][3 nv]) and the
+// CG starts from x0 = x_ext + Q Q^T (b - K x_ext): the extrapolated guess plus
+// its best correction within span(Q) in the energy norm, never a worse start
+// than x_ext.  All sums are per-workgroup partials finished in a fixed order.
+
+// partial[b][i] = sum over the block's entries of Q_i . v, i < nq
+__global__ __launch_bounds__(256) void k_proj_dots(int64_t n, const double *Q, int nq, const double *v,
+                                                   double *partial)
+{
+    __shared__ double lds[4 * kProjMax];
+    double acc[kProjMax];
+#pragma unroll
+    for (int i = 0; i < kProjMax; ++i) acc[i] = 0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const double vj = v[j];
+#pragma unroll
+        for (int i = 0; i < kProjMax; ++i)
+            if (i < nq) acc[i] += Q[i * n + j] * vj;
+    }
+    block_sum<kProjMax>(acc, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < kProjMax; ++i) partial[(int64_t)blockIdx.x * kProjMax + i] = acc[i];
+}
+
+// One workgroup: coef[i] = the sum of the partials of column i (fixed order).
+__global__ __launch_bounds__(256) void k_proj_coef(int nb, int nq, const double *partial, double *coef)
+{
+    __shared__ double lds[4 * kProjMax];
+    double tot[kProjMax];
+    reduce_partials<kProjMax>(partial, nb, nq, tot, lds);
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kProjMax; ++i) coef[i] = i < nq ? tot[i] : 0.0;
+}
+
+// x += sign sum_{i < nq} coef[i] Q_i
+__global__ __launch_bounds__(256) void k_proj_add(int64_t n, const double *Q, int nq, const double *coef,
+                                                  double sign, double *x)
+{
+    double c[kProjMax];
+#pragma unroll
+    for (int i = 0; i < kProjMax; ++i) c[i] = i < nq ? sign * coef[i] : 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        double a = 0;
+#pragma unroll
+        for (int i = 0; i < kProjMax; ++i)
+            if (i < nq) a += c[i] * Q[i * n + j];
+        x[j] += a;
+    }
+}
+
+// y = K w and partial sums of w . y (the three components together)
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_lift_apply_dot(int64_t nv, LiftOp A, const double *w, double *y,
+                                                        double *partial)
+{
+    constexpr int LPR = lift_lpr<VEC>(), RPB = 256 / LPR;
+    __shared__ double lds[4];
+    const int lane = threadIdx.x % LPR;
+    double acc[1] = {0};
+    for (int64_t row = xcd_block() * RPB + threadIdx.x / LPR; row < nv; row += (int64_t)gridDim.x * RPB) {
+        double yv[3];
+        lift_row<LPR, VEC>(row, lane, A, w, yv);
+        if (lane == 0)
+            for (int c = 0; c < 3; ++c) {
+                y[3 * row + c] = yv[c];
+                acc[0] += w[3 * row + c] * yv[c];
+            }
+    }
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc[0];
+}
+
+// One workgroup: the scale 1 / sqrt(w . K w) of the new basis vector, from
+// k_lift_apply_dot's partials (nb1 of them), written to coef[0]; 0 when the
+// energy of w is below 1e-16 of that of the solution d, d . b (column 0 of
+// k_proj_dots's nb2 partials): w is then rounding noise of a solution already
+// in the span, whose normalisation would break the basis' orthogonality.
+__global__ __launch_bounds__(256) void k_proj_norm(int nb1, const double *partial1, int nb2, const double *partial2,
+                                                   double *coef)
+{
+    __shared__ double lds[4 * kProjMax];
+    double wkw[1], db[kProjMax];
+    reduce_partials<1>(partial1, nb1, 1, wkw, lds);
+    reduce_partials<kProjMax>(partial2, nb2, 1, db, lds);
+    if (threadIdx.x == 0) coef[0] = wkw[0] > 1e-16 * db[0] && wkw[0] > 0 ? 1.0 / sqrt(wkw[0]) : 0.0;
+}
+
+__global__ void k_proj_scale(int64_t n, double *w, const double *coef)
+{
+    const double s = coef[0];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        w[j] *= s;
+}
+
 // ------------------------------------------------------------------ host side
 
 lx_status Sim::ale_setup()
@@ -487,15 +590,21 @@ lx_status Sim::ale_setup()
     ALLOC(d_dnew, sizeof(double) * 3 * nv);
     ALLOC(d_dbnd, sizeof(double) * 3 * nv);
     // reduction partials of the lifting CG (one row of 9 per workgroup of the row kernels)
-    ALLOC(d_cg_partial, sizeof(double) * 9 * std::max(kLiftBlocks, 1024));
+    // (also the projection's: w . K w in the first kLiftBlocks, d . b from kProjMax * 1024 on)
+    ALLOC(d_cg_partial, sizeof(double) * std::max(9 * std::max(kLiftBlocks, 1024), 2 * kProjMax * 1024));
+    // projection basis (earlier lifting solutions, K-orthonormal) and its coefficients
+    ALLOC(d_projQ, sizeof(double) * kProjMax * 3 * nv);
+    ALLOC(d_proj_coef, sizeof(double) * 2 * kProjMax);
 #undef ALLOC
     LX_HIP(hipMemcpyAsync(d_lap, Le.data(), sizeof(double) * Le.size(), hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_lapfull, L.data(), sizeof(double) * L.size(), hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_lapdinv, dinv.data(), sizeof(double) * dinv.size(), hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_ale_mark, mark.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemsetAsync(d_cg, 0, sizeof(double) * 3 * nv * 7 + sizeof(CgState), stream));
+    LX_HIP(hipMemsetAsync(d_projQ, 0, sizeof(double) * kProjMax * 3 * nv, stream));
     LX_HIP(hipStreamSynchronize(stream));
     ale_ext_valid = false;
+    proj_n = 0;
     return LX_OK;
 }
 
@@ -579,19 +688,40 @@ lx_status Sim::ale_extend(const double *data)
     const unsigned gvec = (unsigned)std::min<int64_t>((nv + 255) / 256, 1024);
     const LiftOp Afull{d_rowptr, d_col, d_lapfull, nblk}, A{d_rowptr, d_col, d_lap, nblk};
     double *part = d_cg_partial;   // gcg (or gvec) blocks * 9 doubles
-    if (lift_vec) {
+    auto init = [&](bool finish) {
+        if (lift_vec) {
+            hipLaunchKernelGGL(k_cg_init<true>, dim3(gcg), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z,
+                               pb[0], part);
+            if (finish)
+                hipLaunchKernelGGL(k_cg_init_fin<true>, dim3(1), dim3(256), 0, stream, (int)gcg, cst, part, 1e-13);
+        } else {
+            hipLaunchKernelGGL(k_cg_init<false>, dim3(gcg), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z,
+                               pb[0], part);
+            if (finish)
+                hipLaunchKernelGGL(k_cg_init_fin<false>, dim3(1), dim3(256), 0, stream, (int)gcg, cst, part,
+                                   1e-13);
+        }
+    };
+    // With a projection basis the extrapolated guess keeps its own boundary rows: it
+    // then lies in the span of the earlier solutions, and so does its error for a
+    // motion those solutions span (setting the rows to d_B would take it out).
+    const bool project = data && proj_n > 0 && lift_proj;
+    if (lift_vec)
         hipLaunchKernelGGL(k_ale_rhs<true>, dim3(grow), dim3(256), 0, stream, nv, Afull, d_ale_mark,
-                           data ? data : d_ale_shape, 1.0, rhs, ext);
-        hipLaunchKernelGGL(k_cg_init<true>, dim3(gcg), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z,
-                           pb[0], part);
-        hipLaunchKernelGGL(k_cg_init_fin<true>, dim3(1), dim3(256), 0, stream, (int)gcg, cst, part, 1e-13);
-    } else {
+                           data ? data : d_ale_shape, 1.0, rhs, project ? nullptr : ext);
+    else
         hipLaunchKernelGGL(k_ale_rhs<false>, dim3(grow), dim3(256), 0, stream, nv, Afull, d_ale_mark,
-                           data ? data : d_ale_shape, 1.0, rhs, ext);
-        hipLaunchKernelGGL(k_cg_init<false>, dim3(gcg), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z,
-                           pb[0], part);
-        hipLaunchKernelGGL(k_cg_init_fin<false>, dim3(1), dim3(256), 0, stream, (int)gcg, cst, part, 1e-13);
+                           data ? data : d_ale_shape, 1.0, rhs, project ? nullptr : ext);
+    if (project) {
+        // x0 = x_ext + Q Q^T (b - K x_ext)
+        const unsigned gp = (unsigned)std::min<int64_t>((3 * nv + 255) / 256, 1024);
+        init(false);
+        hipLaunchKernelGGL(k_proj_dots, dim3(gp), dim3(256), 0, stream, 3 * nv, d_projQ, proj_n, r, part);
+        hipLaunchKernelGGL(k_proj_coef, dim3(1), dim3(256), 0, stream, (int)gp, proj_n, part, d_proj_coef);
+        hipLaunchKernelGGL(k_proj_add, dim3(gp), dim3(256), 0, stream, 3 * nv, d_projQ, proj_n, d_proj_coef, 1.0,
+                           ext);
     }
+    init(true);
     auto batch = [&](hipStream_t s) {
         for (int k = 0; k < kLiftBatch; ++k) {
             const double *pold = pb[k & 1];
@@ -614,8 +744,9 @@ lx_status Sim::ale_extend(const double *data)
         if (h.done) break;
         if (it >= max_it) return fail(LX_ENOCONV, "ALE lifting CG did not converge");
     }
-    ale_iters = h.iters;
+    ale_iters += h.iters;
     ale_ext_valid = data == nullptr;
+    lift_solved = data != nullptr;
     return LX_OK;
 }
 
@@ -644,8 +775,41 @@ lx_status Sim::ale_update(double t1, const StepCoef &C)
     return LX_OK;
 }
 
+// Adds the step's lifting solution d (in d_cg, with its right-hand side b = K d)
+// to the projection basis: w = d - Q Q^T b (K-orthogonal to Q, since Q^T K d =
+// Q^T b), then w / sqrt(w . K w).  A full basis starts again from d alone.
+void Sim::ale_add_solution()
+{
+    const double *d = d_cg, *b = d_cg + 3 * nv;
+    double *tmp = d_cg + 15 * nv;   // the CG's product buffer, free after the solve
+    if (proj_n == kProjMax) proj_n = 0;
+    double *w = d_projQ + (int64_t)proj_n * 3 * nv;
+    const unsigned gp = (unsigned)std::min<int64_t>((3 * nv + 255) / 256, 1024);
+    double *part = d_cg_partial;
+    (void)hipMemcpyAsync(w, d, sizeof(double) * 3 * nv, hipMemcpyDeviceToDevice, stream);
+    if (proj_n > 0) {
+        hipLaunchKernelGGL(k_proj_dots, dim3(gp), dim3(256), 0, stream, 3 * nv, d_projQ, proj_n, b, part);
+        hipLaunchKernelGGL(k_proj_coef, dim3(1), dim3(256), 0, stream, (int)gp, proj_n, part, d_proj_coef);
+        hipLaunchKernelGGL(k_proj_add, dim3(gp), dim3(256), 0, stream, 3 * nv, d_projQ, proj_n, d_proj_coef, -1.0,
+                           w);
+    }
+    const LiftOp A{d_rowptr, d_col, d_lap, nblk};
+    const unsigned gcg = lift_vec ? lift_grid<true>(nv) : lift_grid<false>(nv);
+    double *part2 = part + kProjMax * 1024;   // d . b, after the kLiftBlocks partials of w . K w
+    hipLaunchKernelGGL(k_proj_dots, dim3(gp), dim3(256), 0, stream, 3 * nv, d, 1, b, part2);
+    if (lift_vec)
+        hipLaunchKernelGGL(k_lift_apply_dot<true>, dim3(gcg), dim3(256), 0, stream, nv, A, w, tmp, part);
+    else
+        hipLaunchKernelGGL(k_lift_apply_dot<false>, dim3(gcg), dim3(256), 0, stream, nv, A, w, tmp, part);
+    hipLaunchKernelGGL(k_proj_norm, dim3(1), dim3(256), 0, stream, (int)gcg, part, (int)gp, part2,
+                       d_proj_coef + kProjMax);
+    hipLaunchKernelGGL(k_proj_scale, dim3(gp), dim3(256), 0, stream, 3 * nv, w, d_proj_coef + kProjMax);
+    ++proj_n;
+}
+
 void Sim::ale_commit()
 {
+    if (ale_nodal && lift_solved && lift_proj) ale_add_solution();
     const int L = prob.bdf_order;
     double *oldest = d_dhist[L - 1];
     for (int l = L - 1; l > 0; --l) d_dhist[l] = d_dhist[l - 1];

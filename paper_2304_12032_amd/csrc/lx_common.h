@@ -14,6 +14,8 @@ namespace lx {
 constexpr int kMaxValves = 8;
 constexpr int kMaxBC = 16;
 constexpr int kMaxRestart = 64;
+// Earlier lifting solutions kept to project the next lifting's initial guess on.
+constexpr int kProjMax = 8;
 
 // Per-step scalar coefficients passed by value to the element kernels.
 struct StepCoef {

@@ -100,7 +100,13 @@ struct Sim {
     bool ale_ext_valid = false;
     double *d_dbnd = nullptr;                                    // [nv][3] nodal boundary displacement at t^{n+1}
     bool ale_nodal = false;                                      // lifting of d_dbnd solved every step
-    int ale_iters = 0;
+    int ale_iters = 0;                                           // CG iterations of the step's lifting solves
+    bool lift_solved = false;                                    // the step solved the lifting for nodal data
+    // projection of the lifting's initial guess onto earlier solutions (nodal data)
+    double *d_projQ = nullptr;                                   // [kProjMax][nv][3], K-orthonormal
+    double *d_proj_coef = nullptr;                               // [2 kProjMax]
+    int32_t proj_n = 0;                                          // vectors in use
+    bool lift_proj = true;                                       // LXNS_LIFT_PROJ=0: off
     // FP64 system
     double *d_val64 = nullptr, *d_rhs64 = nullptr, *d_Finv64 = nullptr, *d_Dinv64 = nullptr, *d_Sinv64 = nullptr;
     double *d_V64 = nullptr, *d_w64 = nullptr, *d_sw64 = nullptr, *d_Z64 = nullptr;
@@ -213,6 +219,7 @@ struct Sim {
     lx_status ale_extend(const double *data);
     lx_status ale_update(double t1, const StepCoef &C);
     void ale_commit();
+    void ale_add_solution();
 };
 
 }  // namespace lx

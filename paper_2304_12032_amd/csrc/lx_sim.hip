@@ -359,6 +359,8 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     {
         const char *ge = getenv("LXNS_GRAPH");
         use_graphs = !(ge && *ge == '0');
+        const char *lp = getenv("LXNS_LIFT_PROJ");
+        lift_proj = !(lp && *lp == '0');
         if (use_graphs) {
             LX_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
             g_step.assign(6 * kMaxRestart, nullptr);
@@ -1468,6 +1470,8 @@ lx_status Sim::step(lx_step_stats *out)
     memset(&S, 0, sizeof(S));
     const double t1 = t + prob.dt;
     const int L = prob.bdf_order;
+    ale_iters = 0;
+    lift_solved = false;
     LX_HIP(hipEventRecord(ev_step0, stream));
     StepCoef C;
     const bool overlap = stream_aux != nullptr;
@@ -1585,6 +1589,7 @@ lx_status Sim::step(lx_step_stats *out)
     S.t_step_ms = ms;
     S.t_assembly_ms = ma;
     S.t_solve_ms = ms - ma;
+    S.lift_iters = ale_iters;
     if (out) *out = S;
     if (!S.converged)
         return fail(LX_ENOCONV, "step did not converge: rel. residual %.3e after %d iterations", S.rel_residual,
@@ -1622,15 +1627,17 @@ struct CkHead {
     int32_t fe, bdf_order, precision, ale, forcing, n_bc, precond, f_degree;
     int32_t levels, nlev, nhist, x_order;
     int32_t f_warm, ale_ext_valid, fv_elem, ale_nodal;
+    int32_t proj_n, pad;
     double t;
     int64_t step_index;
 };
-const char kCkMagic[8] = {'L', 'X', 'N', 'S', 'C', 'K', '0', '1'};
+const char kCkMagic[8] = {'L', 'X', 'N', 'S', 'C', 'K', '0', '2'};
 }  // namespace
 
 // The blob: header, then the solution levels, the nodal Dirichlet values, per
 // nodal Neumann condition its flag and traction, the forcing, the ALE
-// displacement history, lifting and shape, and the power-iteration vector.
+// displacement history, lifting, shape and the lifting projection basis, and the
+// power-iteration vector.
 int64_t Sim::state_bytes() const
 {
     const int L = prob.bdf_order, Lh = std::max(L, 4);
@@ -1640,7 +1647,7 @@ int64_t Sim::state_bytes() const
     for (const auto &bc : bcs)
         if (bc.d_hnodal) b += 8 + 3 * nu * 8;
     if (d_f) b += 3 * nu * 8;
-    if (prob.ale) b += (int64_t)(L + 3) * 3 * nv * 8;
+    if (prob.ale) b += (int64_t)(L + 3 + kProjMax) * 3 * nv * 8;
     const bool f64 = solver.precision == LX_FP64;
     if (solver.precond == LX_PC_AMG && (f64 ? amg64.fv : (void *)amg32.fv))
         b += 4 * nu * (f64 ? 8 : 4) + kLamSlots * 8;   // the vector and the norm slots it is read with
@@ -1666,6 +1673,7 @@ lx_status Sim::save_state(void *blob, int64_t bytes)
     h.f_warm = fv ? (f64 ? amg64.f_warm : amg32.f_warm) : 0;
     h.ale_ext_valid = ale_ext_valid;
     h.ale_nodal = ale_nodal;
+    h.proj_n = proj_n;
     h.fv_elem = fv ? (f64 ? 8 : 4) : 0;
     h.t = t;
     h.step_index = step_index;
@@ -1698,6 +1706,7 @@ lx_status Sim::save_state(void *blob, int64_t bytes)
         CK(d2h(d_cg, 3 * nv * 8));
         CK(d2h(d_ale_shape, 3 * nv * 8));
         CK(d2h(d_dbnd, 3 * nv * 8));
+        CK(d2h(d_projQ, kProjMax * 3 * nv * 8));
     }
     if (fv) {
         CK(d2h(fv, 4 * nu * h.fv_elem));
@@ -1724,7 +1733,8 @@ lx_status Sim::load_state(const void *blob, int64_t bytes)
         h.n_bc != (int32_t)bcs.size() || h.precond != solver.precond || h.f_degree != solver.f_degree ||
         h.levels != Lh || h.fv_elem != (fv ? (f64 ? 8 : 4) : 0))
         return fail(LX_EINVAL, "state blob was saved by a simulation of another mesh, problem or solver");
-    if (h.nlev < 0 || h.nlev > L || h.nhist < 0 || h.nhist > Lh || h.x_order < 2 || h.x_order > 4)
+    if (h.nlev < 0 || h.nlev > L || h.nhist < 0 || h.nhist > Lh || h.x_order < 2 || h.x_order > 4 ||
+        h.proj_n < 0 || h.proj_n > kProjMax)
         return fail(LX_EINVAL, "state blob holds invalid counters");
     LX_HIP(hipSetDevice(device));
     const char *o = (const char *)blob + sizeof(h);
@@ -1756,8 +1766,10 @@ lx_status Sim::load_state(const void *blob, int64_t bytes)
         CK(h2d(d_cg, 3 * nv * 8));
         CK(h2d(d_ale_shape, 3 * nv * 8));
         CK(h2d(d_dbnd, 3 * nv * 8));
+        CK(h2d(d_projQ, kProjMax * 3 * nv * 8));
         ale_ext_valid = h.ale_ext_valid != 0;
         ale_nodal = h.ale_nodal != 0;
+        proj_n = h.proj_n;
     }
     if (fv) {
         CK(h2d(fv, 4 * nu * h.fv_elem));

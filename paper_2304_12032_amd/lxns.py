@@ -117,7 +117,7 @@ class lx_step_stats(ctypes.Structure):
     _fields_ = [("gmres_iters", c_i32), ("ir_iters", c_i32), ("restarts", c_i32), ("converged", c_i32),
                 ("rel_residual", c_dbl), ("t_step_ms", c_dbl), ("t_assembly_ms", c_dbl), ("t_solve_ms", c_dbl),
                 ("spmv_ms", c_dbl), ("spmv_calls", c_i64), ("asm_ms", c_dbl), ("asm_calls", c_i64),
-                ("resid_ms", c_dbl), ("resid_calls", c_i64), ("newton_iters", c_i32), ("pad", c_i32)]
+                ("resid_ms", c_dbl), ("resid_calls", c_i64), ("newton_iters", c_i32), ("lift_iters", c_i32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
