@@ -41,17 +41,12 @@ struct LiftOp {
     int64_t nblk;
 };
 
-// y = K x at one row.  DIR: x = z + beta p_old, the CG direction formed on the fly
-// from the preconditioned residual and the previous direction (x = z, p = p_old).
-template <int LPR, bool VEC, bool DIR = false>
-__device__ inline void lift_row(int64_t row, int lane, const LiftOp &A, const double *x, double y[3],
-                                const double *p = nullptr, const double *beta = nullptr)
+template <int LPR, bool VEC>
+__device__ inline void lift_row(int64_t row, int lane, const LiftOp &A, const double *x, double y[3])
 {
     y[0] = y[1] = y[2] = 0;
     for (int32_t k = A.rowptr[row] + lane; k < A.rowptr[row + 1]; k += LPR) {
-        const int64_t j = 3 * (int64_t)A.col[k];
-        double xj[3];
-        for (int c = 0; c < 3; ++c) xj[c] = DIR ? x[j + c] + beta[c] * p[j + c] : x[j + c];
+        const double *xj = x + 3 * (int64_t)A.col[k];
         if (VEC) {
             for (int c = 0; c < 3; ++c)
                 for (int d = 0; d < 3; ++d) y[c] += A.K[(int64_t)(3 * c + d) * A.nblk + k] * xj[d];
@@ -87,12 +82,12 @@ __device__ inline void lift_combine(double (&tot)[K], int first)
 
 // Lanes per row of the lifting products: a scalar (harmonic) row has one value per
 // neighbour, so four lanes share a row and each walks about four neighbours with
-// independent loads; a 3x3-block (elastic) row has nine, and takes eight lanes.
+// independent loads; a 3x3-block (elastic) row has nine, and takes sixteen lanes.
 // The CG's row passes (k_cg_init, k_cg_ap) stride over the rows with at most
 // kLiftBlocks workgroups, so that the one-workgroup kernels finishing their dot
 // products add at most that many partial sums.
 constexpr int kLiftBlocks = 2048;
-template <bool VEC> constexpr int lift_lpr() { return VEC ? 8 : 4; }
+template <bool VEC> constexpr int lift_lpr() { return VEC ? 16 : 4; }
 template <bool VEC> unsigned lift_blocks(int64_t nv) { return (unsigned)((nv * lift_lpr<VEC>() + 255) / 256); }
 template <bool VEC> unsigned lift_grid(int64_t nv) { return std::min<unsigned>(lift_blocks<VEC>(nv), kLiftBlocks); }
 
@@ -181,7 +176,6 @@ __global__ __launch_bounds__(256) void k_cg_init_fin(int nb, CgState *st, const 
             st->rz[c] = tot[c];
             st->rr[c] = tot[3 + c];
             st->tol2[c] = rtol * rtol * tot[6 + c];
-            st->beta[c] = 0.0;   // the first direction is z (k_cg_init also stores it as p_old)
             if (st->rr[c] > st->tol2[c]) done = false;
         }
         st->done = done ? 1 : 0;
@@ -190,27 +184,23 @@ __global__ __launch_bounds__(256) void k_cg_init_fin(int nb, CgState *st, const 
     }
 }
 
-// p = z + beta p_old (written to pn; p_old stays for the rows still gathering it),
-// q = L p, partial sums of p.q for alpha = rz / (p.q)
+// q = K p, and partial sums of p.q for alpha = rz / (p.q)
 template <bool VEC>
-__global__ __launch_bounds__(256) void k_cg_ap(int64_t nv, LiftOp A, const double *z, const double *pold, double *pn,
-                                               double *q, CgState *st, double *partial)
+__global__ __launch_bounds__(256) void k_cg_ap(int64_t nv, LiftOp A, const double *p, double *q, CgState *st,
+                                               double *partial)
 {
     if (st->done) return;
     constexpr int LPR = lift_lpr<VEC>(), RPB = 256 / LPR;
     __shared__ double lds[4 * 3];
-    const double beta[3] = {st->beta[0], st->beta[1], st->beta[2]};
     const int lane = threadIdx.x % LPR;
     double acc[3] = {0, 0, 0};
     for (int64_t row = xcd_block() * RPB + threadIdx.x / LPR; row < nv; row += (int64_t)gridDim.x * RPB) {
         double y[3];
-        lift_row<LPR, VEC, true>(row, lane, A, z, y, pold, beta);
+        lift_row<LPR, VEC>(row, lane, A, p, y);
         if (lane == 0)
             for (int c = 0; c < 3; ++c) {
-                const double pc = z[3 * row + c] + beta[c] * pold[3 * row + c];
-                pn[3 * row + c] = pc;
                 q[3 * row + c] = y[c];
-                acc[c] += pc * y[c];
+                acc[c] += p[3 * row + c] * y[c];
             }
     }
     block_sum<3>(acc, lds);
@@ -284,6 +274,15 @@ __global__ __launch_bounds__(256) void k_cg_update_fin(int nb, CgState *st, cons
         st->iters += 1;
         st->counter = 0;
     }
+}
+
+// p = z + beta p
+__global__ void k_cg_dir(int64_t nv, const double *z, double *p, const CgState *st)
+{
+    if (st->done) return;
+    const double b[3] = {st->beta[0], st->beta[1], st->beta[2]};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x)
+        for (int c = 0; c < 3; ++c) p[3 * i + c] = z[3 * i + c] + b[c] * p[3 * i + c];
 }
 
 // Distance from p to triangle (a, b, c): the closest point is found from the
@@ -586,7 +585,7 @@ lx_status Sim::ale_setup()
     ALLOC(d_lapfull, sizeof(double) * np * nblk);
     ALLOC(d_lapdinv, sizeof(double) * np * nv);
     ALLOC(d_ale_mark, sizeof(int32_t) * nv);
-    ALLOC(d_cg, sizeof(double) * 3 * nv * 7 + sizeof(CgState));
+    ALLOC(d_cg, sizeof(double) * 3 * nv * 6 + sizeof(CgState));
     ALLOC(d_dnew, sizeof(double) * 3 * nv);
     ALLOC(d_dbnd, sizeof(double) * 3 * nv);
     // reduction partials of the lifting CG (one row of 9 per workgroup of the row kernels)
@@ -600,7 +599,7 @@ lx_status Sim::ale_setup()
     LX_HIP(hipMemcpyAsync(d_lapfull, L.data(), sizeof(double) * L.size(), hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_lapdinv, dinv.data(), sizeof(double) * dinv.size(), hipMemcpyHostToDevice, stream));
     LX_HIP(hipMemcpyAsync(d_ale_mark, mark.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, stream));
-    LX_HIP(hipMemsetAsync(d_cg, 0, sizeof(double) * 3 * nv * 7 + sizeof(CgState), stream));
+    LX_HIP(hipMemsetAsync(d_cg, 0, sizeof(double) * 3 * nv * 6 + sizeof(CgState), stream));
     LX_HIP(hipMemsetAsync(d_projQ, 0, sizeof(double) * kProjMax * 3 * nv, stream));
     LX_HIP(hipStreamSynchronize(stream));
     ale_ext_valid = false;
@@ -663,26 +662,25 @@ lx_status Sim::ale_boundary_distance(std::vector<double> &dist)
 
 // Lifting into d_cg[ext] (CG to rtol 1e-13): of the shape D^ (data = nullptr),
 // or of nodal boundary data starting from the guess already in ext.  The
-// directions alternate between two buffers (k_cg_ap forms the next one from the
-// previous); the iterations run in batches of kLiftBatch, with the host reading
-// the state after each batch.
-constexpr int kLiftBatch = 24;   // even: each batch ends on the buffer it started from
+// iterations run in batches of kLiftBatch, with the host reading the state after
+// each batch.
+constexpr int kLiftBatch = 25;
 template <bool VEC>
 static void lift_iteration(int64_t nv, const LiftOp &A, const double *dinv, double *ext, double *r, double *z,
-                           const double *pold, double *pn, double *q, CgState *cst, double *part, unsigned gcg,
-                           unsigned gvec, hipStream_t s)
+                           double *p, double *q, CgState *cst, double *part, unsigned gcg, unsigned gvec, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cg_ap<VEC>, dim3(gcg), dim3(256), 0, s, nv, A, z, pold, pn, q, cst, part);
+    hipLaunchKernelGGL(k_cg_ap<VEC>, dim3(gcg), dim3(256), 0, s, nv, A, p, q, cst, part);
     hipLaunchKernelGGL(k_cg_ap_fin<VEC>, dim3(1), dim3(256), 0, s, (int)gcg, cst, part);
-    hipLaunchKernelGGL(k_cg_update<VEC>, dim3(gvec), dim3(256), 0, s, nv, dinv, pn, q, ext, r, z, cst, part);
+    hipLaunchKernelGGL(k_cg_update<VEC>, dim3(gvec), dim3(256), 0, s, nv, dinv, p, q, ext, r, z, cst, part);
     hipLaunchKernelGGL(k_cg_update_fin<VEC>, dim3(1), dim3(256), 0, s, (int)gvec, cst, part);
+    hipLaunchKernelGGL(k_cg_dir, dim3(gvec), dim3(256), 0, s, nv, z, p, cst);
 }
 
 lx_status Sim::ale_extend(const double *data)
 {
-    double *ext = d_cg, *rhs = d_cg + 3 * nv, *r = d_cg + 6 * nv, *z = d_cg + 9 * nv, *q = d_cg + 15 * nv;
-    double *pb[2] = {d_cg + 12 * nv, d_cg + 18 * nv};
-    CgState *cst = (CgState *)(d_cg + 21 * nv);
+    double *ext = d_cg, *rhs = d_cg + 3 * nv, *r = d_cg + 6 * nv, *z = d_cg + 9 * nv, *p = d_cg + 12 * nv,
+           *q = d_cg + 15 * nv;
+    CgState *cst = (CgState *)(d_cg + 18 * nv);
     const unsigned grow = lift_vec ? lift_blocks<true>(nv) : lift_blocks<false>(nv);   // k_ale_rhs
     const unsigned gcg = lift_vec ? lift_grid<true>(nv) : lift_grid<false>(nv);        // CG row passes
     const unsigned gvec = (unsigned)std::min<int64_t>((nv + 255) / 256, 1024);
@@ -690,13 +688,13 @@ lx_status Sim::ale_extend(const double *data)
     double *part = d_cg_partial;   // gcg (or gvec) blocks * 9 doubles
     auto init = [&](bool finish) {
         if (lift_vec) {
-            hipLaunchKernelGGL(k_cg_init<true>, dim3(gcg), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z,
-                               pb[0], part);
+            hipLaunchKernelGGL(k_cg_init<true>, dim3(gcg), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z, p,
+                               part);
             if (finish)
                 hipLaunchKernelGGL(k_cg_init_fin<true>, dim3(1), dim3(256), 0, stream, (int)gcg, cst, part, 1e-13);
         } else {
-            hipLaunchKernelGGL(k_cg_init<false>, dim3(gcg), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z,
-                               pb[0], part);
+            hipLaunchKernelGGL(k_cg_init<false>, dim3(gcg), dim3(256), 0, stream, nv, A, d_lapdinv, rhs, ext, r, z, p,
+                               part);
             if (finish)
                 hipLaunchKernelGGL(k_cg_init_fin<false>, dim3(1), dim3(256), 0, stream, (int)gcg, cst, part,
                                    1e-13);
@@ -724,12 +722,10 @@ lx_status Sim::ale_extend(const double *data)
     init(true);
     auto batch = [&](hipStream_t s) {
         for (int k = 0; k < kLiftBatch; ++k) {
-            const double *pold = pb[k & 1];
-            double *pn = pb[(k + 1) & 1];
             if (lift_vec)
-                lift_iteration<true>(nv, A, d_lapdinv, ext, r, z, pold, pn, q, cst, part, gcg, gvec, s);
+                lift_iteration<true>(nv, A, d_lapdinv, ext, r, z, p, q, cst, part, gcg, gvec, s);
             else
-                lift_iteration<false>(nv, A, d_lapdinv, ext, r, z, pold, pn, q, cst, part, gcg, gvec, s);
+                lift_iteration<false>(nv, A, d_lapdinv, ext, r, z, p, q, cst, part, gcg, gvec, s);
         }
     };
     CgState h;

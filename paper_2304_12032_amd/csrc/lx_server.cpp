@@ -107,7 +107,7 @@ int64_t estimate_footprint(const Request &r)
         b += nv * s * 9;                      // Schur Chebyshev work
     if (r.solver.precision != LX_FP64) b += N * (8 * 2 + 4 * 2) + nt * lx::kRRec * 8;
     if (r.problem.ale)   // lifting: stiffness as assembled and eliminated (9 planes when elastic), CG work
-        b += nv * 8 * 3 * (13 + lx::kProjMax) + nblk * 16 * (r.problem.lifting == LX_LIFT_ELASTIC ? 9 : 1) +
+        b += nv * 8 * 3 * (12 + lx::kProjMax) + nblk * 16 * (r.problem.lifting == LX_LIFT_ELASTIC ? 9 : 1) +
              (r.problem.lifting == LX_LIFT_ELASTIC ? nv * 72 : 0);
     return b + (1 << 20);
 }

@@ -95,7 +95,7 @@ struct Sim {
     std::vector<int32_t> h_ale_faces;                            // [n][3] faces with the ALE tags
     int32_t *d_ale_nodes = nullptr;
     int32_t *d_ale_mark = nullptr;                               // [nv] 1 on ALE boundary
-    double *d_cg = nullptr;                                      // CG work: 7 vectors [nv][3] + state
+    double *d_cg = nullptr;                                      // CG work: 6 vectors [nv][3] + state
     double *d_cg_partial = nullptr;
     bool ale_ext_valid = false;
     double *d_dbnd = nullptr;                                    // [nv][3] nodal boundary displacement at t^{n+1}
