@@ -95,6 +95,9 @@ struct TailLayout {
 // [0, kAmgMaxLevels) Gershgorin bounds of diag(A_l)^{-1} A_l, kLamF the
 // Chebyshev bound of F~^{-1} F, kNormA/kNormB the power-iteration norms.
 constexpr int kLamF = kAmgMaxLevels, kNormA = kAmgMaxLevels + 1, kNormB = kAmgMaxLevels + 2, kLamSlots = 16;
+// Most lanes per row any row kernel of the preconditioner runs with (LXNS_LPR and
+// LXNS_AMG_LPR accept 4..32): sizes the per-workgroup partial sums (Amg::partial).
+constexpr int kMaxRowLanes = 32;
 
 template <typename T>
 struct Amg {

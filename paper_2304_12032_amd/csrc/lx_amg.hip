@@ -1415,6 +1415,7 @@ static int block_lpr(const RowPattern &P)
         const int x = e ? atoi(e) : 0;
         return (x == 4 || x == 8 || x == 16 || x == 32) ? x : 0;
     }();
+    static_assert(kMaxRowLanes >= 32, "Amg::partial is sized for kMaxRowLanes lanes per row");
     if (env) return env;
     return P.nblk >= 20 * P.nv ? 16 : 8;
 }

@@ -553,7 +553,9 @@ lx_status Sim::setup_amg(Amg<T> &A)
     A.cycle_coarse = solver.amg_coarse_cycle;
     const char *env = getenv("LXNS_AMG_LPR");
     const int lpr_env = env ? atoi(env) : 0;
-    int64_t maxgrid = (nu * 16 + 255) / 256;
+    // the power iterations on F run with block_lpr lanes per row (up to kMaxRowLanes) and
+    // write one partial sum per workgroup into A.partial
+    int64_t maxgrid = (nu * kMaxRowLanes + 255) / 256;
     auto up = [&](int32_t *&d, const std::vector<int32_t> &h) -> lx_status {
         lx_status s = dalloc((void **)&d, sizeof(int32_t) * std::max<size_t>(h.size(), 1));
         if (s != LX_OK) return s;
