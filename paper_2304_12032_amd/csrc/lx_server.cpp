@@ -113,7 +113,7 @@ int64_t estimate_footprint(const Request &r)
 }
 
 // Host threads that set up admitted simulations concurrently.
-constexpr int kSetupThreads = 4;
+constexpr int kSetupThreads = 8;
 
 }  // namespace
 
