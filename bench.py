@@ -89,7 +89,7 @@ def parse():
                          "t0 = 0.25 s: resistance + backflow outlet, elastic lifting with boundary stiffening "
                          "solved every step, and the fully implicit formulation with Newton; one JSON line")
     ap.add_argument("--features-steps", type=int, default=5)
-    ap.add_argument("--features-only", default="plain,outflow,lifting,implicit",
+    ap.add_argument("--features-only", default="plain,outflow,lifting,implicit,implicit_fp32",
                     help="comma-separated subset of the --features configurations")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy 256 MiB device-to-device twice (a plain copy kernel of known "
@@ -512,13 +512,17 @@ def features(args, torch):
         elif kind == "implicit":
             prob.implicit = True
             sv = SolverCfg(precision="fp64", rtol=1e-8, ir_rtol=1e-8, max_ir=20, max_iters=20000)
+        elif kind == "implicit_fp32":
+            prob.implicit = True
+            sv = SolverCfg(precision="fp32_ir", rtol=1e-8, ir_rtol=1e-8, max_ir=20, max_iters=20000)
         return prob, sv
 
     out = {"metric": "adjacent features: ms/step on the 983k-tet tube from the Poiseuille field (t0 = 0.25 s)",
            "unit": "ms/step", "n_gpus": 1, "data": "synthetic", "steps": args.features_steps, "warmup": 1,
            "config": {"workload": "tube R=1 L=10, %d tets, N=%d, P1-P1 VMS-LES BDF2 dt=1e-3, RIIS disc" %
                                   (mesh.nt, 4 * mesh.nv)}}
-    for kind in [k for k in ("plain", "outflow", "lifting", "implicit") if k in args.features_only.split(",")]:
+    for kind in [k for k in ("plain", "outflow", "lifting", "implicit", "implicit_fp32")
+                 if k in args.features_only.split(",")]:
         prob, sv = make(kind)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -549,7 +553,7 @@ def features(args, torch):
              "max_rel_residual": float(max(s_["rel_residual"] for s_ in stats)), "precision": sv.precision}
         if kind == "lifting":
             r["lift_cg_iters_per_step"] = float(np.mean([s_["lift_iters"] for s_ in stats]))
-        if kind == "implicit":
+        if kind in ("implicit", "implicit_fp32"):
             r["newton_iters_per_step"] = float(np.mean([s_["newton_iters"] for s_ in stats]))
         if kind == "outflow":
             q_, pint, area = sim.boundary_integrals(2)

@@ -179,11 +179,13 @@ typedef struct {
                                 linear solve per step); 0: the fully implicit
                                 formulation (u* = u^{n+1} - u_ALE, implicit LES term,
                                 Sec. 2.3) solved by Newton's method with the consistent
-                                Jacobian (Sec. 2.4): P1-P1, LX_FP64, no resistance or
-                                backflow terms; lx_solver.max_ir caps the Newton
-                                updates and ir_rtol is their tolerance (||R|| <= ir_rtol
-                                ||R_0||, or an update below ir_rtol ||x||); rtol is each
-                                update's linear tolerance                           */
+                                Jacobian (Sec. 2.4): P1-P1, no resistance or backflow
+                                terms; lx_solver.max_ir caps the Newton updates and
+                                ir_rtol is their tolerance (||R|| <= ir_rtol ||R_0||,
+                                or an update below ir_rtol ||x||); rtol is each
+                                update's linear tolerance.  LX_FP32_IR: the FP64
+                                Jacobian and residual rounded, each update solved in
+                                FP32 (to no tighter than inner_rtol)               */
     int32_t ale;             /* 0 | 1                                                */
     int32_t forcing;         /* 0: f = 0; 1: nodal f from lx_sim_set_forcing        */
     int32_t n_bc;

@@ -278,7 +278,8 @@ extern "C" lx_status lx_sim_debug_export(lx_sim *s, int32_t *brow, int32_t *bcol
     if (st != LX_OK) return st;
     const int64_t nb = s->nblk;
     std::vector<double> planes(16 * nb);
-    if (s->solver.precision == LX_FP64) {
+    const bool f64 = s->solver.precision == LX_FP64 || !s->prob.semi_implicit;   // the Newton system is FP64
+    if (f64) {
         LX_HIP(hipMemcpyAsync(planes.data(), s->d_val64, sizeof(double) * 16 * nb, hipMemcpyDeviceToHost, s->stream));
     } else {
         std::vector<float> p32(16 * nb);
@@ -287,7 +288,7 @@ extern "C" lx_status lx_sim_debug_export(lx_sim *s, int32_t *brow, int32_t *bcol
         for (int64_t i = 0; i < 16 * nb; ++i) planes[i] = p32[i];
     }
     std::vector<double> r(4 * s->nv, 0.0);
-    if (s->solver.precision == LX_FP64)
+    if (f64)
         LX_HIP(hipMemcpyAsync(r.data(), s->d_rhs64, sizeof(double) * r.size(), hipMemcpyDeviceToHost, s->stream));
     LX_HIP(hipStreamSynchronize(s->stream));
     for (int64_t i = 0; i < s->nv; ++i) {

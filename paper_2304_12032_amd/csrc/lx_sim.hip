@@ -107,7 +107,6 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     if (pr->semi_implicit != 0 && pr->semi_implicit != 1) return fail(LX_EINVAL, "semi_implicit must be 0 or 1");
     if (pr->semi_implicit == 0) {
         if (pr->fe != LX_P1P1) return fail(LX_EINVAL, "the implicit formulation is built for the P1-P1 pair");
-        if (sv->precision != LX_FP64) return fail(LX_EINVAL, "the implicit formulation runs in FP64 (LX_FP64)");
         for (int i = 0; i < pr->n_bc; ++i)
             if (pr->bc[i].type == LX_BC_RESISTANCE || pr->bc[i].backflow > 0)
                 return fail(LX_EINVAL, "the implicit formulation is built without resistance or backflow terms");
@@ -397,6 +396,11 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         ALLOC(d_nrec, sizeof(double) * kNewtonRec * nt);
         ALLOC(d_dx, sizeof(double) * N);
         ALLOC(d_gdelta, sizeof(double) * 3 * std::max<int64_t>(n_dir, 1));
+        if (solver.precision != LX_FP64) {
+            // FP32 updates: the Newton system is still formed in FP64, then rounded
+            ALLOC(d_val64, sizeof(double) * kPlanes * nblk);
+            ALLOC(d_rhs64, sizeof(double) * N);
+        }
     }
     if (solver.precision == LX_FP64) {
         if (!p2) ALLOC(d_val64, sizeof(double) * kPlanes * nblk);
@@ -414,7 +418,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
         ALLOC(d_Dinv32, sizeof(float) * 3 * nu);
         ALLOC(d_Sinv32, sizeof(float) * nv);
         ALLOC(d_V32, sizeof(float) * N * (m + 1));
-        if (solver.asm_fp64 && !p2) ALLOC(d_val64, sizeof(double) * kPlanes * nblk);
+        if (solver.asm_fp64 && !p2 && !d_val64) ALLOC(d_val64, sizeof(double) * kPlanes * nblk);
         ALLOC(d_Z32, sizeof(float) * N * m);
         ALLOC(d_sw32, sizeof(float) * 9 * nv);
         ALLOC(d_w32, sizeof(float) * N);
@@ -1426,7 +1430,11 @@ lx_status Sim::newton(double t1, const StepCoef &C, lx_step_stats &S)
         newton_system(t1, C);
         launch_norm<double>(N, d_rhs64, d_st, 0.0, d_partial, 1, stream);
         if (it > 0) {
-            launch_norm<double>(N, d_dx, d_st, 0.0, d_partial, 2, stream);
+            // the last update: FP64 in d_dx, or FP32 in d_x32
+            if (solver.precision == LX_FP64)
+                launch_norm<double>(N, d_dx, d_st, 0.0, d_partial, 2, stream);
+            else
+                launch_norm<float>(N, d_x32, d_st, 0.0, d_partial, 2, stream);
             launch_norm<double>(N, d_xs, d_st, 0.0, d_partial, 3, stream);
         }
         lx_status st = read_state();
@@ -1441,22 +1449,41 @@ lx_status Sim::newton(double t1, const StepCoef &C, lx_step_stats &S)
             break;
         }
         if (it >= solver.max_ir || total >= solver.max_iters) break;
-        launch_simple_setup<double>(P, d_val64, d_Finv64, d_Dinv64, solver.precond == LX_PC_AMG ? nullptr : d_Sinv64,
-                                    stream);
-        if (solver.precond == LX_PC_AMG)
-            launch_amg_setup<double>(view<double>(), d_Finv64, d_Dinv64, amg64, stream);
-        else if (solver.schur_degree > 0)
-            launch_schur_bound<double>(P, d_val64, d_Dinv64, d_Sinv64, d_sw64, d_st, d_partial, nb_red, stream);
         // each update to rtol, but no tighter than the Newton test needs: a residual already near
         // ir_rtol ||R_0|| is solved only to a tenth of that level (inexact Newton), so that the
         // linear tolerance never falls below what the Jacobian's conditioning allows
         const double lin = std::min(0.5, std::max(solver.rtol, 0.1 * solver.ir_rtol * r0 / rn));
         GmResult gr;
-        st = gmres<double>(d_rhs64, d_dx, true, lin, solver.max_iters - total, gr, S);
-        if (st != LX_OK) return st;
+        if (solver.precision == LX_FP64) {
+            launch_simple_setup<double>(P, d_val64, d_Finv64, d_Dinv64,
+                                        solver.precond == LX_PC_AMG ? nullptr : d_Sinv64, stream);
+            if (solver.precond == LX_PC_AMG)
+                launch_amg_setup<double>(view<double>(), d_Finv64, d_Dinv64, amg64, stream);
+            else if (solver.schur_degree > 0)
+                launch_schur_bound<double>(P, d_val64, d_Dinv64, d_Sinv64, d_sw64, d_st, d_partial, nb_red, stream);
+            st = gmres<double>(d_rhs64, d_dx, true, lin, solver.max_iters - total, gr, S);
+            if (st != LX_OK) return st;
+            launch_axpy<double, double>(N, d_xs, d_dx, nullptr, 1.0, stream);
+        } else {
+            // FP32 update: the FP64 Jacobian and -R rounded, the preconditioner and GMRES in
+            // FP32 (to no tighter than inner_rtol, what FP32 sums resolve), the update added
+            // to the FP64 iterate; the FP64 residual of the next iterate decides, as in
+            // iterative refinement
+            launch_scale_copy<float, double>(kPlanes * nblk, d_val32, d_val64, 1.0, stream);
+            launch_scale_copy<float, double>(N, d_r32, d_rhs64, 1.0, stream);
+            launch_simple_setup<float>(P, d_val32, d_Finv32, d_Dinv32,
+                                       solver.precond == LX_PC_AMG ? nullptr : d_Sinv32, stream);
+            if (solver.precond == LX_PC_AMG)
+                launch_amg_setup<float>(view<float>(), d_Finv32, d_Dinv32, amg32, stream);
+            else if (solver.schur_degree > 0)
+                launch_schur_bound<float>(P, d_val32, d_Dinv32, d_Sinv32, d_sw32, d_st, d_partial, nb_red, stream);
+            st = gmres<float>(d_r32, d_x32, true, std::max(lin, solver.inner_rtol), solver.max_iters - total, gr, S,
+                              true, std::min(it + 1, 7));
+            if (st != LX_OK) return st;
+            launch_axpy<double, float>(N, d_xs, d_x32, nullptr, 1.0, stream);
+        }
         total += gr.iters;
         S.restarts += gr.restarts;
-        launch_axpy<double, double>(N, d_xs, d_dx, nullptr, 1.0, stream);
     }
     S.gmres_iters = total;
     S.newton_iters = it;

@@ -195,10 +195,10 @@ def test_bad_lifting_parameters_rejected(what):
     assert ei.value.status == -1
 
 
-@pytest.mark.parametrize("what", ["fp32", "p2", "resistance"])
+@pytest.mark.parametrize("what", ["p2", "resistance"])
 def test_implicit_unsupported_options_rejected(what):
-    """The implicit formulation runs P1-P1 in FP64 without outflow terms; anything else is
-    rejected during validation."""
+    """The implicit formulation runs P1-P1 (FP64 or FP32 updates) without outflow terms;
+    anything else is rejected during validation."""
     from paper_2304_12032_amd import LxError
     from inputs.meshes import TUBE_TAGS
     from inputs.problem import Boundary, Profile, TimeLaw
@@ -206,9 +206,7 @@ def test_implicit_unsupported_options_rejected(what):
     prob = tube_problem(m, valve=False)
     prob.implicit = True
     sv = SolverCfg()
-    if what == "fp32":
-        sv.precision = "fp32_ir"
-    elif what == "p2":
+    if what == "p2":
         prob.fe = "p2p1"
     else:
         prob.bcs[2] = Boundary("resistance", (TUBE_TAGS["outlet"],), law=TimeLaw("constant", (0.0,)),

@@ -3,7 +3,7 @@ term) and its Newton's method, against the oracle: the Newton system (Jacobian b
 forward-mode dual numbers on the device, by the complex step in the oracle, both exact
 to rounding) at a given state, row-wise <= 1e-12 and its right-hand side -R <= 1e-12;
 and three implicit steps (device Newton to 1e-13 with each update solved to 1e-14,
-oracle Newton with dense solves) <= 1e-10 for u and p."""
+oracle Newton with dense solves) <= 1e-10 for u and p; with FP32 updates <= 1e-8."""
 import numpy as np
 import pytest
 
@@ -35,9 +35,9 @@ CASES = [lambda: _implicit(tube_valve(4, 8)),
 IDS = ["tube_vms_valve", "tube_supg_symgrad_bdf3_forcing", "tube_galerkin_bdf1", "beltrami4", "tube_ale"]
 
 
-def _gpu(case, stream, rtol=1e-14, newton_rtol=1e-13):
+def _gpu(case, stream, rtol=1e-14, newton_rtol=1e-13, precision="fp64"):
     from paper_2304_12032_amd import Sim
-    sv = SolverCfg(precision="fp64", rtol=rtol, ir_rtol=newton_rtol, max_ir=20, max_iters=50000)
+    sv = SolverCfg(precision=precision, rtol=rtol, ir_rtol=newton_rtol, max_ir=20, max_iters=50000)
     return Sim(case.mesh, case.prob, sv, device=0, stream=stream)
 
 
@@ -71,9 +71,14 @@ STEP_IDS = [IDS[0], IDS[1], IDS[3], IDS[4], "tube_vms_from_rest"]
 
 
 @pytest.mark.parametrize("mk", STEP_CASES, ids=STEP_IDS)
-def test_implicit_steps_parity(mk, stream):
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_implicit_steps_parity(mk, precision, stream):
+    """FP64: Newton to 1e-13, u and p <= 1e-10.  FP32 updates (the FP64 Jacobian and
+    residual rounded, each update to inner_rtol): Newton to 1e-12, <= 1e-8, the bar of
+    the refined FP32 semi-implicit steps."""
     case = mk()
-    g = _gpu(case, stream)
+    f64 = precision == "fp64"
+    g = _gpu(case, stream, precision=precision, newton_rtol=1e-13 if f64 else 1e-12)
     o = OracleSim(case.mesh, case.prob, solve="dense")
     for s in (g, o):
         case.init(s)
@@ -85,8 +90,10 @@ def test_implicit_steps_parity(mk, stream):
         uo, po = o.step_implicit(newton_rtol=1e-13)
         ug, pg, _ = g.solution()
         eu, ep = rel_l2(ug, uo), rel_l2(pg, po)
-        print(case.name, "step", k, "newton", st["newton_iters"], "(oracle %d)" % (len(o.newton_norms) - 1),
-              "gmres", st["gmres_iters"], "err u %.2e p %.2e" % (eu, ep), flush=True)
-        assert 1 <= st["newton_iters"] <= 10
-        assert eu < 1e-10 and ep < 1e-10, (eu, ep)
+        print(case.name, precision, "step", k, "newton", st["newton_iters"],
+              "(oracle %d)" % (len(o.newton_norms) - 1), "gmres", st["gmres_iters"],
+              "err u %.2e p %.2e" % (eu, ep), flush=True)
+        assert 1 <= st["newton_iters"] <= (10 if f64 else 16)
+        tol = 1e-10 if f64 else 1e-8
+        assert eu < tol and ep < tol, (eu, ep)
     g.close()
