@@ -179,8 +179,10 @@ typedef struct {
                                 linear solve per step); 0: the fully implicit
                                 formulation (u* = u^{n+1} - u_ALE, implicit LES term,
                                 Sec. 2.3) solved by Newton's method with the consistent
-                                Jacobian (Sec. 2.4): P1-P1, no resistance or backflow
-                                terms; lx_solver.max_ir caps the Newton updates and
+                                Jacobian (Sec. 2.4): P1-P1 (resistance and backflow
+                                terms join the Jacobian as in the semi-implicit
+                                system, the backflow coefficient at u_EXT);
+                                lx_solver.max_ir caps the Newton updates and
                                 ir_rtol is their tolerance (||R|| <= ir_rtol ||R_0||,
                                 or an update below ir_rtol ||x||); rtol is each
                                 update's linear tolerance.  LX_FP32_IR: the FP64

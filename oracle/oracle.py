@@ -564,11 +564,41 @@ class OracleSim:
                 h = np.broadcast_to(-hv * np.asarray(b.profile.normal, float), (self.nv, 3))
             L.orc_neumann_p1(self.nv, len(faces), _p(np.ascontiguousarray(x)), _p(faces),
                              _p(np.ascontiguousarray(h, dtype=np.float64)), _p(self.rhs))
+        # outflow conditions, both linear in u^{n+1} (the backflow coefficient is taken at
+        # u_EXT, as in the semi-implicit system): the backflow matrix Bf and the resistance
+        # term C_R w_row w^T join the Jacobian, and -R gains b_out - (Bf + C_R w_row w^T) x
+        self.rank1 = []
+        skip = np.ascontiguousarray((self.owner >= 0).astype(np.int8))
+        xu = np.concatenate([u.reshape(-1), p])
+        uE = self._combo(self.u_hist, gamma)
+        for i, b in enumerate(prob.bcs):
+            if b.type not in ("neumann", "resistance"):
+                continue
+            faces = self.bc_faces(i)
+            dirv = np.ascontiguousarray(b.profile.normal, dtype=np.float64)
+            xc = np.ascontiguousarray(x)
+            if b.backflow > 0.0:
+                bf = np.zeros_like(self.val)
+                L.orc_backflow_p1(len(faces), _p(xc), _p(faces), _p(dirv), _p(np.ascontiguousarray(uE)),
+                                  0.5 * b.backflow * prob.rho, _p(skip), _p(self.rowptr), _p(self.col), _p(bf))
+                self.val += bf
+                from scipy.sparse import csr_matrix
+                N = 4 * self.nv
+                self.rhs -= csr_matrix((bf, self.col.copy(), self.rowptr.copy()), shape=(N, N)) @ xu
+            if b.type == "resistance":
+                w = np.zeros(3 * self.nv)
+                L.orc_flux_weights(len(faces), _p(xc), _p(faces), _p(dirv), _p(w))
+                w_row = w.reshape(self.nv, 3).copy()
+                w_row[self.owner >= 0] = 0.0
+                w_row = w_row.reshape(-1)
+                p0 = b.theta * time_law(b.law, t1)
+                self.rhs[:3 * self.nv] += w_row * (-p0 + b.resistance * float(w @ uA.reshape(-1)) -
+                                                   b.resistance * float(w @ u.reshape(-1)))
+                self.rank1.append((b.resistance, w_row, w))
         rows, gvals = self.dirichlet_rows(t1, x, uA)
         cur = np.concatenate([u.reshape(-1), p])[rows]
         L.orc_dirichlet_rows(len(rows), _p(rows), _p(np.ascontiguousarray(gvals - cur)), _p(self.rowptr),
                              _p(self.col), _p(self.val), _p(self.rhs))
-        self.rank1 = []
         return t1
 
     def step_implicit(self, newton_rtol=1e-12, max_newton=30, x0=None):
@@ -576,8 +606,6 @@ class OracleSim:
         the previous solution); the updates are solved directly.  Stops when ||R|| <=
         newton_rtol ||R_0|| or the last update is below newton_rtol ||x||.  Records the
         nonlinear residual norms in self.newton_norms."""
-        if any(b.type == "resistance" or b.backflow > 0 for b in self.prob.bcs):
-            raise ValueError("the implicit formulation is built without outflow terms")
         nv = self.nv
         x = np.concatenate([self.u_hist[0].reshape(-1), self.p_hist[0]]) if x0 is None else np.array(x0, float)
         self._newton_t1 = None

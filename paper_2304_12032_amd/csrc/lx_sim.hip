@@ -107,9 +107,6 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     if (pr->semi_implicit != 0 && pr->semi_implicit != 1) return fail(LX_EINVAL, "semi_implicit must be 0 or 1");
     if (pr->semi_implicit == 0) {
         if (pr->fe != LX_P1P1) return fail(LX_EINVAL, "the implicit formulation is built for the P1-P1 pair");
-        for (int i = 0; i < pr->n_bc; ++i)
-            if (pr->bc[i].type == LX_BC_RESISTANCE || pr->bc[i].backflow > 0)
-                return fail(LX_EINVAL, "the implicit formulation is built without resistance or backflow terms");
         if (sv->max_ir < 1) return fail(LX_EINVAL, "implicit formulation: max_ir (Newton updates) must be >= 1");
     }
     if (pr->n_riis < 0 || pr->n_riis > kMaxValves) return fail(LX_EINVAL, "at most %d RIIS surfaces", kMaxValves);
@@ -516,7 +513,9 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
             const char *e = getenv("LXNS_OVERLAP");
             return !(e && strcmp(e, "0") == 0);
         }();
-        if (overlap && !p2 && solver.precision != LX_FP64 && !solver.asm_fp64 && nt >= (1 << 19)) {
+        // (the implicit formulation forms its systems in the Newton loop: nothing to overlap)
+        if (overlap && prob.semi_implicit && !p2 && solver.precision != LX_FP64 && !solver.asm_fp64 &&
+            nt >= (1 << 19)) {
             LX_HIP(hipStreamCreateWithFlags(&stream_aux, hipStreamNonBlocking));
             LX_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
             LX_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
@@ -1416,6 +1415,13 @@ void Sim::newton_system(double t1, const StepCoef &C)
     launch_newton_p1(A, C, stream);
     timer_end(tm);
     add_neumann(t1, d_rhs64, nullptr);
+    // outflow terms are linear in the new state (the backflow coefficient is taken at
+    // u_EXT): the backflow block joins the Jacobian, -R gains the resistance data minus
+    // (backflow + C_R w w^T) xs; the rank-1 part of the Jacobian is applied in the product
+    for (const OutflowDev &o : outflow) {
+        launch_backflow_add<double>(o, nblk, d_val64, stream);
+        launch_outflow_residual(o, outflow_p0(o, t1), prob.ale ? d_uA : nullptr, d_xs, d_rhs64, nullptr, stream);
+    }
     launch_dirichlet_delta(n_dir, d_dir_node, d_g, d_xs, d_gdelta, stream);
     launch_dirichlet_rows<double>(n_dir, d_dir_node, d_gdelta, P, d_val64, d_rhs64, stream);
 }

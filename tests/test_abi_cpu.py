@@ -195,13 +195,11 @@ def test_bad_lifting_parameters_rejected(what):
     assert ei.value.status == -1
 
 
-@pytest.mark.parametrize("what", ["p2", "resistance"])
+@pytest.mark.parametrize("what", ["p2", "no_newton_updates"])
 def test_implicit_unsupported_options_rejected(what):
-    """The implicit formulation runs P1-P1 (FP64 or FP32 updates) without outflow terms;
-    anything else is rejected during validation."""
+    """The implicit formulation runs P1-P1 (FP64 or FP32 updates, outflow terms included)
+    with at least one Newton update; anything else is rejected during validation."""
     from paper_2304_12032_amd import LxError
-    from inputs.meshes import TUBE_TAGS
-    from inputs.problem import Boundary, Profile, TimeLaw
     m = tube(nxy=3, nz=4, length=1.0)
     prob = tube_problem(m, valve=False)
     prob.implicit = True
@@ -209,8 +207,7 @@ def test_implicit_unsupported_options_rejected(what):
     if what == "p2":
         prob.fe = "p2p1"
     else:
-        prob.bcs[2] = Boundary("resistance", (TUBE_TAGS["outlet"],), law=TimeLaw("constant", (0.0,)),
-                               profile=Profile("uniform", normal=(0.0, 0.0, 1.0)), resistance=10.0)
+        sv.max_ir = 0
     with pytest.raises(LxError) as ei:
         _create(m, prob, sv)
     assert ei.value.status == -1

@@ -1,7 +1,9 @@
 """Device parity for the fully implicit formulation (u* = u^{n+1} - u_ALE, implicit LES
 term) and its Newton's method, against the oracle: the Newton system (Jacobian by
 forward-mode dual numbers on the device, by the complex step in the oracle, both exact
-to rounding) at a given state, row-wise <= 1e-12 and its right-hand side -R <= 1e-12;
+to rounding) at a given state, row-wise <= 1e-12 and its right-hand side -R <= 1e-12
+(outflow conditions included: the backflow block in the planes, the rank-1 resistance
+term applied beside them and left out of the export);
 and three implicit steps (device Newton to 1e-13 with each update solved to 1e-14,
 oracle Newton with dense solves) <= 1e-10 for u and p; with FP32 updates <= 1e-8."""
 import numpy as np
@@ -9,7 +11,8 @@ import pytest
 
 from inputs.problem import SolverCfg
 from oracle import OracleSim
-from tests._cases import beltrami, tube_valve, tube_ale, oracle_matrix_from_blocks, rowwise_rel_err, rel_l2
+from tests._cases import (beltrami, tube_valve, tube_ale, tube_outflow, oracle_matrix_from_blocks, rowwise_rel_err,
+                          rel_l2)
 
 pytestmark = pytest.mark.gpu
 
@@ -31,8 +34,11 @@ CASES = [lambda: _implicit(tube_valve(4, 8)),
          lambda: _implicit(tube_valve(6, 10, bdf=3, stab="supg_pspg", diffusion="symgrad", forcing=True)),
          lambda: _implicit(tube_valve(4, 8, bdf=1, stab="none")),
          lambda: _implicit(beltrami(4)),
-         lambda: _implicit(tube_ale())]
-IDS = ["tube_vms_valve", "tube_supg_symgrad_bdf3_forcing", "tube_galerkin_bdf1", "beltrami4", "tube_ale"]
+         lambda: _implicit(tube_ale()),
+         lambda: _implicit(tube_outflow(kind="resistance", cr=40.0, beta=1.0, ale=True)),
+         lambda: _implicit(tube_outflow(kind="neumann", cr=0.0, beta=2.0, p0=1.0))]
+IDS = ["tube_vms_valve", "tube_supg_symgrad_bdf3_forcing", "tube_galerkin_bdf1", "beltrami4", "tube_ale",
+       "tube_resistance_backflow_ale", "tube_neumann_backflow"]
 
 
 def _gpu(case, stream, rtol=1e-14, newton_rtol=1e-13, precision="fp64"):
@@ -65,9 +71,9 @@ def test_newton_system_parity(mk, stream):
 # pressure modes (the oracle's dense Jacobian is singular from rest), and at the large random
 # states of these cases its velocity block is indefinite, which stalls the SIMPLE-preconditioned
 # GMRES (its Chebyshev velocity block assumes a positive spectrum).
-STEP_CASES = [CASES[0], CASES[1], CASES[3], CASES[4],
+STEP_CASES = [CASES[0], CASES[1], CASES[3], CASES[4], CASES[5], CASES[6],
               lambda: _implicit(tube_valve(4, 8, random_hist=False))]
-STEP_IDS = [IDS[0], IDS[1], IDS[3], IDS[4], "tube_vms_from_rest"]
+STEP_IDS = [IDS[0], IDS[1], IDS[3], IDS[4], IDS[5], IDS[6], "tube_vms_from_rest"]
 
 
 @pytest.mark.parametrize("mk", STEP_CASES, ids=STEP_IDS)

@@ -116,3 +116,81 @@ def test_newton_converges_quadratically():
     C = [n[k + 1] / n[k] ** 2 for k in range(1, len(n) - 1) if n[k + 1] > 1e-14]
     assert len(C) >= 2
     assert all(C[k + 1] <= 10.0 * C[k] for k in range(len(C) - 1)), C
+
+
+def _outflow_sims(ale, stab):
+    from tests._cases import tube_outflow
+    case = tube_outflow(nxy=3, nz=5, kind="resistance", cr=40.0, beta=1.0, ale=ale)
+    case.prob.stab = stab
+    semi = OracleSim(case.mesh, case.prob, solve="dense")
+    case.prob.implicit = True
+    impl = OracleSim(case.mesh, case.prob, solve="dense")
+    for s in (semi, impl):
+        case.init(s)
+    return case, semi, impl
+
+
+@pytest.mark.parametrize("ale", [False, True])
+def test_outflow_residual_equals_semi_implicit_system_at_the_extrapolated_state(ale):
+    """Resistance (C_R w w^T, data -p0 + C_R w . u_ALE) and backflow (coefficient at u_EXT)
+    are linear in the new state, so at (u_EXT, p_EXT) the implicit -R is b - A x of the
+    semi-implicit system with its rank-1 term, on every row that is not a Dirichlet row
+    (those hold a_ii (g_i - x_i) with each formulation's own diagonal)."""
+    case, semi, impl = _outflow_sims(ale, "vms_les")
+    order, alpha, beta, gamma = semi._coeffs()
+    uE, pE = semi._combo(semi.u_hist, gamma), semi._combo(semi.p_hist, gamma)
+    semi.assemble()
+    x = np.concatenate([uE.reshape(-1), pE])
+    ref = semi.rhs - semi.matrix() @ x
+    impl.newton_system(uE, pE)
+    free = np.ones(len(x), bool)
+    free[semi.dir_rows] = False
+    # the outflow terms are a visible part of these rows
+    rows = np.zeros(len(x), bool)
+    for i, b in enumerate(case.prob.bcs):
+        if b.type == "resistance":
+            rows[:3 * semi.nv] |= np.repeat(np.isin(np.arange(semi.nv), semi.bc_faces(i).reshape(-1)), 3)
+    out = (semi.matrix() - semi.matrix(rank1=False)) @ x
+    assert np.abs(out[rows & free]).max() > 1e-3 * np.abs(ref[rows & free]).max()
+    err = np.abs(impl.rhs - ref)[free].max()
+    assert err < 1e-11 * np.abs(ref).max(), err
+
+
+@pytest.mark.parametrize("stab", ["none", "vms_les"])
+def test_outflow_jacobian_against_differences_of_the_residual(stab):
+    """The assembled Jacobian with the outflow terms (backflow block, C_R w_row w^T) is
+    the derivative of -R: without stabilisation R is quadratic and the central second
+    difference is exact (to rounding); with VMS-LES central differences to O(h^2).
+    Rows of Dirichlet vertices are left out (their diagonal moves with the state)."""
+    case, _, o = _outflow_sims(True, stab)
+    r = np.random.default_rng(3)
+    nv = o.nv
+    x = np.concatenate([o.u_hist[0].reshape(-1), o.p_hist[0]]) + r.normal(size=4 * nv)
+    o.newton_system(x[:3 * nv].reshape(nv, 3), x[3 * nv:])
+    J = o.matrix()
+    rows, _ = o.dirichlet_rows(o._newton_t1, o.x_next, o.uA)
+    free = np.ones(4 * nv, bool)
+    free[rows] = False
+
+    def mR(y):
+        o.newton_system(y[:3 * nv].reshape(nv, 3), y[3 * nv:])
+        return o.rhs.copy()
+
+    h = 1.0 if stab == "none" else 1e-6
+    for _ in range(3):
+        v = r.normal(size=4 * nv)
+        d = -(mR(x + h * v) - mR(x - h * v)) / (2 * h)
+        Jv = J @ v
+        tol = (1e-11 if stab == "none" else 1e-6) * np.abs(Jv).max()
+        assert np.abs(d - Jv)[free].max() < tol
+
+
+def test_newton_converges_with_outflow_terms():
+    """A VMS-LES tube with a resistance outlet, backflow and ALE: Newton's method with
+    the outflow terms in the Jacobian still converges quadratically, to 1e-12."""
+    case, _, o = _outflow_sims(True, "vms_les")
+    o.step_implicit(newton_rtol=1e-12)
+    n = np.array(o.newton_norms) / o.newton_norms[0]
+    assert n[-1] <= 1e-12 and len(n) <= 7, n
+    C = [n[k + 1] / n[k] ** 2 for k in range(1, len(n) - 1) if n[k + 1] > 1e-14]
+    assert all(C[k + 1] <= 10.0 * C[k] for k in range(len(C) - 1)), C
