@@ -343,6 +343,58 @@ __global__ __launch_bounds__(256) void k_element_p1(AsmArgs<T> A, StepCoef C)
     }
 }
 
+// What one (block, element) pair reads from the element's record.
+template <typename T, bool RHS>
+struct SlotIn {
+    typename V4<T>::type Da, Db, Eb, G1, G2, Rh;
+    T Xab;
+    int64_t e;
+    int a, b;
+};
+
+template <typename T, bool RHS>
+__device__ __forceinline__ void slot_load(const T *__restrict__ rec, int32_t code, SlotIn<T, RHS> &s)
+{
+    using V = typename V4<T>::type;
+    s.e = code >> 4;
+    s.a = (code >> 2) & 3;
+    s.b = code & 3;
+    const V *R = reinterpret_cast<const V *>(rec + s.e * kRec);
+    s.Da = R[kRD / 4 + s.a];
+    s.Db = R[kRD / 4 + s.b];
+    s.Eb = R[kRE / 4 + s.b];
+    s.Xab = rec[s.e * kRec + kRX + 4 * s.a + s.b];
+    s.G1 = R[kRG1 / 4];
+    s.G2 = R[kRG2 / 4];
+    if (RHS && s.a == s.b) s.Rh = R[kRRhs / 4 + s.a];
+}
+
+template <typename T, bool RHS>
+__device__ __forceinline__ void slot_add(const SlotIn<T, RHS> &s, int symgrad, T acc[16], T racc[4])
+{
+    const T da[3] = {s.Da.v[0], s.Da.v[1], s.Da.v[2]}, db[3] = {s.Db.v[0], s.Db.v[1], s.Db.v[2]};
+    const T Yb[3] = {s.Eb.v[0], s.Eb.v[1], s.Eb.v[2]}, W[3] = {s.G1.v[0], s.G1.v[1], s.G1.v[2]};
+    const T Xab = s.Xab, Za = s.Da.v[3], Sb = s.Eb.v[3];
+    const T TC = s.G1.v[3], TM = s.G2.v[0], w1 = s.G2.v[2];
+    const T mv = symgrad ? s.G2.v[1] : T(0);
+    const T gab = da[0] * db[0] + da[1] * db[1] + da[2] * db[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            T F = da[d] * Yb[c] + TC * da[c] * db[d] + mv * db[c] * da[d];
+            if (c == d) F += Xab;
+            acc[3 * c + d] += F;
+        }
+        acc[9 + c] += -w1 * da[c] + db[c] * Za + gab * W[c];
+        acc[12 + c] += w1 * db[c] + da[c] * Sb;
+    }
+    acc[15] += TM * gab;
+    if (RHS && s.a == s.b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) racc[c] += s.Rh.v[c];
+}
+
 // Slot pass: every block (i, j) of the pattern sums, in the fixed order of its
 // incidence list, the 4x4 block (a, b) of each element containing the edge
 // (i, j), expanded from the element's record:
@@ -352,6 +404,9 @@ __global__ __launch_bounds__(256) void k_element_p1(AsmArgs<T> A, StepCoef C)
 //   C    = (sum tau_M w) (dphi_a . dphi_b)
 // Sums run in T (the assembly precision) and each plane entry is written once (no atomics).  With
 // RHS, the diagonal slot of vertex i also gathers the vertex's right-hand side.
+// The list is walked two elements at a time with the next two codes loaded ahead, so that a
+// lane keeps two records' loads and the following codes in flight instead of one
+// code-then-record round trip per element; the sum order is the list order all the same.
 template <typename T, bool RHS>
 __global__ __launch_bounds__(256) void k_gather_p1(AsmArgs<T> A, int symgrad)
 {
@@ -361,44 +416,41 @@ __global__ __launch_bounds__(256) void k_gather_p1(AsmArgs<T> A, int symgrad)
 #pragma unroll
     for (int p = 0; p < 16; ++p) acc[p] = 0;
     T racc[4] = {0, 0, 0, 0};
-    int32_t vrow = -1;
-    for (int32_t q = A.sinc_ptr[k]; q < A.sinc_ptr[k + 1]; ++q) {
-        const int32_t code = A.sinc[q];
-        const int64_t e = code >> 4;
-        const int a = (code >> 2) & 3, b = code & 3;
-        using V = typename V4<T>::type;
-        const V *R = reinterpret_cast<const V *>(A.rec + e * kRec);
-        const V Da = R[kRD / 4 + a], Db = R[kRD / 4 + b], Eb = R[kRE / 4 + b], Xa = R[kRX / 4 + a];
-        const V G1 = R[kRG1 / 4], G2 = R[kRG2 / 4];
-        const T da[3] = {Da.v[0], Da.v[1], Da.v[2]}, db[3] = {Db.v[0], Db.v[1], Db.v[2]};
-        const T Yb[3] = {Eb.v[0], Eb.v[1], Eb.v[2]}, W[3] = {G1.v[0], G1.v[1], G1.v[2]};
-        const T Xab = Xa.v[b], Za = Da.v[3], Sb = Eb.v[3];
-        const T TC = G1.v[3], TM = G2.v[0], w1 = G2.v[2];
-        const T mv = symgrad ? G2.v[1] : T(0);
-        const T gab = da[0] * db[0] + da[1] * db[1] + da[2] * db[2];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                T F = da[d] * Yb[c] + TC * da[c] * db[d] + mv * db[c] * da[d];
-                if (c == d) F += Xab;
-                acc[3 * c + d] += F;
-            }
-            acc[9 + c] += -w1 * da[c] + db[c] * Za + gab * W[c];
-            acc[12 + c] += w1 * db[c] + da[c] * Sb;
+    int64_t ediag = -1;
+    int adiag = 0;
+    const int32_t q1 = A.sinc_ptr[k + 1];
+    int32_t q = A.sinc_ptr[k];
+    int32_t c0 = q < q1 ? A.sinc[q] : 0, c1 = q + 1 < q1 ? A.sinc[q + 1] : 0;
+    for (; q + 1 < q1; q += 2) {
+        // the next two codes, unconditionally (clamped to the list's last entry, whose value is
+        // then unused), so that no branch joins the loads and their wait moves to the next trip
+        const int32_t n0 = A.sinc[min(q + 2, q1 - 1)], n1 = A.sinc[min(q + 3, q1 - 1)];
+        SlotIn<T, RHS> s0, s1;
+        slot_load<T, RHS>(A.rec, c0, s0);
+        slot_load<T, RHS>(A.rec, c1, s1);
+        __builtin_amdgcn_sched_barrier(0);   // both records' loads issue before any arithmetic
+        slot_add<T, RHS>(s0, symgrad, acc, racc);
+        slot_add<T, RHS>(s1, symgrad, acc, racc);
+        if (RHS && s1.a == s1.b) {
+            ediag = s1.e;
+            adiag = s1.a;
         }
-        acc[15] += TM * gab;
-        if (RHS && a == b) {
-            const V Rh = R[kRRhs / 4 + a];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) racc[c] += Rh.v[c];
-            vrow = A.tet[(int64_t)a * A.nt + e];
+        c0 = n0;
+        c1 = n1;
+    }
+    if (q < q1) {
+        SlotIn<T, RHS> s0;
+        slot_load<T, RHS>(A.rec, c0, s0);
+        slot_add<T, RHS>(s0, symgrad, acc, racc);
+        if (RHS && s0.a == s0.b) {
+            ediag = s0.e;
+            adiag = s0.a;
         }
     }
 #pragma unroll
     for (int p = 0; p < 16; ++p) A.val[(int64_t)p * A.nblk + k] = (T)acc[p];
-    if (RHS && vrow >= 0) {
-        T *r = A.rhs + 4 * (int64_t)vrow;
+    if (RHS && ediag >= 0) {
+        T *r = A.rhs + 4 * A.tet[(int64_t)adiag * A.nt + ediag];
 #pragma unroll
         for (int c = 0; c < 4; ++c) r[c] = (T)racc[c];
     }
