@@ -12,7 +12,8 @@ namespace lx {
 constexpr int kPlanes = 16;
 
 // Per-element record written by the element pass of the P1 assembly and read
-// by the slot gather (kRec values of T per element).
+// by the slot gather (kRec values of T per element in all: the records, then
+// the elements' right-hand side blocks).
 constexpr int kRec = 72;
 
 template <typename T>
@@ -20,7 +21,7 @@ struct AsmArgs {
     int64_t nt, nblk;
     const int32_t *tet;    // [4][nt]
     const int32_t *sinc_ptr, *sinc;   // slot incidence (codes 16 e + 4a + b)
-    T *rec;                // [nt][kRec] element records
+    T *rec;                // [kRec nt] element records and right-hand side blocks
     const double *x;       // [nv][3] current coordinates
     const double *xh;      // [nv][3] reference coordinates
     const double *h0, *h1, *h2;  // history levels [nv][4]

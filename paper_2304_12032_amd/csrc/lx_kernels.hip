@@ -224,20 +224,22 @@ __device__ inline void eval_qp(const Elem<T> &E, int q, const StepCoef &C, QP<T>
 // ------------------------------------------------------------------ assembly
 
 // Record layout: groups of four values, so that the slot gather reads each with
-// one vector load (offsets into the kRec values of an element):
+// one vector load (offsets into the kRStride values of an element):
 //   D_v = (grad phi_v, Z_v), E_v = (Y_v, S_v), X_v = (X_v0 .. X_v3) with
 //   X_ab = X_ab + mu|K| grad phi_a . grad phi_b, G1 = (W, sum w tau_C),
-//   G2 = (sum w tau_M, mu|K|, |K|/4, 0), then the right-hand side (u_x, u_y, u_z, p)
-//   of each vertex.
+//   G2 = (sum w tau_M, mu|K|, |K|/4, 0).  The right-hand side (u_x, u_y, u_z, p) of
+//   each vertex ([4][4] per element) follows all nt records, so that the records the
+//   gather revisits for the element's other vertex rows are as small as they can be
+//   and more of them stay in a die's L2 meanwhile.
 enum : int {
-    kRD = 0,      // D_v [4][4]
-    kRE = 16,     // E_v [4][4]
-    kRX = 32,     // X_v [4][4]
-    kRG1 = 48,    // W[3], sum w tau_C
-    kRG2 = 52,    // sum w tau_M, mu|K|, |K|/4, 0
-    kRRhs = 56    // right-hand side [4][4]
+    kRD = 0,        // D_v [4][4]
+    kRE = 16,       // E_v [4][4]
+    kRX = 32,       // X_v [4][4]
+    kRG1 = 48,      // W[3], sum w tau_C
+    kRG2 = 52,      // sum w tau_M, mu|K|, |K|/4, 0
+    kRStride = 56   // values per record; the right-hand side block starts at nt kRStride
 };
-static_assert(kRRhs + 16 <= kRec, "element record too small");
+static_assert(kRStride + 16 <= kRec, "element record too small");
 
 // Element pass of the assembly: one thread per element evaluates the quadrature
 // moments and writes the element's record.
@@ -306,7 +308,7 @@ __global__ __launch_bounds__(256) void k_element_p1(AsmArgs<T> A, StepCoef C)
         }
     }
     const T mv = (T)C.mu * E.vol;
-    T *R = A.rec + (int64_t)e * kRec;
+    T *R = A.rec + (int64_t)e * kRStride;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
@@ -332,13 +334,14 @@ __global__ __launch_bounds__(256) void k_element_p1(AsmArgs<T> A, StepCoef C)
     R[kRG2 + 2] = E.vol * T(0.25);   // integral of one basis function
     R[kRG2 + 3] = T(0);
     if (RHS) {
+        T *Rr = A.rec + (int64_t)A.nt * kRStride + 16 * e;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                R[kRRhs + 4 * a + c] = KP[a][c] + KW[c][0] * E.dphi[a][0] + KW[c][1] * E.dphi[a][1] +
-                                       KW[c][2] * E.dphi[a][2];
-            R[kRRhs + 4 * a + 3] = KT[0] * E.dphi[a][0] + KT[1] * E.dphi[a][1] + KT[2] * E.dphi[a][2];
+                Rr[4 * a + c] = KP[a][c] + KW[c][0] * E.dphi[a][0] + KW[c][1] * E.dphi[a][1] +
+                                KW[c][2] * E.dphi[a][2];
+            Rr[4 * a + 3] = KT[0] * E.dphi[a][0] + KT[1] * E.dphi[a][1] + KT[2] * E.dphi[a][2];
         }
     }
 }
@@ -353,20 +356,21 @@ struct SlotIn {
 };
 
 template <typename T, bool RHS>
-__device__ __forceinline__ void slot_load(const T *__restrict__ rec, int32_t code, SlotIn<T, RHS> &s)
+__device__ __forceinline__ void slot_load(const T *__restrict__ rec, const T *__restrict__ rhs, int32_t code,
+                                          SlotIn<T, RHS> &s)
 {
     using V = typename V4<T>::type;
     s.e = code >> 4;
     s.a = (code >> 2) & 3;
     s.b = code & 3;
-    const V *R = reinterpret_cast<const V *>(rec + s.e * kRec);
+    const V *R = reinterpret_cast<const V *>(rec + s.e * kRStride);
     s.Da = R[kRD / 4 + s.a];
     s.Db = R[kRD / 4 + s.b];
     s.Eb = R[kRE / 4 + s.b];
-    s.Xab = rec[s.e * kRec + kRX + 4 * s.a + s.b];
+    s.Xab = rec[s.e * kRStride + kRX + 4 * s.a + s.b];
     s.G1 = R[kRG1 / 4];
     s.G2 = R[kRG2 / 4];
-    if (RHS && s.a == s.b) s.Rh = R[kRRhs / 4 + s.a];
+    if (RHS && s.a == s.b) s.Rh = reinterpret_cast<const V *>(rhs + 16 * s.e)[s.a];
 }
 
 template <typename T, bool RHS>
@@ -418,6 +422,7 @@ __global__ __launch_bounds__(256) void k_gather_p1(AsmArgs<T> A, int symgrad)
     T racc[4] = {0, 0, 0, 0};
     int64_t ediag = -1;
     int adiag = 0;
+    const T *rhs = A.rec + (int64_t)A.nt * kRStride;
     const int32_t q1 = A.sinc_ptr[k + 1];
     int32_t q = A.sinc_ptr[k];
     int32_t c0 = q < q1 ? A.sinc[q] : 0, c1 = q + 1 < q1 ? A.sinc[q + 1] : 0;
@@ -426,8 +431,8 @@ __global__ __launch_bounds__(256) void k_gather_p1(AsmArgs<T> A, int symgrad)
         // then unused), so that no branch joins the loads and their wait moves to the next trip
         const int32_t n0 = A.sinc[min(q + 2, q1 - 1)], n1 = A.sinc[min(q + 3, q1 - 1)];
         SlotIn<T, RHS> s0, s1;
-        slot_load<T, RHS>(A.rec, c0, s0);
-        slot_load<T, RHS>(A.rec, c1, s1);
+        slot_load<T, RHS>(A.rec, rhs, c0, s0);
+        slot_load<T, RHS>(A.rec, rhs, c1, s1);
         __builtin_amdgcn_sched_barrier(0);   // both records' loads issue before any arithmetic
         slot_add<T, RHS>(s0, symgrad, acc, racc);
         slot_add<T, RHS>(s1, symgrad, acc, racc);
@@ -440,15 +445,16 @@ __global__ __launch_bounds__(256) void k_gather_p1(AsmArgs<T> A, int symgrad)
     }
     if (q < q1) {
         SlotIn<T, RHS> s0;
-        slot_load<T, RHS>(A.rec, c0, s0);
+        slot_load<T, RHS>(A.rec, rhs, c0, s0);
         slot_add<T, RHS>(s0, symgrad, acc, racc);
         if (RHS && s0.a == s0.b) {
             ediag = s0.e;
             adiag = s0.a;
         }
     }
+    // the planes are read by later kernels only: streaming stores leave the L2 to the records
 #pragma unroll
-    for (int p = 0; p < 16; ++p) A.val[(int64_t)p * A.nblk + k] = (T)acc[p];
+    for (int p = 0; p < 16; ++p) __builtin_nontemporal_store(acc[p], A.val + (int64_t)p * A.nblk + k);
     if (RHS && ediag >= 0) {
         T *r = A.rhs + 4 * A.tet[(int64_t)adiag * A.nt + ediag];
 #pragma unroll
