@@ -141,6 +141,10 @@ struct Sim {
     // residual of the initial guess runs while the FP32 system is assembled
     hipStream_t stream_aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // the norms of b and of the guess's residual, formed on the second stream behind the
+    // residual (partial sums of their own) and copied to pinned memory, so that the host
+    // has them while the set-up still runs on the first
+    double *d_partial_aux = nullptr, *h_norms0 = nullptr;
     // convergence checks inside an Arnoldi cycle: the done flag copied to pinned
     // host memory behind an event, one check in flight (ping-pong slots)
     int32_t *h_flag = nullptr;

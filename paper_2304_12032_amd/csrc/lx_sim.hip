@@ -73,6 +73,7 @@ Sim::~Sim()
     if (h_st) (void)hipHostFree(h_st);
     if (h_flag) (void)hipHostFree(h_flag);
     if (h_gerr) (void)hipHostFree(h_gerr);
+    if (h_norms0) (void)hipHostFree(h_norms0);
     for (auto &ev : ev_chk)
         if (ev) (void)hipEventDestroy(ev);
     for (auto &ev : ev_pool) {
@@ -519,6 +520,9 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
             LX_HIP(hipStreamCreateWithFlags(&stream_aux, hipStreamNonBlocking));
             LX_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
             LX_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+            const lx_status as = dalloc((void **)&d_partial_aux, sizeof(double) * gm_partial_size(N));
+            if (as != LX_OK) return as;
+            LX_HIP(hipHostMalloc((void **)&h_norms0, 2 * sizeof(double), hipHostMallocDefault));
         }
     }
     LX_HIP(hipStreamSynchronize(stream));
@@ -1193,6 +1197,11 @@ lx_status Sim::assemble_system(double t1, StepCoef &C, bool fork_residual)
             const lx_status rs = residual64(C, d_xs, true, t1);
             std::swap(stream, stream_aux);
             if (rs != LX_OK) return rs;
+            // ||b|| and ||r|| behind it on the same stream (norm slots 1 and 2; the set-up on
+            // the first stream writes other fields of the state) and their copy to the host
+            launch_norm<double>(N, d_b64, d_st, 0.0, d_partial_aux, 1, stream_aux);
+            launch_norm<double>(N, d_r64, d_st, 0.0, d_partial_aux, 2, stream_aux);
+            LX_HIP(hipMemcpyAsync(h_norms0, &d_st->norms[1], 2 * sizeof(double), hipMemcpyDeviceToHost, stream_aux));
             LX_HIP(hipEventRecord(ev_join, stream_aux));
         }
         launch_simple_setup<float>(P, d_val32, d_Finv32, d_Dinv32, solver.precond == LX_PC_AMG ? nullptr : d_Sinv32,
@@ -1553,6 +1562,19 @@ lx_status Sim::step(lx_step_stats *out)
         LX_HIP(hipEventRecord(ev_asm1, stream));
         LX_HIP(hipStreamWaitEvent(stream, ev_join, 0));
     }
+    // scoring of the guess orders against the solution (read after the final sync); the
+    // refinement loop scores each iterate it checks before reading its residual, so that the
+    // last check's host round trip covers the scoring too
+    const int nk = extrap ? std::min(nhist, 4) - 1 : 0;
+    bool scored = false;
+    auto score_guess = [&]() -> lx_status {
+        if (nk < 2) return LX_OK;
+        const double *h[4] = {d_hist[0], d_hist[1], d_hist[2], d_hist[3]};
+        launch_guess_err(N, nk, d_xs, h, C.gamma, d_gerr, d_gerr + kGuessErrPartial, stream);
+        LX_HIP(hipMemcpyAsync(h_gerr, d_gerr + kGuessErrPartial, 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
+        scored = true;
+        return LX_OK;
+    };
     GmResult gr;
     if (!prob.semi_implicit) {
         st = newton(t1, C, S);
@@ -1566,16 +1588,24 @@ lx_status Sim::step(lx_step_stats *out)
         S.converged = gr.converged;
     } else {
         // FP32 matrix and inner GMRES inside FP64 iterative refinement
-        if (!overlap) {
+        double n0[2];
+        if (overlap) {
+            // formed on the second stream: wait for that stream only, while the set-up runs on
+            LX_HIP(hipEventSynchronize(ev_join));
+            n0[0] = h_norms0[0];
+            n0[1] = h_norms0[1];
+        } else {
             st = residual64(C, d_xs, true, t1);
             if (st != LX_OK) return st;
+            launch_norm<double>(N, d_b64, d_st, 0.0, d_partial, 1, stream);
+            launch_norm<double>(N, d_r64, d_st, 0.0, d_partial, 2, stream);
+            st = read_state();
+            if (st != LX_OK) return st;
+            n0[0] = h_st->norms[1];
+            n0[1] = h_st->norms[2];
         }
-        launch_norm<double>(N, d_b64, d_st, 0.0, d_partial, 1, stream);
-        launch_norm<double>(N, d_r64, d_st, 0.0, d_partial, 2, stream);
-        st = read_state();
-        if (st != LX_OK) return st;
-        const double bnorm = h_st->norms[1] > 0 ? h_st->norms[1] : 1.0;
-        double rnorm = h_st->norms[2];
+        const double bnorm = n0[0] > 0 ? n0[0] : 1.0;
+        double rnorm = n0[1];
         int total = 0, ir = 0;
         bool conv = rnorm <= solver.ir_rtol * bnorm;
         while (!conv && ir < solver.max_ir && total < solver.max_iters) {
@@ -1593,6 +1623,8 @@ lx_status Sim::step(lx_step_stats *out)
             st = residual64(C, d_xs, false, t1);
             if (st != LX_OK) return st;
             launch_norm<double>(N, d_r64, d_st, 0.0, d_partial, 2, stream);
+            st = score_guess();
+            if (st != LX_OK) return st;
             st = read_state();
             if (st != LX_OK) return st;
             if (verbose())
@@ -1609,12 +1641,9 @@ lx_status Sim::step(lx_step_stats *out)
         S.converged = conv;
         timer_flush(0, S);
     }
-    // score the guess orders against the solution just found (read after the sync below)
-    const int nk = extrap ? std::min(nhist, 4) - 1 : 0;
-    if (nk >= 2) {
-        const double *h[4] = {d_hist[0], d_hist[1], d_hist[2], d_hist[3]};
-        launch_guess_err(N, nk, d_xs, h, C.gamma, d_gerr, d_gerr + kGuessErrPartial, stream);
-        LX_HIP(hipMemcpyAsync(h_gerr, d_gerr + kGuessErrPartial, 3 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    if (!scored) {
+        st = score_guess();
+        if (st != LX_OK) return st;
     }
     LX_HIP(hipEventRecord(ev_step1, stream));
     LX_HIP(hipEventSynchronize(ev_step1));
