@@ -145,9 +145,10 @@ struct Sim {
     // residual (partial sums of their own) and copied to pinned memory, so that the host
     // has them while the set-up still runs on the first
     double *d_partial_aux = nullptr, *h_norms0 = nullptr;
-    // convergence checks inside an Arnoldi cycle: the done flag copied to pinned
-    // host memory behind an event, one check in flight (ping-pong slots)
-    int32_t *h_flag = nullptr;
+    // convergence checks inside an Arnoldi cycle: the scalar part of the state (done
+    // flag, columns used, residual estimate) copied to pinned host memory behind an
+    // event, one check in flight (ping-pong slots)
+    GmState *h_chk = nullptr;
     double *h_gerr = nullptr;  // pinned: errors of the guess orders on the last step
     double *d_gerr = nullptr;  // their partial sums, then the three sums
     int x_order = 4;           // extrapolation order of the next guess (2: BDF weights, 3, 4)

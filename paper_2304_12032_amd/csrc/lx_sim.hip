@@ -71,7 +71,7 @@ Sim::~Sim()
         else (void)hipFree(p);
     }
     if (h_st) (void)hipHostFree(h_st);
-    if (h_flag) (void)hipHostFree(h_flag);
+    if (h_chk) (void)hipHostFree(h_chk);
     if (h_gerr) (void)hipHostFree(h_gerr);
     if (h_norms0) (void)hipHostFree(h_norms0);
     for (auto &ev : ev_chk)
@@ -349,7 +349,7 @@ lx_status Sim::create(const lx_device *dev, const lx_mesh *mesh, const lx_proble
     ALLOC(d_st, sizeof(GmState));
     ALLOC(d_partial, sizeof(double) * std::max<int64_t>((int64_t)nb_red * 64, gm_partial_size(N)));
     LX_HIP(hipHostMalloc((void **)&h_st, sizeof(GmState), hipHostMallocDefault));
-    LX_HIP(hipHostMalloc((void **)&h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
+    LX_HIP(hipHostMalloc((void **)&h_chk, 2 * sizeof(GmState), hipHostMallocDefault));
     LX_HIP(hipHostMalloc((void **)&h_gerr, 4 * sizeof(double), hipHostMallocDefault));
     ALLOC(d_gerr, sizeof(double) * (kGuessErrPartial + 4));
     for (auto &ev : ev_chk) LX_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -885,11 +885,13 @@ void Sim::spmv(const T *x, T *y, const int32_t *done, std::pair<hipEvent_t, hipE
     for (const OutflowDev &o : outflow) launch_rank1<T>(o, x, y, done, s);
 }
 
+// the scalar part of the GMRES state (everything from tol_abs on), which the host reads
+static const size_t kStOff = offsetof(GmState, tol_abs);
+
 lx_status Sim::read_state()
 {
-    const size_t off = offsetof(GmState, tol_abs);
-    LX_HIP(hipMemcpyAsync((char *)h_st + off, (char *)d_st + off, sizeof(GmState) - off, hipMemcpyDeviceToHost,
-                          stream));
+    LX_HIP(hipMemcpyAsync((char *)h_st + kStOff, (char *)d_st + kStOff, sizeof(GmState) - kStOff,
+                          hipMemcpyDeviceToHost, stream));
     LX_HIP(hipStreamSynchronize(stream));
     return LX_OK;
 }
@@ -943,7 +945,7 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
         // of the same cycle in the last solve of this kind, every step if that
         // is unknown, and every eighth step in any case.
         const int kp = (kind >= 0 && kind < 8 && cycle < 8) ? k_hint[kind][cycle] : 0;
-        int pending = -1;
+        int pending = -1, snap = -1, last_timed = -1;
         for (int k = 0; k < kmax; ++k) {
             T *zk = Z + k * ld;
             const bool amg = solver.precond == LX_PC_AMG;
@@ -978,6 +980,7 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
                 // a timed step replays its two parts as graphs of their own around
                 // the product, launched directly so that its events stamp the kernel
                 auto *tm = timer_begin(0, k, false);
+                if (tm) last_timed = k;
                 if (tm) {
                     if (lx_status e = replay(2 * kMaxRestart + k, pre); e != LX_OK) return e;
                     spmv<T>(zk, w, &d_st->done, tm, stream);
@@ -991,26 +994,41 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
                     if (lx_status e = replay(key, whole); e != LX_OK) return e;
                 }
             } else {
+                auto *tm = timer_begin(0, k, false);
+                if (tm) last_timed = k;
                 pre(stream);
-                spmv<T>(zk, w, &d_st->done, timer_begin(0, k, false), stream);
+                spmv<T>(zk, w, &d_st->done, tm, stream);
                 post(stream);
             }
             if (pending >= 0) {
                 LX_HIP(hipEventSynchronize(ev_chk[pending & 1]));
-                const bool stop = h_flag[pending & 1] != 0;
+                const bool stop = h_chk[pending & 1].done != 0;
+                if (stop) {
+                    snap = pending;
+                    break;
+                }
                 pending = -1;
-                if (stop) break;
             }
             const bool check = kp > 0 ? (k + 2 >= kp || (k + 1) % 8 == 0) : true;
             if (check && k + 1 < kmax) {
-                LX_HIP(hipMemcpyAsync(&h_flag[k & 1], &d_st->done, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+                LX_HIP(hipMemcpyAsync((char *)&h_chk[k & 1] + kStOff, (char *)d_st + kStOff, sizeof(GmState) - kStOff,
+                                      hipMemcpyDeviceToHost, stream));
                 LX_HIP(hipEventRecord(ev_chk[k & 1], stream));
                 pending = k;
             }
         }
         LX_HIP(hipGetLastError());
-        lx_status s = read_state();
-        if (s != LX_OK) return s;
+        // A cycle stopped by a check already holds the state as that step left it: the step
+        // queued after it exits on the done flag and writes nothing, so the host takes that
+        // copy and queues the cycle's update without waiting for the device.  Not when a
+        // stamped launch followed the checked step: its events may not have completed.
+        if (snap >= 0 && last_timed <= snap) {
+            memcpy((char *)h_st + kStOff, (char *)&h_chk[snap & 1] + kStOff, sizeof(GmState) - kStOff);
+        } else {
+            lx_status s = read_state();
+            if (s != LX_OK) return s;
+        }
+        lx_status s = LX_OK;
         timer_flush(h_st->kused, tstats);
         if (kind >= 0 && kind < 8 && cycle < 8) k_hint[kind][cycle] = h_st->kused;
         res.bnorm = h_st->norms[0];
