@@ -792,11 +792,13 @@ void Sim::timer_end(std::pair<hipEvent_t, hipEvent_t> *p)
 void Sim::timer_flush(int kused, lx_step_stats &acc)
 {
     for (size_t i = 0; i < ev_used; ++i) {
+        const int kind = ev_tag[i].first, it = ev_tag[i].second;
+        // products of a cycle's steps from kused on exited on the done flag; their events are
+        // not queried (a cycle that a check stopped is flushed before they need have run)
+        if (kind == 0 && it >= 0 && it >= kused) continue;
         float ms = 0;
         if (hipEventElapsedTime(&ms, ev_pool[i].first, ev_pool[i].second) != hipSuccess) continue;
-        int kind = ev_tag[i].first, it = ev_tag[i].second;
         if (kind == 0) {
-            if (it >= 0 && it >= kused) continue;
             acc.spmv_ms += ms;
             acc.spmv_calls += 1;
         } else if (kind == 1) {
@@ -945,7 +947,7 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
         // of the same cycle in the last solve of this kind, every step if that
         // is unknown, and every eighth step in any case.
         const int kp = (kind >= 0 && kind < 8 && cycle < 8) ? k_hint[kind][cycle] : 0;
-        int pending = -1, snap = -1, last_timed = -1;
+        int pending = -1, snap = -1;
         for (int k = 0; k < kmax; ++k) {
             T *zk = Z + k * ld;
             const bool amg = solver.precond == LX_PC_AMG;
@@ -980,7 +982,6 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
                 // a timed step replays its two parts as graphs of their own around
                 // the product, launched directly so that its events stamp the kernel
                 auto *tm = timer_begin(0, k, false);
-                if (tm) last_timed = k;
                 if (tm) {
                     if (lx_status e = replay(2 * kMaxRestart + k, pre); e != LX_OK) return e;
                     spmv<T>(zk, w, &d_st->done, tm, stream);
@@ -994,10 +995,8 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
                     if (lx_status e = replay(key, whole); e != LX_OK) return e;
                 }
             } else {
-                auto *tm = timer_begin(0, k, false);
-                if (tm) last_timed = k;
                 pre(stream);
-                spmv<T>(zk, w, &d_st->done, tm, stream);
+                spmv<T>(zk, w, &d_st->done, timer_begin(0, k, false), stream);
                 post(stream);
             }
             if (pending >= 0) {
@@ -1020,9 +1019,9 @@ lx_status Sim::gmres(const T *b, T *x, bool x_zero, double rtol, int max_iters, 
         LX_HIP(hipGetLastError());
         // A cycle stopped by a check already holds the state as that step left it: the step
         // queued after it exits on the done flag and writes nothing, so the host takes that
-        // copy and queues the cycle's update without waiting for the device.  Not when a
-        // stamped launch followed the checked step: its events may not have completed.
-        if (snap >= 0 && last_timed <= snap) {
+        // copy and queues the cycle's update without waiting for the device (the stamps of
+        // that step's product, if any, are not read: its column is at or past kused).
+        if (snap >= 0) {
             memcpy((char *)h_st + kStOff, (char *)&h_chk[snap & 1] + kStOff, sizeof(GmState) - kStOff);
         } else {
             lx_status s = read_state();
