@@ -17,7 +17,9 @@ What it computes per step (paper Sec. 2.3 and 2.4; readings listed in lxo.c):
   Fully implicit formulation (Sec. 2.3, u* = u^{n+1} - u_ALE, implicit LES term):
   steps 3-4 become Newton's method (Sec. 2.4) on the nonlinear residual, its
   Jacobian by the complex step, each update solved exactly, from the step's
-  starting state until ||R|| <= newton_rtol ||R_0||.
+  starting state until ||R|| <= newton_rtol ||R_0||.  Outflow conditions are
+  linear in the new state as in step 3 (backflow coefficient at u_EXT): their
+  matrix terms join the Jacobian and -R gains b_out - (B + C_R w w^T) x.
 """
 import ctypes
 import os
